@@ -1,0 +1,260 @@
+"""Plain FP64 reference of the localized EVD clutter filter (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may use this module. It is slow on purpose: every step is the
+definition written out with numpy / LAPACK, in complex128, in the paper's
+order:
+
+1. Casorati matrix C (pixels x frames) of the packet   -- Principles section, Fig. 1
+2. Gaussian windows, C_w = W C                          -- Eq. 11
+3. Covariance R = C_w^H C_w                             -- Eqs 1 and 12
+4. EVD R = V Lambda V^H, eigenvalues descending         -- Eq. 2
+5. Eigencomponent weights (hard / curvature / sigmoid)  -- Eqs 4, 6, 9
+6. Projection C_hat = C_w V diag(w) V^H                 -- Eqs 4 and 5
+7. Power Doppler PD_d = sum_t |C_hat|^2                 -- text after Eq. 5
+8. Recombination PD = sum_d alpha_d PD_d, alpha_d = 1/(mean flow power)  -- Eq. 13
+
+Readings where the paper is silent or ambiguous (each is listed in the design doc):
+transposes of complex data are conjugate transposes; PD integrates (sums) over
+slow time; the mean flow power of a subset is taken over all Npix pixels and
+Nt frames, so alpha_d = Npix*Nt / sum_i w_i^2 lambda_i; window centres sit at
+(j + 1/2)*spacing - 1/2 with sigma = sigma_frac * spacing and the window is
+zero outside a +-trunc_sigmas*sigma box; the curvature rule takes numpy-style
+differences (central inside, one-sided at the ends), searches
+n in [2, floor(knee_max_frac*Nt)] and keeps the smallest index on ties; k is
+the number of rejected leading components; the combined filtered IQ is
+sum_d C_hat_d / sum_d w_d.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+from typing import Optional
+
+import numpy as np
+
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP = 0, 1, 2, 3
+SHAPE_HARD, SHAPE_SIGMOID = 0, 1
+PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
+
+FLAG_NONPOSITIVE = 1 << 0   # lambda_1 <= 0 or log10(lambda_1) == 0 under the curvature rule
+
+
+@dataclass
+class Threshold:
+    """Thresholding rule (mirrors the C struct ``lcf_threshold``)."""
+    cut: int = CUT_FIXED_K
+    shape: int = SHAPE_HARD
+    pd_mode: int = PD_EQ13
+    k_fixed: int = 4
+    beta_knee: float = 1.0
+    knee_max_frac: float = 0.5
+    beta_sigmoid: float = 2.0
+    explicit_w: Optional[np.ndarray] = None     # [nd][nt]
+    mlp: Optional[object] = None                # callable(lam) -> weights, for CUT_MLP
+
+
+@dataclass
+class Window:
+    cy: float
+    cx: float
+    sy: float
+    sx: float
+    y0: int
+    y1: int
+    x0: int
+    x1: int
+    flat: bool
+
+
+def window_boxes(ny: int, nx: int, gy: int, gx: int, sigma_frac: float = 1.0 / 3.0,
+                 trunc_sigmas: float = 6.0):
+    """Window grid of Eq. 11 / Fig. 3: gy x gx Gaussian windows, subset index
+    d = a*gx + b. Centres (j + 1/2)*spacing - 1/2, sigma = sigma_frac*spacing
+    per axis (the paper leaves both to the number of subsets). sigma_frac == 0
+    gives one flat window over the whole image (global processing)."""
+    out = []
+    dy, dx = ny / gy, nx / gx
+    for a in range(gy):
+        for b in range(gx):
+            cy = (a + 0.5) * dy - 0.5
+            cx = (b + 0.5) * dx - 0.5
+            sy = sigma_frac * dy
+            sx = sigma_frac * dx
+            flat = sigma_frac == 0.0
+            if flat or trunc_sigmas == 0.0:
+                y0, y1, x0, x1 = 0, ny - 1, 0, nx - 1
+            else:
+                y0 = max(0, int(math.ceil(cy - trunc_sigmas * sy)))
+                y1 = min(ny - 1, int(math.floor(cy + trunc_sigmas * sy)))
+                x0 = max(0, int(math.ceil(cx - trunc_sigmas * sx)))
+                x1 = min(nx - 1, int(math.floor(cx + trunc_sigmas * sx)))
+            out.append(Window(cy, cx, sy, sx, y0, y1, x0, x1, flat))
+    return out
+
+
+def window_table(win: Window, ny: int, nx: int) -> np.ndarray:
+    """Full-image weights w_d(y, x) of one window (Eq. 11), zero outside its box."""
+    w = np.zeros((ny, nx))
+    ys = np.arange(win.y0, win.y1 + 1, dtype=np.float64)
+    xs = np.arange(win.x0, win.x1 + 1, dtype=np.float64)
+    if win.flat:
+        w[win.y0:win.y1 + 1, win.x0:win.x1 + 1] = 1.0
+    else:
+        wy = np.exp(-((ys - win.cy) ** 2) / (2.0 * win.sy ** 2))
+        wx = np.exp(-((xs - win.cx) ** 2) / (2.0 * win.sx ** 2))
+        w[win.y0:win.y1 + 1, win.x0:win.x1 + 1] = np.outer(wy, wx)
+    return w
+
+
+def casorati(iq: np.ndarray) -> np.ndarray:
+    """Casorati matrix of a packet (Fig. 1): rows = pixels (y-major), columns =
+    frames. ``iq`` is [nt][ny][nx]; complex64 widens to complex128 exactly."""
+    nt = iq.shape[0]
+    return np.asarray(iq, dtype=np.complex128).reshape(nt, -1).T.copy()
+
+
+def covariance(cw: np.ndarray) -> np.ndarray:
+    """Temporal covariance R = C_w^H C_w (Eqs 1 and 12, conjugate transpose)."""
+    return cw.conj().T @ cw
+
+
+def evd(r: np.ndarray):
+    """Eigen-decomposition R = V diag(lam) V^H (Eq. 2), eigenvalues descending."""
+    lam, v = np.linalg.eigh(r)
+    return lam[::-1].copy(), v[:, ::-1].copy()
+
+
+def phase_normalize(v: np.ndarray) -> np.ndarray:
+    """Fix each column's free phase: its largest-magnitude entry made real > 0."""
+    v = v.copy()
+    idx = np.argmax(np.abs(v), axis=0)
+    ph = v[idx, np.arange(v.shape[1])]
+    return v * (np.abs(ph) / ph)[None, :]
+
+
+def knee_curvature(lam: np.ndarray, beta: float):
+    """Curvature of the normalised log-eigenvalue curve (Eq. 6).
+
+    y(n) = log10(lambda_n) with lambda floored at lambda_1 * 2^-52, normalised
+    to beta * Nt * y(n) / y(1); first and second derivatives by numpy-style
+    differences; K = |y''| / (1 + y'^2)^(3/2). Returns (K, flags)."""
+    nt = lam.shape[0]
+    lam1 = lam[0]
+    if not lam1 > 0.0:
+        return np.zeros(nt), FLAG_NONPOSITIVE
+    lamc = np.maximum(lam, lam1 * 2.0 ** -52)
+    y = np.log10(lamc)
+    if y[0] == 0.0:
+        return np.zeros(nt), FLAG_NONPOSITIVE
+    yt = beta * nt * y / y[0]
+    d1 = np.gradient(yt)
+    d2 = np.gradient(d1)
+    return np.abs(d2) / (1.0 + d1 * d1) ** 1.5, 0
+
+
+def knee_k(curv: np.ndarray, nt: int, max_frac: float) -> int:
+    """k = smallest argmax of the curvature over 1-based n in [2, floor(max_frac*Nt)]."""
+    hi = max(2, int(math.floor(max_frac * nt)))
+    hi = min(hi, nt)
+    seg = curv[1:hi]          # 0-based indices 1..hi-1  <=>  1-based n = 2..hi
+    return int(np.argmax(seg)) + 2
+
+
+def sigmoid_weights(nt: int, k: int, beta: float) -> np.ndarray:
+    """Soft weights of Eq. 9: w_i = 1 / (1 + exp(-beta (i - k))), i = 1..Nt."""
+    i = np.arange(1, nt + 1, dtype=np.float64)
+    return 1.0 / (1.0 + np.exp(-beta * (i - k)))
+
+
+def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
+    """Eigencomponent weights of one subset.
+
+    FIXED_K / KNEE choose k (Eq. 4 hard cut, Eq. 6 curvature); the shape is a
+    hard 0/1 cut (Eq. 4) or the sigmoid of Eq. 9 centred on k. EXPLICIT takes
+    the caller's weights; MLP calls ``thr.mlp(lam)``. Returns (w, k, curv, flags)."""
+    nt = lam.shape[0]
+    curv = np.zeros(nt)
+    flags = 0
+    if thr.cut == CUT_EXPLICIT:
+        return np.asarray(thr.explicit_w[d], dtype=np.float64).copy(), -1, curv, 0
+    if thr.cut == CUT_MLP:
+        return np.asarray(thr.mlp(lam), dtype=np.float64), -1, curv, 0
+    if thr.cut == CUT_FIXED_K:
+        k = int(thr.k_fixed)
+    elif thr.cut == CUT_KNEE:
+        curv, flags = knee_curvature(lam, thr.beta_knee)
+        k = 0 if flags else knee_k(curv, nt, thr.knee_max_frac)
+    else:
+        raise ValueError("unknown cut")
+    if thr.shape == SHAPE_HARD:
+        w = (np.arange(1, nt + 1) > k).astype(np.float64)
+    else:
+        w = sigmoid_weights(nt, k, thr.beta_sigmoid)
+    return w, k, curv, flags
+
+
+def projector(v: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """P = V diag(w) V^H (Eq. 4 with Lambda_hat = diag(w))."""
+    return (v * w[None, :]) @ v.conj().T
+
+
+def filter_packet(iq: np.ndarray, gy: int, gx: int, thr: Threshold,
+                  sigma_frac: float = 1.0 / 3.0, trunc_sigmas: float = 6.0,
+                  check_eq5: bool = False, keep_chat: bool = False):
+    """Localized EVD clutter filter of one packet (Eqs 11-13).
+
+    Returns a dict with ``iq_out`` ([nt][ny][nx] complex128), ``pd`` ([ny][nx]),
+    and per-subset ``lam``, ``v``, ``w``, ``k``, ``curv``, ``alpha``, ``flags``,
+    ``cov`` and ``wsum`` (sum_d w_d)."""
+    nt, ny, nx = iq.shape
+    npix = ny * nx
+    cfull = casorati(iq)                                   # [npix][nt]
+    wins = window_boxes(ny, nx, gy, gx, sigma_frac, trunc_sigmas)
+    nd = len(wins)
+    acc = np.zeros((npix, nt), dtype=np.complex128)
+    wsum = np.zeros(npix)
+    pd_parts = []
+    res = dict(lam=[], v=[], w=[], k=[], curv=[], alpha=[], flags=[], cov=[], chat=[])
+    for d, win in enumerate(wins):
+        wfull = window_table(win, ny, nx).reshape(-1)
+        rows = (np.arange(win.y0, win.y1 + 1)[:, None] * nx
+                + np.arange(win.x0, win.x1 + 1)[None, :]).reshape(-1)
+        wv = wfull[rows]
+        cw = wv[:, None] * cfull[rows]                         # Eq. 11
+        r = covariance(cw)                                     # Eq. 12
+        lam, v = evd(r)                                        # Eq. 2
+        w, k, curv, flags = rule_weights(lam, thr, d)
+        p = projector(v, w)
+        chat = cw @ p                                          # Eq. 4
+        if check_eq5:
+            chat5 = cw @ (np.eye(nt) - projector(v, 1.0 - w))  # Eq. 5
+            assert np.allclose(chat, chat5, rtol=1e-9, atol=1e-9 * np.linalg.norm(cw))
+        energy = float(np.sum(np.abs(chat) ** 2))
+        if thr.pd_mode == PD_SUM:
+            alpha = 1.0
+        else:
+            alpha = npix * nt / energy if energy > 0.0 else 0.0   # Eq. 13
+        pdd = np.sum(np.abs(chat) ** 2, axis=1)
+        pd_parts.append((rows, pdd, alpha, wv))
+        acc[rows] += chat
+        wsum[rows] += wv
+        for key, val in (("lam", lam), ("v", v), ("w", w), ("k", k), ("curv", curv),
+                         ("alpha", alpha), ("flags", flags), ("cov", r)):
+            res[key].append(val)
+        if keep_chat:
+            res["chat"].append((rows, chat))
+    pd = np.zeros(npix)
+    comp = np.zeros(npix)
+    for rows, pdd, alpha, wv in pd_parts:
+        pd[rows] += alpha * pdd
+        comp[rows] += alpha * wv * wv
+    if thr.pd_mode == PD_EQ13_COMPENSATED:
+        pd = np.where(comp > 0.0, pd / np.where(comp > 0.0, comp, 1.0), 0.0)
+    out = np.where(wsum[:, None] > 0.0, acc / np.where(wsum > 0.0, wsum, 1.0)[:, None], 0.0)
+    res["iq_out"] = out.T.reshape(nt, ny, nx)
+    res["pd"] = pd.reshape(ny, nx)
+    res["wsum"] = wsum.reshape(ny, nx)
+    res["nd"] = nd
+    res["windows"] = wins
+    return res
