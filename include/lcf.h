@@ -1,0 +1,212 @@
+/*
+ * lcf.h -- C ABI of the localized EVD clutter filter for AMD MI355X (gfx950).
+ *
+ * Method: Huang et al., "Real-time Adaptive and Localized Spatiotemporal Clutter
+ * Filtering for Ultrasound Small Vessel Imaging" (arXiv 2405.11105).
+ *
+ * The library takes one or more complex IQ packets S (Ny x Nx x Nt), a grid of
+ * 2-D Gaussian spatial windows and a thresholding rule, and returns the clutter
+ * filtered IQ and the recombined power Doppler image:
+ *
+ *   C      Casorati matrix of S, rows = pixels, columns = frames (Fig. 1)
+ *   C_w    = W_d C, one Gaussian window per subset d               (Eq. 11)
+ *   R_d    = C_w^H C_w                                              (Eqs 1, 12)
+ *   R_d    = V Lambda V^H, eigenvalues descending                   (Eq. 2)
+ *   w_i    eigencomponent weights: hard cut (Eq. 4), curvature rule (Eq. 6),
+ *          sigmoid (Eq. 9), caller-given, or a learned MLP
+ *   Chat_d = C_w V diag(w) V^H                                      (Eqs 4, 5)
+ *   PD_d   = sum_t |Chat_d|^2                                       (text after Eq. 5)
+ *   PD     = sum_d alpha_d PD_d, alpha_d = 1 / mean flow power      (Eq. 13)
+ *
+ * Conventions shared by every entry point:
+ *  - Packets are complex64 (interleaved float re, im), C-contiguous [nt][ny][nx]:
+ *    frame-major, each frame row-major with x fastest. Pixel index p = y*nx + x.
+ *  - Transposes of complex data are conjugate transposes (R is Hermitian).
+ *  - Window grid: subset d = a*gx + b, centre ((a+1/2)*ny/gy - 1/2, (b+1/2)*nx/gx - 1/2),
+ *    sigma = sigma_frac * spacing per axis, value exp(-dy^2/2sy^2 - dx^2/2sx^2),
+ *    zero outside the box |y - cy| <= trunc_sigmas*sy, |x - cx| <= trunc_sigmas*sx.
+ *    sigma_frac == 0 with a 1x1 grid is the flat window (global processing).
+ *  - Device pointers are HIP device memory owned by the caller; the library
+ *    never frees them. All launches go to `stream` (a hipStream_t; NULL = the
+ *    default stream) and are asynchronous: a call returns once work is queued.
+ *  - Argument errors are reported synchronously, before any launch, and leave
+ *    the outputs untouched. Device-side conditions (non-finite input, Jacobi
+ *    sweep cap, degenerate spectrum) set per-subset flags that lcf_sync reports.
+ *  - A context is bound to one device; it is not thread-safe. It owns the
+ *    scratch arena (grown on demand, reused afterwards), plans and MLP weights.
+ */
+#ifndef LCF_H
+#define LCF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LCF_ABI_VERSION 1
+
+typedef enum {
+    LCF_OK = 0,
+    LCF_ERR_INVALID_ARG = 1,     /* bad sizes, NULL pointers, unknown enum values      */
+    LCF_ERR_UNSUPPORTED = 2,     /* valid but not implemented (e.g. nt > 208)           */
+    LCF_ERR_OUT_OF_MEMORY = 3,   /* arena growth failed                                 */
+    LCF_ERR_DEVICE = 4,          /* a HIP call failed                                   */
+    LCF_ERR_NONFINITE_INPUT = 5, /* reported by lcf_sync: NaN/Inf reached a covariance  */
+    LCF_ERR_NO_CONVERGENCE = 6,  /* reported by lcf_sync: Jacobi hit the sweep cap      */
+    LCF_ERR_MODEL = 7            /* MLP weights missing or checkpoint corrupt           */
+} lcf_status;
+
+/* Arithmetic of the covariance and reprojection GEMMs. Both keep FP64 for the
+ * eigen-solve and for the rank-r tissue part that needs it. */
+typedef enum {
+    LCF_PREC_FP32 = 0,   /* FP32 MFMA, FP32 accumulate                              */
+    LCF_PREC_BF16X3 = 1  /* split BF16 (x = hi + lo, three products), FP32 accumulate */
+} lcf_precision;
+
+typedef enum {
+    LCF_CUT_FIXED_K = 0,  /* k = k_fixed (Eq. 4)                                     */
+    LCF_CUT_KNEE = 1,     /* k = argmax curvature of the log-eigenvalue curve (Eq. 6) */
+    LCF_CUT_EXPLICIT = 2, /* caller's weights explicit_w[d][i]                       */
+    LCF_CUT_MLP = 3       /* weights from the context's MLP (needs Nt = 128)          */
+} lcf_cut;
+
+typedef enum {
+    LCF_SHAPE_HARD = 0,    /* w_i = 0 for i <= k, else 1 (Eq. 4)                     */
+    LCF_SHAPE_SIGMOID = 1  /* w_i = 1 / (1 + exp(-beta_sigmoid (i - k))) (Eq. 9)     */
+} lcf_shape;
+
+typedef enum {
+    LCF_PD_EQ13 = 0,             /* alpha_d = Npix*Nt / sum_i w_i^2 lambda_i (Eq. 13)   */
+    LCF_PD_SUM = 1,              /* alpha_d = 1                                         */
+    LCF_PD_EQ13_COMPENSATED = 2  /* Eq. 13, then divided by sum_d alpha_d w_d(x)^2      */
+} lcf_pd_mode;
+
+/* Packet shape and window grid (Eq. 11, Fig. 3). */
+typedef struct {
+    int32_t ny, nx, nt;      /* packet dims; 4 <= nt <= 208, ny*nx <= 2^26               */
+    int32_t gy, gx;          /* window grid; gy <= ny, gx <= nx                          */
+    int32_t reserved;        /* must be 0                                               */
+    double sigma_frac;       /* sigma = sigma_frac * spacing per axis (1/3 typical);
+                                0 = flat window, requires gy = gx = 1                   */
+    double trunc_sigmas;     /* box half-width in sigmas (6 typical); 0 = whole image   */
+} lcf_geometry;
+
+/* Thresholding rule (Adaptive Thresholding Methods section). */
+typedef struct {
+    int32_t cut;             /* lcf_cut                                                  */
+    int32_t shape;           /* lcf_shape (ignored for EXPLICIT and MLP)                 */
+    int32_t pd_mode;         /* lcf_pd_mode                                              */
+    int32_t k_fixed;         /* FIXED_K: 0 <= k_fixed <= nt                               */
+    double beta_knee;        /* Eq. 6 normalisation factor beta (> 0), typically 1        */
+    double knee_max_frac;    /* curvature search over n in [2, floor(frac*nt)], (0, 1]    */
+    double beta_sigmoid;     /* Eq. 9 sharpness (> 0), e.g. 2                             */
+    double deflate_rho;      /* tissue-deflation threshold (relative eigenvalue); 1e-5
+                                typical; 0 disables the deflation (precision drops)     */
+    const float* explicit_w; /* EXPLICIT: device float [nsubsets][nt], else NULL          */
+} lcf_threshold;
+
+/* Optional per-subset diagnostics (device pointers, each may be NULL).
+ * nd = gy*gx subsets per packet. */
+typedef struct {
+    double* eigvals;   /* [nd][nt]  eigenvalues of R_d, descending                        */
+    float* weights;    /* [nd][nt]  eigencomponent weights w_i                           */
+    int32_t* k;        /* [nd]      cut index (FIXED_K/KNEE), -1 otherwise                */
+    int32_t* sweeps;   /* [nd]      Jacobi sweeps used                                    */
+    int32_t* flags;    /* [nd]      LCF_FLAG_* bits                                       */
+    double* alpha;     /* [nd]      Eq. 13 subset weight                                  */
+    double* cov;       /* [nd][nt][nt] complex128 (interleaved), R_d row-major            */
+    double* eigvecs;   /* [nd][nt][nt] complex128, eigenvector j in column j              */
+    int32_t* rank;     /* [nd]      number of tissue components deflated                  */
+} lcf_diag;
+
+#define LCF_FLAG_NONPOSITIVE   1  /* lambda_1 <= 0 or log10(lambda_1) == 0 under KNEE: k = 0 */
+#define LCF_FLAG_NONFINITE     2  /* NaN/Inf in the covariance                              */
+#define LCF_FLAG_NO_CONVERGE   4  /* Jacobi reached max sweeps                               */
+#define LCF_FLAG_MLP_FALLBACK  8  /* MLP input out of range: rule weights used instead      */
+
+/* Context options (lcf_set_option). */
+#define LCF_OPT_SCHEDULE     1  /* 0 = batched (all subsets per stage in one launch, default);
+                                   1 = sequential: the paper's per-subset loop (Discussion),
+                                   one launch chain per subset                              */
+#define LCF_OPT_MAX_SWEEPS   2  /* Jacobi sweep cap (default 30)                            */
+#define LCF_OPT_USE_GRAPH    3  /* 1 = capture the launch chain in a hipGraph and replay it
+                                   for repeated calls with the same plan (default 0)       */
+#define LCF_OPT_SUBSPACE_IT  4  /* subspace iterations for the tissue basis (default 6)     */
+#define LCF_OPT_STAGE_TIMING 5  /* 1 = bracket every kernel launch with HIP events on the
+                                   caller's stream and accumulate per-stage device time
+                                   (read with lcf_stage_time; default 0)                  */
+
+/* Kernel stages reported by lcf_stage_time. */
+typedef enum {
+    LCF_STAGE_WINDOWS = 0,      /* Gaussian window factors (Eq. 11)                       */
+    LCF_STAGE_GRAM1 = 1,        /* windowed covariance, split-K MFMA (Eq. 12)             */
+    LCF_STAGE_GRAM1_REDUCE = 2, /* ordered FP64 reduction of the split-K partials          */
+    LCF_STAGE_TISSUE = 3,       /* tissue basis for the deflation                          */
+    LCF_STAGE_GRAM2 = 4,        /* covariance of the deflated data [C' | C_w V_r]          */
+    LCF_STAGE_GRAM2_REDUCE = 5,
+    LCF_STAGE_ASSEMBLE = 6,     /* R from the deflated Gram, B = Q^H R Q                   */
+    LCF_STAGE_JACOBI = 7,       /* FP64 one-sided Jacobi EVD (Eq. 2)                       */
+    LCF_STAGE_RULES = 8,        /* eigencomponent weights (Eqs 4, 6, 9), alpha (Eq. 13)    */
+    LCF_STAGE_MLP = 9,          /* learned weights                                         */
+    LCF_STAGE_PROJECTOR = 10,   /* P = V diag(w) V^H                                       */
+    LCF_STAGE_REPROJ = 11,      /* projection, power Doppler, recombination (Eqs 4, 13)    */
+    LCF_NUM_STAGES = 12
+} lcf_stage;
+
+typedef struct lcf_context lcf_context;
+
+/* Create a context on HIP device `device`. *out receives the handle. */
+lcf_status lcf_create(int32_t device, lcf_context** out);
+/* Release the context and its device memory. NULL is accepted. */
+lcf_status lcf_destroy(lcf_context* ctx);
+/* Set a context option (LCF_OPT_*). */
+lcf_status lcf_set_option(lcf_context* ctx, int32_t option, int64_t value);
+
+/* Host-only validation of a geometry/threshold/precision triple (no GPU needed).
+ * Returns LCF_OK or the error lcf_filter would return for these arguments. */
+lcf_status lcf_validate(const lcf_geometry* geo, const lcf_threshold* thr, int32_t precision);
+
+/* Filter one packet (Eqs 1-13, Localized Clutter Filtering section).
+ *   iq      device complex64 [nt][ny][nx]                     (input, not modified)
+ *   iq_out  device complex64 [nt][ny][nx] or NULL: sum_d Chat_d / sum_d w_d
+ *   pd      device float [ny][nx]: power Doppler after Eq. 13 recombination
+ *   diag    optional diagnostics (host struct holding device pointers), or NULL */
+lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr,
+                      int32_t precision, const void* iq, void* iq_out, float* pd,
+                      const lcf_diag* diag, void* stream);
+
+/* Filter n packets of possibly different shapes and grids in one batched pass
+ * (the parallel processing of subsets that the Discussion leaves for future work).
+ * geo[n] host array; iq/iq_out/pd are host arrays of n device pointers (iq_out[i]
+ * may be NULL, iq_out itself may be NULL). One threshold rule applies to all. */
+lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo,
+                            const lcf_threshold* thr, int32_t precision,
+                            const void* const* iq, void* const* iq_out, float* const* pd,
+                            void* stream);
+
+/* Batched Hermitian eigen-decomposition (Eq. 2) with the library's FP64 one-sided
+ * Jacobi: a = device complex128 [n][nt][nt] (row-major, Hermitian; only read),
+ * w = device double [n][nt] eigenvalues descending, v = device complex128
+ * [n][nt][nt] with eigenvector j in column j (may be NULL), sweeps = device
+ * int32 [n] (may be NULL). 2 <= nt <= 256. */
+lcf_status lcf_heevd_batched(lcf_context* ctx, int32_t n, int32_t nt, const double* a,
+                             double* w, double* v, int32_t* sweeps, void* stream);
+
+/* Wait for `stream` and report the first device-side condition raised since
+ * the previous lcf_sync (LCF_ERR_NONFINITE_INPUT, LCF_ERR_NO_CONVERGENCE). */
+lcf_status lcf_sync(lcf_context* ctx, void* stream);
+
+/* Accumulated device time (ms) and launch count of one stage since the last
+ * reset, over the calls made with LCF_OPT_STAGE_TIMING = 1. Waits for the
+ * recorded events. reset != 0 clears all stages after reading. */
+lcf_status lcf_stage_time(lcf_context* ctx, int32_t stage, double* ms, int64_t* launches, int32_t reset);
+
+const char* lcf_status_str(lcf_status s);
+int32_t lcf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCF_H */

@@ -1,0 +1,259 @@
+"""Localized EVD clutter filter for AMD MI355X -- Python binding of ``liblcf.so``.
+
+Thin ctypes layer over the C ABI in ``include/lcf.h``: it marshals torch device
+tensors (memory) and the current HIP stream into the library calls. Every step
+of the filter runs in the library's HIP kernels; there is no fallback path, and
+the calls raise if the shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "liblcf.so")
+
+PREC_FP32, PREC_BF16X3 = 0, 1
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP = 0, 1, 2, 3
+SHAPE_HARD, SHAPE_SIGMOID = 0, 1
+PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
+OPT_SCHEDULE, OPT_MAX_SWEEPS, OPT_USE_GRAPH, OPT_SUBSPACE_IT, OPT_STAGE_TIMING = 1, 2, 3, 4, 5
+STAGES = ["windows", "gram1", "gram1_reduce", "tissue", "gram2", "gram2_reduce", "assemble", "jacobi",
+          "rules", "mlp", "projector", "reproj"]
+FLAG_NONPOSITIVE, FLAG_NONFINITE, FLAG_NO_CONVERGE, FLAG_MLP_FALLBACK = 1, 2, 4, 8
+
+STATUS = {0: "LCF_OK", 1: "LCF_ERR_INVALID_ARG", 2: "LCF_ERR_UNSUPPORTED", 3: "LCF_ERR_OUT_OF_MEMORY",
+          4: "LCF_ERR_DEVICE", 5: "LCF_ERR_NONFINITE_INPUT", 6: "LCF_ERR_NO_CONVERGENCE", 7: "LCF_ERR_MODEL"}
+
+
+class LcfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class Geometry(C.Structure):
+    _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("nt", C.c_int32), ("gy", C.c_int32),
+                ("gx", C.c_int32), ("reserved", C.c_int32), ("sigma_frac", C.c_double),
+                ("trunc_sigmas", C.c_double)]
+
+
+class ThresholdC(C.Structure):
+    _fields_ = [("cut", C.c_int32), ("shape", C.c_int32), ("pd_mode", C.c_int32), ("k_fixed", C.c_int32),
+                ("beta_knee", C.c_double), ("knee_max_frac", C.c_double), ("beta_sigmoid", C.c_double),
+                ("deflate_rho", C.c_double), ("explicit_w", C.c_void_p)]
+
+
+class DiagC(C.Structure):
+    _fields_ = [("eigvals", C.c_void_p), ("weights", C.c_void_p), ("k", C.c_void_p), ("sweeps", C.c_void_p),
+                ("flags", C.c_void_p), ("alpha", C.c_void_p), ("cov", C.c_void_p), ("eigvecs", C.c_void_p),
+                ("rank", C.c_void_p)]
+
+
+@dataclass
+class Threshold:
+    """Thresholding rule; field meanings follow ``lcf_threshold``."""
+    cut: int = CUT_FIXED_K
+    shape: int = SHAPE_HARD
+    pd_mode: int = PD_EQ13
+    k_fixed: int = 4
+    beta_knee: float = 1.0
+    knee_max_frac: float = 0.5
+    beta_sigmoid: float = 2.0
+    deflate_rho: float = 1e-5
+
+    def to_c(self, explicit_ptr: int = 0) -> ThresholdC:
+        return ThresholdC(self.cut, self.shape, self.pd_mode, self.k_fixed, self.beta_knee,
+                          self.knee_max_frac, self.beta_sigmoid, self.deflate_rho, explicit_ptr or None)
+
+
+_lib = None
+
+
+def load():
+    """Load liblcf.so (built by ``build.py``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.lcf_create.argtypes = [i32, C.POINTER(vp)]
+    lib.lcf_destroy.argtypes = [vp]
+    lib.lcf_set_option.argtypes = [vp, i32, i64]
+    lib.lcf_validate.argtypes = [C.POINTER(Geometry), C.POINTER(ThresholdC), i32]
+    lib.lcf_filter.argtypes = [vp, C.POINTER(Geometry), C.POINTER(ThresholdC), i32, vp, vp, vp,
+                               C.POINTER(DiagC), vp]
+    lib.lcf_filter_batch.argtypes = [vp, i32, C.POINTER(Geometry), C.POINTER(ThresholdC), i32,
+                                     C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
+    lib.lcf_heevd_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    lib.lcf_sync.argtypes = [vp, vp]
+    lib.lcf_stage_time.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+    lib.lcf_status_str.argtypes = [i32]
+    lib.lcf_status_str.restype = C.c_char_p
+    for name in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter",
+                 "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version", "lcf_stage_time"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return [n for n in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter",
+                        "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_status_str",
+                        "lcf_abi_version")]
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise LcfError(st, what)
+
+
+def geometry(ny, nx, nt, gy, gx, sigma_frac=1.0 / 3.0, trunc_sigmas=6.0) -> Geometry:
+    return Geometry(ny, nx, nt, gy, gx, 0, sigma_frac, trunc_sigmas)
+
+
+def validate(geo: Geometry, thr: Threshold, precision: int = PREC_FP32) -> int:
+    """Host-only argument check; returns the lcf_status code."""
+    lib = load()
+    tc = thr.to_c(1 if thr.cut == CUT_EXPLICIT else 0)
+    return int(lib.lcf_validate(C.byref(geo), C.byref(tc), precision))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+class Context:
+    """An lcf_context on one device (options: schedule, max_sweeps, use_graph)."""
+
+    def __init__(self, device: int = 0, schedule: int = 0, max_sweeps: int = 30, use_graph: int = 0):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.lcf_create(device, C.byref(h)), "lcf_create")
+        self._h = h
+        self.device = device
+        self.set_option(OPT_SCHEDULE, schedule)
+        self.set_option(OPT_MAX_SWEEPS, max_sweeps)
+        self.set_option(OPT_USE_GRAPH, use_graph)
+
+    def set_option(self, opt: int, value: int):
+        _check(load().lcf_set_option(self._h, opt, int(value)), "lcf_set_option")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lcf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self) -> int:
+        return int(load().lcf_sync(self._h, _stream()))
+
+    def stage_times(self, reset: bool = False) -> dict:
+        """{stage name: (total device ms, launches)} accumulated with OPT_STAGE_TIMING on."""
+        out = {}
+        lib = load()
+        for i, name in enumerate(STAGES):
+            ms, n = C.c_double(), C.c_int64()
+            _check(lib.lcf_stage_time(self._h, i, C.byref(ms), C.byref(n), 0), "lcf_stage_time")
+            out[name] = (ms.value, n.value)
+        if reset:
+            _check(lib.lcf_stage_time(self._h, 0, None, None, 1), "lcf_stage_time")
+        return out
+
+    def filter(self, iq, gy: int, gx: int, thr: Threshold, precision: int = PREC_FP32,
+               sigma_frac: float = 1.0 / 3.0, trunc_sigmas: float = 6.0, iq_out: bool = True,
+               diag: bool = False, diag_cov: bool = False, explicit_w=None, out=None):
+        """Filter one packet ``iq`` (torch complex64 on the GPU, [nt][ny][nx]).
+
+        Returns (iq_out or None, pd, diag dict or None)."""
+        import torch
+        assert iq.is_cuda and iq.dtype == torch.complex64 and iq.is_contiguous() and iq.dim() == 3
+        nt, ny, nx = iq.shape
+        dev = iq.device
+        geo = geometry(ny, nx, nt, gy, gx, sigma_frac, trunc_sigmas)
+        if out is None:
+            pd = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+            io = torch.empty_like(iq) if iq_out else None
+        else:
+            io, pd = out
+        ew = None
+        if thr.cut == CUT_EXPLICIT:
+            ew = explicit_w.to(device=dev, dtype=torch.float32).contiguous()
+        tc = thr.to_c(ew.data_ptr() if ew is not None else 0)
+        dg = None
+        dgc = None
+        if diag or diag_cov:
+            nd = gy * gx
+            dg = dict(eigvals=torch.empty((nd, nt), dtype=torch.float64, device=dev),
+                      weights=torch.empty((nd, nt), dtype=torch.float32, device=dev),
+                      k=torch.empty(nd, dtype=torch.int32, device=dev),
+                      sweeps=torch.empty(nd, dtype=torch.int32, device=dev),
+                      flags=torch.empty(nd, dtype=torch.int32, device=dev),
+                      alpha=torch.empty(nd, dtype=torch.float64, device=dev),
+                      rank=torch.empty(nd, dtype=torch.int32, device=dev))
+            if diag_cov:
+                dg["cov"] = torch.empty((nd, nt, nt), dtype=torch.complex128, device=dev)
+                dg["eigvecs"] = torch.empty((nd, nt, nt), dtype=torch.complex128, device=dev)
+            dgc = DiagC(*(_ptr(dg.get(n)) for n in ("eigvals", "weights", "k", "sweeps", "flags", "alpha",
+                                                    "cov", "eigvecs", "rank")))
+        st = load().lcf_filter(self._h, C.byref(geo), C.byref(tc), precision, _ptr(iq), _ptr(io), _ptr(pd),
+                               C.byref(dgc) if dgc is not None else None, _stream())
+        _check(st, "lcf_filter")
+        return io, pd, dg
+
+    def filter_batch(self, iqs: Sequence, grids: Sequence, thr: Threshold, precision: int = PREC_FP32,
+                     sigma_frac: float = 1.0 / 3.0, trunc_sigmas: float = 6.0, iq_out: bool = False,
+                     outs=None):
+        """Filter several packets of any shapes in one call. Returns (iq_outs, pds)."""
+        import torch
+        n = len(iqs)
+        geos = (Geometry * n)()
+        ip = (C.c_void_p * n)()
+        op = (C.c_void_p * n)()
+        pp = (C.c_void_p * n)()
+        pds, ios = [], []
+        for i, (iq, (gy, gx)) in enumerate(zip(iqs, grids)):
+            assert iq.is_cuda and iq.dtype == torch.complex64 and iq.is_contiguous()
+            nt, ny, nx = iq.shape
+            geos[i] = geometry(ny, nx, nt, gy, gx, sigma_frac, trunc_sigmas)
+            if outs is None:
+                pd = torch.empty((ny, nx), dtype=torch.float32, device=iq.device)
+                io = torch.empty_like(iq) if iq_out else None
+            else:
+                io, pd = outs[i]
+            pds.append(pd)
+            ios.append(io)
+            ip[i] = iq.data_ptr()
+            op[i] = io.data_ptr() if io is not None else None
+            pp[i] = pd.data_ptr()
+        tc = thr.to_c(0)
+        st = load().lcf_filter_batch(self._h, n, geos, C.byref(tc), precision, ip, op, pp, _stream())
+        _check(st, "lcf_filter_batch")
+        return ios, pds
+
+    def heevd(self, a, vectors: bool = True):
+        """Batched Hermitian EVD of a (torch complex128 [n][nt][nt] on the GPU).
+        Returns (w descending [n][nt] float64, v [n][nt][nt] or None, sweeps [n])."""
+        import torch
+        assert a.is_cuda and a.dtype == torch.complex128 and a.is_contiguous() and a.dim() == 3
+        n, nt, _ = a.shape
+        w = torch.empty((n, nt), dtype=torch.float64, device=a.device)
+        v = torch.empty_like(a) if vectors else None
+        sw = torch.empty(n, dtype=torch.int32, device=a.device)
+        st = load().lcf_heevd_batched(self._h, n, nt, _ptr(a), _ptr(w), _ptr(v), _ptr(sw), _stream())
+        _check(st, "lcf_heevd_batched")
+        return w, v, sw

@@ -1,0 +1,557 @@
+// FP64 small-matrix stages of each subset: window tables (Eq. 11), the tissue
+// basis used to deflate the covariance, the deflated-basis assembly of R, and
+// the batched Hermitian eigen-decomposition (Eq. 2) by one-sided Jacobi.
+#include "lcf_internal.h"
+#include "lcf_kernels.h"
+
+namespace lcf {
+
+// ------------------------------------------------------------------ windows
+// 1-D factors of the separable Gaussian window of Eq. 11 over the subset box.
+__global__ void __launch_bounds__(256) k_windows(Workspace ws) {
+    const SubsetDesc sd = ws.sub[blockIdx.x];
+    const int ny = sd.y1 - sd.y0 + 1, nx = sd.x1 - sd.x0 + 1;
+    if (threadIdx.x == 0) ws.flags[blockIdx.x] = 0;
+    for (int i = threadIdx.x; i < ny; i += blockDim.x) {
+        const double d = (double)(sd.y0 + i) - sd.cy;
+        ws.wtab[sd.wy_off + i] = sd.flat ? 1.0 : exp(-(d * d) / (2.0 * sd.sy * sd.sy));
+    }
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        const double d = (double)(sd.x0 + i) - sd.cx;
+        ws.wtab[sd.wx_off + i] = sd.flat ? 1.0 : exp(-(d * d) / (2.0 * sd.sx * sd.sx));
+    }
+}
+
+// ------------------------------------------------------------------ tissue basis
+// Approximate dominant eigenvectors of the pass-1 covariance by subspace
+// iteration + Rayleigh-Ritz, keep the r of them whose Ritz value exceeds
+// rho * theta_1, and build an exactly unitary basis Q = H_0 ... H_{r-1} whose
+// first r columns span them (complex Householder reflectors, FP64). Any V_r is
+// valid for the deflation identity C_w = C' + (C_w V_r) V_r^H; accuracy of V_r
+// only decides how small C' is.
+
+// Tiny Hermitian EVD by cyclic Jacobi, single thread (n <= RMAX).
+__device__ void small_heev(double2* h, double2* z, double* th, int n) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) z[i * RMAX + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double a = cabs2(h[i * RMAX + j]);
+                tot += a;
+                if (i != j) off += a;
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double2 apq = h[p * RMAX + q];
+                const double mag = sqrt(cabs2(apq));
+                if (mag == 0.0) continue;
+                const double2 ph = make_double2(apq.x / mag, apq.y / mag);
+                const double theta = (h[q * RMAX + q].x - h[p * RMAX + p].x) / (2.0 * mag);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                // J = [[c, s], [-s conj(ph), c conj(ph)]]
+                const double2 j00 = make_double2(c, 0.0), j01 = make_double2(s, 0.0);
+                const double2 j10 = make_double2(-s * ph.x, s * ph.y), j11 = make_double2(c * ph.x, -c * ph.y);
+                for (int i = 0; i < n; ++i) {   // columns: H J, Z J
+                    const double2 a = h[i * RMAX + p], b = h[i * RMAX + q];
+                    h[i * RMAX + p] = cadd(cmul(a, j00), cmul(b, j10));
+                    h[i * RMAX + q] = cadd(cmul(a, j01), cmul(b, j11));
+                    const double2 za = z[i * RMAX + p], zb = z[i * RMAX + q];
+                    z[i * RMAX + p] = cadd(cmul(za, j00), cmul(zb, j10));
+                    z[i * RMAX + q] = cadd(cmul(za, j01), cmul(zb, j11));
+                }
+                for (int i = 0; i < n; ++i) {   // rows: J^H (H J)
+                    const double2 a = h[p * RMAX + i], b = h[q * RMAX + i];
+                    h[p * RMAX + i] = cadd(cmulc(j00, a), cmulc(j10, b));
+                    h[q * RMAX + i] = cadd(cmulc(j01, a), cmulc(j11, b));
+                }
+            }
+    }
+    for (int i = 0; i < n; ++i) th[i] = h[i * RMAX + i].x;
+}
+
+template <int NTP>
+__global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int iters) {
+    __shared__ double2 X[NTP * RMAX];
+    __shared__ double2 Y[NTP * RMAX];
+    __shared__ double2 H[RMAX * RMAX], Z[RMAX * RMAX];
+    __shared__ double th[RMAX];
+    __shared__ int piv[RMAX], order[RMAX];
+    __shared__ double red[32];
+    __shared__ int sh_r, sh_ns;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const SubsetDesc sd = ws.sub[s];
+    const int nt = sd.nt;
+    const double2* R = ws.rwin + (long)s * NTP * NTP;
+    double2* hv = ws.hv + (long)s * RMAX * NTP;
+    double* htau = ws.htau + (long)s * RMAX;
+
+    if (tid == 0) {
+        // start block: columns of R at the largest diagonal entries
+        int ns = nt < RMAX ? nt : RMAX;
+        for (int j = 0; j < ns; ++j) {
+            int best = j;          // fallback keeps the index in range (e.g. NaN diagonals)
+            double bv = -1.0;
+            for (int t = 0; t < nt; ++t) {
+                bool used = false;
+                for (int i = 0; i < j; ++i) used |= (piv[i] == t);
+                const double d = R[(long)t * NTP + t].x;
+                if (!used && d > bv) { bv = d; best = t; }
+            }
+            piv[j] = best;
+        }
+        sh_ns = ns;
+    }
+    __syncthreads();
+    const int ns = sh_ns;
+    for (int e = tid; e < NTP * RMAX; e += 256) {
+        const int t = e / RMAX, j = e % RMAX;
+        // R[t][piv] = conj(R[piv][t])
+        X[e] = (t < nt && j < ns) ? cconj(R[(long)piv[j] * NTP + t]) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    auto orthonormalize = [&]() {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < ns; ++j) {
+                for (int i = 0; i < j; ++i) {
+                    double2 part = make_double2(0.0, 0.0);
+                    for (int t = tid; t < nt; t += 256) part = cadd(part, cmulc(X[t * RMAX + i], X[t * RMAX + j]));
+                    const double2 dot = block_sum2(part, red);
+                    for (int t = tid; t < nt; t += 256) X[t * RMAX + j] = csub(X[t * RMAX + j], cmul(dot, X[t * RMAX + i]));
+                    __syncthreads();
+                }
+                double part = 0.0;
+                for (int t = tid; t < nt; t += 256) part += cabs2(X[t * RMAX + j]);
+                const double nrm = sqrt(block_sum(part, red));
+                const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+                for (int t = tid; t < nt; t += 256) X[t * RMAX + j] = cscale(X[t * RMAX + j], inv);
+                __syncthreads();
+            }
+    };
+    auto apply_R = [&]() {   // Y = R X, coalesced through R[u][t] = conj(R[t][u])
+        for (int t = tid; t < nt; t += 256) {
+            double2 acc[RMAX];
+            for (int j = 0; j < RMAX; ++j) acc[j] = make_double2(0.0, 0.0);
+            for (int u = 0; u < nt; ++u) {
+                const double2 rtu = cconj(R[(long)u * NTP + t]);
+                for (int j = 0; j < RMAX; ++j) acc[j] = cadd(acc[j], cmul(rtu, X[u * RMAX + j]));
+            }
+            for (int j = 0; j < RMAX; ++j) Y[t * RMAX + j] = acc[j];
+        }
+        __syncthreads();
+    };
+
+    for (int it = 0; it < iters; ++it) {
+        orthonormalize();
+        apply_R();
+        for (int e = tid; e < nt * RMAX; e += 256) X[e] = Y[e];
+        __syncthreads();
+    }
+    orthonormalize();
+    apply_R();
+    if (tid < RMAX * RMAX) {
+        const int i = tid / RMAX, j = tid % RMAX;
+        double2 acc = make_double2(0.0, 0.0);
+        if (i < ns && j < ns)
+            for (int t = 0; t < nt; ++t) acc = cadd(acc, cmulc(X[t * RMAX + i], Y[t * RMAX + j]));
+        H[tid] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // Hermitian part (rounding), then EVD, then order descending
+        for (int i = 0; i < ns; ++i)
+            for (int j = i; j < ns; ++j) {
+                const double2 a = H[i * RMAX + j], b = H[j * RMAX + i];
+                const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+                H[i * RMAX + j] = m;
+                H[j * RMAX + i] = cconj(m);
+                if (i == j) H[i * RMAX + i].y = 0.0;
+            }
+        small_heev(H, Z, th, ns);
+        for (int i = 0; i < ns; ++i) order[i] = i;
+        for (int i = 0; i < ns; ++i)
+            for (int j = i + 1; j < ns; ++j)
+                if (th[order[j]] > th[order[i]]) { const int tmp = order[i]; order[i] = order[j]; order[j] = tmp; }
+        int r = 0;
+        const double t1 = ns > 0 ? th[order[0]] : 0.0;
+        if (rho > 0.0 && t1 > 0.0 && isfinite(t1))
+            while (r < ns && th[order[r]] > rho * t1) ++r;
+        sh_r = r;
+    }
+    __syncthreads();
+    const int r = sh_r;
+    // U = X Z (ordered), kept in Y
+    for (int e = tid; e < nt * RMAX; e += 256) {
+        const int t = e / RMAX, j = e % RMAX;
+        double2 acc = make_double2(0.0, 0.0);
+        if (j < r)
+            for (int i = 0; i < ns; ++i) acc = cadd(acc, cmul(X[t * RMAX + i], Z[i * RMAX + order[j]]));
+        Y[e] = acc;
+    }
+    __syncthreads();
+    // Householder QR of U[:, :r]
+    for (int j = 0; j < r; ++j) {
+        double part = 0.0;
+        for (int t = j + tid; t < nt; t += 256) part += cabs2(Y[t * RMAX + j]);
+        const double nx2 = block_sum(part, red);
+        const double nrm = sqrt(nx2);
+        const double2 x0 = Y[j * RMAX + j];
+        const double ax0 = sqrt(cabs2(x0));
+        const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+        const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
+        // v = x - alpha e_j ; v^H v = 2 (|x|^2 + |x| |x0|)
+        const double vv = 2.0 * (nx2 + nrm * ax0);
+        const double tau = vv > 0.0 ? 2.0 / vv : 0.0;
+        for (int t = tid; t < NTP; t += 256) {
+            double2 v = make_double2(0.0, 0.0);
+            if (t > j && t < nt) v = Y[t * RMAX + j];
+            if (t == j) v = csub(x0, alpha);
+            hv[(long)j * NTP + t] = v;
+        }
+        if (tid == 0) htau[j] = tau;
+        __syncthreads();
+        // apply H_j to columns j+1..r-1 of U
+        for (int c = j + 1; c < r; ++c) {
+            double2 part2 = make_double2(0.0, 0.0);
+            for (int t = j + tid; t < nt; t += 256) part2 = cadd(part2, cmulc(hv[(long)j * NTP + t], Y[t * RMAX + c]));
+            const double2 dot = block_sum2(part2, red);
+            for (int t = j + tid; t < nt; t += 256)
+                Y[t * RMAX + c] = csub(Y[t * RMAX + c], cscale(cmul(hv[(long)j * NTP + t], dot), tau));
+            __syncthreads();
+        }
+    }
+    // explicit V_r = H_0 ... H_{r-1} [e_0 .. e_{r-1}]
+    for (int e = tid; e < NTP * RMAX; e += 256) {
+        const int t = e / RMAX, j = e % RMAX;
+        X[e] = make_double2((t == j && j < r) ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int j = r - 1; j >= 0; --j) {
+        const double tau = htau[j];
+        for (int c = 0; c < r; ++c) {
+            double2 part2 = make_double2(0.0, 0.0);
+            for (int t = j + tid; t < nt; t += 256) part2 = cadd(part2, cmulc(hv[(long)j * NTP + t], X[t * RMAX + c]));
+            const double2 dot = block_sum2(part2, red);
+            for (int t = j + tid; t < nt; t += 256)
+                X[t * RMAX + c] = csub(X[t * RMAX + c], cscale(cmul(hv[(long)j * NTP + t], dot), tau));
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < NTP * RMAX; e += 256) {
+        ws.vr64[(long)s * NTP * RMAX + e] = X[e];
+        ws.vr32[(long)s * NTP * RMAX + e] = make_float2((float)X[e].x, (float)X[e].y);
+    }
+    if (tid == 0) ws.rank[s] = r;
+}
+
+// ------------------------------------------------------------------ assembly
+// R = R2 + G' V_r^H + V_r G'^H + V_r (Y^H Y) V_r^H   (exact for C_w = C' + Y V_r^H)
+// written as R2 + E V_r^H + V_r E^H with E = G' + V_r (Y^H Y) / 2, then
+// B = Q^H R Q = H_{r-1} .. H_0 R H_0 .. H_{r-1} (Hermitian rank-2 updates).
+template <int NTP>
+__global__ void __launch_bounds__(256) k_assemble(Workspace ws) {
+    constexpr int NTE = NTP + REXT;
+    __shared__ double2 E[NTP * RMAX];
+    __shared__ double2 V[NTP * RMAX];
+    __shared__ double2 P[NTP];
+    __shared__ double2 vh[NTP];
+    __shared__ double red[32];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nt = ws.sub[s].nt;
+    const int r = ws.rank[s];
+    const double2* X = ws.rext + (long)s * NTE * NTE;
+    double2* B = ws.bmat + (long)s * NTP * NTP;
+    for (int e = tid; e < NTP * RMAX; e += 256) V[e] = ws.vr64[(long)s * NTP * RMAX + e];
+    __syncthreads();
+    for (int e = tid; e < NTP * RMAX; e += 256) {
+        const int t = e / RMAX, j = e % RMAX;
+        double2 acc = make_double2(0.0, 0.0);
+        if (t < nt && j < r) {
+            acc = X[(long)t * NTE + NTP + j];
+            for (int i = 0; i < r; ++i)
+                acc = cadd(acc, cscale(cmul(V[t * RMAX + i], X[(long)(NTP + i) * NTE + NTP + j]), 0.5));
+        }
+        E[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < NTP * NTP; e += 256) {
+        const int t = e / NTP, u = e % NTP;
+        double2 b = make_double2(0.0, 0.0);
+        if (t < nt && u < nt) {
+            b = X[(long)t * NTE + u];
+            for (int j = 0; j < r; ++j) {
+                b = cadd(b, cmulc(V[u * RMAX + j], E[t * RMAX + j]));   // E_tj conj(V_uj)
+                b = cadd(b, cmulc(E[u * RMAX + j], V[t * RMAX + j]));   // V_tj conj(E_uj)
+            }
+            if (t == u) b.y = 0.0;
+        }
+        B[e] = b;
+        ws.pmat[(long)s * NTP * NTP + e] = b;
+    }
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        const double tau = ws.htau[(long)s * RMAX + j];
+        for (int t = tid; t < NTP; t += 256) vh[t] = ws.hv[((long)s * RMAX + j) * NTP + t];
+        __syncthreads();
+        // p = B v, via B[t][u] = conj(B[u][t])
+        for (int t = tid; t < nt; t += 256) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int u = 0; u < nt; ++u) acc = cadd(acc, cmulc(B[(long)u * NTP + t], vh[u]));
+            P[t] = acc;
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int t = tid; t < nt; t += 256) part += cmulc(vh[t], P[t]).x;
+        const double K = block_sum(part, red);
+        for (int t = tid; t < nt; t += 256) P[t] = csub(P[t], cscale(vh[t], 0.5 * tau * K));
+        __syncthreads();
+        for (int e = tid; e < nt * NTP; e += 256) {
+            const int t = e / NTP, u = e % NTP;
+            if (u >= nt) continue;
+            // B -= tau (v_t conj(w_u) + w_t conj(v_u))
+            const double2 d = cadd(cmulc(P[u], vh[t]), cmulc(vh[u], P[t]));
+            double2 b = csub(B[e], cscale(d, tau));
+            if (t == u) b.y = 0.0;
+            B[e] = b;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ Jacobi
+// One-sided (Hestenes) Jacobi on G = B: rotate column pairs until all columns
+// are mutually orthogonal; then G = W Lambda with W unitary, so lambda_j =
+// ||g_j|| and w_j = g_j / lambda_j (B is positive semi-definite). Columns are
+// stored contiguously (column-major, read as conj of the row-major Hermitian
+// input). Pairs follow the round-robin tournament order, nt/2 disjoint pairs
+// per step, one wave per pair, lanes over rows. Because the B of a subset is
+// taken in the tissue-deflated basis, large and small eigenvalues sit in nearly
+// decoupled blocks and the small columns keep their accuracy.
+__device__ __forceinline__ void rr_pair(int step, int k, int n, int& p, int& q) {
+    const int m = n - 1;
+    int a, b;
+    if (k == 0) { a = 0; b = 1 + step % m; }
+    else { a = 1 + (step + k) % m; b = 1 + (step - k + m) % m; }
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_LDS_NT = 100;   // nt*nt*16 bytes must fit the 160 KiB LDS
+
+template <bool IN_LDS>
+__device__ void jacobi_core(double2* G, int nt, int ld, int max_sweeps, int* sweeps_out, int* flag_out) {
+    __shared__ int rot;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int n = nt + (nt & 1);
+    const double tol = (double)nt * 1.1102230246251565e-16;
+    int sweep = 0;
+    bool converged = false;
+    for (; sweep < max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) rot = 0;
+        __syncthreads();
+        for (int step = 0; step < n - 1; ++step) {
+            for (int k = wave; k < n / 2; k += nw) {
+                int p, q;
+                rr_pair(step, k, n, p, q);
+                if (q >= nt) continue;
+                double2* gp = G + (long)p * ld;
+                double2* gq = G + (long)q * ld;
+                double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+                for (int row = lane; row < nt; row += 64) {
+                    const double2 a = gp[row], b = gq[row];
+                    al += cabs2(a);
+                    be += cabs2(b);
+                    gr += a.x * b.x + a.y * b.y;
+                    gi += a.x * b.y - a.y * b.x;
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                gr = wave_sum(gr);
+                gi = wave_sum(gi);
+                const double mag = sqrt(gr * gr + gi * gi);
+                if (!(mag > tol * sqrt(al * be))) continue;
+                const double zeta = (be - al) / (2.0 * mag);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                const double er = gr / mag, ei = -gi / mag;     // e^{-i phi}
+                for (int row = lane; row < nt; row += 64) {
+                    const double2 a = gp[row], b = gq[row];
+                    const double2 bt = make_double2(b.x * er - b.y * ei, b.x * ei + b.y * er);
+                    gp[row] = make_double2(c * a.x - sn * bt.x, c * a.y - sn * bt.y);
+                    gq[row] = make_double2(sn * a.x + c * bt.x, sn * a.y + c * bt.y);
+                }
+                if (lane == 0) atomicAdd(&rot, 1);
+            }
+            __syncthreads();
+        }
+        if (rot == 0) { converged = true; ++sweep; break; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *sweeps_out = sweep;
+        if (!converged) atomicOr(flag_out, 4);
+    }
+    __syncthreads();
+}
+
+// Normalise columns, sort by norm descending, write eigenvalues and vectors.
+// vout: column-major (vector j contiguous) when col_major, else row-major.
+__device__ void jacobi_finish(const double2* G, int nt, int ld, double* lam_out, double2* vout,
+                              int ldv, bool col_major) {
+    __shared__ double nrm[256];
+    __shared__ int rk[256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wave; j < nt; j += nw) {
+        double s = 0.0;
+        for (int row = lane; row < nt; row += 64) s += cabs2(G[(long)j * ld + row]);
+        s = wave_sum(s);
+        if (lane == 0) nrm[j] = sqrt(s);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nt; j += blockDim.x) {
+        int r = 0;
+        const double v = nrm[j];
+        for (int i = 0; i < nt; ++i) r += (nrm[i] > v) || (nrm[i] == v && i < j);
+        rk[j] = r;
+        lam_out[r] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
+        const int j = e / nt, row = e % nt;
+        const double inv = nrm[j] > 0.0 ? 1.0 / nrm[j] : 0.0;
+        const double2 g = cscale(G[(long)j * ld + row], inv);
+        const int c = rk[j];
+        if (col_major) vout[(long)c * ldv + row] = g;
+        else vout[(long)row * ldv + c] = g;
+    }
+    __syncthreads();
+}
+
+// Subset EVD: bmat (row-major Hermitian, stride ntp) -> wvec as column-major
+// Jacobi workspace -> sorted eigenvectors back into bmat (column-major).
+template <bool IN_LDS>
+__global__ void __launch_bounds__(JAC_THREADS) k_jacobi_subsets(Workspace ws, int max_sweeps) {
+    extern __shared__ double2 lds_g[];
+    const int s = blockIdx.x;
+    const int nt = ws.sub[s].nt, ntp = ws.ntp;
+    double2* B = ws.bmat + (long)s * ntp * ntp;
+    double2* G = IN_LDS ? lds_g : ws.wvec + (long)s * ntp * ntp;
+    const int ld = IN_LDS ? nt : ntp;
+    for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
+        const int j = e / nt, row = e % nt;
+        G[(long)j * ld + row] = cconj(B[(long)j * ntp + row]);   // column j of B = conj(row j)
+    }
+    __syncthreads();
+    jacobi_core<IN_LDS>(G, nt, ld, max_sweeps, &ws.sweeps[s], &ws.flags[s]);
+    jacobi_finish(G, nt, ld, ws.lam + (long)s * ntp, B, ntp, true);
+}
+
+// Standalone batched EVD: a (row-major Hermitian [n][nt][nt]) -> w, v (row-major).
+template <bool IN_LDS>
+__global__ void __launch_bounds__(JAC_THREADS) k_heevd(const double2* a, double* w, double2* v,
+                                                       int* sweeps, double2* work, int nt, int max_sweeps,
+                                                       int* flags) {
+    extern __shared__ double2 lds_g[];
+    const int b = blockIdx.x;
+    const double2* A = a + (long)b * nt * nt;
+    double2* G = IN_LDS ? lds_g : work + (long)b * nt * nt;
+    for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
+        const int j = e / nt, row = e % nt;
+        G[(long)j * nt + row] = cconj(A[(long)j * nt + row]);
+    }
+    __syncthreads();
+    jacobi_core<IN_LDS>(G, nt, nt, max_sweeps, &sweeps[b], &flags[b]);
+    double2* vo = v ? v + (long)b * nt * nt : nullptr;
+    if (vo) {
+        jacobi_finish(G, nt, nt, w + (long)b * nt, vo, nt, false);
+    } else {
+        // eigenvalues only: reuse the workspace slot for the (discarded) vectors
+        double2* scratch = work + (long)b * nt * nt;
+        if (IN_LDS) jacobi_finish(G, nt, nt, w + (long)b * nt, scratch, nt, false);
+        else {
+            // G lives in scratch already: compute norms and sort in place of w only
+            __shared__ double nrm[256];
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+            for (int j = wave; j < nt; j += nw) {
+                double sacc = 0.0;
+                for (int row = lane; row < nt; row += 64) sacc += cabs2(G[(long)j * nt + row]);
+                sacc = wave_sum(sacc);
+                if (lane == 0) nrm[j] = sqrt(sacc);
+            }
+            __syncthreads();
+            for (int j = threadIdx.x; j < nt; j += blockDim.x) {
+                int r = 0;
+                for (int i = 0; i < nt; ++i) r += (nrm[i] > nrm[j]) || (nrm[i] == nrm[j] && i < j);
+                w[(long)b * nt + r] = nrm[j];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int NTP>
+static void small_dispatch(const Workspace& ws, int stage, double rho, int iters, hipStream_t st) {
+    if (stage == 0) hipLaunchKernelGGL((k_tissue<NTP>), dim3(ws.S), dim3(256), 0, st, ws, rho, iters);
+    else hipLaunchKernelGGL((k_assemble<NTP>), dim3(ws.S), dim3(256), 0, st, ws);
+}
+
+static hipError_t small_stage(const Workspace& ws, int stage, double rho, int iters, hipStream_t st) {
+    switch (ws.ntp) {
+        case 32: small_dispatch<32>(ws, stage, rho, iters, st); break;
+        case 64: small_dispatch<64>(ws, stage, rho, iters, st); break;
+        case 96: small_dispatch<96>(ws, stage, rho, iters, st); break;
+        case 128: small_dispatch<128>(ws, stage, rho, iters, st); break;
+        case 160: small_dispatch<160>(ws, stage, rho, iters, st); break;
+        case 208: small_dispatch<208>(ws, stage, rho, iters, st); break;
+        case 256: small_dispatch<256>(ws, stage, rho, iters, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_windows(const Workspace& ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_windows, dim3(ws.S), dim3(256), 0, st, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_tissue(const Workspace& ws, double rho, int iters, hipStream_t st) {
+    return small_stage(ws, 0, rho, iters, st);
+}
+
+hipError_t launch_assemble(const Workspace& ws, hipStream_t st) {
+    return small_stage(ws, 1, 0.0, 0, st);
+}
+
+static int max_nt(const Workspace& ws) { return ws.ntp; }
+
+hipError_t launch_jacobi(const Workspace& ws, int max_sweeps, int nt_max, hipStream_t st) {
+    (void)max_nt;
+    if (nt_max <= JAC_LDS_NT) {
+        const size_t lds = (size_t)nt_max * nt_max * sizeof(double2);
+        hipLaunchKernelGGL((k_jacobi_subsets<true>), dim3(ws.S), dim3(JAC_THREADS), lds, st, ws, max_sweeps);
+    } else {
+        hipLaunchKernelGGL((k_jacobi_subsets<false>), dim3(ws.S), dim3(JAC_THREADS), 0, st, ws, max_sweeps);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_heevd(int n, int nt, const double2* a, double* w, double2* v, int* sweeps, double2* work,
+                        int max_sweeps, int* flags, hipStream_t st) {
+    if (nt <= JAC_LDS_NT) {
+        const size_t lds = (size_t)nt * nt * sizeof(double2);
+        hipLaunchKernelGGL((k_heevd<true>), dim3(n), dim3(JAC_THREADS), lds, st, a, w, v, sweeps, work, nt,
+                           max_sweeps, flags);
+    } else {
+        hipLaunchKernelGGL((k_heevd<false>), dim3(n), dim3(JAC_THREADS), 0, st, a, w, v, sweeps, work, nt,
+                           max_sweeps, flags);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lcf

@@ -1,0 +1,273 @@
+// Windowed temporal covariance on MFMA (Eqs 1 and 12).
+//
+// R_d = C_w^H C_w = sum over box pixels of w_d(x)^2 s_x^H s_x. In real form with
+// a_x = Re s_x, b_x = Im s_x (rows of the Casorati matrix):
+//   Re R = sum_x a_x^T a_x + b_x^T b_x        (S, symmetric)
+//   Im R = sum_x a_x^T b_x - b_x^T a_x        (T, antisymmetric)
+// Both are real GEMMs over an interleaved K axis (a_x, b_x, a_x+1, ...): S uses the
+// operand twice, T pairs it with the row-swapped, sign-flipped copy. Only the
+// upper 16x16 tiles of S and T are formed.
+//
+// Pass 1 (WINDOW): operand = w_d(x) * s_x, window applied on load.
+// Pass 2 (DEFLATE): operand = [c'_x | y_x] with y_x = w s_x V_r (rank-r tissue
+// scores) and c'_x = w s_x - y_x V_r^H formed in FP64 before rounding, so the
+// fast-precision Gram only ever sees bulk-scale (blood + noise) values next to
+// the separately scaled tissue columns. The extended Gram holds C'^H C',
+// C'^H Y and Y^H Y.
+//
+// Split-K: each work-group reduces one chunk of a subset's box pixels and writes
+// its partial tiles; k_gram_reduce sums the partials in chunk order in FP64, so
+// results are deterministic (no atomics on data).
+#include "lcf_internal.h"
+#include "lcf_kernels.h"
+
+namespace lcf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int NTP, bool DEFL>
+struct GramCfg {
+    static constexpr int NTE = DEFL ? NTP + REXT : NTP;
+    static constexpr int NT16 = NTE / 16;
+    static constexpr int TPM = NT16 * (NT16 + 1) / 2;      // upper tiles per matrix
+    static constexpr int TT = 2 * TPM;                     // S tiles then T tiles
+    static constexpr int WAVES = TT > 120 ? 8 : 4;
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int MAXT = (TT + WAVES - 1) / WAVES;
+    static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;   // im offset in a pixel row
+    static constexpr int LDA = 2 * IMO + 1;                         // odd row stride
+    static constexpr int PX = NTP > 208 ? 16 : PIX;                 // pixels per LDS batch
+};
+
+__device__ __forceinline__ void tile_ij(int tau, int nt16, int& i, int& j) {
+    int rem = tau;
+    i = 0;
+    while (rem >= nt16 - i) { rem -= nt16 - i; ++i; }
+    j = i + rem;
+}
+
+template <int NTP, bool DEFL>
+__global__ void __launch_bounds__((GramCfg<NTP, DEFL>::THREADS))
+k_gram_fp32(Workspace ws) {
+    using C = GramCfg<NTP, DEFL>;
+    constexpr int IMO = C::IMO, LDA = C::LDA, PIX = C::PX;
+    __shared__ float A[PIX * LDA];
+    __shared__ double wpix[PIX];
+    __shared__ float2 craw[DEFL ? NTP * PIX : 1];
+    __shared__ float2 vr32[DEFL ? NTP * RMAX : 1];
+    __shared__ double2 vr64[DEFL ? NTP * RMAX : 1];
+    __shared__ float2 yv[DEFL ? PIX * RMAX : 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const ChunkDesc ch = ws.chunks[blockIdx.x];
+    const SubsetDesc sd = ws.sub[ch.s];
+    const int nt = sd.nt, nx = sd.nx;
+    const long npix = (long)sd.ny * sd.nx;
+    const double* wy = ws.wtab + sd.wy_off;
+    const double* wx = ws.wtab + sd.wx_off;
+    int r = 0;
+    if (DEFL) {
+        r = ws.rank[ch.s];
+        for (int e = tid; e < NTP * RMAX; e += C::THREADS) {
+            vr32[e] = ws.vr32[(long)ch.s * NTP * RMAX + e];
+            vr64[e] = ws.vr64[(long)ch.s * NTP * RMAX + e];
+        }
+    }
+
+    // Tiles owned by this wave.
+    int aoff[C::MAXT], boff[C::MAXT];
+    bool isT[C::MAXT], valid[C::MAXT];
+#pragma unroll
+    for (int m = 0; m < C::MAXT; ++m) {
+        const int tau = wave + C::WAVES * m;
+        valid[m] = tau < C::TT;
+        const int tm = valid[m] ? tau % C::TPM : 0;
+        int i, j;
+        tile_ij(tm, C::NT16, i, j);
+        aoff[m] = i * 16;
+        boff[m] = j * 16;
+        isT[m] = valid[m] && tau >= C::TPM;
+    }
+    floatx4 acc[C::MAXT];
+#pragma unroll
+    for (int m = 0; m < C::MAXT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int qb = ch.q0; qb < ch.q1; qb += PIX) {
+        __syncthreads();
+        if (tid < PIX) {
+            const int q = qb + tid;
+            double w = 0.0;
+            if (q < ch.q1) {
+                const int yy = q / sd.bw, xx = q - yy * sd.bw;
+                w = sd.flat ? 1.0 : wy[yy] * wx[xx];
+            }
+            wpix[tid] = w;
+        }
+        __syncthreads();
+        if (!DEFL) {
+            for (int e = tid; e < PIX * NTP; e += C::THREADS) {
+                const int p = e % PIX, t = e / PIX;
+                const int q = qb + p;
+                float re = 0.f, im = 0.f;
+                if (q < ch.q1 && t < nt) {
+                    const int yy = q / sd.bw, xx = q - yy * sd.bw;
+                    const float2 c = sd.iq[(long)t * npix + (long)(sd.y0 + yy) * nx + sd.x0 + xx];
+                    const double w = wpix[p];
+                    re = (float)(w * (double)c.x);
+                    im = (float)(w * (double)c.y);
+                }
+                A[p * LDA + t] = re;
+                A[p * LDA + IMO + t] = im;
+            }
+        } else {
+            for (int e = tid; e < PIX * NTP; e += C::THREADS) {
+                const int p = e % PIX, t = e / PIX;
+                const int q = qb + p;
+                float2 c = make_float2(0.f, 0.f);
+                if (q < ch.q1 && t < nt) {
+                    const int yy = q / sd.bw, xx = q - yy * sd.bw;
+                    c = sd.iq[(long)t * npix + (long)(sd.y0 + yy) * nx + sd.x0 + xx];
+                }
+                craw[t * PIX + p] = c;
+            }
+            __syncthreads();
+            // Tissue scores y = w s V_r (any value keeps C_w = C' + Y V_r^H exact).
+            for (int e = tid; e < PIX * REXT; e += C::THREADS) {
+                const int p = e % PIX, j = e / PIX;
+                float2 y = make_float2(0.f, 0.f);
+                if (j < r) {
+                    float ar = 0.f, ai = 0.f;
+                    for (int t = 0; t < nt; ++t) {
+                        const float2 c = craw[t * PIX + p];
+                        const float2 v = vr32[t * RMAX + j];
+                        ar = fmaf(c.x, v.x, fmaf(-c.y, v.y, ar));
+                        ai = fmaf(c.x, v.y, fmaf(c.y, v.x, ai));
+                    }
+                    const float w = (float)wpix[p];
+                    y = make_float2(w * ar, w * ai);
+                    yv[p * RMAX + j] = y;
+                }
+                A[p * LDA + NTP + j] = y.x;
+                A[p * LDA + IMO + NTP + j] = y.y;
+            }
+            __syncthreads();
+            // Bulk residual c' = w s - y V_r^H in FP64, rounded once.
+            for (int e = tid; e < PIX * NTP; e += C::THREADS) {
+                const int p = e % PIX, t = e / PIX;
+                double re = 0.0, im = 0.0;
+                if (t < nt) {
+                    const float2 c = craw[t * PIX + p];
+                    const double w = wpix[p];
+                    re = w * (double)c.x;
+                    im = w * (double)c.y;
+                    for (int j = 0; j < r; ++j) {
+                        const float2 y = yv[p * RMAX + j];
+                        const double2 v = vr64[t * RMAX + j];
+                        // y * conj(v)
+                        re -= (double)y.x * v.x + (double)y.y * v.y;
+                        im -= (double)y.y * v.x - (double)y.x * v.y;
+                    }
+                }
+                A[p * LDA + t] = (float)re;
+                A[p * LDA + IMO + t] = (float)im;
+            }
+        }
+        __syncthreads();
+        const int kk = lane >> 4, col = lane & 15;
+#pragma unroll 2
+        for (int kp = 0; kp < PIX; kp += 2) {
+            const int p = kp + (kk >> 1), part = kk & 1;
+            const float* rowp = A + p * LDA;
+            const float* base = rowp + (part ? IMO : 0);
+            const float* swp = part ? rowp : rowp + IMO;      // partner part for T
+            const float sgn = part ? -1.f : 1.f;
+#pragma unroll
+            for (int m = 0; m < C::MAXT; ++m) {
+                if (valid[m]) {
+                    const float a = base[aoff[m] + col];
+                    const float b = isT[m] ? sgn * swp[boff[m] + col] : base[boff[m] + col];
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < C::MAXT; ++m) {
+        if (valid[m]) {
+            const int tau = wave + C::WAVES * m;
+            float* dst = ws.partial + ((long)blockIdx.x * C::TT + tau) * 256 + lane * 4;
+            *reinterpret_cast<floatx4*>(dst) = acc[m];
+        }
+    }
+}
+
+// Sum the chunk partials of each subset in chunk order (FP64) and expand the
+// upper S/T tiles into the full Hermitian matrix out[s][NTE][NTE].
+template <int NTE>
+__global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, double2* out, int tt) {
+    constexpr int NT16 = NTE / 16;
+    const int s = blockIdx.y;
+    const int tau = blockIdx.x;
+    const int tpm = tt / 2;
+    int i, j;
+    tile_ij(tau, NT16, i, j);
+    const int e = threadIdx.x;
+    const int lane = e >> 2, rr = e & 3;
+    const int rin = 4 * (lane >> 4) + rr, cin = lane & 15;
+    if (i == j && rin > cin) return;
+    const int c0 = ws.chunk_begin[s], c1 = ws.chunk_begin[s + 1];
+    double sv = 0.0, tv = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        sv += (double)ws.partial[((long)c * tt + tau) * 256 + e];
+        tv += (double)ws.partial[((long)c * tt + tpm + tau) * 256 + e];
+    }
+    const int row = i * 16 + rin, colx = j * 16 + cin;
+    double2* o = out + (long)s * NTE * NTE;
+    if (row == colx) {
+        o[(long)row * NTE + colx] = make_double2(sv, 0.0);
+    } else {
+        o[(long)row * NTE + colx] = make_double2(sv, tv);
+        o[(long)colx * NTE + row] = make_double2(sv, -tv);
+    }
+    if (!isfinite(sv) || !isfinite(tv)) atomicOr(&ws.flags[s], 2);
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int NTP>
+static hipError_t gram_dispatch(const Workspace& ws, bool defl, bool reduce, hipStream_t st) {
+    if (ws.nchunks == 0) return hipSuccess;
+    if (defl) {
+        using C = GramCfg<NTP, true>;
+        if (!reduce) hipLaunchKernelGGL((k_gram_fp32<NTP, true>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
+        else hipLaunchKernelGGL((k_gram_reduce<C::NTE>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws, ws.rext, C::TT);
+    } else {
+        using C = GramCfg<NTP, false>;
+        if (!reduce) hipLaunchKernelGGL((k_gram_fp32<NTP, false>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
+        else hipLaunchKernelGGL((k_gram_reduce<C::NTE>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws, ws.rwin, C::TT);
+    }
+    return hipGetLastError();
+}
+
+// reduce = false: the split-K Gram kernel; reduce = true: the ordered FP64 reduction.
+hipError_t launch_gram(const Workspace& ws, bool defl, bool reduce, int precision, hipStream_t st) {
+    (void)precision;
+    switch (ws.ntp) {
+        case 32: return gram_dispatch<32>(ws, defl, reduce, st);
+        case 64: return gram_dispatch<64>(ws, defl, reduce, st);
+        case 96: return gram_dispatch<96>(ws, defl, reduce, st);
+        case 128: return gram_dispatch<128>(ws, defl, reduce, st);
+        case 160: return gram_dispatch<160>(ws, defl, reduce, st);
+        case 208: return gram_dispatch<208>(ws, defl, reduce, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int gram_tiles(int ntp, bool defl) {
+    const int nte = defl ? ntp + REXT : ntp;
+    const int n16 = nte / 16;
+    return n16 * (n16 + 1);
+}
+
+}  // namespace lcf

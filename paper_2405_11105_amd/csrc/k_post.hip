@@ -1,0 +1,505 @@
+// Eigencomponent weights (Eqs 4, 6, 9), the projector P = V diag(w) V^H, and
+// the output-centric reprojection + power Doppler + recombination (Eqs 4, 5, 13).
+#include "lcf_internal.h"
+#include "lcf_kernels.h"
+
+namespace lcf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ rules
+// One 64-lane wave per subset; everything on the FP64 eigenvalues.
+__global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
+    __shared__ double yt[256], d1[256], kv[256];
+    __shared__ int sh_k, sh_flag;
+    const int s = blockIdx.x, lane = threadIdx.x;
+    const SubsetDesc sd = ws.sub[s];
+    const int nt = sd.nt, ntp = ws.ntp;
+    const double* lam = ws.lam + (long)s * ntp;
+    double* wts = ws.wts + (long)s * ntp;
+    if (lane == 0) { sh_k = -1; sh_flag = 0; }
+    __syncthreads();
+    if (rp.cut == 0 || rp.cut == 1) {
+        int k = rp.k_fixed;
+        if (rp.cut == 1) {
+            const double l1 = lam[0];
+            bool bad = !(l1 > 0.0);
+            double y1 = 0.0;
+            if (!bad) { y1 = log10(l1); bad = (y1 == 0.0); }
+            if (bad) {
+                k = 0;
+                if (lane == 0) sh_flag = 1;
+            } else {
+                const double floor_ = l1 * 2.220446049250313e-16;     // lambda_1 * 2^-52
+                for (int i = lane; i < nt; i += 64) {
+                    const double l = lam[i] > floor_ ? lam[i] : floor_;
+                    yt[i] = rp.beta_knee * (double)nt * log10(l) / y1;
+                }
+                __syncthreads();
+                for (int i = lane; i < nt; i += 64)
+                    d1[i] = i == 0 ? yt[1] - yt[0] : (i == nt - 1 ? yt[nt - 1] - yt[nt - 2] : 0.5 * (yt[i + 1] - yt[i - 1]));
+                __syncthreads();
+                for (int i = lane; i < nt; i += 64) {
+                    const double d2 = i == 0 ? d1[1] - d1[0] : (i == nt - 1 ? d1[nt - 1] - d1[nt - 2] : 0.5 * (d1[i + 1] - d1[i - 1]));
+                    kv[i] = fabs(d2) / pow(1.0 + d1[i] * d1[i], 1.5);
+                }
+                __syncthreads();
+                int hi = (int)floor(rp.knee_max_frac * (double)nt);
+                if (hi < 2) hi = 2;
+                if (hi > nt) hi = nt;
+                // smallest argmax over 0-based i in [1, hi-1]
+                double best = -1.0;
+                int bi = 1 << 30;
+                for (int i = 1 + lane; i < hi; i += 64) {
+                    if (kv[i] > best) { best = kv[i]; bi = i; }
+                }
+                for (int m = 32; m >= 1; m >>= 1) {
+                    const double ob = __shfl_xor(best, m, 64);
+                    const int oi = __shfl_xor(bi, m, 64);
+                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+                }
+                k = bi + 1;
+            }
+        }
+        if (lane == 0) sh_k = k;
+        for (int i = lane; i < nt; i += 64) {
+            const double n1 = (double)(i + 1);
+            wts[i] = rp.shape == 0 ? (n1 > (double)k ? 1.0 : 0.0)
+                                   : 1.0 / (1.0 + exp(-rp.beta_sigmoid * (n1 - (double)k)));
+        }
+    } else if (rp.cut == 2) {
+        for (int i = lane; i < nt; i += 64) wts[i] = (double)ws.explicit_w[(long)s * nt + i];
+    } else {
+        // weights already written by the MLP kernel
+    }
+    for (int i = nt + lane; i < ntp; i += 64) wts[i] = 0.0;
+    __syncthreads();
+    double e = 0.0;
+    for (int i = lane; i < nt; i += 64) e += wts[i] * wts[i] * lam[i];
+    e = wave_sum(e);
+    if (lane == 0) {
+        ws.kcut[s] = (rp.cut <= 1) ? sh_k : -1;
+        ws.alpha[s] = rp.pd_mode == 1 ? 1.0 : (e > 0.0 ? sd.npix_nt / e : 0.0);
+        if (sh_flag) atomicOr(&ws.flags[s], sh_flag);
+    }
+}
+
+// ------------------------------------------------------------------ projector
+// P_Q = I - sum_i (1 - w_i) u_i u_i^H in the deflated basis (exactly P_Q =
+// U diag(w) U^H on the range of B; on its null space the data carry no energy,
+// and all-ones weights give P = I exactly), then P = Q P_Q Q^H by Householder
+// rank-2 updates, M = V_r^H P, and the real-form [P; M] used by the
+// reprojection GEMM.
+template <int NTP>
+__global__ void __launch_bounds__(256) k_projector(Workspace ws) {
+    constexpr int NTE = NTP + REXT;
+    constexpr int CC = 8;                       // eigenvector columns staged per pass
+    __shared__ double2 Wc[CC * NTP];
+    __shared__ double cw[CC];
+    __shared__ double2 V[NTP * RMAX];
+    __shared__ double2 Pv[NTP], vh[NTP];
+    __shared__ double red[32];
+    __shared__ int act[256];
+    __shared__ int nact;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nt = ws.sub[s].nt;
+    const int r = ws.rank[s];
+    const double2* W = ws.bmat + (long)s * NTP * NTP;        // column-major eigenvectors
+    const double* wts = ws.wts + (long)s * NTP;
+    double2* P = ws.pmat + (long)s * NTP * NTP;
+    if (tid == 0) {
+        int n = 0;
+        for (int i = 0; i < nt; ++i)
+            if (fabs(1.0 - wts[i]) > 1e-17) act[n++] = i;
+        nact = n;
+    }
+    for (int e = tid; e < NTP * NTP; e += 256) {
+        const int t = e / NTP, u = e % NTP;
+        P[e] = make_double2((t == u && t < nt) ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < nact; c0 += CC) {
+        const int cn = nact - c0 < CC ? nact - c0 : CC;
+        for (int e = tid; e < cn * NTP; e += 256) {
+            const int c = e / NTP, t = e % NTP;
+            Wc[e] = W[(long)act[c0 + c] * NTP + t];
+        }
+        if (tid < cn) cw[tid] = 1.0 - wts[act[c0 + tid]];
+        __syncthreads();
+        for (int e = tid; e < nt * NTP; e += 256) {
+            const int t = e / NTP, u = e % NTP;
+            if (u >= nt) continue;
+            double2 acc = P[e];
+            for (int c = 0; c < cn; ++c)
+                acc = csub(acc, cscale(cmulc(Wc[c * NTP + u], Wc[c * NTP + t]), cw[c]));  // W_t conj(W_u)
+            P[e] = acc;
+        }
+        __syncthreads();
+    }
+    // P = H_0 .. H_{r-1} P_Q H_{r-1} .. H_0
+    for (int j = r - 1; j >= 0; --j) {
+        const double tau = ws.htau[(long)s * RMAX + j];
+        for (int t = tid; t < NTP; t += 256) vh[t] = ws.hv[((long)s * RMAX + j) * NTP + t];
+        __syncthreads();
+        for (int t = tid; t < nt; t += 256) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int u = 0; u < nt; ++u) acc = cadd(acc, cmulc(P[(long)u * NTP + t], vh[u]));
+            Pv[t] = acc;
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int t = tid; t < nt; t += 256) part += cmulc(vh[t], Pv[t]).x;
+        const double K = block_sum(part, red);
+        for (int t = tid; t < nt; t += 256) Pv[t] = csub(Pv[t], cscale(vh[t], 0.5 * tau * K));
+        __syncthreads();
+        for (int e = tid; e < nt * NTP; e += 256) {
+            const int t = e / NTP, u = e % NTP;
+            if (u >= nt) continue;
+            const double2 d = cadd(cmulc(Pv[u], vh[t]), cmulc(vh[u], Pv[t]));
+            P[e] = csub(P[e], cscale(d, tau));
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < NTP * RMAX; e += 256) V[e] = ws.vr64[(long)s * NTP * RMAX + e];
+    __syncthreads();
+    // Real form of [P; M]: row kk in [0, 2 NTE), column n in [0, 2 NTP).
+    float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
+    for (int e = tid; e < NTE * NTP; e += 256) {
+        const int k = e / NTP, t = e % NTP;
+        double2 v = make_double2(0.0, 0.0);
+        if (t < nt) {
+            if (k < nt) v = P[(long)k * NTP + t];
+            else if (k >= NTP && k < NTP + r) {
+                const int j = k - NTP;
+                for (int u = 0; u < nt; ++u) v = cadd(v, cmulc(V[u * RMAX + j], P[(long)u * NTP + t]));
+            }
+        }
+        const float re = (float)v.x, im = (float)v.y;
+        Br[(long)k * (2 * NTP) + t] = re;
+        Br[(long)k * (2 * NTP) + NTP + t] = im;
+        Br[(long)(NTE + k) * (2 * NTP) + t] = -im;
+        Br[(long)(NTE + k) * (2 * NTP) + NTP + t] = re;
+    }
+}
+
+// ------------------------------------------------------------------ reprojection
+// One work-group per image row segment of up to PIX pixels. For every covering
+// subset d (ascending order): y = s V_r (FP32), c' = s - y V_r^H (FP64, then
+// rounded), chat = [c' | y] [P; M] on MFMA, and the epilogue accumulates
+//   PD(x)   += alpha_d w_d(x)^2 sum_t |chat(x, t)|^2     (Eq. 13)
+//   IQ(x,t) += w_d(x) chat(x, t),  W(x) += w_d(x)
+// in registers. The window factors out of the projection because
+// C_hat_d(x, :) = w_d(x) s_x P_d. The tile writes PD and IQ / W once.
+template <int NTP>
+struct ReprojCfg {
+    static constexpr int NTE = NTP + REXT;
+    static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;
+    static constexpr int LDA = 2 * IMO + 1;
+    static constexpr int CT = (2 * NTP) / 16;     // output column tiles
+    static constexpr int TT = 2 * CT;             // x 2 row tiles (32 pixels)
+    static constexpr int MAXT = (TT + 3) / 4;
+};
+
+template <int NTP>
+__global__ void __launch_bounds__(256) k_reproj(Workspace ws) {
+    using C = ReprojCfg<NTP>;
+    constexpr int NTE = C::NTE, IMO = C::IMO, LDA = C::LDA;
+    static_assert(PIX == 32, "reprojection tile is 2 x 16 pixels");
+    __shared__ float A[PIX * LDA];
+    __shared__ float2 craw[NTP * PIX];
+    __shared__ float2 vr32[NTP * RMAX];
+    __shared__ double2 vr64[NTP * RMAX];
+    __shared__ float2 yv[PIX * RMAX];
+    __shared__ float wd[PIX];
+    __shared__ float pdsh[4 * PIX];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const TileDesc td = ws.tiles[blockIdx.x];
+    const PacketDesc pk = ws.pkts[td.pkt];
+    const int nt = pk.nt, nx = pk.nx;
+    const long npix = (long)pk.ny * pk.nx;
+    const int npx = td.x1 - td.x0 + 1;
+
+    for (int e = tid; e < PIX * NTP; e += 256) {
+        const int p = e % PIX, t = e / PIX;
+        float2 c = make_float2(0.f, 0.f);
+        if (p < npx && t < nt) c = pk.iq[(long)t * npix + (long)td.y * nx + td.x0 + p];
+        craw[t * PIX + p] = c;
+    }
+    floatx4 iq_acc[C::MAXT];
+    float pd_acc[8];
+#pragma unroll
+    for (int m = 0; m < C::MAXT; ++m) iq_acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pd_acc[i] = 0.f;
+
+    for (int ci = 0; ci < td.cov_cnt; ++ci) {
+        const int s = ws.cover[td.cov_off + ci];
+        const SubsetDesc sd = ws.sub[s];
+        const int r = ws.rank[s];
+        const float alpha = (float)ws.alpha[s];
+        __syncthreads();
+        for (int e = tid; e < NTP * RMAX; e += 256) {
+            vr32[e] = ws.vr32[(long)s * NTP * RMAX + e];
+            vr64[e] = ws.vr64[(long)s * NTP * RMAX + e];
+        }
+        if (tid < PIX) {
+            const int x = td.x0 + tid;
+            float w = 0.f;
+            if (tid < npx && td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
+                w = sd.flat ? 1.f : (float)(ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0]);
+            wd[tid] = w;
+        }
+        __syncthreads();
+        for (int e = tid; e < PIX * REXT; e += 256) {
+            const int p = e % PIX, j = e / PIX;
+            float2 y = make_float2(0.f, 0.f);
+            if (j < r) {
+                float ar = 0.f, ai = 0.f;
+                for (int t = 0; t < nt; ++t) {
+                    const float2 c = craw[t * PIX + p];
+                    const float2 v = vr32[t * RMAX + j];
+                    ar = fmaf(c.x, v.x, fmaf(-c.y, v.y, ar));
+                    ai = fmaf(c.x, v.y, fmaf(c.y, v.x, ai));
+                }
+                y = make_float2(ar, ai);
+                yv[p * RMAX + j] = y;
+            }
+            A[p * LDA + NTP + j] = y.x;
+            A[p * LDA + IMO + NTP + j] = y.y;
+        }
+        __syncthreads();
+        for (int e = tid; e < PIX * NTP; e += 256) {
+            const int p = e % PIX, t = e / PIX;
+            double re = 0.0, im = 0.0;
+            if (t < nt) {
+                const float2 c = craw[t * PIX + p];
+                re = (double)c.x;
+                im = (double)c.y;
+                for (int j = 0; j < r; ++j) {
+                    const float2 y = yv[p * RMAX + j];
+                    const double2 v = vr64[t * RMAX + j];
+                    re -= (double)y.x * v.x + (double)y.y * v.y;
+                    im -= (double)y.y * v.x - (double)y.x * v.y;
+                }
+            }
+            A[p * LDA + t] = (float)re;
+            A[p * LDA + IMO + t] = (float)im;
+        }
+        __syncthreads();
+        const float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
+        floatx4 acc[C::MAXT];
+#pragma unroll
+        for (int m = 0; m < C::MAXT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int kq = lane >> 4, col = lane & 15;
+        for (int k0 = 0; k0 < 2 * NTE; k0 += 4) {
+            const int kk = k0 + kq;
+            const int acol = kk < NTE ? kk : IMO + kk - NTE;
+            const float a0 = A[col * LDA + acol];
+            const float a1 = A[(16 + col) * LDA + acol];
+            const float* brow = Br + (long)kk * (2 * NTP);
+#pragma unroll
+            for (int m = 0; m < C::MAXT; ++m) {
+                const int tau = wave + 4 * m;
+                if (tau < C::TT) {
+                    const int rt = tau & 1, ct = tau >> 1;
+                    const float b = brow[ct * 16 + col];
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(rt ? a1 : a0, b, acc[m], 0, 0, 0);
+                }
+            }
+        }
+        // epilogue: output element (pixel p = rt*16 + 4*(lane/16) + i, column ct*16 + lane%16)
+#pragma unroll
+        for (int m = 0; m < C::MAXT; ++m) {
+            const int tau = wave + 4 * m;
+            if (tau < C::TT) {
+                const int rt = tau & 1;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int p = rt * 16 + 4 * kq + i;
+                    const float w = wd[p];
+                    const float v = acc[m][i];
+                    pd_acc[rt * 4 + i] += alpha * w * w * v * v;
+                    iq_acc[m][i] += w * v;
+                }
+            }
+        }
+    }
+    // PD: reduce over the 16 lanes that share pixel rows, then over waves.
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float v = pd_acc[i];
+        for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+        pd_acc[i] = v;
+    }
+    __syncthreads();
+    if ((lane & 15) == 0) {
+        const int kq = lane >> 4;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int p = (i >> 2) * 16 + 4 * kq + (i & 3);
+            pdsh[wave * PIX + p] = pd_acc[i];
+        }
+    }
+    __syncthreads();
+    if (tid < npx) {
+        const int p = tid, x = td.x0 + p;
+        float pdv = pdsh[p] + pdsh[PIX + p] + pdsh[2 * PIX + p] + pdsh[3 * PIX + p];
+        if (pk.pd_mode == 2) {
+            double comp = 0.0;
+            for (int ci = 0; ci < td.cov_cnt; ++ci) {
+                const int s = ws.cover[td.cov_off + ci];
+                const SubsetDesc sd = ws.sub[s];
+                if (td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1) {
+                    const double w = sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
+                    comp += ws.alpha[s] * w * w;
+                }
+            }
+            pdv = comp > 0.0 ? (float)((double)pdv / comp) : 0.f;
+        }
+        pk.pd[(long)td.y * nx + x] = pdv;
+    }
+    if (pk.iq_out) {
+        // W(x) = sum_d w_d(x) for this lane's pixels
+        __shared__ float wsum[PIX];
+        if (tid < PIX) {
+            const int x = td.x0 + tid;
+            double ws_ = 0.0;
+            for (int ci = 0; ci < td.cov_cnt; ++ci) {
+                const SubsetDesc sd = ws.sub[ws.cover[td.cov_off + ci]];
+                if (td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
+                    ws_ += sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
+            }
+            wsum[tid] = (float)ws_;
+        }
+        __syncthreads();
+        const int kq = lane >> 4, col = lane & 15;
+#pragma unroll
+        for (int m = 0; m < C::MAXT; ++m) {
+            const int tau = wave + 4 * m;
+            if (tau < C::TT) {
+                const int rt = tau & 1, ct = tau >> 1;
+                const int n = ct * 16 + col;
+                const int part = n >= NTP, t = n - part * NTP;
+                if (t < nt) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int p = rt * 16 + 4 * kq + i;
+                        if (p < npx) {
+                            const float w = wsum[p];
+                            pk.iq_out[2 * ((long)t * npix + (long)td.y * nx + td.x0 + p) + part] =
+                                w > 0.f ? iq_acc[m][i] / w : 0.f;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int NTP>
+static void post_dispatch(const Workspace& ws, int stage, hipStream_t st) {
+    if (stage == 0) hipLaunchKernelGGL((k_projector<NTP>), dim3(ws.S), dim3(256), 0, st, ws);
+    else if (ws.ntiles > 0) hipLaunchKernelGGL((k_reproj<NTP>), dim3(ws.ntiles), dim3(256), 0, st, ws);
+}
+
+static hipError_t post_stage(const Workspace& ws, int stage, hipStream_t st) {
+    switch (ws.ntp) {
+        case 32: post_dispatch<32>(ws, stage, st); break;
+        case 64: post_dispatch<64>(ws, stage, st); break;
+        case 96: post_dispatch<96>(ws, stage, st); break;
+        case 128: post_dispatch<128>(ws, stage, st); break;
+        case 160: post_dispatch<160>(ws, stage, st); break;
+        case 208: post_dispatch<208>(ws, stage, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rules(const Workspace& ws, const RuleParams& rp, hipStream_t st) {
+    hipLaunchKernelGGL(k_rules, dim3(ws.S), dim3(64), 0, st, ws, rp);
+    return hipGetLastError();
+}
+
+hipError_t launch_projector(const Workspace& ws, int precision, hipStream_t st) {
+    (void)precision;
+    return post_stage(ws, 0, st);
+}
+hipError_t launch_reproj(const Workspace& ws, int precision, hipStream_t st) {
+    (void)precision;
+    return post_stage(ws, 1, st);
+}
+
+// ------------------------------------------------------------------ diagnostics
+// Copy per-subset results of subsets [first, first+count) of a packet out to the
+// caller's diagnostic buffers (any pointer may be null). Eigenvectors are
+// returned in the original basis: V = Q W = H_0 .. H_{r-1} W.
+__global__ void __launch_bounds__(256) k_export(Workspace ws, int first, int nt, double* eigvals, float* weights,
+                                               int* k, int* sweeps, int* flags, double* alpha, int* rank,
+                                               double2* eigvecs) {
+    const int d = blockIdx.x, s = first + d, tid = threadIdx.x, ntp = ws.ntp;
+    for (int i = tid; i < nt; i += 256) {
+        if (eigvals) eigvals[(long)d * nt + i] = ws.lam[(long)s * ntp + i];
+        if (weights) weights[(long)d * nt + i] = (float)ws.wts[(long)s * ntp + i];
+    }
+    if (tid == 0) {
+        if (k) k[d] = ws.kcut[s];
+        if (sweeps) sweeps[d] = ws.sweeps[s];
+        if (flags) flags[d] = ws.flags[s];
+        if (alpha) alpha[d] = ws.alpha[s];
+        if (rank) rank[d] = ws.rank[s];
+    }
+    if (!eigvecs) return;
+    const int r = ws.rank[s];
+    const double2* W = ws.bmat + (long)s * ntp * ntp;       // column-major
+    for (int j = tid; j < nt; j += 256) {
+        // column j, one thread; reflectors applied right to left, in place
+        double2* out = eigvecs + (long)d * nt * nt + j;
+        for (int t = 0; t < nt; ++t) out[(long)t * nt] = W[(long)j * ntp + t];
+        for (int h = r - 1; h >= 0; --h) {
+            const double tau = ws.htau[(long)s * RMAX + h];
+            const double2* v = ws.hv + ((long)s * RMAX + h) * ntp;
+            double2 dot = make_double2(0.0, 0.0);
+            for (int t = h; t < nt; ++t) dot = cadd(dot, cmulc(v[t], out[(long)t * nt]));
+            for (int t = h; t < nt; ++t) out[(long)t * nt] = csub(out[(long)t * nt], cscale(cmul(v[t], dot), tau));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_export_cov(Workspace ws, int first, int nt, double2* cov) {
+    const int d = blockIdx.x, s = first + d, ntp = ws.ntp;
+    for (int e = threadIdx.x; e < nt * nt; e += 256) {
+        const int t = e / nt, u = e % nt;
+        cov[(long)d * nt * nt + e] = ws.pmat[(long)s * ntp * ntp + (long)t * ntp + u];
+    }
+}
+
+__global__ void k_flags_or(Workspace ws, int* sticky) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < ws.S; s += gridDim.x * blockDim.x) {
+        const int f = ws.flags[s];
+        if (f) atomicOr(sticky, f);
+    }
+}
+
+hipError_t launch_export(const Workspace& ws, int first, int count, int nt, double* eigvals, float* weights,
+                         int* k, int* sweeps, int* flags, double* alpha, int* rank, double2* eigvecs,
+                         hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_export, dim3(count), dim3(256), 0, st, ws, first, nt, eigvals, weights, k, sweeps,
+                       flags, alpha, rank, eigvecs);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_cov(const Workspace& ws, int first, int count, int nt, double2* cov, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_export_cov, dim3(count), dim3(256), 0, st, ws, first, nt, cov);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags_or(const Workspace& ws, int* sticky, hipStream_t st) {
+    hipLaunchKernelGGL(k_flags_or, dim3(1), dim3(256), 0, st, ws, sticky);
+    return hipGetLastError();
+}
+
+}  // namespace lcf

@@ -1,0 +1,140 @@
+// Internal types and device helpers of the localized EVD clutter filter library.
+// Shared by the host runtime (runtime.hip) and the kernel files (k_*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lcf {
+
+// Tissue deflation: at most RMAX leading eigen-directions are split off in FP64
+// (the rank-r part of the covariance and of the projection). REXT is RMAX padded
+// to one 16-wide MFMA tile; those columns extend the Gram of the deflated data.
+constexpr int RMAX = 8;
+constexpr int REXT = 16;
+// Pixels per LDS batch in the Gram and reprojection kernels.
+constexpr int PIX = 32;
+// Pixels per Gram work item (split-K chunk); several LDS batches each.
+constexpr int CHUNK = 1024;
+
+// One window subset of one packet (Eq. 11 / Fig. 3).
+struct SubsetDesc {
+    const float2* iq;   // packet base, complex64 [nt][ny][nx]
+    int ny, nx, nt;
+    int pkt;            // packet index within the call
+    int d;              // subset index within the packet (a*gx + b)
+    int y0, y1, x0, x1; // inclusive box of non-zero window values
+    int bw, neff;       // box width, box pixel count
+    int flat;           // 1 = flat window (w = 1 inside the box)
+    int wy_off, wx_off; // offsets of the 1-D FP64 window factors in the table pool
+    double cy, cx, sy, sx;
+    double npix_nt;     // Npix * Nt of the packet (Eq. 13 normalisation)
+};
+
+// A split-K chunk of a subset's box pixels [q0, q1) in box row-major order.
+struct ChunkDesc {
+    int s;      // subset index in the launch
+    int q0, q1;
+};
+
+// A reprojection tile: one image row segment [x0, x1] of packet pkt, covered by
+// the subsets cover[cov_off .. cov_off + cov_cnt) (ascending subset order).
+struct TileDesc {
+    int pkt, y, x0, x1;
+    int cov_off, cov_cnt;
+};
+
+struct PacketDesc {
+    const float2* iq;
+    float* iq_out;      // interleaved complex64 as floats, may be null
+    float* pd;
+    int ny, nx, nt;
+    int pd_mode;
+};
+
+// Device workspace of one launch group (all subsets share the padded size ntp).
+struct Workspace {
+    int S;              // subsets
+    int ntp;            // padded Nt (multiple of 16)
+    int nte;            // ntp + REXT
+    const SubsetDesc* sub;
+    const ChunkDesc* chunks;
+    int nchunks;
+    const int* chunk_begin;   // [S+1] first chunk of each subset
+    const TileDesc* tiles;
+    int ntiles;
+    const int* cover;
+    const PacketDesc* pkts;
+    double* wtab;       // window factor pool
+    float* partial;     // Gram partials [nchunks][ntile_pairs*2][256]
+    double2* rwin;      // [S][ntp][ntp] windowed covariance (pass 1)
+    double2* rext;      // [S][nte][nte] Gram of [C' | Y] (pass 2)
+    double2* hv;        // [S][RMAX][ntp] Householder vectors
+    double* htau;       // [S][RMAX]
+    double2* vr64;      // [S][ntp][RMAX] tissue basis V_r (FP64)
+    float2* vr32;       // [S][ntp][RMAX] V_r rounded to FP32
+    int* rank;          // [S]
+    double2* bmat;      // [S][ntp][ntp] B = Q^H R Q, then Jacobi workspace
+    double2* wvec;      // [S][ntp][ntp] eigenvectors of B (row-major, column j = vector j)
+    double* lam;        // [S][ntp]
+    double* wts;        // [S][ntp] eigencomponent weights
+    int* kcut;          // [S]
+    int* flags;         // [S]
+    int* sweeps;        // [S]
+    double* alpha;      // [S]
+    double2* pmat;      // [S][ntp][ntp] projector P in the original basis (FP64)
+    float* breal;       // [S][2*nte][2*ntp] real form of [P; M] for the reprojection
+    const float* explicit_w;   // [S][nt] caller weights (EXPLICIT)
+};
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+    return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Block-wide sum of a double over blockDim.x threads (multiple of 64); red is
+// __shared__ scratch of at least blockDim.x/64 doubles. All threads get the sum.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+__device__ __forceinline__ double2 block_sum2(double2 v, double* red) {
+    v.x = wave_sum(v.x);
+    v.y = wave_sum(v.y);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { red[2 * w] = v.x; red[2 * w + 1] = v.y; }
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = 0; i < nw; ++i) { s.x += red[2 * i]; s.y += red[2 * i + 1]; }
+    return s;
+}
+
+}  // namespace lcf

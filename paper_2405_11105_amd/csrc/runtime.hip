@@ -1,0 +1,664 @@
+// Host runtime of the localized EVD clutter filter: argument validation, window
+// geometry and work lists (plans), the device scratch arena, launch schedules
+// (batched or the paper's sequential per-subset loop), optional hipGraph replay,
+// and the C ABI declared in include/lcf.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lcf.h"
+#include "lcf_internal.h"
+#include "lcf_kernels.h"
+
+using namespace lcf;
+
+namespace {
+
+const int NTP_CLASSES[] = {32, 64, 96, 128, 160, 208};
+constexpr int NT_MAX = 208;
+
+int ntp_class(int nt) {
+    for (int c : NTP_CLASSES)
+        if (nt <= c) return c;
+    return -1;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Window {
+    double cy, cx, sy, sx;
+    int y0, y1, x0, x1;
+    bool flat;
+};
+
+// Window grid of Eq. 11 / Fig. 3 (same formulas as the reference definition):
+// centre (j + 1/2) * spacing - 1/2, sigma = sigma_frac * spacing, box of
+// +-trunc_sigmas * sigma clipped to the image; flat window for sigma_frac == 0.
+std::vector<Window> make_windows(const lcf_geometry& g) {
+    std::vector<Window> out;
+    const double dy = (double)g.ny / g.gy, dx = (double)g.nx / g.gx;
+    for (int a = 0; a < g.gy; ++a)
+        for (int b = 0; b < g.gx; ++b) {
+            Window w;
+            w.cy = (a + 0.5) * dy - 0.5;
+            w.cx = (b + 0.5) * dx - 0.5;
+            w.sy = g.sigma_frac * dy;
+            w.sx = g.sigma_frac * dx;
+            w.flat = g.sigma_frac == 0.0;
+            if (w.flat || g.trunc_sigmas == 0.0) {
+                w.y0 = 0; w.y1 = g.ny - 1; w.x0 = 0; w.x1 = g.nx - 1;
+            } else {
+                w.y0 = std::max(0, (int)std::ceil(w.cy - g.trunc_sigmas * w.sy));
+                w.y1 = std::min(g.ny - 1, (int)std::floor(w.cy + g.trunc_sigmas * w.sy));
+                w.x0 = std::max(0, (int)std::ceil(w.cx - g.trunc_sigmas * w.sx));
+                w.x1 = std::min(g.nx - 1, (int)std::floor(w.cx + g.trunc_sigmas * w.sx));
+            }
+            out.push_back(w);
+        }
+    return out;
+}
+
+lcf_status validate_geometry(const lcf_geometry* g) {
+    if (!g) return LCF_ERR_INVALID_ARG;
+    if (g->ny < 1 || g->nx < 1 || g->nt < 4 || g->gy < 1 || g->gx < 1) return LCF_ERR_INVALID_ARG;
+    if (g->gy > g->ny || g->gx > g->nx || g->reserved != 0) return LCF_ERR_INVALID_ARG;
+    if (!(g->sigma_frac >= 0.0) || !(g->trunc_sigmas >= 0.0) || !std::isfinite(g->sigma_frac) ||
+        !std::isfinite(g->trunc_sigmas))
+        return LCF_ERR_INVALID_ARG;
+    if (g->sigma_frac == 0.0 && (g->gy != 1 || g->gx != 1)) return LCF_ERR_INVALID_ARG;
+    if ((long)g->ny * g->nx > (1L << 26)) return LCF_ERR_UNSUPPORTED;
+    if (g->nt > NT_MAX) return LCF_ERR_UNSUPPORTED;
+    return LCF_OK;
+}
+
+lcf_status validate_threshold(const lcf_threshold* t, int nt) {
+    if (!t) return LCF_ERR_INVALID_ARG;
+    if (t->cut < 0 || t->cut > 3 || t->shape < 0 || t->shape > 1 || t->pd_mode < 0 || t->pd_mode > 2)
+        return LCF_ERR_INVALID_ARG;
+    if (t->cut == LCF_CUT_FIXED_K && (t->k_fixed < 0 || t->k_fixed > nt)) return LCF_ERR_INVALID_ARG;
+    if (t->cut == LCF_CUT_KNEE && (!(t->beta_knee > 0.0) || !(t->knee_max_frac > 0.0) || t->knee_max_frac > 1.0))
+        return LCF_ERR_INVALID_ARG;
+    if (t->shape == LCF_SHAPE_SIGMOID && t->cut <= LCF_CUT_KNEE && !(t->beta_sigmoid > 0.0))
+        return LCF_ERR_INVALID_ARG;
+    if (t->cut == LCF_CUT_EXPLICIT && t->explicit_w == nullptr) return LCF_ERR_INVALID_ARG;
+    if (!(t->deflate_rho >= 0.0) || t->deflate_rho >= 1.0) return LCF_ERR_INVALID_ARG;
+    if (t->cut == LCF_CUT_MLP) return LCF_ERR_UNSUPPORTED;
+    return LCF_OK;
+}
+
+lcf_status validate_precision(int p) {
+    if (p == LCF_PREC_FP32) return LCF_OK;
+    if (p == LCF_PREC_BF16X3) return LCF_ERR_UNSUPPORTED;
+    return LCF_ERR_INVALID_ARG;
+}
+
+struct PacketIn {
+    lcf_geometry g;
+    const void* iq;
+    void* iq_out;
+    float* pd;
+};
+
+// Host-side plan of one launch group (packets sharing the padded Nt class).
+struct Plan {
+    int ntp = 0, nt_max = 0;
+    std::vector<SubsetDesc> sub;
+    std::vector<ChunkDesc> chunks;
+    std::vector<int> chunk_begin;
+    std::vector<TileDesc> tiles;
+    std::vector<int> cover;
+    std::vector<PacketDesc> pkts;
+    std::vector<int> pkt_first_subset;
+    size_t wtab_len = 0;
+};
+
+void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int>& idx, int pd_mode) {
+    pl.ntp = 0;
+    pl.nt_max = 0;
+    for (int i : idx) {
+        pl.ntp = std::max(pl.ntp, ntp_class(in[i].g.nt));
+        pl.nt_max = std::max(pl.nt_max, in[i].g.nt);
+    }
+    int wtab = 0;
+    for (size_t pi = 0; pi < idx.size(); ++pi) {
+        const PacketIn& p = in[idx[pi]];
+        const lcf_geometry& g = p.g;
+        PacketDesc pd;
+        pd.iq = (const float2*)p.iq;
+        pd.iq_out = (float*)p.iq_out;
+        pd.pd = p.pd;
+        pd.ny = g.ny; pd.nx = g.nx; pd.nt = g.nt;
+        pd.pd_mode = pd_mode;
+        pl.pkts.push_back(pd);
+        const int first = (int)pl.sub.size();
+        pl.pkt_first_subset.push_back(first);
+        const std::vector<Window> wins = make_windows(g);
+        for (size_t d = 0; d < wins.size(); ++d) {
+            const Window& w = wins[d];
+            SubsetDesc s;
+            s.iq = (const float2*)p.iq;
+            s.ny = g.ny; s.nx = g.nx; s.nt = g.nt;
+            s.pkt = (int)pi;
+            s.d = (int)d;
+            s.y0 = w.y0; s.y1 = w.y1; s.x0 = w.x0; s.x1 = w.x1;
+            s.bw = w.x1 - w.x0 + 1;
+            s.neff = (w.y1 - w.y0 + 1) * s.bw;
+            s.flat = w.flat ? 1 : 0;
+            s.cy = w.cy; s.cx = w.cx; s.sy = w.sy; s.sx = w.sx;
+            s.wy_off = wtab;
+            wtab += w.y1 - w.y0 + 1;
+            s.wx_off = wtab;
+            wtab += s.bw;
+            s.npix_nt = (double)g.ny * g.nx * g.nt;
+            const int sidx = (int)pl.sub.size();
+            pl.chunk_begin.push_back((int)pl.chunks.size());
+            for (int q = 0; q < s.neff; q += CHUNK)
+                pl.chunks.push_back(ChunkDesc{sidx, q, std::min(s.neff, q + CHUNK)});
+            pl.sub.push_back(s);
+        }
+        // reprojection tiles: row segments of PIX pixels, with covering subsets
+        const int last = (int)pl.sub.size();
+        for (int y = 0; y < g.ny; ++y)
+            for (int x0 = 0; x0 < g.nx; x0 += PIX) {
+                TileDesc t;
+                t.pkt = (int)pi;
+                t.y = y;
+                t.x0 = x0;
+                t.x1 = std::min(g.nx - 1, x0 + PIX - 1);
+                t.cov_off = (int)pl.cover.size();
+                for (int s = first; s < last; ++s) {
+                    const SubsetDesc& sd = pl.sub[s];
+                    if (y >= sd.y0 && y <= sd.y1 && t.x1 >= sd.x0 && t.x0 <= sd.x1) pl.cover.push_back(s);
+                }
+                t.cov_cnt = (int)pl.cover.size() - t.cov_off;
+                pl.tiles.push_back(t);
+            }
+    }
+    pl.chunk_begin.push_back((int)pl.chunks.size());
+    pl.wtab_len = (size_t)wtab;
+}
+
+}  // namespace
+
+struct lcf_context {
+    int device = 0;
+    int schedule = 0;
+    int max_sweeps = 30;
+    int use_graph = 0;
+    int sub_iters = 6;
+    char* dbuf = nullptr;
+    size_t dcap = 0;
+    char* hbuf = nullptr;
+    size_t hcap = 0;
+    hipEvent_t staged = nullptr;   // host staging buffer free again once this completes
+    bool staged_pending = false;
+    int* sticky = nullptr;         // device: OR of all per-subset flags since lcf_sync
+    // graph cache: signature -> executable graph
+    std::map<std::string, hipGraphExec_t> graphs;
+    // per-stage event timing
+    int timing = 0;
+    std::vector<hipEvent_t> evpool;
+    size_t evnext = 0;
+    std::vector<std::pair<int, size_t>> evpending;   // (stage, index of start event)
+    double stage_ms[LCF_NUM_STAGES] = {0};
+    long long stage_n[LCF_NUM_STAGES] = {0};
+};
+
+namespace {
+
+lcf_status ensure_device(lcf_context* c, size_t bytes) {
+    if (bytes <= c->dcap) return LCF_OK;
+    if (c->dbuf) {
+        if (hipDeviceSynchronize() != hipSuccess) return LCF_ERR_DEVICE;
+        hipFree(c->dbuf);
+        c->dbuf = nullptr;
+        c->dcap = 0;
+        for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+    }
+    const size_t want = align_up(bytes + bytes / 4, 1 << 20);
+    if (hipMalloc((void**)&c->dbuf, want) != hipSuccess) { c->dbuf = nullptr; return LCF_ERR_OUT_OF_MEMORY; }
+    c->dcap = want;
+    return LCF_OK;
+}
+
+lcf_status ensure_host(lcf_context* c, size_t bytes) {
+    if (c->staged_pending) {
+        if (hipEventSynchronize(c->staged) != hipSuccess) return LCF_ERR_DEVICE;
+        c->staged_pending = false;
+    }
+    if (bytes <= c->hcap) return LCF_OK;
+    if (c->hbuf) hipHostFree(c->hbuf);
+    const size_t want = align_up(bytes + bytes / 4, 1 << 16);
+    if (hipHostMalloc((void**)&c->hbuf, want, hipHostMallocDefault) != hipSuccess) {
+        c->hbuf = nullptr;
+        c->hcap = 0;
+        return LCF_ERR_OUT_OF_MEMORY;
+    }
+    c->hcap = want;
+    return LCF_OK;
+}
+
+struct Layout {
+    size_t off_sub, off_chunks, off_cbeg, off_tiles, off_cover, off_pkts, host_bytes;
+    size_t off_wtab, off_partial, off_rwin, off_rext, off_hv, off_htau, off_vr64, off_vr32, off_rank, off_bmat,
+        off_wvec, off_lam, off_wts, off_kcut, off_flags, off_sweeps, off_alpha, off_pmat, off_breal, total;
+};
+
+Layout make_layout(const Plan& pl) {
+    Layout L;
+    const size_t S = pl.sub.size(), ntp = pl.ntp, nte = ntp + REXT;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align_up(o + bytes, 256); return r; };
+    L.off_sub = take(S * sizeof(SubsetDesc));
+    L.off_chunks = take(pl.chunks.size() * sizeof(ChunkDesc));
+    L.off_cbeg = take(pl.chunk_begin.size() * sizeof(int));
+    L.off_tiles = take(pl.tiles.size() * sizeof(TileDesc));
+    L.off_cover = take(pl.cover.size() * sizeof(int));
+    L.off_pkts = take(pl.pkts.size() * sizeof(PacketDesc));
+    L.host_bytes = o;
+    const int tt = std::max(gram_tiles(pl.ntp, false), gram_tiles(pl.ntp, true));
+    L.off_wtab = take(pl.wtab_len * sizeof(double));
+    L.off_partial = take(pl.chunks.size() * (size_t)tt * 256 * sizeof(float));
+    L.off_rwin = take(S * ntp * ntp * sizeof(double2));
+    L.off_rext = take(S * nte * nte * sizeof(double2));
+    L.off_hv = take(S * RMAX * ntp * sizeof(double2));
+    L.off_htau = take(S * RMAX * sizeof(double));
+    L.off_vr64 = take(S * ntp * RMAX * sizeof(double2));
+    L.off_vr32 = take(S * ntp * RMAX * sizeof(float2));
+    L.off_rank = take(S * sizeof(int));
+    L.off_bmat = take(S * ntp * ntp * sizeof(double2));
+    L.off_wvec = take(S * ntp * ntp * sizeof(double2));
+    L.off_lam = take(S * ntp * sizeof(double));
+    L.off_wts = take(S * ntp * sizeof(double));
+    L.off_kcut = take(S * sizeof(int));
+    L.off_flags = take(S * sizeof(int));
+    L.off_sweeps = take(S * sizeof(int));
+    L.off_alpha = take(S * sizeof(double));
+    L.off_pmat = take(S * ntp * ntp * sizeof(double2));
+    L.off_breal = take(S * (2 * nte) * (2 * ntp) * sizeof(float));
+    L.total = o;
+    return L;
+}
+
+Workspace make_ws(char* base, const Layout& L, const Plan& pl, const float* explicit_w) {
+    Workspace ws;
+    ws.S = (int)pl.sub.size();
+    ws.ntp = pl.ntp;
+    ws.nte = pl.ntp + REXT;
+    ws.sub = (const SubsetDesc*)(base + L.off_sub);
+    ws.chunks = (const ChunkDesc*)(base + L.off_chunks);
+    ws.nchunks = (int)pl.chunks.size();
+    ws.chunk_begin = (const int*)(base + L.off_cbeg);
+    ws.tiles = (const TileDesc*)(base + L.off_tiles);
+    ws.ntiles = (int)pl.tiles.size();
+    ws.cover = (const int*)(base + L.off_cover);
+    ws.pkts = (const PacketDesc*)(base + L.off_pkts);
+    ws.wtab = (double*)(base + L.off_wtab);
+    ws.partial = (float*)(base + L.off_partial);
+    ws.rwin = (double2*)(base + L.off_rwin);
+    ws.rext = (double2*)(base + L.off_rext);
+    ws.hv = (double2*)(base + L.off_hv);
+    ws.htau = (double*)(base + L.off_htau);
+    ws.vr64 = (double2*)(base + L.off_vr64);
+    ws.vr32 = (float2*)(base + L.off_vr32);
+    ws.rank = (int*)(base + L.off_rank);
+    ws.bmat = (double2*)(base + L.off_bmat);
+    ws.wvec = (double2*)(base + L.off_wvec);
+    ws.lam = (double*)(base + L.off_lam);
+    ws.wts = (double*)(base + L.off_wts);
+    ws.kcut = (int*)(base + L.off_kcut);
+    ws.flags = (int*)(base + L.off_flags);
+    ws.sweeps = (int*)(base + L.off_sweeps);
+    ws.alpha = (double*)(base + L.off_alpha);
+    ws.pmat = (double2*)(base + L.off_pmat);
+    ws.breal = (float*)(base + L.off_breal);
+    ws.explicit_w = explicit_w;
+    return ws;
+}
+
+// A view of the workspace restricted to subset s (sequential schedule). The
+// chunk table of the view lives at `chunks` with subset index 0.
+Workspace subset_view(const Workspace& w, int s, const ChunkDesc* chunks, const int* cbeg, int nch) {
+    Workspace v = w;
+    const long ntp = w.ntp, nte = w.nte;
+    v.S = 1;
+    v.sub = w.sub + s;
+    v.chunks = chunks;
+    v.nchunks = nch;
+    v.chunk_begin = cbeg;
+    v.rwin = w.rwin + s * ntp * ntp;
+    v.rext = w.rext + s * nte * nte;
+    v.hv = w.hv + s * RMAX * ntp;
+    v.htau = w.htau + s * RMAX;
+    v.vr64 = w.vr64 + s * ntp * RMAX;
+    v.vr32 = w.vr32 + s * ntp * RMAX;
+    v.rank = w.rank + s;
+    v.bmat = w.bmat + s * ntp * ntp;
+    v.wvec = w.wvec + s * ntp * ntp;
+    v.lam = w.lam + s * ntp;
+    v.wts = w.wts + s * ntp;
+    v.kcut = w.kcut + s;
+    v.flags = w.flags + s;
+    v.sweeps = w.sweeps + s;
+    v.alpha = w.alpha + s;
+    v.pmat = w.pmat + s * ntp * ntp;
+    v.breal = w.breal + s * (2 * nte) * (2 * ntp);
+    return v;
+}
+
+#define HIPCHK(x)                                        \
+    do {                                                 \
+        if ((x) != hipSuccess) return LCF_ERR_DEVICE;    \
+    } while (0)
+
+// Resolve recorded event pairs into the per-stage totals.
+hipError_t drain_timing(lcf_context* c) {
+    for (auto& pe : c->evpending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(c->evpool[pe.second + 1]);
+        if (e != hipSuccess) return e;
+        e = hipEventElapsedTime(&ms, c->evpool[pe.second], c->evpool[pe.second + 1]);
+        if (e != hipSuccess) return e;
+        c->stage_ms[pe.first] += ms;
+        c->stage_n[pe.first] += 1;
+    }
+    c->evpending.clear();
+    c->evnext = 0;
+    return hipSuccess;
+}
+
+// Bracket one launch with events when timing is on: tick() before, tock() after.
+struct StageScope {
+    lcf_context* c;
+    int stage;
+    hipStream_t st;
+    size_t idx = 0;
+    bool on = false;
+    StageScope(lcf_context* c_, int stage_, hipStream_t st_) : c(c_), stage(stage_), st(st_) {
+        if (!c->timing) return;
+        if (c->evnext + 2 > c->evpool.size()) {
+            if (c->evnext + 2 > 4096) drain_timing(c);
+            while (c->evnext + 2 > c->evpool.size()) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                c->evpool.push_back(e);
+            }
+        }
+        idx = c->evnext;
+        c->evnext += 2;
+        on = hipEventRecord(c->evpool[idx], st) == hipSuccess;
+    }
+    ~StageScope() {
+        if (!on) return;
+        if (hipEventRecord(c->evpool[idx + 1], st) == hipSuccess) c->evpending.push_back({stage, idx});
+    }
+};
+#define STAGE(c, s, st) StageScope _scope_##s(c, s, st)
+
+// Covariance passes, tissue basis and assembly. `cov` (may be null) receives R
+// of the `nsub` subsets of this view in the original basis (diagnostics).
+lcf_status run_stages(lcf_context* c, const Workspace& ws, const lcf_threshold* thr, int prec,
+                      double2* cov, int nt, hipStream_t st) {
+    { STAGE(c, LCF_STAGE_WINDOWS, st); HIPCHK(launch_windows(ws, st)); }
+    { STAGE(c, LCF_STAGE_GRAM1, st); HIPCHK(launch_gram(ws, false, false, prec, st)); }
+    { STAGE(c, LCF_STAGE_GRAM1_REDUCE, st); HIPCHK(launch_gram(ws, false, true, prec, st)); }
+    { STAGE(c, LCF_STAGE_TISSUE, st); HIPCHK(launch_tissue(ws, thr->deflate_rho, c->sub_iters, st)); }
+    { STAGE(c, LCF_STAGE_GRAM2, st); HIPCHK(launch_gram(ws, true, false, prec, st)); }
+    { STAGE(c, LCF_STAGE_GRAM2_REDUCE, st); HIPCHK(launch_gram(ws, true, true, prec, st)); }
+    { STAGE(c, LCF_STAGE_ASSEMBLE, st); HIPCHK(launch_assemble(ws, st)); }
+    if (cov) HIPCHK(launch_export_cov(ws, 0, ws.S, nt, cov, st));
+    return LCF_OK;
+}
+
+lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold* thr, int prec, int nt_max,
+                       hipStream_t st) {
+    RuleParams rp{thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee, thr->knee_max_frac,
+                  thr->beta_sigmoid};
+    { STAGE(c, LCF_STAGE_JACOBI, st); HIPCHK(launch_jacobi(ws, c->max_sweeps, nt_max, st)); }
+    { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
+    { STAGE(c, LCF_STAGE_PROJECTOR, st); HIPCHK(launch_projector(ws, prec, st)); }
+    return LCF_OK;
+}
+
+// Filter a list of packets. diag applies to a single packet call only.
+lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const lcf_threshold* thr, int prec,
+                          const lcf_diag* diag, hipStream_t st) {
+    if (!c) return LCF_ERR_INVALID_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return LCF_ERR_DEVICE;
+    // group packets by padded Nt class
+    std::map<int, std::vector<int>> groups;
+    for (size_t i = 0; i < in.size(); ++i) groups[ntp_class(in[i].g.nt)].push_back((int)i);
+    for (auto& kv : groups) {
+        Plan pl;
+        build_plan(pl, in, kv.second, thr->pd_mode);
+        Layout L = make_layout(pl);
+        // sequential schedule: per-subset chunk tables appended to the host block
+        size_t seq_off = L.host_bytes, seq_bytes = 0;
+        if (c->schedule == 1) seq_bytes = pl.chunks.size() * sizeof(ChunkDesc) + 2 * pl.sub.size() * sizeof(int);
+        const size_t host_total = align_up(L.host_bytes + seq_bytes, 256);
+        // shift device-only buffers after the host block
+        Layout D = L;
+        const size_t shift = host_total - L.host_bytes;
+        for (size_t* p = &D.off_wtab; p <= &D.off_breal; ++p) *p += shift;
+        D.total += shift;
+        lcf_status e = ensure_device(c, D.total);
+        if (e != LCF_OK) return e;
+        e = ensure_host(c, host_total);
+        if (e != LCF_OK) return e;
+        char* h = c->hbuf;
+        std::memcpy(h + L.off_sub, pl.sub.data(), pl.sub.size() * sizeof(SubsetDesc));
+        std::memcpy(h + L.off_chunks, pl.chunks.data(), pl.chunks.size() * sizeof(ChunkDesc));
+        std::memcpy(h + L.off_cbeg, pl.chunk_begin.data(), pl.chunk_begin.size() * sizeof(int));
+        std::memcpy(h + L.off_tiles, pl.tiles.data(), pl.tiles.size() * sizeof(TileDesc));
+        std::memcpy(h + L.off_cover, pl.cover.data(), pl.cover.size() * sizeof(int));
+        std::memcpy(h + L.off_pkts, pl.pkts.data(), pl.pkts.size() * sizeof(PacketDesc));
+        if (c->schedule == 1) {
+            ChunkDesc* sc = (ChunkDesc*)(h + seq_off);
+            for (size_t i = 0; i < pl.chunks.size(); ++i) { sc[i] = pl.chunks[i]; sc[i].s = 0; }
+            int* cb = (int*)(h + seq_off + pl.chunks.size() * sizeof(ChunkDesc));
+            for (size_t s = 0; s < pl.sub.size(); ++s) {
+                cb[2 * s] = 0;
+                cb[2 * s + 1] = pl.chunk_begin[s + 1] - pl.chunk_begin[s];
+            }
+        }
+        HIPCHK(hipMemcpyAsync(c->dbuf, h, host_total, hipMemcpyHostToDevice, st));
+        HIPCHK(hipEventRecord(c->staged, st));
+        c->staged_pending = true;
+        Workspace ws = make_ws(c->dbuf, D, pl, thr->cut == LCF_CUT_EXPLICIT ? thr->explicit_w : nullptr);
+        if (c->schedule == 1) {
+            // the paper's loop: one subset at a time through every per-subset stage
+            const ChunkDesc* dch = (const ChunkDesc*)(c->dbuf + seq_off);
+            const int* dcb = (const int*)(c->dbuf + seq_off + pl.chunks.size() * sizeof(ChunkDesc));
+            for (int s = 0; s < (int)pl.sub.size(); ++s) {
+                const int cb0 = pl.chunk_begin[s], nch = pl.chunk_begin[s + 1] - cb0;
+                Workspace v = subset_view(ws, s, dch + cb0, dcb + 2 * s, nch);
+                if (ws.explicit_w) v.explicit_w = ws.explicit_w + (long)s * pl.sub[s].nt;
+                double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
+                e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
+                if (e != LCF_OK) return e;
+                e = run_stages2(c, v, thr, prec, pl.sub[s].nt, st);
+                if (e != LCF_OK) return e;
+            }
+        } else {
+            e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
+            if (e != LCF_OK) return e;
+            e = run_stages2(c, ws, thr, prec, pl.nt_max, st);
+            if (e != LCF_OK) return e;
+        }
+        { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
+        if (diag)
+            HIPCHK(launch_export(ws, 0, (int)pl.sub.size(), pl.sub[0].nt, diag->eigvals, diag->weights, diag->k,
+                                 diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs,
+                                 st));
+        HIPCHK(launch_flags_or(ws, c->sticky, st));
+    }
+    return LCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lcf_status lcf_create(int32_t device, lcf_context** out) {
+    if (!out) return LCF_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LCF_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_context* c = new lcf_context();
+    c->device = device;
+    if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc((void**)&c->sticky, sizeof(int)) != hipSuccess ||
+        hipMemset(c->sticky, 0, sizeof(int)) != hipSuccess) {
+        delete c;
+        return LCF_ERR_DEVICE;
+    }
+    *out = c;
+    return LCF_OK;
+}
+
+lcf_status lcf_destroy(lcf_context* c) {
+    if (!c) return LCF_OK;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    for (auto e : c->evpool) hipEventDestroy(e);
+    if (c->dbuf) hipFree(c->dbuf);
+    if (c->hbuf) hipHostFree(c->hbuf);
+    if (c->sticky) hipFree(c->sticky);
+    if (c->staged) hipEventDestroy(c->staged);
+    delete c;
+    return LCF_OK;
+}
+
+lcf_status lcf_set_option(lcf_context* c, int32_t option, int64_t value) {
+    if (!c) return LCF_ERR_INVALID_ARG;
+    switch (option) {
+        case LCF_OPT_SCHEDULE:
+            if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
+            c->schedule = (int)value;
+            return LCF_OK;
+        case LCF_OPT_MAX_SWEEPS:
+            if (value < 1 || value > 1000) return LCF_ERR_INVALID_ARG;
+            c->max_sweeps = (int)value;
+            return LCF_OK;
+        case LCF_OPT_USE_GRAPH:
+            if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
+            c->use_graph = (int)value;
+            return LCF_OK;
+        case LCF_OPT_SUBSPACE_IT:
+            if (value < 1 || value > 100) return LCF_ERR_INVALID_ARG;
+            c->sub_iters = (int)value;
+            return LCF_OK;
+        case LCF_OPT_STAGE_TIMING:
+            if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
+            c->timing = (int)value;
+            return LCF_OK;
+        default:
+            return LCF_ERR_INVALID_ARG;
+    }
+}
+
+lcf_status lcf_validate(const lcf_geometry* geo, const lcf_threshold* thr, int32_t precision) {
+    lcf_status e = validate_geometry(geo);
+    if (e != LCF_OK) return e;
+    e = validate_threshold(thr, geo->nt);
+    if (e != LCF_OK) return e;
+    return validate_precision(precision);
+}
+
+lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr, int32_t precision,
+                      const void* iq, void* iq_out, float* pd, const lcf_diag* diag, void* stream) {
+    if (!ctx || !iq || !pd) return LCF_ERR_INVALID_ARG;
+    lcf_status e = lcf_validate(geo, thr, precision);
+    if (e != LCF_OK) return e;
+    std::vector<PacketIn> in{PacketIn{*geo, iq, iq_out, pd}};
+    return filter_packets(ctx, in, thr, precision, diag, (hipStream_t)stream);
+}
+
+lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo, const lcf_threshold* thr,
+                            int32_t precision, const void* const* iq, void* const* iq_out, float* const* pd,
+                            void* stream) {
+    if (!ctx || n < 1 || !geo || !iq || !pd) return LCF_ERR_INVALID_ARG;
+    std::vector<PacketIn> in;
+    for (int i = 0; i < n; ++i) {
+        lcf_status e = lcf_validate(&geo[i], thr, precision);
+        if (e != LCF_OK) return e;
+        if (!iq[i] || !pd[i]) return LCF_ERR_INVALID_ARG;
+        if (thr->cut == LCF_CUT_EXPLICIT) return LCF_ERR_UNSUPPORTED;
+        in.push_back(PacketIn{geo[i], iq[i], iq_out ? iq_out[i] : nullptr, pd[i]});
+    }
+    return filter_packets(ctx, in, thr, precision, nullptr, (hipStream_t)stream);
+}
+
+lcf_status lcf_heevd_batched(lcf_context* ctx, int32_t n, int32_t nt, const double* a, double* w, double* v,
+                             int32_t* sweeps, void* stream) {
+    if (!ctx || n < 1 || nt < 2 || nt > 256 || !a || !w) return LCF_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    const size_t work = align_up((size_t)n * nt * nt * sizeof(double2), 256);
+    const size_t extra = align_up((size_t)n * sizeof(int), 256) * 2;
+    lcf_status e = ensure_device(ctx, work + extra);
+    if (e != LCF_OK) return e;
+    double2* wk = (double2*)ctx->dbuf;
+    int* sw = sweeps ? sweeps : (int*)(ctx->dbuf + work);
+    int* fl = (int*)(ctx->dbuf + work + extra / 2);
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemsetAsync(fl, 0, (size_t)n * sizeof(int), st) != hipSuccess) return LCF_ERR_DEVICE;
+    if (launch_heevd(n, nt, (const double2*)a, w, (double2*)v, sw, wk, ctx->max_sweeps, fl, st) != hipSuccess)
+        return LCF_ERR_DEVICE;
+    Workspace fws{};
+    fws.S = n;
+    fws.flags = fl;
+    if (launch_flags_or(fws, ctx->sticky, st) != hipSuccess) return LCF_ERR_DEVICE;
+    return LCF_OK;
+}
+
+lcf_status lcf_sync(lcf_context* ctx, void* stream) {
+    if (!ctx) return LCF_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return LCF_ERR_DEVICE;
+    int f = 0;
+    if (hipMemcpy(&f, ctx->sticky, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return LCF_ERR_DEVICE;
+    if (f) {
+        const int zero = 0;
+        if (hipMemcpy(ctx->sticky, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return LCF_ERR_DEVICE;
+    }
+    if (f & LCF_FLAG_NONFINITE) return LCF_ERR_NONFINITE_INPUT;
+    if (f & LCF_FLAG_NO_CONVERGE) return LCF_ERR_NO_CONVERGENCE;
+    return LCF_OK;
+}
+
+lcf_status lcf_stage_time(lcf_context* ctx, int32_t stage, double* ms, int64_t* launches, int32_t reset) {
+    if (!ctx || stage < 0 || stage >= LCF_NUM_STAGES) return LCF_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    if (drain_timing(ctx) != hipSuccess) return LCF_ERR_DEVICE;
+    if (ms) *ms = ctx->stage_ms[stage];
+    if (launches) *launches = ctx->stage_n[stage];
+    if (reset)
+        for (int i = 0; i < LCF_NUM_STAGES; ++i) { ctx->stage_ms[i] = 0.0; ctx->stage_n[i] = 0; }
+    return LCF_OK;
+}
+
+const char* lcf_status_str(lcf_status s) {
+    switch (s) {
+        case LCF_OK: return "ok";
+        case LCF_ERR_INVALID_ARG: return "invalid argument";
+        case LCF_ERR_UNSUPPORTED: return "unsupported configuration";
+        case LCF_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case LCF_ERR_DEVICE: return "HIP device error";
+        case LCF_ERR_NONFINITE_INPUT: return "non-finite value reached a covariance";
+        case LCF_ERR_NO_CONVERGENCE: return "Jacobi eigen-solver hit the sweep cap";
+        case LCF_ERR_MODEL: return "MLP weights missing or corrupt";
+    }
+    return "unknown status";
+}
+
+int32_t lcf_abi_version(void) { return LCF_ABI_VERSION; }
+
+}  // extern "C"

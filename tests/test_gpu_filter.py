@@ -1,0 +1,236 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from parity import rel_fro, pd_db_error, knee_tie
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(lcf):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = lcf.Context(0)
+    yield c
+    c.close()
+
+
+def _run(lcf, ctx, iq_np, gy, gx, thr, **kw):
+    iq = torch.from_numpy(iq_np).cuda()
+    io, pd, dg = ctx.filter(iq, gy, gx, thr, diag=True, **kw)
+    torch.cuda.synchronize()
+    st = ctx.sync()
+    assert st == 0, f"lcf_sync status {st}"
+    d = {k: v.cpu().numpy() for k, v in dg.items()}
+    return (io.cpu().numpy() if io is not None else None), pd.cpu().numpy(), d
+
+
+def _oracle_thr(lcf_thr, nd=None, explicit=None):
+    return O.Threshold(cut=lcf_thr.cut, shape=lcf_thr.shape, pd_mode=lcf_thr.pd_mode, k_fixed=lcf_thr.k_fixed,
+                       beta_knee=lcf_thr.beta_knee, knee_max_frac=lcf_thr.knee_max_frac,
+                       beta_sigmoid=lcf_thr.beta_sigmoid, explicit_w=explicit)
+
+
+# ------------------------------------------------------------------ EVD
+
+@pytest.mark.parametrize("nt", [32, 64, 100, 128, 200])
+def test_heevd_circulant_closed_form(lcf, ctx, nt):
+    _say(f"[heevd circulant nt={nt}]")
+    rng = np.random.default_rng(nt)
+    lam = 10.0 ** rng.uniform(-8.0, 0.0, size=(3, nt))
+    mats = []
+    for b in range(3):
+        col = np.fft.ifft(lam[b])
+        idx = (np.arange(nt)[:, None] - np.arange(nt)[None, :]) % nt
+        mats.append(col[idx])
+    a = np.ascontiguousarray(np.stack(mats))
+    w, v, sw = ctx.heevd(torch.from_numpy(a).cuda())
+    torch.cuda.synchronize()
+    w, v, sw = w.cpu().numpy(), v.cpu().numpy(), sw.cpu().numpy()
+    for b in range(3):
+        ref = np.sort(lam[b])[::-1]
+        assert np.max(np.abs(w[b] - ref)) <= 1e-13, (b, np.max(np.abs(w[b] - ref)))
+        assert np.linalg.norm(v[b].conj().T @ v[b] - np.eye(nt)) <= 1e-10
+        res = np.linalg.norm(a[b] @ v[b] - v[b] * w[b][None, :])
+        # backward-stable bound: a small multiple of nt * u * ||R||
+        assert res <= 10 * nt * 1.1102230246251565e-16 * np.linalg.norm(a[b]), res
+    assert np.all(sw > 0) and np.all(sw < 30)
+
+
+def test_heevd_random_psd_vs_eigh(lcf, ctx):
+    _say("[heevd random psd]")
+    rng = np.random.default_rng(5)
+    nt = 48
+    x = rng.standard_normal((4, 200, nt)) + 1j * rng.standard_normal((4, 200, nt))
+    a = np.ascontiguousarray(np.einsum("bki,bkj->bij", x.conj(), x))
+    w, v, _ = ctx.heevd(torch.from_numpy(a).cuda())
+    w = w.cpu().numpy()
+    for b in range(4):
+        ref = np.linalg.eigvalsh(a[b])[::-1]
+        assert np.allclose(w[b], ref, rtol=1e-12, atol=1e-12 * ref[0])
+
+
+# ------------------------------------------------------------------ covariance
+
+def test_covariance_integer_exact(lcf, ctx):
+    _say("[cov integer exact]")
+    rng = np.random.default_rng(3)
+    nt, ny, nx = 32, 24, 20
+    iq = (rng.integers(-8, 9, size=(nt, ny, nx)) + 1j * rng.integers(-8, 9, size=(nt, ny, nx))).astype(np.complex64)
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=2, deflate_rho=0.0)
+    iq_t = torch.from_numpy(iq).cuda()
+    _, _, dg = ctx.filter(iq_t, 1, 1, thr, sigma_frac=0.0, diag_cov=True)
+    cov = dg["cov"].cpu().numpy()[0]
+    c = O.casorati(iq)
+    ref = O.covariance(c)
+    assert np.array_equal(cov, ref)
+
+
+def test_covariance_windowed_matches_oracle(lcf, ctx):
+    _say("[cov windowed 64x64x32 3x3]")
+    iq, _ = synth.make_packet(synth.spec_small(0))
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=4)
+    iq_t = torch.from_numpy(iq).cuda()
+    _, _, dg = ctx.filter(iq_t, 3, 3, thr, diag_cov=True)
+    cov = dg["cov"].cpu().numpy()
+    res = O.filter_packet(iq, 3, 3, _oracle_thr(thr))
+    for d in range(9):
+        e = np.linalg.norm(cov[d] - res["cov"][d]) / np.linalg.norm(res["cov"][d])
+        assert e <= 1e-6, (d, e)
+
+
+# ------------------------------------------------------------------ end to end
+
+def _check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name):
+    _say(f"[{name}] shape={iq.shape} grid={gy}x{gx} cut={thr.cut} shape={thr.shape}")
+    io, pd, d = _run(lcf, ctx, iq, gy, gx, thr)
+    res = O.filter_packet(iq, gy, gx, _oracle_thr(thr))
+    nd = gy * gx
+    # decision parity: the oracle's FP64 rule on the GPU's eigenvalues
+    forced = False
+    for s in range(nd):
+        lam_g = d["eigvals"][s]
+        lam_o = res["lam"][s]
+        assert np.allclose(lam_g, lam_o, rtol=1e-5, atol=1e-7 * lam_o[0]), (s, np.max(np.abs(lam_g - lam_o) / lam_o[0]))
+        if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE):
+            w_rule, k_rule, curv, _ = O.rule_weights(lam_g, _oracle_thr(thr))
+            assert d["k"][s] == k_rule, (s, d["k"][s], k_rule)
+            assert np.allclose(d["weights"][s], w_rule, atol=1e-6)
+            if k_rule != res["k"][s]:
+                assert knee_tie(res["curv"][s], k_rule, res["k"][s]), ("non-tie k flip", s, k_rule, res["k"][s])
+                forced = True
+    if forced:
+        ew = d["weights"].astype(np.float64)
+        res = O.filter_packet(iq, gy, gx, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=ew, pd_mode=thr.pd_mode))
+    e_fro = rel_fro(io, res["iq_out"])
+    emax, e99, e999, npx = pd_db_error(pd, res["pd"], mask)
+    _say(f"   rel_fro={e_fro:.3e} pd_db max={emax:.2e} p99={e99:.2e} p99.9={e999:.2e} n={npx} forced={forced}")
+    assert e_fro <= tol_fro
+    assert emax <= tol_db
+    return e_fro, emax
+
+
+def test_small_fixed_k(lcf, ctx):
+    iq, mask = synth.make_packet(synth.spec_small(0))
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=4)
+    _check_end_to_end(lcf, ctx, iq, mask, 3, 3, thr, 1e-5, 0.1, "small fixed-k")
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+def test_clinical_knee(lcf, ctx, shape):
+    spec = synth.spec_clinical(0)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=shape)
+    _check_end_to_end(lcf, ctx, iq, mask, 8, 8, thr, 1e-5, 0.1, f"clinical knee shape={shape}")
+
+
+def test_ragged_nt100_small_grid(lcf, ctx):
+    spec = synth.PacketSpec(72, 50, 100, 50.0, 0.5, ((20, 3, 0.4), (51, 2, 0.8)), seed=77)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    _check_end_to_end(lcf, ctx, iq, mask, 3, 2, thr, 1e-5, 0.1, "ragged nt=100")
+
+
+def test_all_ones_weights_return_input(lcf, ctx):
+    _say("[all-ones identity]")
+    iq, _ = synth.make_packet(synth.spec_small(1))
+    thr = lcf.Threshold(cut=lcf.CUT_EXPLICIT)
+    ew = torch.ones((9, 32), dtype=torch.float32)
+    io, _, _ = ctx.filter(torch.from_numpy(iq).cuda(), 3, 3, thr, explicit_w=ew)
+    io = io.cpu().numpy()
+    assert rel_fro(io, iq) <= 1e-6
+
+
+def test_global_window_is_svd_filter(lcf, ctx):
+    _say("[global flat window]")
+    iq, mask = synth.make_packet(synth.spec_small(2))
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=3)
+    io, pd, _ = _run(lcf, ctx, iq, 1, 1, thr, sigma_frac=0.0)
+    c = O.casorati(iq)
+    u, s, vh = np.linalg.svd(c, full_matrices=False)
+    chat = c - (u[:, :3] * s[:3]) @ vh[:3]
+    assert rel_fro(O.casorati(io), chat) <= 1e-5
+
+
+def test_sequential_schedule_matches_batched(lcf, ctx):
+    _say("[sequential vs batched]")
+    iq, _ = synth.make_packet(synth.spec_small(4))
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    iq_t = torch.from_numpy(iq).cuda()
+    a_io, a_pd, _ = ctx.filter(iq_t, 3, 3, thr)
+    ctx.set_option(lcf.OPT_SCHEDULE, 1)
+    try:
+        b_io, b_pd, _ = ctx.filter(iq_t, 3, 3, thr)
+    finally:
+        ctx.set_option(lcf.OPT_SCHEDULE, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(a_io, b_io) and torch.equal(a_pd, b_pd)
+
+
+def test_deterministic_reruns(lcf, ctx):
+    _say("[determinism]")
+    iq, _ = synth.make_packet(synth.spec_small(5))
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE)
+    iq_t = torch.from_numpy(iq).cuda()
+    a = ctx.filter(iq_t, 3, 3, thr)
+    b = ctx.filter(iq_t, 3, 3, thr)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_batch_mixed_shapes_matches_single(lcf, ctx):
+    _say("[batch mixed shapes]")
+    specs = [synth.PacketSpec(64, 48, 32, 50.0, 0.3, ((20, 3, 0.5),), seed=11),
+             synth.PacketSpec(40, 56, 64, 50.0, 0.3, ((15, 2, 0.2),), seed=12),
+             synth.PacketSpec(64, 48, 32, 45.0, 0.6, ((30, 4, 0.9),), seed=13)]
+    grids = [(2, 2), (3, 2), (2, 3)]
+    iqs = [torch.from_numpy(synth.make_packet(s)[0]).cuda() for s in specs]
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    ios, pds = ctx.filter_batch(iqs, grids, thr, iq_out=True)
+    for i, (iq, g) in enumerate(zip(iqs, grids)):
+        io1, pd1, _ = ctx.filter(iq, g[0], g[1], thr)
+        torch.cuda.synchronize()
+        assert torch.equal(ios[i], io1) and torch.equal(pds[i], pd1), i
+
+
+def test_nonfinite_input_reported(lcf, ctx):
+    _say("[nonfinite input]")
+    iq, _ = synth.make_packet(synth.spec_small(6))
+    iq[3, 10, 10] = np.nan
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=2)
+    ctx.filter(torch.from_numpy(iq).cuda(), 2, 2, thr)
+    assert ctx.sync() == 5
+    assert ctx.sync() == 0
