@@ -193,6 +193,40 @@ lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo
 lcf_status lcf_heevd_batched(lcf_context* ctx, int32_t n, int32_t nt, const double* a,
                              double* w, double* v, int32_t* sweeps, void* stream);
 
+/* ---- learned eigencomponent weights ----------------------------------------
+ * A 128-256-256-128 MLP (GELU, GELU, sigmoid) maps a subset's normalised
+ * log-eigenvalue spectrum z_i = log10(max(lambda_i, lambda_1 2^-52)/lambda_1)/8
+ * to soft weights w_i for the projection of Eq. 4 (the role the threshold
+ * rules of Eqs 6 and 9 play). Parameters (FP32 master, BF16 working copy, Adam
+ * moments) live in the context. Parameter order: W1[256][128], b1[256],
+ * W2[256][256], b2[256], W3[128][256], b3[128] (row-major, out x in).
+ * With LCF_CUT_MLP, lcf_filter first applies the curvature rule with the
+ * threshold's shape and betas (the fallback), then replaces the weights of
+ * every subset whose Nt is 128 and whose spectrum is finite and positive;
+ * the others keep the rule and get LCF_FLAG_MLP_FALLBACK. */
+#define LCF_MLP_NPARAM 131712
+
+/* Initialise the parameters from `seed` (uniform, scaled by fan-in). */
+lcf_status lcf_mlp_init(lcf_context* ctx, uint64_t seed);
+/* Copy n = LCF_MLP_NPARAM FP32 parameters in from / out to host memory. */
+lcf_status lcf_mlp_set_params(lcf_context* ctx, const float* host, int64_t n);
+lcf_status lcf_mlp_get_params(lcf_context* ctx, float* host, int64_t n);
+/* Gradients of the last lcf_mlp_train_step (same order), to host memory. */
+lcf_status lcf_mlp_get_grads(lcf_context* ctx, float* host, int64_t n);
+/* Checkpoint: magic, version, sizes, step, FP32 master + Adam moments, CRC32.
+ * lcf_mlp_load returns LCF_ERR_MODEL on a bad magic, size or CRC and leaves the
+ * current parameters untouched. */
+lcf_status lcf_mlp_save(lcf_context* ctx, const char* path);
+lcf_status lcf_mlp_load(lcf_context* ctx, const char* path);
+/* Inference on b spectra: lam device double [b][128] (descending), w device
+ * float [b][128]. */
+lcf_status lcf_mlp_infer(lcf_context* ctx, const double* lam, float* w, int32_t b, void* stream);
+/* One Adam step (lr, betas 0.9/0.999, eps 1e-8) on b spectra with targets
+ * target (device float [b][128]); loss_out (device float, may be NULL) gets the
+ * batch-mean loss sum_i c_i (w_i - t_i)^2, c_i = lambda_i / sum_j lambda_j t_j^2. */
+lcf_status lcf_mlp_train_step(lcf_context* ctx, const double* lam, const float* target, int32_t b, float lr,
+                              float* loss_out, void* stream);
+
 /* Wait for `stream` and report the first device-side condition raised since
  * the previous lcf_sync (LCF_ERR_NONFINITE_INPUT, LCF_ERR_NO_CONVERGENCE). */
 lcf_status lcf_sync(lcf_context* ctx, void* stream);

@@ -92,10 +92,20 @@ def load():
     lib.lcf_heevd_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     lib.lcf_sync.argtypes = [vp, vp]
     lib.lcf_stage_time.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+    lib.lcf_mlp_init.argtypes = [vp, C.c_uint64]
+    lib.lcf_mlp_set_params.argtypes = [vp, vp, i64]
+    lib.lcf_mlp_get_params.argtypes = [vp, vp, i64]
+    lib.lcf_mlp_get_grads.argtypes = [vp, vp, i64]
+    lib.lcf_mlp_save.argtypes = [vp, C.c_char_p]
+    lib.lcf_mlp_load.argtypes = [vp, C.c_char_p]
+    lib.lcf_mlp_infer.argtypes = [vp, vp, vp, i32, vp]
+    lib.lcf_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, vp, vp]
     lib.lcf_status_str.argtypes = [i32]
     lib.lcf_status_str.restype = C.c_char_p
     for name in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter",
-                 "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version", "lcf_stage_time"):
+                 "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version", "lcf_stage_time",
+                 "lcf_mlp_init", "lcf_mlp_set_params", "lcf_mlp_get_params", "lcf_mlp_get_grads", "lcf_mlp_save",
+                 "lcf_mlp_load", "lcf_mlp_infer", "lcf_mlp_train_step"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -244,6 +254,47 @@ class Context:
         st = load().lcf_filter_batch(self._h, n, geos, C.byref(tc), precision, ip, op, pp, _stream())
         _check(st, "lcf_filter_batch")
         return ios, pds
+
+    # ---- learned weights
+    MLP_NPARAM = 131712
+
+    def mlp_init(self, seed: int = 0):
+        _check(load().lcf_mlp_init(self._h, int(seed)), "lcf_mlp_init")
+
+    def mlp_set_params(self, vec):
+        import numpy as np
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        _check(load().lcf_mlp_set_params(self._h, v.ctypes.data, v.size), "lcf_mlp_set_params")
+
+    def mlp_get_params(self):
+        import numpy as np
+        v = np.empty(self.MLP_NPARAM, dtype=np.float32)
+        _check(load().lcf_mlp_get_params(self._h, v.ctypes.data, v.size), "lcf_mlp_get_params")
+        return v
+
+    def mlp_get_grads(self):
+        import numpy as np
+        v = np.empty(self.MLP_NPARAM, dtype=np.float32)
+        _check(load().lcf_mlp_get_grads(self._h, v.ctypes.data, v.size), "lcf_mlp_get_grads")
+        return v
+
+    def mlp_save(self, path: str):
+        _check(load().lcf_mlp_save(self._h, path.encode()), "lcf_mlp_save")
+
+    def mlp_load(self, path: str):
+        _check(load().lcf_mlp_load(self._h, path.encode()), "lcf_mlp_load")
+
+    def mlp_infer(self, lam):
+        """lam: torch float64 [b][128] on the GPU (descending). Returns float32 weights [b][128]."""
+        import torch
+        assert lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous() and lam.shape[1] == 128
+        w = torch.empty(lam.shape, dtype=torch.float32, device=lam.device)
+        _check(load().lcf_mlp_infer(self._h, _ptr(lam), _ptr(w), lam.shape[0], _stream()), "lcf_mlp_infer")
+        return w
+
+    def mlp_train_step(self, lam, target, lr: float, loss_out=None):
+        _check(load().lcf_mlp_train_step(self._h, _ptr(lam), _ptr(target), lam.shape[0], float(lr),
+                                         _ptr(loss_out), _stream()), "lcf_mlp_train_step")
 
     def heevd(self, a, vectors: bool = True):
         """Batched Hermitian EVD of a (torch complex128 [n][nt][nt] on the GPU).

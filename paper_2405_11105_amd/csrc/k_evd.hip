@@ -343,16 +343,25 @@ __device__ __forceinline__ void rr_pair(int step, int k, int n, int& p, int& q) 
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_LDS_NT = 100;   // nt*nt*16 bytes must fit the 160 KiB LDS
 
+// Stopping rule: a sweep without rotations (every pair passes the relative
+// test |g_p^H g_q| <= nt*u*||g_p|| ||g_q||), or stagnation at the rounding floor:
+// when R is ill-conditioned and not graded, the small columns carry absolute
+// rounding noise of order u*||R|| and the relative test cannot be met; after four
+// sweeps, a sweep whose largest relative off-diagonal is below 1e-6 and has not
+// dropped fourfold ends the iteration. Only the sweep cap raises the flag.
 template <bool IN_LDS>
 __device__ void jacobi_core(double2* G, int nt, int ld, int max_sweeps, int* sweeps_out, int* flag_out) {
     __shared__ int rot;
+    __shared__ double wmax[32];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int n = nt + (nt & 1);
     const double tol = (double)nt * 1.1102230246251565e-16;
     int sweep = 0;
     bool converged = false;
+    double prev_off = 1e300;
     for (; sweep < max_sweeps; ++sweep) {
         if (threadIdx.x == 0) rot = 0;
+        double my_off = 0.0;
         __syncthreads();
         for (int step = 0; step < n - 1; ++step) {
             for (int k = wave; k < n / 2; k += nw) {
@@ -374,7 +383,9 @@ __device__ void jacobi_core(double2* G, int nt, int ld, int max_sweeps, int* swe
                 gr = wave_sum(gr);
                 gi = wave_sum(gi);
                 const double mag = sqrt(gr * gr + gi * gi);
-                if (!(mag > tol * sqrt(al * be))) continue;
+                const double scale = sqrt(al * be);
+                if (scale > 0.0) my_off = fmax(my_off, mag / scale);
+                if (!(mag > tol * scale)) continue;
                 const double zeta = (be - al) / (2.0 * mag);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
@@ -389,7 +400,13 @@ __device__ void jacobi_core(double2* G, int nt, int ld, int max_sweeps, int* swe
             }
             __syncthreads();
         }
-        if (rot == 0) { converged = true; ++sweep; break; }
+        if (lane == 0) wmax[wave] = my_off;
+        __syncthreads();
+        double off = 0.0;
+        for (int i = 0; i < nw; ++i) off = fmax(off, wmax[i]);
+        const bool stagnant = sweep >= 3 && off < 1e-6 && off > 0.25 * prev_off;
+        prev_off = off;
+        if (rot == 0 || stagnant) { converged = true; ++sweep; break; }
         __syncthreads();
     }
     if (threadIdx.x == 0) {

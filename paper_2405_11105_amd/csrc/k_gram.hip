@@ -24,39 +24,85 @@
 namespace lcf {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <int NTP, bool DEFL>
+// Tile order shared by both precisions and the reduction: upper tile u (i <= j,
+// row-major) holds S at tau = 2u and T at tau = 2u + 1.
+template <int NTP, bool DEFL, int PREC>
 struct GramCfg {
     static constexpr int NTE = DEFL ? NTP + REXT : NTP;
     static constexpr int NT16 = NTE / 16;
     static constexpr int TPM = NT16 * (NT16 + 1) / 2;      // upper tiles per matrix
-    static constexpr int TT = 2 * TPM;                     // S tiles then T tiles
+    static constexpr int TT = 2 * TPM;                     // S and T tiles, interleaved
     static constexpr int WAVES = TT > 120 ? 8 : 4;
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int MAXT = (TT + WAVES - 1) / WAVES;
-    static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;   // im offset in a pixel row
-    static constexpr int LDA = 2 * IMO + 1;                         // odd row stride
-    static constexpr int PX = NTP > 208 ? 16 : PIX;                 // pixels per LDS batch
+    static constexpr int PX = NTP > 160 ? 16 : PIX;        // pixels per LDS batch
+    // FP32 layout: per pixel a row [re(0..NTE) | im], odd stride
+    static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;
+    static constexpr int LDA = 2 * IMO + 1;
+    // BF16 layout: per complex column a row of PX words (bf16 re, im), padded
+    static constexpr int LDB = PX + 4;
+    static constexpr int A_WORDS = PREC == 0 ? PX * LDA : 2 * NTE * LDB;
 };
 
-__device__ __forceinline__ void tile_ij(int tau, int nt16, int& i, int& j) {
-    int rem = tau;
+__device__ __forceinline__ void tile_ij(int u, int nt16, int& i, int& j) {
+    int rem = u;
     i = 0;
     while (rem >= nt16 - i) { rem -= nt16 - i; ++i; }
     j = i + rem;
 }
 
-template <int NTP, bool DEFL>
-__global__ void __launch_bounds__((GramCfg<NTP, DEFL>::THREADS))
-k_gram_fp32(Workspace ws) {
-    using C = GramCfg<NTP, DEFL>;
-    constexpr int IMO = C::IMO, LDA = C::LDA, PIX = C::PX;
-    __shared__ float A[PIX * LDA];
+// Round-to-nearest-even FP32 -> BF16 bits.
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Split x = hi + lo (both BF16, RNE) and store (re, im) pairs.
+__device__ __forceinline__ void split_pair(float re, float im, uint32_t& h, uint32_t& l) {
+    const uint32_t rh = bf16_rne(re), ih = bf16_rne(im);
+    const float rl = re - __uint_as_float(rh << 16), il = im - __uint_as_float(ih << 16);
+    h = rh | (ih << 16);
+    l = bf16_rne(rl) | (bf16_rne(il) << 16);
+}
+
+// Operand row of B for the T tiles: rows (2p, 2p+1) of the interleaved K axis
+// become (im_p, -re_p): swap the halves of every word, negate the new high half.
+__device__ __forceinline__ u32x4 swap_neg(u32x4 v) {
+    u32x4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = ((v[e] >> 16) | (v[e] << 16)) ^ 0x80000000u;
+    return o;
+}
+
+template <int NTP, bool DEFL, int PREC>
+__global__ void __launch_bounds__((GramCfg<NTP, DEFL, PREC>::THREADS))
+k_gram(Workspace ws) {
+    using C = GramCfg<NTP, DEFL, PREC>;
+    constexpr int NTE = C::NTE, IMO = C::IMO, LDA = C::LDA, LDB = C::LDB, PIX = C::PX;
+    __shared__ __attribute__((aligned(16))) uint32_t Aw[C::A_WORDS];
     __shared__ double wpix[PIX];
     __shared__ float2 craw[DEFL ? NTP * PIX : 1];
     __shared__ float2 vr32[DEFL ? NTP * RMAX : 1];
     __shared__ double2 vr64[DEFL ? NTP * RMAX : 1];
     __shared__ float2 yv[DEFL ? PIX * RMAX : 1];
+    float* A = reinterpret_cast<float*>(Aw);
+    uint32_t* Ah = Aw;                   // BF16 hi words [NTE][LDB]
+    uint32_t* Al = Aw + NTE * LDB;       // BF16 lo words
+
+    auto put = [&](int p, int c, float re, float im) {
+        if (PREC == 0) {
+            A[p * LDA + c] = re;
+            A[p * LDA + IMO + c] = im;
+        } else {
+            uint32_t h, l;
+            split_pair(re, im, h, l);
+            Ah[c * LDB + p] = h;
+            Al[c * LDB + p] = l;
+        }
+    };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -75,19 +121,18 @@ k_gram_fp32(Workspace ws) {
         }
     }
 
-    // Tiles owned by this wave.
+    // Tiles owned by this wave: FP32 round-robin, BF16 contiguous (operand reuse).
     int aoff[C::MAXT], boff[C::MAXT];
     bool isT[C::MAXT], valid[C::MAXT];
 #pragma unroll
     for (int m = 0; m < C::MAXT; ++m) {
-        const int tau = wave + C::WAVES * m;
+        const int tau = PREC == 0 ? wave + C::WAVES * m : wave * C::MAXT + m;
         valid[m] = tau < C::TT;
-        const int tm = valid[m] ? tau % C::TPM : 0;
         int i, j;
-        tile_ij(tm, C::NT16, i, j);
+        tile_ij(valid[m] ? (tau >> 1) : 0, C::NT16, i, j);
         aoff[m] = i * 16;
         boff[m] = j * 16;
-        isT[m] = valid[m] && tau >= C::TPM;
+        isT[m] = valid[m] && (tau & 1);
     }
     floatx4 acc[C::MAXT];
 #pragma unroll
@@ -117,8 +162,7 @@ k_gram_fp32(Workspace ws) {
                     re = (float)(w * (double)c.x);
                     im = (float)(w * (double)c.y);
                 }
-                A[p * LDA + t] = re;
-                A[p * LDA + IMO + t] = im;
+                put(p, t, re, im);
             }
         } else {
             for (int e = tid; e < PIX * NTP; e += C::THREADS) {
@@ -148,8 +192,7 @@ k_gram_fp32(Workspace ws) {
                     y = make_float2(w * ar, w * ai);
                     yv[p * RMAX + j] = y;
                 }
-                A[p * LDA + NTP + j] = y.x;
-                A[p * LDA + IMO + NTP + j] = y.y;
+                put(p, NTP + j, y.x, y.y);
             }
             __syncthreads();
             // Bulk residual c' = w s - y V_r^H in FP64, rounded once.
@@ -169,25 +212,61 @@ k_gram_fp32(Workspace ws) {
                         im -= (double)y.y * v.x - (double)y.x * v.y;
                     }
                 }
-                A[p * LDA + t] = (float)re;
-                A[p * LDA + IMO + t] = (float)im;
+                put(p, t, (float)re, (float)im);
             }
         }
         __syncthreads();
-        const int kk = lane >> 4, col = lane & 15;
+        if (PREC == 0) {
+            const int kk = lane >> 4, col = lane & 15;
 #pragma unroll 2
-        for (int kp = 0; kp < PIX; kp += 2) {
-            const int p = kp + (kk >> 1), part = kk & 1;
-            const float* rowp = A + p * LDA;
-            const float* base = rowp + (part ? IMO : 0);
-            const float* swp = part ? rowp : rowp + IMO;      // partner part for T
-            const float sgn = part ? -1.f : 1.f;
+            for (int kp = 0; kp < PIX; kp += 2) {
+                const int p = kp + (kk >> 1), part = kk & 1;
+                const float* rowp = A + p * LDA;
+                const float* base = rowp + (part ? IMO : 0);
+                const float* swp = part ? rowp : rowp + IMO;      // partner part for T
+                const float sgn = part ? -1.f : 1.f;
 #pragma unroll
-            for (int m = 0; m < C::MAXT; ++m) {
-                if (valid[m]) {
-                    const float a = base[aoff[m] + col];
-                    const float b = isT[m] ? sgn * swp[boff[m] + col] : base[boff[m] + col];
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+                for (int m = 0; m < C::MAXT; ++m) {
+                    if (valid[m]) {
+                        const float a = base[aoff[m] + col];
+                        const float b = isT[m] ? sgn * swp[boff[m] + col] : base[boff[m] + col];
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            // K blocks of 32 = 16 pixels x (re, im); lane group g holds pixels 4g..4g+3.
+            const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+            for (int kb = 0; kb < PIX; kb += 16) {
+                const int wofs = kb + 4 * g;
+                int cur_a = -1;
+                u32x4 ah = u32x4{0, 0, 0, 0}, al = u32x4{0, 0, 0, 0};
+                int cur_b = -1;
+                u32x4 bh = u32x4{0, 0, 0, 0}, bl = u32x4{0, 0, 0, 0};
+#pragma unroll
+                for (int m = 0; m < C::MAXT; ++m) {
+                    if (valid[m]) {
+                        if (aoff[m] != cur_a) {
+                            cur_a = aoff[m];
+                            ah = *reinterpret_cast<const u32x4*>(Ah + (cur_a + col) * LDB + wofs);
+                            al = *reinterpret_cast<const u32x4*>(Al + (cur_a + col) * LDB + wofs);
+                        }
+                        if (boff[m] != cur_b) {
+                            cur_b = boff[m];
+                            bh = *reinterpret_cast<const u32x4*>(Ah + (cur_b + col) * LDB + wofs);
+                            bl = *reinterpret_cast<const u32x4*>(Al + (cur_b + col) * LDB + wofs);
+                        }
+                        const u32x4 uh = isT[m] ? swap_neg(bh) : bh;
+                        const u32x4 ul = isT[m] ? swap_neg(bl) : bl;
+                        const bf16x8 xa_h = __builtin_bit_cast(bf16x8, ah);
+                        const bf16x8 xa_l = __builtin_bit_cast(bf16x8, al);
+                        const bf16x8 xb_h = __builtin_bit_cast(bf16x8, uh);
+                        const bf16x8 xb_l = __builtin_bit_cast(bf16x8, ul);
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_h, acc[m], 0, 0, 0);
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_l, acc[m], 0, 0, 0);
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_l, xb_h, acc[m], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -195,7 +274,7 @@ k_gram_fp32(Workspace ws) {
 #pragma unroll
     for (int m = 0; m < C::MAXT; ++m) {
         if (valid[m]) {
-            const int tau = wave + C::WAVES * m;
+            const int tau = PREC == 0 ? wave + C::WAVES * m : wave * C::MAXT + m;
             float* dst = ws.partial + ((long)blockIdx.x * C::TT + tau) * 256 + lane * 4;
             *reinterpret_cast<floatx4*>(dst) = acc[m];
         }
@@ -208,10 +287,9 @@ template <int NTE>
 __global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, double2* out, int tt) {
     constexpr int NT16 = NTE / 16;
     const int s = blockIdx.y;
-    const int tau = blockIdx.x;
-    const int tpm = tt / 2;
+    const int u = blockIdx.x;
     int i, j;
-    tile_ij(tau, NT16, i, j);
+    tile_ij(u, NT16, i, j);
     const int e = threadIdx.x;
     const int lane = e >> 2, rr = e & 3;
     const int rin = 4 * (lane >> 4) + rr, cin = lane & 15;
@@ -219,8 +297,8 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, double2* out,
     const int c0 = ws.chunk_begin[s], c1 = ws.chunk_begin[s + 1];
     double sv = 0.0, tv = 0.0;
     for (int c = c0; c < c1; ++c) {
-        sv += (double)ws.partial[((long)c * tt + tau) * 256 + e];
-        tv += (double)ws.partial[((long)c * tt + tpm + tau) * 256 + e];
+        sv += (double)ws.partial[((long)c * tt + 2 * u) * 256 + e];
+        tv += (double)ws.partial[((long)c * tt + 2 * u + 1) * 256 + e];
     }
     const int row = i * 16 + rin, colx = j * 16 + cin;
     double2* o = out + (long)s * NTE * NTE;
@@ -235,31 +313,36 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, double2* out,
 
 // ------------------------------------------------------------------ launchers
 
+template <int NTP, bool DEFL, int PREC>
+static void gram_launch(const Workspace& ws, bool reduce, hipStream_t st) {
+    using C = GramCfg<NTP, DEFL, PREC>;
+    if (!reduce) hipLaunchKernelGGL((k_gram<NTP, DEFL, PREC>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
+    else hipLaunchKernelGGL((k_gram_reduce<C::NTE>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws,
+                            DEFL ? ws.rext : ws.rwin, C::TT);
+}
+
 template <int NTP>
-static hipError_t gram_dispatch(const Workspace& ws, bool defl, bool reduce, hipStream_t st) {
+static hipError_t gram_dispatch(const Workspace& ws, bool defl, bool reduce, int prec, hipStream_t st) {
     if (ws.nchunks == 0) return hipSuccess;
     if (defl) {
-        using C = GramCfg<NTP, true>;
-        if (!reduce) hipLaunchKernelGGL((k_gram_fp32<NTP, true>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
-        else hipLaunchKernelGGL((k_gram_reduce<C::NTE>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws, ws.rext, C::TT);
+        if (prec == 0) gram_launch<NTP, true, 0>(ws, reduce, st);
+        else gram_launch<NTP, true, 1>(ws, reduce, st);
     } else {
-        using C = GramCfg<NTP, false>;
-        if (!reduce) hipLaunchKernelGGL((k_gram_fp32<NTP, false>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
-        else hipLaunchKernelGGL((k_gram_reduce<C::NTE>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws, ws.rwin, C::TT);
+        if (prec == 0) gram_launch<NTP, false, 0>(ws, reduce, st);
+        else gram_launch<NTP, false, 1>(ws, reduce, st);
     }
     return hipGetLastError();
 }
 
 // reduce = false: the split-K Gram kernel; reduce = true: the ordered FP64 reduction.
 hipError_t launch_gram(const Workspace& ws, bool defl, bool reduce, int precision, hipStream_t st) {
-    (void)precision;
     switch (ws.ntp) {
-        case 32: return gram_dispatch<32>(ws, defl, reduce, st);
-        case 64: return gram_dispatch<64>(ws, defl, reduce, st);
-        case 96: return gram_dispatch<96>(ws, defl, reduce, st);
-        case 128: return gram_dispatch<128>(ws, defl, reduce, st);
-        case 160: return gram_dispatch<160>(ws, defl, reduce, st);
-        case 208: return gram_dispatch<208>(ws, defl, reduce, st);
+        case 32: return gram_dispatch<32>(ws, defl, reduce, precision, st);
+        case 64: return gram_dispatch<64>(ws, defl, reduce, precision, st);
+        case 96: return gram_dispatch<96>(ws, defl, reduce, precision, st);
+        case 128: return gram_dispatch<128>(ws, defl, reduce, precision, st);
+        case 160: return gram_dispatch<160>(ws, defl, reduce, precision, st);
+        case 208: return gram_dispatch<208>(ws, defl, reduce, precision, st);
         default: return hipErrorInvalidValue;
     }
 }

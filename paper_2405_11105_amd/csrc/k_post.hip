@@ -6,6 +6,14 @@
 namespace lcf {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even FP32 -> BF16 bits.
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
 
 // ------------------------------------------------------------------ rules
 // One 64-lane wave per subset; everything on the FP64 eigenvalues.
@@ -90,9 +98,10 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
 // and all-ones weights give P = I exactly), then P = Q P_Q Q^H by Householder
 // rank-2 updates, M = V_r^H P, and the real-form [P; M] used by the
 // reprojection GEMM.
-template <int NTP>
+template <int NTP, int PREC>
 __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     constexpr int NTE = NTP + REXT;
+    constexpr int NTEP = (NTE + 31) / 32 * 32;
     constexpr int CC = 8;                       // eigenvector columns staged per pass
     __shared__ double2 Wc[CC * NTP];
     __shared__ double cw[CC];
@@ -162,6 +171,31 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     }
     for (int e = tid; e < NTP * RMAX; e += 256) V[e] = ws.vr64[(long)s * NTP * RMAX + e];
     __syncthreads();
+    if (PREC == 1) {
+        // Split-BF16 planes of [P; M]^T, K-contiguous: plane q in (re hi, re lo,
+        // im hi, im lo), row n (output frame), column k (operand column).
+        uint16_t* pt = reinterpret_cast<uint16_t*>(ws.breal + (long)s * (2 * NTE) * (2 * NTP));
+        for (int e = tid; e < NTP * NTEP; e += 256) {
+            const int n = e / NTEP, k = e % NTEP;
+            double2 v = make_double2(0.0, 0.0);
+            if (n < nt) {
+                if (k < nt) v = P[(long)k * NTP + n];
+                else if (k >= NTP && k < NTP + r) {
+                    const int j = k - NTP;
+                    for (int u = 0; u < nt; ++u) v = cadd(v, cmulc(V[u * RMAX + j], P[(long)u * NTP + n]));
+                }
+            }
+            const float re = (float)v.x, im = (float)v.y;
+            const uint32_t rh = bf16_bits(re), ih = bf16_bits(im);
+            const uint32_t rl = bf16_bits(re - __uint_as_float(rh << 16));
+            const uint32_t il = bf16_bits(im - __uint_as_float(ih << 16));
+            pt[(long)0 * NTP * NTEP + e] = (uint16_t)rh;
+            pt[(long)1 * NTP * NTEP + e] = (uint16_t)rl;
+            pt[(long)2 * NTP * NTEP + e] = (uint16_t)ih;
+            pt[(long)3 * NTP * NTEP + e] = (uint16_t)il;
+        }
+        return;
+    }
     // Real form of [P; M]: row kk in [0, 2 NTE), column n in [0, 2 NTP).
     float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
     for (int e = tid; e < NTE * NTP; e += 256) {
@@ -396,22 +430,262 @@ __global__ void __launch_bounds__(256) k_reproj(Workspace ws) {
     }
 }
 
+
+// Split-BF16 reprojection: the same gather as k_reproj with [c' | y] and [P; M]
+// split into BF16 hi + lo and three MFMA products (hi*hi + hi*lo + lo*hi) per
+// tile on v_mfma_f32_16x16x32_bf16. The operand's K axis is padded per part to
+// NTEP so that no 32-wide K block straddles the re/im boundary.
+template <int NTP>
+struct ReprojBfCfg {
+    static constexpr int NTE = NTP + REXT;
+    static constexpr int NTEP = (NTE + 31) / 32 * 32;
+    static constexpr int LDK = 2 * NTEP + 8;          // bf16 units per pixel row
+    static constexpr int CT = (2 * NTP) / 16;         // output column tiles
+    static constexpr int CTW = (CT + 3) / 4;          // per wave (both row tiles)
+};
+
+template <int NTP>
+__global__ void __launch_bounds__(256) k_reproj_bf16(Workspace ws) {
+    using C = ReprojBfCfg<NTP>;
+    constexpr int NTEP = C::NTEP, LDK = C::LDK;
+    static_assert(PIX == 32, "reprojection tile is 2 x 16 pixels");
+    __shared__ __attribute__((aligned(16))) uint16_t Ah[PIX * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Al[PIX * LDK];
+    __shared__ float2 craw[NTP * PIX];
+    __shared__ float2 vr32[NTP * RMAX];
+    __shared__ double2 vr64[NTP * RMAX];
+    __shared__ float2 yv[PIX * RMAX];
+    __shared__ float wd[PIX];
+    __shared__ float pdsh[4 * PIX];
+    __shared__ float wsum[PIX];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const TileDesc td = ws.tiles[blockIdx.x];
+    const PacketDesc pk = ws.pkts[td.pkt];
+    const int nt = pk.nt, nx = pk.nx;
+    const long npix = (long)pk.ny * pk.nx;
+    const int npx = td.x1 - td.x0 + 1;
+
+    auto put = [&](int p, int c, float re, float im) {
+        const uint32_t rh = bf16_bits(re), ih = bf16_bits(im);
+        Ah[p * LDK + c] = (uint16_t)rh;
+        Ah[p * LDK + NTEP + c] = (uint16_t)ih;
+        Al[p * LDK + c] = (uint16_t)bf16_bits(re - __uint_as_float(rh << 16));
+        Al[p * LDK + NTEP + c] = (uint16_t)bf16_bits(im - __uint_as_float(ih << 16));
+    };
+
+    for (int e = tid; e < PIX * NTP; e += 256) {
+        const int p = e % PIX, t = e / PIX;
+        float2 c = make_float2(0.f, 0.f);
+        if (p < npx && t < nt) c = pk.iq[(long)t * npix + (long)td.y * nx + td.x0 + p];
+        craw[t * PIX + p] = c;
+    }
+    for (int e = tid; e < PIX * LDK; e += 256) { Ah[e] = 0; Al[e] = 0; }   // K padding stays zero
+    floatx4 iq_acc[2][C::CTW];
+    float pd_acc[8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int m = 0; m < C::CTW; ++m) iq_acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pd_acc[i] = 0.f;
+    const uint16_t* planes_base = nullptr;
+
+    for (int ci = 0; ci < td.cov_cnt; ++ci) {
+        const int s = ws.cover[td.cov_off + ci];
+        const SubsetDesc sd = ws.sub[s];
+        const int r = ws.rank[s];
+        const float alpha = (float)ws.alpha[s];
+        __syncthreads();
+        for (int e = tid; e < NTP * RMAX; e += 256) {
+            vr32[e] = ws.vr32[(long)s * NTP * RMAX + e];
+            vr64[e] = ws.vr64[(long)s * NTP * RMAX + e];
+        }
+        if (tid < PIX) {
+            const int x = td.x0 + tid;
+            float w = 0.f;
+            if (tid < npx && td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
+                w = sd.flat ? 1.f : (float)(ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0]);
+            wd[tid] = w;
+        }
+        __syncthreads();
+        for (int e = tid; e < PIX * REXT; e += 256) {
+            const int p = e % PIX, j = e / PIX;
+            float2 y = make_float2(0.f, 0.f);
+            if (j < r) {
+                float ar = 0.f, ai = 0.f;
+                for (int t = 0; t < nt; ++t) {
+                    const float2 c = craw[t * PIX + p];
+                    const float2 v = vr32[t * RMAX + j];
+                    ar = fmaf(c.x, v.x, fmaf(-c.y, v.y, ar));
+                    ai = fmaf(c.x, v.y, fmaf(c.y, v.x, ai));
+                }
+                y = make_float2(ar, ai);
+                yv[p * RMAX + j] = y;
+            }
+            put(p, NTP + j, y.x, y.y);
+        }
+        __syncthreads();
+        for (int e = tid; e < PIX * NTP; e += 256) {
+            const int p = e % PIX, t = e / PIX;
+            double re = 0.0, im = 0.0;
+            if (t < nt) {
+                const float2 c = craw[t * PIX + p];
+                re = (double)c.x;
+                im = (double)c.y;
+                for (int j = 0; j < r; ++j) {
+                    const float2 y = yv[p * RMAX + j];
+                    const double2 v = vr64[t * RMAX + j];
+                    re -= (double)y.x * v.x + (double)y.y * v.y;
+                    im -= (double)y.y * v.x - (double)y.x * v.y;
+                }
+            }
+            put(p, t, (float)re, (float)im);
+        }
+        __syncthreads();
+        planes_base = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * (NTP + REXT)) * (2 * NTP));
+        floatx4 acc[2][C::CTW];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int m = 0; m < C::CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
+            const int kq = k0 + 8 * g;
+            const u32x4 a0h = *reinterpret_cast<const u32x4*>(Ah + col * LDK + kq);
+            const u32x4 a0l = *reinterpret_cast<const u32x4*>(Al + col * LDK + kq);
+            const u32x4 a1h = *reinterpret_cast<const u32x4*>(Ah + (16 + col) * LDK + kq);
+            const u32x4 a1l = *reinterpret_cast<const u32x4*>(Al + (16 + col) * LDK + kq);
+            const bool impart = k0 >= NTEP;
+            const int kk = impart ? kq - NTEP : kq;
+#pragma unroll
+            for (int m = 0; m < C::CTW; ++m) {
+                const int ct = wave * C::CTW + m;
+                if (ct < C::CT) {
+                    const int n = ct * 16 + col;
+                    const bool outim = n >= NTP;
+                    const int nn = outim ? n - NTP : n;
+                    // B^T row n: re output [P_re | -P_im], im output [P_im | P_re]
+                    const int plane = (outim != impart) ? 2 : 0;
+                    const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
+                    const uint16_t* src = planes_base + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
+                    u32x4 bh = *reinterpret_cast<const u32x4*>(src);
+                    u32x4 bl = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) { bh[q] ^= sgn; bl[q] ^= sgn; }
+                    const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh), xbl = __builtin_bit_cast(bf16x8, bl);
+                    const bf16x8 x0h = __builtin_bit_cast(bf16x8, a0h), x0l = __builtin_bit_cast(bf16x8, a0l);
+                    const bf16x8 x1h = __builtin_bit_cast(bf16x8, a1h), x1l = __builtin_bit_cast(bf16x8, a1l);
+                    acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbh, acc[0][m], 0, 0, 0);
+                    acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbl, acc[0][m], 0, 0, 0);
+                    acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0l, xbh, acc[0][m], 0, 0, 0);
+                    acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbh, acc[1][m], 0, 0, 0);
+                    acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbl, acc[1][m], 0, 0, 0);
+                    acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1l, xbh, acc[1][m], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int m = 0; m < C::CTW; ++m) {
+                if (wave * C::CTW + m < C::CT) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int p = rt * 16 + 4 * g + i;
+                        const float w = wd[p];
+                        const float v = acc[rt][m][i];
+                        pd_acc[rt * 4 + i] += alpha * w * w * v * v;
+                        iq_acc[rt][m][i] += w * v;
+                    }
+                }
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float v = pd_acc[i];
+        for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+        pd_acc[i] = v;
+    }
+    __syncthreads();
+    if (col == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pdsh[wave * PIX + (i >> 2) * 16 + 4 * g + (i & 3)] = pd_acc[i];
+    }
+    if (tid < PIX) {
+        const int x = td.x0 + tid;
+        double ws_ = 0.0;
+        for (int ci = 0; ci < td.cov_cnt; ++ci) {
+            const SubsetDesc sd = ws.sub[ws.cover[td.cov_off + ci]];
+            if (tid < npx && td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
+                ws_ += sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
+        }
+        wsum[tid] = (float)ws_;
+    }
+    __syncthreads();
+    if (tid < npx) {
+        const int p = tid, x = td.x0 + p;
+        float pdv = 0.f;
+        for (int w = 0; w < 4; ++w) pdv += pdsh[w * PIX + p];
+        if (pk.pd_mode == 2) {
+            double comp = 0.0;
+            for (int ci = 0; ci < td.cov_cnt; ++ci) {
+                const int s = ws.cover[td.cov_off + ci];
+                const SubsetDesc sd = ws.sub[s];
+                if (td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1) {
+                    const double w = sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
+                    comp += ws.alpha[s] * w * w;
+                }
+            }
+            pdv = comp > 0.0 ? (float)((double)pdv / comp) : 0.f;
+        }
+        pk.pd[(long)td.y * nx + x] = pdv;
+    }
+    if (pk.iq_out) {
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int m = 0; m < C::CTW; ++m) {
+                const int ct = wave * C::CTW + m;
+                if (ct < C::CT) {
+                    const int n = ct * 16 + col;
+                    const int part = n >= NTP, t = n - part * NTP;
+                    if (t < nt) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int p = rt * 16 + 4 * g + i;
+                            if (p < npx) {
+                                const float w = wsum[p];
+                                pk.iq_out[2 * ((long)t * npix + (long)td.y * nx + td.x0 + p) + part] =
+                                    w > 0.f ? iq_acc[rt][m][i] / w : 0.f;
+                            }
+                        }
+                    }
+                }
+            }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <int NTP>
-static void post_dispatch(const Workspace& ws, int stage, hipStream_t st) {
-    if (stage == 0) hipLaunchKernelGGL((k_projector<NTP>), dim3(ws.S), dim3(256), 0, st, ws);
-    else if (ws.ntiles > 0) hipLaunchKernelGGL((k_reproj<NTP>), dim3(ws.ntiles), dim3(256), 0, st, ws);
+static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t st) {
+    if (stage == 0) {
+        if (prec == 0) hipLaunchKernelGGL((k_projector<NTP, 0>), dim3(ws.S), dim3(256), 0, st, ws);
+        else hipLaunchKernelGGL((k_projector<NTP, 1>), dim3(ws.S), dim3(256), 0, st, ws);
+    } else if (ws.ntiles > 0) {
+        if (prec == 0) hipLaunchKernelGGL((k_reproj<NTP>), dim3(ws.ntiles), dim3(256), 0, st, ws);
+        else hipLaunchKernelGGL((k_reproj_bf16<NTP>), dim3(ws.ntiles), dim3(256), 0, st, ws);
+    }
 }
 
-static hipError_t post_stage(const Workspace& ws, int stage, hipStream_t st) {
+static hipError_t post_stage(const Workspace& ws, int stage, int prec, hipStream_t st) {
     switch (ws.ntp) {
-        case 32: post_dispatch<32>(ws, stage, st); break;
-        case 64: post_dispatch<64>(ws, stage, st); break;
-        case 96: post_dispatch<96>(ws, stage, st); break;
-        case 128: post_dispatch<128>(ws, stage, st); break;
-        case 160: post_dispatch<160>(ws, stage, st); break;
-        case 208: post_dispatch<208>(ws, stage, st); break;
+        case 32: post_dispatch<32>(ws, stage, prec, st); break;
+        case 64: post_dispatch<64>(ws, stage, prec, st); break;
+        case 96: post_dispatch<96>(ws, stage, prec, st); break;
+        case 128: post_dispatch<128>(ws, stage, prec, st); break;
+        case 160: post_dispatch<160>(ws, stage, prec, st); break;
+        case 208: post_dispatch<208>(ws, stage, prec, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -423,12 +697,10 @@ hipError_t launch_rules(const Workspace& ws, const RuleParams& rp, hipStream_t s
 }
 
 hipError_t launch_projector(const Workspace& ws, int precision, hipStream_t st) {
-    (void)precision;
-    return post_stage(ws, 0, st);
+    return post_stage(ws, 0, precision, st);
 }
 hipError_t launch_reproj(const Workspace& ws, int precision, hipStream_t st) {
-    (void)precision;
-    return post_stage(ws, 1, st);
+    return post_stage(ws, 1, precision, st);
 }
 
 // ------------------------------------------------------------------ diagnostics

@@ -27,4 +27,32 @@ hipError_t launch_export(const Workspace& ws, int first, int count, int nt, doub
 hipError_t launch_export_cov(const Workspace& ws, int first, int count, int nt, double2* cov, hipStream_t st);
 hipError_t launch_flags_or(const Workspace& ws, int* sticky, hipStream_t st);
 
+// ---- learned weights (k_mlp.hip)
+constexpr int MLP_NT = 128;
+constexpr int MLP_H = 256;
+constexpr int MLP_OFF_W1 = 0;
+constexpr int MLP_OFF_B1 = MLP_OFF_W1 + MLP_H * MLP_NT;
+constexpr int MLP_OFF_W2 = MLP_OFF_B1 + MLP_H;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + MLP_H * MLP_H;
+constexpr int MLP_OFF_W3 = MLP_OFF_B2 + MLP_H;
+constexpr int MLP_OFF_B3 = MLP_OFF_W3 + MLP_NT * MLP_H;
+constexpr int MLP_NPARAM = MLP_OFF_B3 + MLP_NT;   // 131712
+
+struct MlpDev {
+    float* master;   // FP32 parameters
+    uint16_t* wbf;   // BF16 working copy (same layout)
+    float* m;        // Adam moments
+    float* v;
+    float* grad;     // last gradients
+};
+
+hipError_t mlp_forward(const MlpDev& net, const float* z, int rows, float* scratch, float* wout, hipStream_t st);
+hipError_t mlp_features(const double* lam, int ldl, int rows, float* z, int* valid, hipStream_t st);
+hipError_t mlp_apply(const Workspace& ws, const float* wout, const int* valid, int pd_mode, hipStream_t st);
+hipError_t mlp_refresh_bf16(const MlpDev& net, hipStream_t st);
+hipError_t mlp_train_step(const MlpDev& net, const double* lam, const float* target, int rows, float lr, int step,
+                          float* scratch, float* loss_out, hipStream_t st);
+size_t mlp_train_scratch_floats(int rows);
+size_t mlp_infer_scratch_floats(int rows);
+
 }  // namespace lcf

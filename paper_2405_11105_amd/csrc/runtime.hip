@@ -87,13 +87,14 @@ lcf_status validate_threshold(const lcf_threshold* t, int nt) {
         return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_EXPLICIT && t->explicit_w == nullptr) return LCF_ERR_INVALID_ARG;
     if (!(t->deflate_rho >= 0.0) || t->deflate_rho >= 1.0) return LCF_ERR_INVALID_ARG;
-    if (t->cut == LCF_CUT_MLP) return LCF_ERR_UNSUPPORTED;
+    if (t->cut == LCF_CUT_MLP && (!(t->beta_knee > 0.0) || !(t->knee_max_frac > 0.0) ||
+                                  t->knee_max_frac > 1.0 || !(t->beta_sigmoid > 0.0)))
+        return LCF_ERR_INVALID_ARG;
     return LCF_OK;
 }
 
 lcf_status validate_precision(int p) {
-    if (p == LCF_PREC_FP32) return LCF_OK;
-    if (p == LCF_PREC_BF16X3) return LCF_ERR_UNSUPPORTED;
+    if (p == LCF_PREC_FP32 || p == LCF_PREC_BF16X3) return LCF_OK;
     return LCF_ERR_INVALID_ARG;
 }
 
@@ -207,6 +208,12 @@ struct lcf_context {
     std::vector<std::pair<int, size_t>> evpending;   // (stage, index of start event)
     double stage_ms[LCF_NUM_STAGES] = {0};
     long long stage_n[LCF_NUM_STAGES] = {0};
+    // learned weights
+    MlpDev mlp{};
+    bool mlp_ready = false;
+    long long mlp_step = 0;
+    float* mlp_scratch = nullptr;
+    size_t mlp_scratch_cap = 0;     // floats
 };
 
 namespace {
@@ -242,6 +249,53 @@ lcf_status ensure_host(lcf_context* c, size_t bytes) {
     }
     c->hcap = want;
     return LCF_OK;
+}
+
+lcf_status ensure_mlp_scratch(lcf_context* c, size_t floats) {
+    if (floats <= c->mlp_scratch_cap) return LCF_OK;
+    if (c->mlp_scratch) {
+        if (hipDeviceSynchronize() != hipSuccess) return LCF_ERR_DEVICE;
+        hipFree(c->mlp_scratch);
+        c->mlp_scratch = nullptr;
+        c->mlp_scratch_cap = 0;
+    }
+    const size_t want = align_up(floats + floats / 4, 1 << 16);
+    if (hipMalloc((void**)&c->mlp_scratch, want * sizeof(float)) != hipSuccess) return LCF_ERR_OUT_OF_MEMORY;
+    c->mlp_scratch_cap = want;
+    return LCF_OK;
+}
+
+lcf_status ensure_mlp(lcf_context* c) {
+    if (c->mlp.master) return LCF_OK;
+    const size_t n = MLP_NPARAM;
+    if (hipMalloc((void**)&c->mlp.master, n * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&c->mlp.wbf, n * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void**)&c->mlp.m, n * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&c->mlp.v, n * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&c->mlp.grad, n * sizeof(float)) != hipSuccess)
+        return LCF_ERR_OUT_OF_MEMORY;
+    if (hipMemset(c->mlp.m, 0, n * sizeof(float)) != hipSuccess ||
+        hipMemset(c->mlp.v, 0, n * sizeof(float)) != hipSuccess ||
+        hipMemset(c->mlp.grad, 0, n * sizeof(float)) != hipSuccess)
+        return LCF_ERR_DEVICE;
+    return LCF_OK;
+}
+
+uint32_t crc32_update(uint32_t crc, const void* data, size_t len) {
+    static uint32_t table[256];
+    static bool init = false;
+    if (!init) {
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t c = i;
+            for (int k = 0; k < 8; ++k) c = (c & 1) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+            table[i] = c;
+        }
+        init = true;
+    }
+    const unsigned char* p = (const unsigned char*)data;
+    crc = ~crc;
+    for (size_t i = 0; i < len; ++i) crc = table[(crc ^ p[i]) & 0xFF] ^ (crc >> 8);
+    return ~crc;
 }
 
 struct Layout {
@@ -418,10 +472,26 @@ lcf_status run_stages(lcf_context* c, const Workspace& ws, const lcf_threshold* 
 
 lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold* thr, int prec, int nt_max,
                        hipStream_t st) {
-    RuleParams rp{thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee, thr->knee_max_frac,
-                  thr->beta_sigmoid};
+    const bool mlp = thr->cut == LCF_CUT_MLP;
+    RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
+                  thr->knee_max_frac, thr->beta_sigmoid};
     { STAGE(c, LCF_STAGE_JACOBI, st); HIPCHK(launch_jacobi(ws, c->max_sweeps, nt_max, st)); }
     { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
+    if (mlp) {
+        STAGE(c, LCF_STAGE_MLP, st);
+        // scratch laid out as [valid ints][z | h1 a1 h2 a2 | w]; sized by the caller
+        int* valid = (int*)c->mlp_scratch;
+        float* z = c->mlp_scratch + align_up((size_t)ws.S, 64);
+        float* act = z + (size_t)ws.S * MLP_NT;
+        float* wout = act + (size_t)ws.S * 4 * MLP_H;
+        if (ws.ntp == MLP_NT) {
+            HIPCHK(mlp_features(ws.lam, ws.ntp, ws.S, z, valid, st));
+            HIPCHK(mlp_forward(c->mlp, z, ws.S, act, wout, st));
+            HIPCHK(mlp_apply(ws, wout, valid, thr->pd_mode, st));
+        } else {
+            HIPCHK(mlp_apply(ws, wout, nullptr, thr->pd_mode, st));   // all subsets keep the rule
+        }
+    }
     { STAGE(c, LCF_STAGE_PROJECTOR, st); HIPCHK(launch_projector(ws, prec, st)); }
     return LCF_OK;
 }
@@ -471,6 +541,11 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
         HIPCHK(hipEventRecord(c->staged, st));
         c->staged_pending = true;
         Workspace ws = make_ws(c->dbuf, D, pl, thr->cut == LCF_CUT_EXPLICIT ? thr->explicit_w : nullptr);
+        if (thr->cut == LCF_CUT_MLP) {
+            const size_t need = align_up(pl.sub.size(), 64) + mlp_infer_scratch_floats((int)pl.sub.size());
+            e = ensure_mlp_scratch(c, need);
+            if (e != LCF_OK) return e;
+        }
         if (c->schedule == 1) {
             // the paper's loop: one subset at a time through every per-subset stage
             const ChunkDesc* dch = (const ChunkDesc*)(c->dbuf + seq_off);
@@ -529,6 +604,9 @@ lcf_status lcf_destroy(lcf_context* c) {
     hipDeviceSynchronize();
     for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
     for (auto e : c->evpool) hipEventDestroy(e);
+    for (void* p : {(void*)c->mlp.master, (void*)c->mlp.wbf, (void*)c->mlp.m, (void*)c->mlp.v, (void*)c->mlp.grad,
+                    (void*)c->mlp_scratch})
+        if (p) hipFree(p);
     if (c->dbuf) hipFree(c->dbuf);
     if (c->hbuf) hipHostFree(c->hbuf);
     if (c->sticky) hipFree(c->sticky);
@@ -578,6 +656,7 @@ lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_thres
     if (!ctx || !iq || !pd) return LCF_ERR_INVALID_ARG;
     lcf_status e = lcf_validate(geo, thr, precision);
     if (e != LCF_OK) return e;
+    if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
     std::vector<PacketIn> in{PacketIn{*geo, iq, iq_out, pd}};
     return filter_packets(ctx, in, thr, precision, diag, (hipStream_t)stream);
 }
@@ -591,6 +670,7 @@ lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo
         lcf_status e = lcf_validate(&geo[i], thr, precision);
         if (e != LCF_OK) return e;
         if (!iq[i] || !pd[i]) return LCF_ERR_INVALID_ARG;
+        if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
         if (thr->cut == LCF_CUT_EXPLICIT) return LCF_ERR_UNSUPPORTED;
         in.push_back(PacketIn{geo[i], iq[i], iq_out ? iq_out[i] : nullptr, pd[i]});
     }
@@ -616,6 +696,156 @@ lcf_status lcf_heevd_batched(lcf_context* ctx, int32_t n, int32_t nt, const doub
     fws.S = n;
     fws.flags = fl;
     if (launch_flags_or(fws, ctx->sticky, st) != hipSuccess) return LCF_ERR_DEVICE;
+    return LCF_OK;
+}
+
+lcf_status lcf_mlp_init(lcf_context* ctx, uint64_t seed) {
+    if (!ctx) return LCF_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status e = ensure_mlp(ctx);
+    if (e != LCF_OK) return e;
+    std::vector<float> h(MLP_NPARAM, 0.f);
+    uint64_t x = seed;
+    auto next = [&]() {   // splitmix64 -> uniform [0, 1)
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    };
+    auto fill = [&](int off, int rows, int cols) {
+        const double bound = std::sqrt(6.0 / cols) * 0.5;
+        for (int i = 0; i < rows * cols; ++i) h[off + i] = (float)((2.0 * next() - 1.0) * bound);
+    };
+    fill(MLP_OFF_W1, MLP_H, MLP_NT);
+    fill(MLP_OFF_W2, MLP_H, MLP_H);
+    fill(MLP_OFF_W3, MLP_NT, MLP_H);
+    for (int i = 0; i < MLP_NT; ++i) h[MLP_OFF_B3 + i] = 2.0f;
+    return lcf_mlp_set_params(ctx, h.data(), MLP_NPARAM);
+}
+
+lcf_status lcf_mlp_set_params(lcf_context* ctx, const float* host, int64_t n) {
+    if (!ctx || !host || n != MLP_NPARAM) return LCF_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status e = ensure_mlp(ctx);
+    if (e != LCF_OK) return e;
+    if (hipMemcpy(ctx->mlp.master, host, n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(ctx->mlp.m, 0, n * sizeof(float)) != hipSuccess ||
+        hipMemset(ctx->mlp.v, 0, n * sizeof(float)) != hipSuccess)
+        return LCF_ERR_DEVICE;
+    if (mlp_refresh_bf16(ctx->mlp, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return LCF_ERR_DEVICE;
+    ctx->mlp_step = 0;
+    ctx->mlp_ready = true;
+    return LCF_OK;
+}
+
+static lcf_status mlp_copy_out(lcf_context* ctx, const float* src, float* host, int64_t n) {
+    if (!ctx || !host || n != MLP_NPARAM) return LCF_ERR_INVALID_ARG;
+    if (!ctx->mlp_ready) return LCF_ERR_MODEL;
+    if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return LCF_ERR_DEVICE;
+    if (hipMemcpy(host, src, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return LCF_ERR_DEVICE;
+    return LCF_OK;
+}
+
+lcf_status lcf_mlp_get_params(lcf_context* ctx, float* host, int64_t n) {
+    return mlp_copy_out(ctx, ctx ? ctx->mlp.master : nullptr, host, n);
+}
+
+lcf_status lcf_mlp_get_grads(lcf_context* ctx, float* host, int64_t n) {
+    return mlp_copy_out(ctx, ctx ? ctx->mlp.grad : nullptr, host, n);
+}
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t nparam;
+    uint64_t step;
+};
+}
+
+lcf_status lcf_mlp_save(lcf_context* ctx, const char* path) {
+    if (!ctx || !path) return LCF_ERR_INVALID_ARG;
+    if (!ctx->mlp_ready) return LCF_ERR_MODEL;
+    const size_t n = MLP_NPARAM;
+    std::vector<float> buf(3 * n);
+    if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(buf.data(), ctx->mlp.master, n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(buf.data() + n, ctx->mlp.m, n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(buf.data() + 2 * n, ctx->mlp.v, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return LCF_ERR_DEVICE;
+    CkptHeader hd;
+    std::memcpy(hd.magic, "LCFMLP01", 8);
+    hd.version = 1;
+    hd.nparam = (uint32_t)n;
+    hd.step = (uint64_t)ctx->mlp_step;
+    uint32_t crc = crc32_update(0, &hd, sizeof(hd));
+    crc = crc32_update(crc, buf.data(), buf.size() * 4);
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return LCF_ERR_INVALID_ARG;
+    const bool ok = std::fwrite(&hd, sizeof(hd), 1, f) == 1 && std::fwrite(buf.data(), 4, buf.size(), f) == buf.size() &&
+                    std::fwrite(&crc, 4, 1, f) == 1;
+    std::fclose(f);
+    return ok ? LCF_OK : LCF_ERR_INVALID_ARG;
+}
+
+lcf_status lcf_mlp_load(lcf_context* ctx, const char* path) {
+    if (!ctx || !path) return LCF_ERR_INVALID_ARG;
+    const size_t n = MLP_NPARAM;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return LCF_ERR_MODEL;
+    CkptHeader hd;
+    std::vector<float> buf(3 * n);
+    uint32_t crc_file = 0;
+    const bool ok = std::fread(&hd, sizeof(hd), 1, f) == 1 && std::memcmp(hd.magic, "LCFMLP01", 8) == 0 &&
+                    hd.version == 1 && hd.nparam == n && std::fread(buf.data(), 4, buf.size(), f) == buf.size() &&
+                    std::fread(&crc_file, 4, 1, f) == 1;
+    std::fclose(f);
+    if (!ok) return LCF_ERR_MODEL;
+    uint32_t crc = crc32_update(0, &hd, sizeof(hd));
+    crc = crc32_update(crc, buf.data(), buf.size() * 4);
+    if (crc != crc_file) return LCF_ERR_MODEL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status e = ensure_mlp(ctx);
+    if (e != LCF_OK) return e;
+    if (hipMemcpy(ctx->mlp.master, buf.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->mlp.m, buf.data() + n, n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->mlp.v, buf.data() + 2 * n, n * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return LCF_ERR_DEVICE;
+    if (mlp_refresh_bf16(ctx->mlp, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return LCF_ERR_DEVICE;
+    ctx->mlp_step = (long long)hd.step;
+    ctx->mlp_ready = true;
+    return LCF_OK;
+}
+
+lcf_status lcf_mlp_infer(lcf_context* ctx, const double* lam, float* w, int32_t b, void* stream) {
+    if (!ctx || !lam || !w || b < 1) return LCF_ERR_INVALID_ARG;
+    if (!ctx->mlp_ready) return LCF_ERR_MODEL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status e = ensure_mlp_scratch(ctx, mlp_infer_scratch_floats(b) + align_up((size_t)b, 64));
+    if (e != LCF_OK) return e;
+    hipStream_t st = (hipStream_t)stream;
+    float* z = ctx->mlp_scratch;
+    float* act = z + (size_t)b * MLP_NT;
+    if (mlp_features(lam, MLP_NT, b, z, nullptr, st) != hipSuccess) return LCF_ERR_DEVICE;
+    if (mlp_forward(ctx->mlp, z, b, act, w, st) != hipSuccess) return LCF_ERR_DEVICE;
+    return LCF_OK;
+}
+
+lcf_status lcf_mlp_train_step(lcf_context* ctx, const double* lam, const float* target, int32_t b, float lr,
+                              float* loss_out, void* stream) {
+    if (!ctx || !lam || !target || b < 1 || !(lr >= 0.f)) return LCF_ERR_INVALID_ARG;
+    if (!ctx->mlp_ready) return LCF_ERR_MODEL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status e = ensure_mlp_scratch(ctx, mlp_train_scratch_floats(b));
+    if (e != LCF_OK) return e;
+    ctx->mlp_step += 1;
+    if (mlp_train_step(ctx->mlp, lam, target, b, lr, (int)ctx->mlp_step, ctx->mlp_scratch, loss_out,
+                       (hipStream_t)stream) != hipSuccess)
+        return LCF_ERR_DEVICE;
     return LCF_OK;
 }
 

@@ -1,0 +1,167 @@
+"""GPU parity of the learned-weight kernels (forward, backward, Adam, checkpoint)
+against the FP64 oracle, and their use inside the filter."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as M
+import synth
+from parity import rel_fro, pd_db_error
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(lcf):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = lcf.Context(0)
+    yield c
+    c.close()
+
+
+def _spectra(b, seed):
+    rng = np.random.default_rng(seed)
+    lam = np.sort(10.0 ** rng.uniform(-7.5, 0, size=(b, M.NT)), axis=1)[:, ::-1] * 10.0 ** rng.uniform(4, 9, size=(b, 1))
+    k = rng.integers(3, 12, size=(b, 1))
+    t = 1.0 / (1.0 + np.exp(-2.0 * (np.arange(1, M.NT + 1)[None, :] - k)))
+    return np.ascontiguousarray(lam), np.ascontiguousarray(t.astype(np.float32))
+
+
+def test_forward_matches_oracle(lcf, ctx):
+    _say("[mlp forward parity]")
+    ctx.mlp_init(7)
+    p = M.unflatten(ctx.mlp_get_params())
+    lam, _ = _spectra(300, 1)
+    w_gpu = ctx.mlp_infer(torch.from_numpy(lam).cuda()).cpu().numpy()
+    w_ref, _ = M.forward(p, M.features(lam), bf16=True)
+    err = np.max(np.abs(w_gpu - w_ref))
+    _say(f"   max |w_gpu - w_oracle| = {err:.2e}")
+    assert err <= 2e-5
+
+
+def test_gradients_and_loss_match_oracle(lcf, ctx):
+    _say("[mlp gradient parity]")
+    ctx.mlp_init(11)
+    p0 = ctx.mlp_get_params()
+    p = M.unflatten(p0)
+    lam, t = _spectra(200, 2)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.mlp_train_step(torch.from_numpy(lam).cuda(), torch.from_numpy(t).cuda(), 0.0, loss_out=loss)
+    torch.cuda.synchronize()
+    g_gpu = M.unflatten(ctx.mlp_get_grads())
+    z = M.features(lam)
+    w, cache = M.forward(p, z, bf16=True)
+    t64 = t.astype(np.float64)
+    c = M.loss_weights(lam, t64)
+    g_ref = M.backward(cache, t64, c)
+    l_ref = M.loss(w, t64, c)
+    _say(f"   loss gpu={loss.item():.6e} oracle={l_ref:.6e}")
+    assert abs(loss.item() - l_ref) <= 1e-3 * abs(l_ref)
+    for k in M.SHAPES:
+        e = np.linalg.norm(g_gpu[k] - g_ref[k]) / max(np.linalg.norm(g_ref[k]), 1e-30)
+        _say(f"   grad {k}: rel err {e:.2e}")
+        assert e <= 1e-2, k
+    # lr = 0 leaves the master weights unchanged
+    assert np.array_equal(ctx.mlp_get_params(), p0)
+
+
+def test_adam_step_matches_oracle(lcf, ctx):
+    _say("[mlp adam step]")
+    ctx.mlp_init(5)
+    p = M.unflatten(ctx.mlp_get_params())
+    lam, t = _spectra(128, 3)
+    ctx.mlp_train_step(torch.from_numpy(lam).cuda(), torch.from_numpy(t).cuda(), 1e-3)
+    torch.cuda.synchronize()
+    got = M.unflatten(ctx.mlp_get_params())
+    g = M.unflatten(ctx.mlp_get_grads())
+    m = {k: np.zeros(s) for k, s in M.SHAPES.items()}
+    v = {k: np.zeros(s) for k, s in M.SHAPES.items()}
+    ref = {k: x.copy() for k, x in p.items()}
+    M.adam_step(ref, {k: g[k].astype(np.float64) for k in g}, m, v, 1, 1e-3)
+    for k in M.SHAPES:
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-6, k
+
+
+def test_checkpoint_roundtrip_and_crc(lcf, ctx):
+    _say("[mlp checkpoint]")
+    ctx.mlp_init(9)
+    p = ctx.mlp_get_params()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "w.ckpt")
+        ctx.mlp_save(path)
+        ctx.mlp_init(10)
+        ctx.mlp_load(path)
+        assert np.array_equal(ctx.mlp_get_params(), p)
+        raw = bytearray(open(path, "rb").read())
+        raw[100] ^= 0x55
+        open(path, "wb").write(bytes(raw))
+        ctx.mlp_init(10)
+        with pytest.raises(lcf.LcfError) as ei:
+            ctx.mlp_load(path)
+        assert ei.value.status == 7
+        assert not np.array_equal(ctx.mlp_get_params(), p)     # untouched by the failed load
+
+
+def test_training_reduces_loss(lcf, ctx):
+    _say("[mlp training]")
+    ctx.mlp_init(3)
+    lam, t = _spectra(2048, 4)
+    lam_t, t_t = torch.from_numpy(lam).cuda(), torch.from_numpy(t).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    for step in range(300):
+        sl = slice((step % 4) * 512, (step % 4 + 1) * 512)
+        ctx.mlp_train_step(lam_t[sl].contiguous(), t_t[sl].contiguous(), 2e-3, loss_out=loss)
+        if step % 50 == 0 or step == 299:
+            torch.cuda.synchronize()
+            losses.append(loss.item())
+    _say(f"   losses {['%.3e' % x for x in losses]}")
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_filter_with_mlp_weights(lcf, ctx):
+    _say("[filter with MLP weights]")
+    ctx.mlp_init(21)
+    p = M.unflatten(ctx.mlp_get_params())
+    spec = synth.spec_clinical(1)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_MLP, shape=lcf.SHAPE_SIGMOID)
+    io, pd, dg = ctx.filter(torch.from_numpy(iq).cuda(), 8, 8, thr, diag=True)
+    torch.cuda.synchronize()
+    assert ctx.sync() == 0
+    d = {k: v.cpu().numpy() for k, v in dg.items()}
+    assert np.all((d["flags"] & lcf.FLAG_MLP_FALLBACK) == 0)
+    w_ref, _ = M.forward(p, M.features(d["eigvals"]), bf16=True)
+    assert np.max(np.abs(d["weights"] - w_ref)) <= 2e-5
+    # the rest of the path with these weights, against the oracle forced to them
+    res = O.filter_packet(iq, 8, 8, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=d["weights"].astype(np.float64)))
+    e_fro = rel_fro(io.cpu().numpy(), res["iq_out"])
+    emax, _, _, _ = pd_db_error(pd.cpu().numpy(), res["pd"], mask)
+    _say(f"   rel_fro={e_fro:.2e} pd_db={emax:.2e}")
+    assert e_fro <= 1e-4 and emax <= 0.1
+
+
+def test_mlp_fallback_for_other_nt(lcf, ctx):
+    _say("[mlp fallback nt=64]")
+    ctx.mlp_init(1)
+    iq, _ = synth.make_packet(synth.PacketSpec(48, 40, 64, 50.0, 0.4, ((20, 3, 0.5),), seed=8))
+    thr = lcf.Threshold(cut=lcf.CUT_MLP, shape=lcf.SHAPE_SIGMOID)
+    _, _, dg = ctx.filter(torch.from_numpy(iq).cuda(), 2, 2, thr, diag=True)
+    torch.cuda.synchronize()
+    flags = dg["flags"].cpu().numpy()
+    assert np.all(flags & lcf.FLAG_MLP_FALLBACK)
+    lam = dg["eigvals"].cpu().numpy()
+    for s in range(4):
+        w_rule, _, _, _ = O.rule_weights(lam[s], O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID))
+        assert np.allclose(dg["weights"].cpu().numpy()[s], w_rule, atol=1e-6)
