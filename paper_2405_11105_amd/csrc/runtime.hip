@@ -251,8 +251,39 @@ lcf_status ensure_host(lcf_context* c, size_t bytes) {
     return LCF_OK;
 }
 
+void drop_graphs(lcf_context* c) {
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+// Everything that shapes a launch group's kernels and their arguments, except
+// the packet pointers (those live in the descriptors re-uploaded every call).
+std::string graph_key(lcf_context* c, const Plan& pl, const std::vector<PacketIn>& in,
+                      const std::vector<int>& idx, const lcf_threshold* thr, int prec, const lcf_diag* diag) {
+    std::string k;
+    char buf[256];
+    for (int i : idx) {
+        const lcf_geometry& g = in[i].g;
+        std::snprintf(buf, sizeof buf, "g%d,%d,%d,%d,%d,%.17g,%.17g,%d|", g.ny, g.nx, g.nt, g.gy, g.gx, g.sigma_frac,
+                      g.trunc_sigmas, in[i].iq_out != nullptr);
+        k += buf;
+    }
+    std::snprintf(buf, sizeof buf, "t%d,%d,%d,%d,%.17g,%.17g,%.17g,%.17g,%p|p%d,s%d,w%d,i%d,n%d", thr->cut, thr->shape,
+                  thr->pd_mode, thr->k_fixed, thr->beta_knee, thr->knee_max_frac, thr->beta_sigmoid, thr->deflate_rho,
+                  (const void*)thr->explicit_w, prec, c->schedule, c->max_sweeps, c->sub_iters, pl.ntp);
+    k += buf;
+    if (diag) {
+        std::snprintf(buf, sizeof buf, "|d%p,%p,%p,%p,%p,%p,%p,%p,%p", (void*)diag->eigvals, (void*)diag->weights,
+                      (void*)diag->k, (void*)diag->sweeps, (void*)diag->flags, (void*)diag->alpha, (void*)diag->cov,
+                      (void*)diag->eigvecs, (void*)diag->rank);
+        k += buf;
+    }
+    return k;
+}
+
 lcf_status ensure_mlp_scratch(lcf_context* c, size_t floats) {
     if (floats <= c->mlp_scratch_cap) return LCF_OK;
+    drop_graphs(c);
     if (c->mlp_scratch) {
         if (hipDeviceSynchronize() != hipSuccess) return LCF_ERR_DEVICE;
         hipFree(c->mlp_scratch);
@@ -546,32 +577,65 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
             e = ensure_mlp_scratch(c, need);
             if (e != LCF_OK) return e;
         }
-        if (c->schedule == 1) {
-            // the paper's loop: one subset at a time through every per-subset stage
-            const ChunkDesc* dch = (const ChunkDesc*)(c->dbuf + seq_off);
-            const int* dcb = (const int*)(c->dbuf + seq_off + pl.chunks.size() * sizeof(ChunkDesc));
-            for (int s = 0; s < (int)pl.sub.size(); ++s) {
-                const int cb0 = pl.chunk_begin[s], nch = pl.chunk_begin[s + 1] - cb0;
-                Workspace v = subset_view(ws, s, dch + cb0, dcb + 2 * s, nch);
-                if (ws.explicit_w) v.explicit_w = ws.explicit_w + (long)s * pl.sub[s].nt;
-                double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
-                e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
+        // Launch chain of the group, optionally captured once into a hipGraph and
+        // replayed for later calls with the same plan (not on the null stream, and
+        // not while stage timing is on).
+        const bool graph = c->use_graph && !c->timing && st != nullptr;
+        std::string key;
+        if (graph) {
+            key = graph_key(c, pl, in, kv.second, thr, prec, diag);
+            auto it = c->graphs.find(key);
+            if (it != c->graphs.end()) {
+                HIPCHK(hipGraphLaunch(it->second, st));
+                continue;
+            }
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        }
+        auto chain = [&]() -> lcf_status {
+            if (c->schedule == 1) {
+                // the paper's loop: one subset at a time through every per-subset stage
+                const ChunkDesc* dch = (const ChunkDesc*)(c->dbuf + seq_off);
+                const int* dcb = (const int*)(c->dbuf + seq_off + pl.chunks.size() * sizeof(ChunkDesc));
+                for (int s = 0; s < (int)pl.sub.size(); ++s) {
+                    const int cb0 = pl.chunk_begin[s], nch = pl.chunk_begin[s + 1] - cb0;
+                    Workspace v = subset_view(ws, s, dch + cb0, dcb + 2 * s, nch);
+                    if (ws.explicit_w) v.explicit_w = ws.explicit_w + (long)s * pl.sub[s].nt;
+                    double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
+                    e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
+                    if (e != LCF_OK) return e;
+                    e = run_stages2(c, v, thr, prec, pl.sub[s].nt, st);
+                    if (e != LCF_OK) return e;
+                }
+            } else {
+                e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
                 if (e != LCF_OK) return e;
-                e = run_stages2(c, v, thr, prec, pl.sub[s].nt, st);
+                e = run_stages2(c, ws, thr, prec, pl.nt_max, st);
                 if (e != LCF_OK) return e;
             }
-        } else {
-            e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
-            if (e != LCF_OK) return e;
-            e = run_stages2(c, ws, thr, prec, pl.nt_max, st);
-            if (e != LCF_OK) return e;
+            { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
+            if (diag)
+                HIPCHK(launch_export(ws, 0, (int)pl.sub.size(), pl.sub[0].nt, diag->eigvals, diag->weights, diag->k,
+                                     diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs,
+                                     st));
+
+            HIPCHK(launch_flags_or(ws, c->sticky, st));
+            return LCF_OK;
+        };
+        e = chain();
+        if (graph) {
+            hipGraph_t gr = nullptr;
+            const hipError_t ce = hipStreamEndCapture(st, &gr);
+            if (e != LCF_OK) { if (gr) hipGraphDestroy(gr); return e; }
+            if (ce != hipSuccess) return LCF_ERR_DEVICE;
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            hipGraphDestroy(gr);
+            if (ie != hipSuccess) return LCF_ERR_DEVICE;
+            c->graphs[key] = ex;
+            HIPCHK(hipGraphLaunch(ex, st));
+        } else if (e != LCF_OK) {
+            return e;
         }
-        { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
-        if (diag)
-            HIPCHK(launch_export(ws, 0, (int)pl.sub.size(), pl.sub[0].nt, diag->eigvals, diag->weights, diag->k,
-                                 diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs,
-                                 st));
-        HIPCHK(launch_flags_or(ws, c->sticky, st));
     }
     return LCF_OK;
 }

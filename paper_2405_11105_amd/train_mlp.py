@@ -1,0 +1,174 @@
+"""Train the learned eigencomponent-weight network on the GPU with the library's
+own forward/backward/Adam kernels, and evaluate it against the rule it replaces.
+
+Teacher. For every training packet the filter runs with the curvature rule
+(Eq. 6) and sigmoid weights (Eq. 9) at each scaling factor beta of a grid; the
+beta whose power Doppler image has the highest CNR against the generator's
+vessel masks is kept, and its per-subset weights become the targets. This is
+the per-packet exhaustive beta search of the Experimental Studies section,
+which the Discussion notes is impractical in real time: the network has to
+produce the searched weights from one subset's spectrum alone.
+
+CNR = 10 log10((mean PD_vessel - mean PD_background) / std PD_background) with
+the background = pixels farther than 3 rows from any vessel (Data processing
+and evaluation section).
+
+  python -m paper_2405_11105_amd.train_mlp --train 782 --holdout 32 --out mlp.ckpt
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+BETAS = (0.5, 0.7, 1.0, 1.4, 2.0, 2.8)
+
+
+def _make(args):
+    kind, seed = args
+    import synth
+    spec = synth.spec_learned(seed) if kind == "learned" else synth.spec_clinical(seed, seed_base=0)
+    iq, mask = synth.make_packet(spec)
+    return seed, iq, mask
+
+
+def cnr_db(pd, mask):
+    """CNR (dB) of a PD map (torch, GPU) against a vessel mask (torch bool)."""
+    import torch
+    bg = ~mask
+    for d in range(1, 4):
+        bg &= ~torch.roll(mask, d, 0) & ~torch.roll(mask, -d, 0)
+    b = pd[mask].double().mean()
+    g = pd[bg].double()
+    num = (b - g.mean()).clamp_min(1e-30)
+    return float(10.0 * torch.log10(num / g.std()))
+
+
+def packet_runs(ctx, lcf, iq, mask_t, grid, prec, betas=BETAS):
+    """Filter one packet at every beta; returns (eigvals [S][nt], weights per beta, cnr per beta)."""
+    import torch
+    out_w, cnrs, lam = [], [], None
+    for beta in betas:
+        thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID, beta_knee=beta)
+        _, pd, dg = ctx.filter(iq, grid[0], grid[1], thr, precision=prec, iq_out=False, diag=True)
+        if lam is None:
+            lam = dg["eigvals"].clone()
+        out_w.append(dg["weights"].clone())
+        cnrs.append(cnr_db(pd, mask_t))
+    return lam, out_w, cnrs
+
+
+def generate(ctx, lcf, kind, seeds, grid, prec, workers):
+    """Teacher data: eigvals [N][128] (float64, GPU), targets [N][128] (float32, GPU), info."""
+    import torch
+    lams, tgts, info = [], [], []
+    ctxmp = mp.get_context("spawn")   # workers run numpy only and never touch the GPU
+    with ctxmp.Pool(workers) as pool:
+        for seed, iq_np, mask_np in pool.imap(_make, [(kind, s) for s in seeds], chunksize=1):
+            iq = torch.from_numpy(iq_np).cuda()
+            mask_t = torch.from_numpy(mask_np).cuda()
+            lam, ws, cnrs = packet_runs(ctx, lcf, iq, mask_t, grid, prec)
+            best = int(np.argmax(cnrs))
+            lams.append(lam)
+            tgts.append(ws[best])
+            info.append({"seed": int(seed), "best_beta": BETAS[best], "cnr": cnrs})
+    return torch.cat(lams), torch.cat(tgts), info
+
+
+def train(ctx, lam, tgt, epochs, batch, lr, seed=0, log=None):
+    import torch
+    n = lam.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device=lam.device)
+    hist = []
+    steps_per_epoch = max(1, n // batch)
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(lam.device)
+        lr_ep = lr * 0.5 * (1.0 + math.cos(math.pi * ep / epochs))
+        acc = 0.0
+        for s in range(steps_per_epoch):
+            idx = perm[s * batch:(s + 1) * batch]
+            ctx.mlp_train_step(lam[idx].contiguous(), tgt[idx].contiguous(), lr_ep, loss_out=loss)
+            acc += loss.item() if s == steps_per_epoch - 1 else 0.0
+        hist.append(acc)
+        if log:
+            log(f"epoch {ep} lr {lr_ep:.2e} loss {acc:.4e}")
+    return hist
+
+
+def evaluate(ctx, lcf, kind, seeds, grid, prec, workers):
+    """Held-out comparison of rule (beta = 1), searched-beta teacher and MLP."""
+    import torch
+    rows = []
+    ctxmp = mp.get_context("spawn")   # workers run numpy only and never touch the GPU
+    with ctxmp.Pool(workers) as pool:
+        for seed, iq_np, mask_np in pool.imap(_make, [(kind, s) for s in seeds], chunksize=1):
+            iq = torch.from_numpy(iq_np).cuda()
+            mask_t = torch.from_numpy(mask_np).cuda()
+            _, ws, cnrs = packet_runs(ctx, lcf, iq, mask_t, grid, prec)
+            best = int(np.argmax(cnrs))
+            thr_t = lcf.Threshold(cut=lcf.CUT_EXPLICIT)
+            _, pd_t, _ = ctx.filter(iq, grid[0], grid[1], thr_t, precision=prec, iq_out=False, explicit_w=ws[best])
+            thr_m = lcf.Threshold(cut=lcf.CUT_MLP, shape=lcf.SHAPE_SIGMOID)
+            _, pd_m, dg = ctx.filter(iq, grid[0], grid[1], thr_m, precision=prec, iq_out=False, diag=True)
+            fallback = float(((dg["flags"] & lcf.FLAG_MLP_FALLBACK) != 0).float().mean())
+            floor = torch.median(pd_t[~mask_t])
+            sel = pd_t >= 2 * floor
+            dev = (10 * torch.log10(pd_m[sel] / pd_t[sel])).abs()
+            rows.append({"seed": int(seed), "cnr_rule": cnrs[BETAS.index(1.0)], "cnr_teacher": cnrs[best],
+                         "cnr_mlp": cnr_db(pd_m, mask_t), "best_beta": BETAS[best],
+                         "pd_db_vs_teacher_p99": float(torch.quantile(dev.double(), 0.99)),
+                         "pd_db_vs_teacher_max": float(dev.max()), "fallback_rate": fallback})
+    return rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--kind", default="learned", choices=["learned", "clinical"])
+    ap.add_argument("--train", type=int, default=782, help="training packets")
+    ap.add_argument("--holdout", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"])
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--out", default="mlp.ckpt")
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args(argv)
+    import torch
+    import paper_2405_11105_amd as lcf
+    grid = (16, 16) if args.kind == "learned" else (8, 8)
+    base_train, base_hold = (10000, 20000) if args.kind == "learned" else (5000, 6000)
+    prec = lcf.PREC_BF16X3 if args.precision == "bf16x3" else lcf.PREC_FP32
+    log = lambda m: print(m, flush=True)
+    ctx = lcf.Context(0)
+    t0 = time.time()
+    lam, tgt, info = generate(ctx, lcf, args.kind, range(base_train, base_train + args.train), grid, prec,
+                              args.workers)
+    log(f"teacher data: {lam.shape[0]} spectra from {args.train} packets in {time.time() - t0:.1f} s; "
+        f"best beta histogram {np.unique([i['best_beta'] for i in info], return_counts=True)}")
+    ctx.mlp_init(1)
+    t1 = time.time()
+    hist = train(ctx, lam, tgt, args.epochs, args.batch, args.lr, log=log)
+    log(f"training: {time.time() - t1:.1f} s")
+    ctx.mlp_save(args.out)
+    rows = evaluate(ctx, lcf, args.kind, range(base_hold, base_hold + args.holdout), grid, prec, args.workers)
+    summ = {k: float(np.mean([r[k] for r in rows])) for k in
+            ("cnr_rule", "cnr_teacher", "cnr_mlp", "pd_db_vs_teacher_p99", "pd_db_vs_teacher_max", "fallback_rate")}
+    log("held-out mean: " + json.dumps(summ))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump({"summary": summ, "rows": rows, "loss": hist, "train_info": info}, f)
+    ctx.close()
+    return summ
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    main()

@@ -278,3 +278,27 @@ def test_precision_60db_fp32(lcf, ctx):
     iq, mask = synth.make_packet(spec)
     thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
     _check_end_to_end(lcf, ctx, iq, mask, 8, 8, thr, 1e-5, 0.1, "60 dB fp32")
+
+
+def test_graph_replay_matches_eager(lcf, ctx):
+    _say("[hipGraph replay]")
+    iqs = [torch.from_numpy(synth.make_packet(synth.spec_small(s))[0]).cuda() for s in (7, 8)]
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ref = [ctx.filter(iq, 3, 3, thr) for iq in iqs]
+        st.synchronize()
+        gctx = lcf.Context(0, use_graph=1)
+        try:
+            for rep in range(4):
+                for i, iq in enumerate(iqs):
+                    io, pd, _ = gctx.filter(iq, 3, 3, thr)
+                    st.synchronize()
+                    assert torch.equal(io, ref[i][0]) and torch.equal(pd, ref[i][1]), (rep, i)
+                # eager work of the program between replays
+                _ = (iqs[0].abs() ** 2).sum().item()
+                ctx.filter(iqs[1], 2, 2, thr)
+                st.synchronize()
+            assert gctx.sync() == 0
+        finally:
+            gctx.close()

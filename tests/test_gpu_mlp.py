@@ -165,3 +165,25 @@ def test_mlp_fallback_for_other_nt(lcf, ctx):
     for s in range(4):
         w_rule, _, _, _ = O.rule_weights(lam[s], O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID))
         assert np.allclose(dg["weights"].cpu().numpy()[s], w_rule, atol=1e-6)
+
+
+def test_learned_weights_gain_over_fixed_rule(lcf, ctx):
+    """Train the network on the GPU (library kernels) to reproduce the per-packet
+    CNR-searched beta of the curvature rule, then compare held-out packets: the
+    network needs no search, and should beat the rule at the default beta."""
+    _say("[mlp gain test]")
+    from paper_2405_11105_amd import train_mlp as T
+    lam, tgt, info = T.generate(ctx, lcf, "clinical", range(100, 148), (8, 8), lcf.PREC_FP32, workers=8)
+    _say(f"   {lam.shape[0]} teacher spectra; best beta counts "
+         f"{dict(zip(*np.unique([i['best_beta'] for i in info], return_counts=True)))}")
+    ctx.mlp_init(2)
+    hist = T.train(ctx, lam, tgt, epochs=60, batch=512, lr=3e-3)
+    _say(f"   loss first/last epoch {hist[0]:.3e} / {hist[-1]:.3e}")
+    rows = T.evaluate(ctx, lcf, "clinical", range(200, 212), (8, 8), lcf.PREC_FP32, workers=8)
+    rule = np.array([r["cnr_rule"] for r in rows])
+    mlp_ = np.array([r["cnr_mlp"] for r in rows])
+    teach = np.array([r["cnr_teacher"] for r in rows])
+    _say(f"   held-out CNR dB: rule(beta=1) {rule.mean():.2f}  mlp {mlp_.mean():.2f}  searched-beta {teach.mean():.2f}")
+    _say(f"   per packet gain mlp-rule: {np.round(mlp_ - rule, 2).tolist()}")
+    assert hist[-1] < hist[0]
+    assert mlp_.mean() > rule.mean()
