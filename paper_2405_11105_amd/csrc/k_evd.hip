@@ -416,6 +416,271 @@ __device__ void jacobi_core(double2* G, int nt, int ld, int max_sweeps, int* swe
     __syncthreads();
 }
 
+__device__ void jacobi_finish(const double2* G, int nt, int ld, double* lam_out, double2* vout, int ldv,
+                              bool col_major);
+
+// ------------------------------------------------------------------ register-resident Jacobi
+// The same one-sided Jacobi with the matrix held in VGPRs: NW waves hold 16
+// columns each (two half-blocks of 8: "top" slots 0-7 and "bottom" slots 8-15),
+// lane l holds rows l + 64 i (i < RPL). A sweep is (1) all pairs inside each
+// half-block (7 steps of the circle method on 8 slots) and (2) 2 NW - 1 rounds in
+// which every wave pairs each top column with each bottom column (8 steps,
+// bottom slots rotated by one after each step), after which half-blocks move
+// between waves through LDS following the circle method over the 2 NW
+// half-blocks (half-block 0 stays in place). Each step handles 8 disjoint pairs:
+// lane partial sums, a transposed butterfly that leaves dot product (l >> 1) in
+// lane l, rotation parameters in lanes 0-7, broadcast by readlane.
+__device__ __forceinline__ double rdl(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Lane-swap sum of two wave-wide doubles: for M = 32 lanes below 32 return
+// a[l] + a[l + 32] and lanes above 32 return b[l - 32] + b[l]; for M = 16 the
+// same within each 32-lane half (rows of 16 lanes), a in even rows, b in odd.
+template <int M>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+    const unsigned alo = (unsigned)(ab & 0xffffffff), ahi = (unsigned)(ab >> 32);
+    const unsigned blo = (unsigned)(bb & 0xffffffff), bhi = (unsigned)(bb >> 32);
+    unsigned x0, x1, y0, y1;
+    if constexpr (M == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    }
+    const double p = __longlong_as_double((long long)(((unsigned long long)x1 << 32) | x0));
+    const double q = __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0));
+    return p + q;
+}
+
+template <int RPL>
+struct JCols {
+    double2 x[16][RPL];
+};
+
+// Pair slots of a step. MODE 0 (inside half-blocks): (0,7) (1,6) (2,5) (3,4) and
+// the same in the bottom half; MODE 1 (across): (i, 8 + i).
+__host__ __device__ constexpr int pslot_a(int mode, int k) { return mode == 0 ? (k < 4 ? k : 4 + k) : k; }
+__host__ __device__ constexpr int pslot_b(int mode, int k) { return mode == 0 ? (k < 4 ? 7 - k : 19 - k) : 8 + k; }
+
+// Rotate 4 disjoint pairs (k = G..G+3) of the wave's registers.
+template <int RPL, int MODE, int G>
+__device__ __forceinline__ void jac_step4(JCols<RPL>& c, int lane, double tol, int& nrot, double& offmax) {
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const double2 a = c.x[pslot_a(MODE, G + k)][i], b = c.x[pslot_b(MODE, G + k)][i];
+            al = fma(a.x, a.x, fma(a.y, a.y, al));
+            be = fma(b.x, b.x, fma(b.y, b.y, be));
+            gr = fma(a.x, b.x, fma(a.y, b.y, gr));
+            gi = fma(a.x, b.y, fma(-a.y, b.x, gi));
+        }
+        v[4 * k + 0] = al;
+        v[4 * k + 1] = be;
+        v[4 * k + 2] = gr;
+        v[4 * k + 3] = gi;
+    }
+    // transposed butterfly: after masks 32,16,8,4 lane l holds value (l >> 2).
+    // Masks 32 and 16 use the lane-swap instructions (no selects); 8 and 4 work
+    // on named scalars so that no select turns into an indexed register access.
+    double w8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w8[j] = swap_sum<32>(v[j], v[j + 8]);
+    double u[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[j] = swap_sum<16>(w8[j], w8[j + 4]);
+    const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
+    const double u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3];
+    const double z0 = (h8 ? u2 : u0) + __shfl_xor(h8 ? u0 : u2, 8, 64);
+    const double z1 = (h8 ? u3 : u1) + __shfl_xor(h8 ? u1 : u3, 8, 64);
+    double tot = (h4 ? z1 : z0) + __shfl_xor(h4 ? z0 : z1, 4, 64);
+    tot += __shfl_xor(tot, 2, 64);
+    tot += __shfl_xor(tot, 1, 64);
+    // gather pair k's four sums into lane k
+    const int k = lane & 3;
+    const double al = __shfl(tot, 4 * (4 * k + 0), 64);
+    const double be = __shfl(tot, 4 * (4 * k + 1), 64);
+    const double gr = __shfl(tot, 4 * (4 * k + 2), 64);
+    const double gi = __shfl(tot, 4 * (4 * k + 3), 64);
+    const double mag = sqrt(gr * gr + gi * gi);
+    const double scale = sqrt(al * be);
+    double cc = 1.0, ss = 0.0, er = 1.0, ei = 0.0;
+    const bool rot = mag > tol * scale;
+    if (rot) {
+        const double zeta = (be - al) / (2.0 * mag);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        cc = 1.0 / sqrt(1.0 + t * t);
+        ss = cc * t;
+        er = gr / mag;
+        ei = -gi / mag;
+    }
+    const double off = scale > 0.0 ? mag / scale : 0.0;
+    const unsigned long long rb = __ballot(rot && lane < 4);
+    nrot += __popcll(rb);
+    double om = lane < 4 ? off : 0.0;
+    om = fmax(om, __shfl_xor(om, 2, 64));
+    om = fmax(om, __shfl_xor(om, 1, 64));
+    offmax = fmax(offmax, rdl(om, 0));
+    const double ser = ss * er, sei = ss * ei, cer = cc * er, cei = cc * ei;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double C = rdl(cc, q), S = rdl(ss, q);
+        const double SR = rdl(ser, q), SI = rdl(sei, q), CR = rdl(cer, q), CI = rdl(cei, q);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const double2 a = c.x[pslot_a(MODE, G + q)][i], b = c.x[pslot_b(MODE, G + q)][i];
+            c.x[pslot_a(MODE, G + q)][i] =
+                make_double2(fma(C, a.x, -fma(SR, b.x, -SI * b.y)), fma(C, a.y, -fma(SR, b.y, SI * b.x)));
+            c.x[pslot_b(MODE, G + q)][i] =
+                make_double2(fma(S, a.x, fma(CR, b.x, -CI * b.y)), fma(S, a.y, fma(CR, b.y, CI * b.x)));
+        }
+    }
+}
+
+template <int RPL, int MODE>
+__device__ __forceinline__ void jac_step8(JCols<RPL>& c, int lane, double tol, int& nrot, double& offmax) {
+    jac_step4<RPL, MODE, 0>(c, lane, tol, nrot, offmax);
+    jac_step4<RPL, MODE, 4>(c, lane, tol, nrot, offmax);
+}
+
+template <int RPL, int NW>
+__global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sweeps) {
+    constexpr int ROWS = 64 * RPL;
+    constexpr int SLOT = 8 * ROWS;                     // double2 per half-block
+    __shared__ double2 xch[(NW + 1) * SLOT];
+    __shared__ int idx[NW + 1];
+    __shared__ int top_id[NW], bot_id[NW];
+    __shared__ int s_rot[NW];
+    __shared__ double s_off[NW];
+    const int s = blockIdx.x, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
+    const int nt = ws.sub[s].nt, ntp = ws.ntp;
+    const double2* B = ws.bmat + (long)s * ntp * ntp;
+    double2* Gout = ws.wvec + (long)s * ntp * ntp;
+    const double tol = (double)nt * 1.1102230246251565e-16;
+
+    int my_top = 2 * wave, my_bot = 2 * wave + 1;
+    JCols<RPL> c;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int col = (j < 8 ? my_top : my_bot) * 8 + (j & 7);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            c.x[j][i] = (row < nt && col < nt) ? cconj(B[(long)col * ntp + row]) : make_double2(0.0, 0.0);
+        }
+    }
+    int sweep = 0;
+    bool converged = false;
+    double prev_off = 1e300;
+    for (; sweep < max_sweeps; ++sweep) {
+        int nrot = 0;
+        double offmax = 0.0;
+        // (1) pairs inside each half-block: circle method, slot 0 (and 8) fixed
+#pragma unroll 1
+        for (int st = 0; st < 7; ++st) {
+            jac_step8<RPL, 0>(c, lane, tol, nrot, offmax);
+#pragma unroll
+            for (int h = 0; h < 16; h += 8) {
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const double2 t7 = c.x[h + 7][i];
+#pragma unroll
+                    for (int j = 7; j > 1; --j) c.x[h + j][i] = c.x[h + j - 1][i];
+                    c.x[h + 1][i] = t7;
+                }
+            }
+        }
+        // (2) cross rounds
+#pragma unroll 1
+        for (int rd = 0; rd < 2 * NW - 1; ++rd) {
+#pragma unroll 1
+            for (int st = 0; st < 8; ++st) {
+                jac_step8<RPL, 1>(c, lane, tol, nrot, offmax);
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const double2 t0 = c.x[8][i];
+#pragma unroll
+                    for (int j = 8; j < 15; ++j) c.x[j][i] = c.x[j + 1][i];
+                    c.x[15][i] = t0;
+                }
+            }
+            if (rd == 2 * NW - 2) break;      // the last round needs no move
+            // move half-blocks (circle method, half-block at wave 0 top fixed)
+            auto put = [&](int slot, int base) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) xch[slot * SLOT + j * ROWS + lane + 64 * i] = c.x[base + j][i];
+            };
+            auto get = [&](int slot, int base) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) c.x[base + j][i] = xch[slot * SLOT + j * ROWS + lane + 64 * i];
+            };
+            __syncthreads();
+            // phase 1: tops move right; wave 0's bottom becomes wave 1's top
+            if (wave >= 1) { put(wave, 0); if (lane == 0) idx[wave] = my_top; }
+            else { put(0, 8); if (lane == 0) idx[0] = my_bot; }
+            __syncthreads();
+            if (wave >= 1) { get(wave - 1, 0); my_top = idx[wave - 1]; }
+            __syncthreads();
+            // phase 2: bottoms move left; the last wave's old top becomes its bottom
+            if (wave == NW - 1) {
+                put(NW, 8);
+                if (lane == 0) idx[NW] = my_bot;
+                get(NW - 1, 8);                 // old top written in phase 1
+                my_bot = idx[NW - 1];
+            } else if (wave >= 1) {
+                put(wave, 8);
+                if (lane == 0) idx[wave] = my_bot;
+            }
+            __syncthreads();
+            if (wave <= NW - 2) {
+                const int src = (wave == NW - 2) ? NW : wave + 1;
+                get(src, 8);
+                my_bot = idx[src];
+            }
+        }
+        if (lane == 0) { s_rot[wave] = nrot; s_off[wave] = offmax; }
+        __syncthreads();
+        int tr = 0;
+        double off = 0.0;
+        for (int w = 0; w < NW; ++w) { tr += s_rot[w]; off = fmax(off, s_off[w]); }
+        const bool stagnant = sweep >= 3 && off < 1e-6 && off > 0.25 * prev_off;
+        prev_off = off;
+        __syncthreads();
+        if (tr == 0 || stagnant) { converged = true; ++sweep; break; }
+    }
+    // write columns back (column-major, stride ntp)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int col = (j < 8 ? my_top : my_bot) * 8 + (j & 7);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row < nt && col < nt) Gout[(long)col * ntp + row] = c.x[j][i];
+        }
+    }
+    if (threadIdx.x == 0) {
+        ws.sweeps[s] = sweep;
+        if (!converged) atomicOr(&ws.flags[s], 4);
+    }
+    __syncthreads();
+    jacobi_finish(Gout, nt, ntp, ws.lam + (long)s * ntp, ws.bmat + (long)s * ntp * ntp, ntp, true);
+}
+
 // Normalise columns, sort by norm descending, write eigenvalues and vectors.
 // vout: column-major (vector j contiguous) when col_major, else row-major.
 __device__ void jacobi_finish(const double2* G, int nt, int ld, double* lam_out, double2* vout,
@@ -549,6 +814,19 @@ static int max_nt(const Workspace& ws) { return ws.ntp; }
 
 hipError_t launch_jacobi(const Workspace& ws, int max_sweeps, int nt_max, hipStream_t st) {
     (void)max_nt;
+    // register-resident variants by padded size; the LDS / global versions beyond 128
+    if (ws.ntp <= 32) {
+        hipLaunchKernelGGL((k_jacobi_reg<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, max_sweeps);
+        return hipGetLastError();
+    }
+    if (ws.ntp <= 64) {
+        hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps);
+        return hipGetLastError();
+    }
+    if (ws.ntp <= 128) {
+        hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps);
+        return hipGetLastError();
+    }
     if (nt_max <= JAC_LDS_NT) {
         const size_t lds = (size_t)nt_max * nt_max * sizeof(double2);
         hipLaunchKernelGGL((k_jacobi_subsets<true>), dim3(ws.S), dim3(JAC_THREADS), lds, st, ws, max_sweeps);
