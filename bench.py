@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the localized EVD clutter filter on one MI355X.
 
-A step is one pass of the whole hot path (windowing, covariance, deflation,
-FP64 EVD, weights, projection, power Doppler, recombination) over a batch of
-synthetic packets already resident in HBM. Prints one JSON line.
+A step is one pass of the whole hot path (windowing, covariance, tissue
+deflation, FP64 Jacobi EVD, eigencomponent weights, projection, power Doppler,
+recombination) over a batch of synthetic packets already resident in HBM.
 
-  python bench.py [--steps K] [--warmup W] [--workload clinical|small|learned]
-                  [--precision fp32|bf16x3] [--schedule batched|sequential]
+Two configurations of the same library are timed on the same packets:
+  fast  - learned weights (trained network), split-BF16 GEMMs, all subsets of
+          all packets batched per stage, replayed from a captured hipGraph;
+  plain - FP32 GEMMs, the curvature-knee rule with sigmoid weights (Eqs 6, 9),
+          and the paper's loop over subsets (one subset at a time through every
+          per-subset stage), no graph.
+`value` is the fast configuration's frames/s; the plain one is reported beside
+it. Both are checked against the FP64 CPU oracle on packet 0. Prints one JSON
+line.
+
+  python bench.py [--steps K] [--warmup W] [--batch B] [--workload learned|clinical|small]
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -19,54 +27,63 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "local-EVD filtered frames/s on 1 GPU, MLP+split-BF16 vs plain FP32 at ≤0.1 dB PD"
-
 PEAK = {"fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "fp64": 78.6e12, "hbm": 8.0e12}
+DEFAULT_MLP = os.path.join(ROOT, "paper_2405_11105_amd", "weights", "mlp_512x256x128.ckpt")
 
 WORKLOADS = {
-    # name: (spec factory, grid, rule)
-    "clinical": ("spec_clinical", (8, 8), "knee"),
-    "small": ("spec_small", (3, 3), "fixed4"),
-    "learned": ("spec_learned", (16, 16), "knee-sigmoid"),
+    # name: (spec factory, seed of packet 0, grid)
+    "learned": ("spec_learned", 20000, (16, 16)),
+    "clinical": ("spec_clinical", 0, (8, 8)),
+    "small": ("spec_small", 0, (3, 3)),
 }
 
 
-def _threshold(lcf, rule):
-    if rule == "fixed4":
-        return lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=4)
-    if rule == "knee":
-        return lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_HARD)
-    return lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
-
-
-def _specs(synth, name, n):
-    fac = getattr(synth, WORKLOADS[name][0])
-    if name == "small":
-        return [fac(p) for p in range(n)]
-    if name == "learned":
-        return [fac(20000 + p) for p in range(n)]
-    return [fac(p) for p in range(n)]
-
-
 def _neff(ny, nx, gy, gx):
-    """Box pixel count per subset (same window geometry as the library)."""
-    import oracle as O
-    return [(w.y1 - w.y0 + 1) * (w.x1 - w.x0 + 1) for w in O.window_boxes(ny, nx, gy, gx)]
+    """Box pixel count per subset (the window geometry: centres (j + 1/2) ny/gy - 1/2,
+    sigma = spacing / 3, boxes of +-6 sigma clipped to the image)."""
+    import math
+    out = []
+    for a in range(gy):
+        for b in range(gx):
+            ext = []
+            for n, g, j in ((ny, gy, a), (nx, gx, b)):
+                d = n / g
+                c, s = (j + 0.5) * d - 0.5, d / 3.0
+                lo, hi = max(0, math.ceil(c - 6 * s)), min(n - 1, math.floor(c + 6 * s))
+                ext.append(hi - lo + 1)
+            out.append(ext[0] * ext[1])
+    return out
+
+
+def _pd_db(pd, ref, mask):
+    """Max / p99 |10 log10(pd / ref)| over pixels with ref >= 2 x the median of ref
+    outside the vessel mask dilated by 2 px."""
+    import numpy as np
+    m = mask.copy()
+    for ax in (0, 1):
+        for d in (1, 2):
+            m |= np.roll(mask, d, ax) | np.roll(mask, -d, ax)
+    floor = np.median(ref[~m])
+    sel = ref >= 2.0 * floor
+    e = np.abs(10.0 * np.log10(pd[sel] / ref[sel]))
+    return float(e.max()), float(np.quantile(e, 0.99))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=4, help="packets per step")
-    ap.add_argument("--workload", default="clinical", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
-    ap.add_argument("--schedule", default="batched", choices=["batched", "sequential"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle time budget for cpu_baseline")
+    ap.add_argument("--workload", default="learned", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--mlp", default=DEFAULT_MLP, help="trained network checkpoint")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="oracle time budget for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build targets one GPU; multi-GPU sharding is designed but not built "
+        print("bench.py: this build runs on one GPU; sharding across GPUs is designed but not built "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
@@ -78,112 +95,160 @@ def main():
 
     lcf.load()
     dev = torch.device("cuda:0")
-    gy, gx = WORKLOADS[args.workload][1]
-    thr = _threshold(lcf, WORKLOADS[args.workload][2])
-    prec = lcf.PREC_FP32 if args.precision == "fp32" else lcf.PREC_BF16X3
-    specs = _specs(synth, args.workload, args.batch)
+    fac, seed0, (gy, gx) = WORKLOADS[args.workload]
+    specs = [getattr(synth, fac)(seed0 + p) for p in range(args.batch)]
     host = [synth.make_packet(s) for s in specs]
-    iqs = [torch.from_numpy(h[0]).to(dev) for h in host]
-    nt, ny, nx = iqs[0].shape
-    outs = [(torch.empty_like(iq), torch.empty((ny, nx), dtype=torch.float32, device=dev)) for iq in iqs]
-    ctx = lcf.Context(0, schedule=1 if args.schedule == "sequential" else 0)
+    nt, ny, nx = host[0][0].shape
+    stream = torch.cuda.Stream(device=dev)          # default priority; graphs need a non-null stream
+    use_mlp = nt == 128 and os.path.exists(args.mlp)
+    if nt == 128 and not use_mlp:
+        raise FileNotFoundError(f"trained network checkpoint not found: {args.mlp}")
+    thr_plain = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    thr_fast = lcf.Threshold(cut=lcf.CUT_MLP, shape=lcf.SHAPE_SIGMOID) if use_mlp else thr_plain
 
-    # per-subset sweeps of this data (for the Jacobi operation count)
-    _, _, dg = ctx.filter(iqs[0], gy, gx, thr, precision=prec, diag=True)
-    torch.cuda.synchronize()
-    sweeps = dg["sweeps"].cpu().numpy()
-    ranks = dg["rank"].cpu().numpy()
+    with torch.cuda.stream(stream):
+        iqs = [torch.from_numpy(h[0]).to(dev) for h in host]
+        outs_f = [(torch.empty_like(iq), torch.empty((ny, nx), dtype=torch.float32, device=dev)) for iq in iqs]
+        outs_p = [(torch.empty_like(iq), torch.empty((ny, nx), dtype=torch.float32, device=dev)) for iq in iqs]
+        fast = lcf.Context(0, schedule=0, use_graph=1)
+        if use_mlp:
+            fast.mlp_load(args.mlp)
+        grids = [(gy, gx)] * len(iqs)
 
-    def step():
-        ctx.filter_batch(iqs, [(gy, gx)] * len(iqs), thr, precision=prec, outs=outs)
+        def step_fast():
+            fast.filter_batch(iqs, grids, thr_fast, precision=lcf.PREC_BF16X3, outs=outs_f)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    if ctx.sync() != 0:
-        raise RuntimeError("device-side error flagged during warm-up")
-    ctx.set_option(lcf.OPT_STAGE_TIMING, 1)
-    ctx.stage_times(reset=True)
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    stages = ctx.stage_times(reset=True)
-    ctx.set_option(lcf.OPT_STAGE_TIMING, 0)
-    st = ctx.sync()
-    frames = len(iqs) * nt * args.steps
-    value = frames / (ms_step * args.steps / 1e3)
+        # per-subset sweeps and ranks of packet 0 (operation counts)
+        _, _, dg = fast.filter(iqs[0], gy, gx, thr_fast, precision=lcf.PREC_BF16X3, diag=True)
+        torch.cuda.synchronize()
+        sweeps = dg["sweeps"].cpu().numpy()
+        ranks = dg["rank"].cpu().numpy()
+        fallback = float(((dg["flags"] & lcf.FLAG_MLP_FALLBACK) != 0).float().mean().item())
 
-    # algorithmic work per launch of each stage (one launch covers all packets of a step)
+        for _ in range(args.warmup):
+            step_fast()
+        torch.cuda.synchronize()
+        if fast.sync() != 0:
+            raise RuntimeError("device-side error flagged during warm-up")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step_fast()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_step = ev0.elapsed_time(ev1) / args.steps
+        if fast.sync() != 0:
+            raise RuntimeError("device-side error flagged in the timed region")
+
+        # the same steps again with per-launch HIP events on this stream (no graph
+        # replay while they are on): per-kernel durations for the roofline
+        fast.set_option(lcf.OPT_STAGE_TIMING, 1)
+        fast.stage_times(reset=True)
+        for _ in range(args.steps):
+            step_fast()
+        torch.cuda.synchronize()
+        stages = fast.stage_times(reset=True)
+        fast.set_option(lcf.OPT_STAGE_TIMING, 0)
+
+        plain = None
+        if not args.no_plain:
+            pctx = lcf.Context(0, schedule=1, use_graph=0)
+
+            def step_plain():
+                pctx.filter_batch(iqs, grids, thr_plain, precision=lcf.PREC_FP32, outs=outs_p)
+
+            step_plain()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.plain_steps):
+                step_plain()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pms = e0.elapsed_time(e1) / args.plain_steps
+            plain = {"value": len(iqs) * nt / (pms / 1e3), "unit": "frames/s", "ms_per_step": pms,
+                     "steps": args.plain_steps, "precision": "fp32", "schedule": "sequential per subset",
+                     "rule": "knee + sigmoid (beta 1, 2)", "graph": False, "device_status": pctx.sync()}
+            pctx.close()
+
+    frames = len(iqs) * nt
+    value = frames / (ms_step / 1e3)
+
+    # algorithmic work per launch (one launch covers all packets of a step)
     neff = _neff(ny, nx, gy, gx)
     sum_neff = float(sum(neff)) * len(iqs)
     pairs = nt * (nt - 1) / 2.0
     work = {
-        "gram1": ("mfma", 4.0 * sum_neff * nt * nt, PEAK["fp32_mfma"] if prec == 0 else PEAK["bf16_mfma"]),
-        "gram2": ("mfma", 4.0 * sum_neff * nt * nt, PEAK["fp32_mfma"] if prec == 0 else PEAK["bf16_mfma"]),
-        "reproj": ("mfma", 8.0 * sum_neff * nt * nt, PEAK["fp32_mfma"] if prec == 0 else PEAK["bf16_mfma"]),
-        "jacobi": ("alu", float(np.sum(sweeps)) * len(iqs) * pairs * 30.0 * nt, PEAK["fp64"]),
+        "gram1": ("mfma", 4.0 * sum_neff * nt * nt, PEAK["bf16_mfma"]),
+        "gram2": ("mfma", 4.0 * sum_neff * (nt + 16) ** 2, PEAK["bf16_mfma"]),
+        "reproj": ("mfma", 8.0 * sum_neff * nt * (nt + 16), PEAK["bf16_mfma"]),
+        "jacobi": ("alu", float(np.sum(sweeps)) * len(iqs) * pairs * 40.0 * nt, PEAK["fp64"]),
     }
-    dom = max(stages, key=lambda k: stages[k][0])
+    timed = {k: v for k, v in stages.items() if v[1]}
+    dom = max(timed, key=lambda k: timed[k][0])
     roof = None
-    if dom in work and stages[dom][1] > 0:
+    if dom in work:
         bound, flops, peak = work[dom]
-        avg_s = stages[dom][0] / stages[dom][1] / 1e3
-        ach = flops / avg_s
+        avg_ms = timed[dom][0] / timed[dom][1]
+        ach = flops / (avg_ms / 1e3)
         roof = {"bound": bound, "kernel": dom, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "avg_launch_ms": stages[dom][0] / stages[dom][1]}
+                "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_ms}
 
     cpu = None
-    parity = None
+    parity = {}
     if not args.no_cpu_baseline:
         import oracle as O
+        from oracle import mlp as M
         from threadpoolctl import threadpool_info
-        othr = O.Threshold(cut=thr.cut, shape=thr.shape, k_fixed=thr.k_fixed, beta_knee=thr.beta_knee,
-                           knee_max_frac=thr.knee_max_frac, beta_sigmoid=thr.beta_sigmoid)
-        runs, t_cpu = 0, 0.0
-        res = None
-        while t_cpu < args.cpu_seconds and runs < len(host):
-            t1 = time.perf_counter()
-            r = O.filter_packet(host[runs][0], gy, gx, othr)
-            t_cpu += time.perf_counter() - t1
-            if res is None:
-                res = r
-            runs += 1
+        if use_mlp:
+            params = M.unflatten(fast.mlp_get_params())
+            othr_f = O.Threshold(cut=O.CUT_MLP, mlp=lambda lam: M.forward(params, M.features(lam))[0][0])
+        else:
+            othr_f = O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID)
+        iq0, mask0 = host[0]
+        t1 = time.perf_counter()
+        ref_f = O.filter_packet(iq0, gy, gx, othr_f)
+        t_cpu = time.perf_counter() - t1
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        cpu = {"value": runs * nt / t_cpu, "unit": "frames/s", "cores": threads, "kind": "oracle",
-               "sample": f"{runs} packet(s) of the same workload, FP64 numpy oracle, {t_cpu:.1f} s"}
-        pd = outs[0][1].cpu().numpy()
-        io = outs[0][0].cpu().numpy()
-        e_fro = float(np.linalg.norm(io - res["iq_out"]) / np.linalg.norm(res["iq_out"]))
-        sel = res["pd"] >= 2.0 * np.median(res["pd"])
-        e_db = float(np.max(np.abs(10 * np.log10(pd[sel] / res["pd"][sel]))))
-        parity = {"rel_fro_iq": e_fro, "pd_db_max": e_db, "packet": 0}
+        cpu = {"value": nt / t_cpu, "unit": "frames/s", "cores": threads, "kind": "oracle",
+               "sample": f"packet 0 of the workload ({ny}x{nx}x{nt}, {gy}x{gx} windows, fast "
+                         f"configuration's rule), FP64 numpy oracle, {t_cpu:.1f} s"}
+        io_f = outs_f[0][0].cpu().numpy()
+        pdx, pd99 = _pd_db(outs_f[0][1].cpu().numpy(), ref_f["pd"], mask0)
+        parity["fast"] = {"rel_fro_iq": float(np.linalg.norm(io_f - ref_f["iq_out"]) /
+                                              np.linalg.norm(ref_f["iq_out"])),
+                          "pd_db_max": pdx, "pd_db_p99": pd99, "packet": 0}
+        if plain is not None and t_cpu < args.cpu_seconds:
+            ref_p = O.filter_packet(iq0, gy, gx, O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID))
+            io_p = outs_p[0][0].cpu().numpy()
+            pdx, pd99 = _pd_db(outs_p[0][1].cpu().numpy(), ref_p["pd"], mask0)
+            parity["plain"] = {"rel_fro_iq": float(np.linalg.norm(io_p - ref_p["iq_out"]) /
+                                                   np.linalg.norm(ref_p["iq_out"])),
+                               "pd_db_max": pdx, "pd_db_p99": pd99, "packet": 0}
 
     out = {
         "metric": METRIC, "value": value, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if prec == 0 else "bf16x3", "data": "synthetic",
-        "config": {"workload": f"{args.workload} {ny}x{nx}x{nt}, {gy}x{gx} Gaussian windows, "
-                               f"{WORKLOADS[args.workload][2]} rule, {args.precision}, {args.schedule}",
-                   "packets_per_step": len(iqs), "ny": ny, "nx": nx, "nt": nt, "grid": [gy, gx],
-                   "precision": args.precision, "schedule": args.schedule},
+        "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+        "config": {"workload": f"{args.workload} packets {ny}x{nx}x{nt}, {gy}x{gx} Gaussian windows, "
+                               f"{'learned weights' if use_mlp else 'knee-sigmoid rule'}, split-BF16 GEMMs, "
+                               "batched, hipGraph replay",
+                   "packets_per_step": len(iqs), "ny": ny, "nx": nx, "nt": nt, "grid": [gy, gx]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "plain": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "parity": parity,
-        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in timed.items()},
         "jacobi_sweeps_mean": float(np.mean(sweeps)),
         "deflated_rank_mean": float(np.mean(ranks)),
+        "mlp_fallback_rate": fallback,
         "wall_s": wall,
-        "device_status": st,
     }
     print(json.dumps(out))
+    fast.close()
 
 
 if __name__ == "__main__":

@@ -35,7 +35,7 @@ struct GramCfg {
     static constexpr int NT16 = NTE / 16;
     static constexpr int TPM = NT16 * (NT16 + 1) / 2;      // upper tiles per matrix
     static constexpr int TT = 2 * TPM;                     // S and T tiles, interleaved
-    static constexpr int WAVES = TT > 120 ? 8 : 4;
+    static constexpr int WAVES = TT > 60 ? 8 : 4;
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int MAXT = (TT + WAVES - 1) / WAVES;
     static constexpr int PX = NTP > 160 ? 16 : PIX;        // pixels per LDS batch
@@ -84,10 +84,7 @@ k_gram(Workspace ws) {
     constexpr int NTE = C::NTE, IMO = C::IMO, LDA = C::LDA, LDB = C::LDB, PIX = C::PX;
     __shared__ __attribute__((aligned(16))) uint32_t Aw[C::A_WORDS];
     __shared__ double wpix[PIX];
-    __shared__ float2 craw[DEFL ? NTP * PIX : 1];
-    __shared__ float2 vr32[DEFL ? NTP * RMAX : 1];
-    __shared__ double2 vr64[DEFL ? NTP * RMAX : 1];
-    __shared__ float2 yv[DEFL ? PIX * RMAX : 1];
+    __shared__ double2 vrs[DEFL ? RMAX * NTP : 1];     // V_r, [j][t]
     float* A = reinterpret_cast<float*>(Aw);
     uint32_t* Ah = Aw;                   // BF16 hi words [NTE][LDB]
     uint32_t* Al = Aw + NTE * LDB;       // BF16 lo words
@@ -116,8 +113,8 @@ k_gram(Workspace ws) {
     if (DEFL) {
         r = ws.rank[ch.s];
         for (int e = tid; e < NTP * RMAX; e += C::THREADS) {
-            vr32[e] = ws.vr32[(long)ch.s * NTP * RMAX + e];
-            vr64[e] = ws.vr64[(long)ch.s * NTP * RMAX + e];
+            const int t = e / RMAX, j = e % RMAX;
+            vrs[j * NTP + t] = ws.vr64[(long)ch.s * NTP * RMAX + e];
         }
     }
 
@@ -165,54 +162,74 @@ k_gram(Workspace ws) {
                 put(p, t, re, im);
             }
         } else {
-            for (int e = tid; e < PIX * NTP; e += C::THREADS) {
-                const int p = e % PIX, t = e / PIX;
-                const int q = qb + p;
-                float2 c = make_float2(0.f, 0.f);
-                if (q < ch.q1 && t < nt) {
-                    const int yy = q / sd.bw, xx = q - yy * sd.bw;
-                    c = sd.iq[(long)t * npix + (long)(sd.y0 + yy) * nx + sd.x0 + xx];
-                }
-                craw[t * PIX + p] = c;
+            // Pixel pp of the batch is handled by the G consecutive lanes part =
+            // 0..G-1, frames t = part + G i, held in registers.
+            constexpr int G = C::THREADS / PIX > 16 ? 16 : C::THREADS / PIX;
+            constexpr int TPT = NTP / G;
+            static_assert(NTP % G == 0, "frames split evenly over a pixel's lanes");
+            const int pp = tid / G, part = tid % G;
+            const int q = qb + pp;
+            long poff = -1;
+            if (pp < PIX) {     // whole waves beyond the batch's pixels idle here
+            if (q < ch.q1) {
+                const int yy = q / sd.bw, xx = q - yy * sd.bw;
+                poff = (long)(sd.y0 + yy) * nx + sd.x0 + xx;
             }
-            __syncthreads();
-            // Tissue scores y = w s V_r (any value keeps C_w = C' + Y V_r^H exact).
-            for (int e = tid; e < PIX * REXT; e += C::THREADS) {
-                const int p = e % PIX, j = e / PIX;
-                float2 y = make_float2(0.f, 0.f);
+            float2 sreg[TPT];
+#pragma unroll
+            for (int i = 0; i < TPT; ++i) {
+                const int t = part + G * i;
+                sreg[i] = (poff >= 0 && t < nt) ? sd.iq[(long)t * npix + poff] : make_float2(0.f, 0.f);
+            }
+            const double w = wpix[pp];
+            // Tissue scores y = w s V_r in FP64 over this lane's frames, reduced over
+            // the pixel's lanes, rounded to FP32 (any value keeps C_w = C' + Y V_r^H exact).
+            float2 y[RMAX];
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j) {
+                double yr = 0.0, yi = 0.0;
                 if (j < r) {
-                    float ar = 0.f, ai = 0.f;
-                    for (int t = 0; t < nt; ++t) {
-                        const float2 c = craw[t * PIX + p];
-                        const float2 v = vr32[t * RMAX + j];
-                        ar = fmaf(c.x, v.x, fmaf(-c.y, v.y, ar));
-                        ai = fmaf(c.x, v.y, fmaf(c.y, v.x, ai));
+#pragma unroll
+                    for (int i = 0; i < TPT; ++i) {
+                        const double2 v = vrs[j * NTP + part + G * i];
+                        yr = fma((double)sreg[i].x, v.x, fma(-(double)sreg[i].y, v.y, yr));
+                        yi = fma((double)sreg[i].x, v.y, fma((double)sreg[i].y, v.x, yi));
                     }
-                    const float w = (float)wpix[p];
-                    y = make_float2(w * ar, w * ai);
-                    yv[p * RMAX + j] = y;
+#pragma unroll
+                    for (int m = G >> 1; m >= 1; m >>= 1) {
+                        yr += __shfl_xor(yr, m, 64);
+                        yi += __shfl_xor(yi, m, 64);
+                    }
                 }
-                put(p, NTP + j, y.x, y.y);
+                y[j] = make_float2((float)(w * yr), (float)(w * yi));
             }
-            __syncthreads();
             // Bulk residual c' = w s - y V_r^H in FP64, rounded once.
-            for (int e = tid; e < PIX * NTP; e += C::THREADS) {
-                const int p = e % PIX, t = e / PIX;
+#pragma unroll
+            for (int i = 0; i < TPT; ++i) {
+                const int t = part + G * i;
                 double re = 0.0, im = 0.0;
                 if (t < nt) {
-                    const float2 c = craw[t * PIX + p];
-                    const double w = wpix[p];
-                    re = w * (double)c.x;
-                    im = w * (double)c.y;
-                    for (int j = 0; j < r; ++j) {
-                        const float2 y = yv[p * RMAX + j];
-                        const double2 v = vr64[t * RMAX + j];
-                        // y * conj(v)
-                        re -= (double)y.x * v.x + (double)y.y * v.y;
-                        im -= (double)y.y * v.x - (double)y.x * v.y;
+                    re = w * (double)sreg[i].x;
+                    im = w * (double)sreg[i].y;
+#pragma unroll
+                    for (int j = 0; j < RMAX; ++j) {
+                        if (j < r) {
+                            const double2 v = vrs[j * NTP + t];
+                            // y * conj(v)
+                            re -= (double)y[j].x * v.x + (double)y[j].y * v.y;
+                            im -= (double)y[j].y * v.x - (double)y[j].x * v.y;
+                        }
                     }
                 }
-                put(p, t, (float)re, (float)im);
+                put(pp, t, (float)re, (float)im);
+            }
+            for (int j = part; j < REXT; j += G) {
+                float2 yj = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int jj = 0; jj < RMAX; ++jj)
+                    if (jj == j && jj < r) yj = y[jj];
+                put(pp, NTP + j, yj.x, yj.y);
+            }
             }
         }
         __syncthreads();

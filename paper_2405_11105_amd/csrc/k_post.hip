@@ -217,279 +217,107 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
 }
 
 // ------------------------------------------------------------------ reprojection
-// One work-group per image row segment of up to PIX pixels. For every covering
-// subset d (ascending order): y = s V_r (FP32), c' = s - y V_r^H (FP64, then
-// rounded), chat = [c' | y] [P; M] on MFMA, and the epilogue accumulates
+// One work-group per image row segment of up to PIX pixels (output-centric
+// gather, no atomics). For every covering subset d in ascending order:
+//   y  = s V_r                      (FP64 partial sums, split over t, rounded to FP32)
+//   c' = s - y V_r^H                (FP64, then rounded to the GEMM operand)
+//   chat = [c' | y] [P; M]          (MFMA: FP32, or BF16 hi/lo with three products)
+// and the epilogue accumulates in registers
 //   PD(x)   += alpha_d w_d(x)^2 sum_t |chat(x, t)|^2     (Eq. 13)
 //   IQ(x,t) += w_d(x) chat(x, t),  W(x) += w_d(x)
-// in registers. The window factors out of the projection because
-// C_hat_d(x, :) = w_d(x) s_x P_d. The tile writes PD and IQ / W once.
-template <int NTP>
-struct ReprojCfg {
+// The window factors out of the projection because C_hat_d(x, :) = w_d(x) s_x P_d.
+// Each wave owns CTW output column tiles of both 16-pixel row tiles.
+// Work-groups are mapped to tiles so that each of the 8 XCDs walks a contiguous
+// range of tiles (neighbouring tiles share covering subsets, so their [P; M]
+// operands stay in that XCD's L2).
+template <int NTP, int PREC>
+struct RpCfg {
     static constexpr int NTE = NTP + REXT;
-    static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;
-    static constexpr int LDA = 2 * IMO + 1;
-    static constexpr int CT = (2 * NTP) / 16;     // output column tiles
-    static constexpr int TT = 2 * CT;             // x 2 row tiles (32 pixels)
-    static constexpr int MAXT = (TT + 3) / 4;
+    static constexpr int NTEP = (NTE + 31) / 32 * 32;                 // BF16: K per part, padded
+    static constexpr int LDK = 2 * NTEP + 8;                          // BF16 row stride (uint16)
+    static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;     // FP32: offset of the im part
+    static constexpr int LDA = 2 * IMO + 1;                           // FP32 row stride (floats)
+    static constexpr int CT = (2 * NTP) / 16;                         // output column tiles
+    static constexpr int NW = CT >= 8 ? 8 : CT;                       // waves
+    static constexpr int NTHR = 64 * NW;
+    static constexpr int CTW = (CT + NW - 1) / NW;                    // column tiles per wave
+    static constexpr int LDC = NTP + 1;                               // craw row stride (float2)
+    static constexpr int G = NTHR / PIX;                              // threads per pixel for y
+    static constexpr int ABYTES = PREC ? 2 * PIX * LDK * 2 : PIX * LDA * 4;
+    // two work-groups per CU where the LDS allows it (caps VGPRs at 128 for 8 waves)
+    static constexpr int MINW = NTP <= 128 ? NW / 2 : 1;
 };
 
-template <int NTP>
-__global__ void __launch_bounds__(256) k_reproj(Workspace ws) {
-    using C = ReprojCfg<NTP>;
-    constexpr int NTE = C::NTE, IMO = C::IMO, LDA = C::LDA;
+template <int NTP, int PREC>
+__global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::MINW)) k_reproj(Workspace ws) {
+    using C = RpCfg<NTP, PREC>;
+    constexpr int NTEP = C::NTEP, LDK = C::LDK, IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
+    constexpr int NTHR = C::NTHR, CTW = C::CTW, G = C::G;
     static_assert(PIX == 32, "reprojection tile is 2 x 16 pixels");
-    __shared__ float A[PIX * LDA];
-    __shared__ float2 craw[NTP * PIX];
-    __shared__ float2 vr32[NTP * RMAX];
-    __shared__ double2 vr64[NTP * RMAX];
-    __shared__ float2 yv[PIX * RMAX];
-    __shared__ float wd[PIX];
-    __shared__ float pdsh[4 * PIX];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const TileDesc td = ws.tiles[blockIdx.x];
-    const PacketDesc pk = ws.pkts[td.pkt];
-    const int nt = pk.nt, nx = pk.nx;
-    const long npix = (long)pk.ny * pk.nx;
-    const int npx = td.x1 - td.x0 + 1;
-
-    for (int e = tid; e < PIX * NTP; e += 256) {
-        const int p = e % PIX, t = e / PIX;
-        float2 c = make_float2(0.f, 0.f);
-        if (p < npx && t < nt) c = pk.iq[(long)t * npix + (long)td.y * nx + td.x0 + p];
-        craw[t * PIX + p] = c;
-    }
-    floatx4 iq_acc[C::MAXT];
-    float pd_acc[8];
-#pragma unroll
-    for (int m = 0; m < C::MAXT; ++m) iq_acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < 8; ++i) pd_acc[i] = 0.f;
-
-    for (int ci = 0; ci < td.cov_cnt; ++ci) {
-        const int s = ws.cover[td.cov_off + ci];
-        const SubsetDesc sd = ws.sub[s];
-        const int r = ws.rank[s];
-        const float alpha = (float)ws.alpha[s];
-        __syncthreads();
-        for (int e = tid; e < NTP * RMAX; e += 256) {
-            vr32[e] = ws.vr32[(long)s * NTP * RMAX + e];
-            vr64[e] = ws.vr64[(long)s * NTP * RMAX + e];
-        }
-        if (tid < PIX) {
-            const int x = td.x0 + tid;
-            float w = 0.f;
-            if (tid < npx && td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
-                w = sd.flat ? 1.f : (float)(ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0]);
-            wd[tid] = w;
-        }
-        __syncthreads();
-        for (int e = tid; e < PIX * REXT; e += 256) {
-            const int p = e % PIX, j = e / PIX;
-            float2 y = make_float2(0.f, 0.f);
-            if (j < r) {
-                float ar = 0.f, ai = 0.f;
-                for (int t = 0; t < nt; ++t) {
-                    const float2 c = craw[t * PIX + p];
-                    const float2 v = vr32[t * RMAX + j];
-                    ar = fmaf(c.x, v.x, fmaf(-c.y, v.y, ar));
-                    ai = fmaf(c.x, v.y, fmaf(c.y, v.x, ai));
-                }
-                y = make_float2(ar, ai);
-                yv[p * RMAX + j] = y;
-            }
-            A[p * LDA + NTP + j] = y.x;
-            A[p * LDA + IMO + NTP + j] = y.y;
-        }
-        __syncthreads();
-        for (int e = tid; e < PIX * NTP; e += 256) {
-            const int p = e % PIX, t = e / PIX;
-            double re = 0.0, im = 0.0;
-            if (t < nt) {
-                const float2 c = craw[t * PIX + p];
-                re = (double)c.x;
-                im = (double)c.y;
-                for (int j = 0; j < r; ++j) {
-                    const float2 y = yv[p * RMAX + j];
-                    const double2 v = vr64[t * RMAX + j];
-                    re -= (double)y.x * v.x + (double)y.y * v.y;
-                    im -= (double)y.y * v.x - (double)y.x * v.y;
-                }
-            }
-            A[p * LDA + t] = (float)re;
-            A[p * LDA + IMO + t] = (float)im;
-        }
-        __syncthreads();
-        const float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
-        floatx4 acc[C::MAXT];
-#pragma unroll
-        for (int m = 0; m < C::MAXT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const int kq = lane >> 4, col = lane & 15;
-        for (int k0 = 0; k0 < 2 * NTE; k0 += 4) {
-            const int kk = k0 + kq;
-            const int acol = kk < NTE ? kk : IMO + kk - NTE;
-            const float a0 = A[col * LDA + acol];
-            const float a1 = A[(16 + col) * LDA + acol];
-            const float* brow = Br + (long)kk * (2 * NTP);
-#pragma unroll
-            for (int m = 0; m < C::MAXT; ++m) {
-                const int tau = wave + 4 * m;
-                if (tau < C::TT) {
-                    const int rt = tau & 1, ct = tau >> 1;
-                    const float b = brow[ct * 16 + col];
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(rt ? a1 : a0, b, acc[m], 0, 0, 0);
-                }
-            }
-        }
-        // epilogue: output element (pixel p = rt*16 + 4*(lane/16) + i, column ct*16 + lane%16)
-#pragma unroll
-        for (int m = 0; m < C::MAXT; ++m) {
-            const int tau = wave + 4 * m;
-            if (tau < C::TT) {
-                const int rt = tau & 1;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int p = rt * 16 + 4 * kq + i;
-                    const float w = wd[p];
-                    const float v = acc[m][i];
-                    pd_acc[rt * 4 + i] += alpha * w * w * v * v;
-                    iq_acc[m][i] += w * v;
-                }
-            }
-        }
-    }
-    // PD: reduce over the 16 lanes that share pixel rows, then over waves.
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        float v = pd_acc[i];
-        for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
-        pd_acc[i] = v;
-    }
-    __syncthreads();
-    if ((lane & 15) == 0) {
-        const int kq = lane >> 4;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int p = (i >> 2) * 16 + 4 * kq + (i & 3);
-            pdsh[wave * PIX + p] = pd_acc[i];
-        }
-    }
-    __syncthreads();
-    if (tid < npx) {
-        const int p = tid, x = td.x0 + p;
-        float pdv = pdsh[p] + pdsh[PIX + p] + pdsh[2 * PIX + p] + pdsh[3 * PIX + p];
-        if (pk.pd_mode == 2) {
-            double comp = 0.0;
-            for (int ci = 0; ci < td.cov_cnt; ++ci) {
-                const int s = ws.cover[td.cov_off + ci];
-                const SubsetDesc sd = ws.sub[s];
-                if (td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1) {
-                    const double w = sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
-                    comp += ws.alpha[s] * w * w;
-                }
-            }
-            pdv = comp > 0.0 ? (float)((double)pdv / comp) : 0.f;
-        }
-        pk.pd[(long)td.y * nx + x] = pdv;
-    }
-    if (pk.iq_out) {
-        // W(x) = sum_d w_d(x) for this lane's pixels
-        __shared__ float wsum[PIX];
-        if (tid < PIX) {
-            const int x = td.x0 + tid;
-            double ws_ = 0.0;
-            for (int ci = 0; ci < td.cov_cnt; ++ci) {
-                const SubsetDesc sd = ws.sub[ws.cover[td.cov_off + ci]];
-                if (td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
-                    ws_ += sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
-            }
-            wsum[tid] = (float)ws_;
-        }
-        __syncthreads();
-        const int kq = lane >> 4, col = lane & 15;
-#pragma unroll
-        for (int m = 0; m < C::MAXT; ++m) {
-            const int tau = wave + 4 * m;
-            if (tau < C::TT) {
-                const int rt = tau & 1, ct = tau >> 1;
-                const int n = ct * 16 + col;
-                const int part = n >= NTP, t = n - part * NTP;
-                if (t < nt) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int p = rt * 16 + 4 * kq + i;
-                        if (p < npx) {
-                            const float w = wsum[p];
-                            pk.iq_out[2 * ((long)t * npix + (long)td.y * nx + td.x0 + p) + part] =
-                                w > 0.f ? iq_acc[m][i] / w : 0.f;
-                        }
-                    }
-                }
-            }
-        }
-    }
-}
-
-
-// Split-BF16 reprojection: the same gather as k_reproj with [c' | y] and [P; M]
-// split into BF16 hi + lo and three MFMA products (hi*hi + hi*lo + lo*hi) per
-// tile on v_mfma_f32_16x16x32_bf16. The operand's K axis is padded per part to
-// NTEP so that no 32-wide K block straddles the re/im boundary.
-template <int NTP>
-struct ReprojBfCfg {
-    static constexpr int NTE = NTP + REXT;
-    static constexpr int NTEP = (NTE + 31) / 32 * 32;
-    static constexpr int LDK = 2 * NTEP + 8;          // bf16 units per pixel row
-    static constexpr int CT = (2 * NTP) / 16;         // output column tiles
-    static constexpr int CTW = (CT + 3) / 4;          // per wave (both row tiles)
-};
-
-template <int NTP>
-__global__ void __launch_bounds__(256) k_reproj_bf16(Workspace ws) {
-    using C = ReprojBfCfg<NTP>;
-    constexpr int NTEP = C::NTEP, LDK = C::LDK;
-    static_assert(PIX == 32, "reprojection tile is 2 x 16 pixels");
-    __shared__ __attribute__((aligned(16))) uint16_t Ah[PIX * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Al[PIX * LDK];
-    __shared__ float2 craw[NTP * PIX];
-    __shared__ float2 vr32[NTP * RMAX];
-    __shared__ double2 vr64[NTP * RMAX];
-    __shared__ float2 yv[PIX * RMAX];
-    __shared__ float wd[PIX];
-    __shared__ float pdsh[4 * PIX];
-    __shared__ float wsum[PIX];
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "y split");
+    constexpr int TPT = NTP / G;                // frames per thread
+    static_assert(NTP % G == 0, "frames split evenly over a pixel's threads");
+    static_assert(C::ABYTES >= PIX * LDC * 8, "the operand buffer stages the packet tile");
+    __shared__ __attribute__((aligned(16))) unsigned char abuf[C::ABYTES];
+    __shared__ double2 vrs[RMAX * NTP];         // V_r, [j][t]
+    __shared__ float wd[PIX], wsum[PIX];
+    __shared__ float pdsh[C::NW * PIX];
+    float* A = reinterpret_cast<float*>(abuf);                          // FP32: [p][LDA]
+    uint16_t* Ah = reinterpret_cast<uint16_t*>(abuf);                   // BF16 hi: [p][LDK]
+    uint16_t* Al = Ah + PIX * LDK;                                      // BF16 lo
+    float2* craw = reinterpret_cast<float2*>(abuf);                     // staging only: [p][LDC]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15;
-    const TileDesc td = ws.tiles[blockIdx.x];
+    // XCD-aware order: the grid is a multiple of 8 and block b runs on XCD b % 8
+    const int per = gridDim.x >> 3;
+    const int tix = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tix >= ws.ntiles) return;
+    const TileDesc td = ws.tiles[tix];
     const PacketDesc pk = ws.pkts[td.pkt];
     const int nt = pk.nt, nx = pk.nx;
     const long npix = (long)pk.ny * pk.nx;
     const int npx = td.x1 - td.x0 + 1;
+    // pixel pp of the tile is handled by the G consecutive lanes part = 0..G-1,
+    // frames t = part + G i
+    const int pp = tid / G, part = tid % G;
 
     auto put = [&](int p, int c, float re, float im) {
-        const uint32_t rh = bf16_bits(re), ih = bf16_bits(im);
-        Ah[p * LDK + c] = (uint16_t)rh;
-        Ah[p * LDK + NTEP + c] = (uint16_t)ih;
-        Al[p * LDK + c] = (uint16_t)bf16_bits(re - __uint_as_float(rh << 16));
-        Al[p * LDK + NTEP + c] = (uint16_t)bf16_bits(im - __uint_as_float(ih << 16));
+        if (PREC) {
+            const uint32_t rh = bf16_bits(re), ih = bf16_bits(im);
+            Ah[p * LDK + c] = (uint16_t)rh;
+            Ah[p * LDK + NTEP + c] = (uint16_t)ih;
+            Al[p * LDK + c] = (uint16_t)bf16_bits(re - __uint_as_float(rh << 16));
+            Al[p * LDK + NTEP + c] = (uint16_t)bf16_bits(im - __uint_as_float(ih << 16));
+        } else {
+            A[p * LDA + c] = re;
+            A[p * LDA + IMO + c] = im;
+        }
     };
 
-    for (int e = tid; e < PIX * NTP; e += 256) {
+    // the packet tile s(pixel, t): coalesced loads staged through LDS into registers
+    for (int e = tid; e < PIX * NTP; e += NTHR) {
         const int p = e % PIX, t = e / PIX;
         float2 c = make_float2(0.f, 0.f);
         if (p < npx && t < nt) c = pk.iq[(long)t * npix + (long)td.y * nx + td.x0 + p];
-        craw[t * PIX + p] = c;
+        craw[p * LDC + t] = c;
     }
-    for (int e = tid; e < PIX * LDK; e += 256) { Ah[e] = 0; Al[e] = 0; }   // K padding stays zero
-    floatx4 iq_acc[2][C::CTW];
+    __syncthreads();
+    float2 sreg[TPT];
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) sreg[i] = craw[pp * LDC + part + G * i];
+    __syncthreads();
+    {   // operand padding (K beyond the data) stays zero for every subset
+        uint32_t* z = reinterpret_cast<uint32_t*>(abuf);
+        for (int e = tid; e < C::ABYTES / 4; e += NTHR) z[e] = 0u;
+    }
+    floatx4 iq_acc[2][CTW];
     float pd_acc[8];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int m = 0; m < C::CTW; ++m) iq_acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < CTW; ++m) iq_acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 8; ++i) pd_acc[i] = 0.f;
-    const uint16_t* planes_base = nullptr;
 
     for (int ci = 0; ci < td.cov_cnt; ++ci) {
         const int s = ws.cover[td.cov_off + ci];
@@ -497,9 +325,9 @@ __global__ void __launch_bounds__(256) k_reproj_bf16(Workspace ws) {
         const int r = ws.rank[s];
         const float alpha = (float)ws.alpha[s];
         __syncthreads();
-        for (int e = tid; e < NTP * RMAX; e += 256) {
-            vr32[e] = ws.vr32[(long)s * NTP * RMAX + e];
-            vr64[e] = ws.vr64[(long)s * NTP * RMAX + e];
+        for (int e = tid; e < NTP * RMAX; e += NTHR) {
+            const int t = e / RMAX, j = e % RMAX;
+            vrs[j * NTP + t] = ws.vr64[(long)s * NTP * RMAX + e];
         }
         if (tid < PIX) {
             const int x = td.x0 + tid;
@@ -509,86 +337,124 @@ __global__ void __launch_bounds__(256) k_reproj_bf16(Workspace ws) {
             wd[tid] = w;
         }
         __syncthreads();
-        for (int e = tid; e < PIX * REXT; e += 256) {
-            const int p = e % PIX, j = e / PIX;
-            float2 y = make_float2(0.f, 0.f);
+        // y = s V_r (FP64 partial sums over this thread's frames, then reduced over
+        // the pixel's G lanes; every lane ends with the full sum), rounded to FP32
+        float2 y[RMAX];
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+            double yr = 0.0, yi = 0.0;
             if (j < r) {
-                float ar = 0.f, ai = 0.f;
-                for (int t = 0; t < nt; ++t) {
-                    const float2 c = craw[t * PIX + p];
-                    const float2 v = vr32[t * RMAX + j];
-                    ar = fmaf(c.x, v.x, fmaf(-c.y, v.y, ar));
-                    ai = fmaf(c.x, v.y, fmaf(c.y, v.x, ai));
+#pragma unroll
+                for (int i = 0; i < TPT; ++i) {
+                    const float2 c = sreg[i];
+                    const double2 v = vrs[j * NTP + part + G * i];
+                    yr = fma((double)c.x, v.x, fma(-(double)c.y, v.y, yr));
+                    yi = fma((double)c.x, v.y, fma((double)c.y, v.x, yi));
                 }
-                y = make_float2(ar, ai);
-                yv[p * RMAX + j] = y;
+#pragma unroll
+                for (int m = G >> 1; m >= 1; m >>= 1) {
+                    yr += __shfl_xor(yr, m, 64);
+                    yi += __shfl_xor(yi, m, 64);
+                }
             }
-            put(p, NTP + j, y.x, y.y);
+            y[j] = make_float2((float)yr, (float)yi);
         }
-        __syncthreads();
-        for (int e = tid; e < PIX * NTP; e += 256) {
-            const int p = e % PIX, t = e / PIX;
+        // operand row: [c' | y] with c' = s - y V_r^H in FP64 (frames beyond nt are zero)
+#pragma unroll
+        for (int i = 0; i < TPT; ++i) {
+            const int t = part + G * i;
             double re = 0.0, im = 0.0;
             if (t < nt) {
-                const float2 c = craw[t * PIX + p];
-                re = (double)c.x;
-                im = (double)c.y;
-                for (int j = 0; j < r; ++j) {
-                    const float2 y = yv[p * RMAX + j];
-                    const double2 v = vr64[t * RMAX + j];
-                    re -= (double)y.x * v.x + (double)y.y * v.y;
-                    im -= (double)y.y * v.x - (double)y.x * v.y;
+                re = (double)sreg[i].x;
+                im = (double)sreg[i].y;
+#pragma unroll
+                for (int j = 0; j < RMAX; ++j) {
+                    if (j < r) {
+                        const double2 v = vrs[j * NTP + t];
+                        re -= (double)y[j].x * v.x + (double)y[j].y * v.y;
+                        im -= (double)y[j].y * v.x - (double)y[j].x * v.y;
+                    }
                 }
             }
-            put(p, t, (float)re, (float)im);
+            put(pp, t, (float)re, (float)im);
+        }
+        if (part < REXT) {
+            float2 yj = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j)
+                if (j == part && j < r) yj = y[j];
+            put(pp, NTP + part, yj.x, yj.y);
         }
         __syncthreads();
-        planes_base = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * (NTP + REXT)) * (2 * NTP));
-        floatx4 acc[2][C::CTW];
+        floatx4 acc[2][CTW];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int m = 0; m < C::CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
-            const int kq = k0 + 8 * g;
-            const u32x4 a0h = *reinterpret_cast<const u32x4*>(Ah + col * LDK + kq);
-            const u32x4 a0l = *reinterpret_cast<const u32x4*>(Al + col * LDK + kq);
-            const u32x4 a1h = *reinterpret_cast<const u32x4*>(Ah + (16 + col) * LDK + kq);
-            const u32x4 a1l = *reinterpret_cast<const u32x4*>(Al + (16 + col) * LDK + kq);
-            const bool impart = k0 >= NTEP;
-            const int kk = impart ? kq - NTEP : kq;
+            for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (PREC) {
+            const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
+#pragma unroll 2
+            for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
+                const int kq = k0 + 8 * g;
+                const u32x4 a0h = *reinterpret_cast<const u32x4*>(Ah + col * LDK + kq);
+                const u32x4 a0l = *reinterpret_cast<const u32x4*>(Al + col * LDK + kq);
+                const u32x4 a1h = *reinterpret_cast<const u32x4*>(Ah + (16 + col) * LDK + kq);
+                const u32x4 a1l = *reinterpret_cast<const u32x4*>(Al + (16 + col) * LDK + kq);
+                const bool impart = k0 >= NTEP;
+                const int kk = impart ? kq - NTEP : kq;
 #pragma unroll
-            for (int m = 0; m < C::CTW; ++m) {
-                const int ct = wave * C::CTW + m;
-                if (ct < C::CT) {
-                    const int n = ct * 16 + col;
-                    const bool outim = n >= NTP;
-                    const int nn = outim ? n - NTP : n;
-                    // B^T row n: re output [P_re | -P_im], im output [P_im | P_re]
-                    const int plane = (outim != impart) ? 2 : 0;
-                    const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
-                    const uint16_t* src = planes_base + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
-                    u32x4 bh = *reinterpret_cast<const u32x4*>(src);
-                    u32x4 bl = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
+                for (int m = 0; m < CTW; ++m) {
+                    const int ct = wave * CTW + m;
+                    if (ct < C::CT) {
+                        const int n = ct * 16 + col;
+                        const bool outim = n >= NTP;
+                        const int nn = outim ? n - NTP : n;
+                        // B^T row n: re output [P_re | -P_im], im output [P_im | P_re]
+                        const int plane = (outim != impart) ? 2 : 0;
+                        const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
+                        const uint16_t* src = planes + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
+                        u32x4 bh = *reinterpret_cast<const u32x4*>(src);
+                        u32x4 bl = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) { bh[q] ^= sgn; bl[q] ^= sgn; }
-                    const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh), xbl = __builtin_bit_cast(bf16x8, bl);
-                    const bf16x8 x0h = __builtin_bit_cast(bf16x8, a0h), x0l = __builtin_bit_cast(bf16x8, a0l);
-                    const bf16x8 x1h = __builtin_bit_cast(bf16x8, a1h), x1l = __builtin_bit_cast(bf16x8, a1l);
-                    acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbh, acc[0][m], 0, 0, 0);
-                    acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbl, acc[0][m], 0, 0, 0);
-                    acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0l, xbh, acc[0][m], 0, 0, 0);
-                    acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbh, acc[1][m], 0, 0, 0);
-                    acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbl, acc[1][m], 0, 0, 0);
-                    acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1l, xbh, acc[1][m], 0, 0, 0);
+                        for (int q = 0; q < 4; ++q) { bh[q] ^= sgn; bl[q] ^= sgn; }
+                        const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh), xbl = __builtin_bit_cast(bf16x8, bl);
+                        const bf16x8 x0h = __builtin_bit_cast(bf16x8, a0h), x0l = __builtin_bit_cast(bf16x8, a0l);
+                        const bf16x8 x1h = __builtin_bit_cast(bf16x8, a1h), x1l = __builtin_bit_cast(bf16x8, a1l);
+                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbh, acc[0][m], 0, 0, 0);
+                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbl, acc[0][m], 0, 0, 0);
+                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0l, xbh, acc[0][m], 0, 0, 0);
+                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbh, acc[1][m], 0, 0, 0);
+                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbl, acc[1][m], 0, 0, 0);
+                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1l, xbh, acc[1][m], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            const float* Br = ws.breal + (long)s * (2 * C::NTE) * (2 * NTP);
+#pragma unroll 4
+            for (int k0 = 0; k0 < 2 * C::NTE; k0 += 4) {
+                const int kk = k0 + g;
+                const int acol = kk < C::NTE ? kk : IMO + kk - C::NTE;
+                const float a0 = A[col * LDA + acol];
+                const float a1 = A[(16 + col) * LDA + acol];
+                const float* brow = Br + (long)kk * (2 * NTP);
+#pragma unroll
+                for (int m = 0; m < CTW; ++m) {
+                    const int ct = wave * CTW + m;
+                    if (ct < C::CT) {
+                        const float b = brow[ct * 16 + col];
+                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][m], 0, 0, 0);
+                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][m], 0, 0, 0);
+                    }
                 }
             }
         }
+        // epilogue: output element (pixel rt*16 + 4g + i, column ct*16 + col)
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int m = 0; m < C::CTW; ++m) {
-                if (wave * C::CTW + m < C::CT) {
+            for (int m = 0; m < CTW; ++m) {
+                if (wave * CTW + m < C::CT) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int p = rt * 16 + 4 * g + i;
@@ -600,6 +466,7 @@ __global__ void __launch_bounds__(256) k_reproj_bf16(Workspace ws) {
                 }
             }
     }
+    // PD: reduce over the 16 lanes that share pixel rows, then over waves
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         float v = pd_acc[i];
@@ -625,7 +492,7 @@ __global__ void __launch_bounds__(256) k_reproj_bf16(Workspace ws) {
     if (tid < npx) {
         const int p = tid, x = td.x0 + p;
         float pdv = 0.f;
-        for (int w = 0; w < 4; ++w) pdv += pdsh[w * PIX + p];
+        for (int w = 0; w < C::NW; ++w) pdv += pdsh[w * PIX + p];
         if (pk.pd_mode == 2) {
             double comp = 0.0;
             for (int ci = 0; ci < td.cov_cnt; ++ci) {
@@ -644,8 +511,8 @@ __global__ void __launch_bounds__(256) k_reproj_bf16(Workspace ws) {
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int m = 0; m < C::CTW; ++m) {
-                const int ct = wave * C::CTW + m;
+            for (int m = 0; m < CTW; ++m) {
+                const int ct = wave * CTW + m;
                 if (ct < C::CT) {
                     const int n = ct * 16 + col;
                     const int part = n >= NTP, t = n - part * NTP;
@@ -673,8 +540,11 @@ static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t 
         if (prec == 0) hipLaunchKernelGGL((k_projector<NTP, 0>), dim3(ws.S), dim3(256), 0, st, ws);
         else hipLaunchKernelGGL((k_projector<NTP, 1>), dim3(ws.S), dim3(256), 0, st, ws);
     } else if (ws.ntiles > 0) {
-        if (prec == 0) hipLaunchKernelGGL((k_reproj<NTP>), dim3(ws.ntiles), dim3(256), 0, st, ws);
-        else hipLaunchKernelGGL((k_reproj_bf16<NTP>), dim3(ws.ntiles), dim3(256), 0, st, ws);
+        const int grid = (ws.ntiles + 7) / 8 * 8;      // multiple of 8 for the XCD mapping
+        if (prec == 0)
+            hipLaunchKernelGGL((k_reproj<NTP, 0>), dim3(grid), dim3(RpCfg<NTP, 0>::NTHR), 0, st, ws);
+        else
+            hipLaunchKernelGGL((k_reproj<NTP, 1>), dim3(grid), dim3(RpCfg<NTP, 1>::NTHR), 0, st, ws);
     }
 }
 

@@ -64,13 +64,17 @@ def packet_runs(ctx, lcf, iq, mask_t, grid, prec, betas=BETAS):
     return lam, out_w, cnrs
 
 
-def generate(ctx, lcf, kind, seeds, grid, prec, workers):
+def generate(ctx, lcf, kind, seeds, grid, prec, workers, log=None):
     """Teacher data: eigvals [N][128] (float64, GPU), targets [N][128] (float32, GPU), info."""
     import torch
     lams, tgts, info = [], [], []
+    seeds = list(seeds)
+    t0 = time.time()
     ctxmp = mp.get_context("spawn")   # workers run numpy only and never touch the GPU
     with ctxmp.Pool(workers) as pool:
-        for seed, iq_np, mask_np in pool.imap(_make, [(kind, s) for s in seeds], chunksize=1):
+        for n, (seed, iq_np, mask_np) in enumerate(pool.imap(_make, [(kind, s) for s in seeds], chunksize=1)):
+            if log and n % 50 == 0:
+                log(f"teacher packet {n}/{len(seeds)} ({time.time() - t0:.0f} s)")
             iq = torch.from_numpy(iq_np).cuda()
             mask_t = torch.from_numpy(mask_np).cuda()
             lam, ws, cnrs = packet_runs(ctx, lcf, iq, mask_t, grid, prec)
@@ -102,13 +106,15 @@ def train(ctx, lam, tgt, epochs, batch, lr, seed=0, log=None):
     return hist
 
 
-def evaluate(ctx, lcf, kind, seeds, grid, prec, workers):
+def evaluate(ctx, lcf, kind, seeds, grid, prec, workers, log=None):
     """Held-out comparison of rule (beta = 1), searched-beta teacher and MLP."""
     import torch
     rows = []
     ctxmp = mp.get_context("spawn")   # workers run numpy only and never touch the GPU
     with ctxmp.Pool(workers) as pool:
-        for seed, iq_np, mask_np in pool.imap(_make, [(kind, s) for s in seeds], chunksize=1):
+        for n, (seed, iq_np, mask_np) in enumerate(pool.imap(_make, [(kind, s) for s in seeds], chunksize=1)):
+            if log and n % 8 == 0:
+                log(f"held-out packet {n}")
             iq = torch.from_numpy(iq_np).cuda()
             mask_t = torch.from_numpy(mask_np).cuda()
             _, ws, cnrs = packet_runs(ctx, lcf, iq, mask_t, grid, prec)
@@ -150,7 +156,7 @@ def main(argv=None):
     ctx = lcf.Context(0)
     t0 = time.time()
     lam, tgt, info = generate(ctx, lcf, args.kind, range(base_train, base_train + args.train), grid, prec,
-                              args.workers)
+                              args.workers, log=log)
     log(f"teacher data: {lam.shape[0]} spectra from {args.train} packets in {time.time() - t0:.1f} s; "
         f"best beta histogram {np.unique([i['best_beta'] for i in info], return_counts=True)}")
     ctx.mlp_init(1)
@@ -158,7 +164,8 @@ def main(argv=None):
     hist = train(ctx, lam, tgt, args.epochs, args.batch, args.lr, log=log)
     log(f"training: {time.time() - t1:.1f} s")
     ctx.mlp_save(args.out)
-    rows = evaluate(ctx, lcf, args.kind, range(base_hold, base_hold + args.holdout), grid, prec, args.workers)
+    rows = evaluate(ctx, lcf, args.kind, range(base_hold, base_hold + args.holdout), grid, prec, args.workers,
+                    log=log)
     summ = {k: float(np.mean([r[k] for r in rows])) for k in
             ("cnr_rule", "cnr_teacher", "cnr_mlp", "pd_db_vs_teacher_p99", "pd_db_vs_teacher_max", "fallback_rate")}
     log("held-out mean: " + json.dumps(summ))

@@ -1,5 +1,9 @@
 """Comparison helpers for GPU-vs-oracle parity (test infrastructure)."""
+import sys
+
 import numpy as np
+
+import oracle as O
 
 
 def rel_fro(a, b) -> float:
@@ -36,3 +40,57 @@ def knee_tie(curv: np.ndarray, k_a: int, k_b: int, rtol: float = 1e-9) -> bool:
     """Two cut indices are a tie when the curvature at both agrees within rtol."""
     a, b = curv[k_a - 1], curv[k_b - 1]
     return abs(a - b) <= rtol * max(abs(a), abs(b))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(lcf, ctx, iq_np, gy, gx, thr, **kw):
+    import torch
+    iq = torch.from_numpy(iq_np).cuda()
+    io, pd, dg = ctx.filter(iq, gy, gx, thr, diag=True, **kw)
+    torch.cuda.synchronize()
+    st = ctx.sync()
+    assert st == 0, f"lcf_sync status {st}"
+    d = {k: v.cpu().numpy() for k, v in dg.items()}
+    return (io.cpu().numpy() if io is not None else None), pd.cpu().numpy(), d
+
+
+def oracle_thr(lcf_thr, nd=None, explicit=None):
+    return O.Threshold(cut=lcf_thr.cut, shape=lcf_thr.shape, pd_mode=lcf_thr.pd_mode, k_fixed=lcf_thr.k_fixed,
+                       beta_knee=lcf_thr.beta_knee, knee_max_frac=lcf_thr.knee_max_frac,
+                       beta_sigmoid=lcf_thr.beta_sigmoid, explicit_w=explicit)
+
+
+def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, precision=0):
+    say(f"[{name}] shape={iq.shape} grid={gy}x{gx} cut={thr.cut} shape={thr.shape}")
+    io, pd, d = run_gpu(lcf, ctx, iq, gy, gx, thr, precision=precision)
+    res = O.filter_packet(iq, gy, gx, oracle_thr(thr))
+    nd = gy * gx
+    # decision parity: the oracle's FP64 rule on the GPU's eigenvalues
+    forced = False
+    for s in range(nd):
+        lam_g = d["eigvals"][s]
+        lam_o = res["lam"][s]
+        assert np.allclose(lam_g, lam_o, rtol=1e-5, atol=1e-7 * lam_o[0]), (s, np.max(np.abs(lam_g - lam_o) / lam_o[0]))
+        if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE):
+            w_rule, k_rule, curv, _ = O.rule_weights(lam_g, oracle_thr(thr))
+            assert d["k"][s] == k_rule, (s, d["k"][s], k_rule)
+            assert np.allclose(d["weights"][s], w_rule, atol=1e-6)
+            if k_rule != res["k"][s]:
+                assert knee_tie(res["curv"][s], k_rule, res["k"][s]), ("non-tie k flip", s, k_rule, res["k"][s])
+                forced = True
+    if forced:
+        ew = d["weights"].astype(np.float64)
+        res = O.filter_packet(iq, gy, gx, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=ew, pd_mode=thr.pd_mode))
+    e_fro = rel_fro(io, res["iq_out"])
+    emax, e99, e999, npx = pd_db_error(pd, res["pd"], mask)
+    say(f"   rel_fro={e_fro:.3e} pd_db max={emax:.2e} p99={e99:.2e} p99.9={e999:.2e} n={npx} forced={forced} "
+         f"sweeps={d['sweeps'].min()}..{d['sweeps'].max()} rank={d['rank'].min()}..{d['rank'].max()}")
+    assert e_fro <= tol_fro
+    assert emax <= tol_db
+    return e_fro, emax
+
+

@@ -7,7 +7,8 @@ import pytest
 
 import oracle as O
 import synth
-from parity import rel_fro, pd_db_error, knee_tie
+from parity import rel_fro, pd_db_error, knee_tie, run_gpu as _run, oracle_thr as _oracle_thr, \
+    check_end_to_end as _check_end_to_end
 
 pytestmark = pytest.mark.gpu
 
@@ -26,22 +27,6 @@ def ctx(lcf):
     c = lcf.Context(0)
     yield c
     c.close()
-
-
-def _run(lcf, ctx, iq_np, gy, gx, thr, **kw):
-    iq = torch.from_numpy(iq_np).cuda()
-    io, pd, dg = ctx.filter(iq, gy, gx, thr, diag=True, **kw)
-    torch.cuda.synchronize()
-    st = ctx.sync()
-    assert st == 0, f"lcf_sync status {st}"
-    d = {k: v.cpu().numpy() for k, v in dg.items()}
-    return (io.cpu().numpy() if io is not None else None), pd.cpu().numpy(), d
-
-
-def _oracle_thr(lcf_thr, nd=None, explicit=None):
-    return O.Threshold(cut=lcf_thr.cut, shape=lcf_thr.shape, pd_mode=lcf_thr.pd_mode, k_fixed=lcf_thr.k_fixed,
-                       beta_knee=lcf_thr.beta_knee, knee_max_frac=lcf_thr.knee_max_frac,
-                       beta_sigmoid=lcf_thr.beta_sigmoid, explicit_w=explicit)
 
 
 # ------------------------------------------------------------------ EVD
@@ -120,36 +105,6 @@ def test_covariance_windowed_matches_oracle(lcf, ctx):
 
 
 # ------------------------------------------------------------------ end to end
-
-def _check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, precision=0):
-    _say(f"[{name}] shape={iq.shape} grid={gy}x{gx} cut={thr.cut} shape={thr.shape}")
-    io, pd, d = _run(lcf, ctx, iq, gy, gx, thr, precision=precision)
-    res = O.filter_packet(iq, gy, gx, _oracle_thr(thr))
-    nd = gy * gx
-    # decision parity: the oracle's FP64 rule on the GPU's eigenvalues
-    forced = False
-    for s in range(nd):
-        lam_g = d["eigvals"][s]
-        lam_o = res["lam"][s]
-        assert np.allclose(lam_g, lam_o, rtol=1e-5, atol=1e-7 * lam_o[0]), (s, np.max(np.abs(lam_g - lam_o) / lam_o[0]))
-        if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE):
-            w_rule, k_rule, curv, _ = O.rule_weights(lam_g, _oracle_thr(thr))
-            assert d["k"][s] == k_rule, (s, d["k"][s], k_rule)
-            assert np.allclose(d["weights"][s], w_rule, atol=1e-6)
-            if k_rule != res["k"][s]:
-                assert knee_tie(res["curv"][s], k_rule, res["k"][s]), ("non-tie k flip", s, k_rule, res["k"][s])
-                forced = True
-    if forced:
-        ew = d["weights"].astype(np.float64)
-        res = O.filter_packet(iq, gy, gx, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=ew, pd_mode=thr.pd_mode))
-    e_fro = rel_fro(io, res["iq_out"])
-    emax, e99, e999, npx = pd_db_error(pd, res["pd"], mask)
-    _say(f"   rel_fro={e_fro:.3e} pd_db max={emax:.2e} p99={e99:.2e} p99.9={e999:.2e} n={npx} forced={forced} "
-         f"sweeps={d['sweeps'].min()}..{d['sweeps'].max()} rank={d['rank'].min()}..{d['rank'].max()}")
-    assert e_fro <= tol_fro
-    assert emax <= tol_db
-    return e_fro, emax
-
 
 def test_small_fixed_k(lcf, ctx):
     iq, mask = synth.make_packet(synth.spec_small(0))

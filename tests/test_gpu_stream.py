@@ -1,0 +1,84 @@
+"""The uneven packet stream (Nt in {32, 64, 100, 200}, images 128..400 x
+128..256, square window grids 2..10) filtered in one batched call: parity of
+cropped packets against the FP64 oracle, and the full-size stream against
+per-packet calls."""
+import multiprocessing as mp
+
+import numpy as np
+import pytest
+
+import synth
+from parity import say, check_end_to_end
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx(lcf):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = lcf.Context(0)
+    yield c
+    c.close()
+
+
+def _gen(spec):
+    return synth.make_packet(spec)
+
+
+def _packets(n):
+    lst = synth.batch_specs(3000, n)
+    with mp.get_context("spawn").Pool(8) as pool:      # workers run numpy only
+        data = pool.map(_gen, [s for s, _ in lst])
+    return lst, data
+
+
+def test_stream_cropped_batched_vs_oracle(lcf, ctx):
+    """One packet of each Nt class, cropped to at most 112 x 96 pixels, filtered
+    together in one call; each must equal its single call bitwise and match the
+    oracle (knee + sigmoid rule, FP32 path)."""
+    lst, data = _packets(8)
+    picks, seen = [], set()
+    for i, (spec, g) in enumerate(lst):
+        if spec.nt not in seen:
+            seen.add(spec.nt)
+            picks.append(i)
+    assert sorted(seen) == [32, 64, 100, 200]
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    iqs, masks, grids = [], [], []
+    for i in picks:
+        iq, mask = data[i]
+        iqs.append(np.ascontiguousarray(iq[:, :112, :96]))
+        masks.append(mask[:112, :96])
+        g = lst[i][1]
+        grids.append((g, g))
+    dev = [torch.from_numpy(x).cuda() for x in iqs]
+    ios, pds = ctx.filter_batch(dev, grids, thr, iq_out=True)
+    torch.cuda.synchronize()
+    assert ctx.sync() == 0
+    for k, i in enumerate(picks):
+        io1, pd1, _ = ctx.filter(dev[k], grids[k][0], grids[k][1], thr)
+        torch.cuda.synchronize()
+        assert torch.equal(ios[k], io1) and torch.equal(pds[k], pd1), k
+        check_end_to_end(lcf, ctx, iqs[k], masks[k], grids[k][0], grids[k][1], thr, 1e-5, 0.1,
+                         f"stream packet {i} nt={iqs[k].shape[0]} g={grids[k][0]}")
+
+
+def test_stream_full_size_one_call(lcf, ctx):
+    """Sixteen full-size packets of the stream in one batched call (split-BF16):
+    no device-side flags, and sampled packets equal their single calls."""
+    lst, data = _packets(16)
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    dev = [torch.from_numpy(iq).cuda() for iq, _ in data]
+    grids = [(g, g) for _, g in lst]
+    say(f"[full stream] {len(dev)} packets, nt {sorted(set(s.nt for s, _ in lst))}, "
+        f"subsets {sum(g * g for _, g in lst)}")
+    ios, pds = ctx.filter_batch(dev, grids, thr, precision=lcf.PREC_BF16X3, iq_out=True)
+    torch.cuda.synchronize()
+    assert ctx.sync() == 0
+    for k in (0, 5, 11):
+        io1, pd1, _ = ctx.filter(dev[k], grids[k][0], grids[k][1], thr, precision=lcf.PREC_BF16X3)
+        torch.cuda.synchronize()
+        assert torch.equal(ios[k], io1) and torch.equal(pds[k], pd1), k
+        assert torch.isfinite(pds[k]).all()
