@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="oracle time budget for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--ablation-steps", type=int, default=3, help="0 skips the ablation legs")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; sharding across GPUs is designed but not built "
@@ -114,6 +117,12 @@ def main():
         if use_mlp:
             fast.mlp_load(args.mlp)
         grids = [(gy, gx)] * len(iqs)
+        if args.copy_probe_mib > 0:
+            src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
 
         def step_fast():
             fast.filter_batch(iqs, grids, thr_fast, precision=lcf.PREC_BF16X3, outs=outs_f)
@@ -151,6 +160,31 @@ def main():
         torch.cuda.synchronize()
         stages = fast.stage_times(reset=True)
         fast.set_option(lcf.OPT_STAGE_TIMING, 0)
+
+        # ablation: one change at a time back toward the plain configuration
+        ablation = {}
+        if args.ablation_steps > 0:
+            legs = [("fast without hipGraph", thr_fast, lcf.PREC_BF16X3, 0),
+                    ("rule instead of network, split-BF16, graph", thr_plain, lcf.PREC_BF16X3, 1),
+                    ("rule, FP32, graph", thr_plain, lcf.PREC_FP32, 1),
+                    ("rule, FP32, batched, no graph", thr_plain, lcf.PREC_FP32, 0)]
+            for name, thr_l, prec_l, graph_l in legs:
+                actx = lcf.Context(0, schedule=0, use_graph=graph_l)
+                if use_mlp and thr_l.cut == lcf.CUT_MLP:
+                    actx.mlp_load(args.mlp)
+                run = lambda: actx.filter_batch(iqs, grids, thr_l, precision=prec_l, outs=outs_p)
+                run()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.ablation_steps):
+                    run()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ams = e0.elapsed_time(e1) / args.ablation_steps
+                ablation[name] = {"frames_per_s": len(iqs) * nt / (ams / 1e3), "ms_per_step": ams,
+                                  "device_status": actx.sync()}
+                actx.close()
 
         plain = None
         if not args.no_plain:
@@ -240,6 +274,7 @@ def main():
         "cpu_baseline": cpu,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "ablation": ablation,
         "parity": parity,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in timed.items()},
         "jacobi_sweeps_mean": float(np.mean(sweeps)),

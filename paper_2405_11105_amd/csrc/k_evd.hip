@@ -460,6 +460,37 @@ __device__ __forceinline__ double swap_sum(double a, double b) {
     return p + q;
 }
 
+// Data-parallel lane moves of a double within a row of 16 lanes (DPP):
+// 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = quad_perm [2,3,0,1] (lane ^ 2),
+// 0x141 = row_half_mirror (lane ^ 7), 0x140 = row_mirror (lane ^ 15).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// The lane-swap instructions on a double: returns the two swapped operands.
+template <int M>
+__device__ __forceinline__ void swap_d(double a, double b, double& x, double& y) {
+    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+    const unsigned alo = (unsigned)(ab & 0xffffffff), ahi = (unsigned)(ab >> 32);
+    const unsigned blo = (unsigned)(bb & 0xffffffff), bhi = (unsigned)(bb >> 32);
+    unsigned x0, x1, y0, y1;
+    if constexpr (M == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    }
+    x = __longlong_as_double((long long)(((unsigned long long)x1 << 32) | x0));
+    y = __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0));
+}
+
 template <int RPL>
 struct JCols {
     double2 x[16][RPL];
@@ -470,7 +501,11 @@ struct JCols {
 __host__ __device__ constexpr int pslot_a(int mode, int k) { return mode == 0 ? (k < 4 ? k : 4 + k) : k; }
 __host__ __device__ constexpr int pslot_b(int mode, int k) { return mode == 0 ? (k < 4 ? 7 - k : 19 - k) : 8 + k; }
 
-// Rotate 4 disjoint pairs (k = G..G+3) of the wave's registers.
+// Rotate 4 disjoint pairs (k = G..G+3) of the wave's registers. The 16 lane
+// partial sums are ordered quantity-major (4 q + k: q = |a|^2, |b|^2, Re a^H b,
+// Im a^H b) so that after the transposed reduction lane l holds quantity l >> 4
+// of pair (l >> 2) & 3, and two lane swaps bring all four quantities of pair k
+// to lanes 4k..4k+3 of the first row.
 template <int RPL, int MODE, int G>
 __device__ __forceinline__ void jac_step4(JCols<RPL>& c, int lane, double tol, int& nrot, double& offmax) {
     double v[16];
@@ -485,14 +520,15 @@ __device__ __forceinline__ void jac_step4(JCols<RPL>& c, int lane, double tol, i
             gr = fma(a.x, b.x, fma(a.y, b.y, gr));
             gi = fma(a.x, b.y, fma(-a.y, b.x, gi));
         }
-        v[4 * k + 0] = al;
-        v[4 * k + 1] = be;
-        v[4 * k + 2] = gr;
-        v[4 * k + 3] = gi;
+        v[0 + k] = al;
+        v[4 + k] = be;
+        v[8 + k] = gr;
+        v[12 + k] = gi;
     }
-    // transposed butterfly: after masks 32,16,8,4 lane l holds value (l >> 2).
-    // Masks 32 and 16 use the lane-swap instructions (no selects); 8 and 4 work
-    // on named scalars so that no select turns into an indexed register access.
+    // transposed reduction: lane bit 5 <- index bit 3 (lane swap 32), bit 4 <- bit 2
+    // (lane swap 16), bit 3 <- bit 1 (row mirror), bit 2 <- bit 0 (half-row
+    // mirror), then a plain sum over the quad. Selects work on named scalars so
+    // that none turns into an indexed register access.
     double w8[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) w8[j] = swap_sum<32>(v[j], v[j + 8]);
@@ -501,17 +537,17 @@ __device__ __forceinline__ void jac_step4(JCols<RPL>& c, int lane, double tol, i
     for (int j = 0; j < 4; ++j) u[j] = swap_sum<16>(w8[j], w8[j + 4]);
     const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
     const double u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3];
-    const double z0 = (h8 ? u2 : u0) + __shfl_xor(h8 ? u0 : u2, 8, 64);
-    const double z1 = (h8 ? u3 : u1) + __shfl_xor(h8 ? u1 : u3, 8, 64);
-    double tot = (h4 ? z1 : z0) + __shfl_xor(h4 ? z0 : z1, 4, 64);
-    tot += __shfl_xor(tot, 2, 64);
-    tot += __shfl_xor(tot, 1, 64);
-    // gather pair k's four sums into lane k
-    const int k = lane & 3;
-    const double al = __shfl(tot, 4 * (4 * k + 0), 64);
-    const double be = __shfl(tot, 4 * (4 * k + 1), 64);
-    const double gr = __shfl(tot, 4 * (4 * k + 2), 64);
-    const double gi = __shfl(tot, 4 * (4 * k + 3), 64);
+    const double z0 = (h8 ? u2 : u0) + dpp_d<0x140>(h8 ? u0 : u2);
+    const double z1 = (h8 ? u3 : u1) + dpp_d<0x140>(h8 ? u1 : u3);
+    double tot = (h4 ? z1 : z0) + dpp_d<0x141>(h4 ? z0 : z1);
+    tot += dpp_d<0x4E>(tot);
+    tot += dpp_d<0xB1>(tot);
+    // rows of tot: |a|^2, |b|^2, Re, Im; bring rows 1-3 to row 0
+    double r0, r1, s0, s1, t0, t1;
+    swap_d<32>(tot, tot, r0, r1);      // r0 rows: al be al be; r1: gr gi gr gi
+    swap_d<16>(r0, r1, s0, s1);        // s1 rows: be gi be gi
+    swap_d<16>(r1, r1, t0, t1);        // t1 rows: gi gi gi gi (row 0 = gi)
+    const double al = tot, be = s1, gr = r1, gi = t1;
     const double mag = sqrt(gr * gr + gi * gi);
     const double scale = sqrt(al * be);
     double cc = 1.0, ss = 0.0, er = 1.0, ei = 0.0;
@@ -525,17 +561,14 @@ __device__ __forceinline__ void jac_step4(JCols<RPL>& c, int lane, double tol, i
         ei = -gi / mag;
     }
     const double off = scale > 0.0 ? mag / scale : 0.0;
-    const unsigned long long rb = __ballot(rot && lane < 4);
+    const unsigned long long rb = __ballot(rot && lane < 16 && (lane & 3) == 0);
     nrot += __popcll(rb);
-    double om = lane < 4 ? off : 0.0;
-    om = fmax(om, __shfl_xor(om, 2, 64));
-    om = fmax(om, __shfl_xor(om, 1, 64));
-    offmax = fmax(offmax, rdl(om, 0));
+    offmax = fmax(offmax, fmax(fmax(rdl(off, 0), rdl(off, 4)), fmax(rdl(off, 8), rdl(off, 12))));
     const double ser = ss * er, sei = ss * ei, cer = cc * er, cei = cc * ei;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const double C = rdl(cc, q), S = rdl(ss, q);
-        const double SR = rdl(ser, q), SI = rdl(sei, q), CR = rdl(cer, q), CI = rdl(cei, q);
+        const double C = rdl(cc, 4 * q), S = rdl(ss, 4 * q);
+        const double SR = rdl(ser, 4 * q), SI = rdl(sei, 4 * q), CR = rdl(cer, 4 * q), CI = rdl(cei, 4 * q);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const double2 a = c.x[pslot_a(MODE, G + q)][i], b = c.x[pslot_b(MODE, G + q)][i];
