@@ -491,6 +491,24 @@ __device__ __forceinline__ void swap_d(double a, double b, double& x, double& y)
     y = __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0));
 }
 
+// 1/sqrt(x) and 1/x to double precision: the hardware estimates refined by two
+// Newton steps each (y <- y + y (1 - x y^2) / 2 and y <- y + y (1 - x y)).
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double r = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, r, y);
+    }
+    return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
 template <int RPL>
 struct JCols {
     double2 x[16][RPL];
@@ -548,27 +566,25 @@ __device__ __forceinline__ void jac_step4(JCols<RPL>& c, int lane, double tol, i
     swap_d<16>(r0, r1, s0, s1);        // s1 rows: be gi be gi
     swap_d<16>(r1, r1, t0, t1);        // t1 rows: gi gi gi gi (row 0 = gi)
     const double al = tot, be = s1, gr = r1, gi = t1;
-    const double mag = sqrt(gr * gr + gi * gi);
-    const double scale = sqrt(al * be);
-    double cc = 1.0, ss = 0.0, er = 1.0, ei = 0.0;
-    const bool rot = mag > tol * scale;
-    if (rot) {
-        const double zeta = (be - al) / (2.0 * mag);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        cc = 1.0 / sqrt(1.0 + t * t);
-        ss = cc * t;
-        er = gr / mag;
-        ei = -gi / mag;
-    }
-    const double off = scale > 0.0 ? mag / scale : 0.0;
+    // rotation of pair (lane >> 2) & 3 from squared quantities (no square roots or
+    // divisions beyond three reciprocal square roots and one reciprocal)
+    const double m2 = fma(gr, gr, gi * gi), ab = al * be;
+    const bool rot = m2 > tol * tol * ab;
+    const double im = rsq_nr(m2);
+    const double zeta = 0.5 * (be - al) * im;
+    const double z2 = fma(zeta, zeta, 1.0);
+    const double t = (zeta >= 0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + z2 * rsq_nr(z2));
+    const double cr = rsq_nr(fma(t, t, 1.0));
+    const double cc = rot ? cr : 1.0, ss = rot ? cr * t : 0.0;
+    const double er = rot ? gr * im : 1.0, ei = rot ? -gi * im : 0.0;
+    const double off2 = ab > 0.0 ? m2 / ab : 0.0;
     const unsigned long long rb = __ballot(rot && lane < 16 && (lane & 3) == 0);
     nrot += __popcll(rb);
-    offmax = fmax(offmax, fmax(fmax(rdl(off, 0), rdl(off, 4)), fmax(rdl(off, 8), rdl(off, 12))));
-    const double ser = ss * er, sei = ss * ei, cer = cc * er, cei = cc * ei;
+    if (lane < 16) offmax = fmax(offmax, off2);      // lane-local; reduced once per sweep
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const double C = rdl(cc, 4 * q), S = rdl(ss, 4 * q);
-        const double SR = rdl(ser, 4 * q), SI = rdl(sei, 4 * q), CR = rdl(cer, 4 * q), CI = rdl(cei, 4 * q);
+        const double C = rdl(cc, 4 * q), S = rdl(ss, 4 * q), ER = rdl(er, 4 * q), EI = rdl(ei, 4 * q);
+        const double SR = S * ER, SI = S * EI, CR = C * ER, CI = C * EI;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const double2 a = c.x[pslot_a(MODE, G + q)][i], b = c.x[pslot_b(MODE, G + q)][i];
@@ -686,7 +702,9 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
                 my_bot = idx[src];
             }
         }
-        if (lane == 0) { s_rot[wave] = nrot; s_off[wave] = offmax; }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) offmax = fmax(offmax, __shfl_xor(offmax, m, 64));
+        if (lane == 0) { s_rot[wave] = nrot; s_off[wave] = sqrt(offmax); }
         __syncthreads();
         int tr = 0;
         double off = 0.0;

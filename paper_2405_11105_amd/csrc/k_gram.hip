@@ -83,7 +83,6 @@ k_gram(Workspace ws) {
     using C = GramCfg<NTP, DEFL, PREC>;
     constexpr int NTE = C::NTE, IMO = C::IMO, LDA = C::LDA, LDB = C::LDB, PIX = C::PX;
     __shared__ __attribute__((aligned(16))) uint32_t Aw[C::A_WORDS];
-    __shared__ double wpix[PIX];
     __shared__ double2 vrs[DEFL ? RMAX * NTP : 1];     // V_r, [j][t]
     float* A = reinterpret_cast<float*>(Aw);
     uint32_t* Ah = Aw;                   // BF16 hi words [NTE][LDB]
@@ -135,53 +134,52 @@ k_gram(Workspace ws) {
 #pragma unroll
     for (int m = 0; m < C::MAXT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int qb = ch.q0; qb < ch.q1; qb += PIX) {
-        __syncthreads();
-        if (tid < PIX) {
-            const int q = qb + tid;
-            double w = 0.0;
-            if (q < ch.q1) {
-                const int yy = q / sd.bw, xx = q - yy * sd.bw;
-                w = sd.flat ? 1.0 : wy[yy] * wx[xx];
-            }
-            wpix[tid] = w;
+    // Operand staging is software-pipelined: the global loads of the next batch of
+    // box pixels are issued before the MFMAs of the current batch. Each thread
+    // owns one pixel of a batch and frames t = t0 + TSTEP i.
+    //   pass 1: pixel tid % PIX, t0 = tid / PIX, TSTEP = THREADS / PIX
+    //   pass 2: pixel tid / G,   t0 = tid % G,   TSTEP = G (lanes of a pixel are
+    //           consecutive, so the tissue scores reduce with shuffles)
+    constexpr int G = DEFL ? (C::THREADS / PIX > 16 ? 16 : C::THREADS / PIX) : 1;
+    constexpr int TSTEP = DEFL ? G : C::THREADS / PIX;
+    constexpr int NPT = (NTP + TSTEP - 1) / TSTEP;
+    static_assert(C::THREADS % PIX == 0, "whole pixels per thread group");
+    static_assert(!DEFL || NTP % G == 0, "frames split evenly over a pixel's lanes");
+    const int my_p = DEFL ? tid / G : tid % PIX;
+    const int my_t0 = DEFL ? tid % G : tid / PIX;
+    const bool active = my_p < PIX;       // pass 2 with 16-pixel batches leaves whole waves idle
+    float2 nxt[NPT];
+    double nw = 0.0;
+    auto fetch = [&](int qb) {
+        const int q = qb + my_p;
+        long poff = -1;
+        nw = 0.0;
+        if (active && q < ch.q1) {
+            const int yy = q / sd.bw, xx = q - yy * sd.bw;
+            poff = (long)(sd.y0 + yy) * nx + sd.x0 + xx;
+            nw = sd.flat ? 1.0 : wy[yy] * wx[xx];
         }
-        __syncthreads();
-        if (!DEFL) {
-            for (int e = tid; e < PIX * NTP; e += C::THREADS) {
-                const int p = e % PIX, t = e / PIX;
-                const int q = qb + p;
-                float re = 0.f, im = 0.f;
-                if (q < ch.q1 && t < nt) {
-                    const int yy = q / sd.bw, xx = q - yy * sd.bw;
-                    const float2 c = sd.iq[(long)t * npix + (long)(sd.y0 + yy) * nx + sd.x0 + xx];
-                    const double w = wpix[p];
-                    re = (float)(w * (double)c.x);
-                    im = (float)(w * (double)c.y);
-                }
-                put(p, t, re, im);
-            }
-        } else {
-            // Pixel pp of the batch is handled by the G consecutive lanes part =
-            // 0..G-1, frames t = part + G i, held in registers.
-            constexpr int G = C::THREADS / PIX > 16 ? 16 : C::THREADS / PIX;
-            constexpr int TPT = NTP / G;
-            static_assert(NTP % G == 0, "frames split evenly over a pixel's lanes");
-            const int pp = tid / G, part = tid % G;
-            const int q = qb + pp;
-            long poff = -1;
-            if (pp < PIX) {     // whole waves beyond the batch's pixels idle here
-            if (q < ch.q1) {
-                const int yy = q / sd.bw, xx = q - yy * sd.bw;
-                poff = (long)(sd.y0 + yy) * nx + sd.x0 + xx;
-            }
-            float2 sreg[TPT];
 #pragma unroll
-            for (int i = 0; i < TPT; ++i) {
-                const int t = part + G * i;
-                sreg[i] = (poff >= 0 && t < nt) ? sd.iq[(long)t * npix + poff] : make_float2(0.f, 0.f);
+        for (int i = 0; i < NPT; ++i) {
+            const int t = my_t0 + TSTEP * i;
+            nxt[i] = (poff >= 0 && t < nt) ? sd.iq[(long)t * npix + poff] : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(ch.q0);
+    for (int qb = ch.q0; qb < ch.q1; qb += PIX) {
+        float2 cur[NPT];
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) cur[i] = nxt[i];
+        const double w = nw;
+        __syncthreads();                           // the previous batch's MFMAs are done
+        if (qb + PIX < ch.q1) fetch(qb + PIX);     // in flight during this batch
+        if (!DEFL) {
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                const int t = my_t0 + TSTEP * i;
+                if (t < NTP) put(my_p, t, (float)(w * (double)cur[i].x), (float)(w * (double)cur[i].y));
             }
-            const double w = wpix[pp];
+        } else if (active) {
             // Tissue scores y = w s V_r in FP64 over this lane's frames, reduced over
             // the pixel's lanes, rounded to FP32 (any value keeps C_w = C' + Y V_r^H exact).
             float2 y[RMAX];
@@ -190,10 +188,10 @@ k_gram(Workspace ws) {
                 double yr = 0.0, yi = 0.0;
                 if (j < r) {
 #pragma unroll
-                    for (int i = 0; i < TPT; ++i) {
-                        const double2 v = vrs[j * NTP + part + G * i];
-                        yr = fma((double)sreg[i].x, v.x, fma(-(double)sreg[i].y, v.y, yr));
-                        yi = fma((double)sreg[i].x, v.y, fma((double)sreg[i].y, v.x, yi));
+                    for (int i = 0; i < NPT; ++i) {
+                        const double2 v = vrs[j * NTP + my_t0 + G * i];
+                        yr = fma((double)cur[i].x, v.x, fma(-(double)cur[i].y, v.y, yr));
+                        yi = fma((double)cur[i].x, v.y, fma((double)cur[i].y, v.x, yi));
                     }
 #pragma unroll
                     for (int m = G >> 1; m >= 1; m >>= 1) {
@@ -205,12 +203,12 @@ k_gram(Workspace ws) {
             }
             // Bulk residual c' = w s - y V_r^H in FP64, rounded once.
 #pragma unroll
-            for (int i = 0; i < TPT; ++i) {
-                const int t = part + G * i;
+            for (int i = 0; i < NPT; ++i) {
+                const int t = my_t0 + G * i;
                 double re = 0.0, im = 0.0;
                 if (t < nt) {
-                    re = w * (double)sreg[i].x;
-                    im = w * (double)sreg[i].y;
+                    re = w * (double)cur[i].x;
+                    im = w * (double)cur[i].y;
 #pragma unroll
                     for (int j = 0; j < RMAX; ++j) {
                         if (j < r) {
@@ -221,15 +219,14 @@ k_gram(Workspace ws) {
                         }
                     }
                 }
-                put(pp, t, (float)re, (float)im);
+                put(my_p, t, (float)re, (float)im);
             }
-            for (int j = part; j < REXT; j += G) {
+            for (int j = my_t0; j < REXT; j += G) {
                 float2 yj = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int jj = 0; jj < RMAX; ++jj)
                     if (jj == j && jj < r) yj = y[jj];
-                put(pp, NTP + j, yj.x, yj.y);
-            }
+                put(my_p, NTP + j, yj.x, yj.y);
             }
         }
         __syncthreads();

@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
 }
 
 // ------------------------------------------------------------------ reprojection
-// One work-group per image row segment of up to PIX pixels (output-centric
+// One work-group per tile of trows_for(NTP) image rows x PIX pixels (output-centric
 // gather, no atomics). For every covering subset d in ascending order:
 //   y  = s V_r                      (FP64 partial sums, split over t, rounded to FP32)
 //   c' = s - y V_r^H                (FP64, then rounded to the GEMM operand)
@@ -226,12 +226,15 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
 //   PD(x)   += alpha_d w_d(x)^2 sum_t |chat(x, t)|^2     (Eq. 13)
 //   IQ(x,t) += w_d(x) chat(x, t),  W(x) += w_d(x)
 // The window factors out of the projection because C_hat_d(x, :) = w_d(x) s_x P_d.
-// Each wave owns CTW output column tiles of both 16-pixel row tiles.
+// Each wave owns CTW output column tiles of all TP/16 pixel row tiles, so every
+// [P; M] fragment read from memory serves TP pixels.
 // Work-groups are mapped to tiles so that each of the 8 XCDs walks a contiguous
 // range of tiles (neighbouring tiles share covering subsets, so their [P; M]
-// operands stay in that XCD's L2).
+// operands are shared in that XCD's L2).
 template <int NTP, int PREC>
 struct RpCfg {
+    static constexpr int TP = trows_for(NTP) * PIX;                   // pixels per tile
+    static constexpr int NRT = TP / 16;                               // MFMA row tiles
     static constexpr int NTE = NTP + REXT;
     static constexpr int NTEP = (NTE + 31) / 32 * 32;                 // BF16: K per part, padded
     static constexpr int LDK = 2 * NTEP + 8;                          // BF16 row stride (uint16)
@@ -241,30 +244,28 @@ struct RpCfg {
     static constexpr int NW = CT >= 8 ? 8 : CT;                       // waves
     static constexpr int NTHR = 64 * NW;
     static constexpr int CTW = (CT + NW - 1) / NW;                    // column tiles per wave
-    static constexpr int LDC = NTP + 1;                               // craw row stride (float2)
-    static constexpr int G = NTHR / PIX;                              // threads per pixel for y
-    static constexpr int ABYTES = PREC ? 2 * PIX * LDK * 2 : PIX * LDA * 4;
-    // two work-groups per CU where the LDS allows it (caps VGPRs at 128 for 8 waves)
-    static constexpr int MINW = NTP <= 128 ? NW / 2 : 1;
+    static constexpr int LDC = NTP + 1;                               // staging row stride (float2)
+    static constexpr int G = NTHR / TP;                               // threads per pixel for y
+    static constexpr int ABYTES = PREC ? 2 * TP * LDK * 2 : TP * LDA * 4;
 };
 
 template <int NTP, int PREC>
-__global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::MINW)) k_reproj(Workspace ws) {
+__global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR)) k_reproj(Workspace ws) {
     using C = RpCfg<NTP, PREC>;
     constexpr int NTEP = C::NTEP, LDK = C::LDK, IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
-    constexpr int NTHR = C::NTHR, CTW = C::CTW, G = C::G;
-    static_assert(PIX == 32, "reprojection tile is 2 x 16 pixels");
-    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "y split");
+    constexpr int NTHR = C::NTHR, CTW = C::CTW, G = C::G, TP = C::TP, NRT = C::NRT;
+    static_assert(TP % 16 == 0 && NTHR % TP == 0, "tile of whole MFMA row tiles");
+    static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "y split within a row of 16 lanes");
     constexpr int TPT = NTP / G;                // frames per thread
     static_assert(NTP % G == 0, "frames split evenly over a pixel's threads");
-    static_assert(C::ABYTES >= PIX * LDC * 8, "the operand buffer stages the packet tile");
+    static_assert(C::ABYTES >= TP * LDC * 8, "the operand buffer stages the packet tile");
     __shared__ __attribute__((aligned(16))) unsigned char abuf[C::ABYTES];
     __shared__ double2 vrs[RMAX * NTP];         // V_r, [j][t]
-    __shared__ float wd[PIX], wsum[PIX];
-    __shared__ float pdsh[C::NW * PIX];
+    __shared__ float wd[TP], wsum[TP];
+    __shared__ float pdsh[C::NW * TP];
     float* A = reinterpret_cast<float*>(abuf);                          // FP32: [p][LDA]
     uint16_t* Ah = reinterpret_cast<uint16_t*>(abuf);                   // BF16 hi: [p][LDK]
-    uint16_t* Al = Ah + PIX * LDK;                                      // BF16 lo
+    uint16_t* Al = Ah + TP * LDK;                                       // BF16 lo
     float2* craw = reinterpret_cast<float2*>(abuf);                     // staging only: [p][LDC]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15;
@@ -277,6 +278,9 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
     const int nt = pk.nt, nx = pk.nx;
     const long npix = (long)pk.ny * pk.nx;
     const int npx = td.x1 - td.x0 + 1;
+    // tile pixel p = row (p / PIX) of the tile, column x0 + p % PIX
+    auto in_tile = [&](int p) { return (p / PIX) < td.nrow && (p % PIX) < npx; };
+    auto pix_off = [&](int p) { return (long)(td.y + p / PIX) * nx + td.x0 + p % PIX; };
     // pixel pp of the tile is handled by the G consecutive lanes part = 0..G-1,
     // frames t = part + G i
     const int pp = tid / G, part = tid % G;
@@ -293,12 +297,17 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
             A[p * LDA + IMO + c] = im;
         }
     };
+    auto window = [&](const SubsetDesc& sd, int p) -> double {
+        const int y = td.y + p / PIX, x = td.x0 + p % PIX;
+        if (!in_tile(p) || y < sd.y0 || y > sd.y1 || x < sd.x0 || x > sd.x1) return 0.0;
+        return sd.flat ? 1.0 : ws.wtab[sd.wy_off + y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
+    };
 
     // the packet tile s(pixel, t): coalesced loads staged through LDS into registers
-    for (int e = tid; e < PIX * NTP; e += NTHR) {
-        const int p = e % PIX, t = e / PIX;
+    for (int e = tid; e < TP * NTP; e += NTHR) {
+        const int p = e % TP, t = e / TP;
         float2 c = make_float2(0.f, 0.f);
-        if (p < npx && t < nt) c = pk.iq[(long)t * npix + (long)td.y * nx + td.x0 + p];
+        if (in_tile(p) && t < nt) c = pk.iq[(long)t * npix + pix_off(p)];
         craw[p * LDC + t] = c;
     }
     __syncthreads();
@@ -310,14 +319,14 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
         uint32_t* z = reinterpret_cast<uint32_t*>(abuf);
         for (int e = tid; e < C::ABYTES / 4; e += NTHR) z[e] = 0u;
     }
-    floatx4 iq_acc[2][CTW];
-    float pd_acc[8];
+    floatx4 iq_acc[NRT][CTW];
+    float pd_acc[NRT * 4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NRT; ++a)
 #pragma unroll
         for (int m = 0; m < CTW; ++m) iq_acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) pd_acc[i] = 0.f;
+    for (int i = 0; i < NRT * 4; ++i) pd_acc[i] = 0.f;
 
     for (int ci = 0; ci < td.cov_cnt; ++ci) {
         const int s = ws.cover[td.cov_off + ci];
@@ -329,13 +338,7 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
             const int t = e / RMAX, j = e % RMAX;
             vrs[j * NTP + t] = ws.vr64[(long)s * NTP * RMAX + e];
         }
-        if (tid < PIX) {
-            const int x = td.x0 + tid;
-            float w = 0.f;
-            if (tid < npx && td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
-                w = sd.flat ? 1.f : (float)(ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0]);
-            wd[tid] = w;
-        }
+        if (tid < TP) wd[tid] = (float)window(sd, tid);
         __syncthreads();
         // y = s V_r (FP64 partial sums over this thread's frames, then reduced over
         // the pixel's G lanes; every lane ends with the full sum), rounded to FP32
@@ -378,28 +381,31 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
             }
             put(pp, t, (float)re, (float)im);
         }
-        if (part < REXT) {
+        for (int j = part; j < REXT; j += G) {
             float2 yj = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int j = 0; j < RMAX; ++j)
-                if (j == part && j < r) yj = y[j];
-            put(pp, NTP + part, yj.x, yj.y);
+            for (int jj = 0; jj < RMAX; ++jj)
+                if (jj == j && jj < r) yj = y[jj];
+            put(pp, NTP + j, yj.x, yj.y);
         }
         __syncthreads();
-        floatx4 acc[2][CTW];
+        floatx4 acc[NRT][CTW];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
         if (PREC) {
             const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
-#pragma unroll 2
+            constexpr int KUNR = NTP > 128 ? 1 : 2;      // register budget of the widest subsets
+#pragma unroll KUNR
             for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
                 const int kq = k0 + 8 * g;
-                const u32x4 a0h = *reinterpret_cast<const u32x4*>(Ah + col * LDK + kq);
-                const u32x4 a0l = *reinterpret_cast<const u32x4*>(Al + col * LDK + kq);
-                const u32x4 a1h = *reinterpret_cast<const u32x4*>(Ah + (16 + col) * LDK + kq);
-                const u32x4 a1l = *reinterpret_cast<const u32x4*>(Al + (16 + col) * LDK + kq);
+                bf16x8 xh[NRT], xl[NRT];
+#pragma unroll
+                for (int a = 0; a < NRT; ++a) {
+                    xh[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + (16 * a + col) * LDK + kq));
+                    xl[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Al + (16 * a + col) * LDK + kq));
+                }
                 const bool impart = k0 >= NTEP;
                 const int kk = impart ? kq - NTEP : kq;
 #pragma unroll
@@ -418,14 +424,12 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
 #pragma unroll
                         for (int q = 0; q < 4; ++q) { bh[q] ^= sgn; bl[q] ^= sgn; }
                         const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh), xbl = __builtin_bit_cast(bf16x8, bl);
-                        const bf16x8 x0h = __builtin_bit_cast(bf16x8, a0h), x0l = __builtin_bit_cast(bf16x8, a0l);
-                        const bf16x8 x1h = __builtin_bit_cast(bf16x8, a1h), x1l = __builtin_bit_cast(bf16x8, a1l);
-                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbh, acc[0][m], 0, 0, 0);
-                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0h, xbl, acc[0][m], 0, 0, 0);
-                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0l, xbh, acc[0][m], 0, 0, 0);
-                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbh, acc[1][m], 0, 0, 0);
-                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1h, xbl, acc[1][m], 0, 0, 0);
-                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1l, xbh, acc[1][m], 0, 0, 0);
+#pragma unroll
+                        for (int a = 0; a < NRT; ++a) {
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbh, acc[a][m], 0, 0, 0);
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbl, acc[a][m], 0, 0, 0);
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[a], xbh, acc[a][m], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -435,40 +439,41 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
             for (int k0 = 0; k0 < 2 * C::NTE; k0 += 4) {
                 const int kk = k0 + g;
                 const int acol = kk < C::NTE ? kk : IMO + kk - C::NTE;
-                const float a0 = A[col * LDA + acol];
-                const float a1 = A[(16 + col) * LDA + acol];
+                float av[NRT];
+#pragma unroll
+                for (int a = 0; a < NRT; ++a) av[a] = A[(16 * a + col) * LDA + acol];
                 const float* brow = Br + (long)kk * (2 * NTP);
 #pragma unroll
                 for (int m = 0; m < CTW; ++m) {
                     const int ct = wave * CTW + m;
                     if (ct < C::CT) {
                         const float b = brow[ct * 16 + col];
-                        acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][m], 0, 0, 0);
-                        acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][m], 0, 0, 0);
+#pragma unroll
+                        for (int a = 0; a < NRT; ++a)
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], b, acc[a][m], 0, 0, 0);
                     }
                 }
             }
         }
-        // epilogue: output element (pixel rt*16 + 4g + i, column ct*16 + col)
+        // epilogue: output element (pixel 16 a + 4 g + i, column ct * 16 + col)
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) {
                 if (wave * CTW + m < C::CT) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int p = rt * 16 + 4 * g + i;
-                        const float w = wd[p];
-                        const float v = acc[rt][m][i];
-                        pd_acc[rt * 4 + i] += alpha * w * w * v * v;
-                        iq_acc[rt][m][i] += w * v;
+                        const float w = wd[16 * a + 4 * g + i];
+                        const float v = acc[a][m][i];
+                        pd_acc[a * 4 + i] += alpha * w * w * v * v;
+                        iq_acc[a][m][i] += w * v;
                     }
                 }
             }
     }
     // PD: reduce over the 16 lanes that share pixel rows, then over waves
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NRT * 4; ++i) {
         float v = pd_acc[i];
         for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
         pd_acc[i] = v;
@@ -476,54 +481,45 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR), (RpCfg<NTP, PREC>::M
     __syncthreads();
     if (col == 0) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) pdsh[wave * PIX + (i >> 2) * 16 + 4 * g + (i & 3)] = pd_acc[i];
+        for (int i = 0; i < NRT * 4; ++i) pdsh[wave * TP + (i >> 2) * 16 + 4 * g + (i & 3)] = pd_acc[i];
     }
-    if (tid < PIX) {
-        const int x = td.x0 + tid;
+    if (tid < TP) {
         double ws_ = 0.0;
-        for (int ci = 0; ci < td.cov_cnt; ++ci) {
-            const SubsetDesc sd = ws.sub[ws.cover[td.cov_off + ci]];
-            if (tid < npx && td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1)
-                ws_ += sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
-        }
+        for (int ci = 0; ci < td.cov_cnt; ++ci) ws_ += window(ws.sub[ws.cover[td.cov_off + ci]], tid);
         wsum[tid] = (float)ws_;
     }
     __syncthreads();
-    if (tid < npx) {
-        const int p = tid, x = td.x0 + p;
+    if (tid < TP && in_tile(tid)) {
+        const int p = tid;
         float pdv = 0.f;
-        for (int w = 0; w < C::NW; ++w) pdv += pdsh[w * PIX + p];
+        for (int w = 0; w < C::NW; ++w) pdv += pdsh[w * TP + p];
         if (pk.pd_mode == 2) {
             double comp = 0.0;
             for (int ci = 0; ci < td.cov_cnt; ++ci) {
                 const int s = ws.cover[td.cov_off + ci];
-                const SubsetDesc sd = ws.sub[s];
-                if (td.y >= sd.y0 && td.y <= sd.y1 && x >= sd.x0 && x <= sd.x1) {
-                    const double w = sd.flat ? 1.0 : ws.wtab[sd.wy_off + td.y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
-                    comp += ws.alpha[s] * w * w;
-                }
+                const double w = window(ws.sub[s], p);
+                comp += ws.alpha[s] * w * w;
             }
             pdv = comp > 0.0 ? (float)((double)pdv / comp) : 0.f;
         }
-        pk.pd[(long)td.y * nx + x] = pdv;
+        pk.pd[pix_off(p)] = pdv;
     }
     if (pk.iq_out) {
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) {
                 const int ct = wave * CTW + m;
                 if (ct < C::CT) {
                     const int n = ct * 16 + col;
-                    const int part = n >= NTP, t = n - part * NTP;
+                    const int part_ = n >= NTP, t = n - part_ * NTP;
                     if (t < nt) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const int p = rt * 16 + 4 * g + i;
-                            if (p < npx) {
+                            const int p = 16 * a + 4 * g + i;
+                            if (in_tile(p)) {
                                 const float w = wsum[p];
-                                pk.iq_out[2 * ((long)t * npix + (long)td.y * nx + td.x0 + p) + part] =
-                                    w > 0.f ? iq_acc[rt][m][i] / w : 0.f;
+                                pk.iq_out[2 * ((long)t * npix + pix_off(p)) + part_] = w > 0.f ? iq_acc[a][m][i] / w : 0.f;
                             }
                         }
                     }

@@ -14,6 +14,10 @@ constexpr int RMAX = 8;
 constexpr int REXT = 16;
 // Pixels per LDS batch in the Gram and reprojection kernels.
 constexpr int PIX = 32;
+// Image rows per reprojection tile (a tile is trows x PIX pixels); one row for
+// the widest subsets, whose accumulators fill the register file.
+constexpr int TROWS = 2;
+__host__ __device__ constexpr int trows_for(int ntp) { return ntp <= 128 ? TROWS : 1; }
 // Pixels per Gram work item (split-K chunk); several LDS batches each.
 constexpr int CHUNK = 1024;
 
@@ -37,10 +41,12 @@ struct ChunkDesc {
     int q0, q1;
 };
 
-// A reprojection tile: one image row segment [x0, x1] of packet pkt, covered by
-// the subsets cover[cov_off .. cov_off + cov_cnt) (ascending subset order).
+// A reprojection tile: rows y .. y + nrow - 1 (nrow <= trows_for(ntp)), columns [x0, x1]
+// of packet pkt, covered by the subsets cover[cov_off .. cov_off + cov_cnt)
+// (ascending subset order).
 struct TileDesc {
     int pkt, y, x0, x1;
+    int nrow;
     int cov_off, cov_cnt;
 };
 

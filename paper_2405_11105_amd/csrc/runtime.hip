@@ -162,19 +162,22 @@ void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int
                 pl.chunks.push_back(ChunkDesc{sidx, q, std::min(s.neff, q + CHUNK)});
             pl.sub.push_back(s);
         }
-        // reprojection tiles: row segments of PIX pixels, with covering subsets
+        // reprojection tiles: trows rows x PIX pixels, with covering subsets
         const int last = (int)pl.sub.size();
-        for (int y = 0; y < g.ny; ++y)
+        const int trows = trows_for(pl.ntp);
+        for (int y = 0; y < g.ny; y += trows)
             for (int x0 = 0; x0 < g.nx; x0 += PIX) {
                 TileDesc t;
                 t.pkt = (int)pi;
                 t.y = y;
+                t.nrow = std::min(trows, g.ny - y);
                 t.x0 = x0;
                 t.x1 = std::min(g.nx - 1, x0 + PIX - 1);
                 t.cov_off = (int)pl.cover.size();
+                const int y1 = y + t.nrow - 1;
                 for (int s = first; s < last; ++s) {
                     const SubsetDesc& sd = pl.sub[s];
-                    if (y >= sd.y0 && y <= sd.y1 && t.x1 >= sd.x0 && t.x0 <= sd.x1) pl.cover.push_back(s);
+                    if (y1 >= sd.y0 && y <= sd.y1 && t.x1 >= sd.x0 && t.x0 <= sd.x1) pl.cover.push_back(s);
                 }
                 t.cov_cnt = (int)pl.cover.size() - t.cov_off;
                 pl.tiles.push_back(t);
