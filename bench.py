@@ -218,7 +218,7 @@ def main():
         "gram1": ("mfma", 4.0 * sum_neff * nt * nt, PEAK["bf16_mfma"]),
         "gram2": ("mfma", 4.0 * sum_neff * (nt + 16) ** 2, PEAK["bf16_mfma"]),
         "reproj": ("mfma", 8.0 * sum_neff * nt * (nt + 16), PEAK["bf16_mfma"]),
-        "jacobi": ("alu", float(np.sum(sweeps)) * len(iqs) * pairs * 40.0 * nt, PEAK["fp64"]),
+        "jacobi": ("alu", float(np.sum(sweeps)) * len(iqs) * pairs * 36.0 * nt, PEAK["fp64"]),
     }
     timed = {k: v for k, v in stages.items() if v[1]}
     dom = max(timed, key=lambda k: timed[k][0])
