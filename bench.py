@@ -7,7 +7,8 @@ recombination) over a batch of synthetic packets already resident in HBM.
 
 Two configurations of the same library are timed on the same packets:
   fast  - learned weights (trained network), split-BF16 GEMMs, all subsets of
-          all packets batched per stage, replayed from a captured hipGraph;
+          all packets batched per stage, plan sizes picked by the autotuner
+          (before the timed region), replayed from a captured hipGraph;
   plain - FP32 GEMMs, the curvature-knee rule with sigmoid weights (Eqs 6, 9),
           and the paper's loop over subsets (one subset at a time through every
           per-subset stage), no graph.
@@ -81,6 +82,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="oracle time budget for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="fast configuration with the default plan sizes")
     ap.add_argument("--ablation-steps", type=int, default=3, help="0 skips the ablation legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM byte counters)")
@@ -113,7 +115,7 @@ def main():
         iqs = [torch.from_numpy(h[0]).to(dev) for h in host]
         outs_f = [(torch.empty_like(iq), torch.empty((ny, nx), dtype=torch.float32, device=dev)) for iq in iqs]
         outs_p = [(torch.empty_like(iq), torch.empty((ny, nx), dtype=torch.float32, device=dev)) for iq in iqs]
-        fast = lcf.Context(0, schedule=0, use_graph=1)
+        fast = lcf.Context(0, schedule=0, use_graph=1, autotune=0 if args.no_autotune else 1)
         if use_mlp:
             fast.mlp_load(args.mlp)
         grids = [(gy, gx)] * len(iqs)
@@ -151,6 +153,12 @@ def main():
         if fast.sync() != 0:
             raise RuntimeError("device-side error flagged in the timed region")
 
+        import tempfile
+        with tempfile.NamedTemporaryFile("r", suffix=".txt", delete=False) as tf:
+            tune_file = tf.name
+        fast.tune_save(tune_file)
+        tuned = [ln.split() for ln in open(tune_file).read().splitlines() if ln.strip()]
+
         # the same steps again with per-launch HIP events on this stream (no graph
         # replay while they are on): per-kernel durations for the roofline
         fast.set_option(lcf.OPT_STAGE_TIMING, 1)
@@ -170,6 +178,7 @@ def main():
                     ("rule, FP32, batched, no graph", thr_plain, lcf.PREC_FP32, 0)]
             for name, thr_l, prec_l, graph_l in legs:
                 actx = lcf.Context(0, schedule=0, use_graph=graph_l)
+                actx.tune_load(tune_file)
                 if use_mlp and thr_l.cut == lcf.CUT_MLP:
                     actx.mlp_load(args.mlp)
                 run = lambda: actx.filter_batch(iqs, grids, thr_l, precision=prec_l, outs=outs_p)
@@ -280,10 +289,12 @@ def main():
         "jacobi_sweeps_mean": float(np.mean(sweeps)),
         "deflated_rank_mean": float(np.mean(ranks)),
         "mlp_fallback_rate": fallback,
+        "autotune": {t[0]: {"gram_chunk_px": int(t[1]), "reproj_tile_rows": int(t[2])} for t in tuned},
         "wall_s": wall,
     }
     print(json.dumps(out))
     fast.close()
+    os.unlink(tune_file)
 
 
 if __name__ == "__main__":

@@ -136,6 +136,13 @@ typedef struct {
 #define LCF_OPT_STAGE_TIMING 5  /* 1 = bracket every kernel launch with HIP events on the
                                    caller's stream and accumulate per-stage device time
                                    (read with lcf_stage_time; default 0)                  */
+#define LCF_OPT_AUTOTUNE     6  /* 1 = before the first call of a launch-group class (padded
+                                   Nt, precision, schedule, log2 subset count, log2 mean
+                                   box size) with no stored choice, time every split-K
+                                   chunk {512..4096 px} x reprojection tile {1, 2 rows}
+                                   on the call's own packets and keep the fastest
+                                   (default 0: 1024 px, 2 rows up to 128 frames). Tuning
+                                   is skipped while the stream is being captured.          */
 
 /* Kernel stages reported by lcf_stage_time. */
 typedef enum {
@@ -235,6 +242,16 @@ lcf_status lcf_sync(lcf_context* ctx, void* stream);
  * reset, over the calls made with LCF_OPT_STAGE_TIMING = 1. Waits for the
  * recorded events. reset != 0 clears all stages after reading. */
 lcf_status lcf_stage_time(lcf_context* ctx, int32_t stage, double* ms, int64_t* launches, int32_t reset);
+
+/* Autotuner choices (batched form of many packets and subsets, Discussion:
+ * parallel processing of subsets) as text, one line per launch-group class:
+ * "<class> <chunk> <rows>". lcf_tune_save writes the context's choices to `path`;
+ * lcf_tune_load adds the choices in `path` to the context (replacing entries of
+ * the same class) and drops captured graphs. Errors: LCF_ERR_INVALID_ARG for
+ * NULL arguments, an unreadable/unwritable file or a malformed line (nothing is
+ * loaded from a file with a malformed line). */
+lcf_status lcf_tune_save(lcf_context* ctx, const char* path);
+lcf_status lcf_tune_load(lcf_context* ctx, const char* path);
 
 const char* lcf_status_str(lcf_status s);
 int32_t lcf_abi_version(void);

@@ -19,7 +19,7 @@ PREC_FP32, PREC_BF16X3 = 0, 1
 CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP = 0, 1, 2, 3
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
-OPT_SCHEDULE, OPT_MAX_SWEEPS, OPT_USE_GRAPH, OPT_SUBSPACE_IT, OPT_STAGE_TIMING = 1, 2, 3, 4, 5
+OPT_SCHEDULE, OPT_MAX_SWEEPS, OPT_USE_GRAPH, OPT_SUBSPACE_IT, OPT_STAGE_TIMING, OPT_AUTOTUNE = 1, 2, 3, 4, 5, 6
 STAGES = ["windows", "gram1", "gram1_reduce", "tissue", "gram2", "gram2_reduce", "assemble", "jacobi",
           "rules", "mlp", "projector", "reproj"]
 FLAG_NONPOSITIVE, FLAG_NONFINITE, FLAG_NO_CONVERGE, FLAG_MLP_FALLBACK = 1, 2, 4, 8
@@ -100,12 +100,14 @@ def load():
     lib.lcf_mlp_load.argtypes = [vp, C.c_char_p]
     lib.lcf_mlp_infer.argtypes = [vp, vp, vp, i32, vp]
     lib.lcf_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, vp, vp]
+    lib.lcf_tune_save.argtypes = [vp, C.c_char_p]
+    lib.lcf_tune_load.argtypes = [vp, C.c_char_p]
     lib.lcf_status_str.argtypes = [i32]
     lib.lcf_status_str.restype = C.c_char_p
     for name in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter",
                  "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version", "lcf_stage_time",
                  "lcf_mlp_init", "lcf_mlp_set_params", "lcf_mlp_get_params", "lcf_mlp_get_grads", "lcf_mlp_save",
-                 "lcf_mlp_load", "lcf_mlp_infer", "lcf_mlp_train_step"):
+                 "lcf_mlp_load", "lcf_mlp_infer", "lcf_mlp_train_step", "lcf_tune_save", "lcf_tune_load"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -143,9 +145,10 @@ def _ptr(t) -> C.c_void_p:
 
 
 class Context:
-    """An lcf_context on one device (options: schedule, max_sweeps, use_graph)."""
+    """An lcf_context on one device (options: schedule, max_sweeps, use_graph, autotune)."""
 
-    def __init__(self, device: int = 0, schedule: int = 0, max_sweeps: int = 30, use_graph: int = 0):
+    def __init__(self, device: int = 0, schedule: int = 0, max_sweeps: int = 30, use_graph: int = 0,
+                 autotune: int = 0):
         lib = load()
         h = C.c_void_p()
         _check(lib.lcf_create(device, C.byref(h)), "lcf_create")
@@ -154,6 +157,13 @@ class Context:
         self.set_option(OPT_SCHEDULE, schedule)
         self.set_option(OPT_MAX_SWEEPS, max_sweeps)
         self.set_option(OPT_USE_GRAPH, use_graph)
+        self.set_option(OPT_AUTOTUNE, autotune)
+
+    def tune_save(self, path: str):
+        _check(load().lcf_tune_save(self._h, path.encode()), "lcf_tune_save")
+
+    def tune_load(self, path: str):
+        _check(load().lcf_tune_load(self._h, path.encode()), "lcf_tune_load")
 
     def set_option(self, opt: int, value: int):
         _check(load().lcf_set_option(self._h, opt, int(value)), "lcf_set_option")

@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
 }
 
 // ------------------------------------------------------------------ reprojection
-// One work-group per tile of trows_for(NTP) image rows x PIX pixels (output-centric
+// One work-group per tile of TR image rows x PIX pixels (output-centric
 // gather, no atomics). For every covering subset d in ascending order:
 //   y  = s V_r                      (FP64 partial sums, split over t, rounded to FP32)
 //   c' = s - y V_r^H                (FP64, then rounded to the GEMM operand)
@@ -231,9 +231,9 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
 // Work-groups are mapped to tiles so that each of the 8 XCDs walks a contiguous
 // range of tiles (neighbouring tiles share covering subsets, so their [P; M]
 // operands are shared in that XCD's L2).
-template <int NTP, int PREC>
+template <int NTP, int PREC, int TR>
 struct RpCfg {
-    static constexpr int TP = trows_for(NTP) * PIX;                   // pixels per tile
+    static constexpr int TP = TR * PIX;                               // pixels per tile
     static constexpr int NRT = TP / 16;                               // MFMA row tiles
     static constexpr int NTE = NTP + REXT;
     static constexpr int NTEP = (NTE + 31) / 32 * 32;                 // BF16: K per part, padded
@@ -249,9 +249,9 @@ struct RpCfg {
     static constexpr int ABYTES = PREC ? 2 * TP * LDK * 2 : TP * LDA * 4;
 };
 
-template <int NTP, int PREC>
-__global__ void __launch_bounds__((RpCfg<NTP, PREC>::NTHR)) k_reproj(Workspace ws) {
-    using C = RpCfg<NTP, PREC>;
+template <int NTP, int PREC, int TR>
+__global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspace ws) {
+    using C = RpCfg<NTP, PREC, TR>;
     constexpr int NTEP = C::NTEP, LDK = C::LDK, IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
     constexpr int NTHR = C::NTHR, CTW = C::CTW, G = C::G, TP = C::TP, NRT = C::NRT;
     static_assert(TP % 16 == 0 && NTHR % TP == 0, "tile of whole MFMA row tiles");
@@ -537,10 +537,19 @@ static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t 
         else hipLaunchKernelGGL((k_projector<NTP, 1>), dim3(ws.S), dim3(256), 0, st, ws);
     } else if (ws.ntiles > 0) {
         const int grid = (ws.ntiles + 7) / 8 * 8;      // multiple of 8 for the XCD mapping
+        if constexpr (trows_max(NTP) >= 2) {
+            if (ws.trows == 2) {
+                if (prec == 0)
+                    hipLaunchKernelGGL((k_reproj<NTP, 0, 2>), dim3(grid), dim3(RpCfg<NTP, 0, 2>::NTHR), 0, st, ws);
+                else
+                    hipLaunchKernelGGL((k_reproj<NTP, 1, 2>), dim3(grid), dim3(RpCfg<NTP, 1, 2>::NTHR), 0, st, ws);
+                return;
+            }
+        }
         if (prec == 0)
-            hipLaunchKernelGGL((k_reproj<NTP, 0>), dim3(grid), dim3(RpCfg<NTP, 0>::NTHR), 0, st, ws);
+            hipLaunchKernelGGL((k_reproj<NTP, 0, 1>), dim3(grid), dim3(RpCfg<NTP, 0, 1>::NTHR), 0, st, ws);
         else
-            hipLaunchKernelGGL((k_reproj<NTP, 1>), dim3(grid), dim3(RpCfg<NTP, 1>::NTHR), 0, st, ws);
+            hipLaunchKernelGGL((k_reproj<NTP, 1, 1>), dim3(grid), dim3(RpCfg<NTP, 1, 1>::NTHR), 0, st, ws);
     }
 }
 

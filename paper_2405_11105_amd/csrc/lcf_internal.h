@@ -14,10 +14,11 @@ constexpr int RMAX = 8;
 constexpr int REXT = 16;
 // Pixels per LDS batch in the Gram and reprojection kernels.
 constexpr int PIX = 32;
-// Image rows per reprojection tile (a tile is trows x PIX pixels); one row for
-// the widest subsets, whose accumulators fill the register file.
+// Image rows per reprojection tile (a tile is trows x PIX pixels): 1 or 2, the
+// latter only up to 128 frames (the accumulators of wider subsets fill the
+// register file). Chosen per launch group (default, or by the autotuner).
 constexpr int TROWS = 2;
-__host__ __device__ constexpr int trows_for(int ntp) { return ntp <= 128 ? TROWS : 1; }
+__host__ __device__ constexpr int trows_max(int ntp) { return ntp <= 128 ? TROWS : 1; }
 // Pixels per Gram work item (split-K chunk); several LDS batches each.
 constexpr int CHUNK = 1024;
 
@@ -41,7 +42,7 @@ struct ChunkDesc {
     int q0, q1;
 };
 
-// A reprojection tile: rows y .. y + nrow - 1 (nrow <= trows_for(ntp)), columns [x0, x1]
+// A reprojection tile: rows y .. y + nrow - 1 (nrow <= the group's trows), columns [x0, x1]
 // of packet pkt, covered by the subsets cover[cov_off .. cov_off + cov_cnt)
 // (ascending subset order).
 struct TileDesc {
@@ -69,6 +70,7 @@ struct Workspace {
     const int* chunk_begin;   // [S+1] first chunk of each subset
     const TileDesc* tiles;
     int ntiles;
+    int trows;          // rows per reprojection tile (1 or 2)
     const int* cover;
     const PacketDesc* pkts;
     double* wtab;       // window factor pool

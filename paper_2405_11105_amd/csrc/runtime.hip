@@ -98,6 +98,11 @@ lcf_status validate_precision(int p) {
     return LCF_ERR_INVALID_ARG;
 }
 
+struct TuneChoice {
+    int chunk;      // split-K chunk of the Gram passes (box pixels)
+    int trows;      // image rows per reprojection tile
+};
+
 struct PacketIn {
     lcf_geometry g;
     const void* iq;
@@ -108,6 +113,8 @@ struct PacketIn {
 // Host-side plan of one launch group (packets sharing the padded Nt class).
 struct Plan {
     int ntp = 0, nt_max = 0;
+    int chunk = CHUNK;      // split-K chunk of the Gram passes (box pixels)
+    int trows = 1;          // image rows per reprojection tile
     std::vector<SubsetDesc> sub;
     std::vector<ChunkDesc> chunks;
     std::vector<int> chunk_begin;
@@ -118,9 +125,12 @@ struct Plan {
     size_t wtab_len = 0;
 };
 
-void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int>& idx, int pd_mode) {
+void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int>& idx, int pd_mode, int chunk,
+                int trows) {
     pl.ntp = 0;
     pl.nt_max = 0;
+    pl.chunk = chunk;
+    pl.trows = trows;
     for (int i : idx) {
         pl.ntp = std::max(pl.ntp, ntp_class(in[i].g.nt));
         pl.nt_max = std::max(pl.nt_max, in[i].g.nt);
@@ -158,13 +168,13 @@ void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int
             s.npix_nt = (double)g.ny * g.nx * g.nt;
             const int sidx = (int)pl.sub.size();
             pl.chunk_begin.push_back((int)pl.chunks.size());
-            for (int q = 0; q < s.neff; q += CHUNK)
-                pl.chunks.push_back(ChunkDesc{sidx, q, std::min(s.neff, q + CHUNK)});
+            for (int q = 0; q < s.neff; q += pl.chunk)
+                pl.chunks.push_back(ChunkDesc{sidx, q, std::min(s.neff, q + pl.chunk)});
             pl.sub.push_back(s);
         }
         // reprojection tiles: trows rows x PIX pixels, with covering subsets
         const int last = (int)pl.sub.size();
-        const int trows = trows_for(pl.ntp);
+        const int trows = pl.trows;
         for (int y = 0; y < g.ny; y += trows)
             for (int x0 = 0; x0 < g.nx; x0 += PIX) {
                 TileDesc t;
@@ -211,6 +221,9 @@ struct lcf_context {
     std::vector<std::pair<int, size_t>> evpending;   // (stage, index of start event)
     double stage_ms[LCF_NUM_STAGES] = {0};
     long long stage_n[LCF_NUM_STAGES] = {0};
+    // autotuner: choices per launch-group class (tune_key)
+    int autotune = 0;
+    std::map<std::string, TuneChoice> tuned;
     // learned weights
     MlpDev mlp{};
     bool mlp_ready = false;
@@ -274,6 +287,8 @@ std::string graph_key(lcf_context* c, const Plan& pl, const std::vector<PacketIn
     std::snprintf(buf, sizeof buf, "t%d,%d,%d,%d,%.17g,%.17g,%.17g,%.17g,%p|p%d,s%d,w%d,i%d,n%d", thr->cut, thr->shape,
                   thr->pd_mode, thr->k_fixed, thr->beta_knee, thr->knee_max_frac, thr->beta_sigmoid, thr->deflate_rho,
                   (const void*)thr->explicit_w, prec, c->schedule, c->max_sweeps, c->sub_iters, pl.ntp);
+    k += buf;
+    std::snprintf(buf, sizeof buf, "|c%d,r%d", pl.chunk, pl.trows);
     k += buf;
     if (diag) {
         std::snprintf(buf, sizeof buf, "|d%p,%p,%p,%p,%p,%p,%p,%p,%p", (void*)diag->eigvals, (void*)diag->weights,
@@ -385,6 +400,7 @@ Workspace make_ws(char* base, const Layout& L, const Plan& pl, const float* expl
     ws.chunk_begin = (const int*)(base + L.off_cbeg);
     ws.tiles = (const TileDesc*)(base + L.off_tiles);
     ws.ntiles = (int)pl.tiles.size();
+    ws.trows = pl.trows;
     ws.cover = (const int*)(base + L.off_cover);
     ws.pkts = (const PacketDesc*)(base + L.off_pkts);
     ws.wtab = (double*)(base + L.off_wtab);
@@ -530,60 +546,181 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     return LCF_OK;
 }
 
+// A launch group staged on the device: plan descriptors uploaded, workspace
+// views set up.
+struct Staged {
+    Workspace ws;
+    size_t seq_off = 0;
+};
+
+lcf_status stage_group(lcf_context* c, const Plan& pl, const lcf_threshold* thr, hipStream_t st, Staged& sg) {
+    Layout L = make_layout(pl);
+    // sequential schedule: per-subset chunk tables appended to the host block
+    const size_t seq_off = L.host_bytes;
+    size_t seq_bytes = 0;
+    if (c->schedule == 1) seq_bytes = pl.chunks.size() * sizeof(ChunkDesc) + 2 * pl.sub.size() * sizeof(int);
+    const size_t host_total = align_up(L.host_bytes + seq_bytes, 256);
+    // shift device-only buffers after the host block
+    Layout D = L;
+    const size_t shift = host_total - L.host_bytes;
+    for (size_t* p = &D.off_wtab; p <= &D.off_breal; ++p) *p += shift;
+    D.total += shift;
+    lcf_status e = ensure_device(c, D.total);
+    if (e != LCF_OK) return e;
+    e = ensure_host(c, host_total);
+    if (e != LCF_OK) return e;
+    char* h = c->hbuf;
+    std::memcpy(h + L.off_sub, pl.sub.data(), pl.sub.size() * sizeof(SubsetDesc));
+    std::memcpy(h + L.off_chunks, pl.chunks.data(), pl.chunks.size() * sizeof(ChunkDesc));
+    std::memcpy(h + L.off_cbeg, pl.chunk_begin.data(), pl.chunk_begin.size() * sizeof(int));
+    std::memcpy(h + L.off_tiles, pl.tiles.data(), pl.tiles.size() * sizeof(TileDesc));
+    std::memcpy(h + L.off_cover, pl.cover.data(), pl.cover.size() * sizeof(int));
+    std::memcpy(h + L.off_pkts, pl.pkts.data(), pl.pkts.size() * sizeof(PacketDesc));
+    if (c->schedule == 1) {
+        ChunkDesc* sc = (ChunkDesc*)(h + seq_off);
+        for (size_t i = 0; i < pl.chunks.size(); ++i) { sc[i] = pl.chunks[i]; sc[i].s = 0; }
+        int* cb = (int*)(h + seq_off + pl.chunks.size() * sizeof(ChunkDesc));
+        for (size_t s = 0; s < pl.sub.size(); ++s) {
+            cb[2 * s] = 0;
+            cb[2 * s + 1] = pl.chunk_begin[s + 1] - pl.chunk_begin[s];
+        }
+    }
+    HIPCHK(hipMemcpyAsync(c->dbuf, h, host_total, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(c->staged, st));
+    c->staged_pending = true;
+    sg.ws = make_ws(c->dbuf, D, pl, thr->cut == LCF_CUT_EXPLICIT ? thr->explicit_w : nullptr);
+    sg.seq_off = seq_off;
+    if (thr->cut == LCF_CUT_MLP) {
+        const size_t need = align_up(pl.sub.size(), 64) + mlp_infer_scratch_floats((int)pl.sub.size());
+        e = ensure_mlp_scratch(c, need);
+        if (e != LCF_OK) return e;
+    }
+    return LCF_OK;
+}
+
+// The launch chain of one staged group (every stage through the reprojection).
+lcf_status run_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf_threshold* thr, int prec,
+                     const lcf_diag* diag, hipStream_t st) {
+    const Workspace& ws = sg.ws;
+    lcf_status e;
+    if (c->schedule == 1) {
+        // the paper's loop: one subset at a time through every per-subset stage
+        const ChunkDesc* dch = (const ChunkDesc*)(c->dbuf + sg.seq_off);
+        const int* dcb = (const int*)(c->dbuf + sg.seq_off + pl.chunks.size() * sizeof(ChunkDesc));
+        for (int s = 0; s < (int)pl.sub.size(); ++s) {
+            const int cb0 = pl.chunk_begin[s], nch = pl.chunk_begin[s + 1] - cb0;
+            Workspace v = subset_view(ws, s, dch + cb0, dcb + 2 * s, nch);
+            if (ws.explicit_w) v.explicit_w = ws.explicit_w + (long)s * pl.sub[s].nt;
+            double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
+            e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
+            if (e != LCF_OK) return e;
+            e = run_stages2(c, v, thr, prec, pl.sub[s].nt, st);
+            if (e != LCF_OK) return e;
+        }
+    } else {
+        e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
+        if (e != LCF_OK) return e;
+        e = run_stages2(c, ws, thr, prec, pl.nt_max, st);
+        if (e != LCF_OK) return e;
+    }
+    { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
+    if (diag)
+        HIPCHK(launch_export(ws, 0, (int)pl.sub.size(), pl.sub[0].nt, diag->eigvals, diag->weights, diag->k,
+                             diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs, st));
+    HIPCHK(launch_flags_or(ws, c->sticky, st));
+    return LCF_OK;
+}
+
+// Autotuner key of a launch group: padded Nt class, precision, schedule and
+// the log2 classes of the subset count and of the mean box size.
+std::string tune_key(const Plan& pl, int prec, int schedule) {
+    double neff = 0.0;
+    for (const SubsetDesc& sd : pl.sub) neff += sd.neff;
+    neff /= std::max<size_t>(1, pl.sub.size());
+    const int sc = (int)std::floor(std::log2((double)std::max<size_t>(1, pl.sub.size())));
+    const int nc = (int)std::floor(std::log2(std::max(1.0, neff)));
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "ntp%d_p%d_s%d_S%d_N%d", pl.ntp, prec, schedule, sc, nc);
+    return buf;
+}
+
+// Time every (split-K chunk, tile rows) candidate on the caller's packets with
+// HIP events (one untimed run, one timed run each) and keep the fastest. The
+// outputs end up written by the last candidate; the caller's run overwrites them.
+lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std::vector<int>& idx,
+                      const lcf_threshold* thr, int prec, hipStream_t st, const std::string& key) {
+    static const int chunks[] = {512, 1024, 2048, 4096};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return LCF_ERR_DEVICE; }
+    const int saved_timing = c->timing;
+    c->timing = 0;
+    float best = 0.f;
+    TuneChoice choice{CHUNK, 1};
+    lcf_status res = LCF_OK;
+    int ntp = 0;
+    for (int i : idx) ntp = std::max(ntp, ntp_class(in[i].g.nt));
+    for (int tr = 1; tr <= trows_max(ntp) && res == LCF_OK; ++tr) {
+        for (int ch : chunks) {
+            Plan pl;
+            build_plan(pl, in, idx, thr->pd_mode, ch, tr);
+            Staged sg;
+            res = stage_group(c, pl, thr, st, sg);
+            if (res != LCF_OK) break;
+            res = run_chain(c, pl, sg, thr, prec, nullptr, st);
+            if (res != LCF_OK) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { res = LCF_ERR_DEVICE; break; }
+            res = run_chain(c, pl, sg, thr, prec, nullptr, st);
+            if (res != LCF_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { res = LCF_ERR_DEVICE; break; }
+            if (best == 0.f || ms < best) { best = ms; choice = TuneChoice{ch, tr}; }
+        }
+    }
+    c->timing = saved_timing;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (res == LCF_OK) c->tuned[key] = choice;
+    return res;
+}
+
 // Filter a list of packets. diag applies to a single packet call only.
 lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const lcf_threshold* thr, int prec,
                           const lcf_diag* diag, hipStream_t st) {
     if (!c) return LCF_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return LCF_ERR_DEVICE;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (st != nullptr && hipStreamIsCapturing(st, &cap) != hipSuccess) return LCF_ERR_DEVICE;
     // group packets by padded Nt class
     std::map<int, std::vector<int>> groups;
     for (size_t i = 0; i < in.size(); ++i) groups[ntp_class(in[i].g.nt)].push_back((int)i);
     for (auto& kv : groups) {
+        // plan parameters: the tuned choice for this group's class, else the defaults
         Plan pl;
-        build_plan(pl, in, kv.second, thr->pd_mode);
-        Layout L = make_layout(pl);
-        // sequential schedule: per-subset chunk tables appended to the host block
-        size_t seq_off = L.host_bytes, seq_bytes = 0;
-        if (c->schedule == 1) seq_bytes = pl.chunks.size() * sizeof(ChunkDesc) + 2 * pl.sub.size() * sizeof(int);
-        const size_t host_total = align_up(L.host_bytes + seq_bytes, 256);
-        // shift device-only buffers after the host block
-        Layout D = L;
-        const size_t shift = host_total - L.host_bytes;
-        for (size_t* p = &D.off_wtab; p <= &D.off_breal; ++p) *p += shift;
-        D.total += shift;
-        lcf_status e = ensure_device(c, D.total);
-        if (e != LCF_OK) return e;
-        e = ensure_host(c, host_total);
-        if (e != LCF_OK) return e;
-        char* h = c->hbuf;
-        std::memcpy(h + L.off_sub, pl.sub.data(), pl.sub.size() * sizeof(SubsetDesc));
-        std::memcpy(h + L.off_chunks, pl.chunks.data(), pl.chunks.size() * sizeof(ChunkDesc));
-        std::memcpy(h + L.off_cbeg, pl.chunk_begin.data(), pl.chunk_begin.size() * sizeof(int));
-        std::memcpy(h + L.off_tiles, pl.tiles.data(), pl.tiles.size() * sizeof(TileDesc));
-        std::memcpy(h + L.off_cover, pl.cover.data(), pl.cover.size() * sizeof(int));
-        std::memcpy(h + L.off_pkts, pl.pkts.data(), pl.pkts.size() * sizeof(PacketDesc));
-        if (c->schedule == 1) {
-            ChunkDesc* sc = (ChunkDesc*)(h + seq_off);
-            for (size_t i = 0; i < pl.chunks.size(); ++i) { sc[i] = pl.chunks[i]; sc[i].s = 0; }
-            int* cb = (int*)(h + seq_off + pl.chunks.size() * sizeof(ChunkDesc));
-            for (size_t s = 0; s < pl.sub.size(); ++s) {
-                cb[2 * s] = 0;
-                cb[2 * s + 1] = pl.chunk_begin[s + 1] - pl.chunk_begin[s];
+        build_plan(pl, in, kv.second, thr->pd_mode, CHUNK, trows_max(kv.first));
+        const std::string tkey = tune_key(pl, prec, c->schedule);
+        auto tit = c->tuned.find(tkey);
+        if (tit == c->tuned.end() && c->autotune && cap == hipStreamCaptureStatusNone) {
+            lcf_status e = tune_group(c, in, kv.second, thr, prec, st, tkey);
+            if (e != LCF_OK) return e;
+            tit = c->tuned.find(tkey);
+        }
+        if (tit != c->tuned.end()) {
+            const int tr = std::min(std::max(tit->second.trows, 1), trows_max(kv.first));
+            if (tit->second.chunk != pl.chunk || tr != pl.trows) {
+                Plan tuned;
+                build_plan(tuned, in, kv.second, thr->pd_mode, tit->second.chunk, tr);
+                pl = std::move(tuned);
             }
         }
-        HIPCHK(hipMemcpyAsync(c->dbuf, h, host_total, hipMemcpyHostToDevice, st));
-        HIPCHK(hipEventRecord(c->staged, st));
-        c->staged_pending = true;
-        Workspace ws = make_ws(c->dbuf, D, pl, thr->cut == LCF_CUT_EXPLICIT ? thr->explicit_w : nullptr);
-        if (thr->cut == LCF_CUT_MLP) {
-            const size_t need = align_up(pl.sub.size(), 64) + mlp_infer_scratch_floats((int)pl.sub.size());
-            e = ensure_mlp_scratch(c, need);
-            if (e != LCF_OK) return e;
-        }
+        Staged sg;
+        lcf_status e = stage_group(c, pl, thr, st, sg);
+        if (e != LCF_OK) return e;
         // Launch chain of the group, optionally captured once into a hipGraph and
         // replayed for later calls with the same plan (not on the null stream, and
         // not while stage timing is on).
-        const bool graph = c->use_graph && !c->timing && st != nullptr;
+        const bool graph = c->use_graph && !c->timing && st != nullptr && cap == hipStreamCaptureStatusNone;
         std::string key;
         if (graph) {
             key = graph_key(c, pl, in, kv.second, thr, prec, diag);
@@ -594,37 +731,7 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
             }
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         }
-        auto chain = [&]() -> lcf_status {
-            if (c->schedule == 1) {
-                // the paper's loop: one subset at a time through every per-subset stage
-                const ChunkDesc* dch = (const ChunkDesc*)(c->dbuf + seq_off);
-                const int* dcb = (const int*)(c->dbuf + seq_off + pl.chunks.size() * sizeof(ChunkDesc));
-                for (int s = 0; s < (int)pl.sub.size(); ++s) {
-                    const int cb0 = pl.chunk_begin[s], nch = pl.chunk_begin[s + 1] - cb0;
-                    Workspace v = subset_view(ws, s, dch + cb0, dcb + 2 * s, nch);
-                    if (ws.explicit_w) v.explicit_w = ws.explicit_w + (long)s * pl.sub[s].nt;
-                    double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
-                    e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
-                    if (e != LCF_OK) return e;
-                    e = run_stages2(c, v, thr, prec, pl.sub[s].nt, st);
-                    if (e != LCF_OK) return e;
-                }
-            } else {
-                e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
-                if (e != LCF_OK) return e;
-                e = run_stages2(c, ws, thr, prec, pl.nt_max, st);
-                if (e != LCF_OK) return e;
-            }
-            { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
-            if (diag)
-                HIPCHK(launch_export(ws, 0, (int)pl.sub.size(), pl.sub[0].nt, diag->eigvals, diag->weights, diag->k,
-                                     diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs,
-                                     st));
-
-            HIPCHK(launch_flags_or(ws, c->sticky, st));
-            return LCF_OK;
-        };
-        e = chain();
+        e = run_chain(c, pl, sg, thr, prec, diag, st);
         if (graph) {
             hipGraph_t gr = nullptr;
             const hipError_t ce = hipStreamEndCapture(st, &gr);
@@ -704,6 +811,10 @@ lcf_status lcf_set_option(lcf_context* c, int32_t option, int64_t value) {
         case LCF_OPT_STAGE_TIMING:
             if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
             c->timing = (int)value;
+            return LCF_OK;
+        case LCF_OPT_AUTOTUNE:
+            if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
+            c->autotune = (int)value;
             return LCF_OK;
         default:
             return LCF_ERR_INVALID_ARG;
@@ -939,6 +1050,38 @@ lcf_status lcf_stage_time(lcf_context* ctx, int32_t stage, double* ms, int64_t* 
     if (launches) *launches = ctx->stage_n[stage];
     if (reset)
         for (int i = 0; i < LCF_NUM_STAGES; ++i) { ctx->stage_ms[i] = 0.0; ctx->stage_n[i] = 0; }
+    return LCF_OK;
+}
+
+lcf_status lcf_tune_save(lcf_context* ctx, const char* path) {
+    if (!ctx || !path) return LCF_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return LCF_ERR_INVALID_ARG;
+    bool ok = true;
+    for (const auto& kv : ctx->tuned)
+        ok = ok && std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.chunk, kv.second.trows) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? LCF_OK : LCF_ERR_INVALID_ARG;
+}
+
+lcf_status lcf_tune_load(lcf_context* ctx, const char* path) {
+    if (!ctx || !path) return LCF_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return LCF_ERR_INVALID_ARG;
+    std::map<std::string, TuneChoice> got;
+    char key[128];
+    int chunk = 0, rows = 0;
+    bool ok = true;
+    for (;;) {
+        const int n = std::fscanf(f, "%127s %d %d", key, &chunk, &rows);
+        if (n == EOF) break;
+        if (n != 3 || chunk < PIX || chunk > (1 << 20) || rows < 1 || rows > TROWS) { ok = false; break; }
+        got[key] = TuneChoice{chunk, rows};
+    }
+    std::fclose(f);
+    if (!ok) return LCF_ERR_INVALID_ARG;
+    for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
+    drop_graphs(ctx);
     return LCF_OK;
 }
 

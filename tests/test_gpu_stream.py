@@ -82,3 +82,41 @@ def test_stream_full_size_one_call(lcf, ctx):
         torch.cuda.synchronize()
         assert torch.equal(ios[k], io1) and torch.equal(pds[k], pd1), k
         assert torch.isfinite(pds[k]).all()
+
+
+def test_autotune_choice_roundtrip(lcf, ctx, tmp_path):
+    """Autotuned plans give the same filter (the tile height does not change the
+    arithmetic; the split-K chunk only moves FP32 rounding), and the stored
+    choices reproduce the tuned run bitwise in a fresh context."""
+    iq, mask = synth.make_packet(synth.spec_clinical(3))
+    dev = torch.from_numpy(iq).cuda()
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    io0, pd0, _ = ctx.filter(dev, 8, 8, thr)
+    tuned = lcf.Context(0, autotune=1)
+    try:
+        io1, pd1, _ = tuned.filter(dev, 8, 8, thr)
+        torch.cuda.synchronize()
+        assert tuned.sync() == 0
+        path = str(tmp_path / "tune.txt")
+        tuned.tune_save(path)
+        lines = open(path).read().split("\n")
+        say(f"[autotune] {lines[0]}")
+        assert len([x for x in lines if x.strip()]) == 1 and len(lines[0].split()) == 3
+        e_io = float(torch.linalg.vector_norm(io1 - io0) / torch.linalg.vector_norm(io0))
+        e_pd = float(torch.max(torch.abs(pd1 - pd0) / pd0))
+        assert e_io <= 1e-5 and e_pd <= 1e-4, (e_io, e_pd)
+        again = lcf.Context(0)
+        try:
+            again.tune_load(path)
+            io2, pd2, _ = again.filter(dev, 8, 8, thr)
+            torch.cuda.synchronize()
+            assert torch.equal(io1, io2) and torch.equal(pd1, pd2)
+            bad = tmp_path / "bad.txt"
+            bad.write_text("ntp128_p0_s0_S6_N13 1024\n")
+            with pytest.raises(lcf.LcfError) as ei:
+                again.tune_load(str(bad))
+            assert ei.value.status == 1
+        finally:
+            again.close()
+    finally:
+        tuned.close()
