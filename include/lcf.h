@@ -139,9 +139,9 @@ typedef struct {
 #define LCF_OPT_AUTOTUNE     6  /* 1 = before the first call of a launch-group class (padded
                                    Nt, precision, schedule, log2 subset count, log2 mean
                                    box size) with no stored choice, time every split-K
-                                   chunk {512..4096 px} x reprojection tile {1, 2 rows}
+                                   chunk {512..4096 px} x reprojection tile {2, 4 rows}
                                    on the call's own packets and keep the fastest
-                                   (default 0: 1024 px, 2 rows up to 128 frames). Tuning
+                                   (default 0: 1024 px, 4 rows up to 128 frames). Tuning
                                    is skipped while the stream is being captured.          */
 
 /* Kernel stages reported by lcf_stage_time. */

@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
 }
 
 // ------------------------------------------------------------------ reprojection
-// One work-group per tile of TR image rows x PIX pixels (output-centric
+// One work-group per tile of TR image rows x TW pixels (output-centric
 // gather, no atomics). For every covering subset d in ascending order:
 //   y  = s V_r                      (FP64 partial sums, split over t, rounded to FP32)
 //   c' = s - y V_r^H                (FP64, then rounded to the GEMM operand)
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
 // operands are shared in that XCD's L2).
 template <int NTP, int PREC, int TR>
 struct RpCfg {
-    static constexpr int TP = TR * PIX;                               // pixels per tile
+    static constexpr int TP = TR * TW;                                // pixels per tile
     static constexpr int NRT = TP / 16;                               // MFMA row tiles
     static constexpr int NTE = NTP + REXT;
     static constexpr int NTEP = (NTE + 31) / 32 * 32;                 // BF16: K per part, padded
@@ -278,9 +278,11 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
     const int nt = pk.nt, nx = pk.nx;
     const long npix = (long)pk.ny * pk.nx;
     const int npx = td.x1 - td.x0 + 1;
-    // tile pixel p = row (p / PIX) of the tile, column x0 + p % PIX
-    auto in_tile = [&](int p) { return (p / PIX) < td.nrow && (p % PIX) < npx; };
-    auto pix_off = [&](int p) { return (long)(td.y + p / PIX) * nx + td.x0 + p % PIX; };
+    // tile pixel p = row (p / TW) of the tile, column x0 + p % TW; MFMA row tile
+    // a is tile row a
+    static_assert(TW == 16, "one MFMA row tile per tile row");
+    auto in_tile = [&](int p) { return (p / TW) < td.nrow && (p % TW) < npx; };
+    auto pix_off = [&](int p) { return (long)(td.y + p / TW) * nx + td.x0 + p % TW; };
     // pixel pp of the tile is handled by the G consecutive lanes part = 0..G-1,
     // frames t = part + G i
     const int pp = tid / G, part = tid % G;
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         }
     };
     auto window = [&](const SubsetDesc& sd, int p) -> double {
-        const int y = td.y + p / PIX, x = td.x0 + p % PIX;
+        const int y = td.y + p / TW, x = td.x0 + p % TW;
         if (!in_tile(p) || y < sd.y0 || y > sd.y1 || x < sd.x0 || x > sd.x1) return 0.0;
         return sd.flat ? 1.0 : ws.wtab[sd.wy_off + y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
     };
@@ -328,17 +330,66 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
 #pragma unroll
     for (int i = 0; i < NRT * 4; ++i) pd_acc[i] = 0.f;
 
+    // V_r of the next covering subset is loaded into registers while the
+    // current one is processed (element e = tid + NTHR i of [t][j]).
+    constexpr int VPT = (NTP * RMAX + NTHR - 1) / NTHR;
+    double2 vnext[VPT];
+    auto vload = [&](int ci) {
+        const int s = ws.cover[td.cov_off + ci];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = tid + NTHR * i;
+            vnext[i] = e < NTP * RMAX ? ws.vr64[(long)s * NTP * RMAX + e] : make_double2(0.0, 0.0);
+        }
+    };
+    // [P; M] fragments of the first K iterations are loaded before the operand
+    // rows of a subset are formed (they do not depend on them).
+    constexpr int KIT = 2 * NTEP / 32;
+    constexpr int KPF = (PREC && CTW <= 2 && KIT >= 2) ? 2 : 0;
+    auto bload = [&](const uint16_t* planes, int k, int m, u32x4& bh, u32x4& bl) {
+        const int ct = wave * CTW + m;
+        bh = u32x4{0u, 0u, 0u, 0u};
+        bl = u32x4{0u, 0u, 0u, 0u};
+        if (ct < C::CT) {
+            const int kq = 32 * k + 8 * g;
+            const bool impart = 32 * k >= NTEP;
+            const int kk = impart ? kq - NTEP : kq;
+            const int n = ct * 16 + col;
+            const bool outim = n >= NTP;
+            const int nn = outim ? n - NTP : n;
+            // B^T row n: re output [P_re | -P_im], im output [P_im | P_re]
+            const int plane = (outim != impart) ? 2 : 0;
+            const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
+            const uint16_t* src = planes + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
+            bh = *reinterpret_cast<const u32x4*>(src);
+            bl = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { bh[q] ^= sgn; bl[q] ^= sgn; }
+        }
+    };
+    if (td.cov_cnt > 0) vload(0);
+
     for (int ci = 0; ci < td.cov_cnt; ++ci) {
         const int s = ws.cover[td.cov_off + ci];
         const SubsetDesc sd = ws.sub[s];
         const int r = ws.rank[s];
         const float alpha = (float)ws.alpha[s];
+        const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
+        u32x4 pbh[2][CTW], pbl[2][CTW];
+        if (PREC) {
+#pragma unroll
+            for (int k = 0; k < KPF; ++k)
+#pragma unroll
+                for (int m = 0; m < CTW; ++m) bload(planes, k, m, pbh[k][m], pbl[k][m]);
+        }
         __syncthreads();
-        for (int e = tid; e < NTP * RMAX; e += NTHR) {
-            const int t = e / RMAX, j = e % RMAX;
-            vrs[j * NTP + t] = ws.vr64[(long)s * NTP * RMAX + e];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = tid + NTHR * i;
+            if (e < NTP * RMAX) vrs[(e % RMAX) * NTP + e / RMAX] = vnext[i];
         }
         if (tid < TP) wd[tid] = (float)window(sd, tid);
+        if (ci + 1 < td.cov_cnt) vload(ci + 1);
         __syncthreads();
         // y = s V_r (FP64 partial sums over this thread's frames, then reduced over
         // the pixel's G lanes; every lane ends with the full sum), rounded to FP32
@@ -394,8 +445,41 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (PREC) {
-            const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
+        if (PREC && KPF > 0) {
+            // ping-pong: fragments of K iterations k, k+1 are in registers while
+            // those of k+2, k+3 load (KIT = 2 NTEP / 32 is even)
+            static_assert(KIT % 2 == 0, "K iterations come in pairs");
+#pragma unroll 1
+            for (int k = 0; k < KIT; k += 2) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int kq = 32 * (k + h) + 8 * g;
+                    bf16x8 xh[NRT], xl[NRT];
+#pragma unroll
+                    for (int a = 0; a < NRT; ++a) {
+                        xh[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + (16 * a + col) * LDK + kq));
+                        xl[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Al + (16 * a + col) * LDK + kq));
+                    }
+#pragma unroll
+                    for (int m = 0; m < CTW; ++m) {
+                        if (wave * CTW + m < C::CT) {
+                            const bf16x8 xbh = __builtin_bit_cast(bf16x8, pbh[h][m]);
+                            const bf16x8 xbl = __builtin_bit_cast(bf16x8, pbl[h][m]);
+#pragma unroll
+                            for (int a = 0; a < NRT; ++a) {
+                                acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbh, acc[a][m], 0, 0, 0);
+                                acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbl, acc[a][m], 0, 0, 0);
+                                acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[a], xbh, acc[a][m], 0, 0, 0);
+                            }
+                        }
+                    }
+                    if (k + h + 2 < KIT) {
+#pragma unroll
+                        for (int m = 0; m < CTW; ++m) bload(planes, k + h + 2, m, pbh[h][m], pbl[h][m]);
+                    }
+                }
+            }
+        } else if (PREC) {
             constexpr int KUNR = NTP > 128 ? 1 : 2;      // register budget of the widest subsets
 #pragma unroll KUNR
             for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
@@ -537,19 +621,19 @@ static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t 
         else hipLaunchKernelGGL((k_projector<NTP, 1>), dim3(ws.S), dim3(256), 0, st, ws);
     } else if (ws.ntiles > 0) {
         const int grid = (ws.ntiles + 7) / 8 * 8;      // multiple of 8 for the XCD mapping
-        if constexpr (trows_max(NTP) >= 2) {
-            if (ws.trows == 2) {
+        if constexpr (trows_max(NTP) >= 4) {
+            if (ws.trows == 4) {
                 if (prec == 0)
-                    hipLaunchKernelGGL((k_reproj<NTP, 0, 2>), dim3(grid), dim3(RpCfg<NTP, 0, 2>::NTHR), 0, st, ws);
+                    hipLaunchKernelGGL((k_reproj<NTP, 0, 4>), dim3(grid), dim3(RpCfg<NTP, 0, 4>::NTHR), 0, st, ws);
                 else
-                    hipLaunchKernelGGL((k_reproj<NTP, 1, 2>), dim3(grid), dim3(RpCfg<NTP, 1, 2>::NTHR), 0, st, ws);
+                    hipLaunchKernelGGL((k_reproj<NTP, 1, 4>), dim3(grid), dim3(RpCfg<NTP, 1, 4>::NTHR), 0, st, ws);
                 return;
             }
         }
         if (prec == 0)
-            hipLaunchKernelGGL((k_reproj<NTP, 0, 1>), dim3(grid), dim3(RpCfg<NTP, 0, 1>::NTHR), 0, st, ws);
+            hipLaunchKernelGGL((k_reproj<NTP, 0, 2>), dim3(grid), dim3(RpCfg<NTP, 0, 2>::NTHR), 0, st, ws);
         else
-            hipLaunchKernelGGL((k_reproj<NTP, 1, 1>), dim3(grid), dim3(RpCfg<NTP, 1, 1>::NTHR), 0, st, ws);
+            hipLaunchKernelGGL((k_reproj<NTP, 1, 2>), dim3(grid), dim3(RpCfg<NTP, 1, 2>::NTHR), 0, st, ws);
     }
 }
 

@@ -14,11 +14,12 @@ constexpr int RMAX = 8;
 constexpr int REXT = 16;
 // Pixels per LDS batch in the Gram and reprojection kernels.
 constexpr int PIX = 32;
-// Image rows per reprojection tile (a tile is trows x PIX pixels): 1 or 2, the
-// latter only up to 128 frames (the accumulators of wider subsets fill the
-// register file). Chosen per launch group (default, or by the autotuner).
-constexpr int TROWS = 2;
-__host__ __device__ constexpr int trows_max(int ntp) { return ntp <= 128 ? TROWS : 1; }
+// Reprojection tiles are TW pixels wide (one MFMA row tile per image row) and
+// 2 or 4 rows high: 4 only up to 128 frames (the accumulators of wider subsets
+// fill the register file). Chosen per launch group (default, or by the autotuner).
+constexpr int TW = 16;
+constexpr int TROWS = 4;
+__host__ __device__ constexpr int trows_max(int ntp) { return ntp <= 128 ? 4 : 2; }
 // Pixels per Gram work item (split-K chunk); several LDS batches each.
 constexpr int CHUNK = 1024;
 
@@ -70,7 +71,7 @@ struct Workspace {
     const int* chunk_begin;   // [S+1] first chunk of each subset
     const TileDesc* tiles;
     int ntiles;
-    int trows;          // rows per reprojection tile (1 or 2)
+    int trows;          // rows per reprojection tile (2 or 4)
     const int* cover;
     const PacketDesc* pkts;
     double* wtab;       // window factor pool

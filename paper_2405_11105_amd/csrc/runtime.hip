@@ -114,7 +114,7 @@ struct PacketIn {
 struct Plan {
     int ntp = 0, nt_max = 0;
     int chunk = CHUNK;      // split-K chunk of the Gram passes (box pixels)
-    int trows = 1;          // image rows per reprojection tile
+    int trows = 2;          // image rows per reprojection tile (2 or 4)
     std::vector<SubsetDesc> sub;
     std::vector<ChunkDesc> chunks;
     std::vector<int> chunk_begin;
@@ -172,26 +172,54 @@ void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int
                 pl.chunks.push_back(ChunkDesc{sidx, q, std::min(s.neff, q + pl.chunk)});
             pl.sub.push_back(s);
         }
-        // reprojection tiles: trows rows x PIX pixels, with covering subsets
+        // Reprojection tiles of trows rows x TW pixels with their covering subsets.
+        // The tile origin is shifted (per axis, 0..size-1) so that as few box
+        // edges as possible fall inside tiles: with grid windows a tile's
+        // covering count is (#window rows over its rows) x (#window columns
+        // over its columns), so each axis is chosen on its own.
         const int last = (int)pl.sub.size();
         const int trows = pl.trows;
-        for (int y = 0; y < g.ny; y += trows)
-            for (int x0 = 0; x0 < g.nx; x0 += PIX) {
+        auto best_origin = [&](int n, int size, int ngrid, int stride, bool xaxis) {
+            int best = 0;
+            long best_cost = -1;
+            for (int o = 0; o < size; ++o) {
+                long cost = 0;
+                for (int a0 = o - size; a0 < n; a0 += size) {
+                    const int lo = std::max(0, a0), hi = std::min(n - 1, a0 + size - 1);
+                    if (lo > hi) continue;
+                    for (int j = 0; j < ngrid; ++j) {
+                        const SubsetDesc& sd = pl.sub[first + j * stride];
+                        const int b0 = xaxis ? sd.x0 : sd.y0, b1 = xaxis ? sd.x1 : sd.y1;
+                        cost += (hi >= b0 && lo <= b1);
+                    }
+                }
+                if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = o; }
+            }
+            return best;
+        };
+        const int ox = best_origin(g.nx, TW, g.gx, 1, true);
+        const int oy = best_origin(g.ny, trows, g.gy, g.gx, false);
+        for (int ys = oy - trows; ys < g.ny; ys += trows) {
+            const int ty0 = std::max(0, ys), ty1 = std::min(g.ny - 1, ys + trows - 1);
+            if (ty0 > ty1) continue;
+            for (int xs = ox - TW; xs < g.nx; xs += TW) {
+                const int tx0 = std::max(0, xs), tx1 = std::min(g.nx - 1, xs + TW - 1);
+                if (tx0 > tx1) continue;
                 TileDesc t;
                 t.pkt = (int)pi;
-                t.y = y;
-                t.nrow = std::min(trows, g.ny - y);
-                t.x0 = x0;
-                t.x1 = std::min(g.nx - 1, x0 + PIX - 1);
+                t.y = ty0;
+                t.nrow = ty1 - ty0 + 1;
+                t.x0 = tx0;
+                t.x1 = tx1;
                 t.cov_off = (int)pl.cover.size();
-                const int y1 = y + t.nrow - 1;
                 for (int s = first; s < last; ++s) {
                     const SubsetDesc& sd = pl.sub[s];
-                    if (y1 >= sd.y0 && y <= sd.y1 && t.x1 >= sd.x0 && t.x0 <= sd.x1) pl.cover.push_back(s);
+                    if (ty1 >= sd.y0 && ty0 <= sd.y1 && tx1 >= sd.x0 && tx0 <= sd.x1) pl.cover.push_back(s);
                 }
                 t.cov_cnt = (int)pl.cover.size() - t.cov_off;
                 pl.tiles.push_back(t);
             }
+        }
     }
     pl.chunk_begin.push_back((int)pl.chunks.size());
     pl.wtab_len = (size_t)wtab;
@@ -656,11 +684,11 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
     const int saved_timing = c->timing;
     c->timing = 0;
     float best = 0.f;
-    TuneChoice choice{CHUNK, 1};
+    TuneChoice choice{CHUNK, 2};
     lcf_status res = LCF_OK;
     int ntp = 0;
     for (int i : idx) ntp = std::max(ntp, ntp_class(in[i].g.nt));
-    for (int tr = 1; tr <= trows_max(ntp) && res == LCF_OK; ++tr) {
+    for (int tr = 2; tr <= trows_max(ntp) && res == LCF_OK; tr += 2) {
         for (int ch : chunks) {
             Plan pl;
             build_plan(pl, in, idx, thr->pd_mode, ch, tr);
@@ -707,7 +735,7 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
             tit = c->tuned.find(tkey);
         }
         if (tit != c->tuned.end()) {
-            const int tr = std::min(std::max(tit->second.trows, 1), trows_max(kv.first));
+            const int tr = std::min(tit->second.trows, trows_max(kv.first));
             if (tit->second.chunk != pl.chunk || tr != pl.trows) {
                 Plan tuned;
                 build_plan(tuned, in, kv.second, thr->pd_mode, tit->second.chunk, tr);
@@ -1075,7 +1103,7 @@ lcf_status lcf_tune_load(lcf_context* ctx, const char* path) {
     for (;;) {
         const int n = std::fscanf(f, "%127s %d %d", key, &chunk, &rows);
         if (n == EOF) break;
-        if (n != 3 || chunk < PIX || chunk > (1 << 20) || rows < 1 || rows > TROWS) { ok = false; break; }
+        if (n != 3 || chunk < PIX || chunk > (1 << 20) || (rows != 2 && rows != 4)) { ok = false; break; }
         got[key] = TuneChoice{chunk, rows};
     }
     std::fclose(f);
