@@ -223,11 +223,17 @@ def main():
     neff = _neff(ny, nx, gy, gx)
     sum_neff = float(sum(neff)) * len(iqs)
     pairs = nt * (nt - 1) / 2.0
+    # Algorithmic work per launch. Split BF16 issues three BF16 MFMA products
+    # (hi hi, hi lo, lo hi) per logical multiply-add, so its GEMM work is counted
+    # as 3x the logical flops against the BF16 peak.
+    r_mean = float(np.mean(ranks))
     work = {
-        "gram1": ("mfma", 4.0 * sum_neff * nt * nt, PEAK["bf16_mfma"]),
-        "gram2": ("mfma", 4.0 * sum_neff * (nt + 16) ** 2, PEAK["bf16_mfma"]),
-        "reproj": ("mfma", 8.0 * sum_neff * nt * (nt + 16), PEAK["bf16_mfma"]),
-        "jacobi": ("alu", float(np.sum(sweeps)) * len(iqs) * pairs * 36.0 * nt, PEAK["fp64"]),
+        "gram1": ("mfma", 3.0 * 4.0 * sum_neff * nt * nt, PEAK["bf16_mfma"]),
+        "gram2": ("mfma", 3.0 * 4.0 * sum_neff * (nt + r_mean) ** 2, PEAK["bf16_mfma"]),
+        "reproj": ("mfma", 3.0 * 8.0 * sum_neff * nt * (nt + r_mean), PEAK["bf16_mfma"]),
+        # Householder reduction (16/3 nt^3 real flops for a complex Hermitian
+        # matrix) plus the back-transformation of nt vectors (8 nt^3)
+        "jacobi": ("alu", (16.0 / 3.0 + 8.0) * nt ** 3 * len(neff) * len(iqs), PEAK["fp64"]),
     }
     timed = {k: v for k, v in stages.items() if v[1]}
     dom = max(timed, key=lambda k: timed[k][0])

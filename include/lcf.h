@@ -124,6 +124,8 @@ typedef struct {
 #define LCF_FLAG_NONFINITE     2  /* NaN/Inf in the covariance                              */
 #define LCF_FLAG_NO_CONVERGE   4  /* Jacobi reached max sweeps                               */
 #define LCF_FLAG_MLP_FALLBACK  8  /* MLP input out of range: rule weights used instead      */
+#define LCF_FLAG_EVD_JACOBI   16  /* near-degenerate spectrum: EVD by Jacobi instead of the
+                                     tridiagonal solver (informational)                   */
 
 /* Context options (lcf_set_option). */
 #define LCF_OPT_SCHEDULE     1  /* 0 = batched (all subsets per stage in one launch, default);
@@ -143,6 +145,13 @@ typedef struct {
                                    on the call's own packets and keep the fastest
                                    (default 0: 1024 px, 4 rows up to 128 frames). Tuning
                                    is skipped while the stream is being captured.          */
+
+#define LCF_OPT_EVD          7  /* subset EVD (Eq. 2) up to 128 frames: 0 = Householder
+                                   tridiagonal reduction, multisection eigenvalues and
+                                   twisted-factorisation eigenvectors, with the Jacobi
+                                   solver for subsets whose eigenvalues are closer than
+                                   1e-12 lambda_1 (flag LCF_FLAG_EVD_JACOBI; default);
+                                   1 = FP64 one-sided Jacobi for every subset           */
 
 /* Kernel stages reported by lcf_stage_time. */
 typedef enum {

@@ -603,7 +603,8 @@ __device__ __forceinline__ void jac_step8(JCols<RPL>& c, int lane, double tol, i
 }
 
 template <int RPL, int NW>
-__global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sweeps) {
+__global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sweeps, int only_flag) {
+    if (only_flag != 0 && (ws.flags[blockIdx.x] & only_flag) == 0) return;   // not selected: whole block exits
     constexpr int ROWS = 64 * RPL;
     constexpr int SLOT = 8 * ROWS;                     // double2 per half-block
     __shared__ double2 xch[(NW + 1) * SLOT];
@@ -730,6 +731,375 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
     }
     __syncthreads();
     jacobi_finish(Gout, nt, ntp, ws.lam + (long)s * ntp, ws.bmat + (long)s * ntp * ntp, ntp, true);
+}
+
+
+// ------------------------------------------------------------------ tridiagonal EVD
+// Subset EVD (Eq. 2) through a real symmetric tridiagonal matrix, for padded
+// sizes up to 128 (the matrix lives in VGPRs as in k_jacobi_reg: wave w holds
+// columns 16 w .. 16 w + 15, lane l rows l + 64 i):
+//  1. Householder reduction B = Q T Q^H, Q = H_0 .. H_{n-3}, H_j = I - tau v v^H,
+//     with the two-sided update A <- A - v q^H - q v^H (p = tau A v,
+//     q = p - (tau / 2)(v^H p) v); the vectors go to scratch.
+//  2. T = D T_r D^H with a diagonal unitary D makes the off-diagonal real >= 0.
+//  3. Eigenvalues of T_r by multisection of Sturm counts (4 lanes per
+//     eigenvalue, 5 sub-intervals per round), sorted descending by construction.
+//  4. Each eigenvector of T_r from a twisted factorisation
+//     (T_r - lambda I) = N_r Delta_r N_r^T at the twist index r of smallest
+//     |gamma_r|, one lane per eigenvalue (one O(n) solve, no iteration).
+//  5. Eigenvectors of B: y = Q D z, the reflectors applied in reverse order.
+// A subset whose eigenvalues are closer than 1e-12 lambda_1 (where such vectors
+// would lose orthogonality) keeps its B and is flagged for the Jacobi kernel.
+constexpr int FLAG_EVD_FALLBACK = 16;
+
+template <int RPL, int NW>
+__global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
+    constexpr int N = 16 * NW;             // padded size held (columns)
+    constexpr int NTHR = 64 * NW;
+    static_assert(64 * RPL >= N, "rows per lane cover the padded size");
+    __shared__ double2 xsh[N];             // column j
+    __shared__ double2 vsh[N];             // Householder vector v_j
+    __shared__ double2 psh[NW * N];        // per-wave partials of A v
+    __shared__ double2 qsh[N];             // p = tau A v, then q
+    __shared__ double red[2 * NW];
+    __shared__ double dsh[N], esh[N], e2sh[N];
+    __shared__ double2 phs[N];             // D
+    __shared__ double lamsh[N], insh[N];
+    __shared__ double bnd[2];
+    __shared__ int cluster;
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nt = ws.sub[s].nt;
+    double2* Bm = ws.bmat + (long)s * N * N;
+    double2* H = ws.wvec + (long)s * N * N;                 // Householder vectors, tau in element 0
+    double* Dm = reinterpret_cast<double*>(ws.pmat + (long)s * N * N);   // [i][k]
+    double* Dp = Dm + N * N;                                // [i][k], then z
+    if (tid == 0) cluster = 0;
+
+    double2 A[16][RPL];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int col = 16 * wave + c;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            A[c][i] = (row < nt && col < nt) ? cconj(Bm[(long)col * N + row]) : make_double2(0.0, 0.0);
+        }
+    }
+
+    // ---- 1. Householder reduction
+    for (int j = 0; j + 2 < nt; ++j) {
+        const int jw = j >> 4, jc = j & 15;
+        const int wstart = (j + 1) >> 4;          // waves below hold only finished columns
+        if (wave == jw) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                double2 x = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c == jc) x = A[c][i];
+                if (row < N) xsh[row] = x;
+            }
+        }
+        __syncthreads();
+        double s2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row > j + 1 && row < nt) s2 += cabs2(xsh[row]);
+        }
+        s2 = wave_sum(s2);
+        const double2 x0 = xsh[j + 1];
+        const double ax0 = sqrt(cabs2(x0));
+        const double alpha = sqrt(s2 + ax0 * ax0);
+        const double2 ph = ax0 > 0.0 ? cscale(x0, 1.0 / ax0) : make_double2(1.0, 0.0);
+        const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+        if (tid < N) {
+            const double2 v = tid <= j ? make_double2(0.0, 0.0)
+                                       : (tid == j + 1 ? cadd(x0, cscale(ph, alpha)) : xsh[tid]);
+            vsh[tid] = v;
+            H[(long)j * N + tid] = tid == 0 ? make_double2(tau, 0.0) : v;   // row 0 of v_j is zero: holds tau
+        }
+        if (tid == 0) {
+            dsh[j] = xsh[j].x;
+            phs[j] = cscale(ph, -alpha);                               // complex e_j for now
+        }
+        __syncthreads();
+        // partial A v over this wave's columns
+        if (wave >= wstart) {
+            double2 acc[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) acc[i] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const double2 vc = vsh[16 * wave + c];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    acc[i].x = fma(A[c][i].x, vc.x, fma(-A[c][i].y, vc.y, acc[i].x));
+                    acc[i].y = fma(A[c][i].x, vc.y, fma(A[c][i].y, vc.x, acc[i].y));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                if (row < N) psh[wave * N + row] = acc[i];
+            }
+        }
+        __syncthreads();
+        // p = tau sum_w partials, and v^H p
+        double kr = 0.0, ki = 0.0;
+        if (tid < N) {
+            double2 p = make_double2(0.0, 0.0);
+            for (int w = wstart; w < NW; ++w) p = cadd(p, psh[w * N + tid]);
+            p = cscale(p, tau);
+            qsh[tid] = p;
+            const double2 v = vsh[tid];
+            kr = fma(v.x, p.x, v.y * p.y);                             // conj(v) p
+            ki = fma(v.x, p.y, -v.y * p.x);
+        }
+        if (tid < ((N + 63) & ~63)) {
+            kr = wave_sum(kr);
+            ki = wave_sum(ki);
+            if (lane == 0) { red[2 * wave] = kr; red[2 * wave + 1] = ki; }
+        }
+        __syncthreads();
+        // q = p - (tau / 2) (v^H p) v
+        if (tid < N) {
+            double2 K = make_double2(0.0, 0.0);
+            for (int w = 0; w < (N + 63) / 64; ++w) K = cadd(K, make_double2(red[2 * w], red[2 * w + 1]));
+            K = cscale(K, 0.5 * tau);
+            qsh[tid] = csub(qsh[tid], cmul(K, vsh[tid]));
+        }
+        __syncthreads();
+        // A -= v q^H + q v^H
+        if (wave >= wstart) {
+            double2 vr[RPL], qr[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                vr[i] = row < N ? vsh[row] : make_double2(0.0, 0.0);
+                qr[i] = row < N ? qsh[row] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int col = 16 * wave + c;
+                const double2 vc = vsh[col], qc = qsh[col];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    double ax = A[c][i].x, ay = A[c][i].y;
+                    ax = fma(-vr[i].x, qc.x, fma(-vr[i].y, qc.y, ax));
+                    ay = fma(-vr[i].y, qc.x, fma(vr[i].x, qc.y, ay));
+                    ax = fma(-qr[i].x, vc.x, fma(-qr[i].y, vc.y, ax));
+                    ay = fma(-qr[i].y, vc.x, fma(qr[i].x, vc.y, ay));
+                    A[c][i] = make_double2(ax, ay);
+                }
+            }
+        }
+    }
+    // last 2 x 2 block: d_{nt-2}, d_{nt-1}, e_{nt-2}
+    {
+        const int r0 = nt - 2, r1 = nt - 1;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int col = 16 * wave + c;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                if (row == r0 && col == r0) dsh[r0] = A[c][i].x;
+                if (row == r1 && col == r1) dsh[r1] = A[c][i].x;
+                if (row == r1 && col == r0) phs[r0] = A[c][i];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- 2. real tridiagonal: |e_j| and the phases D (d_0 = 1, d_{j+1} = d_j e_j / |e_j|)
+    if (tid == 0) {
+        double2 d = make_double2(1.0, 0.0);
+        double emax = 0.0, lo = 1e300, hi = -1e300;
+        for (int j = 0; j < nt; ++j) {
+            double2 e = j + 1 < nt ? phs[j] : make_double2(0.0, 0.0);
+            const double ae = sqrt(cabs2(e));
+            phs[j] = d;
+            if (j + 1 < nt) {
+                esh[j] = ae;
+                e2sh[j] = ae * ae;
+                emax = fmax(emax, ae * ae);
+                d = ae > 0.0 ? cmul(d, cscale(e, 1.0 / ae)) : d;
+            }
+            const double rad = (j > 0 ? esh[j - 1] : 0.0) + (j + 1 < nt ? ae : 0.0);
+            lo = fmin(lo, dsh[j] - rad);
+            hi = fmax(hi, dsh[j] + rad);
+        }
+        const double margin = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+        bnd[0] = lo - margin;
+        bnd[1] = hi + margin;
+        red[0] = 1e-290 * fmax(1.0, emax);                             // pivmin
+    }
+    __syncthreads();
+    const double pivmin = red[0];
+    // ---- 3. eigenvalues by multisection (lanes 4k .. 4k+3 for the k-th largest)
+    {
+        const int k = tid >> 2, m = tid & 3;
+        const int target = nt - 1 - k;                                 // index among ascending
+        double a = bnd[0], b = bnd[1];
+        for (int it = 0; it < 28; ++it) {
+            const double x = a + (double)(m + 1) * 0.2 * (b - a);
+            int cnt = 0;
+            if (k < nt) {
+                double q = dsh[0] - x;
+                cnt = q < 0.0;
+                for (int i = 1; i < nt; ++i) {
+                    if (fabs(q) < pivmin) q = -pivmin;
+                    q = (dsh[i] - x) - e2sh[i - 1] * rcp_nr(q);
+                    cnt += q < 0.0;
+                }
+            }
+            const int base = lane & ~3;
+            double na = a, nb = b;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int cu = __shfl(cnt, base + u, 64);
+                const double xu = a + (double)(u + 1) * 0.2 * (b - a);
+                if (cu <= target) na = xu;
+            }
+#pragma unroll
+            for (int u = 3; u >= 0; --u) {
+                const int cu = __shfl(cnt, base + u, 64);
+                const double xu = a + (double)(u + 1) * 0.2 * (b - a);
+                if (cu > target) nb = xu;
+            }
+            a = na;
+            b = nb;
+        }
+        if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
+    }
+    __syncthreads();
+    // ---- 4. eigenvectors of T_r by twisted factorisation (lane k)
+    if (tid < nt) {
+        const int k = tid;
+        const double lam = lamsh[k];
+        if (k + 1 < nt && lamsh[k] - lamsh[k + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
+        double q = dsh[nt - 1] - lam;
+        Dm[(long)(nt - 1) * N + k] = q;
+        for (int i = nt - 2; i >= 0; --i) {
+            if (fabs(q) < pivmin) q = -pivmin;
+            q = (dsh[i] - lam) - e2sh[i] * rcp_nr(q);
+            Dm[(long)i * N + k] = q;
+        }
+        double p = dsh[0] - lam;
+        Dp[k] = p;
+        int r = 0;
+        double g = fabs(Dm[k]);
+        for (int i = 0; i + 1 < nt; ++i) {
+            if (fabs(p) < pivmin) p = -pivmin;
+            p = (dsh[i + 1] - lam) - e2sh[i] * rcp_nr(p);
+            Dp[(long)(i + 1) * N + k] = p;
+            const double gam = p + Dm[(long)(i + 1) * N + k] - (dsh[i + 1] - lam);
+            if (fabs(gam) < g) { g = fabs(gam); r = i + 1; }
+        }
+        // z overwrites Dp: below r from Dp, above r from Dm
+        double z = 1.0, nrm = 1.0;
+        Dp[(long)r * N + k] = 1.0;
+        for (int i = r - 1; i >= 0; --i) {
+            double d = Dp[(long)i * N + k];
+            if (fabs(d) < pivmin) d = -pivmin;
+            z = -esh[i] * rcp_nr(d) * z;
+            Dp[(long)i * N + k] = z;
+            nrm += z * z;
+        }
+        z = 1.0;
+        for (int i = r; i + 1 < nt; ++i) {
+            double d = Dm[(long)(i + 1) * N + k];
+            if (fabs(d) < pivmin) d = -pivmin;
+            z = -esh[i] * rcp_nr(d) * z;
+            Dp[(long)(i + 1) * N + k] = z;
+            nrm += z * z;
+        }
+        insh[k] = rsq_nr(nrm);
+    }
+    __syncthreads();
+    if (cluster) {                  // leave B for the Jacobi kernel
+        if (tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
+        return;
+    }
+    // ---- 5. y = Q D z in registers, reflectors in reverse order
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int col = 16 * wave + c;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            A[c][i] = (row < nt && col < nt) ? cscale(phs[row], Dp[(long)row * N + col] * insh[col])
+                                             : make_double2(0.0, 0.0);
+        }
+    }
+    for (int j = nt - 3; j >= 0; --j) {
+        const double tauj = H[(long)j * N].x;
+        double2 vr[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            vr[i] = (row > j && row < N) ? H[(long)j * N + row] : make_double2(0.0, 0.0);
+        }
+        // w_c = v^H y_c for this wave's 16 columns: lane partials, then a
+        // transposed reduction leaving value (l >> 1) in lane l
+        double v32[32];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            double ar = 0.0, ai = 0.0;                                 // conj(v) y
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                ar = fma(vr[i].x, A[c][i].x, fma(vr[i].y, A[c][i].y, ar));
+                ai = fma(vr[i].x, A[c][i].y, fma(-vr[i].y, A[c][i].x, ai));
+            }
+            v32[2 * c] = ar;
+            v32[2 * c + 1] = ai;
+        }
+        double w16[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) w16[t] = swap_sum<32>(v32[t], v32[t + 16]);
+        double w8[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) w8[t] = swap_sum<16>(w16[t], w16[t + 8]);
+        const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0, h2 = (lane & 2) != 0;
+        double w4[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double a0 = w8[t], a1 = w8[t + 4];
+            w4[t] = (h8 ? a1 : a0) + dpp_d<0x140>(h8 ? a0 : a1);
+        }
+        double w2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const double a0 = w4[t], a1 = w4[t + 2];
+            w2[t] = (h4 ? a1 : a0) + dpp_d<0x141>(h4 ? a0 : a1);
+        }
+        double tot = (h2 ? w2[1] : w2[0]) + dpp_d<0x4E>(h2 ? w2[0] : w2[1]);
+        tot += dpp_d<0xB1>(tot);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const double twx = tauj * rdl(tot, 4 * c), twy = tauj * rdl(tot, 4 * c + 2);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {                            // y -= v (tau w)
+                const double ax = fma(-vr[i].x, twx, fma(vr[i].y, twy, A[c][i].x));
+                const double ay = fma(-vr[i].x, twy, fma(-vr[i].y, twx, A[c][i].y));
+                A[c][i] = make_double2(ax, ay);
+            }
+        }
+    }
+    // write eigenvectors (column k contiguous) and eigenvalues
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int col = 16 * wave + c;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row < N) Bm[(long)col * N + row] = A[c][i];
+        }
+    }
+    if (tid < nt) ws.lam[(long)s * N + tid] = lamsh[tid];
+    if (tid == 0) ws.sweeps[s] = 0;
 }
 
 // Normalise columns, sort by norm descending, write eigenvalues and vectors.
@@ -863,19 +1233,25 @@ hipError_t launch_assemble(const Workspace& ws, hipStream_t st) {
 
 static int max_nt(const Workspace& ws) { return ws.ntp; }
 
-hipError_t launch_jacobi(const Workspace& ws, int max_sweeps, int nt_max, hipStream_t st) {
+hipError_t launch_jacobi(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
     (void)max_nt;
-    // register-resident variants by padded size; the LDS / global versions beyond 128
+    // Up to 128 frames: the tridiagonal solver (method 0), with the
+    // register-resident Jacobi for the subsets it flags, or the Jacobi for all
+    // (method 1). Beyond 128: the LDS / global Jacobi.
+    const int sel = method == 0 ? FLAG_EVD_FALLBACK : 0;
     if (ws.ntp <= 32) {
-        hipLaunchKernelGGL((k_jacobi_reg<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, max_sweeps);
+        if (method == 0) hipLaunchKernelGGL((k_heev_tri<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
+        hipLaunchKernelGGL((k_jacobi_reg<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp <= 64) {
-        hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps);
+        if (method == 0) hipLaunchKernelGGL((k_heev_tri<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
+        hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp <= 128) {
-        hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps);
+        if (method == 0) hipLaunchKernelGGL((k_heev_tri<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
+        hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (nt_max <= JAC_LDS_NT) {

@@ -249,6 +249,7 @@ struct lcf_context {
     std::vector<std::pair<int, size_t>> evpending;   // (stage, index of start event)
     double stage_ms[LCF_NUM_STAGES] = {0};
     long long stage_n[LCF_NUM_STAGES] = {0};
+    int evd_method = 0;            // 0: tridiagonal solver (Jacobi for flagged subsets), 1: Jacobi
     // autotuner: choices per launch-group class (tune_key)
     int autotune = 0;
     std::map<std::string, TuneChoice> tuned;
@@ -316,7 +317,7 @@ std::string graph_key(lcf_context* c, const Plan& pl, const std::vector<PacketIn
                   thr->pd_mode, thr->k_fixed, thr->beta_knee, thr->knee_max_frac, thr->beta_sigmoid, thr->deflate_rho,
                   (const void*)thr->explicit_w, prec, c->schedule, c->max_sweeps, c->sub_iters, pl.ntp);
     k += buf;
-    std::snprintf(buf, sizeof buf, "|c%d,r%d", pl.chunk, pl.trows);
+    std::snprintf(buf, sizeof buf, "|c%d,r%d,e%d", pl.chunk, pl.trows, c->evd_method);
     k += buf;
     if (diag) {
         std::snprintf(buf, sizeof buf, "|d%p,%p,%p,%p,%p,%p,%p,%p,%p", (void*)diag->eigvals, (void*)diag->weights,
@@ -553,7 +554,7 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     const bool mlp = thr->cut == LCF_CUT_MLP;
     RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
                   thr->knee_max_frac, thr->beta_sigmoid};
-    { STAGE(c, LCF_STAGE_JACOBI, st); HIPCHK(launch_jacobi(ws, c->max_sweeps, nt_max, st)); }
+    { STAGE(c, LCF_STAGE_JACOBI, st); HIPCHK(launch_jacobi(ws, c->max_sweeps, nt_max, c->evd_method, st)); }
     { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
     if (mlp) {
         STAGE(c, LCF_STAGE_MLP, st);
@@ -843,6 +844,11 @@ lcf_status lcf_set_option(lcf_context* c, int32_t option, int64_t value) {
         case LCF_OPT_AUTOTUNE:
             if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
             c->autotune = (int)value;
+            return LCF_OK;
+        case LCF_OPT_EVD:
+            if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
+            c->evd_method = (int)value;
+            drop_graphs(c);
             return LCF_OK;
         default:
             return LCF_ERR_INVALID_ARG;

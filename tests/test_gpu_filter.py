@@ -257,3 +257,43 @@ def test_graph_replay_matches_eager(lcf, ctx):
             assert gctx.sync() == 0
         finally:
             gctx.close()
+
+
+def test_evd_tridiagonal_matches_jacobi(lcf, ctx):
+    """The two subset eigen-solvers give the same filter (FP32 path)."""
+    _say("[tridiagonal vs Jacobi EVD]")
+    iq, mask = synth.make_packet(synth.spec_clinical(2))
+    dev = torch.from_numpy(iq).cuda()
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    io_t, pd_t, d_t = ctx.filter(dev, 8, 8, thr, diag=True)
+    ctx.set_option(lcf.OPT_EVD, lcf.EVD_JACOBI)
+    try:
+        io_j, pd_j, d_j = ctx.filter(dev, 8, 8, thr, diag=True)
+    finally:
+        ctx.set_option(lcf.OPT_EVD, lcf.EVD_TRIDIAGONAL)
+    torch.cuda.synchronize()
+    assert ctx.sync() == 0
+    lt, lj = d_t["eigvals"].cpu().numpy(), d_j["eigvals"].cpu().numpy()
+    e_lam = float(np.max(np.abs(lt - lj) / lj[:, :1]))
+    e_io = float(torch.linalg.vector_norm(io_t - io_j) / torch.linalg.vector_norm(io_j))
+    e_pd = float(torch.max(torch.abs(pd_t - pd_j) / pd_j))
+    fb = int(((d_t["flags"] & lcf.FLAG_EVD_JACOBI) != 0).sum())
+    _say(f"   eigenvalues {e_lam:.1e} (of lambda_1), iq {e_io:.1e}, pd {e_pd:.1e}, Jacobi fallbacks {fb}")
+    assert fb == 0                       # every subset took the tridiagonal path
+    assert e_lam <= 1e-12 and e_io <= 1e-7 and e_pd <= 1e-6
+    assert np.array_equal(d_t["k"].cpu().numpy(), d_j["k"].cpu().numpy())
+
+
+def test_evd_rank_deficient_falls_back_to_jacobi(lcf, ctx):
+    """Boxes of 30 pixels and 32 frames: every subset covariance is singular with
+    a repeated zero eigenvalue, so the tridiagonal solver hands it to Jacobi."""
+    _say("[rank-deficient subsets]")
+    spec = synth.PacketSpec(6, 5, 32, 30.0, 0.3, ((3, 1, 0.5),), seed=21)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=3)
+    io, pd, d = _run(lcf, ctx, iq, 2, 2, thr)
+    assert np.all(d["flags"] & lcf.FLAG_EVD_JACOBI)
+    res = O.filter_packet(iq, 2, 2, _oracle_thr(thr))
+    e = rel_fro(io, res["iq_out"])
+    _say(f"   rel_fro={e:.2e}")
+    assert e <= 1e-5
