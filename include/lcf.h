@@ -162,7 +162,7 @@ typedef enum {
     LCF_STAGE_GRAM2 = 4,        /* covariance of the deflated data [C' | C_w V_r]          */
     LCF_STAGE_GRAM2_REDUCE = 5,
     LCF_STAGE_ASSEMBLE = 6,     /* R from the deflated Gram, B = Q^H R Q                   */
-    LCF_STAGE_JACOBI = 7,       /* FP64 one-sided Jacobi EVD (Eq. 2)                       */
+    LCF_STAGE_EVD = 7,          /* FP64 subset EVD (Eq. 2): tridiagonal solver or Jacobi   */
     LCF_STAGE_RULES = 8,        /* eigencomponent weights (Eqs 4, 6, 9), alpha (Eq. 13)    */
     LCF_STAGE_MLP = 9,          /* learned weights                                         */
     LCF_STAGE_PROJECTOR = 10,   /* P = V diag(w) V^H                                       */

@@ -1233,7 +1233,7 @@ hipError_t launch_assemble(const Workspace& ws, hipStream_t st) {
 
 static int max_nt(const Workspace& ws) { return ws.ntp; }
 
-hipError_t launch_jacobi(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
+hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
     (void)max_nt;
     // Up to 128 frames: the tridiagonal solver (method 0), with the
     // register-resident Jacobi for the subsets it flags, or the Jacobi for all

@@ -554,7 +554,7 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     const bool mlp = thr->cut == LCF_CUT_MLP;
     RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
                   thr->knee_max_frac, thr->beta_sigmoid};
-    { STAGE(c, LCF_STAGE_JACOBI, st); HIPCHK(launch_jacobi(ws, c->max_sweeps, nt_max, c->evd_method, st)); }
+    { STAGE(c, LCF_STAGE_EVD, st); HIPCHK(launch_evd(ws, c->max_sweeps, nt_max, c->evd_method, st)); }
     { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
     if (mlp) {
         STAGE(c, LCF_STAGE_MLP, st);
