@@ -295,7 +295,8 @@ def main():
         "jacobi_sweeps_mean": float(np.mean(sweeps)),   # 0 where the tridiagonal solver ran
         "deflated_rank_mean": float(np.mean(ranks)),
         "mlp_fallback_rate": fallback,
-        "autotune": {t[0]: {"gram_chunk_px": int(t[1]), "reproj_tile_rows": int(t[2])} for t in tuned},
+        "autotune": {t[0]: {"gram_chunk_px": int(t[1]), "reproj_tile_rows": int(t[2]),
+                            "reproj_producer_consumer": bool(int(t[3]))} for t in tuned},
         "wall_s": wall,
     }
     print(json.dumps(out))

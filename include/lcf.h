@@ -141,9 +141,12 @@ typedef struct {
 #define LCF_OPT_AUTOTUNE     6  /* 1 = before the first call of a launch-group class (padded
                                    Nt, precision, schedule, log2 subset count, log2 mean
                                    box size) with no stored choice, time every split-K
-                                   chunk {512..4096 px} x reprojection tile {2, 4 rows}
+                                   chunk {512..4096 px} x reprojection kernel (tiles of
+                                   2 or 4 rows; with 4 rows, all waves alike or split
+                                   into producer and consumer waves)
                                    on the call's own packets and keep the fastest
-                                   (default 0: 1024 px, 4 rows up to 128 frames). Tuning
+                                   (default 0: 1024 px, 4 rows up to 128 frames, else 2;
+                                   producer/consumer waves for FP32 only). Tuning
                                    is skipped while the stream is being captured.          */
 
 #define LCF_OPT_EVD          7  /* subset EVD (Eq. 2) up to 128 frames: 0 = Householder
@@ -254,7 +257,7 @@ lcf_status lcf_stage_time(lcf_context* ctx, int32_t stage, double* ms, int64_t* 
 
 /* Autotuner choices (batched form of many packets and subsets, Discussion:
  * parallel processing of subsets) as text, one line per launch-group class:
- * "<class> <chunk> <rows>". lcf_tune_save writes the context's choices to `path`;
+ * "<class> <chunk> <rows> <variant>". lcf_tune_save writes the context's choices to `path`;
  * lcf_tune_load adds the choices in `path` to the context (replacing entries of
  * the same class) and drops captured graphs. Errors: LCF_ERR_INVALID_ARG for
  * NULL arguments, an unreadable/unwritable file or a malformed line (nothing is

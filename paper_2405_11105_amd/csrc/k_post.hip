@@ -612,6 +612,420 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
     }
 }
 
+// Producer/consumer form of the same reprojection. Waves 0-3 (consumers) run
+// the MFMAs and the PD / IQ epilogue of covering subset d while waves 4-7
+// (producers) form the operand rows [c' | y] of subset d + 1 in registers, so
+// the FP64 VALU work and the matrix cores overlap on every SIMD. Two barriers
+// per subset: producers write the operand (and the next V_r, window weights)
+// between them, consumers read it after the second. Producer lane layout:
+// pixel pt / G, frames part * TPT .. part * TPT + TPT - 1 (contiguous, so the
+// operand rows are written with 16-byte stores).
+template <int NTP, int PREC, int TR>
+struct RpPcCfg {
+    static constexpr int TP = TR * TW;
+    static constexpr int NRT = TP / 16;
+    static constexpr int NTE = NTP + REXT;
+    static constexpr int NTEP = (NTE + 31) / 32 * 32;
+    static constexpr int LDK = 2 * NTEP + 8;
+    static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;
+    static constexpr int LDA = 2 * IMO + 4;                         // 16-byte aligned rows
+    static constexpr int CT = (2 * NTP) / 16;
+    static constexpr int NCW = 4, NPW = 4;                          // consumer, producer waves
+    static constexpr int NTHR = 64 * (NCW + NPW);
+    static constexpr int PTHR = 64 * NPW;
+    static constexpr int CTW = (CT + NCW - 1) / NCW;
+    static constexpr int G = PTHR / TP;                             // producer lanes per pixel
+    static constexpr int TPT = NTP / G;                             // frames per producer lane
+    static constexpr int YPT = (REXT + G - 1) / G;                  // y columns per producer lane
+    static constexpr int LDC = NTP + 1;
+    static constexpr int VPT = (NTP * RMAX + PTHR - 1) / PTHR;      // V_r elements per producer lane
+    static constexpr int ABYTES = PREC ? 2 * TP * LDK * 2 : TP * LDA * 4;
+};
+
+template <int NTP, int PREC, int TR>
+__global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Workspace ws) {
+    using C = RpPcCfg<NTP, PREC, TR>;
+    constexpr int NTEP = C::NTEP, LDK = C::LDK, IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
+    constexpr int NTHR = C::NTHR, CTW = C::CTW, G = C::G, TP = C::TP, NRT = C::NRT;
+    constexpr int TPT = C::TPT, YPT = C::YPT, VPT = C::VPT, PTHR = C::PTHR;
+    static_assert(PTHR % TP == 0 && G >= 1 && G <= 16 && (G & (G - 1)) == 0, "pixel lanes in one row");
+    static_assert(NTP % G == 0 && TPT % 8 == 0, "frames per lane in whole 16-byte groups");
+    static_assert(C::ABYTES >= TP * LDC * 8, "the operand buffer stages the packet tile");
+    __shared__ __attribute__((aligned(16))) unsigned char abuf[C::ABYTES];
+    __shared__ double2 vrs[RMAX * NTP];         // V_r of the subset the producers work on, [j][t]
+    __shared__ float wd[2][TP], wsum[TP];
+    __shared__ float pdsh[C::NCW * TP];
+    __shared__ float2 ysh[TP * RMAX];          // tissue scores of the subset being formed
+    __shared__ float2 vrs32[RMAX * NTP];       // V_r rounded to FP32, [j][t] (for the scores only)
+    float* A = reinterpret_cast<float*>(abuf);
+    uint16_t* Ah = reinterpret_cast<uint16_t*>(abuf);
+    uint16_t* Al = Ah + TP * LDK;
+    float2* craw = reinterpret_cast<float2*>(abuf);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool producer = wave >= C::NCW;
+    const int g = lane >> 4, col = lane & 15;
+    const int per = gridDim.x >> 3;
+    const int tix = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tix >= ws.ntiles) return;
+    const TileDesc td = ws.tiles[tix];
+    const PacketDesc pk = ws.pkts[td.pkt];
+    const int nt = pk.nt, nx = pk.nx;
+    const long npix = (long)pk.ny * pk.nx;
+    const int npx = td.x1 - td.x0 + 1;
+    const int ncov = td.cov_cnt;
+    auto in_tile = [&](int p) { return (p / TW) < td.nrow && (p % TW) < npx; };
+    auto pix_off = [&](int p) { return (long)(td.y + p / TW) * nx + td.x0 + p % TW; };
+    auto window = [&](const SubsetDesc& sd, int p) -> double {
+        const int y = td.y + p / TW, x = td.x0 + p % TW;
+        if (!in_tile(p) || y < sd.y0 || y > sd.y1 || x < sd.x0 || x > sd.x1) return 0.0;
+        return sd.flat ? 1.0 : ws.wtab[sd.wy_off + y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
+    };
+    const int pt = tid - 64 * C::NCW;           // producer thread index
+    const int pp = producer ? pt / G : 0, part = producer ? pt % G : 0;
+
+    // packet tile, staged through LDS (all threads), kept in producer registers
+    for (int e = tid; e < TP * NTP; e += NTHR) {
+        const int p = e % TP, t = e / TP;
+        float2 c = make_float2(0.f, 0.f);
+        if (in_tile(p) && t < nt) c = pk.iq[(long)t * npix + pix_off(p)];
+        craw[p * LDC + t] = c;
+    }
+    __syncthreads();
+    // One register array holds the state of either role (a wave is one or the
+    // other), so the two never compete for VGPRs:
+    //   producer: packet tile s (2 TPT) | next operand rows (2 TPT) | y (2 YPT) | next V_r (4 VPT)
+    //   consumer: filtered IQ accumulators (4 NRT CTW) | PD accumulators (4 NRT)
+    constexpr int O_OP = 2 * TPT, O_Y = 4 * TPT, O_V = 4 * TPT + 2 * YPT, NPROD = O_V + 4 * VPT;
+    constexpr int O_PD = 4 * NRT * CTW, NCONS = O_PD + 4 * NRT;
+    constexpr int NST = NPROD > NCONS ? NPROD : NCONS;
+    float st[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) st[k] = 0.f;
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const float2 c = producer ? craw[pp * LDC + part * TPT + i] : make_float2(0.f, 0.f);
+        st[2 * i] = c.x;
+        st[2 * i + 1] = c.y;
+    }
+    __syncthreads();
+    {
+        uint32_t* z = reinterpret_cast<uint32_t*>(abuf);
+        for (int e = tid; e < C::ABYTES / 4; e += NTHR) z[e] = 0u;
+    }
+    auto sx = [&](int i) { return st[2 * i]; };
+    auto sy = [&](int i) { return st[2 * i + 1]; };
+    // operand words: BF16 path, word q of (re hi, im hi, re lo, im lo) packs frames
+    // 2q, 2q + 1; FP32 path, (re, im) of frame i
+    auto opw = [&](int k) -> uint32_t { return __float_as_uint(st[O_OP + k]); };
+    auto dset = [&](int k, double v) {
+        const long long b = __double_as_longlong(v);
+        st[k] = __uint_as_float((uint32_t)(b & 0xffffffff));
+        st[k + 1] = __uint_as_float((uint32_t)(b >> 32));
+    };
+    auto dget = [&](int k) -> double {
+        return __longlong_as_double((long long)(((unsigned long long)__float_as_uint(st[k + 1]) << 32) |
+                                                __float_as_uint(st[k])));
+    };
+    auto vload = [&](int ci) {
+        const int s = ws.cover[td.cov_off + ci];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = pt + PTHR * i;
+            const double2 v = e < NTP * RMAX ? ws.vr64[(long)s * NTP * RMAX + e] : make_double2(0.0, 0.0);
+            dset(O_V + 4 * i, v.x);
+            dset(O_V + 4 * i + 2, v.y);
+        }
+    };
+    auto vstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = pt + PTHR * i;
+            if (e < NTP * RMAX) {
+                const double2 v = make_double2(dget(O_V + 4 * i), dget(O_V + 4 * i + 2));
+                vrs[(e % RMAX) * NTP + e / RMAX] = v;
+                vrs32[(e % RMAX) * NTP + e / RMAX] = make_float2((float)v.x, (float)v.y);
+            }
+        }
+    };
+    // operand rows of covering subset ci from vrs (producers). The tissue scores
+    // y_j (one per pixel) go through ysh so that the loops over j stay rolled.
+    auto form = [&](int ci) {
+        const int r = ws.rank[ws.cover[td.cov_off + ci]];
+#pragma unroll 1
+        for (int j = 0; j < r; ++j) {
+            // FP32 scores suffice: c' below is formed in FP64 from the rounded y,
+            // so C' + Y V_r^H = C holds exactly whatever y is
+            float yr = 0.f, yi = 0.f;
+#pragma unroll
+            for (int i = 0; i < TPT; ++i) {
+                const float2 v = vrs32[j * NTP + part * TPT + i];
+                yr = fmaf(sx(i), v.x, fmaf(-sy(i), v.y, yr));
+                yi = fmaf(sx(i), v.y, fmaf(sy(i), v.x, yi));
+            }
+#pragma unroll
+            for (int m = G >> 1; m >= 1; m >>= 1) {
+                yr += __shfl_xor(yr, m, 64);
+                yi += __shfl_xor(yi, m, 64);
+            }
+            if (part == 0) ysh[pp * RMAX + j] = make_float2(yr, yi);
+        }
+        // ysh is written and read by the lanes of one pixel, all in this wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int i = 0; i < TPT; ++i) {
+            const int t = part * TPT + i;
+            double re = 0.0, im = 0.0;
+            if (t < nt) {
+                re = (double)sx(i);
+                im = (double)sy(i);
+#pragma unroll 1
+                for (int j = 0; j < r; ++j) {
+                    const float2 y = ysh[pp * RMAX + j];
+                    const double2 v = vrs[j * NTP + t];
+                    re -= (double)y.x * v.x + (double)y.y * v.y;
+                    im -= (double)y.y * v.x - (double)y.x * v.y;
+                }
+            }
+            if (PREC) {
+                const uint32_t rh = bf16_bits((float)re), ih = bf16_bits((float)im);
+                const uint32_t rl = bf16_bits((float)re - __uint_as_float(rh << 16));
+                const uint32_t il = bf16_bits((float)im - __uint_as_float(ih << 16));
+                const int h = i >> 1, sh = (i & 1) * 16;
+                const uint32_t keep = (i & 1) ? 0xffffu : 0u;     // low half from frame 2h
+                st[O_OP + h] = __uint_as_float((opw(h) & keep) | (rh << sh));
+                st[O_OP + TPT / 2 + h] = __uint_as_float((opw(TPT / 2 + h) & keep) | (ih << sh));
+                st[O_OP + TPT + h] = __uint_as_float((opw(TPT + h) & keep) | (rl << sh));
+                st[O_OP + 3 * TPT / 2 + h] = __uint_as_float((opw(3 * TPT / 2 + h) & keep) | (il << sh));
+            } else {
+                st[O_OP + 2 * i] = (float)re;
+                st[O_OP + 2 * i + 1] = (float)im;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < YPT; ++m) {
+            const int j = part * YPT + m;
+            const float2 yj = (j < r) ? ysh[pp * RMAX + j] : make_float2(0.f, 0.f);
+            st[O_Y + 2 * m] = yj.x;
+            st[O_Y + 2 * m + 1] = yj.y;
+        }
+    };
+    auto write_operand = [&]() {
+        if (PREC) {
+            uint16_t* rowh = Ah + pp * LDK + part * TPT;
+            uint16_t* rowl = Al + pp * LDK + part * TPT;
+#pragma unroll
+            for (int q = 0; q < TPT / 8; ++q) {
+                const int b0 = 4 * q;
+                *reinterpret_cast<u32x4*>(rowh + 8 * q) = u32x4{opw(b0), opw(b0 + 1), opw(b0 + 2), opw(b0 + 3)};
+                *reinterpret_cast<u32x4*>(rowh + NTEP + 8 * q) =
+                    u32x4{opw(TPT / 2 + b0), opw(TPT / 2 + b0 + 1), opw(TPT / 2 + b0 + 2), opw(TPT / 2 + b0 + 3)};
+                *reinterpret_cast<u32x4*>(rowl + 8 * q) =
+                    u32x4{opw(TPT + b0), opw(TPT + b0 + 1), opw(TPT + b0 + 2), opw(TPT + b0 + 3)};
+                *reinterpret_cast<u32x4*>(rowl + NTEP + 8 * q) =
+                    u32x4{opw(3 * TPT / 2 + b0), opw(3 * TPT / 2 + b0 + 1), opw(3 * TPT / 2 + b0 + 2), opw(3 * TPT / 2 + b0 + 3)};
+            }
+#pragma unroll
+            for (int m = 0; m < YPT; ++m) {
+                const int j = part * YPT + m;
+                if (j < REXT) {
+                    const float yx = st[O_Y + 2 * m], yy = st[O_Y + 2 * m + 1];
+                    const uint32_t rh = bf16_bits(yx), ih = bf16_bits(yy);
+                    Ah[pp * LDK + NTP + j] = (uint16_t)rh;
+                    Ah[pp * LDK + NTEP + NTP + j] = (uint16_t)ih;
+                    Al[pp * LDK + NTP + j] = (uint16_t)bf16_bits(yx - __uint_as_float(rh << 16));
+                    Al[pp * LDK + NTEP + NTP + j] = (uint16_t)bf16_bits(yy - __uint_as_float(ih << 16));
+                }
+            }
+        } else {
+            float* row = A + pp * LDA + part * TPT;
+#pragma unroll
+            for (int q = 0; q < TPT / 4; ++q) {
+                const int f0 = O_OP + 8 * q;
+                *reinterpret_cast<float4*>(row + 4 * q) = make_float4(st[f0], st[f0 + 2], st[f0 + 4], st[f0 + 6]);
+                *reinterpret_cast<float4*>(row + IMO + 4 * q) = make_float4(st[f0 + 1], st[f0 + 3], st[f0 + 5], st[f0 + 7]);
+            }
+#pragma unroll
+            for (int m = 0; m < YPT; ++m) {
+                const int j = part * YPT + m;
+                if (j < REXT) {
+                    A[pp * LDA + NTP + j] = st[O_Y + 2 * m];
+                    A[pp * LDA + IMO + NTP + j] = st[O_Y + 2 * m + 1];
+                }
+            }
+        }
+    };
+    // consumer accumulators live in st (zeroed above): iq (a, m, i) at 4 (a CTW + m) + i, pd at O_PD
+
+    if (producer && ncov > 0) { vload(0); vstore(); }
+    __syncthreads();
+    if (producer && ncov > 0) {
+        form(0);
+        if (ncov > 1) vload(1);
+    }
+    for (int ci = 0; ci < ncov; ++ci) {
+        const int s = ws.cover[td.cov_off + ci];
+        __syncthreads();                               // the operand buffer is free
+        if (producer) {
+            write_operand();
+            if (pt < TP) wd[ci & 1][pt] = (float)window(ws.sub[s], pt);
+            if (ci + 1 < ncov) vstore();
+        }
+        __syncthreads();                               // operand of subset ci and V_r of ci + 1 ready
+        if (producer) {
+            if (ci + 1 < ncov) {
+                if (ci + 2 < ncov) vload(ci + 2);
+                form(ci + 1);
+            }
+            continue;
+        }
+        const float alpha = (float)ws.alpha[s];
+        floatx4 acc[NRT][CTW];
+#pragma unroll
+        for (int a = 0; a < NRT; ++a)
+#pragma unroll
+            for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (PREC) {
+            const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
+#pragma unroll 1
+            for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
+                const int kq = k0 + 8 * g;
+                const bool impart = k0 >= NTEP;
+                const int kk = impart ? kq - NTEP : kq;
+                u32x4 bh[CTW], bl[CTW];
+#pragma unroll
+                for (int m = 0; m < CTW; ++m) {
+                    const int ct = wave * CTW + m;
+                    bh[m] = u32x4{0u, 0u, 0u, 0u};
+                    bl[m] = u32x4{0u, 0u, 0u, 0u};
+                    if (ct < C::CT) {
+                        const int n = ct * 16 + col;
+                        const bool outim = n >= NTP;
+                        const int nn = outim ? n - NTP : n;
+                        const int plane = (outim != impart) ? 2 : 0;
+                        const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
+                        const uint16_t* src = planes + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
+                        bh[m] = *reinterpret_cast<const u32x4*>(src);
+                        bl[m] = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) { bh[m][q] ^= sgn; bl[m][q] ^= sgn; }
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < NRT; ++a) {
+                    const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + (16 * a + col) * LDK + kq));
+                    const bf16x8 xl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Al + (16 * a + col) * LDK + kq));
+#pragma unroll
+                    for (int m = 0; m < CTW; ++m) {
+                        if (wave * CTW + m < C::CT) {
+                            const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh[m]), xbl = __builtin_bit_cast(bf16x8, bl[m]);
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, xbh, acc[a][m], 0, 0, 0);
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, xbl, acc[a][m], 0, 0, 0);
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, xbh, acc[a][m], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        } else {
+            const float* Br = ws.breal + (long)s * (2 * C::NTE) * (2 * NTP);
+#pragma unroll 2
+            for (int k0 = 0; k0 < 2 * C::NTE; k0 += 4) {
+                const int kk = k0 + g;
+                const int acol = kk < C::NTE ? kk : IMO + kk - C::NTE;
+                const float* brow = Br + (long)kk * (2 * NTP);
+                float bv[CTW];
+#pragma unroll
+                for (int m = 0; m < CTW; ++m) {
+                    const int ct = wave * CTW + m;
+                    bv[m] = ct < C::CT ? brow[ct * 16 + col] : 0.f;
+                }
+#pragma unroll
+                for (int a = 0; a < NRT; ++a) {
+                    const float av = A[(16 * a + col) * LDA + acol];
+#pragma unroll
+                    for (int m = 0; m < CTW; ++m)
+                        if (wave * CTW + m < C::CT)
+                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[m], acc[a][m], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NRT; ++a)
+#pragma unroll
+            for (int m = 0; m < CTW; ++m) {
+                if (wave * CTW + m < C::CT) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float w = wd[ci & 1][16 * a + 4 * g + i];
+                        const float v = acc[a][m][i];
+                        st[O_PD + a * 4 + i] += alpha * w * w * v * v;
+                        st[4 * (a * CTW + m) + i] += w * v;
+                    }
+                }
+            }
+    }
+    // PD: reduce over the 16 lanes that share pixel rows, then over consumer waves
+    if (!producer) {
+#pragma unroll
+        for (int i = 0; i < NRT * 4; ++i) {
+            float v = st[O_PD + i];
+            for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+            st[O_PD + i] = v;
+        }
+    }
+    __syncthreads();
+    if (!producer && col == 0) {
+#pragma unroll
+        for (int i = 0; i < NRT * 4; ++i) pdsh[wave * TP + (i >> 2) * 16 + 4 * g + (i & 3)] = st[O_PD + i];
+    }
+    if (producer && pt < TP) {
+        double ws_ = 0.0;
+        for (int ci = 0; ci < ncov; ++ci) ws_ += window(ws.sub[ws.cover[td.cov_off + ci]], pt);
+        wsum[pt] = (float)ws_;
+    }
+    __syncthreads();
+    if (tid < TP && in_tile(tid)) {
+        const int p = tid;
+        float pdv = 0.f;
+        for (int w = 0; w < C::NCW; ++w) pdv += pdsh[w * TP + p];
+        if (pk.pd_mode == 2) {
+            double comp = 0.0;
+            for (int ci = 0; ci < ncov; ++ci) {
+                const int s = ws.cover[td.cov_off + ci];
+                const double w = window(ws.sub[s], p);
+                comp += ws.alpha[s] * w * w;
+            }
+            pdv = comp > 0.0 ? (float)((double)pdv / comp) : 0.f;
+        }
+        pk.pd[pix_off(p)] = pdv;
+    }
+    if (pk.iq_out && !producer) {
+#pragma unroll
+        for (int a = 0; a < NRT; ++a)
+#pragma unroll
+            for (int m = 0; m < CTW; ++m) {
+                const int ct = wave * CTW + m;
+                if (ct < C::CT) {
+                    const int n = ct * 16 + col;
+                    const int part_ = n >= NTP, t = n - part_ * NTP;
+                    if (t < nt) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int p = 16 * a + 4 * g + i;
+                            if (in_tile(p)) {
+                                const float w = wsum[p];
+                                pk.iq_out[2 * ((long)t * npix + pix_off(p)) + part_] =
+                                    w > 0.f ? st[4 * (a * CTW + m) + i] / w : 0.f;
+                            }
+                        }
+                    }
+                }
+            }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <int NTP>
@@ -622,6 +1036,13 @@ static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t 
     } else if (ws.ntiles > 0) {
         const int grid = (ws.ntiles + 7) / 8 * 8;      // multiple of 8 for the XCD mapping
         if constexpr (trows_max(NTP) >= 4) {
+            if (ws.trows == 4 && ws.rvar == 1) {
+                if (prec == 0)
+                    hipLaunchKernelGGL((k_reproj_pc<NTP, 0, 4>), dim3(grid), dim3(RpPcCfg<NTP, 0, 4>::NTHR), 0, st, ws);
+                else
+                    hipLaunchKernelGGL((k_reproj_pc<NTP, 1, 4>), dim3(grid), dim3(RpPcCfg<NTP, 1, 4>::NTHR), 0, st, ws);
+                return;
+            }
             if (ws.trows == 4) {
                 if (prec == 0)
                     hipLaunchKernelGGL((k_reproj<NTP, 0, 4>), dim3(grid), dim3(RpCfg<NTP, 0, 4>::NTHR), 0, st, ws);

@@ -72,6 +72,7 @@ struct Workspace {
     const TileDesc* tiles;
     int ntiles;
     int trows;          // rows per reprojection tile (2 or 4)
+    int rvar;           // reprojection kernel: 0 = every wave does everything, 1 = producer/consumer waves
     const int* cover;
     const PacketDesc* pkts;
     double* wtab;       // window factor pool

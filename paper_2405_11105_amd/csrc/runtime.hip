@@ -101,6 +101,7 @@ lcf_status validate_precision(int p) {
 struct TuneChoice {
     int chunk;      // split-K chunk of the Gram passes (box pixels)
     int trows;      // image rows per reprojection tile
+    int rvar;       // reprojection kernel variant
 };
 
 struct PacketIn {
@@ -115,6 +116,7 @@ struct Plan {
     int ntp = 0, nt_max = 0;
     int chunk = CHUNK;      // split-K chunk of the Gram passes (box pixels)
     int trows = 2;          // image rows per reprojection tile (2 or 4)
+    int rvar = 0;           // reprojection kernel variant (1: producer/consumer, 4-row tiles only)
     std::vector<SubsetDesc> sub;
     std::vector<ChunkDesc> chunks;
     std::vector<int> chunk_begin;
@@ -126,11 +128,12 @@ struct Plan {
 };
 
 void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int>& idx, int pd_mode, int chunk,
-                int trows) {
+                int trows, int rvar) {
     pl.ntp = 0;
     pl.nt_max = 0;
     pl.chunk = chunk;
     pl.trows = trows;
+    pl.rvar = (trows == 4) ? rvar : 0;
     for (int i : idx) {
         pl.ntp = std::max(pl.ntp, ntp_class(in[i].g.nt));
         pl.nt_max = std::max(pl.nt_max, in[i].g.nt);
@@ -317,7 +320,7 @@ std::string graph_key(lcf_context* c, const Plan& pl, const std::vector<PacketIn
                   thr->pd_mode, thr->k_fixed, thr->beta_knee, thr->knee_max_frac, thr->beta_sigmoid, thr->deflate_rho,
                   (const void*)thr->explicit_w, prec, c->schedule, c->max_sweeps, c->sub_iters, pl.ntp);
     k += buf;
-    std::snprintf(buf, sizeof buf, "|c%d,r%d,e%d", pl.chunk, pl.trows, c->evd_method);
+    std::snprintf(buf, sizeof buf, "|c%d,r%d,v%d,e%d", pl.chunk, pl.trows, pl.rvar, c->evd_method);
     k += buf;
     if (diag) {
         std::snprintf(buf, sizeof buf, "|d%p,%p,%p,%p,%p,%p,%p,%p,%p", (void*)diag->eigvals, (void*)diag->weights,
@@ -430,6 +433,7 @@ Workspace make_ws(char* base, const Layout& L, const Plan& pl, const float* expl
     ws.tiles = (const TileDesc*)(base + L.off_tiles);
     ws.ntiles = (int)pl.tiles.size();
     ws.trows = pl.trows;
+    ws.rvar = pl.rvar;
     ws.cover = (const int*)(base + L.off_cover);
     ws.pkts = (const PacketDesc*)(base + L.off_pkts);
     ws.wtab = (double*)(base + L.off_wtab);
@@ -685,14 +689,17 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
     const int saved_timing = c->timing;
     c->timing = 0;
     float best = 0.f;
-    TuneChoice choice{CHUNK, 2};
+    TuneChoice choice{CHUNK, 2, 0};
     lcf_status res = LCF_OK;
     int ntp = 0;
     for (int i : idx) ntp = std::max(ntp, ntp_class(in[i].g.nt));
-    for (int tr = 2; tr <= trows_max(ntp) && res == LCF_OK; tr += 2) {
+    std::vector<std::pair<int, int>> tiles = {{2, 0}};                 // (rows, variant)
+    if (trows_max(ntp) >= 4) { tiles.push_back({4, 0}); tiles.push_back({4, 1}); }
+    for (const auto& tv : tiles) {
+        if (res != LCF_OK) break;
         for (int ch : chunks) {
             Plan pl;
-            build_plan(pl, in, idx, thr->pd_mode, ch, tr);
+            build_plan(pl, in, idx, thr->pd_mode, ch, tv.first, tv.second);
             Staged sg;
             res = stage_group(c, pl, thr, st, sg);
             if (res != LCF_OK) break;
@@ -704,7 +711,7 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
             float ms = 0.f;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { res = LCF_ERR_DEVICE; break; }
-            if (best == 0.f || ms < best) { best = ms; choice = TuneChoice{ch, tr}; }
+            if (best == 0.f || ms < best) { best = ms; choice = TuneChoice{ch, tv.first, tv.second}; }
         }
     }
     c->timing = saved_timing;
@@ -727,7 +734,10 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
     for (auto& kv : groups) {
         // plan parameters: the tuned choice for this group's class, else the defaults
         Plan pl;
-        build_plan(pl, in, kv.second, thr->pd_mode, CHUNK, trows_max(kv.first));
+        // default: 4-row tiles where allowed; producer/consumer waves for the FP32
+        // GEMM (measured faster there), one role per wave for split BF16
+        build_plan(pl, in, kv.second, thr->pd_mode, CHUNK, trows_max(kv.first),
+                   (trows_max(kv.first) >= 4 && prec == LCF_PREC_FP32) ? 1 : 0);
         const std::string tkey = tune_key(pl, prec, c->schedule);
         auto tit = c->tuned.find(tkey);
         if (tit == c->tuned.end() && c->autotune && cap == hipStreamCaptureStatusNone) {
@@ -737,9 +747,10 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
         }
         if (tit != c->tuned.end()) {
             const int tr = std::min(tit->second.trows, trows_max(kv.first));
-            if (tit->second.chunk != pl.chunk || tr != pl.trows) {
+            const int rv = tr == 4 ? tit->second.rvar : 0;
+            if (tit->second.chunk != pl.chunk || tr != pl.trows || rv != pl.rvar) {
                 Plan tuned;
-                build_plan(tuned, in, kv.second, thr->pd_mode, tit->second.chunk, tr);
+                build_plan(tuned, in, kv.second, thr->pd_mode, tit->second.chunk, tr, rv);
                 pl = std::move(tuned);
             }
         }
@@ -1093,7 +1104,8 @@ lcf_status lcf_tune_save(lcf_context* ctx, const char* path) {
     if (!f) return LCF_ERR_INVALID_ARG;
     bool ok = true;
     for (const auto& kv : ctx->tuned)
-        ok = ok && std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.chunk, kv.second.trows) > 0;
+        ok = ok && std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.chunk, kv.second.trows,
+                                kv.second.rvar) > 0;
     ok = (std::fclose(f) == 0) && ok;
     return ok ? LCF_OK : LCF_ERR_INVALID_ARG;
 }
@@ -1104,13 +1116,14 @@ lcf_status lcf_tune_load(lcf_context* ctx, const char* path) {
     if (!f) return LCF_ERR_INVALID_ARG;
     std::map<std::string, TuneChoice> got;
     char key[128];
-    int chunk = 0, rows = 0;
+    int chunk = 0, rows = 0, var = 0;
     bool ok = true;
     for (;;) {
-        const int n = std::fscanf(f, "%127s %d %d", key, &chunk, &rows);
+        const int n = std::fscanf(f, "%127s %d %d %d", key, &chunk, &rows, &var);
         if (n == EOF) break;
-        if (n != 3 || chunk < PIX || chunk > (1 << 20) || (rows != 2 && rows != 4)) { ok = false; break; }
-        got[key] = TuneChoice{chunk, rows};
+        if (n != 4 || chunk < PIX || chunk > (1 << 20) || (rows != 2 && rows != 4) || var < 0 || var > 1 ||
+            (var == 1 && rows != 4)) { ok = false; break; }
+        got[key] = TuneChoice{chunk, rows, var};
     }
     std::fclose(f);
     if (!ok) return LCF_ERR_INVALID_ARG;

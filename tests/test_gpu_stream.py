@@ -101,7 +101,7 @@ def test_autotune_choice_roundtrip(lcf, ctx, tmp_path):
         tuned.tune_save(path)
         lines = open(path).read().split("\n")
         say(f"[autotune] {lines[0]}")
-        assert len([x for x in lines if x.strip()]) == 1 and len(lines[0].split()) == 3
+        assert len([x for x in lines if x.strip()]) == 1 and len(lines[0].split()) == 4
         e_io = float(torch.linalg.vector_norm(io1 - io0) / torch.linalg.vector_norm(io0))
         e_pd = float(torch.max(torch.abs(pd1 - pd0) / pd0))
         assert e_io <= 1e-5 and e_pd <= 1e-4, (e_io, e_pd)
