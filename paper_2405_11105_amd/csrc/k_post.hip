@@ -241,9 +241,12 @@ struct RpCfg {
     static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;     // FP32: offset of the im part
     static constexpr int LDA = 2 * IMO + 1;                           // FP32 row stride (floats)
     static constexpr int CT = (2 * NTP) / 16;                         // output column tiles
+    static constexpr int NNT = NTP / 16;                              // output frame tiles
     static constexpr int NW = CT >= 8 ? 8 : CT;                       // waves
     static constexpr int NTHR = 64 * NW;
-    static constexpr int CTW = (CT + NW - 1) / NW;                    // column tiles per wave
+    // column tiles per wave: split BF16 pairs the re and im output tiles of the
+    // same frames in one wave (each [P; M] fragment then serves both)
+    static constexpr int CTW = PREC ? 2 * ((NNT + NW - 1) / NW) : (CT + NW - 1) / NW;
     static constexpr int LDC = NTP + 1;                               // staging row stride (float2)
     static constexpr int G = NTHR / TP;                               // threads per pixel for y
     static constexpr int ABYTES = PREC ? 2 * TP * LDK * 2 : TP * LDA * 4;
@@ -299,6 +302,16 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
             A[p * LDA + IMO + c] = im;
         }
     };
+    // output column tile of accumulator m: split BF16 pairs (re, im) of frame
+    // tile q = wave * CTW / 2 + m / 2; FP32 takes consecutive tiles
+    auto ct_of = [&](int m) -> int {
+        if (PREC) {
+            const int q = wave * (CTW / 2) + (m >> 1);
+            return (m & 1) ? C::NNT + q : q;
+        }
+        return wave * CTW + m;
+    };
+    auto ct_ok = [&](int m) -> bool { return PREC ? wave * (CTW / 2) + (m >> 1) < C::NNT : ct_of(m) < C::CT; };
     auto window = [&](const SubsetDesc& sd, int p) -> double {
         const int y = td.y + p / TW, x = td.x0 + p % TW;
         if (!in_tile(p) || y < sd.y0 || y > sd.y1 || x < sd.x0 || x > sd.x1) return 0.0;
@@ -342,31 +355,6 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
             vnext[i] = e < NTP * RMAX ? ws.vr64[(long)s * NTP * RMAX + e] : make_double2(0.0, 0.0);
         }
     };
-    // [P; M] fragments of the first K iterations are loaded before the operand
-    // rows of a subset are formed (they do not depend on them).
-    constexpr int KIT = 2 * NTEP / 32;
-    constexpr int KPF = (PREC && CTW <= 2 && KIT >= 2) ? 2 : 0;
-    auto bload = [&](const uint16_t* planes, int k, int m, u32x4& bh, u32x4& bl) {
-        const int ct = wave * CTW + m;
-        bh = u32x4{0u, 0u, 0u, 0u};
-        bl = u32x4{0u, 0u, 0u, 0u};
-        if (ct < C::CT) {
-            const int kq = 32 * k + 8 * g;
-            const bool impart = 32 * k >= NTEP;
-            const int kk = impart ? kq - NTEP : kq;
-            const int n = ct * 16 + col;
-            const bool outim = n >= NTP;
-            const int nn = outim ? n - NTP : n;
-            // B^T row n: re output [P_re | -P_im], im output [P_im | P_re]
-            const int plane = (outim != impart) ? 2 : 0;
-            const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
-            const uint16_t* src = planes + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
-            bh = *reinterpret_cast<const u32x4*>(src);
-            bl = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) { bh[q] ^= sgn; bl[q] ^= sgn; }
-        }
-    };
     if (td.cov_cnt > 0) vload(0);
 
     for (int ci = 0; ci < td.cov_cnt; ++ci) {
@@ -375,13 +363,6 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         const int r = ws.rank[s];
         const float alpha = (float)ws.alpha[s];
         const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
-        u32x4 pbh[2][CTW], pbl[2][CTW];
-        if (PREC) {
-#pragma unroll
-            for (int k = 0; k < KPF; ++k)
-#pragma unroll
-                for (int m = 0; m < CTW; ++m) bload(planes, k, m, pbh[k][m], pbl[k][m]);
-        }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
@@ -445,74 +426,58 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (PREC && KPF > 0) {
-            // ping-pong: fragments of K iterations k, k+1 are in registers while
-            // those of k+2, k+3 load (KIT = 2 NTEP / 32 is even)
-            static_assert(KIT % 2 == 0, "K iterations come in pairs");
-#pragma unroll 1
-            for (int k = 0; k < KIT; k += 2) {
+        if (PREC) {
+            // K runs over the re part only; each step loads P_re and P_im fragments
+            // once and forms out_re = a_re P_re - a_im P_im, out_im = a_re P_im + a_im P_re
+            constexpr int KUNR = NTP > 128 ? 1 : 2;      // register budget of the widest subsets
+            constexpr int QW = CTW / 2 > 0 ? CTW / 2 : 1;
+#pragma unroll KUNR
+            for (int k0 = 0; k0 < NTEP; k0 += 32) {
+                const int kq = k0 + 8 * g;
+                u32x4 brh[QW], brl[QW], bih[QW], bil[QW];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int kq = 32 * (k + h) + 8 * g;
-                    bf16x8 xh[NRT], xl[NRT];
-#pragma unroll
-                    for (int a = 0; a < NRT; ++a) {
-                        xh[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + (16 * a + col) * LDK + kq));
-                        xl[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Al + (16 * a + col) * LDK + kq));
-                    }
-#pragma unroll
-                    for (int m = 0; m < CTW; ++m) {
-                        if (wave * CTW + m < C::CT) {
-                            const bf16x8 xbh = __builtin_bit_cast(bf16x8, pbh[h][m]);
-                            const bf16x8 xbl = __builtin_bit_cast(bf16x8, pbl[h][m]);
-#pragma unroll
-                            for (int a = 0; a < NRT; ++a) {
-                                acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbh, acc[a][m], 0, 0, 0);
-                                acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbl, acc[a][m], 0, 0, 0);
-                                acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[a], xbh, acc[a][m], 0, 0, 0);
-                            }
-                        }
-                    }
-                    if (k + h + 2 < KIT) {
-#pragma unroll
-                        for (int m = 0; m < CTW; ++m) bload(planes, k + h + 2, m, pbh[h][m], pbl[h][m]);
+                for (int q = 0; q < QW; ++q) {
+                    const int nq = wave * QW + q;
+                    brh[q] = brl[q] = bih[q] = bil[q] = u32x4{0u, 0u, 0u, 0u};
+                    if (nq < C::NNT) {
+                        const uint16_t* src = planes + (long)(nq * 16 + col) * NTEP + kq;
+                        brh[q] = *reinterpret_cast<const u32x4*>(src);
+                        brl[q] = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
+                        bih[q] = *reinterpret_cast<const u32x4*>(src + 2 * NTP * NTEP);
+                        bil[q] = *reinterpret_cast<const u32x4*>(src + 3 * NTP * NTEP);
                     }
                 }
-            }
-        } else if (PREC) {
-            constexpr int KUNR = NTP > 128 ? 1 : 2;      // register budget of the widest subsets
-#pragma unroll KUNR
-            for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
-                const int kq = k0 + 8 * g;
-                bf16x8 xh[NRT], xl[NRT];
 #pragma unroll
                 for (int a = 0; a < NRT; ++a) {
-                    xh[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + (16 * a + col) * LDK + kq));
-                    xl[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Al + (16 * a + col) * LDK + kq));
-                }
-                const bool impart = k0 >= NTEP;
-                const int kk = impart ? kq - NTEP : kq;
+                    const uint16_t* arow = Ah + (16 * a + col) * LDK + kq;
+                    const uint16_t* lrow = Al + (16 * a + col) * LDK + kq;
+                    const bf16x8 xrh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow));
+                    const bf16x8 xrl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow));
+                    const bf16x8 xih = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow + NTEP));
+                    const bf16x8 xil = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow + NTEP));
 #pragma unroll
-                for (int m = 0; m < CTW; ++m) {
-                    const int ct = wave * CTW + m;
-                    if (ct < C::CT) {
-                        const int n = ct * 16 + col;
-                        const bool outim = n >= NTP;
-                        const int nn = outim ? n - NTP : n;
-                        // B^T row n: re output [P_re | -P_im], im output [P_im | P_re]
-                        const int plane = (outim != impart) ? 2 : 0;
-                        const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
-                        const uint16_t* src = planes + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
-                        u32x4 bh = *reinterpret_cast<const u32x4*>(src);
-                        u32x4 bl = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
+                    for (int q = 0; q < QW; ++q) {
+                        if (wave * QW + q < C::NNT) {
+                            const bf16x8 prh = __builtin_bit_cast(bf16x8, brh[q]), prl = __builtin_bit_cast(bf16x8, brl[q]);
+                            const bf16x8 pih = __builtin_bit_cast(bf16x8, bih[q]), pil = __builtin_bit_cast(bf16x8, bil[q]);
+                            u32x4 nh = bih[q], nl = bil[q];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) { bh[q] ^= sgn; bl[q] ^= sgn; }
-                        const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh), xbl = __builtin_bit_cast(bf16x8, bl);
-#pragma unroll
-                        for (int a = 0; a < NRT; ++a) {
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbh, acc[a][m], 0, 0, 0);
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], xbl, acc[a][m], 0, 0, 0);
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[a], xbh, acc[a][m], 0, 0, 0);
+                            for (int e = 0; e < 4; ++e) { nh[e] ^= 0x80008000u; nl[e] ^= 0x80008000u; }
+                            const bf16x8 nih = __builtin_bit_cast(bf16x8, nh), nil = __builtin_bit_cast(bf16x8, nl);
+                            floatx4& ore = acc[a][2 * q];
+                            floatx4& oim = acc[a][2 * q + 1];
+                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, prh, ore, 0, 0, 0);
+                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, prl, ore, 0, 0, 0);
+                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrl, prh, ore, 0, 0, 0);
+                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, nih, ore, 0, 0, 0);
+                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, nil, ore, 0, 0, 0);
+                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xil, nih, ore, 0, 0, 0);
+                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, pih, oim, 0, 0, 0);
+                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, pil, oim, 0, 0, 0);
+                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrl, pih, oim, 0, 0, 0);
+                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, prh, oim, 0, 0, 0);
+                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, prl, oim, 0, 0, 0);
+                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xil, prh, oim, 0, 0, 0);
                         }
                     }
                 }
@@ -544,7 +509,7 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) {
-                if (wave * CTW + m < C::CT) {
+                if (ct_ok(m)) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const float w = wd[16 * a + 4 * g + i];
@@ -593,8 +558,8 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) {
-                const int ct = wave * CTW + m;
-                if (ct < C::CT) {
+                const int ct = ct_of(m);
+                if (ct_ok(m)) {
                     const int n = ct * 16 + col;
                     const int part_ = n >= NTP, t = n - part_ * NTP;
                     if (t < nt) {
