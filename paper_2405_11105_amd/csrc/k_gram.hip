@@ -37,7 +37,11 @@ struct GramCfg {
     static constexpr int TT = 2 * TPM;                     // S and T tiles, interleaved
     static constexpr int WAVES = TT > 60 ? 8 : 4;
     static constexpr int THREADS = 64 * WAVES;
-    static constexpr int MAXT = (TT + WAVES - 1) / WAVES;
+    static constexpr int MAXT = (TT + WAVES - 1) / WAVES;  // FP32: tiles per wave
+    static constexpr int MAXP = (TPM + WAVES - 1) / WAVES; // split BF16: tile positions per wave
+    // waves per SIMD asked of the register allocator: two work-groups per CU for
+    // the split-BF16 pass-1 Gram up to 128 frames
+    static constexpr int MIN_WAVES = (PREC == 1 && !DEFL && NTP <= 128) ? 2 * WAVES / 4 : 1;
     static constexpr int PX = NTP > 160 ? 16 : PIX;        // pixels per LDS batch
     // FP32 layout: per pixel a row [re(0..NTE) | im], odd stride
     static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;
@@ -54,31 +58,19 @@ __device__ __forceinline__ void tile_ij(int u, int nt16, int& i, int& j) {
     j = i + rem;
 }
 
-// Round-to-nearest-even FP32 -> BF16 bits.
-__device__ __forceinline__ uint32_t bf16_rne(float x) {
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-
-// Split x = hi + lo (both BF16, RNE) and store (re, im) pairs.
-__device__ __forceinline__ void split_pair(float re, float im, uint32_t& h, uint32_t& l) {
-    const uint32_t rh = bf16_rne(re), ih = bf16_rne(im);
-    const float rl = re - __uint_as_float(rh << 16), il = im - __uint_as_float(ih << 16);
-    h = rh | (ih << 16);
-    l = bf16_rne(rl) | (bf16_rne(il) << 16);
-}
-
-// Operand row of B for the T tiles: rows (2p, 2p+1) of the interleaved K axis
-// become (im_p, -re_p): swap the halves of every word, negate the new high half.
+// Row fragment for the T tiles: each (re, im) word of the interleaved K axis
+// becomes (-im, re), so that the product with the plain column fragment sums
+// re_r im_c - im_r re_c.
 __device__ __forceinline__ u32x4 swap_neg(u32x4 v) {
     u32x4 o;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) o[e] = ((v[e] >> 16) | (v[e] << 16)) ^ 0x80000000u;
+    for (int e = 0; e < 4; ++e) o[e] = ((v[e] >> 16) | (v[e] << 16)) ^ 0x00008000u;
     return o;
 }
 
 template <int NTP, bool DEFL, int PREC>
 __global__ void __launch_bounds__((GramCfg<NTP, DEFL, PREC>::THREADS))
+__attribute__((amdgpu_waves_per_eu(GramCfg<NTP, DEFL, PREC>::MIN_WAVES)))
 k_gram(Workspace ws) {
     using C = GramCfg<NTP, DEFL, PREC>;
     constexpr int NTE = C::NTE, IMO = C::IMO, LDA = C::LDA, LDB = C::LDB, PIX = C::PX;
@@ -94,14 +86,14 @@ k_gram(Workspace ws) {
             A[p * LDA + IMO + c] = im;
         } else {
             uint32_t h, l;
-            split_pair(re, im, h, l);
+            split_bf16x2(re, im, h, l);
             Ah[c * LDB + p] = h;
             Al[c * LDB + p] = l;
         }
     };
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const ChunkDesc ch = ws.chunks[blockIdx.x];
     const SubsetDesc sd = ws.sub[ch.s];
     const int nt = sd.nt, nx = sd.nx;
@@ -117,12 +109,15 @@ k_gram(Workspace ws) {
         }
     }
 
-    // Tiles owned by this wave: FP32 round-robin, BF16 contiguous (operand reuse).
-    int aoff[C::MAXT], boff[C::MAXT];
-    bool isT[C::MAXT], valid[C::MAXT];
+    // FP32: tiles tau = wave + WAVES m (round-robin). Split BF16: contiguous upper
+    // tile positions u, S and T of each (row fragments shared along a tile row).
+    constexpr int NACC = PREC == 0 ? C::MAXT : 2 * C::MAXP;
+    constexpr int NOWN = PREC == 0 ? C::MAXT : C::MAXP;
+    int aoff[NOWN], boff[NOWN];
+    bool isT[NOWN], valid[NOWN];
 #pragma unroll
-    for (int m = 0; m < C::MAXT; ++m) {
-        const int tau = PREC == 0 ? wave + C::WAVES * m : wave * C::MAXT + m;
+    for (int m = 0; m < NOWN; ++m) {
+        const int tau = PREC == 0 ? wave + C::WAVES * m : 2 * (wave * C::MAXP + m);
         valid[m] = tau < C::TT;
         int i, j;
         tile_ij(valid[m] ? (tau >> 1) : 0, C::NT16, i, j);
@@ -130,9 +125,9 @@ k_gram(Workspace ws) {
         boff[m] = j * 16;
         isT[m] = valid[m] && (tau & 1);
     }
-    floatx4 acc[C::MAXT];
+    floatx4 acc[NACC];
 #pragma unroll
-    for (int m = 0; m < C::MAXT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < NACC; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     // Operand staging is software-pipelined: the global loads of the next batch of
     // box pixels are issued before the MFMAs of the current batch. Each thread
@@ -150,15 +145,18 @@ k_gram(Workspace ws) {
     const bool active = my_p < PIX;       // pass 2 with 16-pixel batches leaves whole waves idle
     float2 nxt[NPT];
     double nw = 0.0;
+    // box coordinates of this thread's pixel q = qb + my_p, advanced by PIX per batch
+    int fy = (ch.q0 + my_p) / sd.bw, fx = (ch.q0 + my_p) - fy * sd.bw;
     auto fetch = [&](int qb) {
         const int q = qb + my_p;
         long poff = -1;
         nw = 0.0;
         if (active && q < ch.q1) {
-            const int yy = q / sd.bw, xx = q - yy * sd.bw;
-            poff = (long)(sd.y0 + yy) * nx + sd.x0 + xx;
-            nw = sd.flat ? 1.0 : wy[yy] * wx[xx];
+            poff = (long)(sd.y0 + fy) * nx + sd.x0 + fx;
+            nw = sd.flat ? 1.0 : wy[fy] * wx[fx];
         }
+        fx += PIX;
+        while (fx >= sd.bw) { fx -= sd.bw; ++fy; }
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int t = my_t0 + TSTEP * i;
@@ -172,12 +170,16 @@ k_gram(Workspace ws) {
         for (int i = 0; i < NPT; ++i) cur[i] = nxt[i];
         const double w = nw;
         __syncthreads();                           // the previous batch's MFMAs are done
-        if (qb + PIX < ch.q1) fetch(qb + PIX);     // in flight during this batch
+        // pass 2: the next batch's loads overlap the FP64 operand work as well;
+        // pass 1 issues them after the (short) operand writes, reusing the registers
+        if (DEFL && qb + PIX < ch.q1) fetch(qb + PIX);
         if (!DEFL) {
+            // the pass-1 Gram only locates the tissue subspace: FP32 window product
+            const float wf = (float)w;
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
                 const int t = my_t0 + TSTEP * i;
-                if (t < NTP) put(my_p, t, (float)(w * (double)cur[i].x), (float)(w * (double)cur[i].y));
+                if (t < NTP) put(my_p, t, wf * cur[i].x, wf * cur[i].y);
             }
         } else if (active) {
             // Tissue scores y = w s V_r in FP64 over this lane's frames, reduced over
@@ -229,6 +231,7 @@ k_gram(Workspace ws) {
                 put(my_p, NTP + j, yj.x, yj.y);
             }
         }
+        if (!DEFL && qb + PIX < ch.q1) fetch(qb + PIX);   // in flight during the MFMAs
         __syncthreads();
         if (PREC == 0) {
             const int kk = lane >> 4, col = lane & 15;
@@ -250,51 +253,50 @@ k_gram(Workspace ws) {
             }
         } else {
             // K blocks of 32 = 16 pixels x (re, im); lane group g holds pixels 4g..4g+3.
+            // Position (i, j): S from (A_i, A_j), T from (A_i swapped, A_j).
             const int g = lane >> 4, col = lane & 15;
 #pragma unroll
             for (int kb = 0; kb < PIX; kb += 16) {
                 const int wofs = kb + 4 * g;
                 int cur_a = -1;
-                u32x4 ah = u32x4{0, 0, 0, 0}, al = u32x4{0, 0, 0, 0};
-                int cur_b = -1;
-                u32x4 bh = u32x4{0, 0, 0, 0}, bl = u32x4{0, 0, 0, 0};
+                u32x4 ah = u32x4{0, 0, 0, 0}, al = ah, sh = ah, sl = ah;
 #pragma unroll
-                for (int m = 0; m < C::MAXT; ++m) {
+                for (int m = 0; m < C::MAXP; ++m) {
                     if (valid[m]) {
                         if (aoff[m] != cur_a) {
                             cur_a = aoff[m];
                             ah = *reinterpret_cast<const u32x4*>(Ah + (cur_a + col) * LDB + wofs);
                             al = *reinterpret_cast<const u32x4*>(Al + (cur_a + col) * LDB + wofs);
+                            sh = swap_neg(ah);
+                            sl = swap_neg(al);
                         }
-                        if (boff[m] != cur_b) {
-                            cur_b = boff[m];
-                            bh = *reinterpret_cast<const u32x4*>(Ah + (cur_b + col) * LDB + wofs);
-                            bl = *reinterpret_cast<const u32x4*>(Al + (cur_b + col) * LDB + wofs);
-                        }
-                        const u32x4 uh = isT[m] ? swap_neg(bh) : bh;
-                        const u32x4 ul = isT[m] ? swap_neg(bl) : bl;
-                        const bf16x8 xa_h = __builtin_bit_cast(bf16x8, ah);
-                        const bf16x8 xa_l = __builtin_bit_cast(bf16x8, al);
-                        const bf16x8 xb_h = __builtin_bit_cast(bf16x8, uh);
-                        const bf16x8 xb_l = __builtin_bit_cast(bf16x8, ul);
-                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_h, acc[m], 0, 0, 0);
-                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_l, acc[m], 0, 0, 0);
-                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_l, xb_h, acc[m], 0, 0, 0);
+                        const u32x4 bh = *reinterpret_cast<const u32x4*>(Ah + (boff[m] + col) * LDB + wofs);
+                        const u32x4 bl = *reinterpret_cast<const u32x4*>(Al + (boff[m] + col) * LDB + wofs);
+                        const bf16x8 xa_h = __builtin_bit_cast(bf16x8, ah), xa_l = __builtin_bit_cast(bf16x8, al);
+                        const bf16x8 xs_h = __builtin_bit_cast(bf16x8, sh), xs_l = __builtin_bit_cast(bf16x8, sl);
+                        const bf16x8 xb_h = __builtin_bit_cast(bf16x8, bh), xb_l = __builtin_bit_cast(bf16x8, bl);
+                        floatx4& sa = acc[2 * m];
+                        floatx4& ta = acc[2 * m + 1];
+                        sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_h, sa, 0, 0, 0);
+                        ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_h, xb_h, ta, 0, 0, 0);
+                        sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_l, sa, 0, 0, 0);
+                        ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_h, xb_l, ta, 0, 0, 0);
+                        sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_l, xb_h, sa, 0, 0, 0);
+                        ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_l, xb_h, ta, 0, 0, 0);
                     }
                 }
             }
         }
     }
 #pragma unroll
-    for (int m = 0; m < C::MAXT; ++m) {
-        if (valid[m]) {
-            const int tau = PREC == 0 ? wave + C::WAVES * m : wave * C::MAXT + m;
+    for (int m = 0; m < NACC; ++m) {
+        const int tau = PREC == 0 ? wave + C::WAVES * m : 2 * (wave * C::MAXP + (m >> 1)) + (m & 1);
+        if (tau < C::TT) {
             float* dst = ws.partial + ((long)blockIdx.x * C::TT + tau) * 256 + lane * 4;
             *reinterpret_cast<floatx4*>(dst) = acc[m];
         }
     }
 }
-
 // Sum the chunk partials of each subset in chunk order (FP64) and expand the
 // upper S/T tiles into the full Hermitian matrix out[s][NTE][NTE].
 template <int NTE>

@@ -99,6 +99,19 @@ struct Workspace {
 
 // ------------------------------------------------------------------ helpers
 
+typedef __bf16 lcf_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float lcf_floatx2 __attribute__((ext_vector_type(2)));
+
+// Split-BF16 pair: (re, im) = hi + lo with hi = bf16(x), lo = bf16(x - hi), both
+// rounded to nearest even by the packed hardware conversion. Each word holds
+// the re part in its low half and the im part in its high half.
+__device__ __forceinline__ void split_bf16x2(float re, float im, uint32_t& h, uint32_t& l) {
+    const lcf_floatx2 v = {re, im};
+    h = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, lcf_bf16x2));
+    const lcf_floatx2 r = {re - __uint_as_float(h << 16), im - __uint_as_float(h & 0xFFFF0000u)};
+    l = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, lcf_bf16x2));
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
