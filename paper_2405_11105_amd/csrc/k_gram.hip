@@ -68,6 +68,48 @@ __device__ __forceinline__ u32x4 swap_neg(u32x4 v) {
     return o;
 }
 
+// Split-BF16 Gram MFMAs of one batch of C::PX pixels in LDS (hi words Ah, lo
+// words Al, [column][pixel] with stride LDB). K blocks of 32 = 16 pixels x
+// (re, im); lane group g holds pixels 4g..4g+3. Position (i, j) of the wave:
+// S from (A_i, A_j), T from (A_i swapped, A_j); acc[2m] = S, acc[2m + 1] = T.
+template <class C>
+__device__ __forceinline__ void gram_mfma_bf16(const uint32_t* Ah, const uint32_t* Al, const int* aoff,
+                                               const int* boff, const bool* valid, floatx4* acc, int lane) {
+    constexpr int LDB = C::LDB;
+    const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int kb = 0; kb < C::PX; kb += 16) {
+        const int wofs = kb + 4 * g;
+        int cur_a = -1;
+        u32x4 ah = u32x4{0, 0, 0, 0}, al = ah, sh = ah, sl = ah;
+#pragma unroll
+        for (int m = 0; m < C::MAXP; ++m) {
+            if (valid[m]) {
+                if (aoff[m] != cur_a) {
+                    cur_a = aoff[m];
+                    ah = *reinterpret_cast<const u32x4*>(Ah + (cur_a + col) * LDB + wofs);
+                    al = *reinterpret_cast<const u32x4*>(Al + (cur_a + col) * LDB + wofs);
+                    sh = swap_neg(ah);
+                    sl = swap_neg(al);
+                }
+                const u32x4 bh = *reinterpret_cast<const u32x4*>(Ah + (boff[m] + col) * LDB + wofs);
+                const u32x4 bl = *reinterpret_cast<const u32x4*>(Al + (boff[m] + col) * LDB + wofs);
+                const bf16x8 xa_h = __builtin_bit_cast(bf16x8, ah), xa_l = __builtin_bit_cast(bf16x8, al);
+                const bf16x8 xs_h = __builtin_bit_cast(bf16x8, sh), xs_l = __builtin_bit_cast(bf16x8, sl);
+                const bf16x8 xb_h = __builtin_bit_cast(bf16x8, bh), xb_l = __builtin_bit_cast(bf16x8, bl);
+                floatx4& sa = acc[2 * m];
+                floatx4& ta = acc[2 * m + 1];
+                sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_h, sa, 0, 0, 0);
+                ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_h, xb_h, ta, 0, 0, 0);
+                sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_l, sa, 0, 0, 0);
+                ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_h, xb_l, ta, 0, 0, 0);
+                sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_l, xb_h, sa, 0, 0, 0);
+                ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_l, xb_h, ta, 0, 0, 0);
+            }
+        }
+    }
+}
+
 template <int NTP, bool DEFL, int PREC>
 __global__ void __launch_bounds__((GramCfg<NTP, DEFL, PREC>::THREADS))
 __attribute__((amdgpu_waves_per_eu(GramCfg<NTP, DEFL, PREC>::MIN_WAVES)))
@@ -252,40 +294,7 @@ k_gram(Workspace ws) {
                 }
             }
         } else {
-            // K blocks of 32 = 16 pixels x (re, im); lane group g holds pixels 4g..4g+3.
-            // Position (i, j): S from (A_i, A_j), T from (A_i swapped, A_j).
-            const int g = lane >> 4, col = lane & 15;
-#pragma unroll
-            for (int kb = 0; kb < PIX; kb += 16) {
-                const int wofs = kb + 4 * g;
-                int cur_a = -1;
-                u32x4 ah = u32x4{0, 0, 0, 0}, al = ah, sh = ah, sl = ah;
-#pragma unroll
-                for (int m = 0; m < C::MAXP; ++m) {
-                    if (valid[m]) {
-                        if (aoff[m] != cur_a) {
-                            cur_a = aoff[m];
-                            ah = *reinterpret_cast<const u32x4*>(Ah + (cur_a + col) * LDB + wofs);
-                            al = *reinterpret_cast<const u32x4*>(Al + (cur_a + col) * LDB + wofs);
-                            sh = swap_neg(ah);
-                            sl = swap_neg(al);
-                        }
-                        const u32x4 bh = *reinterpret_cast<const u32x4*>(Ah + (boff[m] + col) * LDB + wofs);
-                        const u32x4 bl = *reinterpret_cast<const u32x4*>(Al + (boff[m] + col) * LDB + wofs);
-                        const bf16x8 xa_h = __builtin_bit_cast(bf16x8, ah), xa_l = __builtin_bit_cast(bf16x8, al);
-                        const bf16x8 xs_h = __builtin_bit_cast(bf16x8, sh), xs_l = __builtin_bit_cast(bf16x8, sl);
-                        const bf16x8 xb_h = __builtin_bit_cast(bf16x8, bh), xb_l = __builtin_bit_cast(bf16x8, bl);
-                        floatx4& sa = acc[2 * m];
-                        floatx4& ta = acc[2 * m + 1];
-                        sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_h, sa, 0, 0, 0);
-                        ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_h, xb_h, ta, 0, 0, 0);
-                        sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_h, xb_l, sa, 0, 0, 0);
-                        ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_h, xb_l, ta, 0, 0, 0);
-                        sa = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa_l, xb_h, sa, 0, 0, 0);
-                        ta = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xs_l, xb_h, ta, 0, 0, 0);
-                    }
-                }
-            }
+            gram_mfma_bf16<C>(Ah, Al, aoff, boff, valid, acc, lane);
         }
     }
 #pragma unroll
@@ -297,6 +306,263 @@ k_gram(Workspace ws) {
         }
     }
 }
+// Pass 2 in split BF16 (DEFLATE). Each batch of PX box pixels goes through:
+//  A  coalesced loads -> raw s (FP32) and the split rows w s (LDS)
+//  B  tissue scores y = (w s) V_r on MFMA, split BF16, K split over waves (any
+//     y keeps C_w = C' + Y V_r^H exact, so its precision is free)
+//  C  each wave sums the partial scores of its own pixels in a fixed order and
+//     writes the y columns of the operand
+//  D  c' = w s - y V_r^H in FP64, one lane per frame: every V_r row read from
+//     LDS serves all pixels of the wave
+//  E  the Gram MFMAs over [c' | y] (as in pass 1)
+template <int NTP>
+struct DeflCfg {
+    using GC = GramCfg<NTP, true, 1>;
+    static constexpr int NTE = GC::NTE, LDB = GC::LDB, PX = GC::PX;
+    static constexpr int WAVES = GC::WAVES, THREADS = GC::THREADS;
+    static constexpr int TSTEP = THREADS / PX;            // phase A: pixel tid % PX, frames tid / PX + TSTEP i
+    static constexpr int NPT = (NTP + TSTEP - 1) / TSTEP;
+    static constexpr int MT = PX / 16;                    // y row tiles
+    static constexpr int KSTEPS = NTP / 16;               // K blocks of 32 over (frame, re/im)
+    static constexpr int KG = WAVES / MT;                 // K groups (one partial each)
+    static constexpr int MAXKS = (KSTEPS + KG - 1) / KG;
+    static constexpr int LDS_S = NTP + 1;                 // raw row stride (float2), odd
+    static constexpr int FPT = (NTP + 63) / 64;           // phase D frames per lane
+    static constexpr int PPW = PX / WAVES;                // phase D pixels per wave
+    static_assert(PX % 16 == 0 && WAVES % MT == 0 && THREADS % PX == 0, "tiling");
+    static_assert(PPW * 16 <= 128 && PPW >= 1, "phase C lanes");
+};
+
+template <int NTP>
+__global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace ws) {
+    using D = DeflCfg<NTP>;
+    using C = typename D::GC;
+    constexpr int NTE = D::NTE, LDB = D::LDB, PX = D::PX, WAVES = D::WAVES;
+    __shared__ __attribute__((aligned(16))) uint32_t Aw[2 * NTE * LDB];
+    __shared__ float2 sraw[PX * D::LDS_S];
+    __shared__ double2 vrs[RMAX * NTP];                  // V_r, [j][t]
+    __shared__ float ypart[D::KG * PX * 16];
+    __shared__ float2 ysh[PX * RMAX];
+    __shared__ double wsh[PX];
+    uint32_t* Ah = Aw;
+    uint32_t* Al = Aw + NTE * LDB;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, col = lane & 15;
+    const ChunkDesc ch = ws.chunks[blockIdx.x];
+    const SubsetDesc sd = ws.sub[ch.s];
+    const int nt = sd.nt, nx = sd.nx;
+    const long npix = (long)sd.ny * sd.nx;
+    const double* wy = ws.wtab + sd.wy_off;
+    const double* wx = ws.wtab + sd.wx_off;
+    const int r = ws.rank[ch.s];
+    for (int e = tid; e < NTP * RMAX; e += D::THREADS) {
+        const int t = e / RMAX, j = e % RMAX;
+        vrs[j * NTP + t] = ws.vr64[(long)ch.s * NTP * RMAX + e];
+    }
+
+    // Phase B operands of this wave: row tile ymt, K steps ykg + KG i. Column n of
+    // the real form: n < 8 gives Re y_n, n >= 8 gives Im y_(n-8); K row (t, re)
+    // holds (Re v, Im v) and (t, im) holds (-Im v, Re v).
+    const int ymt = wave % D::MT, ykg = wave / D::MT;
+    u32x4 vbh[D::MAXKS], vbl[D::MAXKS];
+#pragma unroll
+    for (int i = 0; i < D::MAXKS; ++i) {
+        const int ks = ykg + D::KG * i;
+        const int j = col & 7;
+        const bool imcol = col >= 8;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int t = 16 * ks + 4 * g + e;
+            float kr = 0.f, ki = 0.f;
+            if (ks < D::KSTEPS && t < nt && j < r) {
+                const float2 v = ws.vr32[((long)ch.s * NTP + t) * RMAX + j];
+                kr = imcol ? v.y : v.x;
+                ki = imcol ? v.x : -v.y;
+            }
+            uint32_t h, l;
+            split_bf16x2(kr, ki, h, l);
+            vbh[i][e] = h;
+            vbl[i][e] = l;
+        }
+    }
+
+    // Gram tile positions (contiguous upper positions, S and T of each)
+    int aoff[C::MAXP], boff[C::MAXP];
+    bool valid[C::MAXP];
+#pragma unroll
+    for (int m = 0; m < C::MAXP; ++m) {
+        const int u = wave * C::MAXP + m;
+        valid[m] = u < C::TPM;
+        int i, j;
+        tile_ij(valid[m] ? u : 0, C::NT16, i, j);
+        aoff[m] = i * 16;
+        boff[m] = j * 16;
+    }
+    floatx4 acc[2 * C::MAXP];
+#pragma unroll
+    for (int m = 0; m < 2 * C::MAXP; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    // phase A layout and the software-pipelined loads of the next batch
+    const int my_p = tid % PX, my_t0 = tid / PX;
+    float2 nxt[D::NPT];
+    double nw = 0.0;
+    int fy = (ch.q0 + my_p) / sd.bw, fx = (ch.q0 + my_p) - fy * sd.bw;
+    auto fetch = [&](int qb) {
+        const int q = qb + my_p;
+        long poff = -1;
+        nw = 0.0;
+        if (q < ch.q1) {
+            poff = (long)(sd.y0 + fy) * nx + sd.x0 + fx;
+            nw = sd.flat ? 1.0 : wy[fy] * wx[fx];
+        }
+        fx += PX;
+        while (fx >= sd.bw) { fx -= sd.bw; ++fy; }
+#pragma unroll
+        for (int i = 0; i < D::NPT; ++i) {
+            const int t = my_t0 + D::TSTEP * i;
+            nxt[i] = (poff >= 0 && t < nt) ? sd.iq[(long)t * npix + poff] : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(ch.q0);
+    for (int qb = ch.q0; qb < ch.q1; qb += PX) {
+        __syncthreads();                           // phases D and E of the previous batch are done
+        // ---- A
+        {
+            const float wf = (float)nw;
+            if (my_t0 == 0) wsh[my_p] = nw;
+#pragma unroll
+            for (int i = 0; i < D::NPT; ++i) {
+                const int t = my_t0 + D::TSTEP * i;
+                if (t < NTP) {
+                    sraw[my_p * D::LDS_S + t] = nxt[i];
+                    uint32_t h, l;
+                    split_bf16x2(wf * nxt[i].x, wf * nxt[i].y, h, l);
+                    Ah[t * LDB + my_p] = h;
+                    Al[t * LDB + my_p] = l;
+                }
+            }
+        }
+        if (qb + PX < ch.q1) fetch(qb + PX);       // in flight until the next batch
+        __syncthreads();
+        // ---- B: y partial of row tile ymt over this wave's K steps
+        {
+            floatx4 ya = floatx4{0.f, 0.f, 0.f, 0.f};
+            const int prow = 16 * ymt + col;
+#pragma unroll
+            for (int i = 0; i < D::MAXKS; ++i) {
+                const int ks = ykg + D::KG * i;
+                if (ks < D::KSTEPS) {
+                    u32x4 xh, xl;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int t = 16 * ks + 4 * g + e;
+                        xh[e] = Ah[t * LDB + prow];
+                        xl[e] = Al[t * LDB + prow];
+                    }
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, xh), al = __builtin_bit_cast(bf16x8, xl);
+                    const bf16x8 bh = __builtin_bit_cast(bf16x8, vbh[i]), bl = __builtin_bit_cast(bf16x8, vbl[i]);
+                    ya = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, ya, 0, 0, 0);
+                    ya = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, ya, 0, 0, 0);
+                    ya = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, ya, 0, 0, 0);
+                }
+            }
+            // element (pixel 16 ymt + 4 g + i, column col)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ypart[(ykg * PX + 16 * ymt + 4 * g + i) * 16 + col] = ya[i];
+        }
+        __syncthreads();                           // also: phase B's reads of Ah/Al rows < NTP are done
+        // ---- C: scores of this wave's pixels (lane: pixel 16-lane group, column)
+#pragma unroll
+        for (int h2 = 0; h2 < (D::PPW * 16 + 63) / 64; ++h2) {
+            const int k = (lane >> 4) + 4 * h2;            // pixel of the wave
+            const bool on = k < D::PPW;
+            const int p = wave * D::PPW + (on ? k : 0);
+            float v = 0.f;
+#pragma unroll
+            for (int q = 0; q < D::KG; ++q) v += ypart[(q * PX + p) * 16 + col];
+            // (Re y_j, Im y_j) meet in lane col = j after a rotate by 8 within the row
+            const float vi = __shfl_xor(v, 8, 16);
+            const int j = col;
+            float yr = 0.f, yi = 0.f;
+            if (j < RMAX && j < r) { yr = v; yi = vi; }
+            if (on) {
+                if (j < RMAX) ysh[p * RMAX + j] = make_float2(yr, yi);
+                uint32_t hh, ll;
+                split_bf16x2(yr, yi, hh, ll);
+                Ah[(NTP + j) * LDB + p] = hh;      // REXT = 16 columns, zero beyond r
+                Al[(NTP + j) * LDB + p] = ll;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // ---- D: c' = w s - y V_r^H for frames lane + 64 f, pixels of the wave
+        {
+            double cr[D::PPW][D::FPT], ci[D::PPW][D::FPT];
+            double wp[D::PPW];
+#pragma unroll
+            for (int k = 0; k < D::PPW; ++k) {
+                const int p = wave * D::PPW + k;
+                wp[k] = wsh[p];
+#pragma unroll
+                for (int f = 0; f < D::FPT; ++f) {
+                    const int t = lane + 64 * f;
+                    const float2 c = t < NTP ? sraw[p * D::LDS_S + t] : make_float2(0.f, 0.f);
+                    cr[k][f] = wp[k] * (double)c.x;
+                    ci[k][f] = wp[k] * (double)c.y;
+                }
+            }
+            for (int j = 0; j < r; ++j) {
+                double2 v[D::FPT];
+#pragma unroll
+                for (int f = 0; f < D::FPT; ++f) {
+                    const int t = lane + 64 * f;
+                    v[f] = t < NTP ? vrs[j * NTP + t] : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int k = 0; k < D::PPW; ++k) {
+                    const float2 yk = ysh[(wave * D::PPW + k) * RMAX + j];
+                    const double yr = (double)yk.x, yi = (double)yk.y;
+#pragma unroll
+                    for (int f = 0; f < D::FPT; ++f) {
+                        // minus y * conj(v)
+                        cr[k][f] = fma(-yr, v[f].x, fma(-yi, v[f].y, cr[k][f]));
+                        ci[k][f] = fma(-yi, v[f].x, fma(yr, v[f].y, ci[k][f]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < D::PPW; ++k) {
+                const int p = wave * D::PPW + k;
+#pragma unroll
+                for (int f = 0; f < D::FPT; ++f) {
+                    const int t = lane + 64 * f;
+                    if (t < NTP) {
+                        const bool in = t < nt;
+                        uint32_t h, l;
+                        split_bf16x2(in ? (float)cr[k][f] : 0.f, in ? (float)ci[k][f] : 0.f, h, l);
+                        Ah[t * LDB + p] = h;
+                        Al[t * LDB + p] = l;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- E
+        gram_mfma_bf16<C>(Ah, Al, aoff, boff, valid, acc, lane);
+    }
+#pragma unroll
+    for (int m = 0; m < 2 * C::MAXP; ++m) {
+        const int tau = 2 * (wave * C::MAXP + (m >> 1)) + (m & 1);
+        if (tau < C::TT) {
+            float* dst = ws.partial + ((long)blockIdx.x * C::TT + tau) * 256 + lane * 4;
+            *reinterpret_cast<floatx4*>(dst) = acc[m];
+        }
+    }
+}
+
 // Sum the chunk partials of each subset in chunk order (FP64) and expand the
 // upper S/T tiles into the full Hermitian matrix out[s][NTE][NTE].
 template <int NTE>
@@ -332,7 +598,10 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, double2* out,
 template <int NTP, bool DEFL, int PREC>
 static void gram_launch(const Workspace& ws, bool reduce, hipStream_t st) {
     using C = GramCfg<NTP, DEFL, PREC>;
-    if (!reduce) hipLaunchKernelGGL((k_gram<NTP, DEFL, PREC>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
+    if (!reduce) {
+        if (DEFL && PREC == 1) hipLaunchKernelGGL((k_gram_defl<NTP>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
+        else hipLaunchKernelGGL((k_gram<NTP, DEFL, (DEFL ? 0 : PREC)>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
+    }
     else hipLaunchKernelGGL((k_gram_reduce<C::NTE>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws,
                             DEFL ? ws.rext : ws.rwin, C::TT);
 }
