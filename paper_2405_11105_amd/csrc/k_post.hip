@@ -991,6 +991,384 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
     }
 }
 
+// Split-BF16 reprojection with the tissue scores on MFMA. The packet values of
+// the tile stay in registers for all covering subsets, in the A-operand layout
+// of the score product: wave w, lane (col, g) holds s(16 a + col, 16 ks + 4 g + e)
+// for its K steps ks = w + NW i, every row tile a and e < 4. Per subset:
+//   B  partial scores y = s V_r over the wave's frames (MFMA, split BF16; any
+//      y keeps s = c' + y V_r^H exact, so its precision is free)
+//   C  the partials summed in a fixed order; the y columns of the operand
+//   D  c' = s - y V_r^H in FP64 from the same registers (each V_r value read
+//      from LDS serves the lane's NRT pixels)
+//   E  chat = [c' | y] [P; M] and the PD / IQ epilogue, as in k_reproj;
+//      V_r and the window of the next subset go to the other LDS buffers
+template <int NTP, int TR>
+struct RpSbCfg {
+    using R = RpCfg<NTP, 1, TR>;
+    static constexpr int TP = R::TP, NRT = R::NRT, NTEP = R::NTEP, LDK = R::LDK;
+    static constexpr int NW = R::NW, NTHR = R::NTHR, CTW = R::CTW, NNT = R::NNT;
+    static constexpr int QW = CTW / 2;                        // output frame tiles per wave
+    static constexpr int KSTEPS = NTP / 16;                   // score K blocks of 32 (frame, re/im)
+    static constexpr int MKS = (KSTEPS + NW - 1) / NW;        // K blocks per wave
+    static constexpr int VPT = (NTP * RMAX + NTHR - 1) / NTHR;
+};
+
+template <int NTP, int TR>
+__global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspace ws) {
+    using C = RpSbCfg<NTP, TR>;
+    constexpr int NTEP = C::NTEP, LDK = C::LDK, NTHR = C::NTHR, CTW = C::CTW, QW = C::QW;
+    constexpr int TP = C::TP, NRT = C::NRT, NW = C::NW, MKS = C::MKS, VPT = C::VPT;
+    static_assert(QW >= 1 && CTW == 2 * QW, "re and im output tiles in pairs");
+    __shared__ __attribute__((aligned(16))) uint16_t abuf[2 * TP * LDK];
+    __shared__ double2 vrs[2][RMAX * NTP];      // V_r, [j][t], double-buffered over subsets
+    __shared__ float ypart[NW * TP * 16];       // score partials [wave][pixel][column]
+    __shared__ float2 ysh[TP * RMAX];
+    __shared__ float wd[2][TP];
+    __shared__ float wsum[TP];
+    __shared__ float pdsh[NW * TP];
+    uint16_t* Ah = abuf;                        // hi: [p][LDK], re at c, im at NTEP + c
+    uint16_t* Al = abuf + TP * LDK;             // lo
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, col = lane & 15;
+    // XCD-aware order: the grid is a multiple of 8 and block b runs on XCD b % 8
+    const int per = gridDim.x >> 3;
+    const int tix = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (tix >= ws.ntiles) return;
+    const TileDesc td = ws.tiles[tix];
+    const PacketDesc pk = ws.pkts[td.pkt];
+    const int nt = pk.nt, nx = pk.nx;
+    const long npix = (long)pk.ny * pk.nx;
+    const int npx = td.x1 - td.x0 + 1;
+    static_assert(TW == 16, "one MFMA row tile per tile row");
+    auto in_tile = [&](int p) { return (p / TW) < td.nrow && (p % TW) < npx; };
+    auto pix_off = [&](int p) { return (long)(td.y + p / TW) * nx + td.x0 + p % TW; };
+    auto window = [&](const SubsetDesc& sd, int p) -> double {
+        const int y = td.y + p / TW, x = td.x0 + p % TW;
+        if (!in_tile(p) || y < sd.y0 || y > sd.y1 || x < sd.x0 || x > sd.x1) return 0.0;
+        return sd.flat ? 1.0 : ws.wtab[sd.wy_off + y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
+    };
+
+    {   // K padding and the y columns beyond RMAX stay zero for every subset
+        uint32_t* z = reinterpret_cast<uint32_t*>(abuf);
+        for (int e = tid; e < TP * LDK; e += NTHR) z[e] = 0u;
+    }
+    float2 sv[MKS][NRT][4];
+#pragma unroll
+    for (int i = 0; i < MKS; ++i)
+#pragma unroll
+        for (int a = 0; a < NRT; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ks = wave + NW * i, p = 16 * a + col, t = 16 * ks + 4 * g + e;
+                sv[i][a][e] = (ks < C::KSTEPS && in_tile(p) && t < nt) ? pk.iq[(long)t * npix + pix_off(p)]
+                                                                        : make_float2(0.f, 0.f);
+            }
+
+    double2 vnext[VPT];
+    auto vload = [&](int ci) {
+        const int s = ws.cover[td.cov_off + ci];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = tid + NTHR * i;
+            vnext[i] = e < NTP * RMAX ? ws.vr64[(long)s * NTP * RMAX + e] : make_double2(0.0, 0.0);
+        }
+    };
+    auto vstore = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = tid + NTHR * i;
+            if (e < NTP * RMAX) vrs[b][(e % RMAX) * NTP + e / RMAX] = vnext[i];
+        }
+    };
+    if (td.cov_cnt > 0) {
+        vload(0);
+        vstore(0);
+        if (tid < TP) wd[0][tid] = (float)window(ws.sub[ws.cover[td.cov_off]], tid);
+        if (td.cov_cnt > 1) vload(1);
+    }
+
+    floatx4 iq_acc[NRT][CTW];
+    float pd_acc[NRT * 4];
+#pragma unroll
+    for (int a = 0; a < NRT; ++a)
+#pragma unroll
+        for (int m = 0; m < CTW; ++m) iq_acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < NRT * 4; ++i) pd_acc[i] = 0.f;
+
+    for (int ci = 0; ci < td.cov_cnt; ++ci) {
+        const int b = ci & 1;
+        const int s = ws.cover[td.cov_off + ci];
+        const int r = ws.rank[s];
+        const float alpha = (float)ws.alpha[s];
+        const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * (NTP + REXT)) * (2 * NTP));
+        __syncthreads();            // V_r and window of this subset are in; the previous GEMM is done
+        // ---- B: partial scores of all row tiles over this wave's K blocks
+        {
+            floatx4 ya[NRT];
+#pragma unroll
+            for (int a = 0; a < NRT; ++a) ya[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const int j = col & 7;
+            const bool imc = col >= 8;
+#pragma unroll
+            for (int i = 0; i < MKS; ++i) {
+                const int ks = wave + NW * i;
+                if (ks < C::KSTEPS) {
+                    // column col of the real form: Re y_j (col < 8) or Im y_j; K row
+                    // (t, re) holds (Re v, Im v), (t, im) holds (-Im v, Re v)
+                    u32x4 bh, bl;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int t = 16 * ks + 4 * g + e;
+                        double2 v = make_double2(0.0, 0.0);
+                        if (j < r && t < nt) v = vrs[b][j * NTP + t];
+                        uint32_t h, l;
+                        split_bf16x2(imc ? (float)v.y : (float)v.x, imc ? (float)v.x : -(float)v.y, h, l);
+                        bh[e] = h;
+                        bl[e] = l;
+                    }
+                    const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh), xbl = __builtin_bit_cast(bf16x8, bl);
+#pragma unroll
+                    for (int a = 0; a < NRT; ++a) {
+                        u32x4 ah, al;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            uint32_t h, l;
+                            split_bf16x2(sv[i][a][e].x, sv[i][a][e].y, h, l);
+                            ah[e] = h;
+                            al[e] = l;
+                        }
+                        const bf16x8 xah = __builtin_bit_cast(bf16x8, ah), xal = __builtin_bit_cast(bf16x8, al);
+                        ya[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xah, xbh, ya[a], 0, 0, 0);
+                        ya[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xah, xbl, ya[a], 0, 0, 0);
+                        ya[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xal, xbh, ya[a], 0, 0, 0);
+                    }
+                }
+            }
+            // element (pixel 16 a + 4 g + i, column col)
+#pragma unroll
+            for (int a = 0; a < NRT; ++a)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ypart[(wave * TP + 16 * a + 4 * g + i) * 16 + col] = ya[a][i];
+        }
+        __syncthreads();
+        // ---- C: y(p, j) and the y columns of the operand
+        for (int e = tid; e < TP * RMAX; e += NTHR) {
+            const int p = e / RMAX, j = e % RMAX;
+            float yr = 0.f, yi = 0.f;
+            if (j < r) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    yr += ypart[(w * TP + p) * 16 + j];
+                    yi += ypart[(w * TP + p) * 16 + 8 + j];
+                }
+            }
+            ysh[p * RMAX + j] = make_float2(yr, yi);
+            uint32_t h, l;
+            split_bf16x2(yr, yi, h, l);
+            Ah[p * LDK + NTP + j] = (uint16_t)h;
+            Ah[p * LDK + NTEP + NTP + j] = (uint16_t)(h >> 16);
+            Al[p * LDK + NTP + j] = (uint16_t)l;
+            Al[p * LDK + NTEP + NTP + j] = (uint16_t)(l >> 16);
+        }
+        __syncthreads();
+        // ---- D: c' = s - y V_r^H (FP64), written as four frames per store
+#pragma unroll
+        for (int i = 0; i < MKS; ++i) {
+            const int ks = wave + NW * i;
+            if (ks < C::KSTEPS) {
+                const int t0 = 16 * ks + 4 * g;
+                double cr[NRT][4], cim[NRT][4];
+#pragma unroll
+                for (int a = 0; a < NRT; ++a)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        cr[a][e] = (double)sv[i][a][e].x;
+                        cim[a][e] = (double)sv[i][a][e].y;
+                    }
+                for (int j = 0; j < r; ++j) {
+                    double yr[NRT], yi[NRT];
+#pragma unroll
+                    for (int a = 0; a < NRT; ++a) {
+                        const float2 y = ysh[(16 * a + col) * RMAX + j];
+                        yr[a] = (double)y.x;
+                        yi[a] = (double)y.y;
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double2 v = vrs[b][j * NTP + t0 + e];
+#pragma unroll
+                        for (int a = 0; a < NRT; ++a) {
+                            // minus y * conj(v)
+                            cr[a][e] = fma(-yr[a], v.x, fma(-yi[a], v.y, cr[a][e]));
+                            cim[a][e] = fma(-yi[a], v.x, fma(yr[a], v.y, cim[a][e]));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < NRT; ++a) {
+                    uint32_t h[4], l[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool in = t0 + e < nt;
+                        split_bf16x2(in ? (float)cr[a][e] : 0.f, in ? (float)cim[a][e] : 0.f, h[e], l[e]);
+                    }
+                    const int p = 16 * a + col;
+                    // (re of frames e, e + 1) and (im of frames e, e + 1) from two split words
+                    const uint2 hre = make_uint2(__builtin_amdgcn_perm(h[1], h[0], 0x05040100u),
+                                                 __builtin_amdgcn_perm(h[3], h[2], 0x05040100u));
+                    const uint2 him = make_uint2(__builtin_amdgcn_perm(h[1], h[0], 0x07060302u),
+                                                 __builtin_amdgcn_perm(h[3], h[2], 0x07060302u));
+                    const uint2 lre = make_uint2(__builtin_amdgcn_perm(l[1], l[0], 0x05040100u),
+                                                 __builtin_amdgcn_perm(l[3], l[2], 0x05040100u));
+                    const uint2 lim = make_uint2(__builtin_amdgcn_perm(l[1], l[0], 0x07060302u),
+                                                 __builtin_amdgcn_perm(l[3], l[2], 0x07060302u));
+                    *reinterpret_cast<uint2*>(Ah + p * LDK + t0) = hre;
+                    *reinterpret_cast<uint2*>(Ah + p * LDK + NTEP + t0) = him;
+                    *reinterpret_cast<uint2*>(Al + p * LDK + t0) = lre;
+                    *reinterpret_cast<uint2*>(Al + p * LDK + NTEP + t0) = lim;
+                }
+            }
+        }
+        __syncthreads();
+        // the next subset's V_r and window go to the other buffers (last read by
+        // the previous subset, which every wave has finished)
+        if (ci + 1 < td.cov_cnt) {
+            vstore(b ^ 1);
+            if (tid < TP) wd[b ^ 1][tid] = (float)window(ws.sub[ws.cover[td.cov_off + ci + 1]], tid);
+            if (ci + 2 < td.cov_cnt) vload(ci + 2);
+        }
+        // ---- E: chat = [c' | y] [P; M]; K over the re part, each step forms
+        // out_re = a_re P_re - a_im P_im and out_im = a_re P_im + a_im P_re
+        floatx4 acc[NRT][CTW];
+#pragma unroll
+        for (int a = 0; a < NRT; ++a)
+#pragma unroll
+            for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+        constexpr int KUNR = NTP > 128 ? 1 : 2;
+#pragma unroll KUNR
+        for (int k0 = 0; k0 < NTEP; k0 += 32) {
+            const int kq = k0 + 8 * g;
+            u32x4 brh[QW], brl[QW], bih[QW], bil[QW];
+#pragma unroll
+            for (int q = 0; q < QW; ++q) {
+                const int nq = wave * QW + q;
+                brh[q] = brl[q] = bih[q] = bil[q] = u32x4{0u, 0u, 0u, 0u};
+                if (nq < C::NNT) {
+                    const uint16_t* src = planes + (long)(nq * 16 + col) * NTEP + kq;
+                    brh[q] = *reinterpret_cast<const u32x4*>(src);
+                    brl[q] = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
+                    bih[q] = *reinterpret_cast<const u32x4*>(src + 2 * NTP * NTEP);
+                    bil[q] = *reinterpret_cast<const u32x4*>(src + 3 * NTP * NTEP);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < NRT; ++a) {
+                const uint16_t* arow = Ah + (16 * a + col) * LDK + kq;
+                const uint16_t* lrow = Al + (16 * a + col) * LDK + kq;
+                const bf16x8 xrh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow));
+                const bf16x8 xrl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow));
+                const bf16x8 xih = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow + NTEP));
+                const bf16x8 xil = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow + NTEP));
+#pragma unroll
+                for (int q = 0; q < QW; ++q) {
+                    if (wave * QW + q < C::NNT) {
+                        const bf16x8 prh = __builtin_bit_cast(bf16x8, brh[q]), prl = __builtin_bit_cast(bf16x8, brl[q]);
+                        const bf16x8 pih = __builtin_bit_cast(bf16x8, bih[q]), pil = __builtin_bit_cast(bf16x8, bil[q]);
+                        u32x4 nh = bih[q], nl = bil[q];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) { nh[e] ^= 0x80008000u; nl[e] ^= 0x80008000u; }
+                        const bf16x8 nih = __builtin_bit_cast(bf16x8, nh), nil = __builtin_bit_cast(bf16x8, nl);
+                        floatx4& ore = acc[a][2 * q];
+                        floatx4& oim = acc[a][2 * q + 1];
+                        ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, prh, ore, 0, 0, 0);
+                        ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, prl, ore, 0, 0, 0);
+                        ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrl, prh, ore, 0, 0, 0);
+                        ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, nih, ore, 0, 0, 0);
+                        ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, nil, ore, 0, 0, 0);
+                        ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xil, nih, ore, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, pih, oim, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, pil, oim, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrl, pih, oim, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, prh, oim, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, prl, oim, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xil, prh, oim, 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // epilogue: output element (pixel 16 a + 4 g + i, column tile of accumulator m)
+#pragma unroll
+        for (int a = 0; a < NRT; ++a)
+#pragma unroll
+            for (int m = 0; m < CTW; ++m) {
+                if (wave * QW + (m >> 1) < C::NNT) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float w = wd[b][16 * a + 4 * g + i];
+                        const float v = acc[a][m][i];
+                        pd_acc[a * 4 + i] += alpha * w * w * v * v;
+                        iq_acc[a][m][i] += w * v;
+                    }
+                }
+            }
+    }
+    // PD: reduce over the 16 lanes that share pixel rows, then over waves
+#pragma unroll
+    for (int i = 0; i < NRT * 4; ++i) {
+        float v = pd_acc[i];
+        for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+        pd_acc[i] = v;
+    }
+    __syncthreads();
+    if (col == 0) {
+#pragma unroll
+        for (int i = 0; i < NRT * 4; ++i) pdsh[wave * TP + (i >> 2) * 16 + 4 * g + (i & 3)] = pd_acc[i];
+    }
+    if (tid < TP) {
+        double ws_ = 0.0;
+        for (int ci = 0; ci < td.cov_cnt; ++ci) ws_ += window(ws.sub[ws.cover[td.cov_off + ci]], tid);
+        wsum[tid] = (float)ws_;
+    }
+    __syncthreads();
+    if (tid < TP && in_tile(tid)) {
+        const int p = tid;
+        float pdv = 0.f;
+        for (int w = 0; w < NW; ++w) pdv += pdsh[w * TP + p];
+        if (pk.pd_mode == 2) {
+            double comp = 0.0;
+            for (int ci = 0; ci < td.cov_cnt; ++ci) {
+                const int s = ws.cover[td.cov_off + ci];
+                const double w = window(ws.sub[s], p);
+                comp += ws.alpha[s] * w * w;
+            }
+            pdv = comp > 0.0 ? (float)((double)pdv / comp) : 0.f;
+        }
+        pk.pd[pix_off(p)] = pdv;
+    }
+    if (pk.iq_out) {
+#pragma unroll
+        for (int a = 0; a < NRT; ++a)
+#pragma unroll
+            for (int m = 0; m < CTW; ++m) {
+                const int q = wave * QW + (m >> 1);
+                if (q < C::NNT) {
+                    const int part_ = m & 1, t = q * 16 + col;
+                    if (t < nt) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int p = 16 * a + 4 * g + i;
+                            if (in_tile(p)) {
+                                const float w = wsum[p];
+                                pk.iq_out[2 * ((long)t * npix + pix_off(p)) + part_] = w > 0.f ? iq_acc[a][m][i] / w : 0.f;
+                            }
+                        }
+                    }
+                }
+            }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <int NTP>
@@ -1012,14 +1390,14 @@ static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t 
                 if (prec == 0)
                     hipLaunchKernelGGL((k_reproj<NTP, 0, 4>), dim3(grid), dim3(RpCfg<NTP, 0, 4>::NTHR), 0, st, ws);
                 else
-                    hipLaunchKernelGGL((k_reproj<NTP, 1, 4>), dim3(grid), dim3(RpCfg<NTP, 1, 4>::NTHR), 0, st, ws);
+                    hipLaunchKernelGGL((k_reproj_sb<NTP, 4>), dim3(grid), dim3(RpSbCfg<NTP, 4>::NTHR), 0, st, ws);
                 return;
             }
         }
         if (prec == 0)
             hipLaunchKernelGGL((k_reproj<NTP, 0, 2>), dim3(grid), dim3(RpCfg<NTP, 0, 2>::NTHR), 0, st, ws);
         else
-            hipLaunchKernelGGL((k_reproj<NTP, 1, 2>), dim3(grid), dim3(RpCfg<NTP, 1, 2>::NTHR), 0, st, ws);
+            hipLaunchKernelGGL((k_reproj_sb<NTP, 2>), dim3(grid), dim3(RpSbCfg<NTP, 2>::NTHR), 0, st, ws);
     }
 }
 
