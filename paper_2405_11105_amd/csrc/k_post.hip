@@ -1023,7 +1023,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
     __shared__ double2 vrs[2][RMAX * NTP];      // V_r, [j][t], double-buffered over subsets
     __shared__ float ypart[NW * TP * 16];       // score partials [wave][pixel][column]
     __shared__ float2 ysh[TP * RMAX];
-    __shared__ float wd[2][TP];
+    __shared__ float wd[TP];
     __shared__ float wsum[TP];
     __shared__ float pdsh[NW * TP];
     uint16_t* Ah = abuf;                        // hi: [p][LDK], re at c, im at NTEP + c
@@ -1065,8 +1065,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
             }
 
     double2 vnext[VPT];
-    auto vload = [&](int ci) {
-        const int s = ws.cover[td.cov_off + ci];
+    auto vload = [&](int s) {
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             const int e = tid + NTHR * i;
@@ -1080,12 +1079,32 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
             if (e < NTP * RMAX) vrs[b][(e % RMAX) * NTP + e / RMAX] = vnext[i];
         }
     };
-    if (td.cov_cnt > 0) {
-        vload(0);
+    // Subset data is requested ahead of use so that no chain of dependent global
+    // loads sits between two barriers: the cover index two subsets ahead, and
+    // rank, weight and window geometry one subset ahead.
+    struct SubNext {
+        int s, r, y0, y1, x0, x1, flat, wy_off, wx_off;
+        double alpha;
+    };
+    auto sub_load = [&](int s) {
+        const SubsetDesc* d = ws.sub + s;
+        return SubNext{s, ws.rank[s], d->y0, d->y1, d->x0, d->x1, d->flat, d->wy_off, d->wx_off, ws.alpha[s]};
+    };
+    const int ncov = td.cov_cnt;
+    SubNext nxt = SubNext{0, 0, 0, -1, 0, -1, 1, 0, 0, 0.0};
+    int s_ahead = 0;
+    if (ncov > 0) {
+        const int s0 = ws.cover[td.cov_off];
+        nxt = sub_load(s0);
+        vload(s0);
         vstore(0);
-        if (tid < TP) wd[0][tid] = (float)window(ws.sub[ws.cover[td.cov_off]], tid);
-        if (td.cov_cnt > 1) vload(1);
+        if (ncov > 1) {
+            s_ahead = ws.cover[td.cov_off + 1];
+            vload(s_ahead);
+        }
     }
+    // window sum and sum of alpha w^2 of this thread's pixel (tid < TP), FP64
+    double wsum_acc = 0.0, comp_acc = 0.0;
 
     floatx4 iq_acc[NRT][CTW];
     float pd_acc[NRT * 4];
@@ -1096,13 +1115,24 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
 #pragma unroll
     for (int i = 0; i < NRT * 4; ++i) pd_acc[i] = 0.f;
 
-    for (int ci = 0; ci < td.cov_cnt; ++ci) {
+    for (int ci = 0; ci < ncov; ++ci) {
         const int b = ci & 1;
-        const int s = ws.cover[td.cov_off + ci];
-        const int r = ws.rank[s];
-        const float alpha = (float)ws.alpha[s];
+        const SubNext cur = nxt;
+        const int s = cur.s, r = cur.r;
+        const float alpha = (float)cur.alpha;
         const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * (NTP + REXT)) * (2 * NTP));
-        __syncthreads();            // V_r and window of this subset are in; the previous GEMM is done
+        if (ci + 1 < ncov) nxt = sub_load(s_ahead);
+        const int s_ahead2 = ci + 2 < ncov ? ws.cover[td.cov_off + ci + 2] : 0;
+        // this subset's window factors of the thread's pixel (written to LDS after D)
+        double wyv = 0.0, wxv = 0.0;
+        if (tid < TP) {
+            const int y = td.y + tid / TW, x = td.x0 + tid % TW;
+            if (in_tile(tid) && y >= cur.y0 && y <= cur.y1 && x >= cur.x0 && x <= cur.x1) {
+                wyv = cur.flat ? 1.0 : ws.wtab[cur.wy_off + y - cur.y0];
+                wxv = cur.flat ? 1.0 : ws.wtab[cur.wx_off + x - cur.x0];
+            }
+        }
+        __syncthreads();            // V_r of this subset is in; the previous GEMM is done
         // ---- B: partial scores of all row tiles over this wave's K blocks
         {
             floatx4 ya[NRT];
@@ -1230,14 +1260,20 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
                 }
             }
         }
-        __syncthreads();
-        // the next subset's V_r and window go to the other buffers (last read by
-        // the previous subset, which every wave has finished)
-        if (ci + 1 < td.cov_cnt) {
-            vstore(b ^ 1);
-            if (tid < TP) wd[b ^ 1][tid] = (float)window(ws.sub[ws.cover[td.cov_off + ci + 1]], tid);
-            if (ci + 2 < td.cov_cnt) vload(ci + 2);
+        if (tid < TP) {
+            const double w = wyv * wxv;
+            wd[tid] = (float)w;
+            wsum_acc += w;
+            comp_acc += cur.alpha * w * w;
         }
+        __syncthreads();
+        // the next subset's V_r goes to the other buffer (last read by the
+        // previous subset, which every wave has finished)
+        if (ci + 1 < ncov) {
+            vstore(b ^ 1);
+            if (ci + 2 < ncov) vload(s_ahead2);
+        }
+        s_ahead = s_ahead2;
         // ---- E: chat = [c' | y] [P; M]; K over the re part, each step forms
         // out_re = a_re P_re - a_im P_im and out_im = a_re P_im + a_im P_re
         floatx4 acc[NRT][CTW];
@@ -1305,7 +1341,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
                 if (wave * QW + (m >> 1) < C::NNT) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const float w = wd[b][16 * a + 4 * g + i];
+                        const float w = wd[16 * a + 4 * g + i];
                         const float v = acc[a][m][i];
                         pd_acc[a * 4 + i] += alpha * w * w * v * v;
                         iq_acc[a][m][i] += w * v;
@@ -1325,25 +1361,13 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
 #pragma unroll
         for (int i = 0; i < NRT * 4; ++i) pdsh[wave * TP + (i >> 2) * 16 + 4 * g + (i & 3)] = pd_acc[i];
     }
-    if (tid < TP) {
-        double ws_ = 0.0;
-        for (int ci = 0; ci < td.cov_cnt; ++ci) ws_ += window(ws.sub[ws.cover[td.cov_off + ci]], tid);
-        wsum[tid] = (float)ws_;
-    }
+    if (tid < TP) wsum[tid] = (float)wsum_acc;
     __syncthreads();
     if (tid < TP && in_tile(tid)) {
         const int p = tid;
         float pdv = 0.f;
         for (int w = 0; w < NW; ++w) pdv += pdsh[w * TP + p];
-        if (pk.pd_mode == 2) {
-            double comp = 0.0;
-            for (int ci = 0; ci < td.cov_cnt; ++ci) {
-                const int s = ws.cover[td.cov_off + ci];
-                const double w = window(ws.sub[s], p);
-                comp += ws.alpha[s] * w * w;
-            }
-            pdv = comp > 0.0 ? (float)((double)pdv / comp) : 0.f;
-        }
+        if (pk.pd_mode == 2) pdv = comp_acc > 0.0 ? (float)((double)pdv / comp_acc) : 0.f;
         pk.pd[pix_off(p)] = pdv;
     }
     if (pk.iq_out) {
