@@ -755,25 +755,24 @@ constexpr int FLAG_EVD_FALLBACK = 16;
 template <int RPL, int NW>
 __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
     constexpr int N = 16 * NW;             // padded size held (columns)
-    constexpr int NTHR = 64 * NW;
     static_assert(64 * RPL >= N, "rows per lane cover the padded size");
-    __shared__ double2 xsh[N];             // column j
-    __shared__ double2 vsh[N];             // Householder vector v_j
+    __shared__ double2 vshb[2][N];         // Householder vector v_j, by the parity of j
     __shared__ double2 psh[NW * N];        // per-wave partials of A v
-    __shared__ double2 qsh[N];             // p = tau A v, then q
-    __shared__ double red[2 * NW];
+    __shared__ double2 qsh[N];             // p = tau A v
+    __shared__ double red[2];
     __shared__ double dsh[N], esh[N], e2sh[N];
-    __shared__ double2 phs[N];             // D
+    __shared__ double2 phs[N];             // complex e_j, then D
     __shared__ double lamsh[N], insh[N];
+    __shared__ double dml[N * N];          // [i][k]: D- of eigenvalue k, then its z
     __shared__ double bnd[2];
+    __shared__ double tau_sh[2];
     __shared__ int cluster;
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nt = ws.sub[s].nt;
     double2* Bm = ws.bmat + (long)s * N * N;
     double2* H = ws.wvec + (long)s * N * N;                 // Householder vectors, tau in element 0
-    double* Dm = reinterpret_cast<double*>(ws.pmat + (long)s * N * N);   // [i][k]
-    double* Dp = Dm + N * N;                                // [i][k], then z
+    double* Dp = reinterpret_cast<double*>(ws.pmat + (long)s * N * N);   // [i][k]: D+
     if (tid == 0) cluster = 0;
 
     double2 A[16][RPL];
@@ -787,45 +786,59 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
         }
     }
 
-    // ---- 1. Householder reduction
+    // ---- 1. Householder reduction, three barriers per column
     for (int j = 0; j + 2 < nt; ++j) {
+        // the wave forming v_{j+1} may start while others still apply v_j
+        double2* vsh = vshb[j & 1];
         const int jw = j >> 4, jc = j & 15;
         const int wstart = (j + 1) >> 4;          // waves below hold only finished columns
         if (wave == jw) {
+            // the reflector of column j (rows j + 1 ..), formed by the wave that holds it
+            double2 x[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                x[i] = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c == jc) x[i] = A[c][i];
+            }
+            double s2 = 0.0;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int row = lane + 64 * i;
-                double2 x = make_double2(0.0, 0.0);
+                if (row > j + 1 && row < nt) s2 += cabs2(x[i]);
+            }
+            s2 = wave_sum(s2);
+            double2 t1 = x[0], t0 = x[0];
 #pragma unroll
-                for (int c = 0; c < 16; ++c)
-                    if (c == jc) x = A[c][i];
-                if (row < N) xsh[row] = x;
+            for (int i = 1; i < RPL; ++i) {
+                if (i == ((j + 1) >> 6)) t1 = x[i];
+                if (i == (j >> 6)) t0 = x[i];
+            }
+            const double2 x0 = make_double2(rdl(t1.x, (j + 1) & 63), rdl(t1.y, (j + 1) & 63));
+            const double xjj = rdl(t0.x, j & 63);
+            const double ax0 = sqrt(cabs2(x0));
+            const double alpha = sqrt(s2 + ax0 * ax0);
+            const double2 ph = ax0 > 0.0 ? cscale(x0, 1.0 / ax0) : make_double2(1.0, 0.0);
+            const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                if (row < N) {
+                    const double2 v = row <= j ? make_double2(0.0, 0.0)
+                                               : (row == j + 1 ? cadd(x0, cscale(ph, alpha)) : x[i]);
+                    vsh[row] = v;
+                    H[(long)j * N + row] = row == 0 ? make_double2(tau, 0.0) : v;   // row 0 of v_j is zero: holds tau
+                }
+            }
+            if (lane == 0) {
+                dsh[j] = xjj;
+                phs[j] = cscale(ph, -alpha);                           // complex e_j for now
+                tau_sh[j & 1] = tau;
             }
         }
         __syncthreads();
-        double s2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int row = lane + 64 * i;
-            if (row > j + 1 && row < nt) s2 += cabs2(xsh[row]);
-        }
-        s2 = wave_sum(s2);
-        const double2 x0 = xsh[j + 1];
-        const double ax0 = sqrt(cabs2(x0));
-        const double alpha = sqrt(s2 + ax0 * ax0);
-        const double2 ph = ax0 > 0.0 ? cscale(x0, 1.0 / ax0) : make_double2(1.0, 0.0);
-        const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
-        if (tid < N) {
-            const double2 v = tid <= j ? make_double2(0.0, 0.0)
-                                       : (tid == j + 1 ? cadd(x0, cscale(ph, alpha)) : xsh[tid]);
-            vsh[tid] = v;
-            H[(long)j * N + tid] = tid == 0 ? make_double2(tau, 0.0) : v;   // row 0 of v_j is zero: holds tau
-        }
-        if (tid == 0) {
-            dsh[j] = xsh[j].x;
-            phs[j] = cscale(ph, -alpha);                               // complex e_j for now
-        }
-        __syncthreads();
+        const double tau = tau_sh[j & 1];
         // partial A v over this wave's columns
         if (wave >= wstart) {
             double2 acc[RPL];
@@ -847,44 +860,36 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
             }
         }
         __syncthreads();
-        // p = tau sum_w partials, and v^H p
-        double kr = 0.0, ki = 0.0;
+        // p = tau sum_w partials
         if (tid < N) {
             double2 p = make_double2(0.0, 0.0);
             for (int w = wstart; w < NW; ++w) p = cadd(p, psh[w * N + tid]);
-            p = cscale(p, tau);
-            qsh[tid] = p;
-            const double2 v = vsh[tid];
-            kr = fma(v.x, p.x, v.y * p.y);                             // conj(v) p
-            ki = fma(v.x, p.y, -v.y * p.x);
-        }
-        if (tid < ((N + 63) & ~63)) {
-            kr = wave_sum(kr);
-            ki = wave_sum(ki);
-            if (lane == 0) { red[2 * wave] = kr; red[2 * wave + 1] = ki; }
+            qsh[tid] = cscale(p, tau);
         }
         __syncthreads();
-        // q = p - (tau / 2) (v^H p) v
-        if (tid < N) {
-            double2 K = make_double2(0.0, 0.0);
-            for (int w = 0; w < (N + 63) / 64; ++w) K = cadd(K, make_double2(red[2 * w], red[2 * w + 1]));
-            K = cscale(K, 0.5 * tau);
-            qsh[tid] = csub(qsh[tid], cmul(K, vsh[tid]));
-        }
-        __syncthreads();
-        // A -= v q^H + q v^H
+        // q = p - (tau / 2) (v^H p) v, with v^H p summed in every active wave
+        // (each holds all rows), then A -= v q^H + q v^H
         if (wave >= wstart) {
             double2 vr[RPL], qr[RPL];
+            double kr = 0.0, ki = 0.0;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int row = lane + 64 * i;
                 vr[i] = row < N ? vsh[row] : make_double2(0.0, 0.0);
                 qr[i] = row < N ? qsh[row] : make_double2(0.0, 0.0);
+                kr = fma(vr[i].x, qr[i].x, fma(vr[i].y, qr[i].y, kr));       // conj(v) p
+                ki = fma(vr[i].x, qr[i].y, fma(-vr[i].y, qr[i].x, ki));
             }
+            kr = wave_sum(kr);
+            ki = wave_sum(ki);
+            const double2 K = make_double2(0.5 * tau * kr, 0.5 * tau * ki);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) qr[i] = csub(qr[i], cmul(K, vr[i]));
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 const int col = 16 * wave + c;
-                const double2 vc = vsh[col], qc = qsh[col];
+                const double2 vc = vsh[col];
+                const double2 qc = csub(qsh[col], cmul(K, vc));
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
                     double ax = A[c][i].x, ay = A[c][i].y;
@@ -913,107 +918,154 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
         }
     }
     __syncthreads();
-    // ---- 2. real tridiagonal: |e_j| and the phases D (d_0 = 1, d_{j+1} = d_j e_j / |e_j|)
-    if (tid == 0) {
-        double2 d = make_double2(1.0, 0.0);
-        double emax = 0.0, lo = 1e300, hi = -1e300;
-        for (int j = 0; j < nt; ++j) {
-            double2 e = j + 1 < nt ? phs[j] : make_double2(0.0, 0.0);
-            const double ae = sqrt(cabs2(e));
-            phs[j] = d;
+    // ---- 2. real tridiagonal (wave 0, element j in lane j % 64, register j / 64):
+    // |e_j|, the phases D (d_0 = 1, d_{j+1} = d_j e_j / |e_j|, a prefix product
+    // by a shuffle scan) and the Gershgorin interval
+    if (wave == 0) {
+        double2 u[RPL];
+        double ae[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int j = lane + 64 * i;
+            const double2 e = j + 1 < nt ? phs[j] : make_double2(0.0, 0.0);
+            ae[i] = sqrt(cabs2(e));
+            u[i] = ae[i] > 0.0 ? cscale(e, 1.0 / ae[i]) : make_double2(1.0, 0.0);
             if (j + 1 < nt) {
-                esh[j] = ae;
-                e2sh[j] = ae * ae;
-                emax = fmax(emax, ae * ae);
-                d = ae > 0.0 ? cmul(d, cscale(e, 1.0 / ae)) : d;
+                esh[j] = ae[i];
+                e2sh[j] = ae[i] * ae[i];
             }
-            const double rad = (j > 0 ? esh[j - 1] : 0.0) + (j + 1 < nt ? ae : 0.0);
-            lo = fmin(lo, dsh[j] - rad);
-            hi = fmax(hi, dsh[j] + rad);
         }
-        const double margin = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
-        bnd[0] = lo - margin;
-        bnd[1] = hi + margin;
-        red[0] = 1e-290 * fmax(1.0, emax);                             // pivmin
+        // inclusive products within each 64-element segment, then across segments
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const double2 t = make_double2(__shfl_up(u[i].x, off, 64), __shfl_up(u[i].y, off, 64));
+                if (lane >= off) u[i] = cmul(t, u[i]);
+            }
+        double2 carry = make_double2(1.0, 0.0);
+        double2 dexc[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const double2 incl = cmul(carry, u[i]);
+            const double2 prev = make_double2(__shfl_up(incl.x, 1, 64), __shfl_up(incl.y, 1, 64));
+            dexc[i] = lane == 0 ? carry : prev;
+            carry = make_double2(rdl(incl.x, 63), rdl(incl.y, 63));
+        }
+        double lo = 1e300, hi = -1e300, emax = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int j = lane + 64 * i;
+            if (j < N) phs[j] = dexc[i];
+            if (j < nt) {
+                const double aprev = __shfl_up(ae[i], 1, 64);
+                const double aprv = lane == 0 ? (i > 0 ? rdl(ae[i - 1 >= 0 ? i - 1 : 0], 63) : 0.0) : aprev;
+                const double rad = (j > 0 ? aprv : 0.0) + (j + 1 < nt ? ae[i] : 0.0);
+                lo = fmin(lo, dsh[j] - rad);
+                hi = fmax(hi, dsh[j] + rad);
+                if (j + 1 < nt) emax = fmax(emax, ae[i] * ae[i]);
+            }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, m, 64));
+            hi = fmax(hi, __shfl_xor(hi, m, 64));
+            emax = fmax(emax, __shfl_xor(emax, m, 64));
+        }
+        if (lane == 0) {
+            const double margin = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+            bnd[0] = lo - margin;
+            bnd[1] = hi + margin;
+            red[0] = 1e-290 * fmax(1.0, emax);                         // pivmin
+        }
     }
     __syncthreads();
     const double pivmin = red[0];
-    // ---- 3. eigenvalues by multisection (lanes 4k .. 4k+3 for the k-th largest)
+    // ---- 3. eigenvalues by multisection: lanes 4k .. 4k+3 for the k-th largest,
+    // two Sturm counts per lane (8 points, 9 sub-intervals per round)
     {
         const int k = tid >> 2, m = tid & 3;
         const int target = nt - 1 - k;                                 // index among ascending
         double a = bnd[0], b = bnd[1];
-        for (int it = 0; it < 28; ++it) {
-            const double x = a + (double)(m + 1) * 0.2 * (b - a);
-            int cnt = 0;
+        for (int it = 0; it < 18; ++it) {
+            const double h = (b - a) * (1.0 / 9.0);
+            const double xa = a + (double)(2 * m + 1) * h, xb = a + (double)(2 * m + 2) * h;
+            int ca = 0, cb = 0;
             if (k < nt) {
-                double q = dsh[0] - x;
-                cnt = q < 0.0;
+                double qa = dsh[0] - xa, qb = dsh[0] - xb;
+                ca = qa < 0.0;
+                cb = qb < 0.0;
                 for (int i = 1; i < nt; ++i) {
-                    if (fabs(q) < pivmin) q = -pivmin;
-                    q = (dsh[i] - x) - e2sh[i - 1] * rcp_nr(q);
-                    cnt += q < 0.0;
+                    const double di = dsh[i], ei = e2sh[i - 1];
+                    if (fabs(qa) < pivmin) qa = -pivmin;
+                    if (fabs(qb) < pivmin) qb = -pivmin;
+                    qa = (di - xa) - ei * rcp_nr(qa);
+                    qb = (di - xb) - ei * rcp_nr(qb);
+                    ca += qa < 0.0;
+                    cb += qb < 0.0;
                 }
             }
-            const int base = lane & ~3;
-            double na = a, nb = b;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int cu = __shfl(cnt, base + u, 64);
-                const double xu = a + (double)(u + 1) * 0.2 * (b - a);
-                if (cu <= target) na = xu;
-            }
-#pragma unroll
-            for (int u = 3; u >= 0; --u) {
-                const int cu = __shfl(cnt, base + u, 64);
-                const double xu = a + (double)(u + 1) * 0.2 * (b - a);
-                if (cu > target) nb = xu;
-            }
+            // counts are nondecreasing in x: the points left of the eigenvalue are
+            // those with count <= target
+            int le = (ca <= target) + (cb <= target);
+            le += __shfl_xor(le, 1, 64);
+            le += __shfl_xor(le, 2, 64);
+            const double na = a + (double)le * h;
+            b = le == 8 ? b : a + (double)(le + 1) * h;
             a = na;
-            b = nb;
         }
         if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
     }
     __syncthreads();
-    // ---- 4. eigenvectors of T_r by twisted factorisation (lane k)
+    // ---- 4. eigenvectors of T_r by twisted factorisation (lane k); D- and then
+    // z live in LDS, D+ goes to scratch and is read back eight at a time
     if (tid < nt) {
         const int k = tid;
         const double lam = lamsh[k];
         if (k + 1 < nt && lamsh[k] - lamsh[k + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
         double q = dsh[nt - 1] - lam;
-        Dm[(long)(nt - 1) * N + k] = q;
+        dml[(nt - 1) * N + k] = q;
         for (int i = nt - 2; i >= 0; --i) {
             if (fabs(q) < pivmin) q = -pivmin;
             q = (dsh[i] - lam) - e2sh[i] * rcp_nr(q);
-            Dm[(long)i * N + k] = q;
+            dml[i * N + k] = q;
         }
         double p = dsh[0] - lam;
         Dp[k] = p;
         int r = 0;
-        double g = fabs(Dm[k]);
+        double g = fabs(dml[k]);
         for (int i = 0; i + 1 < nt; ++i) {
             if (fabs(p) < pivmin) p = -pivmin;
             p = (dsh[i + 1] - lam) - e2sh[i] * rcp_nr(p);
             Dp[(long)(i + 1) * N + k] = p;
-            const double gam = p + Dm[(long)(i + 1) * N + k] - (dsh[i + 1] - lam);
+            const double gam = p + dml[(i + 1) * N + k] - (dsh[i + 1] - lam);
             if (fabs(gam) < g) { g = fabs(gam); r = i + 1; }
         }
-        // z overwrites Dp: below r from Dp, above r from Dm
+        // z_r = 1; below r from D+, above r from D- (each D- is read before its
+        // slot takes the z value)
         double z = 1.0, nrm = 1.0;
-        Dp[(long)r * N + k] = 1.0;
-        for (int i = r - 1; i >= 0; --i) {
-            double d = Dp[(long)i * N + k];
-            if (fabs(d) < pivmin) d = -pivmin;
-            z = -esh[i] * rcp_nr(d) * z;
-            Dp[(long)i * N + k] = z;
-            nrm += z * z;
+        dml[r * N + k] = 1.0;
+        for (int i = r - 1; i >= 0; i -= 8) {
+            double dv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dv[u] = i - u >= 0 ? Dp[(long)(i - u) * N + k] : 1.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (i - u >= 0) {
+                    double d = dv[u];
+                    if (fabs(d) < pivmin) d = -pivmin;
+                    z = -esh[i - u] * rcp_nr(d) * z;
+                    dml[(i - u) * N + k] = z;
+                    nrm += z * z;
+                }
+            }
         }
         z = 1.0;
         for (int i = r; i + 1 < nt; ++i) {
-            double d = Dm[(long)(i + 1) * N + k];
+            double d = dml[(i + 1) * N + k];
             if (fabs(d) < pivmin) d = -pivmin;
             z = -esh[i] * rcp_nr(d) * z;
-            Dp[(long)(i + 1) * N + k] = z;
+            dml[(i + 1) * N + k] = z;
             nrm += z * z;
         }
         insh[k] = rsq_nr(nrm);
@@ -1023,25 +1075,35 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
         if (tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
         return;
     }
-    // ---- 5. y = Q D z in registers, reflectors in reverse order
+    // ---- 5. y = Q D z in registers, reflectors in reverse order (the next
+    // reflector is loaded while the current one is applied)
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int col = 16 * wave + c;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
-            A[c][i] = (row < nt && col < nt) ? cscale(phs[row], Dp[(long)row * N + col] * insh[col])
+            A[c][i] = (row < nt && col < nt) ? cscale(phs[row], dml[row * N + col] * insh[col])
                                              : make_double2(0.0, 0.0);
         }
     }
-    for (int j = nt - 3; j >= 0; --j) {
-        const double tauj = H[(long)j * N].x;
-        double2 vr[RPL];
+    double2 vn[RPL];
+    double taun = 0.0;
+    auto hload = [&](int j) {
+        taun = H[(long)j * N].x;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
-            vr[i] = (row > j && row < N) ? H[(long)j * N + row] : make_double2(0.0, 0.0);
+            vn[i] = (row > j && row < N) ? H[(long)j * N + row] : make_double2(0.0, 0.0);
         }
+    };
+    if (nt >= 3) hload(nt - 3);
+    for (int j = nt - 3; j >= 0; --j) {
+        const double tauj = taun;
+        double2 vr[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) vr[i] = vn[i];
+        if (j > 0) hload(j - 1);
         // w_c = v^H y_c for this wave's 16 columns: lane partials, then a
         // transposed reduction leaving value (l >> 1) in lane l
         double v32[32];
