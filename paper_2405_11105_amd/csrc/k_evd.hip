@@ -839,7 +839,9 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
         }
         __syncthreads();
         const double tau = tau_sh[j & 1];
-        // partial A v over this wave's columns
+        // partial A v over this wave's columns (row blocks i with 64 i + 63 <= j
+        // hold only finished rows, where v and A v vanish)
+        const int ilo = (j + 1) >> 6;
         if (wave >= wstart) {
             double2 acc[RPL];
 #pragma unroll
@@ -849,6 +851,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
                 const double2 vc = vsh[16 * wave + c];
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
+                    if (i < ilo) continue;
                     acc[i].x = fma(A[c][i].x, vc.x, fma(-A[c][i].y, vc.y, acc[i].x));
                     acc[i].y = fma(A[c][i].x, vc.y, fma(A[c][i].y, vc.x, acc[i].y));
                 }
@@ -892,6 +895,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
                 const double2 qc = csub(qsh[col], cmul(K, vc));
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
+                    if (i < ilo) continue;              // finished rows keep their values
                     double ax = A[c][i].x, ay = A[c][i].y;
                     ax = fma(-vr[i].x, qc.x, fma(-vr[i].y, qc.y, ax));
                     ay = fma(-vr[i].y, qc.x, fma(vr[i].x, qc.y, ay));
@@ -982,36 +986,33 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
     __syncthreads();
     const double pivmin = red[0];
     // ---- 3. eigenvalues by multisection: lanes 4k .. 4k+3 for the k-th largest,
-    // two Sturm counts per lane (8 points, 9 sub-intervals per round)
+    // one Sturm count per lane (4 points, 5 sub-intervals per round; 24 rounds
+    // narrow the Gershgorin interval by 5^24 ~ 6e16, below the rounding of the
+    // largest eigenvalue)
     {
         const int k = tid >> 2, m = tid & 3;
         const int target = nt - 1 - k;                                 // index among ascending
         double a = bnd[0], b = bnd[1];
-        for (int it = 0; it < 18; ++it) {
-            const double h = (b - a) * (1.0 / 9.0);
-            const double xa = a + (double)(2 * m + 1) * h, xb = a + (double)(2 * m + 2) * h;
-            int ca = 0, cb = 0;
+        for (int it = 0; it < 24; ++it) {
+            const double h = (b - a) * 0.2;
+            const double x = a + (double)(m + 1) * h;
+            int cnt = 0;
             if (k < nt) {
-                double qa = dsh[0] - xa, qb = dsh[0] - xb;
-                ca = qa < 0.0;
-                cb = qb < 0.0;
+                double q = dsh[0] - x;
+                cnt = q < 0.0;
                 for (int i = 1; i < nt; ++i) {
-                    const double di = dsh[i], ei = e2sh[i - 1];
-                    if (fabs(qa) < pivmin) qa = -pivmin;
-                    if (fabs(qb) < pivmin) qb = -pivmin;
-                    qa = (di - xa) - ei * rcp_nr(qa);
-                    qb = (di - xb) - ei * rcp_nr(qb);
-                    ca += qa < 0.0;
-                    cb += qb < 0.0;
+                    if (fabs(q) < pivmin) q = -pivmin;
+                    q = (dsh[i] - x) - e2sh[i - 1] * rcp_nr(q);
+                    cnt += q < 0.0;
                 }
             }
             // counts are nondecreasing in x: the points left of the eigenvalue are
             // those with count <= target
-            int le = (ca <= target) + (cb <= target);
+            int le = cnt <= target;
             le += __shfl_xor(le, 1, 64);
             le += __shfl_xor(le, 2, 64);
             const double na = a + (double)le * h;
-            b = le == 8 ? b : a + (double)(le + 1) * h;
+            b = le == 4 ? b : a + (double)(le + 1) * h;
             a = na;
         }
         if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
