@@ -93,126 +93,210 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
 }
 
 // ------------------------------------------------------------------ projector
-// P_Q = I - sum_i (1 - w_i) u_i u_i^H in the deflated basis (exactly P_Q =
-// U diag(w) U^H on the range of B; on its null space the data carry no energy,
-// and all-ones weights give P = I exactly), then P = Q P_Q Q^H by Householder
-// rank-2 updates, M = V_r^H P, and the real-form [P; M] used by the
-// reprojection GEMM.
+// With the eigenvectors W of B = Q^H R Q (Q = H_0 .. H_{r-1}) and the weights w,
+// the projector of Eq. 4 in the original basis is
+//   P = Q (I - W diag(1 - w) W^H) Q^H = I - W' diag(1 - w) W'^H,  W' = Q W,
+// (exactly U diag(w) U^H on the range of B; all-ones weights give P = I). Only
+// the columns with w != 1 enter. Since V_r = Q [e_0 .. e_{r-1}],
+//   M = V_r^H P = V_r^H - W[0..r-1, :] diag(1 - w) W'^H.
+// Per chunk of PCC columns: W' by the r reflectors (16 lanes per column), then
+// the P block in registers (thread: 8 consecutive rows t x 8 columns u with
+// stride 16, 128 x 128 per pass) and M in LDS; finally the real-form or
+// split-BF16 [P; M] planes used by the reprojection GEMM.
+constexpr int PCC = 16;
+
 template <int NTP, int PREC>
 __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     constexpr int NTE = NTP + REXT;
     constexpr int NTEP = (NTE + 31) / 32 * 32;
-    constexpr int CC = 8;                       // eigenvector columns staged per pass
-    __shared__ double2 Wc[CC * NTP];
-    __shared__ double cw[CC];
-    __shared__ double2 V[NTP * RMAX];
-    __shared__ double2 Pv[NTP], vh[NTP];
-    __shared__ double red[32];
-    __shared__ int act[256];
-    __shared__ int nact;
-    const int s = blockIdx.x, tid = threadIdx.x;
+    constexpr int NB = (NTP + 127) / 128;       // 128 x 128 blocks per dimension
+    constexpr int RW = NTP / 16;                // rows per lane in the reflector pass
+    __shared__ double2 Wl[PCC * NTP];           // chunk of W, then W', [c][t]
+    __shared__ double2 vh[RMAX * NTP];          // reflectors [j][t]
+    __shared__ double2 Msh[RMAX * NTP];         // M [j][n]
+    __shared__ double2 Wj[RMAX * PCC];          // rows 0 .. r-1 of the chunk of W
+    __shared__ double cw[PCC];
+    __shared__ double tau[RMAX];
+    __shared__ int act[NTP];
+    __shared__ int wcnt[4];
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nt = ws.sub[s].nt;
     const int r = ws.rank[s];
     const double2* W = ws.bmat + (long)s * NTP * NTP;        // column-major eigenvectors
     const double* wts = ws.wts + (long)s * NTP;
-    double2* P = ws.pmat + (long)s * NTP * NTP;
-    if (tid == 0) {
-        int n = 0;
-        for (int i = 0; i < nt; ++i)
-            if (fabs(1.0 - wts[i]) > 1e-17) act[n++] = i;
-        nact = n;
+
+    // active columns (w != 1) in ascending order, by ballots
+    const bool flag = tid < nt && fabs(1.0 - wts[tid < NTP ? tid : 0]) > 1e-17;
+    const unsigned long long mask = __ballot(flag);
+    if (lane == 0) wcnt[wave] = __popcll(mask);
+    for (int e = tid; e < RMAX * NTP; e += 256) {
+        const int j = e / NTP, t = e % NTP;
+        vh[e] = j < r ? ws.hv[((long)s * RMAX + j) * NTP + t] : make_double2(0.0, 0.0);
+        // M starts from V_r^H (zero beyond nt and r)
+        Msh[e] = (j < r && t < nt) ? cconj(ws.vr64[((long)s * NTP + t) * RMAX + j]) : make_double2(0.0, 0.0);
     }
-    for (int e = tid; e < NTP * NTP; e += 256) {
-        const int t = e / NTP, u = e % NTP;
-        P[e] = make_double2((t == u && t < nt) ? 1.0 : 0.0, 0.0);
-    }
+    if (tid < RMAX) tau[tid] = tid < r ? ws.htau[(long)s * RMAX + tid] : 0.0;
     __syncthreads();
-    for (int c0 = 0; c0 < nact; c0 += CC) {
-        const int cn = nact - c0 < CC ? nact - c0 : CC;
-        for (int e = tid; e < cn * NTP; e += 256) {
-            const int c = e / NTP, t = e % NTP;
-            Wc[e] = W[(long)act[c0 + c] * NTP + t];
-        }
-        if (tid < cn) cw[tid] = 1.0 - wts[act[c0 + tid]];
-        __syncthreads();
-        for (int e = tid; e < nt * NTP; e += 256) {
-            const int t = e / NTP, u = e % NTP;
-            if (u >= nt) continue;
-            double2 acc = P[e];
-            for (int c = 0; c < cn; ++c)
-                acc = csub(acc, cscale(cmulc(Wc[c * NTP + u], Wc[c * NTP + t]), cw[c]));  // W_t conj(W_u)
-            P[e] = acc;
-        }
-        __syncthreads();
+    int nact = 0, off = 0;
+    for (int w = 0; w < 4; ++w) {
+        off += w < wave ? wcnt[w] : 0;
+        nact += wcnt[w];
     }
-    // P = H_0 .. H_{r-1} P_Q H_{r-1} .. H_0
-    for (int j = r - 1; j >= 0; --j) {
-        const double tau = ws.htau[(long)s * RMAX + j];
-        for (int t = tid; t < NTP; t += 256) vh[t] = ws.hv[((long)s * RMAX + j) * NTP + t];
-        __syncthreads();
-        for (int t = tid; t < nt; t += 256) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int u = 0; u < nt; ++u) acc = cadd(acc, cmulc(P[(long)u * NTP + t], vh[u]));
-            Pv[t] = acc;
-        }
-        __syncthreads();
-        double part = 0.0;
-        for (int t = tid; t < nt; t += 256) part += cmulc(vh[t], Pv[t]).x;
-        const double K = block_sum(part, red);
-        for (int t = tid; t < nt; t += 256) Pv[t] = csub(Pv[t], cscale(vh[t], 0.5 * tau * K));
-        __syncthreads();
-        for (int e = tid; e < nt * NTP; e += 256) {
-            const int t = e / NTP, u = e % NTP;
-            if (u >= nt) continue;
-            const double2 d = cadd(cmulc(Pv[u], vh[t]), cmulc(vh[u], Pv[t]));
-            P[e] = csub(P[e], cscale(d, tau));
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < NTP * RMAX; e += 256) V[e] = ws.vr64[(long)s * NTP * RMAX + e];
+    if (flag) act[off + __popcll(mask & ((1ull << lane) - 1ull))] = tid;
     __syncthreads();
-    if (PREC == 1) {
-        // Split-BF16 planes of [P; M]^T, K-contiguous: plane q in (re hi, re lo,
-        // im hi, im lo), row n (output frame), column k (operand column).
-        uint16_t* pt = reinterpret_cast<uint16_t*>(ws.breal + (long)s * (2 * NTE) * (2 * NTP));
-        for (int e = tid; e < NTP * NTEP; e += 256) {
-            const int n = e / NTEP, k = e % NTEP;
-            double2 v = make_double2(0.0, 0.0);
-            if (n < nt) {
-                if (k < nt) v = P[(long)k * NTP + n];
-                else if (k >= NTP && k < NTP + r) {
-                    const int j = k - NTP;
-                    for (int u = 0; u < nt; ++u) v = cadd(v, cmulc(V[u * RMAX + j], P[(long)u * NTP + n]));
+
+    const int ti = tid >> 4, ui = tid & 15;
+    for (int bb = 0; bb < NB * NB; ++bb) {
+        const int tb = 128 * (bb / NB), ub = 128 * (bb % NB);
+        double2 acc[8][8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 8; ++b) acc[a][b] = make_double2(0.0, 0.0);
+        for (int c0 = 0; c0 < nact; c0 += PCC) {
+            const int cn = nact - c0 < PCC ? nact - c0 : PCC;
+            // W' of the chunk: column c by lanes 16 c .. 16 c + 15, rows l + 16 i
+            {
+                const int c = tid >> 4, l = tid & 15;
+                double2 x[RW];
+#pragma unroll
+                for (int i = 0; i < RW; ++i)
+                    x[i] = c < cn ? W[(long)act[c0 + c] * NTP + l + 16 * i] : make_double2(0.0, 0.0);
+                if (bb == 0 && l < RMAX) Wj[l * PCC + c] = x[0];
+                for (int j = r - 1; j >= 0; --j) {
+                    double dr = 0.0, di = 0.0;
+#pragma unroll
+                    for (int i = 0; i < RW; ++i) {
+                        const double2 v = vh[j * NTP + l + 16 * i];
+                        dr = fma(v.x, x[i].x, fma(v.y, x[i].y, dr));       // conj(v) x
+                        di = fma(v.x, x[i].y, fma(-v.y, x[i].x, di));
+                    }
+#pragma unroll
+                    for (int m = 8; m >= 1; m >>= 1) {
+                        dr += __shfl_xor(dr, m, 16);
+                        di += __shfl_xor(di, m, 16);
+                    }
+                    const double2 d = make_double2(tau[j] * dr, tau[j] * di);
+#pragma unroll
+                    for (int i = 0; i < RW; ++i) x[i] = csub(x[i], cmul(vh[j * NTP + l + 16 * i], d));
+                }
+#pragma unroll
+                for (int i = 0; i < RW; ++i) Wl[c * NTP + l + 16 * i] = x[i];
+                if (tid < PCC) cw[tid] = tid < cn ? 1.0 - wts[act[c0 + tid]] : 0.0;
+            }
+            __syncthreads();
+            // P block: acc[a][b] -= cw_c W'[t_a][c] conj(W'[u_b][c])
+            for (int c = 0; c < cn; ++c) {
+                double2 wt[8], wu[8];
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    const int t = tb + 8 * ti + a;
+                    wt[a] = t < NTP ? cscale(Wl[c * NTP + t], cw[c]) : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int u = ub + ui + 16 * b;
+                    wu[b] = u < NTP ? Wl[c * NTP + u] : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) {
+                        acc[a][b].x -= fma(wt[a].x, wu[b].x, wt[a].y * wu[b].y);
+                        acc[a][b].y -= fma(wt[a].y, wu[b].x, -wt[a].x * wu[b].y);
+                    }
+            }
+            // M once: M[j][n] -= sum_c W[j][c] (1 - w_c) conj(W'[n][c])
+            if (bb == 0) {
+                for (int e = tid; e < RMAX * NTP; e += 256) {
+                    const int j = e / NTP, n = e % NTP;
+                    if (j < r && n < nt) {
+                        double2 m = Msh[e];
+                        for (int c = 0; c < cn; ++c) {
+                            const double2 q = cscale(Wj[j * PCC + c], cw[c]);
+                            const double2 wn = Wl[c * NTP + n];
+                            m.x -= fma(q.x, wn.x, q.y * wn.y);            // q conj(wn)
+                            m.y -= fma(q.y, wn.x, -q.x * wn.y);
+                        }
+                        Msh[e] = m;
+                    }
                 }
             }
-            const float re = (float)v.x, im = (float)v.y;
-            const uint32_t rh = bf16_bits(re), ih = bf16_bits(im);
-            const uint32_t rl = bf16_bits(re - __uint_as_float(rh << 16));
-            const uint32_t il = bf16_bits(im - __uint_as_float(ih << 16));
-            pt[(long)0 * NTP * NTEP + e] = (uint16_t)rh;
-            pt[(long)1 * NTP * NTEP + e] = (uint16_t)rl;
-            pt[(long)2 * NTP * NTEP + e] = (uint16_t)ih;
-            pt[(long)3 * NTP * NTEP + e] = (uint16_t)il;
+            __syncthreads();
         }
-        return;
-    }
-    // Real form of [P; M]: row kk in [0, 2 NTE), column n in [0, 2 NTP).
-    float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
-    for (int e = tid; e < NTE * NTP; e += 256) {
-        const int k = e / NTP, t = e % NTP;
-        double2 v = make_double2(0.0, 0.0);
-        if (t < nt) {
-            if (k < nt) v = P[(long)k * NTP + t];
-            else if (k >= NTP && k < NTP + r) {
-                const int j = k - NTP;
-                for (int u = 0; u < nt; ++u) v = cadd(v, cmulc(V[u * RMAX + j], P[(long)u * NTP + t]));
+        // write the block: operand row k = t, output frame n = u; P = I - ... on
+        // [0, nt) x [0, nt), zero elsewhere
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int n = ub + ui + 16 * b;
+            if (n >= NTP) continue;
+            float re[8], im[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int k = tb + 8 * ti + a;
+                const bool in = k < nt && n < nt;
+                re[a] = in ? (float)((k == n ? 1.0 : 0.0) + acc[a][b].x) : 0.f;
+                im[a] = in ? (float)acc[a][b].y : 0.f;
+            }
+            const int k0 = tb + 8 * ti;
+            if (k0 >= NTP) continue;
+            if (PREC == 1) {
+                uint16_t* pt = reinterpret_cast<uint16_t*>(ws.breal + (long)s * (2 * NTE) * (2 * NTP));
+                uint32_t h[8], l[8];
+#pragma unroll
+                for (int a = 0; a < 8; ++a) split_bf16x2(re[a], im[a], h[a], l[a]);
+                u32x4 hr, lr, hi4, li4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    hr[q] = __builtin_amdgcn_perm(h[2 * q + 1], h[2 * q], 0x05040100u);
+                    lr[q] = __builtin_amdgcn_perm(l[2 * q + 1], l[2 * q], 0x05040100u);
+                    hi4[q] = __builtin_amdgcn_perm(h[2 * q + 1], h[2 * q], 0x07060302u);
+                    li4[q] = __builtin_amdgcn_perm(l[2 * q + 1], l[2 * q], 0x07060302u);
+                }
+                const long e = (long)n * NTEP + k0;
+                *reinterpret_cast<u32x4*>(pt + 0L * NTP * NTEP + e) = hr;
+                *reinterpret_cast<u32x4*>(pt + 1L * NTP * NTEP + e) = lr;
+                *reinterpret_cast<u32x4*>(pt + 2L * NTP * NTEP + e) = hi4;
+                *reinterpret_cast<u32x4*>(pt + 3L * NTP * NTEP + e) = li4;
+            } else {
+                // real form: row k of [P; M] at k, its i-multiple at NTE + k
+                float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    const int k = k0 + a;
+                    Br[(long)k * (2 * NTP) + n] = re[a];
+                    Br[(long)k * (2 * NTP) + NTP + n] = im[a];
+                    Br[(long)(NTE + k) * (2 * NTP) + n] = -im[a];
+                    Br[(long)(NTE + k) * (2 * NTP) + NTP + n] = re[a];
+                }
             }
         }
-        const float re = (float)v.x, im = (float)v.y;
-        Br[(long)k * (2 * NTP) + t] = re;
-        Br[(long)k * (2 * NTP) + NTP + t] = im;
-        Br[(long)(NTE + k) * (2 * NTP) + t] = -im;
-        Br[(long)(NTE + k) * (2 * NTP) + NTP + t] = re;
+    }
+    // rows k in [NTP, NTEP) of the operand: M for k < NTP + r, zero beyond
+    if (PREC == 1) {
+        uint16_t* pt = reinterpret_cast<uint16_t*>(ws.breal + (long)s * (2 * NTE) * (2 * NTP));
+        for (int e = tid; e < NTP * (NTEP - NTP); e += 256) {
+            const int n = e / (NTEP - NTP), j = e % (NTEP - NTP);
+            const double2 v = j < RMAX ? Msh[j * NTP + n] : make_double2(0.0, 0.0);
+            uint32_t h, l;
+            split_bf16x2((float)v.x, (float)v.y, h, l);
+            const long o = (long)n * NTEP + NTP + j;
+            pt[0L * NTP * NTEP + o] = (uint16_t)h;
+            pt[1L * NTP * NTEP + o] = (uint16_t)l;
+            pt[2L * NTP * NTEP + o] = (uint16_t)(h >> 16);
+            pt[3L * NTP * NTEP + o] = (uint16_t)(l >> 16);
+        }
+    } else {
+        float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
+        for (int e = tid; e < REXT * NTP; e += 256) {
+            const int j = e / NTP, n = e % NTP;
+            const double2 v = j < RMAX ? Msh[j * NTP + n] : make_double2(0.0, 0.0);
+            const int k = NTP + j;
+            Br[(long)k * (2 * NTP) + n] = (float)v.x;
+            Br[(long)k * (2 * NTP) + NTP + n] = (float)v.y;
+            Br[(long)(NTE + k) * (2 * NTP) + n] = -(float)v.y;
+            Br[(long)(NTE + k) * (2 * NTP) + NTP + n] = (float)v.x;
+        }
     }
 }
 
