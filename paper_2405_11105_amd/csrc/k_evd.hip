@@ -30,83 +30,115 @@ __global__ void __launch_bounds__(256) k_windows(Workspace ws) {
 // valid for the deflation identity C_w = C' + (C_w V_r) V_r^H; accuracy of V_r
 // only decides how small C' is.
 
-// Tiny Hermitian EVD by cyclic Jacobi, single thread (n <= RMAX).
-__device__ void small_heev(double2* h, double2* z, double* th, int n) {
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) z[i * RMAX + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                const double a = cabs2(h[i * RMAX + j]);
-                tot += a;
-                if (i != j) off += a;
-            }
-        if (off <= 1e-30 * tot || off == 0.0) break;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const double2 apq = h[p * RMAX + q];
-                const double mag = sqrt(cabs2(apq));
-                if (mag == 0.0) continue;
-                const double2 ph = make_double2(apq.x / mag, apq.y / mag);
-                const double theta = (h[q * RMAX + q].x - h[p * RMAX + p].x) / (2.0 * mag);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                // J = [[c, s], [-s conj(ph), c conj(ph)]]
-                const double2 j00 = make_double2(c, 0.0), j01 = make_double2(s, 0.0);
-                const double2 j10 = make_double2(-s * ph.x, s * ph.y), j11 = make_double2(c * ph.x, -c * ph.y);
-                for (int i = 0; i < n; ++i) {   // columns: H J, Z J
-                    const double2 a = h[i * RMAX + p], b = h[i * RMAX + q];
-                    h[i * RMAX + p] = cadd(cmul(a, j00), cmul(b, j10));
-                    h[i * RMAX + q] = cadd(cmul(a, j01), cmul(b, j11));
-                    const double2 za = z[i * RMAX + p], zb = z[i * RMAX + q];
-                    z[i * RMAX + p] = cadd(cmul(za, j00), cmul(zb, j10));
-                    z[i * RMAX + q] = cadd(cmul(za, j01), cmul(zb, j11));
-                }
-                for (int i = 0; i < n; ++i) {   // rows: J^H (H J)
-                    const double2 a = h[p * RMAX + i], b = h[q * RMAX + i];
-                    h[p * RMAX + i] = cadd(cmulc(j00, a), cmulc(j10, b));
-                    h[q * RMAX + i] = cadd(cmulc(j01, a), cmulc(j11, b));
-                }
-            }
+// Tiny Hermitian EVD (order RMAX = 8, zero-padded) by parallel cyclic Jacobi on
+// one wave: lane l holds H[l / 8][l % 8] and Z[l / 8][l % 8]. A sweep is 7
+// rounds of 4 disjoint pairs (circle schedule). All rotations of a round are
+// formed from the entries before it (disjoint pairs do not touch each other's
+// 2 x 2 blocks), then H <- H J, Z <- Z J and H <- J^H H for every pair, with
+//   J = [[c, s], [-s conj(e), c conj(e)]] for pair p < q,  e = H_pq / |H_pq|,
+//   theta = (H_qq - H_pp) / (2 |H_pq|), t = sign(theta) / (|theta| + sqrt(theta^2 + 1)),
+//   c = 1 / sqrt(t^2 + 1), s = t c.
+static_assert(RMAX == 8, "one wave holds the 8 x 8 Ritz matrix");
+
+__device__ __forceinline__ int circle_partner(int m, int k) {
+    // players 1..7 sit at positions (m - 1 + k) mod 7 and player 0 at the hub;
+    // the hub meets position 0, position i meets position 7 - i
+    if (m == 0) return ((7 - k) % 7) + 1;
+    const int pos = (m - 1 + k) % 7;
+    if (pos == 0) return 0;
+    return ((7 - pos - k + 14) % 7) + 1;
+}
+
+__device__ __forceinline__ double2 shfl2(double2 v, int src) {
+    return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+__device__ __forceinline__ void jac8_params(double2 h, int p, int q, double2& j00, double2& j01, double2& j10,
+                                            double2& j11) {
+    const double2 apq = shfl2(h, p * 8 + q);
+    const double hpp = __shfl(h.x, p * 9, 64), hqq = __shfl(h.x, q * 9, 64);
+    const double mag = sqrt(cabs2(apq));
+    j00 = make_double2(1.0, 0.0);
+    j01 = make_double2(0.0, 0.0);
+    j10 = make_double2(0.0, 0.0);
+    j11 = make_double2(1.0, 0.0);
+    if (mag > 0.0) {
+        const double2 ph = make_double2(apq.x / mag, apq.y / mag);
+        const double theta = (hqq - hpp) / (2.0 * mag);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        j00 = make_double2(c, 0.0);
+        j01 = make_double2(sn, 0.0);
+        j10 = make_double2(-sn * ph.x, sn * ph.y);
+        j11 = make_double2(c * ph.x, -c * ph.y);
     }
-    for (int i = 0; i < n; ++i) th[i] = h[i * RMAX + i].x;
+}
+
+__device__ void wave_heev8(double2& h, double2& z, int lane) {
+    const int i = lane >> 3, j = lane & 7;
+    z = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        const double a = cabs2(h);
+        const double tot = wave_sum(a), off = wave_sum(i != j ? a : 0.0);
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int k = 0; k < 7; ++k) {
+            const int pj = circle_partner(j, k), pi = circle_partner(i, k);
+            const int pc = j < pj ? j : pj, qc = j < pj ? pj : j;
+            const int pr = i < pi ? i : pi, qr = i < pi ? pi : i;
+            double2 c00, c01, c10, c11, r00, r01, r10, r11;
+            jac8_params(h, pc, qc, c00, c01, c10, c11);
+            jac8_params(h, pr, qr, r00, r01, r10, r11);
+            // columns: H J, Z J
+            const double2 hp = shfl2(h, i * 8 + pc), hq = shfl2(h, i * 8 + qc);
+            const double2 zp = shfl2(z, i * 8 + pc), zq = shfl2(z, i * 8 + qc);
+            if (j == pc) {
+                h = cadd(cmul(hp, c00), cmul(hq, c10));
+                z = cadd(cmul(zp, c00), cmul(zq, c10));
+            } else {
+                h = cadd(cmul(hp, c01), cmul(hq, c11));
+                z = cadd(cmul(zp, c01), cmul(zq, c11));
+            }
+            // rows: J^H (H J)
+            const double2 gp = shfl2(h, pr * 8 + j), gq = shfl2(h, qr * 8 + j);
+            h = i == pr ? cadd(cmulc(r00, gp), cmulc(r10, gq)) : cadd(cmulc(r01, gp), cmulc(r11, gq));
+        }
+    }
 }
 
 template <int NTP>
 __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int iters) {
+    constexpr int XR = (NTP + 63) / 64;         // rows per lane in the one-wave passes
     __shared__ double2 X[NTP * RMAX];
     __shared__ double2 Y[NTP * RMAX];
     __shared__ double2 H[RMAX * RMAX], Z[RMAX * RMAX];
     __shared__ double th[RMAX];
+    __shared__ double dg[NTP];
     __shared__ int piv[RMAX], order[RMAX];
     __shared__ double red[32];
-    __shared__ int sh_r, sh_ns;
-    const int s = blockIdx.x, tid = threadIdx.x;
+    __shared__ int sh_r;
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const SubsetDesc sd = ws.sub[s];
     const int nt = sd.nt;
     const double2* R = ws.rwin + (long)s * NTP * NTP;
     double2* hv = ws.hv + (long)s * RMAX * NTP;
     double* htau = ws.htau + (long)s * RMAX;
+    const int ns = nt < RMAX ? nt : RMAX;
 
-    if (tid == 0) {
-        // start block: columns of R at the largest diagonal entries
-        int ns = nt < RMAX ? nt : RMAX;
-        for (int j = 0; j < ns; ++j) {
-            int best = j;          // fallback keeps the index in range (e.g. NaN diagonals)
-            double bv = -1.0;
-            for (int t = 0; t < nt; ++t) {
-                bool used = false;
-                for (int i = 0; i < j; ++i) used |= (piv[i] == t);
-                const double d = R[(long)t * NTP + t].x;
-                if (!used && d > bv) { bv = d; best = t; }
-            }
-            piv[j] = best;
-        }
-        sh_ns = ns;
+    // start block: the columns of R at its ns largest diagonal entries, found by
+    // the rank of each entry (ties by index; NaN ranks last)
+    for (int t = tid; t < nt; t += 256) {
+        const double d = R[(long)t * NTP + t].x;
+        dg[t] = d == d ? d : -1e300;
+    }
+    if (tid < RMAX) piv[tid] = tid;
+    __syncthreads();
+    for (int t = tid; t < nt; t += 256) {
+        const double d = dg[t];
+        int rk = 0;
+        for (int u = 0; u < nt; ++u) rk += (dg[u] > d) || (dg[u] == d && u < t);
+        if (rk < ns) piv[rk] = t;
     }
     __syncthreads();
-    const int ns = sh_ns;
     for (int e = tid; e < NTP * RMAX; e += 256) {
         const int t = e / RMAX, j = e % RMAX;
         // R[t][piv] = conj(R[piv][t])
@@ -114,33 +146,76 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
     }
     __syncthreads();
 
+    // modified Gram-Schmidt, two passes, in the registers of wave 0
     auto orthonormalize = [&]() {
-        for (int pass = 0; pass < 2; ++pass)
-            for (int j = 0; j < ns; ++j) {
-                for (int i = 0; i < j; ++i) {
-                    double2 part = make_double2(0.0, 0.0);
-                    for (int t = tid; t < nt; t += 256) part = cadd(part, cmulc(X[t * RMAX + i], X[t * RMAX + j]));
-                    const double2 dot = block_sum2(part, red);
-                    for (int t = tid; t < nt; t += 256) X[t * RMAX + j] = csub(X[t * RMAX + j], cmul(dot, X[t * RMAX + i]));
-                    __syncthreads();
+        if (wave == 0) {
+            double2 x[XR][RMAX];
+#pragma unroll
+            for (int i = 0; i < XR; ++i)
+#pragma unroll
+                for (int j = 0; j < RMAX; ++j) {
+                    const int t = lane + 64 * i;
+                    x[i][j] = t < nt ? X[t * RMAX + j] : make_double2(0.0, 0.0);
                 }
-                double part = 0.0;
-                for (int t = tid; t < nt; t += 256) part += cabs2(X[t * RMAX + j]);
-                const double nrm = sqrt(block_sum(part, red));
-                const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-                for (int t = tid; t < nt; t += 256) X[t * RMAX + j] = cscale(X[t * RMAX + j], inv);
-                __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                for (int j = 0; j < RMAX; ++j) {
+                    if (j >= ns) continue;
+#pragma unroll
+                    for (int q = 0; q < j; ++q) {
+                        double dr = 0.0, di = 0.0;                 // conj(x_q) x_j
+#pragma unroll
+                        for (int i = 0; i < XR; ++i) {
+                            dr = fma(x[i][q].x, x[i][j].x, fma(x[i][q].y, x[i][j].y, dr));
+                            di = fma(x[i][q].x, x[i][j].y, fma(-x[i][q].y, x[i][j].x, di));
+                        }
+                        const double2 dot = make_double2(wave_sum(dr), wave_sum(di));
+#pragma unroll
+                        for (int i = 0; i < XR; ++i) x[i][j] = csub(x[i][j], cmul(dot, x[i][q]));
+                    }
+                    double n2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < XR; ++i) n2 += cabs2(x[i][j]);
+                    const double nrm = sqrt(wave_sum(n2));
+                    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+#pragma unroll
+                    for (int i = 0; i < XR; ++i) x[i][j] = cscale(x[i][j], inv);
+                }
             }
+#pragma unroll
+            for (int i = 0; i < XR; ++i)
+#pragma unroll
+                for (int j = 0; j < RMAX; ++j) {
+                    const int t = lane + 64 * i;
+                    if (t < NTP) X[t * RMAX + j] = x[i][j];
+                }
+        }
+        __syncthreads();
     };
-    auto apply_R = [&]() {   // Y = R X, coalesced through R[u][t] = conj(R[t][u])
-        for (int t = tid; t < nt; t += 256) {
+    // Y = R X, coalesced through R[u][t] = conj(R[t][u]); two threads per row t
+    // (alternate u), combined by a lane swap
+    auto apply_R = [&]() {
+        for (int t0 = 0; t0 < nt; t0 += 128) {
+            const int t = t0 + (tid >> 1), half = tid & 1;
             double2 acc[RMAX];
+#pragma unroll
             for (int j = 0; j < RMAX; ++j) acc[j] = make_double2(0.0, 0.0);
-            for (int u = 0; u < nt; ++u) {
-                const double2 rtu = cconj(R[(long)u * NTP + t]);
-                for (int j = 0; j < RMAX; ++j) acc[j] = cadd(acc[j], cmul(rtu, X[u * RMAX + j]));
+            if (t < nt) {
+                for (int u = half; u < nt; u += 2) {
+                    const double2 rtu = cconj(R[(long)u * NTP + t]);
+#pragma unroll
+                    for (int j = 0; j < RMAX; ++j) acc[j] = cadd(acc[j], cmul(rtu, X[u * RMAX + j]));
+                }
             }
-            for (int j = 0; j < RMAX; ++j) Y[t * RMAX + j] = acc[j];
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j) {
+                acc[j].x += __shfl_xor(acc[j].x, 1, 64);
+                acc[j].y += __shfl_xor(acc[j].y, 1, 64);
+            }
+            if (t < nt && half == 0) {
+#pragma unroll
+                for (int j = 0; j < RMAX; ++j) Y[t * RMAX + j] = acc[j];
+            }
         }
         __syncthreads();
     };
@@ -161,17 +236,20 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
         H[tid] = acc;
     }
     __syncthreads();
+    if (wave == 0) {
+        // Hermitian part (rounding), then the Ritz pairs
+        const int i = lane >> 3, j = lane & 7;
+        const double2 a = H[lane], b = H[j * RMAX + i];
+        double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+        if (i == j) h.y = 0.0;
+        double2 z;
+        wave_heev8(h, z, lane);
+        Z[lane] = z;
+        if (i == j) th[i] = h.x;
+    }
+    __syncthreads();
     if (tid == 0) {
-        // Hermitian part (rounding), then EVD, then order descending
-        for (int i = 0; i < ns; ++i)
-            for (int j = i; j < ns; ++j) {
-                const double2 a = H[i * RMAX + j], b = H[j * RMAX + i];
-                const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-                H[i * RMAX + j] = m;
-                H[j * RMAX + i] = cconj(m);
-                if (i == j) H[i * RMAX + i].y = 0.0;
-            }
-        small_heev(H, Z, th, ns);
+        // order descending, then the rank cut
         for (int i = 0; i < ns; ++i) order[i] = i;
         for (int i = 0; i < ns; ++i)
             for (int j = i + 1; j < ns; ++j)
