@@ -335,15 +335,19 @@ __global__ void __launch_bounds__(256) k_assemble(Workspace ws) {
     constexpr int NTE = NTP + REXT;
     __shared__ double2 E[NTP * RMAX];
     __shared__ double2 V[NTP * RMAX];
-    __shared__ double2 P[NTP];
-    __shared__ double2 vh[NTP];
-    __shared__ double red[32];
+    __shared__ double2 P[2][NTP];
+    __shared__ double2 vh[RMAX * NTP];
+    __shared__ double red[2][16];
     const int s = blockIdx.x, tid = threadIdx.x;
     const int nt = ws.sub[s].nt;
     const int r = ws.rank[s];
     const double2* X = ws.rext + (long)s * NTE * NTE;
     double2* B = ws.bmat + (long)s * NTP * NTP;
-    for (int e = tid; e < NTP * RMAX; e += 256) V[e] = ws.vr64[(long)s * NTP * RMAX + e];
+    for (int e = tid; e < NTP * RMAX; e += 256) {
+        V[e] = ws.vr64[(long)s * NTP * RMAX + e];
+        const int j = e / NTP;
+        vh[e] = j < r ? ws.hv[(long)s * RMAX * NTP + e] : make_double2(0.0, 0.0);
+    }
     __syncthreads();
     for (int e = tid; e < NTP * RMAX; e += 256) {
         const int t = e / RMAX, j = e % RMAX;
@@ -356,47 +360,131 @@ __global__ void __launch_bounds__(256) k_assemble(Workspace ws) {
         E[e] = acc;
     }
     __syncthreads();
-    for (int e = tid; e < NTP * NTP; e += 256) {
-        const int t = e / NTP, u = e % NTP;
-        double2 b = make_double2(0.0, 0.0);
-        if (t < nt && u < nt) {
-            b = X[(long)t * NTE + u];
-            for (int j = 0; j < r; ++j) {
-                b = cadd(b, cmulc(V[u * RMAX + j], E[t * RMAX + j]));   // E_tj conj(V_uj)
-                b = cadd(b, cmulc(E[u * RMAX + j], V[t * RMAX + j]));   // V_tj conj(E_uj)
+    if constexpr (NTP <= 128) {
+        // R, then B, in registers: thread (ti, ui) holds rows 8 ti + a, columns
+        // ui + 16 b. Per reflector: p = B v by lane shuffles over the 16 lanes of
+        // a row group, v^H p and the rows of p through LDS (one barrier), then
+        // B -= tau (v w^H + w v^H), w = p - (tau / 2)(v^H p) v.
+        const int ti = threadIdx.x >> 4, ui = threadIdx.x & 15;
+        double2 acc[8][8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int t = 8 * ti + a, u = ui + 16 * b;
+                double2 v = make_double2(0.0, 0.0);
+                if (t < nt && u < nt) {
+                    v = X[(long)t * NTE + u];
+                    for (int j = 0; j < r; ++j) {
+                        v = cadd(v, cmulc(V[u * RMAX + j], E[t * RMAX + j]));   // E_tj conj(V_uj)
+                        v = cadd(v, cmulc(E[u * RMAX + j], V[t * RMAX + j]));   // V_tj conj(E_uj)
+                    }
+                    if (t == u) v.y = 0.0;
+                }
+                if (t < NTP && u < NTP) ws.pmat[(long)s * NTP * NTP + (long)t * NTP + u] = v;
+                acc[a][b] = v;
             }
-            if (t == u) b.y = 0.0;
+        for (int j = 0; j < r; ++j) {
+            const double tau = ws.htau[(long)s * RMAX + j];
+            const double2* v = vh + j * NTP;
+            double2 vu[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int u = ui + 16 * b;
+                vu[b] = u < NTP ? v[u] : make_double2(0.0, 0.0);
+            }
+            double kpart = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                double2 pa = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) pa = cadd(pa, cmul(acc[a][b], vu[b]));
+#pragma unroll
+                for (int m = 8; m >= 1; m >>= 1) {
+                    pa.x += __shfl_xor(pa.x, m, 16);
+                    pa.y += __shfl_xor(pa.y, m, 16);
+                }
+                const int t = 8 * ti + a;
+                if (ui == 0 && t < NTP) P[j & 1][t] = pa;
+                if (t < NTP) kpart += cmulc(v[t], pa).x;
+            }
+            if (ui == 0) red[j & 1][ti] = kpart;
+            __syncthreads();
+            double K = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) K += red[j & 1][q];
+            const double hk = 0.5 * tau * K;
+            double2 wu[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int u = ui + 16 * b;
+                wu[b] = u < NTP ? csub(P[j & 1][u], cscale(vu[b], hk)) : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int t = 8 * ti + a;
+                const double2 vt = t < NTP ? v[t] : make_double2(0.0, 0.0);
+                const double2 wt = t < NTP ? csub(P[j & 1][t], cscale(vt, hk)) : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    // B -= tau (v_t conj(w_u) + w_t conj(v_u))
+                    const double2 d = cadd(cmulc(wu[b], vt), cmulc(vu[b], wt));
+                    double2 x = csub(acc[a][b], cscale(d, tau));
+                    if (t == ui + 16 * b) x.y = 0.0;
+                    acc[a][b] = x;
+                }
+            }
         }
-        B[e] = b;
-        ws.pmat[(long)s * NTP * NTP + e] = b;
-    }
-    __syncthreads();
-    for (int j = 0; j < r; ++j) {
-        const double tau = ws.htau[(long)s * RMAX + j];
-        for (int t = tid; t < NTP; t += 256) vh[t] = ws.hv[((long)s * RMAX + j) * NTP + t];
-        __syncthreads();
-        // p = B v, via B[t][u] = conj(B[u][t])
-        for (int t = tid; t < nt; t += 256) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int u = 0; u < nt; ++u) acc = cadd(acc, cmulc(B[(long)u * NTP + t], vh[u]));
-            P[t] = acc;
-        }
-        __syncthreads();
-        double part = 0.0;
-        for (int t = tid; t < nt; t += 256) part += cmulc(vh[t], P[t]).x;
-        const double K = block_sum(part, red);
-        for (int t = tid; t < nt; t += 256) P[t] = csub(P[t], cscale(vh[t], 0.5 * tau * K));
-        __syncthreads();
-        for (int e = tid; e < nt * NTP; e += 256) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int t = 8 * ti + a, u = ui + 16 * b;
+                if (t < NTP && u < NTP) B[(long)t * NTP + u] = (t < nt && u < nt) ? acc[a][b] : make_double2(0.0, 0.0);
+            }
+    } else {
+        for (int e = tid; e < NTP * NTP; e += 256) {
             const int t = e / NTP, u = e % NTP;
-            if (u >= nt) continue;
-            // B -= tau (v_t conj(w_u) + w_t conj(v_u))
-            const double2 d = cadd(cmulc(P[u], vh[t]), cmulc(vh[u], P[t]));
-            double2 b = csub(B[e], cscale(d, tau));
-            if (t == u) b.y = 0.0;
+            double2 b = make_double2(0.0, 0.0);
+            if (t < nt && u < nt) {
+                b = X[(long)t * NTE + u];
+                for (int j = 0; j < r; ++j) {
+                    b = cadd(b, cmulc(V[u * RMAX + j], E[t * RMAX + j]));   // E_tj conj(V_uj)
+                    b = cadd(b, cmulc(E[u * RMAX + j], V[t * RMAX + j]));   // V_tj conj(E_uj)
+                }
+                if (t == u) b.y = 0.0;
+            }
             B[e] = b;
+            ws.pmat[(long)s * NTP * NTP + e] = b;
         }
         __syncthreads();
+        for (int j = 0; j < r; ++j) {
+            const double tau = ws.htau[(long)s * RMAX + j];
+            for (int t = tid; t < NTP; t += 256) vh[t] = ws.hv[((long)s * RMAX + j) * NTP + t];
+            __syncthreads();
+            // p = B v, via B[t][u] = conj(B[u][t])
+            for (int t = tid; t < nt; t += 256) {
+                double2 acc = make_double2(0.0, 0.0);
+                for (int u = 0; u < nt; ++u) acc = cadd(acc, cmulc(B[(long)u * NTP + t], vh[u]));
+                P[0][t] = acc;
+            }
+            __syncthreads();
+            double part = 0.0;
+            for (int t = tid; t < nt; t += 256) part += cmulc(vh[t], P[0][t]).x;
+            const double K = block_sum(part, &red[0][0]);
+            for (int t = tid; t < nt; t += 256) P[0][t] = csub(P[0][t], cscale(vh[t], 0.5 * tau * K));
+            __syncthreads();
+            for (int e = tid; e < nt * NTP; e += 256) {
+                const int t = e / NTP, u = e % NTP;
+                if (u >= nt) continue;
+                // B -= tau (v_t conj(w_u) + w_t conj(v_u))
+                const double2 d = cadd(cmulc(P[0][u], vh[t]), cmulc(vh[u], P[0][t]));
+                double2 b = csub(B[e], cscale(d, tau));
+                if (t == u) b.y = 0.0;
+                B[e] = b;
+            }
+            __syncthreads();
+        }
     }
 }
 
