@@ -202,12 +202,22 @@ void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int
         };
         const int ox = best_origin(g.nx, TW, g.gx, 1, true);
         const int oy = best_origin(g.ny, trows, g.gy, g.gx, false);
+        // Tiles are listed patch by patch (patches of 64 rows x 32 pixels, tiles
+        // row-major inside): the work-groups of one XCD run consecutive tiles, and
+        // a compact patch shares more covering subsets, so more [P; M] operands
+        // stay in that XCD's L2.
+        const int pr = std::max(1, 64 / trows), pc = std::max(1, 32 / TW);
+        std::vector<std::pair<long, TileDesc>> ptiles;
+        int iy = -1;
         for (int ys = oy - trows; ys < g.ny; ys += trows) {
             const int ty0 = std::max(0, ys), ty1 = std::min(g.ny - 1, ys + trows - 1);
             if (ty0 > ty1) continue;
+            ++iy;
+            int ix = -1;
             for (int xs = ox - TW; xs < g.nx; xs += TW) {
                 const int tx0 = std::max(0, xs), tx1 = std::min(g.nx - 1, xs + TW - 1);
                 if (tx0 > tx1) continue;
+                ++ix;
                 TileDesc t;
                 t.pkt = (int)pi;
                 t.y = ty0;
@@ -220,9 +230,13 @@ void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int
                     if (ty1 >= sd.y0 && ty0 <= sd.y1 && tx1 >= sd.x0 && tx0 <= sd.x1) pl.cover.push_back(s);
                 }
                 t.cov_cnt = (int)pl.cover.size() - t.cov_off;
-                pl.tiles.push_back(t);
+                const long patch = (long)(iy / pr) * 1000000L + ix / pc;
+                ptiles.push_back({(patch * pr + iy % pr) * pc + ix % pc, t});
             }
         }
+        std::stable_sort(ptiles.begin(), ptiles.end(),
+                         [](const std::pair<long, TileDesc>& a, const std::pair<long, TileDesc>& b) { return a.first < b.first; });
+        for (const auto& pt : ptiles) pl.tiles.push_back(pt.second);
     }
     pl.chunk_begin.push_back((int)pl.chunks.size());
     pl.wtab_len = (size_t)wtab;
