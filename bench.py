@@ -70,6 +70,30 @@ def _pd_db(pd, ref, mask):
     return float(e.max()), float(np.quantile(e, 0.99))
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_counters.json")
+
+
+def measured_traffic(stage, workload):
+    """HBM bytes per launch of a stage from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record, or None when there is none or when the sources it was
+    taken from have changed since (compared by SHA-256)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)[workload][stage]
+    except (OSError, KeyError, ValueError):
+        return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel, digest in rec["sources"].items():
+        try:
+            with open(os.path.join(root, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,7 +267,7 @@ def main():
         avg_ms = timed[dom][0] / timed[dom][1]
         ach = flops / (avg_ms / 1e3)
         roof = {"bound": bound, "kernel": dom, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_ms}
+                "frac": ach / peak, "traffic": measured_traffic(dom, args.workload), "avg_launch_ms": avg_ms}
 
     cpu = None
     parity = {}
