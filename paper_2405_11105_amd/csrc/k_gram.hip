@@ -58,6 +58,9 @@ __device__ __forceinline__ void tile_ij(int u, int nt16, int& i, int& j) {
     j = i + rem;
 }
 
+// Boxes with at least this many rows and columns are sampled 2 x 2 in pass 1.
+constexpr int DEC_MIN = 8;
+
 // Row fragment for the T tiles: each (re, im) word of the interleaved K axis
 // becomes (-im, re), so that the product with the plain column fragment sums
 // re_r im_c - im_r re_c.
@@ -187,26 +190,38 @@ k_gram(Workspace ws) {
     const bool active = my_p < PIX;       // pass 2 with 16-pixel batches leaves whole waves idle
     float2 nxt[NPT];
     double nw = 0.0;
-    // box coordinates of this thread's pixel q = qb + my_p, advanced by PIX per batch
-    int fy = (ch.q0 + my_p) / sd.bw, fx = (ch.q0 + my_p) - fy * sd.bw;
+    // Pass 1 only has to locate the tissue subspace (any V_r keeps the pass-2
+    // decomposition exact), so in split BF16 boxes of at least DEC_MIN rows and
+    // columns are sampled on every second row and column (the FP32 path keeps
+    // every pixel: its covariance error tracks the size of C'): chunk [q0, q1)
+    // of the box maps to
+    // [q0 ne / neff, q1 ne / neff) of the ne sampled pixels.
+    const int bh = sd.y1 - sd.y0 + 1;
+    const int dec = (!DEFL && PREC == 1 && sd.bw >= DEC_MIN && bh >= DEC_MIN) ? 2 : 1;
+    const int bwe = (sd.bw + dec - 1) / dec;
+    const long ne = (long)bwe * ((bh + dec - 1) / dec);
+    const int q0 = dec == 1 ? ch.q0 : (int)((long)ch.q0 * ne / sd.neff);
+    const int q1 = dec == 1 ? ch.q1 : (int)((long)ch.q1 * ne / sd.neff);
+    // coordinates of this thread's pixel q = qb + my_p, advanced by PIX per batch
+    int fy = (q0 + my_p) / bwe, fx = (q0 + my_p) - fy * bwe;
     auto fetch = [&](int qb) {
         const int q = qb + my_p;
         long poff = -1;
         nw = 0.0;
-        if (active && q < ch.q1) {
-            poff = (long)(sd.y0 + fy) * nx + sd.x0 + fx;
-            nw = sd.flat ? 1.0 : wy[fy] * wx[fx];
+        if (active && q < q1) {
+            poff = (long)(sd.y0 + dec * fy) * nx + sd.x0 + dec * fx;
+            nw = sd.flat ? 1.0 : wy[dec * fy] * wx[dec * fx];
         }
         fx += PIX;
-        while (fx >= sd.bw) { fx -= sd.bw; ++fy; }
+        while (fx >= bwe) { fx -= bwe; ++fy; }
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int t = my_t0 + TSTEP * i;
             nxt[i] = (poff >= 0 && t < nt) ? sd.iq[(long)t * npix + poff] : make_float2(0.f, 0.f);
         }
     };
-    fetch(ch.q0);
-    for (int qb = ch.q0; qb < ch.q1; qb += PIX) {
+    fetch(q0);
+    for (int qb = q0; qb < q1; qb += PIX) {
         float2 cur[NPT];
 #pragma unroll
         for (int i = 0; i < NPT; ++i) cur[i] = nxt[i];
@@ -214,7 +229,7 @@ k_gram(Workspace ws) {
         __syncthreads();                           // the previous batch's MFMAs are done
         // pass 2: the next batch's loads overlap the FP64 operand work as well;
         // pass 1 issues them after the (short) operand writes, reusing the registers
-        if (DEFL && qb + PIX < ch.q1) fetch(qb + PIX);
+        if (DEFL && qb + PIX < q1) fetch(qb + PIX);
         if (!DEFL) {
             // the pass-1 Gram only locates the tissue subspace: FP32 window product
             const float wf = (float)w;
@@ -273,7 +288,7 @@ k_gram(Workspace ws) {
                 put(my_p, NTP + j, yj.x, yj.y);
             }
         }
-        if (!DEFL && qb + PIX < ch.q1) fetch(qb + PIX);   // in flight during the MFMAs
+        if (!DEFL && qb + PIX < q1) fetch(qb + PIX);   // in flight during the MFMAs
         __syncthreads();
         if (PREC == 0) {
             const int kk = lane >> 4, col = lane & 15;
