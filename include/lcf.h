@@ -170,7 +170,8 @@ typedef enum {
     LCF_STAGE_MLP = 9,          /* learned weights                                         */
     LCF_STAGE_PROJECTOR = 10,   /* P = V diag(w) V^H                                       */
     LCF_STAGE_REPROJ = 11,      /* projection, power Doppler, recombination (Eqs 4, 13)    */
-    LCF_NUM_STAGES = 12
+    LCF_STAGE_EVD_VECTORS = 12, /* eigenvectors of the weighted components (tridiagonal solver) */
+    LCF_NUM_STAGES = 13
 } lcf_stage;
 
 typedef struct lcf_context lcf_context;

@@ -22,7 +22,7 @@ PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 OPT_SCHEDULE, OPT_MAX_SWEEPS, OPT_USE_GRAPH, OPT_SUBSPACE_IT, OPT_STAGE_TIMING, OPT_AUTOTUNE, OPT_EVD = 1, 2, 3, 4, 5, 6, 7
 EVD_TRIDIAGONAL, EVD_JACOBI = 0, 1
 STAGES = ["windows", "gram1", "gram1_reduce", "tissue", "gram2", "gram2_reduce", "assemble", "evd",
-          "rules", "mlp", "projector", "reproj"]
+          "rules", "mlp", "projector", "reproj", "evd_vectors"]
 FLAG_NONPOSITIVE, FLAG_NONFINITE, FLAG_NO_CONVERGE, FLAG_MLP_FALLBACK, FLAG_EVD_JACOBI = 1, 2, 4, 8, 16
 
 STATUS = {0: "LCF_OK", 1: "LCF_ERR_INVALID_ARG", 2: "LCF_ERR_UNSUPPORTED", 3: "LCF_ERR_OUT_OF_MEMORY",

@@ -919,7 +919,7 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
 constexpr int FLAG_EVD_FALLBACK = 16;
 
 template <int RPL, int NW>
-__global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
+__global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
     constexpr int N = 16 * NW;             // padded size held (columns)
     static_assert(64 * RPL >= N, "rows per lane cover the padded size");
     __shared__ double2 vshb[2][N];         // Householder vector v_j, by the parity of j
@@ -929,7 +929,6 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
     __shared__ double dsh[N], esh[N], e2sh[N];
     __shared__ double2 phs[N];             // complex e_j, then D
     __shared__ double lamsh[N], insh[N];
-    __shared__ double dml[N * N];          // [i][k]: D- of eigenvalue k, then its z
     __shared__ double bnd[2];
     __shared__ double tau_sh[2];
     __shared__ int cluster;
@@ -938,7 +937,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
     const int nt = ws.sub[s].nt;
     double2* Bm = ws.bmat + (long)s * N * N;
     double2* H = ws.wvec + (long)s * N * N;                 // Householder vectors, tau in element 0
-    double* Dp = reinterpret_cast<double*>(ws.pmat + (long)s * N * N);   // [i][k]: D+
+    double* trid = reinterpret_cast<double*>(ws.pmat + (long)s * N * N) + N * N;   // tridiagonal form
     if (tid == 0) cluster = 0;
 
     double2 A[16][RPL];
@@ -1184,12 +1183,75 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
         if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
     }
     __syncthreads();
+    // eigenvalues; the tridiagonal form (d, |e|, |e|^2, D, pivmin) for the
+    // eigenvector pass; a subset with eigenvalues closer than 1e-12 lambda_1
+    // keeps its B for the Jacobi kernel
+    if (tid < nt) {
+        ws.lam[(long)s * N + tid] = lamsh[tid];
+        if (tid + 1 < nt && lamsh[tid] - lamsh[tid + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
+    }
+    for (int i = tid; i < N; i += 64 * NW) {
+        trid[i] = dsh[i];
+        trid[N + i] = esh[i];
+        trid[2 * N + i] = e2sh[i];
+        trid[3 * N + i] = phs[i].x;
+        trid[4 * N + i] = phs[i].y;
+    }
+    if (tid == 0) {
+        trid[5 * N] = pivmin;
+        ws.sweeps[s] = 0;
+    }
+    __syncthreads();
+    if (cluster && tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
+}
+
+// Eigenvectors of the subsets solved by k_heev_tri_vals (steps 4 and 5), for
+// the components whose weight differs from 1 (all of them when `all` is set):
+// only those enter the projector P = I - W' diag(1 - w) W'^H.
+template <int RPL, int NW>
+__global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all) {
+    constexpr int N = 16 * NW;
+    static_assert(64 * RPL >= N, "rows per lane cover the padded size");
+    __shared__ double dsh[N], esh[N], e2sh[N];
+    __shared__ double2 phs[N];
+    __shared__ double lamsh[N], insh[N];
+    __shared__ double dml[N * N];          // [i][slot]: D- of the slot's eigenvalue, then its z
+    __shared__ int act[N];
+    __shared__ int wcnt[NW];
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (ws.flags[s] & FLAG_EVD_FALLBACK) return;          // solved by the Jacobi kernel
+    const int nt = ws.sub[s].nt;
+    double2* Bm = ws.bmat + (long)s * N * N;
+    const double2* H = ws.wvec + (long)s * N * N;
+    double* Dp = reinterpret_cast<double*>(ws.pmat + (long)s * N * N);   // [i][slot]: D+
+    const double* trid = Dp + N * N;
+    const double* wts = ws.wts + (long)s * N;
+    for (int i = tid; i < N; i += 64 * NW) {
+        dsh[i] = trid[i];
+        esh[i] = trid[N + i];
+        e2sh[i] = trid[2 * N + i];
+        phs[i] = make_double2(trid[3 * N + i], trid[4 * N + i]);
+        lamsh[i] = ws.lam[(long)s * N + i];
+    }
+    const double pivmin = trid[5 * N];
+    // selected components in ascending order, by ballots
+    const bool flag = tid < nt && (all || fabs(1.0 - wts[tid < N ? tid : 0]) > 1e-17);
+    const unsigned long long mask = __ballot(flag);
+    if (lane == 0) wcnt[wave] = __popcll(mask);
+    __syncthreads();
+    int nact = 0, off = 0;
+    for (int w = 0; w < NW; ++w) {
+        off += w < wave ? wcnt[w] : 0;
+        nact += wcnt[w];
+    }
+    if (flag) act[off + __popcll(mask & ((1ull << lane) - 1ull))] = tid;
+    __syncthreads();
     // ---- 4. eigenvectors of T_r by twisted factorisation (lane k); D- and then
     // z live in LDS, D+ goes to scratch and is read back eight at a time
-    if (tid < nt) {
-        const int k = tid;
-        const double lam = lamsh[k];
-        if (k + 1 < nt && lamsh[k] - lamsh[k + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
+    if (tid < nact) {
+        const int k = tid;                         // slot; the eigenvalue is act[k]
+        const double lam = lamsh[act[k]];
         double q = dsh[nt - 1] - lam;
         dml[(nt - 1) * N + k] = q;
         for (int i = nt - 2; i >= 0; --i) {
@@ -1238,20 +1300,17 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
         insh[k] = rsq_nr(nrm);
     }
     __syncthreads();
-    if (cluster) {                  // leave B for the Jacobi kernel
-        if (tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
-        return;
-    }
     // ---- 5. y = Q D z in registers, reflectors in reverse order (the next
     // reflector is loaded while the current one is applied)
+    double2 A[16][RPL];
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int col = 16 * wave + c;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
-            A[c][i] = (row < nt && col < nt) ? cscale(phs[row], dml[row * N + col] * insh[col])
-                                             : make_double2(0.0, 0.0);
+            A[c][i] = (row < nt && col < nact) ? cscale(phs[row], dml[row * N + col] * insh[col])
+                                               : make_double2(0.0, 0.0);
         }
     }
     double2 vn[RPL];
@@ -1264,6 +1323,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
             vn[i] = (row > j && row < N) ? H[(long)j * N + row] : make_double2(0.0, 0.0);
         }
     };
+    if (16 * wave >= nact) return;                // no selected column in this wave
     if (nt >= 3) hload(nt - 3);
     for (int j = nt - 3; j >= 0; --j) {
         const double tauj = taun;
@@ -1317,18 +1377,18 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri(Workspace ws) {
             }
         }
     }
-    // write eigenvectors (column k contiguous) and eigenvalues
+    // eigenvector of slot c into column act[c] (contiguous)
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int col = 16 * wave + c;
+        if (col < nact) {
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int row = lane + 64 * i;
-            if (row < N) Bm[(long)col * N + row] = A[c][i];
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                if (row < N) Bm[(long)act[col] * N + row] = A[c][i];
+            }
         }
     }
-    if (tid < nt) ws.lam[(long)s * N + tid] = lamsh[tid];
-    if (tid == 0) ws.sweeps[s] = 0;
 }
 
 // Normalise columns, sort by norm descending, write eigenvalues and vectors.
@@ -1469,17 +1529,17 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
     // (method 1). Beyond 128: the LDS / global Jacobi.
     const int sel = method == 0 ? FLAG_EVD_FALLBACK : 0;
     if (ws.ntp <= 32) {
-        if (method == 0) hipLaunchKernelGGL((k_heev_tri<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
+        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
         hipLaunchKernelGGL((k_jacobi_reg<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp <= 64) {
-        if (method == 0) hipLaunchKernelGGL((k_heev_tri<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
+        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
         hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp <= 128) {
-        if (method == 0) hipLaunchKernelGGL((k_heev_tri<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
+        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
         hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
@@ -1489,6 +1549,16 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
     } else {
         hipLaunchKernelGGL((k_jacobi_subsets<false>), dim3(ws.S), dim3(JAC_THREADS), 0, st, ws, max_sweeps);
     }
+    return hipGetLastError();
+}
+
+// Eigenvectors after the weights are known (tridiagonal solver, up to 128
+// frames); the Jacobi paths produced theirs already.
+hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStream_t st) {
+    if (method != 0 || ws.ntp > 128) return hipSuccess;
+    if (ws.ntp <= 32) hipLaunchKernelGGL((k_heev_tri_vecs<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, all);
+    else if (ws.ntp <= 64) hipLaunchKernelGGL((k_heev_tri_vecs<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, all);
+    else hipLaunchKernelGGL((k_heev_tri_vecs<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, all);
     return hipGetLastError();
 }
 

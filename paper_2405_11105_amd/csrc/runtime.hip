@@ -568,7 +568,7 @@ lcf_status run_stages(lcf_context* c, const Workspace& ws, const lcf_threshold* 
 }
 
 lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold* thr, int prec, int nt_max,
-                       hipStream_t st) {
+                       int all_vectors, hipStream_t st) {
     const bool mlp = thr->cut == LCF_CUT_MLP;
     RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
                   thr->knee_max_frac, thr->beta_sigmoid};
@@ -589,6 +589,7 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
             HIPCHK(mlp_apply(ws, wout, nullptr, thr->pd_mode, st));   // all subsets keep the rule
         }
     }
+    { STAGE(c, LCF_STAGE_EVD_VECTORS, st); HIPCHK(launch_evd_vectors(ws, c->evd_method, all_vectors, st)); }
     { STAGE(c, LCF_STAGE_PROJECTOR, st); HIPCHK(launch_projector(ws, prec, st)); }
     return LCF_OK;
 }
@@ -661,13 +662,13 @@ lcf_status run_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf
             double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
             e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
             if (e != LCF_OK) return e;
-            e = run_stages2(c, v, thr, prec, pl.sub[s].nt, st);
+            e = run_stages2(c, v, thr, prec, pl.sub[s].nt, diag && diag->eigvecs ? 1 : 0, st);
             if (e != LCF_OK) return e;
         }
     } else {
         e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
         if (e != LCF_OK) return e;
-        e = run_stages2(c, ws, thr, prec, pl.nt_max, st);
+        e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, st);
         if (e != LCF_OK) return e;
     }
     { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
