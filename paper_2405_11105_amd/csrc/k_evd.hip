@@ -1209,15 +1209,18 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
 // the components whose weight differs from 1 (all of them when `all` is set):
 // only those enter the projector P = I - W' diag(1 - w) W'^H.
 template <int RPL, int NW>
-__global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all) {
+__global__ void __launch_bounds__(64 * (NW < 4 ? NW : 4)) k_heev_tri_vecs(Workspace ws, int all) {
     constexpr int N = 16 * NW;
+    constexpr int NWV = NW < 4 ? NW : 4;   // waves: groups of SG selected columns at a time
+    constexpr int SG = 16 * NWV;
+    static_assert(64 * NWV >= N, "one thread per component for the selection");
     static_assert(64 * RPL >= N, "rows per lane cover the padded size");
     __shared__ double dsh[N], esh[N], e2sh[N];
     __shared__ double2 phs[N];
-    __shared__ double lamsh[N], insh[N];
-    __shared__ double dml[N * N];          // [i][slot]: D- of the slot's eigenvalue, then its z
+    __shared__ double lamsh[N], insh[SG];
+    __shared__ double dml[N * SG];         // [i][slot in group]: D- of the slot's eigenvalue, then its z
     __shared__ int act[N];
-    __shared__ int wcnt[NW];
+    __shared__ int wcnt[NWV];
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (ws.flags[s] & FLAG_EVD_FALLBACK) return;          // solved by the Jacobi kernel
@@ -1227,7 +1230,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all
     double* Dp = reinterpret_cast<double*>(ws.pmat + (long)s * N * N);   // [i][slot]: D+
     const double* trid = Dp + N * N;
     const double* wts = ws.wts + (long)s * N;
-    for (int i = tid; i < N; i += 64 * NW) {
+    for (int i = tid; i < N; i += 64 * NWV) {
         dsh[i] = trid[i];
         esh[i] = trid[N + i];
         e2sh[i] = trid[2 * N + i];
@@ -1241,23 +1244,25 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all
     if (lane == 0) wcnt[wave] = __popcll(mask);
     __syncthreads();
     int nact = 0, off = 0;
-    for (int w = 0; w < NW; ++w) {
+    for (int w = 0; w < NWV; ++w) {
         off += w < wave ? wcnt[w] : 0;
         nact += wcnt[w];
     }
     if (flag) act[off + __popcll(mask & ((1ull << lane) - 1ull))] = tid;
     __syncthreads();
+    for (int g0 = 0; g0 < nact; g0 += SG) {
+    const int cnt = nact - g0 < SG ? nact - g0 : SG;
     // ---- 4. eigenvectors of T_r by twisted factorisation (lane k); D- and then
     // z live in LDS, D+ goes to scratch and is read back eight at a time
-    if (tid < nact) {
-        const int k = tid;                         // slot; the eigenvalue is act[k]
-        const double lam = lamsh[act[k]];
+    if (tid < cnt) {
+        const int k = tid;                         // slot in the group; the eigenvalue is act[g0 + k]
+        const double lam = lamsh[act[g0 + k]];
         double q = dsh[nt - 1] - lam;
-        dml[(nt - 1) * N + k] = q;
+        dml[(nt - 1) * SG + k] = q;
         for (int i = nt - 2; i >= 0; --i) {
             if (fabs(q) < pivmin) q = -pivmin;
             q = (dsh[i] - lam) - e2sh[i] * rcp_nr(q);
-            dml[i * N + k] = q;
+            dml[i * SG + k] = q;
         }
         double p = dsh[0] - lam;
         Dp[k] = p;
@@ -1267,13 +1272,13 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all
             if (fabs(p) < pivmin) p = -pivmin;
             p = (dsh[i + 1] - lam) - e2sh[i] * rcp_nr(p);
             Dp[(long)(i + 1) * N + k] = p;
-            const double gam = p + dml[(i + 1) * N + k] - (dsh[i + 1] - lam);
+            const double gam = p + dml[(i + 1) * SG + k] - (dsh[i + 1] - lam);
             if (fabs(gam) < g) { g = fabs(gam); r = i + 1; }
         }
         // z_r = 1; below r from D+, above r from D- (each D- is read before its
         // slot takes the z value)
         double z = 1.0, nrm = 1.0;
-        dml[r * N + k] = 1.0;
+        dml[r * SG + k] = 1.0;
         for (int i = r - 1; i >= 0; i -= 8) {
             double dv[8];
 #pragma unroll
@@ -1284,17 +1289,17 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all
                     double d = dv[u];
                     if (fabs(d) < pivmin) d = -pivmin;
                     z = -esh[i - u] * rcp_nr(d) * z;
-                    dml[(i - u) * N + k] = z;
+                    dml[(i - u) * SG + k] = z;
                     nrm += z * z;
                 }
             }
         }
         z = 1.0;
         for (int i = r; i + 1 < nt; ++i) {
-            double d = dml[(i + 1) * N + k];
+            double d = dml[(i + 1) * SG + k];
             if (fabs(d) < pivmin) d = -pivmin;
             z = -esh[i] * rcp_nr(d) * z;
-            dml[(i + 1) * N + k] = z;
+            dml[(i + 1) * SG + k] = z;
             nrm += z * z;
         }
         insh[k] = rsq_nr(nrm);
@@ -1309,8 +1314,8 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
-            A[c][i] = (row < nt && col < nact) ? cscale(phs[row], dml[row * N + col] * insh[col])
-                                               : make_double2(0.0, 0.0);
+            A[c][i] = (row < nt && col < cnt) ? cscale(phs[row], dml[row * SG + col] * insh[col])
+                                              : make_double2(0.0, 0.0);
         }
     }
     double2 vn[RPL];
@@ -1323,7 +1328,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all
             vn[i] = (row > j && row < N) ? H[(long)j * N + row] : make_double2(0.0, 0.0);
         }
     };
-    if (16 * wave >= nact) return;                // no selected column in this wave
+    if (16 * wave < cnt) {                        // the wave holds selected columns
     if (nt >= 3) hload(nt - 3);
     for (int j = nt - 3; j >= 0; --j) {
         const double tauj = taun;
@@ -1381,13 +1386,16 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vecs(Workspace ws, int all
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int col = 16 * wave + c;
-        if (col < nact) {
+        if (col < cnt) {
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int row = lane + 64 * i;
-                if (row < N) Bm[(long)act[col] * N + row] = A[c][i];
+                if (row < N) Bm[(long)act[g0 + col] * N + row] = A[c][i];
             }
         }
+    }
+    }
+    __syncthreads();                              // dml and insh are reused by the next group
     }
 }
 
@@ -1558,7 +1566,7 @@ hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStrea
     if (method != 0 || ws.ntp > 128) return hipSuccess;
     if (ws.ntp <= 32) hipLaunchKernelGGL((k_heev_tri_vecs<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, all);
     else if (ws.ntp <= 64) hipLaunchKernelGGL((k_heev_tri_vecs<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, all);
-    else hipLaunchKernelGGL((k_heev_tri_vecs<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, all);
+    else hipLaunchKernelGGL((k_heev_tri_vecs<2, 8>), dim3(ws.S), dim3(256), 0, st, ws, all);
     return hipGetLastError();
 }
 
