@@ -921,6 +921,7 @@ constexpr int FLAG_EVD_FALLBACK = 16;
 template <int RPL, int NW>
 __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
     constexpr int N = 16 * NW;             // padded size held (columns)
+    constexpr int NTHR = 64 * NW;
     static_assert(64 * RPL >= N, "rows per lane cover the padded size");
     __shared__ double2 vshb[2][N];         // Householder vector v_j, by the parity of j
     __shared__ double2 psh[NW * N];        // per-wave partials of A v
@@ -930,6 +931,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
     __shared__ double2 phs[N];             // complex e_j, then D
     __shared__ double lamsh[N], insh[N];
     __shared__ double bnd[2];
+    __shared__ int gcnt[64 * NW];          // Sturm counts at the bracketing grid
     __shared__ double tau_sh[2];
     __shared__ int cluster;
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
@@ -1150,29 +1152,47 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
     }
     __syncthreads();
     const double pivmin = red[0];
-    // ---- 3. eigenvalues by multisection: lanes 4k .. 4k+3 for the k-th largest,
-    // one Sturm count per lane (4 points, 5 sub-intervals per round; 24 rounds
-    // narrow the Gershgorin interval by 5^24 ~ 6e16, below the rounding of the
-    // largest eigenvalue)
+    // ---- 3. eigenvalues. One Sturm count per thread at NTHR grid points (the
+    // lower Gershgorin bound, then geometric steps from hi 2^-64 up to hi) brackets
+    // every eigenvalue; then multisection, lanes 4k .. 4k+3 for the k-th largest,
+    // 4 points and 5 sub-intervals per round, until the bracket is no wider than
+    // (hi - lo) 5^-24 (the width 24 rounds from the Gershgorin interval reach,
+    // below the rounding of the largest eigenvalue)
     {
+        const double lo = bnd[0], hi = bnd[1];
+        auto sturm = [&](double x) {
+            double q = dsh[0] - x;
+            int c = q < 0.0;
+            for (int i = 1; i < nt; ++i) {
+                if (fabs(q) < pivmin) q = -pivmin;
+                q = (dsh[i] - x) - e2sh[i - 1] * rcp_nr(q);
+                c += q < 0.0;
+            }
+            return c;
+        };
+        auto grid = [&](int g) {
+            if (hi <= 0.0) return lo + (hi - lo) * (double)g / (double)(NTHR - 1);
+            if (g == 0) return lo;
+            return fmax(lo, hi * exp2(-64.0 * (double)(NTHR - 1 - g) / (double)(NTHR - 2)));
+        };
+        gcnt[tid] = sturm(grid(tid));
+        __syncthreads();
         const int k = tid >> 2, m = tid & 3;
         const int target = nt - 1 - k;                                 // index among ascending
-        double a = bnd[0], b = bnd[1];
-        for (int it = 0; it < 24; ++it) {
+        // counts are nondecreasing along the grid: the last point with count <= target
+        int g0 = 0, g1 = NTHR - 1;                                     // gcnt[g0] <= target < gcnt[g1]
+        while (g1 - g0 > 1) {
+            const int gm = (g0 + g1) >> 1;
+            if (gcnt[gm] <= target) g0 = gm;
+            else g1 = gm;
+        }
+        double a = grid(g0), b = g1 == NTHR - 1 ? hi : grid(g1);
+        const double tol = (hi - lo) * 1.7e-17;
+        for (int it = 0; it < 24 && b - a > tol; ++it) {
             const double h = (b - a) * 0.2;
             const double x = a + (double)(m + 1) * h;
-            int cnt = 0;
-            if (k < nt) {
-                double q = dsh[0] - x;
-                cnt = q < 0.0;
-                for (int i = 1; i < nt; ++i) {
-                    if (fabs(q) < pivmin) q = -pivmin;
-                    q = (dsh[i] - x) - e2sh[i - 1] * rcp_nr(q);
-                    cnt += q < 0.0;
-                }
-            }
-            // counts are nondecreasing in x: the points left of the eigenvalue are
-            // those with count <= target
+            const int cnt = k < nt ? sturm(x) : 0;
+            // the points left of the eigenvalue are those with count <= target
             int le = cnt <= target;
             le += __shfl_xor(le, 1, 64);
             le += __shfl_xor(le, 2, 64);
