@@ -71,6 +71,17 @@ __device__ __forceinline__ u32x4 swap_neg(u32x4 v) {
     return o;
 }
 
+// Operand loads of the next batch go through global-address-space pointers:
+// flat loads also count against the LDS wait counter, so every LDS wait of the
+// current batch (the MFMA operand reads) would wait for them as well. A complex64
+// element is loaded as one 64-bit word (re | im << 32).
+typedef const uint64_t __attribute__((address_space(1)))* gptr_u64;
+typedef const double __attribute__((address_space(1)))* gptr_f64;
+__device__ __forceinline__ float2 c64_bits(uint64_t u, bool keep) {
+    return keep ? make_float2(__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32)))
+                : make_float2(0.f, 0.f);
+}
+
 // Split-BF16 Gram MFMAs of one batch of C::PX pixels in LDS (hi words Ah, lo
 // words Al, [column][pixel] with stride LDB). K blocks of 32 = 16 pixels x
 // (re, im); lane group g holds pixels 4g..4g+3. Position (i, j) of the wave:
@@ -188,8 +199,14 @@ k_gram(Workspace ws) {
     const int my_p = DEFL ? tid / G : tid % PIX;
     const int my_t0 = DEFL ? tid % G : tid / PIX;
     const bool active = my_p < PIX;       // pass 2 with 16-pixel batches leaves whole waves idle
-    float2 nxt[NPT];
-    double nw = 0.0;
+    // Loads of the next batch: every lane reads a valid address (frames beyond nt
+    // clamped to frame nt - 1, pixels outside the chunk at the box origin) and the
+    // mask and window product are applied when the batch is taken, so that nothing
+    // waits for the loads before then. The empty asm keeps the per-frame offsets
+    // from being hoisted out of the batch loop.
+    uint64_t nxt[NPT];
+    bool fok = false;                    // the fetched pixel lies in the chunk
+    double fwy = 1.0, fwx = 1.0;         // its window factors as loaded
     // Pass 1 only has to locate the tissue subspace (any V_r keeps the pass-2
     // decomposition exact), so in split BF16 boxes of at least DEC_MIN rows and
     // columns are sampled on every second row and column (the FP32 path keeps
@@ -204,28 +221,37 @@ k_gram(Workspace ws) {
     const int q1 = dec == 1 ? ch.q1 : (int)((long)ch.q1 * ne / sd.neff);
     // coordinates of this thread's pixel q = qb + my_p, advanced by PIX per batch
     int fy = (q0 + my_p) / bwe, fx = (q0 + my_p) - fy * bwe;
+    const gptr_u64 giq = (gptr_u64)sd.iq;
     auto fetch = [&](int qb) {
         const int q = qb + my_p;
-        long poff = -1;
-        nw = 0.0;
-        if (active && q < q1) {
-            poff = (long)(sd.y0 + dec * fy) * nx + sd.x0 + dec * fx;
-            nw = sd.flat ? 1.0 : wy[dec * fy] * wx[dec * fx];
+        const bool okp = active && q < q1;
+        long pb = (long)sd.y0 * nx + sd.x0;
+        fok = okp;
+        if (okp) {
+            pb = (long)(sd.y0 + dec * fy) * nx + sd.x0 + dec * fx;
+            if (!sd.flat) {
+                fwy = ((gptr_f64)wy)[dec * fy];
+                fwx = ((gptr_f64)wx)[dec * fx];
+            }
         }
         fx += PIX;
         while (fx >= bwe) { fx -= bwe; ++fy; }
+        int mt = my_t0;
+        asm volatile("" : "+v"(pb), "+v"(mt));
+        if (active) {
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const int t = my_t0 + TSTEP * i;
-            nxt[i] = (poff >= 0 && t < nt) ? sd.iq[(long)t * npix + poff] : make_float2(0.f, 0.f);
+            for (int i = 0; i < NPT; ++i) {
+                const int t = min(mt + TSTEP * i, nt - 1);
+                nxt[i] = giq[(long)t * npix + pb];
+            }
         }
     };
     fetch(q0);
     for (int qb = q0; qb < q1; qb += PIX) {
         float2 cur[NPT];
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) cur[i] = nxt[i];
-        const double w = nw;
+        for (int i = 0; i < NPT; ++i) cur[i] = c64_bits(nxt[i], fok && my_t0 + TSTEP * i < nt);
+        const double w = fok ? (sd.flat ? 1.0 : fwy * fwx) : 0.0;
         __syncthreads();                           // the previous batch's MFMAs are done
         // pass 2: the next batch's loads overlap the FP64 operand work as well;
         // pass 1 issues them after the (short) operand writes, reusing the registers
@@ -421,23 +447,32 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
 
     // phase A layout and the software-pipelined loads of the next batch
     const int my_p = tid % PX, my_t0 = tid / PX;
-    float2 nxt[D::NPT];
-    double nw = 0.0;
+    // loads as in k_gram: valid addresses, mask and window product applied in phase A
+    uint64_t nxt[D::NPT];
+    bool fok = false;
+    double fwy = 1.0, fwx = 1.0;
+    const gptr_u64 giq = (gptr_u64)sd.iq;
     int fy = (ch.q0 + my_p) / sd.bw, fx = (ch.q0 + my_p) - fy * sd.bw;
     auto fetch = [&](int qb) {
         const int q = qb + my_p;
-        long poff = -1;
-        nw = 0.0;
-        if (q < ch.q1) {
-            poff = (long)(sd.y0 + fy) * nx + sd.x0 + fx;
-            nw = sd.flat ? 1.0 : wy[fy] * wx[fx];
+        const bool okp = q < ch.q1;
+        long pb = (long)sd.y0 * nx + sd.x0;
+        fok = okp;
+        if (okp) {
+            pb = (long)(sd.y0 + fy) * nx + sd.x0 + fx;
+            if (!sd.flat) {
+                fwy = ((gptr_f64)wy)[fy];
+                fwx = ((gptr_f64)wx)[fx];
+            }
         }
         fx += PX;
         while (fx >= sd.bw) { fx -= sd.bw; ++fy; }
+        int mt = my_t0;
+        asm volatile("" : "+v"(pb), "+v"(mt));
 #pragma unroll
         for (int i = 0; i < D::NPT; ++i) {
-            const int t = my_t0 + D::TSTEP * i;
-            nxt[i] = (poff >= 0 && t < nt) ? sd.iq[(long)t * npix + poff] : make_float2(0.f, 0.f);
+            const int t = min(mt + D::TSTEP * i, nt - 1);
+            nxt[i] = giq[(long)t * npix + pb];
         }
     };
     fetch(ch.q0);
@@ -445,15 +480,17 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
         __syncthreads();                           // phases D and E of the previous batch are done
         // ---- A
         {
+            const double nw = fok ? (sd.flat ? 1.0 : fwy * fwx) : 0.0;
             const float wf = (float)nw;
             if (my_t0 == 0) wsh[my_p] = nw;
 #pragma unroll
             for (int i = 0; i < D::NPT; ++i) {
                 const int t = my_t0 + D::TSTEP * i;
                 if (t < NTP) {
-                    sraw[my_p * D::LDS_S + t] = nxt[i];
+                    const float2 c = c64_bits(nxt[i], fok && t < nt);
+                    sraw[my_p * D::LDS_S + t] = c;
                     uint32_t h, l;
-                    split_bf16x2(wf * nxt[i].x, wf * nxt[i].y, h, l);
+                    split_bf16x2(wf * c.x, wf * c.y, h, l);
                     Ah[t * LDB + my_p] = h;
                     Al[t * LDB + my_p] = l;
                 }
