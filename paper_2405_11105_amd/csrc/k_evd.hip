@@ -925,7 +925,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
     static_assert(64 * RPL >= N, "rows per lane cover the padded size");
     __shared__ double2 vshb[2][N];         // Householder vector v_j, by the parity of j
     __shared__ double2 psh[NW * N];        // per-wave partials of A v
-    __shared__ double2 qsh[N];             // p = tau A v
+    __shared__ double2 qsh[N];             // q at the columns of each wave (written by that wave)
     __shared__ double red[2];
     __shared__ double dsh[N], esh[N], e2sh[N];
     __shared__ double2 phs[N];             // complex e_j, then D
@@ -953,59 +953,63 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
         }
     }
 
-    // ---- 1. Householder reduction, three barriers per column
-    for (int j = 0; j + 2 < nt; ++j) {
-        // the wave forming v_{j+1} may start while others still apply v_j
-        double2* vsh = vshb[j & 1];
-        const int jw = j >> 4, jc = j & 15;
-        const int wstart = (j + 1) >> 4;          // waves below hold only finished columns
-        if (wave == jw) {
-            // the reflector of column j (rows j + 1 ..), formed by the wave that holds it
-            double2 x[RPL];
+    // ---- 1. Householder reduction, two barriers per column. Each active wave
+    // sums the partials of A v for every row itself, and the wave holding column
+    // j + 1 applies step j to that column first and forms v_{j+1} while the other
+    // waves are still applying step j.
+    // The reflector of column jj (rows jj + 1 ..), formed by the wave holding it.
+    auto form = [&](int jj) {
+        const int jc = jj & 15;
+        double2* vsh = vshb[jj & 1];
+        double2 x[RPL];
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                x[i] = make_double2(0.0, 0.0);
+        for (int i = 0; i < RPL; ++i) {
+            x[i] = make_double2(0.0, 0.0);
 #pragma unroll
-                for (int c = 0; c < 16; ++c)
-                    if (c == jc) x[i] = A[c][i];
-            }
-            double s2 = 0.0;
+            for (int c = 0; c < 16; ++c)
+                if (c == jc) x[i] = A[c][i];
+        }
+        double s2 = 0.0;
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int row = lane + 64 * i;
-                if (row > j + 1 && row < nt) s2 += cabs2(x[i]);
-            }
-            s2 = wave_sum(s2);
-            double2 t1 = x[0], t0 = x[0];
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row > jj + 1 && row < nt) s2 += cabs2(x[i]);
+        }
+        s2 = wave_sum(s2);
+        double2 t1 = x[0], t0 = x[0];
 #pragma unroll
-            for (int i = 1; i < RPL; ++i) {
-                if (i == ((j + 1) >> 6)) t1 = x[i];
-                if (i == (j >> 6)) t0 = x[i];
-            }
-            const double2 x0 = make_double2(rdl(t1.x, (j + 1) & 63), rdl(t1.y, (j + 1) & 63));
-            const double xjj = rdl(t0.x, j & 63);
-            const double ax0 = sqrt(cabs2(x0));
-            const double alpha = sqrt(s2 + ax0 * ax0);
-            const double2 ph = ax0 > 0.0 ? cscale(x0, 1.0 / ax0) : make_double2(1.0, 0.0);
-            const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+        for (int i = 1; i < RPL; ++i) {
+            if (i == ((jj + 1) >> 6)) t1 = x[i];
+            if (i == (jj >> 6)) t0 = x[i];
+        }
+        const double2 x0 = make_double2(rdl(t1.x, (jj + 1) & 63), rdl(t1.y, (jj + 1) & 63));
+        const double xjj = rdl(t0.x, jj & 63);
+        const double ax0 = sqrt(cabs2(x0));
+        const double alpha = sqrt(s2 + ax0 * ax0);
+        const double2 ph = ax0 > 0.0 ? cscale(x0, 1.0 / ax0) : make_double2(1.0, 0.0);
+        const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int row = lane + 64 * i;
-                if (row < N) {
-                    const double2 v = row <= j ? make_double2(0.0, 0.0)
-                                               : (row == j + 1 ? cadd(x0, cscale(ph, alpha)) : x[i]);
-                    vsh[row] = v;
-                    H[(long)j * N + row] = row == 0 ? make_double2(tau, 0.0) : v;   // row 0 of v_j is zero: holds tau
-                }
-            }
-            if (lane == 0) {
-                dsh[j] = xjj;
-                phs[j] = cscale(ph, -alpha);                           // complex e_j for now
-                tau_sh[j & 1] = tau;
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row < N) {
+                const double2 v = row <= jj ? make_double2(0.0, 0.0)
+                                            : (row == jj + 1 ? cadd(x0, cscale(ph, alpha)) : x[i]);
+                vsh[row] = v;
+                H[(long)jj * N + row] = row == 0 ? make_double2(tau, 0.0) : v;   // row 0 of v_j is zero: holds tau
             }
         }
-        __syncthreads();
+        if (lane == 0) {
+            dsh[jj] = xjj;
+            phs[jj] = cscale(ph, -alpha);                           // complex e_j for now
+            tau_sh[jj & 1] = tau;
+        }
+    };
+    if (nt > 2 && wave == 0) form(0);
+    __syncthreads();
+    for (int j = 0; j + 2 < nt; ++j) {
+        const double2* vsh = vshb[j & 1];
         const double tau = tau_sh[j & 1];
+        const int wstart = (j + 1) >> 4;          // waves below hold only finished columns
         // partial A v over this wave's columns (row blocks i with 64 i + 63 <= j
         // hold only finished rows, where v and A v vanish)
         const int ilo = (j + 1) >> 6;
@@ -1030,23 +1034,19 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
             }
         }
         __syncthreads();
-        // p = tau sum_w partials
-        if (tid < N) {
-            double2 p = make_double2(0.0, 0.0);
-            for (int w = wstart; w < NW; ++w) p = cadd(p, psh[w * N + tid]);
-            qsh[tid] = cscale(p, tau);
-        }
-        __syncthreads();
-        // q = p - (tau / 2) (v^H p) v, with v^H p summed in every active wave
-        // (each holds all rows), then A -= v q^H + q v^H
+        // p = tau A v for this lane's rows, q = p - (tau / 2) (v^H p) v, then
+        // A -= v q^H + q v^H on this wave's columns
         if (wave >= wstart) {
             double2 vr[RPL], qr[RPL];
             double kr = 0.0, ki = 0.0;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int row = lane + 64 * i;
+                double2 p = make_double2(0.0, 0.0);
+                if (row < N && i >= ilo)
+                    for (int w = wstart; w < NW; ++w) p = cadd(p, psh[w * N + row]);
+                qr[i] = cscale(p, tau);
                 vr[i] = row < N ? vsh[row] : make_double2(0.0, 0.0);
-                qr[i] = row < N ? qsh[row] : make_double2(0.0, 0.0);
                 kr = fma(vr[i].x, qr[i].x, fma(vr[i].y, qr[i].y, kr));       // conj(v) p
                 ki = fma(vr[i].x, qr[i].y, fma(-vr[i].y, qr[i].x, ki));
             }
@@ -1054,12 +1054,20 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
             ki = wave_sum(ki);
             const double2 K = make_double2(0.5 * tau * kr, 0.5 * tau * ki);
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) qr[i] = csub(qr[i], cmul(K, vr[i]));
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
+            for (int i = 0; i < RPL; ++i) {
+                qr[i] = csub(qr[i], cmul(K, vr[i]));
+                // q at this wave's columns, for the column factors below (each wave
+                // writes and reads only its own 16 rows of qsh)
+                const int row = lane + 64 * i;
+                if (row >= 16 * wave && row < 16 * wave + 16) qsh[row] = qr[i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            auto update = [&](int c) {
                 const int col = 16 * wave + c;
                 const double2 vc = vsh[col];
-                const double2 qc = csub(qsh[col], cmul(K, vc));
+                const double2 qc = qsh[col];
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
                     if (i < ilo) continue;              // finished rows keep their values
@@ -1070,8 +1078,20 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
                     ay = fma(-qr[i].y, vc.x, fma(qr[i].x, vc.y, ay));
                     A[c][i] = make_double2(ax, ay);
                 }
+            };
+            const bool own = j + 3 < nt && wave == ((j + 1) >> 4);
+            const int jcn = (j + 1) & 15;
+            if (own) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c == jcn) update(c);
+                form(j + 1);
             }
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (!(own && c == jcn)) update(c);
         }
+        __syncthreads();
     }
     // last 2 x 2 block: d_{nt-2}, d_{nt-1}, e_{nt-2}
     {
