@@ -379,14 +379,19 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
     using D = DeflCfg<NTP>;
     using C = typename D::GC;
     constexpr int NTE = D::NTE, LDB = D::LDB, PX = D::PX, WAVES = D::WAVES;
-    __shared__ __attribute__((aligned(16))) uint32_t Aw[2 * NTE * LDB];
+    // With eight waves (up to 128 frames; above, the second buffer does not fit
+    // in LDS) the operand is double-buffered: the Gram MFMAs of batch k - 1 run
+    // in the same phase as C and D of batch k, on every SIMD one wave doing the
+    // FP64 residual while the other issues MFMAs (waves w and w + 4 share a SIMD
+    // and take the two in opposite order).
+    constexpr bool PIPE = WAVES == 8 && NTP <= 128;
+    constexpr int BUFW = 2 * NTE * LDB;                  // words of one operand buffer (hi, lo)
+    __shared__ __attribute__((aligned(16))) uint32_t Aw[(PIPE ? 2 : 1) * BUFW];
     __shared__ float2 sraw[PX * D::LDS_S];
     __shared__ double2 vrs[RMAX * NTP];                  // V_r, [j][t]
     __shared__ float ypart[D::KG * PX * 16];
     __shared__ float2 ysh[PX * RMAX];
     __shared__ double wsh[PX];
-    uint32_t* Ah = Aw;
-    uint32_t* Al = Aw + NTE * LDB;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -475,11 +480,19 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
             nxt[i] = giq[(long)t * npix + pb];
         }
     };
+    const int nb = (ch.q1 - ch.q0 + PX - 1) / PX;
+    const bool cd_first = !PIPE || ((wave >> 2) & 1) == 0;
     fetch(ch.q0);
-    for (int qb = ch.q0; qb < ch.q1; qb += PX) {
-        __syncthreads();                           // phases D and E of the previous batch are done
+    for (int k = 0; k < nb + (PIPE ? 1 : 0); ++k) {
+        const int qb = ch.q0 + k * PX;
+        uint32_t* Ah = Aw + (PIPE ? (k & 1) * BUFW : 0);     // operand being formed: batch k
+        uint32_t* Al = Ah + NTE * LDB;
+        const uint32_t* Eh = PIPE ? Aw + ((k & 1) ^ 1) * BUFW : Ah;   // Gram of batch k - 1 (PIPE) or k
+        const uint32_t* El = Eh + NTE * LDB;
+        const bool work = k < nb, egram = PIPE ? k > 0 : true;
+        __syncthreads();                           // the previous batch's C, D and E are done
         // ---- A
-        {
+        if (work) {
             const double nw = fok ? (sd.flat ? 1.0 : fwy * fwx) : 0.0;
             const float wf = (float)nw;
             if (my_t0 == 0) wsh[my_p] = nw;
@@ -496,10 +509,10 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
                 }
             }
         }
-        if (qb + PX < ch.q1) fetch(qb + PX);       // in flight until the next batch
+        if (work && qb + PX < ch.q1) fetch(qb + PX);   // in flight until the next batch
         __syncthreads();
         // ---- B: y partial of row tile ymt over this wave's K steps
-        {
+        if (work) {
             floatx4 ya = floatx4{0.f, 0.f, 0.f, 0.f};
             const int prow = 16 * ymt + col;
 #pragma unroll
@@ -525,85 +538,88 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
             for (int i = 0; i < 4; ++i) ypart[(ykg * PX + 16 * ymt + 4 * g + i) * 16 + col] = ya[i];
         }
         __syncthreads();                           // also: phase B's reads of Ah/Al rows < NTP are done
+        if (PIPE && !cd_first && egram) gram_mfma_bf16<C>(Eh, El, aoff, boff, valid, acc, lane);
         // ---- C: scores of this wave's pixels (lane: pixel 16-lane group, column)
+        if (work) {
 #pragma unroll
-        for (int h2 = 0; h2 < (D::PPW * 16 + 63) / 64; ++h2) {
-            const int k = (lane >> 4) + 4 * h2;            // pixel of the wave
-            const bool on = k < D::PPW;
-            const int p = wave * D::PPW + (on ? k : 0);
-            float v = 0.f;
+            for (int h2 = 0; h2 < (D::PPW * 16 + 63) / 64; ++h2) {
+                const int kp = (lane >> 4) + 4 * h2;            // pixel of the wave
+                const bool on = kp < D::PPW;
+                const int p = wave * D::PPW + (on ? kp : 0);
+                float v = 0.f;
 #pragma unroll
-            for (int q = 0; q < D::KG; ++q) v += ypart[(q * PX + p) * 16 + col];
-            // (Re y_j, Im y_j) meet in lane col = j after a rotate by 8 within the row
-            const float vi = __shfl_xor(v, 8, 16);
-            const int j = col;
-            float yr = 0.f, yi = 0.f;
-            if (j < RMAX && j < r) { yr = v; yi = vi; }
-            if (on) {
-                if (j < RMAX) ysh[p * RMAX + j] = make_float2(yr, yi);
-                uint32_t hh, ll;
-                split_bf16x2(yr, yi, hh, ll);
-                Ah[(NTP + j) * LDB + p] = hh;      // REXT = 16 columns, zero beyond r
-                Al[(NTP + j) * LDB + p] = ll;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // ---- D: c' = w s - y V_r^H for frames lane + 64 f, pixels of the wave
-        {
-            double cr[D::PPW][D::FPT], ci[D::PPW][D::FPT];
-            double wp[D::PPW];
-#pragma unroll
-            for (int k = 0; k < D::PPW; ++k) {
-                const int p = wave * D::PPW + k;
-                wp[k] = wsh[p];
-#pragma unroll
-                for (int f = 0; f < D::FPT; ++f) {
-                    const int t = lane + 64 * f;
-                    const float2 c = t < NTP ? sraw[p * D::LDS_S + t] : make_float2(0.f, 0.f);
-                    cr[k][f] = wp[k] * (double)c.x;
-                    ci[k][f] = wp[k] * (double)c.y;
+                for (int q = 0; q < D::KG; ++q) v += ypart[(q * PX + p) * 16 + col];
+                // (Re y_j, Im y_j) meet in lane col = j after a rotate by 8 within the row
+                const float vi = __shfl_xor(v, 8, 16);
+                const int j = col;
+                float yr = 0.f, yi = 0.f;
+                if (j < RMAX && j < r) { yr = v; yi = vi; }
+                if (on) {
+                    if (j < RMAX) ysh[p * RMAX + j] = make_float2(yr, yi);
+                    uint32_t hh, ll;
+                    split_bf16x2(yr, yi, hh, ll);
+                    Ah[(NTP + j) * LDB + p] = hh;      // REXT = 16 columns, zero beyond r
+                    Al[(NTP + j) * LDB + p] = ll;
                 }
             }
-            for (int j = 0; j < r; ++j) {
-                double2 v[D::FPT];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // ---- D: c' = w s - y V_r^H for frames lane + 64 f, pixels of the wave
+            {
+                double cr[D::PPW][D::FPT], ci[D::PPW][D::FPT];
+                double wp[D::PPW];
 #pragma unroll
-                for (int f = 0; f < D::FPT; ++f) {
-                    const int t = lane + 64 * f;
-                    v[f] = t < NTP ? vrs[j * NTP + t] : make_double2(0.0, 0.0);
-                }
-#pragma unroll
-                for (int k = 0; k < D::PPW; ++k) {
-                    const float2 yk = ysh[(wave * D::PPW + k) * RMAX + j];
-                    const double yr = (double)yk.x, yi = (double)yk.y;
+                for (int kp = 0; kp < D::PPW; ++kp) {
+                    const int p = wave * D::PPW + kp;
+                    wp[kp] = wsh[p];
 #pragma unroll
                     for (int f = 0; f < D::FPT; ++f) {
-                        // minus y * conj(v)
-                        cr[k][f] = fma(-yr, v[f].x, fma(-yi, v[f].y, cr[k][f]));
-                        ci[k][f] = fma(-yi, v[f].x, fma(yr, v[f].y, ci[k][f]));
+                        const int t = lane + 64 * f;
+                        const float2 c = t < NTP ? sraw[p * D::LDS_S + t] : make_float2(0.f, 0.f);
+                        cr[kp][f] = wp[kp] * (double)c.x;
+                        ci[kp][f] = wp[kp] * (double)c.y;
                     }
                 }
-            }
+                for (int j = 0; j < r; ++j) {
+                    double2 v[D::FPT];
 #pragma unroll
-            for (int k = 0; k < D::PPW; ++k) {
-                const int p = wave * D::PPW + k;
+                    for (int f = 0; f < D::FPT; ++f) {
+                        const int t = lane + 64 * f;
+                        v[f] = t < NTP ? vrs[j * NTP + t] : make_double2(0.0, 0.0);
+                    }
 #pragma unroll
-                for (int f = 0; f < D::FPT; ++f) {
-                    const int t = lane + 64 * f;
-                    if (t < NTP) {
-                        const bool in = t < nt;
-                        uint32_t h, l;
-                        split_bf16x2(in ? (float)cr[k][f] : 0.f, in ? (float)ci[k][f] : 0.f, h, l);
-                        Ah[t * LDB + p] = h;
-                        Al[t * LDB + p] = l;
+                    for (int kp = 0; kp < D::PPW; ++kp) {
+                        const float2 yk = ysh[(wave * D::PPW + kp) * RMAX + j];
+                        const double yr = (double)yk.x, yi = (double)yk.y;
+#pragma unroll
+                        for (int f = 0; f < D::FPT; ++f) {
+                            // minus y * conj(v)
+                            cr[kp][f] = fma(-yr, v[f].x, fma(-yi, v[f].y, cr[kp][f]));
+                            ci[kp][f] = fma(-yi, v[f].x, fma(yr, v[f].y, ci[kp][f]));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int kp = 0; kp < D::PPW; ++kp) {
+                    const int p = wave * D::PPW + kp;
+#pragma unroll
+                    for (int f = 0; f < D::FPT; ++f) {
+                        const int t = lane + 64 * f;
+                        if (t < NTP) {
+                            const bool in = t < nt;
+                            uint32_t h, l;
+                            split_bf16x2(in ? (float)cr[kp][f] : 0.f, in ? (float)ci[kp][f] : 0.f, h, l);
+                            Ah[t * LDB + p] = h;
+                            Al[t * LDB + p] = l;
+                        }
                     }
                 }
             }
         }
-        __syncthreads();
+        if (!PIPE) __syncthreads();
         // ---- E
-        gram_mfma_bf16<C>(Ah, Al, aoff, boff, valid, acc, lane);
+        if (cd_first && egram) gram_mfma_bf16<C>(Eh, El, aoff, boff, valid, acc, lane);
     }
 #pragma unroll
     for (int m = 0; m < 2 * C::MAXP; ++m) {
