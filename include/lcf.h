@@ -134,7 +134,7 @@ typedef struct {
 #define LCF_OPT_MAX_SWEEPS   2  /* Jacobi sweep cap (default 30)                            */
 #define LCF_OPT_USE_GRAPH    3  /* 1 = capture the launch chain in a hipGraph and replay it
                                    for repeated calls with the same plan (default 0)       */
-#define LCF_OPT_SUBSPACE_IT  4  /* subspace iterations for the tissue basis (default 6)     */
+#define LCF_OPT_SUBSPACE_IT  4  /* subspace iterations for the tissue basis (default 3)     */
 #define LCF_OPT_STAGE_TIMING 5  /* 1 = bracket every kernel launch with HIP events on the
                                    caller's stream and accumulate per-stage device time
                                    (read with lcf_stage_time; default 0)                  */

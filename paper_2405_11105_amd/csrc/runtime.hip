@@ -249,7 +249,7 @@ struct lcf_context {
     int schedule = 0;
     int max_sweeps = 30;
     int use_graph = 0;
-    int sub_iters = 6;
+    int sub_iters = 3;
     char* dbuf = nullptr;
     size_t dcap = 0;
     char* hbuf = nullptr;
