@@ -119,7 +119,8 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const SubsetDesc sd = ws.sub[s];
     const int nt = sd.nt;
-    const double2* R = ws.rwin + (long)s * NTP * NTP;
+    const float2* Rf = ws.rwin + (long)s * NTP * NTP;
+    auto R = [&](long i) { const float2 f = Rf[i]; return make_double2((double)f.x, (double)f.y); };
     double2* hv = ws.hv + (long)s * RMAX * NTP;
     double* htau = ws.htau + (long)s * RMAX;
     const int ns = nt < RMAX ? nt : RMAX;
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
     // start block: the columns of R at its ns largest diagonal entries, found by
     // the rank of each entry (ties by index; NaN ranks last)
     for (int t = tid; t < nt; t += 256) {
-        const double d = R[(long)t * NTP + t].x;
+        const double d = R((long)t * NTP + t).x;
         dg[t] = d == d ? d : -1e300;
     }
     if (tid < RMAX) piv[tid] = tid;
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
     for (int e = tid; e < NTP * RMAX; e += 256) {
         const int t = e / RMAX, j = e % RMAX;
         // R[t][piv] = conj(R[piv][t])
-        X[e] = (t < nt && j < ns) ? cconj(R[(long)piv[j] * NTP + t]) : make_double2(0.0, 0.0);
+        X[e] = (t < nt && j < ns) ? cconj(R((long)piv[j] * NTP + t)) : make_double2(0.0, 0.0);
     }
     __syncthreads();
 
@@ -202,7 +203,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
             for (int j = 0; j < RMAX; ++j) acc[j] = make_double2(0.0, 0.0);
             if (t < nt) {
                 for (int u = half; u < nt; u += 2) {
-                    const double2 rtu = cconj(R[(long)u * NTP + t]);
+                    const double2 rtu = cconj(R((long)u * NTP + t));
 #pragma unroll
                     for (int j = 0; j < RMAX; ++j) acc[j] = cadd(acc[j], cmul(rtu, X[u * RMAX + j]));
                 }
@@ -330,8 +331,10 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
 // R = R2 + G' V_r^H + V_r G'^H + V_r (Y^H Y) V_r^H   (exact for C_w = C' + Y V_r^H)
 // written as R2 + E V_r^H + V_r E^H with E = G' + V_r (Y^H Y) / 2, then
 // B = Q^H R Q = H_{r-1} .. H_0 R H_0 .. H_{r-1} (Hermitian rank-2 updates).
+// keep_r: also write R (original basis) to the P area, for the covariance
+// diagnostics exported right after this stage (the EVD reuses that area).
 template <int NTP>
-__global__ void __launch_bounds__(256) k_assemble(Workspace ws) {
+__global__ void __launch_bounds__(256) k_assemble(Workspace ws, int keep_r) {
     constexpr int NTE = NTP + REXT;
     __shared__ double2 E[NTP * RMAX];
     __shared__ double2 V[NTP * RMAX];
@@ -381,7 +384,7 @@ __global__ void __launch_bounds__(256) k_assemble(Workspace ws) {
                     }
                     if (t == u) v.y = 0.0;
                 }
-                if (t < NTP && u < NTP) ws.pmat[(long)s * NTP * NTP + (long)t * NTP + u] = v;
+                if (keep_r && t < NTP && u < NTP) ws.pmat[(long)s * NTP * NTP + (long)t * NTP + u] = v;
                 acc[a][b] = v;
             }
         for (int j = 0; j < r; ++j) {
@@ -455,7 +458,7 @@ __global__ void __launch_bounds__(256) k_assemble(Workspace ws) {
                 if (t == u) b.y = 0.0;
             }
             B[e] = b;
-            ws.pmat[(long)s * NTP * NTP + e] = b;
+            if (keep_r) ws.pmat[(long)s * NTP * NTP + e] = b;
         }
         __syncthreads();
         for (int j = 0; j < r; ++j) {
@@ -1536,20 +1539,21 @@ __global__ void __launch_bounds__(JAC_THREADS) k_heevd(const double2* a, double*
 // ------------------------------------------------------------------ launchers
 
 template <int NTP>
-static void small_dispatch(const Workspace& ws, int stage, double rho, int iters, hipStream_t st) {
-    if (stage == 0) hipLaunchKernelGGL((k_tissue<NTP>), dim3(ws.S), dim3(256), 0, st, ws, rho, iters);
-    else hipLaunchKernelGGL((k_assemble<NTP>), dim3(ws.S), dim3(256), 0, st, ws);
+// iarg: subspace iterations (tissue basis) or the keep-R flag (assembly)
+static void small_dispatch(const Workspace& ws, int stage, double rho, int iarg, hipStream_t st) {
+    if (stage == 0) hipLaunchKernelGGL((k_tissue<NTP>), dim3(ws.S), dim3(256), 0, st, ws, rho, iarg);
+    else hipLaunchKernelGGL((k_assemble<NTP>), dim3(ws.S), dim3(256), 0, st, ws, iarg);
 }
 
-static hipError_t small_stage(const Workspace& ws, int stage, double rho, int iters, hipStream_t st) {
+static hipError_t small_stage(const Workspace& ws, int stage, double rho, int iarg, hipStream_t st) {
     switch (ws.ntp) {
-        case 32: small_dispatch<32>(ws, stage, rho, iters, st); break;
-        case 64: small_dispatch<64>(ws, stage, rho, iters, st); break;
-        case 96: small_dispatch<96>(ws, stage, rho, iters, st); break;
-        case 128: small_dispatch<128>(ws, stage, rho, iters, st); break;
-        case 160: small_dispatch<160>(ws, stage, rho, iters, st); break;
-        case 208: small_dispatch<208>(ws, stage, rho, iters, st); break;
-        case 256: small_dispatch<256>(ws, stage, rho, iters, st); break;
+        case 32: small_dispatch<32>(ws, stage, rho, iarg, st); break;
+        case 64: small_dispatch<64>(ws, stage, rho, iarg, st); break;
+        case 96: small_dispatch<96>(ws, stage, rho, iarg, st); break;
+        case 128: small_dispatch<128>(ws, stage, rho, iarg, st); break;
+        case 160: small_dispatch<160>(ws, stage, rho, iarg, st); break;
+        case 208: small_dispatch<208>(ws, stage, rho, iarg, st); break;
+        case 256: small_dispatch<256>(ws, stage, rho, iarg, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1564,8 +1568,8 @@ hipError_t launch_tissue(const Workspace& ws, double rho, int iters, hipStream_t
     return small_stage(ws, 0, rho, iters, st);
 }
 
-hipError_t launch_assemble(const Workspace& ws, hipStream_t st) {
-    return small_stage(ws, 1, 0.0, 0, st);
+hipError_t launch_assemble(const Workspace& ws, int keep_r, hipStream_t st) {
+    return small_stage(ws, 1, 0.0, keep_r ? 1 : 0, st);
 }
 
 static int max_nt(const Workspace& ws) { return ws.ntp; }

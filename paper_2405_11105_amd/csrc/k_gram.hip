@@ -633,8 +633,9 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
 
 // Sum the chunk partials of each subset in chunk order (FP64) and expand the
 // upper S/T tiles into the full Hermitian matrix out[s][NTE][NTE].
-template <int NTE>
-__global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, double2* out, int tt) {
+// T = double2 (pass 2: the extended Gram) or float2 (pass 1).
+template <int NTE, class T>
+__global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, T* out, int tt) {
     constexpr int NT16 = NTE / 16;
     const int s = blockIdx.y;
     const int u = blockIdx.x;
@@ -651,12 +652,13 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Workspace ws, double2* out,
         tv += (double)ws.partial[((long)c * tt + 2 * u + 1) * 256 + e];
     }
     const int row = i * 16 + rin, colx = j * 16 + cin;
-    double2* o = out + (long)s * NTE * NTE;
+    T* o = out + (long)s * NTE * NTE;
+    using E = decltype(o->x);
     if (row == colx) {
-        o[(long)row * NTE + colx] = make_double2(sv, 0.0);
+        o[(long)row * NTE + colx] = T{(E)sv, (E)0};
     } else {
-        o[(long)row * NTE + colx] = make_double2(sv, tv);
-        o[(long)colx * NTE + row] = make_double2(sv, -tv);
+        o[(long)row * NTE + colx] = T{(E)sv, (E)tv};
+        o[(long)colx * NTE + row] = T{(E)sv, (E)(-tv)};
     }
     if (!isfinite(sv) || !isfinite(tv)) atomicOr(&ws.flags[s], 2);
 }
@@ -670,8 +672,10 @@ static void gram_launch(const Workspace& ws, bool reduce, hipStream_t st) {
         if (DEFL && PREC == 1) hipLaunchKernelGGL((k_gram_defl<NTP>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
         else hipLaunchKernelGGL((k_gram<NTP, DEFL, (DEFL ? 0 : PREC)>), dim3(ws.nchunks), dim3(C::THREADS), 0, st, ws);
     }
-    else hipLaunchKernelGGL((k_gram_reduce<C::NTE>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws,
-                            DEFL ? ws.rext : ws.rwin, C::TT);
+    else if constexpr (DEFL)
+        hipLaunchKernelGGL((k_gram_reduce<C::NTE, double2>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws, ws.rext, C::TT);
+    else
+        hipLaunchKernelGGL((k_gram_reduce<C::NTE, float2>), dim3(C::TPM, ws.S), dim3(256), 0, st, ws, ws.rwin, C::TT);
 }
 
 template <int NTP>

@@ -77,7 +77,8 @@ struct Workspace {
     const PacketDesc* pkts;
     double* wtab;       // window factor pool
     float* partial;     // Gram partials [nchunks][ntile_pairs*2][256]
-    double2* rwin;      // [S][ntp][ntp] windowed covariance (pass 1)
+    float2* rwin;       // [S][ntp][ntp] windowed covariance of pass 1, FP32 (it only locates the
+                        // tissue subspace, and its own Gram is no more accurate than that)
     double2* rext;      // [S][nte][nte] Gram of [C' | Y] (pass 2)
     double2* hv;        // [S][RMAX][ntp] Householder vectors
     double* htau;       // [S][RMAX]

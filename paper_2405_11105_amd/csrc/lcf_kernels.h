@@ -14,7 +14,7 @@ hipError_t launch_windows(const Workspace& ws, hipStream_t st);
 hipError_t launch_gram(const Workspace& ws, bool defl, bool reduce, int precision, hipStream_t st);
 int gram_tiles(int ntp, bool defl);
 hipError_t launch_tissue(const Workspace& ws, double rho, int iters, hipStream_t st);
-hipError_t launch_assemble(const Workspace& ws, hipStream_t st);
+hipError_t launch_assemble(const Workspace& ws, int keep_r, hipStream_t st);
 hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st);
 hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStream_t st);
 hipError_t launch_heevd(int n, int nt, const double2* a, double* w, double2* v, int* sweeps,

@@ -414,7 +414,7 @@ Layout make_layout(const Plan& pl) {
     const int tt = std::max(gram_tiles(pl.ntp, false), gram_tiles(pl.ntp, true));
     L.off_wtab = take(pl.wtab_len * sizeof(double));
     L.off_partial = take(pl.chunks.size() * (size_t)tt * 256 * sizeof(float));
-    L.off_rwin = take(S * ntp * ntp * sizeof(double2));
+    L.off_rwin = take(S * ntp * ntp * sizeof(float2));
     L.off_rext = take(S * nte * nte * sizeof(double2));
     L.off_hv = take(S * RMAX * ntp * sizeof(double2));
     L.off_htau = take(S * RMAX * sizeof(double));
@@ -452,7 +452,7 @@ Workspace make_ws(char* base, const Layout& L, const Plan& pl, const float* expl
     ws.pkts = (const PacketDesc*)(base + L.off_pkts);
     ws.wtab = (double*)(base + L.off_wtab);
     ws.partial = (float*)(base + L.off_partial);
-    ws.rwin = (double2*)(base + L.off_rwin);
+    ws.rwin = (float2*)(base + L.off_rwin);
     ws.rext = (double2*)(base + L.off_rext);
     ws.hv = (double2*)(base + L.off_hv);
     ws.htau = (double*)(base + L.off_htau);
@@ -562,7 +562,7 @@ lcf_status run_stages(lcf_context* c, const Workspace& ws, const lcf_threshold* 
     { STAGE(c, LCF_STAGE_TISSUE, st); HIPCHK(launch_tissue(ws, thr->deflate_rho, c->sub_iters, st)); }
     { STAGE(c, LCF_STAGE_GRAM2, st); HIPCHK(launch_gram(ws, true, false, prec, st)); }
     { STAGE(c, LCF_STAGE_GRAM2_REDUCE, st); HIPCHK(launch_gram(ws, true, true, prec, st)); }
-    { STAGE(c, LCF_STAGE_ASSEMBLE, st); HIPCHK(launch_assemble(ws, st)); }
+    { STAGE(c, LCF_STAGE_ASSEMBLE, st); HIPCHK(launch_assemble(ws, cov != nullptr, st)); }
     if (cov) HIPCHK(launch_export_cov(ws, 0, ws.S, nt, cov, st));
     return LCF_OK;
 }
