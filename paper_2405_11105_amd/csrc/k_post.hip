@@ -105,8 +105,18 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
 // split-BF16 [P; M] planes used by the reprojection GEMM.
 constexpr int PCC = 16;
 
+// From 96 frames up the 128 x 128 P blocks are spread over 512 threads (4 rows
+// x 8 columns each): with 256 threads the 8 x 8 FP64 accumulators left room
+// for one wave per SIMD only.
+template <int NTP>
+struct PjCfg {
+    static constexpr int NTHR = NTP >= 96 ? 512 : 256;
+    static constexpr int RA = 2048 / NTHR;      // rows per thread in a 128 x 128 block
+};
+
 template <int NTP, int PREC>
-__global__ void __launch_bounds__(256) k_projector(Workspace ws) {
+__global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
+    constexpr int NTHR = PjCfg<NTP>::NTHR, RA = PjCfg<NTP>::RA, NWV = NTHR / 64;
     constexpr int NTE = NTP + REXT;
     constexpr int NTEP = (NTE + 31) / 32 * 32;
     constexpr int NB = (NTP + 127) / 128;       // 128 x 128 blocks per dimension
@@ -118,7 +128,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     __shared__ double cw[PCC];
     __shared__ double tau[RMAX];
     __shared__ int act[NTP];
-    __shared__ int wcnt[4];
+    __shared__ int wcnt[NWV];
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nt = ws.sub[s].nt;
     const int r = ws.rank[s];
@@ -129,7 +139,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     const bool flag = tid < nt && fabs(1.0 - wts[tid < NTP ? tid : 0]) > 1e-17;
     const unsigned long long mask = __ballot(flag);
     if (lane == 0) wcnt[wave] = __popcll(mask);
-    for (int e = tid; e < RMAX * NTP; e += 256) {
+    for (int e = tid; e < RMAX * NTP; e += NTHR) {
         const int j = e / NTP, t = e % NTP;
         vh[e] = j < r ? ws.hv[((long)s * RMAX + j) * NTP + t] : make_double2(0.0, 0.0);
         // M starts from V_r^H (zero beyond nt and r)
@@ -138,7 +148,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     if (tid < RMAX) tau[tid] = tid < r ? ws.htau[(long)s * RMAX + tid] : 0.0;
     __syncthreads();
     int nact = 0, off = 0;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < NWV; ++w) {
         off += w < wave ? wcnt[w] : 0;
         nact += wcnt[w];
     }
@@ -148,15 +158,16 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     const int ti = tid >> 4, ui = tid & 15;
     for (int bb = 0; bb < NB * NB; ++bb) {
         const int tb = 128 * (bb / NB), ub = 128 * (bb % NB);
-        double2 acc[8][8];
+        double2 acc[RA][8];
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
             for (int b = 0; b < 8; ++b) acc[a][b] = make_double2(0.0, 0.0);
         for (int c0 = 0; c0 < nact; c0 += PCC) {
             const int cn = nact - c0 < PCC ? nact - c0 : PCC;
             // W' of the chunk: column c by lanes 16 c .. 16 c + 15, rows l + 16 i
-            {
+            // (threads 0 .. 255)
+            if (tid < 16 * PCC) {
                 const int c = tid >> 4, l = tid & 15;
                 double2 x[RW];
 #pragma unroll
@@ -187,10 +198,10 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
             __syncthreads();
             // P block: acc[a][b] -= cw_c W'[t_a][c] conj(W'[u_b][c])
             for (int c = 0; c < cn; ++c) {
-                double2 wt[8], wu[8];
+                double2 wt[RA], wu[8];
 #pragma unroll
-                for (int a = 0; a < 8; ++a) {
-                    const int t = tb + 8 * ti + a;
+                for (int a = 0; a < RA; ++a) {
+                    const int t = tb + RA * ti + a;
                     wt[a] = t < NTP ? cscale(Wl[c * NTP + t], cw[c]) : make_double2(0.0, 0.0);
                 }
 #pragma unroll
@@ -199,7 +210,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
                     wu[b] = u < NTP ? Wl[c * NTP + u] : make_double2(0.0, 0.0);
                 }
 #pragma unroll
-                for (int a = 0; a < 8; ++a)
+                for (int a = 0; a < RA; ++a)
 #pragma unroll
                     for (int b = 0; b < 8; ++b) {
                         acc[a][b].x -= fma(wt[a].x, wu[b].x, wt[a].y * wu[b].y);
@@ -208,7 +219,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
             }
             // M once: M[j][n] -= sum_c W[j][c] (1 - w_c) conj(W'[n][c])
             if (bb == 0) {
-                for (int e = tid; e < RMAX * NTP; e += 256) {
+                for (int e = tid; e < RMAX * NTP; e += NTHR) {
                     const int j = e / NTP, n = e % NTP;
                     if (j < r && n < nt) {
                         double2 m = Msh[e];
@@ -230,39 +241,46 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
         for (int b = 0; b < 8; ++b) {
             const int n = ub + ui + 16 * b;
             if (n >= NTP) continue;
-            float re[8], im[8];
+            float re[RA], im[RA];
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const int k = tb + 8 * ti + a;
+            for (int a = 0; a < RA; ++a) {
+                const int k = tb + RA * ti + a;
                 const bool in = k < nt && n < nt;
                 re[a] = in ? (float)((k == n ? 1.0 : 0.0) + acc[a][b].x) : 0.f;
                 im[a] = in ? (float)acc[a][b].y : 0.f;
             }
-            const int k0 = tb + 8 * ti;
+            const int k0 = tb + RA * ti;
             if (k0 >= NTP) continue;
             if (PREC == 1) {
                 uint16_t* pt = reinterpret_cast<uint16_t*>(ws.breal + (long)s * (2 * NTE) * (2 * NTP));
-                uint32_t h[8], l[8];
+                uint32_t h[RA], l[RA];
 #pragma unroll
-                for (int a = 0; a < 8; ++a) split_bf16x2(re[a], im[a], h[a], l[a]);
-                u32x4 hr, lr, hi4, li4;
+                for (int a = 0; a < RA; ++a) split_bf16x2(re[a], im[a], h[a], l[a]);
+                // RA consecutive rows k of each plane: RA / 2 words
+                uint32_t hr[RA / 2], lr[RA / 2], hi4[RA / 2], li4[RA / 2];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < RA / 2; ++q) {
                     hr[q] = __builtin_amdgcn_perm(h[2 * q + 1], h[2 * q], 0x05040100u);
                     lr[q] = __builtin_amdgcn_perm(l[2 * q + 1], l[2 * q], 0x05040100u);
                     hi4[q] = __builtin_amdgcn_perm(h[2 * q + 1], h[2 * q], 0x07060302u);
                     li4[q] = __builtin_amdgcn_perm(l[2 * q + 1], l[2 * q], 0x07060302u);
                 }
                 const long e = (long)n * NTEP + k0;
-                *reinterpret_cast<u32x4*>(pt + 0L * NTP * NTEP + e) = hr;
-                *reinterpret_cast<u32x4*>(pt + 1L * NTP * NTEP + e) = lr;
-                *reinterpret_cast<u32x4*>(pt + 2L * NTP * NTEP + e) = hi4;
-                *reinterpret_cast<u32x4*>(pt + 3L * NTP * NTEP + e) = li4;
+                auto put = [&](long plane, const uint32_t* w) {
+                    if constexpr (RA == 8)
+                        *reinterpret_cast<u32x4*>(pt + plane * NTP * NTEP + e) = u32x4{w[0], w[1], w[2], w[3]};
+                    else
+                        *reinterpret_cast<uint2*>(pt + plane * NTP * NTEP + e) = make_uint2(w[0], w[1]);
+                };
+                put(0, hr);
+                put(1, lr);
+                put(2, hi4);
+                put(3, li4);
             } else {
                 // real form: row k of [P; M] at k, its i-multiple at NTE + k
                 float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
 #pragma unroll
-                for (int a = 0; a < 8; ++a) {
+                for (int a = 0; a < RA; ++a) {
                     const int k = k0 + a;
                     Br[(long)k * (2 * NTP) + n] = re[a];
                     Br[(long)k * (2 * NTP) + NTP + n] = im[a];
@@ -275,7 +293,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
     // rows k in [NTP, NTEP) of the operand: M for k < NTP + r, zero beyond
     if (PREC == 1) {
         uint16_t* pt = reinterpret_cast<uint16_t*>(ws.breal + (long)s * (2 * NTE) * (2 * NTP));
-        for (int e = tid; e < NTP * (NTEP - NTP); e += 256) {
+        for (int e = tid; e < NTP * (NTEP - NTP); e += NTHR) {
             const int n = e / (NTEP - NTP), j = e % (NTEP - NTP);
             const double2 v = j < RMAX ? Msh[j * NTP + n] : make_double2(0.0, 0.0);
             uint32_t h, l;
@@ -288,7 +306,7 @@ __global__ void __launch_bounds__(256) k_projector(Workspace ws) {
         }
     } else {
         float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
-        for (int e = tid; e < REXT * NTP; e += 256) {
+        for (int e = tid; e < REXT * NTP; e += NTHR) {
             const int j = e / NTP, n = e % NTP;
             const double2 v = j < RMAX ? Msh[j * NTP + n] : make_double2(0.0, 0.0);
             const int k = NTP + j;
@@ -1482,8 +1500,8 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
 template <int NTP>
 static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t st) {
     if (stage == 0) {
-        if (prec == 0) hipLaunchKernelGGL((k_projector<NTP, 0>), dim3(ws.S), dim3(256), 0, st, ws);
-        else hipLaunchKernelGGL((k_projector<NTP, 1>), dim3(ws.S), dim3(256), 0, st, ws);
+        if (prec == 0) hipLaunchKernelGGL((k_projector<NTP, 0>), dim3(ws.S), dim3(PjCfg<NTP>::NTHR), 0, st, ws);
+        else hipLaunchKernelGGL((k_projector<NTP, 1>), dim3(ws.S), dim3(PjCfg<NTP>::NTHR), 0, st, ws);
     } else if (ws.ntiles > 0) {
         const int grid = (ws.ntiles + 7) / 8 * 8;      // multiple of 8 for the XCD mapping
         if constexpr (trows_max(NTP) >= 4) {
