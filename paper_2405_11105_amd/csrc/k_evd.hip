@@ -333,26 +333,36 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
 // B = Q^H R Q = H_{r-1} .. H_0 R H_0 .. H_{r-1} (Hermitian rank-2 updates).
 // keep_r: also write R (original basis) to the P area, for the covariance
 // diagnostics exported right after this stage (the EVD reuses that area).
+// Up to 128 frames B is held in registers, 4 rows x 8 columns of it per thread
+// over 512 threads (8 x 8 per thread over 256 needed AGPRs as spill space and
+// left one wave per SIMD); beyond, 256 threads work on it in global memory.
 template <int NTP>
-__global__ void __launch_bounds__(256) k_assemble(Workspace ws, int keep_r) {
+struct AsmCfg {
+    static constexpr int NTHR = NTP <= 128 ? 512 : 256;
+    static constexpr int RA = 2048 / NTHR;      // rows per thread (register path)
+};
+
+template <int NTP>
+__global__ void __launch_bounds__(AsmCfg<NTP>::NTHR) k_assemble(Workspace ws, int keep_r) {
     constexpr int NTE = NTP + REXT;
+    constexpr int NTHR = AsmCfg<NTP>::NTHR, RA = AsmCfg<NTP>::RA, NRG = NTHR / 16;
     __shared__ double2 E[NTP * RMAX];
     __shared__ double2 V[NTP * RMAX];
     __shared__ double2 P[2][NTP];
     __shared__ double2 vh[RMAX * NTP];
-    __shared__ double red[2][16];
+    __shared__ double red[2][NRG > 16 ? NRG : 16];
     const int s = blockIdx.x, tid = threadIdx.x;
     const int nt = ws.sub[s].nt;
     const int r = ws.rank[s];
     const double2* X = ws.rext + (long)s * NTE * NTE;
     double2* B = ws.bmat + (long)s * NTP * NTP;
-    for (int e = tid; e < NTP * RMAX; e += 256) {
+    for (int e = tid; e < NTP * RMAX; e += NTHR) {
         V[e] = ws.vr64[(long)s * NTP * RMAX + e];
         const int j = e / NTP;
         vh[e] = j < r ? ws.hv[(long)s * RMAX * NTP + e] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int e = tid; e < NTP * RMAX; e += 256) {
+    for (int e = tid; e < NTP * RMAX; e += NTHR) {
         const int t = e / RMAX, j = e % RMAX;
         double2 acc = make_double2(0.0, 0.0);
         if (t < nt && j < r) {
@@ -364,17 +374,17 @@ __global__ void __launch_bounds__(256) k_assemble(Workspace ws, int keep_r) {
     }
     __syncthreads();
     if constexpr (NTP <= 128) {
-        // R, then B, in registers: thread (ti, ui) holds rows 8 ti + a, columns
+        // R, then B, in registers: thread (ti, ui) holds rows RA ti + a, columns
         // ui + 16 b. Per reflector: p = B v by lane shuffles over the 16 lanes of
         // a row group, v^H p and the rows of p through LDS (one barrier), then
         // B -= tau (v w^H + w v^H), w = p - (tau / 2)(v^H p) v.
         const int ti = threadIdx.x >> 4, ui = threadIdx.x & 15;
-        double2 acc[8][8];
+        double2 acc[RA][8];
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                const int t = 8 * ti + a, u = ui + 16 * b;
+                const int t = RA * ti + a, u = ui + 16 * b;
                 double2 v = make_double2(0.0, 0.0);
                 if (t < nt && u < nt) {
                     v = X[(long)t * NTE + u];
@@ -390,59 +400,62 @@ __global__ void __launch_bounds__(256) k_assemble(Workspace ws, int keep_r) {
         for (int j = 0; j < r; ++j) {
             const double tau = ws.htau[(long)s * RMAX + j];
             const double2* v = vh + j * NTP;
-            double2 vu[8];
+            // column-outer loops keep one column's v (and w) live at a time
+            double2 pa[RA];
+#pragma unroll
+            for (int a = 0; a < RA; ++a) pa[a] = make_double2(0.0, 0.0);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int u = ui + 16 * b;
-                vu[b] = u < NTP ? v[u] : make_double2(0.0, 0.0);
+                const double2 vu = u < NTP ? v[u] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int a = 0; a < RA; ++a) pa[a] = cadd(pa[a], cmul(acc[a][b], vu));
             }
             double kpart = 0.0;
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                double2 pa = make_double2(0.0, 0.0);
-#pragma unroll
-                for (int b = 0; b < 8; ++b) pa = cadd(pa, cmul(acc[a][b], vu[b]));
+            for (int a = 0; a < RA; ++a) {
 #pragma unroll
                 for (int m = 8; m >= 1; m >>= 1) {
-                    pa.x += __shfl_xor(pa.x, m, 16);
-                    pa.y += __shfl_xor(pa.y, m, 16);
+                    pa[a].x += __shfl_xor(pa[a].x, m, 16);
+                    pa[a].y += __shfl_xor(pa[a].y, m, 16);
                 }
-                const int t = 8 * ti + a;
-                if (ui == 0 && t < NTP) P[j & 1][t] = pa;
-                if (t < NTP) kpart += cmulc(v[t], pa).x;
+                const int t = RA * ti + a;
+                if (ui == 0 && t < NTP) P[j & 1][t] = pa[a];
+                if (t < NTP) kpart += cmulc(v[t], pa[a]).x;
             }
             if (ui == 0) red[j & 1][ti] = kpart;
             __syncthreads();
             double K = 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) K += red[j & 1][q];
+            for (int q = 0; q < NRG; ++q) K += red[j & 1][q];
             const double hk = 0.5 * tau * K;
-            double2 wu[8];
+            double2 vt[RA], wt[RA];
+#pragma unroll
+            for (int a = 0; a < RA; ++a) {
+                const int t = RA * ti + a;
+                vt[a] = t < NTP ? v[t] : make_double2(0.0, 0.0);
+                wt[a] = t < NTP ? csub(P[j & 1][t], cscale(vt[a], hk)) : make_double2(0.0, 0.0);
+            }
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const int u = ui + 16 * b;
-                wu[b] = u < NTP ? csub(P[j & 1][u], cscale(vu[b], hk)) : make_double2(0.0, 0.0);
-            }
+                const double2 vu = u < NTP ? v[u] : make_double2(0.0, 0.0);
+                const double2 wu = u < NTP ? csub(P[j & 1][u], cscale(vu, hk)) : make_double2(0.0, 0.0);
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const int t = 8 * ti + a;
-                const double2 vt = t < NTP ? v[t] : make_double2(0.0, 0.0);
-                const double2 wt = t < NTP ? csub(P[j & 1][t], cscale(vt, hk)) : make_double2(0.0, 0.0);
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
+                for (int a = 0; a < RA; ++a) {
                     // B -= tau (v_t conj(w_u) + w_t conj(v_u))
-                    const double2 d = cadd(cmulc(wu[b], vt), cmulc(vu[b], wt));
+                    const double2 d = cadd(cmulc(wu, vt[a]), cmulc(vu, wt[a]));
                     double2 x = csub(acc[a][b], cscale(d, tau));
-                    if (t == ui + 16 * b) x.y = 0.0;
+                    if (RA * ti + a == u) x.y = 0.0;
                     acc[a][b] = x;
                 }
             }
         }
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                const int t = 8 * ti + a, u = ui + 16 * b;
+                const int t = RA * ti + a, u = ui + 16 * b;
                 if (t < NTP && u < NTP) B[(long)t * NTP + u] = (t < nt && u < nt) ? acc[a][b] : make_double2(0.0, 0.0);
             }
     } else {
@@ -1542,7 +1555,7 @@ template <int NTP>
 // iarg: subspace iterations (tissue basis) or the keep-R flag (assembly)
 static void small_dispatch(const Workspace& ws, int stage, double rho, int iarg, hipStream_t st) {
     if (stage == 0) hipLaunchKernelGGL((k_tissue<NTP>), dim3(ws.S), dim3(256), 0, st, ws, rho, iarg);
-    else hipLaunchKernelGGL((k_assemble<NTP>), dim3(ws.S), dim3(256), 0, st, ws, iarg);
+    else hipLaunchKernelGGL((k_assemble<NTP>), dim3(ws.S), dim3(AsmCfg<NTP>::NTHR), 0, st, ws, iarg);
 }
 
 static hipError_t small_stage(const Workspace& ws, int stage, double rho, int iarg, hipStream_t st) {
