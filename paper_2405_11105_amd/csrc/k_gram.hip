@@ -130,10 +130,14 @@ __attribute__((amdgpu_waves_per_eu(GramCfg<NTP, DEFL, PREC>::MIN_WAVES)))
 k_gram(Workspace ws) {
     using C = GramCfg<NTP, DEFL, PREC>;
     constexpr int NTE = C::NTE, IMO = C::IMO, LDA = C::LDA, LDB = C::LDB, PIX = C::PX;
-    __shared__ __attribute__((aligned(16))) uint32_t Aw[C::A_WORDS];
+    // Split-BF16 pass 1 with eight waves double-buffers the operand: the MFMAs
+    // of batch k - 1 run beside the writes of batch k (waves w and w + 4 share a
+    // SIMD and take the two in opposite order), one barrier per batch.
+    constexpr bool PIPE1 = !DEFL && PREC == 1 && C::WAVES == 8 && NTP <= 128;
+    __shared__ __attribute__((aligned(16))) uint32_t Aw[(PIPE1 ? 2 : 1) * C::A_WORDS];
     __shared__ double2 vrs[DEFL ? RMAX * NTP : 1];     // V_r, [j][t]
     float* A = reinterpret_cast<float*>(Aw);
-    uint32_t* Ah = Aw;                   // BF16 hi words [NTE][LDB]
+    uint32_t* Ah = Aw;                   // BF16 hi words [NTE][LDB] (batch being written)
     uint32_t* Al = Aw + NTE * LDB;       // BF16 lo words
 
     auto put = [&](int p, int c, float re, float im) {
@@ -247,6 +251,32 @@ k_gram(Workspace ws) {
         }
     };
     fetch(q0);
+    if constexpr (PIPE1) {
+        const int nb = (q1 - q0 + PIX - 1) / PIX;
+        const bool put_first = ((wave >> 2) & 1) == 0;
+        for (int k = 0; k < nb + 1; ++k) {
+            Ah = Aw + (k & 1) * C::A_WORDS;
+            Al = Ah + NTE * LDB;
+            const uint32_t* Eh = Aw + ((k & 1) ^ 1) * C::A_WORDS;    // batch k - 1
+            const uint32_t* El = Eh + NTE * LDB;
+            float2 cur[NPT];
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) cur[i] = c64_bits(nxt[i], fok && my_t0 + TSTEP * i < nt);
+            const double w = fok ? (sd.flat ? 1.0 : fwy * fwx) : 0.0;
+            __syncthreads();                       // batch k - 1 is written, batch k - 2's MFMAs are done
+            if (!put_first && k > 0) gram_mfma_bf16<C>(Eh, El, aoff, boff, valid, acc, lane);
+            if (k < nb) {
+                const float wf = (float)w;
+#pragma unroll
+                for (int i = 0; i < NPT; ++i) {
+                    const int t = my_t0 + TSTEP * i;
+                    if (t < NTP) put(my_p, t, wf * cur[i].x, wf * cur[i].y);
+                }
+                if (k + 1 < nb) fetch(q0 + (k + 1) * PIX);
+            }
+            if (put_first && k > 0) gram_mfma_bf16<C>(Eh, El, aoff, boff, valid, acc, lane);
+        }
+    } else
     for (int qb = q0; qb < q1; qb += PIX) {
         float2 cur[NPT];
 #pragma unroll
