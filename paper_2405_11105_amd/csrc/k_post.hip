@@ -356,8 +356,9 @@ struct RpCfg {
 
 template <int NTP, int PREC, int TR>
 __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspace ws) {
+    static_assert(PREC == 0, "the split-BF16 reprojection is k_reproj_sb");
     using C = RpCfg<NTP, PREC, TR>;
-    constexpr int NTEP = C::NTEP, LDK = C::LDK, IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
+    constexpr int IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
     constexpr int NTHR = C::NTHR, CTW = C::CTW, G = C::G, TP = C::TP, NRT = C::NRT;
     static_assert(TP % 16 == 0 && NTHR % TP == 0, "tile of whole MFMA row tiles");
     static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "y split within a row of 16 lanes");
@@ -368,9 +369,7 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
     __shared__ double2 vrs[RMAX * NTP];         // V_r, [j][t]
     __shared__ float wd[TP], wsum[TP];
     __shared__ float pdsh[C::NW * TP];
-    float* A = reinterpret_cast<float*>(abuf);                          // FP32: [p][LDA]
-    uint16_t* Ah = reinterpret_cast<uint16_t*>(abuf);                   // BF16 hi: [p][LDK]
-    uint16_t* Al = Ah + TP * LDK;                                       // BF16 lo
+    float* A = reinterpret_cast<float*>(abuf);                          // [p][LDA]
     float2* craw = reinterpret_cast<float2*>(abuf);                     // staging only: [p][LDC]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15;
@@ -393,27 +392,12 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
     const int pp = tid / G, part = tid % G;
 
     auto put = [&](int p, int c, float re, float im) {
-        if (PREC) {
-            const uint32_t rh = bf16_bits(re), ih = bf16_bits(im);
-            Ah[p * LDK + c] = (uint16_t)rh;
-            Ah[p * LDK + NTEP + c] = (uint16_t)ih;
-            Al[p * LDK + c] = (uint16_t)bf16_bits(re - __uint_as_float(rh << 16));
-            Al[p * LDK + NTEP + c] = (uint16_t)bf16_bits(im - __uint_as_float(ih << 16));
-        } else {
-            A[p * LDA + c] = re;
-            A[p * LDA + IMO + c] = im;
-        }
+        A[p * LDA + c] = re;
+        A[p * LDA + IMO + c] = im;
     };
-    // output column tile of accumulator m: split BF16 pairs (re, im) of frame
-    // tile q = wave * CTW / 2 + m / 2; FP32 takes consecutive tiles
-    auto ct_of = [&](int m) -> int {
-        if (PREC) {
-            const int q = wave * (CTW / 2) + (m >> 1);
-            return (m & 1) ? C::NNT + q : q;
-        }
-        return wave * CTW + m;
-    };
-    auto ct_ok = [&](int m) -> bool { return PREC ? wave * (CTW / 2) + (m >> 1) < C::NNT : ct_of(m) < C::CT; };
+    // output column tile of accumulator m: consecutive tiles per wave
+    auto ct_of = [&](int m) -> int { return wave * CTW + m; };
+    auto ct_ok = [&](int m) -> bool { return ct_of(m) < C::CT; };
     auto window = [&](const SubsetDesc& sd, int p) -> double {
         const int y = td.y + p / TW, x = td.x0 + p % TW;
         if (!in_tile(p) || y < sd.y0 || y > sd.y1 || x < sd.x0 || x > sd.x1) return 0.0;
@@ -464,7 +448,6 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         const SubsetDesc sd = ws.sub[s];
         const int r = ws.rank[s];
         const float alpha = (float)ws.alpha[s];
-        const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
@@ -528,81 +511,23 @@ __global__ void __launch_bounds__((RpCfg<NTP, PREC, TR>::NTHR)) k_reproj(Workspa
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (PREC) {
-            // K runs over the re part only; each step loads P_re and P_im fragments
-            // once and forms out_re = a_re P_re - a_im P_im, out_im = a_re P_im + a_im P_re
-            constexpr int KUNR = NTP > 128 ? 1 : 2;      // register budget of the widest subsets
-            constexpr int QW = CTW / 2 > 0 ? CTW / 2 : 1;
-#pragma unroll KUNR
-            for (int k0 = 0; k0 < NTEP; k0 += 32) {
-                const int kq = k0 + 8 * g;
-                u32x4 brh[QW], brl[QW], bih[QW], bil[QW];
-#pragma unroll
-                for (int q = 0; q < QW; ++q) {
-                    const int nq = wave * QW + q;
-                    brh[q] = brl[q] = bih[q] = bil[q] = u32x4{0u, 0u, 0u, 0u};
-                    if (nq < C::NNT) {
-                        const uint16_t* src = planes + (long)(nq * 16 + col) * NTEP + kq;
-                        brh[q] = *reinterpret_cast<const u32x4*>(src);
-                        brl[q] = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
-                        bih[q] = *reinterpret_cast<const u32x4*>(src + 2 * NTP * NTEP);
-                        bil[q] = *reinterpret_cast<const u32x4*>(src + 3 * NTP * NTEP);
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < NRT; ++a) {
-                    const uint16_t* arow = Ah + (16 * a + col) * LDK + kq;
-                    const uint16_t* lrow = Al + (16 * a + col) * LDK + kq;
-                    const bf16x8 xrh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow));
-                    const bf16x8 xrl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow));
-                    const bf16x8 xih = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow + NTEP));
-                    const bf16x8 xil = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow + NTEP));
-#pragma unroll
-                    for (int q = 0; q < QW; ++q) {
-                        if (wave * QW + q < C::NNT) {
-                            const bf16x8 prh = __builtin_bit_cast(bf16x8, brh[q]), prl = __builtin_bit_cast(bf16x8, brl[q]);
-                            const bf16x8 pih = __builtin_bit_cast(bf16x8, bih[q]), pil = __builtin_bit_cast(bf16x8, bil[q]);
-                            u32x4 nh = bih[q], nl = bil[q];
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) { nh[e] ^= 0x80008000u; nl[e] ^= 0x80008000u; }
-                            const bf16x8 nih = __builtin_bit_cast(bf16x8, nh), nil = __builtin_bit_cast(bf16x8, nl);
-                            floatx4& ore = acc[a][2 * q];
-                            floatx4& oim = acc[a][2 * q + 1];
-                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, prh, ore, 0, 0, 0);
-                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, prl, ore, 0, 0, 0);
-                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrl, prh, ore, 0, 0, 0);
-                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, nih, ore, 0, 0, 0);
-                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, nil, ore, 0, 0, 0);
-                            ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xil, nih, ore, 0, 0, 0);
-                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, pih, oim, 0, 0, 0);
-                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrh, pil, oim, 0, 0, 0);
-                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xrl, pih, oim, 0, 0, 0);
-                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, prh, oim, 0, 0, 0);
-                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xih, prl, oim, 0, 0, 0);
-                            oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xil, prh, oim, 0, 0, 0);
-                        }
-                    }
-                }
-            }
-        } else {
-            const float* Br = ws.breal + (long)s * (2 * C::NTE) * (2 * NTP);
+        const float* Br = ws.breal + (long)s * (2 * C::NTE) * (2 * NTP);
 #pragma unroll 4
-            for (int k0 = 0; k0 < 2 * C::NTE; k0 += 4) {
-                const int kk = k0 + g;
-                const int acol = kk < C::NTE ? kk : IMO + kk - C::NTE;
-                float av[NRT];
+        for (int k0 = 0; k0 < 2 * C::NTE; k0 += 4) {
+            const int kk = k0 + g;
+            const int acol = kk < C::NTE ? kk : IMO + kk - C::NTE;
+            float av[NRT];
 #pragma unroll
-                for (int a = 0; a < NRT; ++a) av[a] = A[(16 * a + col) * LDA + acol];
-                const float* brow = Br + (long)kk * (2 * NTP);
+            for (int a = 0; a < NRT; ++a) av[a] = A[(16 * a + col) * LDA + acol];
+            const float* brow = Br + (long)kk * (2 * NTP);
 #pragma unroll
-                for (int m = 0; m < CTW; ++m) {
-                    const int ct = wave * CTW + m;
-                    if (ct < C::CT) {
-                        const float b = brow[ct * 16 + col];
+            for (int m = 0; m < CTW; ++m) {
+                const int ct = wave * CTW + m;
+                if (ct < C::CT) {
+                    const float b = brow[ct * 16 + col];
 #pragma unroll
-                        for (int a = 0; a < NRT; ++a)
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], b, acc[a][m], 0, 0, 0);
-                    }
+                    for (int a = 0; a < NRT; ++a)
+                        acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], b, acc[a][m], 0, 0, 0);
                 }
             }
         }
