@@ -1562,7 +1562,6 @@ static hipError_t small_stage(const Workspace& ws, int stage, double rho, int ia
     switch (ws.ntp) {
         case 32: small_dispatch<32>(ws, stage, rho, iarg, st); break;
         case 64: small_dispatch<64>(ws, stage, rho, iarg, st); break;
-        case 96: small_dispatch<96>(ws, stage, rho, iarg, st); break;
         case 128: small_dispatch<128>(ws, stage, rho, iarg, st); break;
         case 160: small_dispatch<160>(ws, stage, rho, iarg, st); break;
         case 208: small_dispatch<208>(ws, stage, rho, iarg, st); break;
@@ -1587,8 +1586,14 @@ hipError_t launch_assemble(const Workspace& ws, int keep_r, hipStream_t st) {
 
 static int max_nt(const Workspace& ws) { return ws.ntp; }
 
+// The tridiagonal solver and its vector stage hold B padded to 16 columns per
+// wave and address every per-subset slot with that size: up to 128 frames the
+// class must be one of those sizes.
+static bool tri_sized(int ntp) { return ntp > 128 || ntp == 32 || ntp == 64 || ntp == 128; }
+
 hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
     (void)max_nt;
+    if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
     // Up to 128 frames: the tridiagonal solver (method 0), with the
     // register-resident Jacobi for the subsets it flags, or the Jacobi for all
     // (method 1). Beyond 128: the LDS / global Jacobi.
@@ -1620,6 +1625,7 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
 // Eigenvectors after the weights are known (tridiagonal solver, up to 128
 // frames); the Jacobi paths produced theirs already.
 hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStream_t st) {
+    if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
     if (method != 0 || ws.ntp > 128) return hipSuccess;
     if (ws.ntp <= 32) hipLaunchKernelGGL((k_heev_tri_vecs<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, all);
     else if (ws.ntp <= 64) hipLaunchKernelGGL((k_heev_tri_vecs<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, all);

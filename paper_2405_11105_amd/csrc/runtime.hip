@@ -19,7 +19,10 @@ using namespace lcf;
 
 namespace {
 
-const int NTP_CLASSES[] = {32, 64, 96, 128, 160, 208};
+// Padded frame classes. Up to 128 frames they are exactly the sizes of the
+// tridiagonal EVD's 2-, 4- and 8-wave shapes (16 columns per wave), which hold
+// B at that size and address it with it, so there is no class between 64 and 128.
+const int NTP_CLASSES[] = {32, 64, 128, 160, 208};
 constexpr int NT_MAX = 208;
 
 int ntp_class(int nt) {

@@ -127,6 +127,18 @@ def test_ragged_nt100_small_grid(lcf, ctx):
     _check_end_to_end(lcf, ctx, iq, mask, 3, 2, thr, 1e-5, 0.1, "ragged nt=100")
 
 
+@pytest.mark.parametrize("nt", [80, 150])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ragged_frame_counts_80_150(lcf, ctx, nt, prec):
+    # 80 frames fall in the 128 class with 48 padding frames, 150 in the 160
+    # class; both are ragged in the pixels as well
+    spec = synth.PacketSpec(90, 70, nt, 50.0, 0.4, ((25, 3, 0.3), (60, 4, 0.7)), seed=500 + nt)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
+    _check_end_to_end(lcf, ctx, iq, mask, 3, 2, thr, tol, 0.1, f"nt={nt} prec={prec}", precision=prec)
+
+
 def test_all_ones_weights_return_input(lcf, ctx):
     _say("[all-ones identity]")
     iq, _ = synth.make_packet(synth.spec_small(1))
