@@ -139,6 +139,26 @@ def test_ragged_frame_counts_80_150(lcf, ctx, nt, prec):
     _check_end_to_end(lcf, ctx, iq, mask, 3, 2, thr, tol, 0.1, f"nt={nt} prec={prec}", precision=prec)
 
 
+@pytest.mark.parametrize("nt", [4, 208])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_frame_count_limits(lcf, ctx, nt, prec):
+    # the shortest packet the library accepts (28 padding frames in the 32 class,
+    # tissue rank capped by nt) and the longest (the 208 class exactly filled)
+    spec = synth.PacketSpec(48, 40, nt, 50.0, 0.4, ((20, 3, 0.5),), seed=900 + nt)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
+    _check_end_to_end(lcf, ctx, iq, mask, 2, 2, thr, tol, 0.1, f"nt={nt} prec={prec}", precision=prec)
+
+
+def test_empty_batch_rejected(lcf, ctx):
+    _say("[empty batch]")
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE)
+    with pytest.raises(lcf.LcfError) as ei:
+        ctx.filter_batch([], [], thr)
+    assert ei.value.status == 1     # LCF_ERR_INVALID_ARG
+
+
 def test_all_ones_weights_return_input(lcf, ctx):
     _say("[all-ones identity]")
     iq, _ = synth.make_packet(synth.spec_small(1))
