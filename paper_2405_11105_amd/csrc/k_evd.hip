@@ -1565,7 +1565,6 @@ static hipError_t small_stage(const Workspace& ws, int stage, double rho, int ia
         case 128: small_dispatch<128>(ws, stage, rho, iarg, st); break;
         case 160: small_dispatch<160>(ws, stage, rho, iarg, st); break;
         case 208: small_dispatch<208>(ws, stage, rho, iarg, st); break;
-        case 256: small_dispatch<256>(ws, stage, rho, iarg, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1584,15 +1583,12 @@ hipError_t launch_assemble(const Workspace& ws, int keep_r, hipStream_t st) {
     return small_stage(ws, 1, 0.0, keep_r ? 1 : 0, st);
 }
 
-static int max_nt(const Workspace& ws) { return ws.ntp; }
-
 // The tridiagonal solver and its vector stage hold B padded to 16 columns per
 // wave and address every per-subset slot with that size: up to 128 frames the
 // class must be one of those sizes.
 static bool tri_sized(int ntp) { return ntp > 128 || ntp == 32 || ntp == 64 || ntp == 128; }
 
 hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
-    (void)max_nt;
     if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
     // Up to 128 frames: the tridiagonal solver (method 0), with the
     // register-resident Jacobi for the subsets it flags, or the Jacobi for all
