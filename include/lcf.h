@@ -13,7 +13,7 @@
  *   R_d    = C_w^H C_w                                              (Eqs 1, 12)
  *   R_d    = V Lambda V^H, eigenvalues descending                   (Eq. 2)
  *   w_i    eigencomponent weights: hard cut (Eq. 4), curvature rule (Eq. 6),
- *          sigmoid (Eq. 9), caller-given, or a learned MLP
+ *          median rule (Eq. 7), sigmoid (Eq. 9), caller-given, or a learned MLP
  *   Chat_d = C_w V diag(w) V^H                                      (Eqs 4, 5)
  *   PD_d   = sum_t |Chat_d|^2                                       (text after Eq. 5)
  *   PD     = sum_d alpha_d PD_d, alpha_d = 1 / mean flow power      (Eq. 13)
@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LCF_ABI_VERSION 1
+#define LCF_ABI_VERSION 2
 
 typedef enum {
     LCF_OK = 0,
@@ -68,7 +68,8 @@ typedef enum {
     LCF_CUT_FIXED_K = 0,  /* k = k_fixed (Eq. 4)                                     */
     LCF_CUT_KNEE = 1,     /* k = argmax curvature of the log-eigenvalue curve (Eq. 6) */
     LCF_CUT_EXPLICIT = 2, /* caller's weights explicit_w[d][i]                       */
-    LCF_CUT_MLP = 3       /* weights from the context's MLP (needs Nt = 128)          */
+    LCF_CUT_MLP = 3,      /* weights from the context's MLP (needs Nt = 128)          */
+    LCF_CUT_MEDIAN = 4    /* k = #{i : lambda_i > beta_median * lambda_median} (Eq. 7) */
 } lcf_cut;
 
 typedef enum {
@@ -104,6 +105,9 @@ typedef struct {
     double deflate_rho;      /* tissue-deflation threshold (relative eigenvalue); 1e-5
                                 typical; 0 disables the deflation (precision drops)     */
     const float* explicit_w; /* EXPLICIT: device float [nsubsets][nt], else NULL          */
+    double beta_median;      /* MEDIAN: Eq. 7 scaling factor beta (> 0, finite); the median
+                                of an even number of eigenvalues is the mean of the two
+                                middle ones, and lambda_i equal to the threshold is kept */
 } lcf_threshold;
 
 /* Optional per-subset diagnostics (device pointers, each may be NULL).
@@ -111,7 +115,7 @@ typedef struct {
 typedef struct {
     double* eigvals;   /* [nd][nt]  eigenvalues of R_d, descending                        */
     float* weights;    /* [nd][nt]  eigencomponent weights w_i                           */
-    int32_t* k;        /* [nd]      cut index (FIXED_K/KNEE), -1 otherwise                */
+    int32_t* k;        /* [nd]      cut index (FIXED_K/KNEE/MEDIAN), -1 otherwise         */
     int32_t* sweeps;   /* [nd]      Jacobi sweeps used                                    */
     int32_t* flags;    /* [nd]      LCF_FLAG_* bits                                       */
     double* alpha;     /* [nd]      Eq. 13 subset weight                                  */

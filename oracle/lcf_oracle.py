@@ -9,7 +9,7 @@ order:
 2. Gaussian windows, C_w = W C                          -- Eq. 11
 3. Covariance R = C_w^H C_w                             -- Eqs 1 and 12
 4. EVD R = V Lambda V^H, eigenvalues descending         -- Eq. 2
-5. Eigencomponent weights (hard / curvature / sigmoid)  -- Eqs 4, 6, 9
+5. Eigencomponent weights (hard / curvature / median / sigmoid)  -- Eqs 4, 6, 7, 9
 6. Projection C_hat = C_w V diag(w) V^H                 -- Eqs 4 and 5
 7. Power Doppler PD_d = sum_t |C_hat|^2                 -- text after Eq. 5
 8. Recombination PD = sum_d alpha_d PD_d, alpha_d = 1/(mean flow power)  -- Eq. 13
@@ -22,8 +22,9 @@ Nt frames, so alpha_d = Npix*Nt / sum_i w_i^2 lambda_i; window centres sit at
 zero outside a +-trunc_sigmas*sigma box; the curvature rule takes numpy-style
 differences (central inside, one-sided at the ends), searches
 n in [2, floor(knee_max_frac*Nt)] and keeps the smallest index on ties; k is
-the number of rejected leading components; the combined filtered IQ is
-sum_d C_hat_d / sum_d w_d.
+the number of rejected leading components; the median rule takes the mean of
+the two middle eigenvalues when Nt is even and rejects only eigenvalues strictly
+above its threshold; the combined filtered IQ is sum_d C_hat_d / sum_d w_d.
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ from typing import Optional
 
 import numpy as np
 
-CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP = 0, 1, 2, 3
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN = 0, 1, 2, 3, 4
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 
@@ -50,6 +51,7 @@ class Threshold:
     beta_knee: float = 1.0
     knee_max_frac: float = 0.5
     beta_sigmoid: float = 2.0
+    beta_median: float = 1.43                   # Eq. 7 scaling factor (Fig. 2a's example)
     explicit_w: Optional[np.ndarray] = None     # [nd][nt]
     mlp: Optional[object] = None                # callable(lam) -> weights, for CUT_MLP
 
@@ -161,6 +163,18 @@ def knee_k(curv: np.ndarray, nt: int, max_frac: float) -> int:
     return int(np.argmax(seg)) + 2
 
 
+def median_k(lam: np.ndarray, beta: float) -> int:
+    """Method 3 (Eq. 7): threshold T = beta * lambda_median; the components whose
+    eigenvalue exceeds T are tissue, so k = #{i : lambda_i > T}. The median of an
+    even number of eigenvalues is the mean of the two middle ones."""
+    s = np.sort(np.asarray(lam, dtype=np.float64))[::-1]
+    n = s.shape[0]
+    h = n // 2
+    med = s[h] if n % 2 == 1 else 0.5 * (s[h - 1] + s[h])
+    t = beta * med
+    return int(np.count_nonzero(s > t))
+
+
 def sigmoid_weights(nt: int, k: int, beta: float) -> np.ndarray:
     """Soft weights of Eq. 9: w_i = 1 / (1 + exp(-beta (i - k))), i = 1..Nt."""
     i = np.arange(1, nt + 1, dtype=np.float64)
@@ -170,7 +184,8 @@ def sigmoid_weights(nt: int, k: int, beta: float) -> np.ndarray:
 def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
     """Eigencomponent weights of one subset.
 
-    FIXED_K / KNEE choose k (Eq. 4 hard cut, Eq. 6 curvature); the shape is a
+    FIXED_K / KNEE / MEDIAN choose k (Eq. 4 hard cut, Eq. 6 curvature, Eq. 7
+    median); the shape is a
     hard 0/1 cut (Eq. 4) or the sigmoid of Eq. 9 centred on k. EXPLICIT takes
     the caller's weights; MLP calls ``thr.mlp(lam)``. Returns (w, k, curv, flags)."""
     nt = lam.shape[0]
@@ -185,6 +200,8 @@ def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
     elif thr.cut == CUT_KNEE:
         curv, flags = knee_curvature(lam, thr.beta_knee)
         k = 0 if flags else knee_k(curv, nt, thr.knee_max_frac)
+    elif thr.cut == CUT_MEDIAN:
+        k = median_k(lam, thr.beta_median)
     else:
         raise ValueError("unknown cut")
     if thr.shape == SHAPE_HARD:

@@ -1,4 +1,4 @@
-// Eigencomponent weights (Eqs 4, 6, 9), the projector P = V diag(w) V^H, and
+// Eigencomponent weights (Eqs 4, 6, 7, 9), the projector P = V diag(w) V^H, and
 // the output-centric reprojection + power Doppler + recombination (Eqs 4, 5, 13).
 #include "lcf_internal.h"
 #include "lcf_kernels.h"
@@ -27,8 +27,20 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     double* wts = ws.wts + (long)s * ntp;
     if (lane == 0) { sh_k = -1; sh_flag = 0; }
     __syncthreads();
-    if (rp.cut == 0 || rp.cut == 1) {
+    if (rp.cut == 0 || rp.cut == 1 || rp.cut == 4) {
         int k = rp.k_fixed;
+        if (rp.cut == 4) {
+            // Eq. 7: threshold beta times the median eigenvalue (lam is sorted
+            // descending; an even count takes the mean of the two middle values);
+            // k counts the eigenvalues strictly above it
+            const int h = nt >> 1;
+            const double med = (nt & 1) ? lam[h] : 0.5 * (lam[h - 1] + lam[h]);
+            const double tval = rp.beta_median * med;
+            int cnt = 0;
+            for (int i = lane; i < nt; i += 64) cnt += lam[i] > tval ? 1 : 0;
+            for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+            k = cnt;
+        }
         if (rp.cut == 1) {
             const double l1 = lam[0];
             bool bad = !(l1 > 0.0);
@@ -86,7 +98,7 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     for (int i = lane; i < nt; i += 64) e += wts[i] * wts[i] * lam[i];
     e = wave_sum(e);
     if (lane == 0) {
-        ws.kcut[s] = (rp.cut <= 1) ? sh_k : -1;
+        ws.kcut[s] = (rp.cut <= 1 || rp.cut == 4) ? sh_k : -1;
         ws.alpha[s] = rp.pd_mode == 1 ? 1.0 : (e > 0.0 ? sd.npix_nt / e : 0.0);
         if (sh_flag) atomicOr(&ws.flags[s], sh_flag);
     }

@@ -61,7 +61,17 @@ def run_gpu(lcf, ctx, iq_np, gy, gx, thr, **kw):
 def oracle_thr(lcf_thr, nd=None, explicit=None):
     return O.Threshold(cut=lcf_thr.cut, shape=lcf_thr.shape, pd_mode=lcf_thr.pd_mode, k_fixed=lcf_thr.k_fixed,
                        beta_knee=lcf_thr.beta_knee, knee_max_frac=lcf_thr.knee_max_frac,
-                       beta_sigmoid=lcf_thr.beta_sigmoid, explicit_w=explicit)
+                       beta_sigmoid=lcf_thr.beta_sigmoid, beta_median=lcf_thr.beta_median, explicit_w=explicit)
+
+
+def median_tie(lam, beta, k1, k2):
+    """True when every eigenvalue between the two cuts lies within the eigenvalue
+    parity tolerance of the median rule's threshold (Eq. 7) on ``lam``."""
+    s = np.sort(np.asarray(lam, dtype=np.float64))[::-1]
+    n, h = s.shape[0], s.shape[0] // 2
+    t = beta * (s[h] if n % 2 else 0.5 * (s[h - 1] + s[h]))
+    lo, hi = min(k1, k2), max(k1, k2)
+    return all(abs(s[i] - t) <= 1e-5 * t + 1e-7 * s[0] for i in range(lo, hi))
 
 
 def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, precision=0):
@@ -75,12 +85,14 @@ def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, pre
         lam_g = d["eigvals"][s]
         lam_o = res["lam"][s]
         assert np.allclose(lam_g, lam_o, rtol=1e-5, atol=1e-7 * lam_o[0]), (s, np.max(np.abs(lam_g - lam_o) / lam_o[0]))
-        if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE):
+        if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE, lcf.CUT_MEDIAN):
             w_rule, k_rule, curv, _ = O.rule_weights(lam_g, oracle_thr(thr))
             assert d["k"][s] == k_rule, (s, d["k"][s], k_rule)
             assert np.allclose(d["weights"][s], w_rule, atol=1e-6)
             if k_rule != res["k"][s]:
-                assert knee_tie(res["curv"][s], k_rule, res["k"][s]), ("non-tie k flip", s, k_rule, res["k"][s])
+                tie = (median_tie(lam_o, thr.beta_median, k_rule, res["k"][s]) if thr.cut == lcf.CUT_MEDIAN
+                       else knee_tie(res["curv"][s], k_rule, res["k"][s]))
+                assert tie, ("non-tie k flip", s, k_rule, res["k"][s])
                 forced = True
     if forced:
         ew = d["weights"].astype(np.float64)

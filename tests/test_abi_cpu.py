@@ -43,6 +43,15 @@ def test_validate_geometry_and_threshold(lcf):
     assert lcf.validate(ok, lcf.Threshold(pd_mode=3)) == 1
     assert lcf.validate(ok, lcf.Threshold(deflate_rho=-1.0)) == 1
     assert lcf.validate(ok, thr, precision=7) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=1.43)) == 0
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=0.0)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=float("inf"))) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_MEDIAN, shape=lcf.SHAPE_SIGMOID, beta_sigmoid=0.0)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=5)) == 1
+
+
+def test_abi_version_matches_binding(lcf):
+    assert lcf.load().lcf_abi_version() == lcf.ABI_VERSION
 
 
 def test_python_package_has_no_compute_fallback():

@@ -159,6 +159,27 @@ def test_empty_batch_rejected(lcf, ctx):
     assert ei.value.status == 1     # LCF_ERR_INVALID_ARG
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_clinical_median_rule(lcf, ctx, prec):
+    # method 3 (Eq. 7) at the clinical shape. beta = 30 puts the cut at the
+    # tissue / blood transition of these packets (k = 3 to 7; the curvature rule
+    # gives 5 to 19). The 1.43 of the paper's Fig. 2a, fitted to its own data,
+    # cuts 35 to 52 components deep here, leaving only noise-floor components
+    # whose small norm is not what the FP32 bound on the filtered IQ is for.
+    iq, mask = synth.make_packet(synth.spec_clinical(1))
+    thr = lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=30.0)
+    tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
+    _check_end_to_end(lcf, ctx, iq, mask, 8, 8, thr, tol, 0.1, f"clinical median prec={prec}", precision=prec)
+
+
+def test_median_rule_odd_frame_count_sigmoid(lcf, ctx):
+    # an odd count takes the middle eigenvalue itself; soft weights centred on k
+    spec = synth.PacketSpec(80, 64, 45, 50.0, 0.5, ((30, 3, 0.6),), seed=45)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=30.0, shape=lcf.SHAPE_SIGMOID)
+    _check_end_to_end(lcf, ctx, iq, mask, 3, 3, thr, 1e-5, 0.1, "median odd nt=45 sigmoid")
+
+
 def test_all_ones_weights_return_input(lcf, ctx):
     _say("[all-ones identity]")
     iq, _ = synth.make_packet(synth.spec_small(1))
@@ -286,6 +307,29 @@ def test_graph_replay_matches_eager(lcf, ctx):
                 _ = (iqs[0].abs() ** 2).sum().item()
                 ctx.filter(iqs[1], 2, 2, thr)
                 st.synchronize()
+            assert gctx.sync() == 0
+        finally:
+            gctx.close()
+
+
+def test_graph_cache_keys_on_median_beta(lcf, ctx):
+    # the rule parameters are baked into a captured graph: a call that changes
+    # only beta of Eq. 7 must not replay the graph of another beta
+    _say("[hipGraph median beta]")
+    iq = torch.from_numpy(synth.make_packet(synth.spec_small(9))[0]).cuda()
+    thrs = [lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=b) for b in (1.43, 20.0)]
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ref = [ctx.filter(iq, 3, 3, t, diag=True) for t in thrs]
+        st.synchronize()
+        assert not np.array_equal(ref[0][2]["k"].cpu().numpy(), ref[1][2]["k"].cpu().numpy())
+        gctx = lcf.Context(0, use_graph=1)
+        try:
+            for rep in range(3):
+                for i, t in enumerate(thrs):
+                    io, pd, _ = gctx.filter(iq, 3, 3, t)
+                    st.synchronize()
+                    assert torch.equal(pd, ref[i][1]), (rep, i)
             assert gctx.sync() == 0
         finally:
             gctx.close()

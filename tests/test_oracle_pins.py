@@ -208,6 +208,50 @@ def test_fixed_k_hard_and_soft():
     assert abs(w[2] - 0.5) < 1e-15
 
 
+def test_median_rule_geometric_odd_count():
+    # Eq. 7 worked by hand: lambda_i = 2^-i, i = 0..8; the median is 2^-4. With
+    # beta = 4 the threshold 1/4 equals lambda_2, which is kept (only eigenvalues
+    # above it are tissue): k = 2. With beta = 3 the threshold 3/16 lies below
+    # lambda_2: k = 3. A threshold divided by beta would give k = 9 and 6.
+    lam = 2.0 ** -np.arange(9, dtype=np.float64)
+    assert O.median_k(lam, 4.0) == 2
+    assert O.median_k(lam, 3.0) == 3
+    w, k, _, _ = O.rule_weights(lam, O.Threshold(cut=O.CUT_MEDIAN, beta_median=4.0))
+    assert k == 2 and np.array_equal(w, [0, 0] + [1] * 7)
+
+
+def test_median_rule_even_count_takes_mean_of_middle_pair():
+    # lambda = 100, 10, 4, 2, 1, 0.5: the median of the even count is (4 + 2) / 2 = 3.
+    # beta = 1: threshold 3, so 100, 10, 4 are tissue (k = 3); the lower middle
+    # value as median would give threshold 4 and k = 2.
+    # beta = 0.9: threshold 2.7, k = 3; the upper middle value would give 1.8 and k = 4.
+    lam = np.array([100.0, 10.0, 4.0, 2.0, 1.0, 0.5])
+    assert O.median_k(lam, 1.0) == 3
+    assert O.median_k(lam, 0.9) == 3
+    # the order of the input does not matter
+    assert O.median_k(lam[::-1].copy(), 1.0) == 3
+
+
+def test_median_rule_flat_spectrum_and_sigmoid():
+    lam = np.full(7, 2.5)
+    assert O.median_k(lam, 1.0) == 0          # nothing lies above its own median
+    assert O.median_k(lam, 0.5) == 7
+    w, k, _, _ = O.rule_weights(2.0 ** -np.arange(9, dtype=np.float64),
+                                O.Threshold(cut=O.CUT_MEDIAN, beta_median=3.0, shape=O.SHAPE_SIGMOID,
+                                            beta_sigmoid=2.0))
+    assert k == 3 and abs(w[2] - 0.5) < 1e-15
+
+
+def test_median_rule_above_spread_returns_input():
+    # beta larger than lambda_1 / lambda_median rejects nothing: all-ones weights,
+    # so the filter returns its input (Eqs 4, 11, 13)
+    iq = synth.make_packet(synth.PacketSpec(24, 20, 12, 40.0, 0.3, ((10, 2, 0.4),), seed=9))[0]
+    res = O.filter_packet(iq, 2, 2, O.Threshold(cut=O.CUT_MEDIAN, beta_median=1e12))
+    assert all(k == 0 for k in res["k"])
+    ref = iq.astype(np.complex128)
+    assert np.linalg.norm(res["iq_out"] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
 def test_knee_degenerate_spectrum_flagged():
     w, k, _, flags = O.rule_weights(np.zeros(8), O.Threshold(cut=O.CUT_KNEE))
     assert flags == 1 and k == 0 and np.all(w == 1)
