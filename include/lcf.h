@@ -13,7 +13,8 @@
  *   R_d    = C_w^H C_w                                              (Eqs 1, 12)
  *   R_d    = V Lambda V^H, eigenvalues descending                   (Eq. 2)
  *   w_i    eigencomponent weights: hard cut (Eq. 4), curvature rule (Eq. 6),
- *          median rule (Eq. 7), sigmoid (Eq. 9), caller-given, or a learned MLP
+ *          median rule (Eq. 7), slope rule, sigmoid (Eq. 9), caller-given, or a
+ *          learned MLP
  *   Chat_d = C_w V diag(w) V^H                                      (Eqs 4, 5)
  *   PD_d   = sum_t |Chat_d|^2                                       (text after Eq. 5)
  *   PD     = sum_d alpha_d PD_d, alpha_d = 1 / mean flow power      (Eq. 13)
@@ -44,7 +45,7 @@
 extern "C" {
 #endif
 
-#define LCF_ABI_VERSION 2
+#define LCF_ABI_VERSION 3
 
 typedef enum {
     LCF_OK = 0,
@@ -69,7 +70,8 @@ typedef enum {
     LCF_CUT_KNEE = 1,     /* k = argmax curvature of the log-eigenvalue curve (Eq. 6) */
     LCF_CUT_EXPLICIT = 2, /* caller's weights explicit_w[d][i]                       */
     LCF_CUT_MLP = 3,      /* weights from the context's MLP (needs Nt = 128)          */
-    LCF_CUT_MEDIAN = 4    /* k = #{i : lambda_i > beta_median * lambda_median} (Eq. 7) */
+    LCF_CUT_MEDIAN = 4,   /* k = #{i : lambda_i > beta_median * lambda_median} (Eq. 7) */
+    LCF_CUT_SLOPE = 5     /* k = first n with |slope| <= slope_thr (method 2, Fig. 2c) */
 } lcf_cut;
 
 typedef enum {
@@ -108,6 +110,10 @@ typedef struct {
     double beta_median;      /* MEDIAN: Eq. 7 scaling factor beta (> 0, finite); the median
                                 of an even number of eigenvalues is the mean of the two
                                 middle ones, and lambda_i equal to the threshold is kept */
+    double slope_thr;        /* SLOPE: threshold (> 0, finite) on |y'(n)| of the curve
+                                y(n) = Nt lambda_n / lambda_1, differences as for Eq. 6;
+                                k = 0-based index of the first n with |y'(n)| <= slope_thr
+                                (Nt if none); lambda_1 <= 0 sets NONPOSITIVE and k = 0 */
 } lcf_threshold;
 
 /* Optional per-subset diagnostics (device pointers, each may be NULL).
@@ -115,7 +121,7 @@ typedef struct {
 typedef struct {
     double* eigvals;   /* [nd][nt]  eigenvalues of R_d, descending                        */
     float* weights;    /* [nd][nt]  eigencomponent weights w_i                           */
-    int32_t* k;        /* [nd]      cut index (FIXED_K/KNEE/MEDIAN), -1 otherwise         */
+    int32_t* k;        /* [nd]      cut index (FIXED_K/KNEE/MEDIAN/SLOPE), -1 otherwise   */
     int32_t* sweeps;   /* [nd]      Jacobi sweeps used                                    */
     int32_t* flags;    /* [nd]      LCF_FLAG_* bits                                       */
     double* alpha;     /* [nd]      Eq. 13 subset weight                                  */

@@ -9,7 +9,8 @@ order:
 2. Gaussian windows, C_w = W C                          -- Eq. 11
 3. Covariance R = C_w^H C_w                             -- Eqs 1 and 12
 4. EVD R = V Lambda V^H, eigenvalues descending         -- Eq. 2
-5. Eigencomponent weights (hard / curvature / median / sigmoid)  -- Eqs 4, 6, 7, 9
+5. Eigencomponent weights (hard / curvature / slope / median / sigmoid)
+                                                        -- Eqs 4, 6, 7, 9, Fig. 2c
 6. Projection C_hat = C_w V diag(w) V^H                 -- Eqs 4 and 5
 7. Power Doppler PD_d = sum_t |C_hat|^2                 -- text after Eq. 5
 8. Recombination PD = sum_d alpha_d PD_d, alpha_d = 1/(mean flow power)  -- Eq. 13
@@ -24,7 +25,10 @@ differences (central inside, one-sided at the ends), searches
 n in [2, floor(knee_max_frac*Nt)] and keeps the smallest index on ties; k is
 the number of rejected leading components; the median rule takes the mean of
 the two middle eigenvalues when Nt is even and rejects only eigenvalues strictly
-above its threshold; the combined filtered IQ is sum_d C_hat_d / sum_d w_d.
+above its threshold; the slope rule differentiates y(n) = lambda_n scaled as the
+curvature rule scales its curve (Nt y(n) / y(1)) and cuts before the first n
+whose slope magnitude is at most its threshold; the combined filtered IQ is
+sum_d C_hat_d / sum_d w_d.
 """
 from __future__ import annotations
 
@@ -34,7 +38,7 @@ from typing import Optional
 
 import numpy as np
 
-CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN = 0, 1, 2, 3, 4
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE = 0, 1, 2, 3, 4, 5
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 
@@ -52,6 +56,7 @@ class Threshold:
     knee_max_frac: float = 0.5
     beta_sigmoid: float = 2.0
     beta_median: float = 1.43                   # Eq. 7 scaling factor (Fig. 2a's example)
+    slope_thr: float = 1.1                      # slope rule threshold (Fig. 2c's example)
     explicit_w: Optional[np.ndarray] = None     # [nd][nt]
     mlp: Optional[object] = None                # callable(lam) -> weights, for CUT_MLP
 
@@ -163,6 +168,30 @@ def knee_k(curv: np.ndarray, nt: int, max_frac: float) -> int:
     return int(np.argmax(seg)) + 2
 
 
+def slope_k(lam: np.ndarray, thr: float):
+    """Method 2 (the slope rule, Fig. 2c): the eigenvalue curve y(n) = lambda_n,
+    scaled as the curvature rule scales its curve, y(n) Nt / y(1); its first
+    derivative by central differences inside and one-sided ones at the ends; the
+    leading components are tissue up to the turning point, the first n whose
+    slope magnitude is at most ``thr``. Returns (k, flags): k = that 0-based n
+    (Nt when every slope is steeper); lambda_1 <= 0 gives k = 0 and NONPOSITIVE."""
+    lam = np.asarray(lam, dtype=np.float64)
+    nt = lam.shape[0]
+    if not lam[0] > 0.0:
+        return 0, FLAG_NONPOSITIVE
+    y = nt * lam / lam[0]
+    for n in range(nt):
+        if n == 0:
+            d = y[1] - y[0]
+        elif n == nt - 1:
+            d = y[nt - 1] - y[nt - 2]
+        else:
+            d = 0.5 * (y[n + 1] - y[n - 1])
+        if abs(d) <= thr:
+            return n, 0
+    return nt, 0
+
+
 def median_k(lam: np.ndarray, beta: float) -> int:
     """Method 3 (Eq. 7): threshold T = beta * lambda_median; the components whose
     eigenvalue exceeds T are tissue, so k = #{i : lambda_i > T}. The median of an
@@ -184,8 +213,8 @@ def sigmoid_weights(nt: int, k: int, beta: float) -> np.ndarray:
 def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
     """Eigencomponent weights of one subset.
 
-    FIXED_K / KNEE / MEDIAN choose k (Eq. 4 hard cut, Eq. 6 curvature, Eq. 7
-    median); the shape is a
+    FIXED_K / KNEE / MEDIAN / SLOPE choose k (Eq. 4 hard cut, Eq. 6 curvature,
+    Eq. 7 median, the slope rule of Fig. 2c); the shape is a
     hard 0/1 cut (Eq. 4) or the sigmoid of Eq. 9 centred on k. EXPLICIT takes
     the caller's weights; MLP calls ``thr.mlp(lam)``. Returns (w, k, curv, flags)."""
     nt = lam.shape[0]
@@ -202,6 +231,8 @@ def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
         k = 0 if flags else knee_k(curv, nt, thr.knee_max_frac)
     elif thr.cut == CUT_MEDIAN:
         k = median_k(lam, thr.beta_median)
+    elif thr.cut == CUT_SLOPE:
+        k, flags = slope_k(lam, thr.slope_thr)
     else:
         raise ValueError("unknown cut")
     if thr.shape == SHAPE_HARD:

@@ -1,4 +1,4 @@
-// Eigencomponent weights (Eqs 4, 6, 7, 9), the projector P = V diag(w) V^H, and
+// Eigencomponent weights (Eqs 4, 6, 7, 9, slope rule), the projector P = V diag(w) V^H, and
 // the output-centric reprojection + power Doppler + recombination (Eqs 4, 5, 13).
 #include "lcf_internal.h"
 #include "lcf_kernels.h"
@@ -27,8 +27,28 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     double* wts = ws.wts + (long)s * ntp;
     if (lane == 0) { sh_k = -1; sh_flag = 0; }
     __syncthreads();
-    if (rp.cut == 0 || rp.cut == 1 || rp.cut == 4) {
+    if (rp.cut == 0 || rp.cut == 1 || rp.cut == 4 || rp.cut == 5) {
         int k = rp.k_fixed;
+        if (rp.cut == 5) {
+            // slope rule: y(n) = Nt lambda_n / lambda_1, slopes by the differences
+            // of the curvature rule; k = first 0-based n with |y'(n)| <= threshold
+            const double l1 = lam[0];
+            if (!(l1 > 0.0)) {
+                k = 0;
+                if (lane == 0) sh_flag = 1;
+            } else {
+                for (int i = lane; i < nt; i += 64) yt[i] = (double)nt * lam[i] / l1;
+                __syncthreads();
+                int first = nt;
+                for (int i = lane; i < nt; i += 64) {
+                    const double d = i == 0 ? yt[1] - yt[0]
+                                            : (i == nt - 1 ? yt[nt - 1] - yt[nt - 2] : 0.5 * (yt[i + 1] - yt[i - 1]));
+                    if (fabs(d) <= rp.slope_thr && i < first) first = i;
+                }
+                for (int m = 32; m >= 1; m >>= 1) first = min(first, __shfl_xor(first, m, 64));
+                k = first;
+            }
+        }
         if (rp.cut == 4) {
             // Eq. 7: threshold beta times the median eigenvalue (lam is sorted
             // descending; an even count takes the mean of the two middle values);
@@ -98,7 +118,7 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     for (int i = lane; i < nt; i += 64) e += wts[i] * wts[i] * lam[i];
     e = wave_sum(e);
     if (lane == 0) {
-        ws.kcut[s] = (rp.cut <= 1 || rp.cut == 4) ? sh_k : -1;
+        ws.kcut[s] = (rp.cut <= 1 || rp.cut >= 4) ? sh_k : -1;
         ws.alpha[s] = rp.pd_mode == 1 ? 1.0 : (e > 0.0 ? sd.npix_nt / e : 0.0);
         if (sh_flag) atomicOr(&ws.flags[s], sh_flag);
     }

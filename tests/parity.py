@@ -61,7 +61,19 @@ def run_gpu(lcf, ctx, iq_np, gy, gx, thr, **kw):
 def oracle_thr(lcf_thr, nd=None, explicit=None):
     return O.Threshold(cut=lcf_thr.cut, shape=lcf_thr.shape, pd_mode=lcf_thr.pd_mode, k_fixed=lcf_thr.k_fixed,
                        beta_knee=lcf_thr.beta_knee, knee_max_frac=lcf_thr.knee_max_frac,
-                       beta_sigmoid=lcf_thr.beta_sigmoid, beta_median=lcf_thr.beta_median, explicit_w=explicit)
+                       beta_sigmoid=lcf_thr.beta_sigmoid, beta_median=lcf_thr.beta_median,
+                       slope_thr=lcf_thr.slope_thr, explicit_w=explicit)
+
+
+def slope_tie(lam, thr, k1, k2):
+    """True when the slope at the earlier of two turning points lies within the
+    eigenvalue parity tolerance of the slope rule's threshold on ``lam``."""
+    lam = np.asarray(lam, dtype=np.float64)
+    nt = lam.shape[0]
+    y = nt * lam / lam[0]
+    n = min(k1, k2)
+    d = y[1] - y[0] if n == 0 else (y[n] - y[n - 1] if n == nt - 1 else 0.5 * (y[n + 1] - y[n - 1]))
+    return abs(abs(d) - thr) <= 1e-4 * thr + 1e-6 * nt
 
 
 def median_tie(lam, beta, k1, k2):
@@ -85,13 +97,17 @@ def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, pre
         lam_g = d["eigvals"][s]
         lam_o = res["lam"][s]
         assert np.allclose(lam_g, lam_o, rtol=1e-5, atol=1e-7 * lam_o[0]), (s, np.max(np.abs(lam_g - lam_o) / lam_o[0]))
-        if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE, lcf.CUT_MEDIAN):
+        if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE, lcf.CUT_MEDIAN, lcf.CUT_SLOPE):
             w_rule, k_rule, curv, _ = O.rule_weights(lam_g, oracle_thr(thr))
             assert d["k"][s] == k_rule, (s, d["k"][s], k_rule)
             assert np.allclose(d["weights"][s], w_rule, atol=1e-6)
             if k_rule != res["k"][s]:
-                tie = (median_tie(lam_o, thr.beta_median, k_rule, res["k"][s]) if thr.cut == lcf.CUT_MEDIAN
-                       else knee_tie(res["curv"][s], k_rule, res["k"][s]))
+                if thr.cut == lcf.CUT_MEDIAN:
+                    tie = median_tie(lam_o, thr.beta_median, k_rule, res["k"][s])
+                elif thr.cut == lcf.CUT_SLOPE:
+                    tie = slope_tie(lam_o, thr.slope_thr, k_rule, res["k"][s])
+                else:
+                    tie = knee_tie(res["curv"][s], k_rule, res["k"][s])
                 assert tie, ("non-tie k flip", s, k_rule, res["k"][s])
                 forced = True
     if forced:

@@ -47,7 +47,10 @@ def test_validate_geometry_and_threshold(lcf):
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=0.0)) == 1
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=float("inf"))) == 1
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_MEDIAN, shape=lcf.SHAPE_SIGMOID, beta_sigmoid=0.0)) == 1
-    assert lcf.validate(ok, lcf.Threshold(cut=5)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=1.1)) == 0
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=-1.0)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=float("nan"))) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=6)) == 1
 
 
 def test_abi_version_matches_binding(lcf):

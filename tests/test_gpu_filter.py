@@ -180,6 +180,23 @@ def test_median_rule_odd_frame_count_sigmoid(lcf, ctx):
     _check_end_to_end(lcf, ctx, iq, mask, 3, 3, thr, 1e-5, 0.1, "median odd nt=45 sigmoid")
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_clinical_slope_rule(lcf, ctx, prec):
+    # the slope rule at the clinical shape with the threshold of the paper's
+    # Fig. 2c example (the turning point falls after the tissue components)
+    iq, mask = synth.make_packet(synth.spec_clinical(2))
+    thr = lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=1.1)
+    tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
+    _check_end_to_end(lcf, ctx, iq, mask, 8, 8, thr, tol, 0.1, f"clinical slope prec={prec}", precision=prec)
+
+
+def test_slope_rule_odd_frame_count_sigmoid(lcf, ctx):
+    spec = synth.PacketSpec(80, 64, 45, 50.0, 0.5, ((30, 3, 0.6),), seed=46)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=0.3, shape=lcf.SHAPE_SIGMOID)
+    _check_end_to_end(lcf, ctx, iq, mask, 3, 3, thr, 1e-5, 0.1, "slope nt=45 sigmoid")
+
+
 def test_all_ones_weights_return_input(lcf, ctx):
     _say("[all-ones identity]")
     iq, _ = synth.make_packet(synth.spec_small(1))

@@ -208,6 +208,32 @@ def test_fixed_k_hard_and_soft():
     assert abs(w[2] - 0.5) < 1e-15
 
 
+def test_slope_rule_hand_worked():
+    # lambda = 1, .5, .1, .09, .08, .07, .06, .05 (Nt = 8): y = 8 lambda / lambda_1 =
+    # 8, 4, .8, .72, .64, .56, .48, .4; slopes (central inside, one-sided at the
+    # ends) -4, -3.6, -1.64, -.08, -.08, -.08, -.08, -.08. Threshold 1.1: the first
+    # slope with magnitude <= 1.1 is at 0-based n = 3, so k = 3; threshold 2 gives
+    # k = 2 and threshold 5 gives k = 0. Forward differences would give k = 2 at
+    # 1.1, the unscaled curve k = 0.
+    lam = np.array([1.0, 0.5, 0.1, 0.09, 0.08, 0.07, 0.06, 0.05])
+    assert O.slope_k(lam, 1.1) == (3, 0)
+    assert O.slope_k(lam, 2.0) == (2, 0)
+    assert O.slope_k(lam, 5.0) == (0, 0)
+    w, k, _, _ = O.rule_weights(lam, O.Threshold(cut=O.CUT_SLOPE, slope_thr=1.1))
+    assert k == 3 and np.array_equal(w, [0, 0, 0, 1, 1, 1, 1, 1])
+
+
+def test_slope_rule_linear_spectrum_and_degenerate():
+    # lambda_i = Nt - i scales to y = Nt - i exactly: every slope is -1, so a
+    # threshold of 1 cuts nothing (|y'| <= 1 already at n = 0) and 0.5 cuts all
+    nt = 16
+    lam = np.arange(nt, 0, -1, dtype=np.float64)
+    assert O.slope_k(lam, 1.0) == (0, 0)
+    assert O.slope_k(lam, 0.5) == (nt, 0)
+    w, k, _, flags = O.rule_weights(np.zeros(8), O.Threshold(cut=O.CUT_SLOPE))
+    assert flags == 1 and k == 0 and np.all(w == 1)
+
+
 def test_median_rule_geometric_odd_count():
     # Eq. 7 worked by hand: lambda_i = 2^-i, i = 0..8; the median is 2^-4. With
     # beta = 4 the threshold 1/4 equals lambda_2, which is kept (only eigenvalues
