@@ -13,8 +13,8 @@
  *   R_d    = C_w^H C_w                                              (Eqs 1, 12)
  *   R_d    = V Lambda V^H, eigenvalues descending                   (Eq. 2)
  *   w_i    eigencomponent weights: hard cut (Eq. 4), curvature rule (Eq. 6),
- *          median rule (Eq. 7), slope rule, sigmoid (Eq. 9), caller-given, or a
- *          learned MLP
+ *          median rule (Eq. 7), slope rule, sigmoid (Eq. 9), eigenvalue power
+ *          weighting (Eq. 10), caller-given, or a learned MLP
  *   Chat_d = C_w V diag(w) V^H                                      (Eqs 4, 5)
  *   PD_d   = sum_t |Chat_d|^2                                       (text after Eq. 5)
  *   PD     = sum_d alpha_d PD_d, alpha_d = 1 / mean flow power      (Eq. 13)
@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define LCF_ABI_VERSION 3
+#define LCF_ABI_VERSION 4
 
 typedef enum {
     LCF_OK = 0,
@@ -71,7 +71,8 @@ typedef enum {
     LCF_CUT_EXPLICIT = 2, /* caller's weights explicit_w[d][i]                       */
     LCF_CUT_MLP = 3,      /* weights from the context's MLP (needs Nt = 128)          */
     LCF_CUT_MEDIAN = 4,   /* k = #{i : lambda_i > beta_median * lambda_median} (Eq. 7) */
-    LCF_CUT_SLOPE = 5     /* k = first n with |slope| <= slope_thr (method 2, Fig. 2c) */
+    LCF_CUT_SLOPE = 5,    /* k = first n with |slope| <= slope_thr (method 2, Fig. 2c) */
+    LCF_CUT_POWER = 6     /* soft w_i = win(i) / lambda_i^beta_power, max 1 (Eq. 10)   */
 } lcf_cut;
 
 typedef enum {
@@ -98,7 +99,7 @@ typedef struct {
 /* Thresholding rule (Adaptive Thresholding Methods section). */
 typedef struct {
     int32_t cut;             /* lcf_cut                                                  */
-    int32_t shape;           /* lcf_shape (ignored for EXPLICIT and MLP)                 */
+    int32_t shape;           /* lcf_shape (ignored for EXPLICIT, MLP and POWER)          */
     int32_t pd_mode;         /* lcf_pd_mode                                              */
     int32_t k_fixed;         /* FIXED_K: 0 <= k_fixed <= nt                               */
     double beta_knee;        /* Eq. 6 normalisation factor beta (> 0), typically 1        */
@@ -114,6 +115,10 @@ typedef struct {
                                 y(n) = Nt lambda_n / lambda_1, differences as for Eq. 6;
                                 k = 0-based index of the first n with |y'(n)| <= slope_thr
                                 (Nt if none); lambda_1 <= 0 sets NONPOSITIVE and k = 0 */
+    double beta_power;       /* POWER: Eq. 10 order beta (> 0, finite); win(i) =
+                                exp(-(2.5 i / (Nt - 1))^2 / 2), eigenvalues floored at
+                                lambda_1 2^-52, weights scaled to a maximum of 1;
+                                lambda_1 <= 0 sets NONPOSITIVE with all-ones weights  */
 } lcf_threshold;
 
 /* Optional per-subset diagnostics (device pointers, each may be NULL).

@@ -9,8 +9,8 @@ order:
 2. Gaussian windows, C_w = W C                          -- Eq. 11
 3. Covariance R = C_w^H C_w                             -- Eqs 1 and 12
 4. EVD R = V Lambda V^H, eigenvalues descending         -- Eq. 2
-5. Eigencomponent weights (hard / curvature / slope / median / sigmoid)
-                                                        -- Eqs 4, 6, 7, 9, Fig. 2c
+5. Eigencomponent weights (hard / curvature / slope / median / sigmoid /
+   eigenvalue power)                                   -- Eqs 4, 6, 7, 9, 10, Fig. 2c
 6. Projection C_hat = C_w V diag(w) V^H                 -- Eqs 4 and 5
 7. Power Doppler PD_d = sum_t |C_hat|^2                 -- text after Eq. 5
 8. Recombination PD = sum_d alpha_d PD_d, alpha_d = 1/(mean flow power)  -- Eq. 13
@@ -27,7 +27,10 @@ the number of rejected leading components; the median rule takes the mean of
 the two middle eigenvalues when Nt is even and rejects only eigenvalues strictly
 above its threshold; the slope rule differentiates y(n) = lambda_n scaled as the
 curvature rule scales its curve (Nt y(n) / y(1)) and cuts before the first n
-whose slope magnitude is at most its threshold; the combined filtered IQ is
+whose slope magnitude is at most its threshold; the window of Eq. 10 is the half
+of a Gaussian window of length 2 Nt - 1 with MATLAB's default width (alpha 2.5)
+that starts at its peak, eigenvalues are floored at lambda_1 2^-52 there, and
+"normalised" scales the weights to a maximum of 1; the combined filtered IQ is
 sum_d C_hat_d / sum_d w_d.
 """
 from __future__ import annotations
@@ -38,7 +41,7 @@ from typing import Optional
 
 import numpy as np
 
-CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE = 0, 1, 2, 3, 4, 5
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER = 0, 1, 2, 3, 4, 5, 6
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 
@@ -57,6 +60,7 @@ class Threshold:
     beta_sigmoid: float = 2.0
     beta_median: float = 1.43                   # Eq. 7 scaling factor (Fig. 2a's example)
     slope_thr: float = 1.1                      # slope rule threshold (Fig. 2c's example)
+    beta_power: float = 2.0                     # Eq. 10 order (Fig. 2g's example)
     explicit_w: Optional[np.ndarray] = None     # [nd][nt]
     mlp: Optional[object] = None                # callable(lam) -> weights, for CUT_MLP
 
@@ -192,6 +196,22 @@ def slope_k(lam: np.ndarray, thr: float):
     return nt, 0
 
 
+def power_weights(lam: np.ndarray, beta: float):
+    """Method 6 (Eq. 10 with its Gaussian window): wt_i = win(i) / lambda_i^beta,
+    i = 0..Nt-1, win(i) = exp(-(2.5 i / (Nt - 1))^2 / 2), then wt / max(wt).
+    Eigenvalues are floored at lambda_1 2^-52. Returns (w, flags); lambda_1 <= 0
+    gives all-ones weights and NONPOSITIVE."""
+    lam = np.asarray(lam, dtype=np.float64)
+    nt = lam.shape[0]
+    if not lam[0] > 0.0:
+        return np.ones(nt), FLAG_NONPOSITIVE
+    lf = np.maximum(lam, lam[0] * 2.0 ** -52)
+    i = np.arange(nt, dtype=np.float64)
+    win = np.exp(-0.5 * (2.5 * i / (nt - 1)) ** 2)
+    wt = win / lf ** beta
+    return wt / np.max(wt), 0
+
+
 def median_k(lam: np.ndarray, beta: float) -> int:
     """Method 3 (Eq. 7): threshold T = beta * lambda_median; the components whose
     eigenvalue exceeds T are tissue, so k = #{i : lambda_i > T}. The median of an
@@ -224,6 +244,9 @@ def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
         return np.asarray(thr.explicit_w[d], dtype=np.float64).copy(), -1, curv, 0
     if thr.cut == CUT_MLP:
         return np.asarray(thr.mlp(lam), dtype=np.float64), -1, curv, 0
+    if thr.cut == CUT_POWER:
+        w, flags = power_weights(lam, thr.beta_power)
+        return w, -1, curv, flags
     if thr.cut == CUT_FIXED_K:
         k = int(thr.k_fixed)
     elif thr.cut == CUT_KNEE:

@@ -16,8 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblcf.so")
 
 PREC_FP32, PREC_BF16X3 = 0, 1
-CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE = 0, 1, 2, 3, 4, 5
-ABI_VERSION = 3
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER = 0, 1, 2, 3, 4, 5, 6
+ABI_VERSION = 4
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 OPT_SCHEDULE, OPT_MAX_SWEEPS, OPT_USE_GRAPH, OPT_SUBSPACE_IT, OPT_STAGE_TIMING, OPT_AUTOTUNE, OPT_EVD = 1, 2, 3, 4, 5, 6, 7
@@ -46,7 +46,7 @@ class ThresholdC(C.Structure):
     _fields_ = [("cut", C.c_int32), ("shape", C.c_int32), ("pd_mode", C.c_int32), ("k_fixed", C.c_int32),
                 ("beta_knee", C.c_double), ("knee_max_frac", C.c_double), ("beta_sigmoid", C.c_double),
                 ("deflate_rho", C.c_double), ("explicit_w", C.c_void_p), ("beta_median", C.c_double),
-                ("slope_thr", C.c_double)]
+                ("slope_thr", C.c_double), ("beta_power", C.c_double)]
 
 
 class DiagC(C.Structure):
@@ -68,11 +68,12 @@ class Threshold:
     deflate_rho: float = 1e-5
     beta_median: float = 1.43      # the scaling factor of the paper's Fig. 2a example
     slope_thr: float = 1.1         # the slope threshold of the paper's Fig. 2c example
+    beta_power: float = 2.0        # the order of the paper's Fig. 2g example
 
     def to_c(self, explicit_ptr: int = 0) -> ThresholdC:
         return ThresholdC(self.cut, self.shape, self.pd_mode, self.k_fixed, self.beta_knee,
                           self.knee_max_frac, self.beta_sigmoid, self.deflate_rho, explicit_ptr or None,
-                          self.beta_median, self.slope_thr)
+                          self.beta_median, self.slope_thr, self.beta_power)
 
 
 _lib = None

@@ -1,4 +1,4 @@
-// Eigencomponent weights (Eqs 4, 6, 7, 9, slope rule), the projector P = V diag(w) V^H, and
+// Eigencomponent weights (Eqs 4, 6, 7, 9, 10, slope rule), the projector P = V diag(w) V^H, and
 // the output-centric reprojection + power Doppler + recombination (Eqs 4, 5, 13).
 #include "lcf_internal.h"
 #include "lcf_kernels.h"
@@ -107,6 +107,27 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
             wts[i] = rp.shape == 0 ? (n1 > (double)k ? 1.0 : 0.0)
                                    : 1.0 / (1.0 + exp(-rp.beta_sigmoid * (n1 - (double)k)));
         }
+    } else if (rp.cut == 6) {
+        // Eq. 10: w_i = win(i) / lambda_i^beta with the half Gaussian window
+        // win(i) = exp(-(2.5 i / (Nt - 1))^2 / 2), scaled to a maximum of 1; taken
+        // in logarithms so that no power overflows
+        const double l1 = lam[0];
+        if (!(l1 > 0.0)) {
+            for (int i = lane; i < nt; i += 64) wts[i] = 1.0;
+            if (lane == 0) sh_flag = 1;
+        } else {
+            const double floor_ = l1 * 2.220446049250313e-16;     // lambda_1 * 2^-52
+            double mx = -INFINITY;
+            for (int i = lane; i < nt; i += 64) {
+                const double l = lam[i] > floor_ ? lam[i] : floor_;
+                const double u = 2.5 * (double)i / (double)(nt - 1);
+                const double lw = -0.5 * u * u - rp.beta_power * log(l);
+                yt[i] = lw;
+                mx = fmax(mx, lw);
+            }
+            for (int m = 32; m >= 1; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m, 64));
+            for (int i = lane; i < nt; i += 64) wts[i] = exp(yt[i] - mx);
+        }
     } else if (rp.cut == 2) {
         for (int i = lane; i < nt; i += 64) wts[i] = (double)ws.explicit_w[(long)s * nt + i];
     } else {
@@ -118,7 +139,7 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     for (int i = lane; i < nt; i += 64) e += wts[i] * wts[i] * lam[i];
     e = wave_sum(e);
     if (lane == 0) {
-        ws.kcut[s] = (rp.cut <= 1 || rp.cut >= 4) ? sh_k : -1;
+        ws.kcut[s] = (rp.cut <= 1 || rp.cut == 4 || rp.cut == 5) ? sh_k : -1;
         ws.alpha[s] = rp.pd_mode == 1 ? 1.0 : (e > 0.0 ? sd.npix_nt / e : 0.0);
         if (sh_flag) atomicOr(&ws.flags[s], sh_flag);
     }

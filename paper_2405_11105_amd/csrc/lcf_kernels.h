@@ -7,7 +7,7 @@ namespace lcf {
 
 struct RuleParams {
     int cut, shape, pd_mode, k_fixed;
-    double beta_knee, knee_max_frac, beta_sigmoid, beta_median, slope_thr;
+    double beta_knee, knee_max_frac, beta_sigmoid, beta_median, slope_thr, beta_power;
 };
 
 hipError_t launch_windows(const Workspace& ws, hipStream_t st);

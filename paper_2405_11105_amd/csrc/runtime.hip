@@ -81,7 +81,7 @@ lcf_status validate_geometry(const lcf_geometry* g) {
 
 lcf_status validate_threshold(const lcf_threshold* t, int nt) {
     if (!t) return LCF_ERR_INVALID_ARG;
-    if (t->cut < 0 || t->cut > 5 || t->shape < 0 || t->shape > 1 || t->pd_mode < 0 || t->pd_mode > 2)
+    if (t->cut < 0 || t->cut > 6 || t->shape < 0 || t->shape > 1 || t->pd_mode < 0 || t->pd_mode > 2)
         return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_FIXED_K && (t->k_fixed < 0 || t->k_fixed > nt)) return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_KNEE && (!(t->beta_knee > 0.0) || !(t->knee_max_frac > 0.0) || t->knee_max_frac > 1.0))
@@ -90,7 +90,10 @@ lcf_status validate_threshold(const lcf_threshold* t, int nt) {
         return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_SLOPE && !(t->slope_thr > 0.0 && std::isfinite(t->slope_thr)))
         return LCF_ERR_INVALID_ARG;
-    if (t->shape == LCF_SHAPE_SIGMOID && (t->cut <= LCF_CUT_KNEE || t->cut >= LCF_CUT_MEDIAN) &&
+    if (t->cut == LCF_CUT_POWER && !(t->beta_power > 0.0 && std::isfinite(t->beta_power)))
+        return LCF_ERR_INVALID_ARG;
+    if (t->shape == LCF_SHAPE_SIGMOID && (t->cut <= LCF_CUT_KNEE || t->cut == LCF_CUT_MEDIAN ||
+                                          t->cut == LCF_CUT_SLOPE) &&
         !(t->beta_sigmoid > 0.0))
         return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_EXPLICIT && t->explicit_w == nullptr) return LCF_ERR_INVALID_ARG;
@@ -342,7 +345,7 @@ std::string graph_key(lcf_context* c, const Plan& pl, const std::vector<PacketIn
                   thr->pd_mode, thr->k_fixed, thr->beta_knee, thr->knee_max_frac, thr->beta_sigmoid, thr->deflate_rho,
                   (const void*)thr->explicit_w, prec, c->schedule, c->max_sweeps, c->sub_iters, pl.ntp);
     k += buf;
-    std::snprintf(buf, sizeof buf, "|m%.17g,%.17g", thr->beta_median, thr->slope_thr);
+    std::snprintf(buf, sizeof buf, "|m%.17g,%.17g,%.17g", thr->beta_median, thr->slope_thr, thr->beta_power);
     k += buf;
     std::snprintf(buf, sizeof buf, "|c%d,r%d,v%d,e%d", pl.chunk, pl.trows, pl.rvar, c->evd_method);
     k += buf;
@@ -581,7 +584,7 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
                        int all_vectors, hipStream_t st) {
     const bool mlp = thr->cut == LCF_CUT_MLP;
     RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
-                  thr->knee_max_frac, thr->beta_sigmoid, thr->beta_median, thr->slope_thr};
+                  thr->knee_max_frac, thr->beta_sigmoid, thr->beta_median, thr->slope_thr, thr->beta_power};
     { STAGE(c, LCF_STAGE_EVD, st); HIPCHK(launch_evd(ws, c->max_sweeps, nt_max, c->evd_method, st)); }
     { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
     if (mlp) {

@@ -62,7 +62,7 @@ def oracle_thr(lcf_thr, nd=None, explicit=None):
     return O.Threshold(cut=lcf_thr.cut, shape=lcf_thr.shape, pd_mode=lcf_thr.pd_mode, k_fixed=lcf_thr.k_fixed,
                        beta_knee=lcf_thr.beta_knee, knee_max_frac=lcf_thr.knee_max_frac,
                        beta_sigmoid=lcf_thr.beta_sigmoid, beta_median=lcf_thr.beta_median,
-                       slope_thr=lcf_thr.slope_thr, explicit_w=explicit)
+                       slope_thr=lcf_thr.slope_thr, beta_power=lcf_thr.beta_power, explicit_w=explicit)
 
 
 def slope_tie(lam, thr, k1, k2):
@@ -97,6 +97,9 @@ def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, pre
         lam_g = d["eigvals"][s]
         lam_o = res["lam"][s]
         assert np.allclose(lam_g, lam_o, rtol=1e-5, atol=1e-7 * lam_o[0]), (s, np.max(np.abs(lam_g - lam_o) / lam_o[0]))
+        if thr.cut == lcf.CUT_POWER:
+            w_rule, _, _, _ = O.rule_weights(lam_g, oracle_thr(thr))
+            assert np.allclose(d["weights"][s], w_rule, rtol=1e-6, atol=1e-7), s
         if thr.cut in (lcf.CUT_FIXED_K, lcf.CUT_KNEE, lcf.CUT_MEDIAN, lcf.CUT_SLOPE):
             w_rule, k_rule, curv, _ = O.rule_weights(lam_g, oracle_thr(thr))
             assert d["k"][s] == k_rule, (s, d["k"][s], k_rule)

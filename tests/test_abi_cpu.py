@@ -50,7 +50,9 @@ def test_validate_geometry_and_threshold(lcf):
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=1.1)) == 0
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=-1.0)) == 1
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=float("nan"))) == 1
-    assert lcf.validate(ok, lcf.Threshold(cut=6)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_POWER, beta_power=2.0)) == 0
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_POWER, beta_power=0.0)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=7)) == 1
 
 
 def test_abi_version_matches_binding(lcf):

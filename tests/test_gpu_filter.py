@@ -164,8 +164,10 @@ def test_clinical_median_rule(lcf, ctx, prec):
     # method 3 (Eq. 7) at the clinical shape. beta = 30 puts the cut at the
     # tissue / blood transition of these packets (k = 3 to 7; the curvature rule
     # gives 5 to 19). The 1.43 of the paper's Fig. 2a, fitted to its own data,
-    # cuts 35 to 52 components deep here, leaving only noise-floor components
-    # whose small norm is not what the FP32 bound on the filtered IQ is for.
+    # cuts 35 to 52 components deep here, inside the noise floor, where the
+    # eigen-gap at the cut is about 3e-10 lambda_1: a hard cut there moves the
+    # rejected subspace by the Gram's rounding over that gap, beyond the FP32
+    # bound on the filtered IQ, in any FP32 implementation.
     iq, mask = synth.make_packet(synth.spec_clinical(1))
     thr = lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=30.0)
     tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
@@ -195,6 +197,22 @@ def test_slope_rule_odd_frame_count_sigmoid(lcf, ctx):
     iq, mask = synth.make_packet(spec)
     thr = lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=0.3, shape=lcf.SHAPE_SIGMOID)
     _check_end_to_end(lcf, ctx, iq, mask, 3, 3, thr, 1e-5, 0.1, "slope nt=45 sigmoid")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_clinical_power_weights(lcf, ctx, prec):
+    # method 6 (Eq. 10) with the order of the paper's Fig. 2g example
+    iq, mask = synth.make_packet(synth.spec_clinical(3))
+    thr = lcf.Threshold(cut=lcf.CUT_POWER, beta_power=2.0)
+    tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
+    _check_end_to_end(lcf, ctx, iq, mask, 8, 8, thr, tol, 0.1, f"clinical power prec={prec}", precision=prec)
+
+
+def test_power_weights_odd_frame_count(lcf, ctx):
+    spec = synth.PacketSpec(80, 64, 45, 50.0, 0.5, ((30, 3, 0.6),), seed=47)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_POWER, beta_power=1.0)
+    _check_end_to_end(lcf, ctx, iq, mask, 3, 3, thr, 1e-5, 0.1, "power nt=45")
 
 
 def test_all_ones_weights_return_input(lcf, ctx):

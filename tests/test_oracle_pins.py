@@ -234,6 +234,37 @@ def test_slope_rule_linear_spectrum_and_degenerate():
     assert flags == 1 and k == 0 and np.all(w == 1)
 
 
+def test_power_weights_flat_spectrum_is_the_window():
+    # equal eigenvalues leave the window of Eq. 10 itself: for Nt = 5,
+    # u_i = 2.5 i / 4 and win = exp(-u^2 / 2) = exp(0, -.1953125, -.78125,
+    # -1.7578125, -3.125), already at maximum 1 for i = 0
+    w, flags = O.power_weights(np.full(5, 3.0), 2.0)
+    assert flags == 0
+    assert np.allclose(w, np.exp([0.0, -0.1953125, -0.78125, -1.7578125, -3.125]), rtol=1e-14)
+
+
+def test_power_weights_geometric_hand_worked():
+    # lambda_i = 2^-i, Nt = 5, beta = 1: log wt_i = -.1953125 i^2 + i ln 2 =
+    # 0, .4978347, .6050444, .3216290, -.3524113; the maximum is at i = 2
+    w, _ = O.power_weights(2.0 ** -np.arange(5, dtype=np.float64), 1.0)
+    lw = np.array([0.0, 0.4978347, 0.6050444, 0.3216290, -0.3524113])
+    assert w[2] == 1.0
+    assert np.allclose(w, np.exp(lw - lw[2]), rtol=1e-6)
+    # a common scale of the eigenvalues cancels in the normalisation
+    w2, _ = O.power_weights(7.5 * 2.0 ** -np.arange(5, dtype=np.float64), 1.0)
+    assert np.allclose(w2, w, rtol=1e-13)
+
+
+def test_power_weights_floor_and_degenerate():
+    # zero eigenvalues are floored at lambda_1 2^-52: for Nt = 4 they dominate,
+    # and the last one is worth win(3) / win(2) = exp(-(6.25 - 25 / 9) / 2)
+    w, _ = O.power_weights(np.array([1.0, 0.5, 0.0, 0.0]), 1.0)
+    assert w[2] == 1.0 and abs(w[3] - math.exp(-0.5 * (6.25 - 25.0 / 9.0))) < 1e-14
+    assert w[0] < 1e-14
+    w, k, _, flags = O.rule_weights(np.zeros(6), O.Threshold(cut=O.CUT_POWER))
+    assert flags == 1 and k == -1 and np.all(w == 1)
+
+
 def test_median_rule_geometric_odd_count():
     # Eq. 7 worked by hand: lambda_i = 2^-i, i = 0..8; the median is 2^-4. With
     # beta = 4 the threshold 1/4 equals lambda_2, which is kept (only eigenvalues
