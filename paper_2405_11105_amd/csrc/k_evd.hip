@@ -1562,6 +1562,7 @@ static hipError_t small_stage(const Workspace& ws, int stage, double rho, int ia
     switch (ws.ntp) {
         case 32: small_dispatch<32>(ws, stage, rho, iarg, st); break;
         case 64: small_dispatch<64>(ws, stage, rho, iarg, st); break;
+        case 96: small_dispatch<96>(ws, stage, rho, iarg, st); break;
         case 128: small_dispatch<128>(ws, stage, rho, iarg, st); break;
         case 160: small_dispatch<160>(ws, stage, rho, iarg, st); break;
         case 208: small_dispatch<208>(ws, stage, rho, iarg, st); break;
@@ -1586,7 +1587,7 @@ hipError_t launch_assemble(const Workspace& ws, int keep_r, hipStream_t st) {
 // The tridiagonal solver and its vector stage hold B padded to 16 columns per
 // wave and address every per-subset slot with that size: up to 128 frames the
 // class must be one of those sizes.
-static bool tri_sized(int ntp) { return ntp > 128 || ntp == 32 || ntp == 64 || ntp == 128; }
+static bool tri_sized(int ntp) { return ntp > 128 || ntp == 32 || ntp == 64 || ntp == 96 || ntp == 128; }
 
 hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
     if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
@@ -1602,6 +1603,11 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
     if (ws.ntp <= 64) {
         if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
         hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps, sel);
+        return hipGetLastError();
+    }
+    if (ws.ntp == 96) {
+        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<2, 6>), dim3(ws.S), dim3(384), 0, st, ws);
+        hipLaunchKernelGGL((k_jacobi_reg<2, 6>), dim3(ws.S), dim3(384), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp <= 128) {
@@ -1625,6 +1631,7 @@ hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStrea
     if (method != 0 || ws.ntp > 128) return hipSuccess;
     if (ws.ntp <= 32) hipLaunchKernelGGL((k_heev_tri_vecs<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, all);
     else if (ws.ntp <= 64) hipLaunchKernelGGL((k_heev_tri_vecs<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, all);
+    else if (ws.ntp == 96) hipLaunchKernelGGL((k_heev_tri_vecs<2, 6>), dim3(ws.S), dim3(256), 0, st, ws, all);
     else hipLaunchKernelGGL((k_heev_tri_vecs<2, 8>), dim3(ws.S), dim3(256), 0, st, ws, all);
     return hipGetLastError();
 }

@@ -726,6 +726,7 @@ hipError_t launch_gram(const Workspace& ws, bool defl, bool reduce, int precisio
     switch (ws.ntp) {
         case 32: return gram_dispatch<32>(ws, defl, reduce, precision, st);
         case 64: return gram_dispatch<64>(ws, defl, reduce, precision, st);
+        case 96: return gram_dispatch<96>(ws, defl, reduce, precision, st);
         case 128: return gram_dispatch<128>(ws, defl, reduce, precision, st);
         case 160: return gram_dispatch<160>(ws, defl, reduce, precision, st);
         case 208: return gram_dispatch<208>(ws, defl, reduce, precision, st);

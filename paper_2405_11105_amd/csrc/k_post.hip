@@ -158,12 +158,12 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
 // split-BF16 [P; M] planes used by the reprojection GEMM.
 constexpr int PCC = 16;
 
-// From 128 frames up the 128 x 128 P blocks are spread over 512 threads (4 rows
+// From 96 frames up the 128 x 128 P blocks are spread over 512 threads (4 rows
 // x 8 columns each): with 256 threads the 8 x 8 FP64 accumulators left room
 // for one wave per SIMD only.
 template <int NTP>
 struct PjCfg {
-    static constexpr int NTHR = NTP >= 128 ? 512 : 256;
+    static constexpr int NTHR = NTP >= 96 ? 512 : 256;
     static constexpr int RA = 2048 / NTHR;      // rows per thread in a 128 x 128 block
 };
 
@@ -1509,6 +1509,7 @@ static hipError_t post_stage(const Workspace& ws, int stage, int prec, hipStream
     switch (ws.ntp) {
         case 32: post_dispatch<32>(ws, stage, prec, st); break;
         case 64: post_dispatch<64>(ws, stage, prec, st); break;
+        case 96: post_dispatch<96>(ws, stage, prec, st); break;
         case 128: post_dispatch<128>(ws, stage, prec, st); break;
         case 160: post_dispatch<160>(ws, stage, prec, st); break;
         case 208: post_dispatch<208>(ws, stage, prec, st); break;

@@ -20,9 +20,9 @@ using namespace lcf;
 namespace {
 
 // Padded frame classes. Up to 128 frames they are exactly the sizes of the
-// tridiagonal EVD's 2-, 4- and 8-wave shapes (16 columns per wave), which hold
-// B at that size and address it with it, so there is no class between 64 and 128.
-const int NTP_CLASSES[] = {32, 64, 128, 160, 208};
+// tridiagonal EVD's 2-, 4-, 6- and 8-wave shapes (16 columns per wave), which
+// hold B at that size and address it with it.
+const int NTP_CLASSES[] = {32, 64, 96, 128, 160, 208};
 constexpr int NT_MAX = 208;
 
 int ntp_class(int nt) {

@@ -130,8 +130,8 @@ def test_ragged_nt100_small_grid(lcf, ctx):
 @pytest.mark.parametrize("nt", [80, 150])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_ragged_frame_counts_80_150(lcf, ctx, nt, prec):
-    # 80 frames fall in the 128 class with 48 padding frames, 150 in the 160
-    # class; both are ragged in the pixels as well
+    # 80 frames fall in the 96 class (16 padding frames), 150 in the 160 class;
+    # both are ragged in the pixels as well
     spec = synth.PacketSpec(90, 70, nt, 50.0, 0.4, ((25, 3, 0.3), (60, 4, 0.7)), seed=500 + nt)
     iq, mask = synth.make_packet(spec)
     thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
@@ -370,10 +370,12 @@ def test_graph_cache_keys_on_median_beta(lcf, ctx):
             gctx.close()
 
 
-def test_evd_tridiagonal_matches_jacobi(lcf, ctx):
-    """The two subset eigen-solvers give the same filter (FP32 path)."""
-    _say("[tridiagonal vs Jacobi EVD]")
-    iq, mask = synth.make_packet(synth.spec_clinical(2))
+@pytest.mark.parametrize("nt", [128, 80])
+def test_evd_tridiagonal_matches_jacobi(lcf, ctx, nt):
+    """The two subset eigen-solvers give the same filter (FP32 path); 80 frames
+    run the 6-wave shapes of both (96-frame class)."""
+    _say(f"[tridiagonal vs Jacobi EVD nt={nt}]")
+    iq, mask = synth.make_packet(synth.spec_clinical(2, nt=nt))
     dev = torch.from_numpy(iq).cuda()
     thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
     io_t, pd_t, d_t = ctx.filter(dev, 8, 8, thr, diag=True)
