@@ -266,8 +266,9 @@ def test_batch_mixed_shapes_matches_single(lcf, ctx):
     _say("[batch mixed shapes]")
     specs = [synth.PacketSpec(64, 48, 32, 50.0, 0.3, ((20, 3, 0.5),), seed=11),
              synth.PacketSpec(40, 56, 64, 50.0, 0.3, ((15, 2, 0.2),), seed=12),
-             synth.PacketSpec(64, 48, 32, 45.0, 0.6, ((30, 4, 0.9),), seed=13)]
-    grids = [(2, 2), (3, 2), (2, 3)]
+             synth.PacketSpec(64, 48, 32, 45.0, 0.6, ((30, 4, 0.9),), seed=13),
+             synth.PacketSpec(56, 40, 80, 50.0, 0.4, ((25, 3, 0.5),), seed=14)]
+    grids = [(2, 2), (3, 2), (2, 3), (3, 3)]
     iqs = [torch.from_numpy(synth.make_packet(s)[0]).cuda() for s in specs]
     thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
     ios, pds = ctx.filter_batch(iqs, grids, thr, iq_out=True)
