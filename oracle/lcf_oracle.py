@@ -15,7 +15,7 @@ order:
 7. Power Doppler PD_d = sum_t |C_hat|^2                 -- text after Eq. 5
 8. Recombination PD = sum_d alpha_d PD_d, alpha_d = 1/(mean flow power)  -- Eq. 13
 
-Readings where the paper is silent or ambiguous (each is listed in the design doc):
+Readings where the paper is silent or ambiguous:
 transposes of complex data are conjugate transposes; PD integrates (sums) over
 slow time; the mean flow power of a subset is taken over all Npix pixels and
 Nt frames, so alpha_d = Npix*Nt / sum_i w_i^2 lambda_i; window centres sit at
