@@ -215,7 +215,8 @@ lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_thres
  * (the parallel processing of subsets that the Discussion leaves for future work).
  * geo[n] host array; iq/iq_out/pd are host arrays of n device pointers (iq_out[i]
  * may be NULL, iq_out itself may be NULL). One threshold rule applies to all.
- * n >= 1: an empty batch returns LCF_ERR_INVALID_ARG. */
+ * n >= 1: an empty batch returns LCF_ERR_INVALID_ARG. Caller-given weights
+ * (LCF_CUT_EXPLICIT) are per packet and not taken here: LCF_ERR_UNSUPPORTED. */
 lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo,
                             const lcf_threshold* thr, int32_t precision,
                             const void* const* iq, void* const* iq_out, float* const* pd,

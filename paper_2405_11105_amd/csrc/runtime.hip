@@ -915,14 +915,14 @@ lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_thres
 lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo, const lcf_threshold* thr,
                             int32_t precision, const void* const* iq, void* const* iq_out, float* const* pd,
                             void* stream) {
-    if (!ctx || n < 1 || !geo || !iq || !pd) return LCF_ERR_INVALID_ARG;
+    if (!ctx || n < 1 || !geo || !iq || !pd || !thr) return LCF_ERR_INVALID_ARG;
+    if (thr->cut == LCF_CUT_EXPLICIT) return LCF_ERR_UNSUPPORTED;    // weights are per packet
     std::vector<PacketIn> in;
     for (int i = 0; i < n; ++i) {
         lcf_status e = lcf_validate(&geo[i], thr, precision);
         if (e != LCF_OK) return e;
         if (!iq[i] || !pd[i]) return LCF_ERR_INVALID_ARG;
         if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
-        if (thr->cut == LCF_CUT_EXPLICIT) return LCF_ERR_UNSUPPORTED;
         in.push_back(PacketIn{geo[i], iq[i], iq_out ? iq_out[i] : nullptr, pd[i]});
     }
     return filter_packets(ctx, in, thr, precision, nullptr, (hipStream_t)stream);

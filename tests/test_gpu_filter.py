@@ -151,12 +151,17 @@ def test_frame_count_limits(lcf, ctx, nt, prec):
     _check_end_to_end(lcf, ctx, iq, mask, 2, 2, thr, tol, 0.1, f"nt={nt} prec={prec}", precision=prec)
 
 
-def test_empty_batch_rejected(lcf, ctx):
-    _say("[empty batch]")
+def test_batch_argument_errors(lcf, ctx):
+    _say("[batch argument errors]")
     thr = lcf.Threshold(cut=lcf.CUT_KNEE)
     with pytest.raises(lcf.LcfError) as ei:
         ctx.filter_batch([], [], thr)
     assert ei.value.status == 1     # LCF_ERR_INVALID_ARG
+    # caller-given weights are per packet: not taken by the batched call
+    iq = torch.from_numpy(synth.make_packet(synth.spec_small(3))[0]).cuda()
+    with pytest.raises(lcf.LcfError) as ei:
+        ctx.filter_batch([iq], [(2, 2)], lcf.Threshold(cut=lcf.CUT_EXPLICIT))
+    assert ei.value.status == 2     # LCF_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("prec", [0, 1])
