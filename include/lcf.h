@@ -35,6 +35,12 @@
  *    sweep cap, degenerate spectrum) set per-subset flags that lcf_sync reports.
  *  - A context is bound to one device; it is not thread-safe. It owns the
  *    scratch arena (grown on demand, reused afterwards), plans and MLP weights.
+ *  - Stream capture: lcf_filter, lcf_filter_batch, lcf_heevd_batched,
+ *    lcf_mlp_infer and lcf_mlp_train_step return LCF_ERR_UNSUPPORTED, before any
+ *    launch, when `stream` is being captured into a graph by the caller (they
+ *    upload plans and may grow the arena, which a later call would overwrite or
+ *    free under the caller's graph). With LCF_OPT_USE_GRAPH the library captures
+ *    and replays its own graphs instead.
  */
 #ifndef LCF_H
 #define LCF_H
@@ -216,7 +222,8 @@ lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_thres
  * geo[n] host array; iq/iq_out/pd are host arrays of n device pointers (iq_out[i]
  * may be NULL, iq_out itself may be NULL). One threshold rule applies to all.
  * n >= 1: an empty batch returns LCF_ERR_INVALID_ARG. Caller-given weights
- * (LCF_CUT_EXPLICIT) are per packet and not taken here: LCF_ERR_UNSUPPORTED. */
+ * (LCF_CUT_EXPLICIT): thr->explicit_w holds each packet's [nd_i][nt_i] block,
+ * packets back to back in call order (sum_i nd_i nt_i floats). */
 lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo,
                             const lcf_threshold* thr, int32_t precision,
                             const void* const* iq, void* const* iq_out, float* const* pd,

@@ -136,14 +136,6 @@ def evd(r: np.ndarray):
     return lam[::-1].copy(), v[:, ::-1].copy()
 
 
-def phase_normalize(v: np.ndarray) -> np.ndarray:
-    """Fix each column's free phase: its largest-magnitude entry made real > 0."""
-    v = v.copy()
-    idx = np.argmax(np.abs(v), axis=0)
-    ph = v[idx, np.arange(v.shape[1])]
-    return v * (np.abs(ph) / ph)[None, :]
-
-
 def knee_curvature(lam: np.ndarray, beta: float):
     """Curvature of the normalised log-eigenvalue curve (Eq. 6).
 
@@ -272,12 +264,14 @@ def projector(v: np.ndarray, w: np.ndarray) -> np.ndarray:
 
 def filter_packet(iq: np.ndarray, gy: int, gx: int, thr: Threshold,
                   sigma_frac: float = 1.0 / 3.0, trunc_sigmas: float = 6.0,
-                  check_eq5: bool = False, keep_chat: bool = False):
+                  check_eq5: bool = False, keep_chat: bool = False, subsets=None):
     """Localized EVD clutter filter of one packet (Eqs 11-13).
 
     Returns a dict with ``iq_out`` ([nt][ny][nx] complex128), ``pd`` ([ny][nx]),
     and per-subset ``lam``, ``v``, ``w``, ``k``, ``curv``, ``alpha``, ``flags``,
-    ``cov`` and ``wsum`` (sum_d w_d)."""
+    ``cov`` and ``wsum`` (sum_d w_d). ``subsets`` (a list of subset indices)
+    restricts the work to those windows (a timing sample; the recombined
+    outputs then cover those windows only)."""
     nt, ny, nx = iq.shape
     npix = ny * nx
     cfull = casorati(iq)                                   # [npix][nt]
@@ -288,6 +282,8 @@ def filter_packet(iq: np.ndarray, gy: int, gx: int, thr: Threshold,
     pd_parts = []
     res = dict(lam=[], v=[], w=[], k=[], curv=[], alpha=[], flags=[], cov=[], chat=[])
     for d, win in enumerate(wins):
+        if subsets is not None and d not in subsets:
+            continue
         wfull = window_table(win, ny, nx).reshape(-1)
         rows = (np.arange(win.y0, win.y1 + 1)[:, None] * nx
                 + np.arange(win.x0, win.x1 + 1)[None, :]).reshape(-1)

@@ -112,7 +112,8 @@ def load():
     lib.lcf_status_str.argtypes = [i32]
     lib.lcf_status_str.restype = C.c_char_p
     for name in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter",
-                 "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version", "lcf_stage_time",
+                 "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version",
+                 "lcf_stage_time",
                  "lcf_mlp_init", "lcf_mlp_set_params", "lcf_mlp_get_params", "lcf_mlp_get_grads", "lcf_mlp_save",
                  "lcf_mlp_load", "lcf_mlp_infer", "lcf_mlp_train_step", "lcf_tune_save", "lcf_tune_load"):
         getattr(lib, name).restype = i32
@@ -120,12 +121,6 @@ def load():
         raise RuntimeError(f"{LIB_PATH}: ABI version {lib.lcf_abi_version()}, the binding needs {ABI_VERSION}")
     _lib = lib
     return lib
-
-
-def exported_symbols():
-    return [n for n in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter",
-                        "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_status_str",
-                        "lcf_abi_version")]
 
 
 def _check(st: int, what: str):
@@ -246,8 +241,11 @@ class Context:
 
     def filter_batch(self, iqs: Sequence, grids: Sequence, thr: Threshold, precision: int = PREC_FP32,
                      sigma_frac: float = 1.0 / 3.0, trunc_sigmas: float = 6.0, iq_out: bool = False,
-                     outs=None):
-        """Filter several packets of any shapes in one call. Returns (iq_outs, pds)."""
+                     outs=None, explicit_w=None):
+        """Filter several packets of any shapes in one call. Returns (iq_outs, pds).
+
+        With CUT_EXPLICIT, ``explicit_w`` is a list of per-packet [nd][nt] weight
+        tensors; they are passed to the library back to back in call order."""
         import torch
         n = len(iqs)
         geos = (Geometry * n)()
@@ -269,7 +267,10 @@ class Context:
             ip[i] = iq.data_ptr()
             op[i] = io.data_ptr() if io is not None else None
             pp[i] = pd.data_ptr()
-        tc = thr.to_c(0)
+        ew = None
+        if thr.cut == CUT_EXPLICIT and explicit_w is not None:
+            ew = torch.cat([w.reshape(-1).to(device=iqs[0].device, dtype=torch.float32) for w in explicit_w])
+        tc = thr.to_c(ew.data_ptr() if ew is not None else 0)
         st = load().lcf_filter_batch(self._h, n, geos, C.byref(tc), precision, ip, op, pp, _stream())
         _check(st, "lcf_filter_batch")
         return ios, pds

@@ -188,6 +188,16 @@ k_gram(Workspace ws) {
     floatx4 acc[NACC];
 #pragma unroll
     for (int m = 0; m < NACC; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // FP32 pass 2 up to 128 frames: the MFMA accumulators hold one batch of PIX
+    // pixels (16 K steps) and are added into FP64 sums after every batch, so FP32
+    // rounding accumulates over 16 steps instead of a whole chunk (512). The bulk
+    // Gram C'^H C' is what sets the FP32 path's error where a cut falls between
+    // close bulk eigenvalues (the median rule at beta 1.43: 2.6e-5 -> below 1e-5).
+    // Wider classes would spill the FP64 sums and keep the chunk-long accumulation.
+    constexpr bool FLUSH = DEFL && PREC == 0 && NTP <= 128;
+    double acc64[FLUSH ? 4 * NACC : 1];
+#pragma unroll
+    for (int m = 0; m < (FLUSH ? 4 * NACC : 1); ++m) acc64[m] = 0.0;
 
     // Operand staging is software-pipelined: the global loads of the next batch of
     // box pixels are issued before the MFMAs of the current batch. Each thread
@@ -364,6 +374,14 @@ k_gram(Workspace ws) {
                     }
                 }
             }
+            if (FLUSH) {
+#pragma unroll
+                for (int m = 0; m < NACC; ++m) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc64[4 * m + e] += (double)acc[m][e];
+                    acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+            }
         } else {
             gram_mfma_bf16<C>(Ah, Al, aoff, boff, valid, acc, lane);
         }
@@ -373,6 +391,10 @@ k_gram(Workspace ws) {
         const int tau = PREC == 0 ? wave + C::WAVES * m : 2 * (wave * C::MAXP + (m >> 1)) + (m & 1);
         if (tau < C::TT) {
             float* dst = ws.partial + ((long)blockIdx.x * C::TT + tau) * 256 + lane * 4;
+            if (FLUSH) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[m][e] = (float)acc64[4 * m + e];
+            }
             *reinterpret_cast<floatx4*>(dst) = acc[m];
         }
     }

@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
             for (int i = lane; i < nt; i += 64) wts[i] = exp(yt[i] - mx);
         }
     } else if (rp.cut == 2) {
-        for (int i = lane; i < nt; i += 64) wts[i] = (double)ws.explicit_w[(long)s * nt + i];
+        for (int i = lane; i < nt; i += 64) wts[i] = (double)ws.explicit_w[sd.ew_off + i];
     } else {
         // weights already written by the MLP kernel
     }

@@ -35,6 +35,7 @@ struct SubsetDesc {
     int wy_off, wx_off; // offsets of the 1-D FP64 window factors in the table pool
     double cy, cx, sy, sx;
     double npix_nt;     // Npix * Nt of the packet (Eq. 13 normalisation)
+    long ew_off;        // offset of this subset's caller-given weights in explicit_w (floats)
 };
 
 // A split-K chunk of a subset's box pixels [q0, q1) in box row-major order.

@@ -120,6 +120,7 @@ struct PacketIn {
     const void* iq;
     void* iq_out;
     float* pd;
+    long ew_off;    // first caller-given weight of this packet in explicit_w (floats)
 };
 
 // Host-side plan of one launch group (packets sharing the padded Nt class).
@@ -180,6 +181,7 @@ void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int
             s.wx_off = wtab;
             wtab += s.bw;
             s.npix_nt = (double)g.ny * g.nx * g.nt;
+            s.ew_off = p.ew_off + (long)d * g.nt;
             const int sidx = (int)pl.sub.size();
             pl.chunk_begin.push_back((int)pl.chunks.size());
             for (int q = 0; q < s.neff; q += pl.chunk)
@@ -322,6 +324,14 @@ lcf_status ensure_host(lcf_context* c, size_t bytes) {
     }
     c->hcap = want;
     return LCF_OK;
+}
+
+// LCF_ERR_UNSUPPORTED when `st` is being captured into a graph by the caller
+// (the entry points that stage plans or grow buffers cannot be captured).
+lcf_status refuse_capture(hipStream_t st) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (st != nullptr && hipStreamIsCapturing(st, &cap) != hipSuccess) return LCF_ERR_DEVICE;
+    return cap == hipStreamCaptureStatusNone ? LCF_OK : LCF_ERR_UNSUPPORTED;
 }
 
 void drop_graphs(lcf_context* c) {
@@ -671,7 +681,6 @@ lcf_status run_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf
         for (int s = 0; s < (int)pl.sub.size(); ++s) {
             const int cb0 = pl.chunk_begin[s], nch = pl.chunk_begin[s + 1] - cb0;
             Workspace v = subset_view(ws, s, dch + cb0, dcb + 2 * s, nch);
-            if (ws.explicit_w) v.explicit_w = ws.explicit_w + (long)s * pl.sub[s].nt;
             double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
             e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
             if (e != LCF_OK) return e;
@@ -754,8 +763,11 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
                           const lcf_diag* diag, hipStream_t st) {
     if (!c) return LCF_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return LCF_ERR_DEVICE;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (st != nullptr && hipStreamIsCapturing(st, &cap) != hipSuccess) return LCF_ERR_DEVICE;
+    // A call made while the caller captures the stream is refused: the plan
+    // upload and the workspace of a captured chain would be overwritten or
+    // reallocated by later calls before the caller's graph is replayed.
+    lcf_status ce = refuse_capture(st);
+    if (ce != LCF_OK) return ce;
     // group packets by padded Nt class
     std::map<int, std::vector<int>> groups;
     for (size_t i = 0; i < in.size(); ++i) groups[ntp_class(in[i].g.nt)].push_back((int)i);
@@ -768,7 +780,7 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
                    (trows_max(kv.first) >= 4 && prec == LCF_PREC_FP32) ? 1 : 0);
         const std::string tkey = tune_key(pl, prec, c->schedule);
         auto tit = c->tuned.find(tkey);
-        if (tit == c->tuned.end() && c->autotune && cap == hipStreamCaptureStatusNone) {
+        if (tit == c->tuned.end() && c->autotune) {
             lcf_status e = tune_group(c, in, kv.second, thr, prec, st, tkey);
             if (e != LCF_OK) return e;
             tit = c->tuned.find(tkey);
@@ -788,7 +800,7 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
         // Launch chain of the group, optionally captured once into a hipGraph and
         // replayed for later calls with the same plan (not on the null stream, and
         // not while stage timing is on).
-        const bool graph = c->use_graph && !c->timing && st != nullptr && cap == hipStreamCaptureStatusNone;
+        const bool graph = c->use_graph && !c->timing && st != nullptr;
         std::string key;
         if (graph) {
             key = graph_key(c, pl, in, kv.second, thr, prec, diag);
@@ -908,7 +920,7 @@ lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_thres
     lcf_status e = lcf_validate(geo, thr, precision);
     if (e != LCF_OK) return e;
     if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
-    std::vector<PacketIn> in{PacketIn{*geo, iq, iq_out, pd}};
+    std::vector<PacketIn> in{PacketIn{*geo, iq, iq_out, pd, 0}};
     return filter_packets(ctx, in, thr, precision, diag, (hipStream_t)stream);
 }
 
@@ -916,14 +928,15 @@ lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo
                             int32_t precision, const void* const* iq, void* const* iq_out, float* const* pd,
                             void* stream) {
     if (!ctx || n < 1 || !geo || !iq || !pd || !thr) return LCF_ERR_INVALID_ARG;
-    if (thr->cut == LCF_CUT_EXPLICIT) return LCF_ERR_UNSUPPORTED;    // weights are per packet
     std::vector<PacketIn> in;
+    long ew = 0;     // caller-given weights: packets' [nd][nt] blocks back to back
     for (int i = 0; i < n; ++i) {
         lcf_status e = lcf_validate(&geo[i], thr, precision);
         if (e != LCF_OK) return e;
         if (!iq[i] || !pd[i]) return LCF_ERR_INVALID_ARG;
         if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
-        in.push_back(PacketIn{geo[i], iq[i], iq_out ? iq_out[i] : nullptr, pd[i]});
+        in.push_back(PacketIn{geo[i], iq[i], iq_out ? iq_out[i] : nullptr, pd[i], ew});
+        ew += (long)geo[i].gy * geo[i].gx * geo[i].nt;
     }
     return filter_packets(ctx, in, thr, precision, nullptr, (hipStream_t)stream);
 }
@@ -932,6 +945,8 @@ lcf_status lcf_heevd_batched(lcf_context* ctx, int32_t n, int32_t nt, const doub
                              int32_t* sweeps, void* stream) {
     if (!ctx || n < 1 || nt < 2 || nt > 256 || !a || !w) return LCF_ERR_INVALID_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status ce = refuse_capture((hipStream_t)stream);
+    if (ce != LCF_OK) return ce;
     const size_t work = align_up((size_t)n * nt * nt * sizeof(double2), 256);
     const size_t extra = align_up((size_t)n * sizeof(int), 256) * 2;
     lcf_status e = ensure_device(ctx, work + extra);
@@ -1076,6 +1091,8 @@ lcf_status lcf_mlp_infer(lcf_context* ctx, const double* lam, float* w, int32_t 
     if (!ctx || !lam || !w || b < 1) return LCF_ERR_INVALID_ARG;
     if (!ctx->mlp_ready) return LCF_ERR_MODEL;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status ce = refuse_capture((hipStream_t)stream);
+    if (ce != LCF_OK) return ce;
     lcf_status e = ensure_mlp_scratch(ctx, mlp_infer_scratch_floats(b) + align_up((size_t)b, 64));
     if (e != LCF_OK) return e;
     hipStream_t st = (hipStream_t)stream;
@@ -1091,6 +1108,8 @@ lcf_status lcf_mlp_train_step(lcf_context* ctx, const double* lam, const float* 
     if (!ctx || !lam || !target || b < 1 || !(lr >= 0.f)) return LCF_ERR_INVALID_ARG;
     if (!ctx->mlp_ready) return LCF_ERR_MODEL;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_status ce = refuse_capture((hipStream_t)stream);
+    if (ce != LCF_OK) return ce;
     lcf_status e = ensure_mlp_scratch(ctx, mlp_train_scratch_floats(b));
     if (e != LCF_OK) return e;
     ctx->mlp_step += 1;

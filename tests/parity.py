@@ -86,10 +86,13 @@ def median_tie(lam, beta, k1, k2):
     return all(abs(s[i] - t) <= 1e-5 * t + 1e-7 * s[0] for i in range(lo, hi))
 
 
-def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, precision=0):
-    say(f"[{name}] shape={iq.shape} grid={gy}x{gx} cut={thr.cut} shape={thr.shape}")
-    io, pd, d = run_gpu(lcf, ctx, iq, gy, gx, thr, precision=precision)
-    res = O.filter_packet(iq, gy, gx, oracle_thr(thr))
+def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, precision=0,
+                     sigma_frac=1.0 / 3.0, trunc_sigmas=6.0):
+    say(f"[{name}] shape={iq.shape} grid={gy}x{gx} cut={thr.cut} shape={thr.shape} pd_mode={thr.pd_mode} "
+        f"trunc={trunc_sigmas} prec={precision}")
+    geo = dict(sigma_frac=sigma_frac, trunc_sigmas=trunc_sigmas)
+    io, pd, d = run_gpu(lcf, ctx, iq, gy, gx, thr, precision=precision, **geo)
+    res = O.filter_packet(iq, gy, gx, oracle_thr(thr), **geo)
     nd = gy * gx
     # decision parity: the oracle's FP64 rule on the GPU's eigenvalues
     forced = False
@@ -115,13 +118,14 @@ def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, pre
                 forced = True
     if forced:
         ew = d["weights"].astype(np.float64)
-        res = O.filter_packet(iq, gy, gx, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=ew, pd_mode=thr.pd_mode))
+        res = O.filter_packet(iq, gy, gx, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=ew, pd_mode=thr.pd_mode),
+                              **geo)
     e_fro = rel_fro(io, res["iq_out"])
     emax, e99, e999, npx = pd_db_error(pd, res["pd"], mask)
     say(f"   rel_fro={e_fro:.3e} pd_db max={emax:.2e} p99={e99:.2e} p99.9={e999:.2e} n={npx} forced={forced} "
          f"sweeps={d['sweeps'].min()}..{d['sweeps'].max()} rank={d['rank'].min()}..{d['rank'].max()}")
     assert e_fro <= tol_fro
     assert emax <= tol_db
-    return e_fro, emax
+    return e_fro, emax, io, pd
 
 

@@ -157,26 +157,36 @@ def test_batch_argument_errors(lcf, ctx):
     with pytest.raises(lcf.LcfError) as ei:
         ctx.filter_batch([], [], thr)
     assert ei.value.status == 1     # LCF_ERR_INVALID_ARG
-    # caller-given weights are per packet: not taken by the batched call
+    # caller-given weights without a weight array
     iq = torch.from_numpy(synth.make_packet(synth.spec_small(3))[0]).cuda()
     with pytest.raises(lcf.LcfError) as ei:
         ctx.filter_batch([iq], [(2, 2)], lcf.Threshold(cut=lcf.CUT_EXPLICIT))
-    assert ei.value.status == 2     # LCF_ERR_UNSUPPORTED
+    assert ei.value.status == 1     # LCF_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_clinical_median_rule(lcf, ctx, prec):
-    # method 3 (Eq. 7) at the clinical shape. beta = 30 puts the cut at the
-    # tissue / blood transition of these packets (k = 3 to 7; the curvature rule
-    # gives 5 to 19). The 1.43 of the paper's Fig. 2a, fitted to its own data,
-    # cuts 35 to 52 components deep here, inside the noise floor, where the
-    # eigen-gap at the cut is about 3e-10 lambda_1: a hard cut there moves the
-    # rejected subspace by the Gram's rounding over that gap, beyond the FP32
-    # bound on the filtered IQ, in any FP32 implementation.
+    # method 3 (Eq. 7) at the clinical shape with beta = 30, which puts the cut
+    # at the tissue / blood transition of these packets (k = 3 to 7; the
+    # curvature rule gives 5 to 19); the paper's own beta follows.
     iq, mask = synth.make_packet(synth.spec_clinical(1))
     thr = lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=30.0)
     tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
     _check_end_to_end(lcf, ctx, iq, mask, 8, 8, thr, tol, 0.1, f"clinical median prec={prec}", precision=prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_clinical_median_rule_paper_beta(lcf, ctx, prec):
+    # method 3 (Eq. 7) at the scaling factor of the paper's Fig. 2a example, fitted
+    # to the paper's data: here it cuts 35 to 52 components deep, inside the noise
+    # floor, where the eigen-gap at the cut is about 3e-10 lambda_1, so the
+    # filtered IQ follows the rounding of the bulk Gram C'^H C' over that gap
+    # (the FP32 pass-2 Gram sums its MFMA batches in FP64 for this)
+    iq, mask = synth.make_packet(synth.spec_clinical(1))
+    thr = lcf.Threshold(cut=lcf.CUT_MEDIAN, beta_median=1.43)
+    tol = 1e-5 if prec == lcf.PREC_FP32 else 1e-3
+    _check_end_to_end(lcf, ctx, iq, mask, 8, 8, thr, tol, 0.1, f"clinical median beta=1.43 prec={prec}",
+                      precision=prec)
 
 
 def test_median_rule_odd_frame_count_sigmoid(lcf, ctx):

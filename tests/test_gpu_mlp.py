@@ -149,7 +149,7 @@ def test_filter_with_mlp_weights(lcf, ctx):
     e_fro = rel_fro(io.cpu().numpy(), res["iq_out"])
     emax, _, _, _ = pd_db_error(pd.cpu().numpy(), res["pd"], mask)
     _say(f"   rel_fro={e_fro:.2e} pd_db={emax:.2e}")
-    assert e_fro <= 1e-4 and emax <= 0.1
+    assert e_fro <= 1e-5 and emax <= 0.1
 
 
 def test_mlp_fallback_for_other_nt(lcf, ctx):
