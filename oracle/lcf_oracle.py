@@ -31,7 +31,12 @@ whose slope magnitude is at most its threshold; the window of Eq. 10 is the half
 of a Gaussian window of length 2 Nt - 1 with MATLAB's default width (alpha 2.5)
 that starts at its peak, eigenvalues are floored at lambda_1 2^-52 there, and
 "normalised" scales the weights to a maximum of 1; the combined filtered IQ is
-sum_d C_hat_d / sum_d w_d.
+sum_d C_hat_d / sum_d w_d. Method 4 (Eq. 8) takes the left singular vectors
+u_i = C_w v_i / sigma_i of the windowed subset (u_i = 0 where sigma_i = 0), the
+images I_T(k) = sum of |u_i| over i = k-fn+1..k and I_B(k) = over i = k+1..k+fn
+(fn = 5, unit weights), their normalised cross-correlation as Eq. 8 writes it
+(no mean removed), over 1-based k in [fn, Nt - fn] where both sums exist, and k
+= the smallest index of the minimum; a pair of zero images gives no value there.
 """
 from __future__ import annotations
 
@@ -41,7 +46,8 @@ from typing import Optional
 
 import numpy as np
 
-CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER = 0, 1, 2, 3, 4, 5, 6
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER, CUT_NCC = 0, 1, 2, 3, 4, 5, 6, 7
+NCC_FN = 5     # singular vectors on each side of the cut (method 4: fn = 5)
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 
@@ -216,19 +222,52 @@ def median_k(lam: np.ndarray, beta: float) -> int:
     return int(np.count_nonzero(s > t))
 
 
+def ncc_curve(cw: np.ndarray, lam: np.ndarray, v: np.ndarray, fn: int = NCC_FN) -> np.ndarray:
+    """Method 4 (Eq. 8): normalised cross-correlation of the tissue image
+    I_T(k) = sum_{i=k-fn+1..k} |u_i| and the blood image I_B(k) = sum_{i=k+1..k+fn} |u_i|,
+    with the left singular vectors u_i = C_w v_i / sigma_i, sigma_i^2 = lambda_i
+    (C V = U D). Entry k-1 holds 1-based k in [fn, Nt - fn]; NaN elsewhere and
+    where an image is zero."""
+    lam = np.asarray(lam, dtype=np.float64)
+    nt = lam.shape[0]
+    sig = np.sqrt(np.maximum(lam, 0.0))
+    u = cw @ v
+    inv = np.where(sig > 0.0, 1.0 / np.where(sig > 0.0, sig, 1.0), 0.0)
+    a = np.abs(u) * inv[None, :]
+    curve = np.full(nt, np.nan)
+    for k in range(fn, nt - fn + 1):
+        it = a[:, k - fn:k].sum(axis=1)
+        ib = a[:, k:k + fn].sum(axis=1)
+        den = math.sqrt(float(it @ it)) * math.sqrt(float(ib @ ib))
+        if den > 0.0:
+            curve[k - 1] = float(it @ ib) / den
+    return curve
+
+
+def ncc_k(curve: np.ndarray):
+    """k = the smallest 1-based index of the minimum of Eq. 8's curve; 0 and the
+    NONPOSITIVE flag when no k has a value."""
+    if not np.any(np.isfinite(curve)):
+        return 0, FLAG_NONPOSITIVE
+    c = np.where(np.isfinite(curve), curve, np.inf)
+    return int(np.argmin(c)) + 1, 0
+
+
 def sigmoid_weights(nt: int, k: int, beta: float) -> np.ndarray:
     """Soft weights of Eq. 9: w_i = 1 / (1 + exp(-beta (i - k))), i = 1..Nt."""
     i = np.arange(1, nt + 1, dtype=np.float64)
     return 1.0 / (1.0 + np.exp(-beta * (i - k)))
 
 
-def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
+def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0, ncc=None):
     """Eigencomponent weights of one subset.
 
-    FIXED_K / KNEE / MEDIAN / SLOPE choose k (Eq. 4 hard cut, Eq. 6 curvature,
-    Eq. 7 median, the slope rule of Fig. 2c); the shape is a
-    hard 0/1 cut (Eq. 4) or the sigmoid of Eq. 9 centred on k. EXPLICIT takes
-    the caller's weights; MLP calls ``thr.mlp(lam)``. Returns (w, k, curv, flags)."""
+    FIXED_K / KNEE / MEDIAN / SLOPE / NCC choose k (Eq. 4 hard cut, Eq. 6
+    curvature, Eq. 7 median, the slope rule of Fig. 2c, Eq. 8 with its curve
+    ``ncc`` from ``ncc_curve``); the shape is a hard 0/1 cut (Eq. 4) or the
+    sigmoid of Eq. 9 centred on k (method 5 with the NCC cut). EXPLICIT takes
+    the caller's weights; MLP calls ``thr.mlp(lam)``. Returns (w, k, curv, flags);
+    curv is the Eq. 6 or Eq. 8 curve where the rule has one."""
     nt = lam.shape[0]
     curv = np.zeros(nt)
     flags = 0
@@ -248,6 +287,9 @@ def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0):
         k = median_k(lam, thr.beta_median)
     elif thr.cut == CUT_SLOPE:
         k, flags = slope_k(lam, thr.slope_thr)
+    elif thr.cut == CUT_NCC:
+        curv = np.asarray(ncc, dtype=np.float64)
+        k, flags = ncc_k(curv)
     else:
         raise ValueError("unknown cut")
     if thr.shape == SHAPE_HARD:
@@ -291,7 +333,8 @@ def filter_packet(iq: np.ndarray, gy: int, gx: int, thr: Threshold,
         cw = wv[:, None] * cfull[rows]                         # Eq. 11
         r = covariance(cw)                                     # Eq. 12
         lam, v = evd(r)                                        # Eq. 2
-        w, k, curv, flags = rule_weights(lam, thr, d)
+        ncc = ncc_curve(cw, lam, v) if thr.cut == CUT_NCC else None   # Eq. 8
+        w, k, curv, flags = rule_weights(lam, thr, d, ncc)
         p = projector(v, w)
         chat = cw @ p                                          # Eq. 4
         if check_eq5:

@@ -434,3 +434,77 @@ def test_generator_powers():
     spec0 = synth.PacketSpec(64, 64, 16, -300.0, 0.0, (), seed=5)
     iq0, _ = synth.make_packet(spec0)
     assert abs(10 * np.log10(np.mean(np.abs(iq0) ** 2)) + 10.0) < 0.2
+
+
+# ------------------------------------------------------------------ method 4 (Eq. 8)
+
+def _unitary(rng, n):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+
+
+def test_ncc_rule_hand_worked():
+    """Eq. 8 on a constructed case whose |u_i| are known exactly (tests/golden/ncc_hand.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "ncc_hand.json")))
+    h4 = np.array([[1, 1, 1, 1], [1, -1, 1, -1], [1, 1, -1, -1], [1, -1, -1, 1]], dtype=float) / 2.0
+    u = np.zeros((8, 6), dtype=complex)
+    u[0:4, 0:3] = h4[:, 0:3]
+    u[4:8, 3:6] = h4[:, 0:3] * np.exp(1j * np.array([0.3, 1.1, 2.0]))[None, :]
+    sig = np.array(g["sigma"], dtype=float)
+    v = _unitary(np.random.default_rng(8), 6)
+    c = (u * sig[None, :]) @ v.conj().T
+    lam, vv = O.evd(O.covariance(c))
+    curve = O.ncc_curve(c, lam, vv, fn=g["fn"])
+    ref = np.array([np.nan if x is None else x for x in g["curve"]])
+    assert np.array_equal(np.isnan(curve), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.allclose(curve[ok], ref[ok], atol=1e-12)
+    k, fl = O.ncc_k(curve)
+    assert (k, fl) == (g["k"], 0)
+
+
+def test_ncc_rule_disjoint_supports_and_svd():
+    """Tissue components on one half of the pixels, blood on the other: the
+    curve is exactly 0 at the cut between the groups (fn = 5), and it equals the
+    curve built from numpy's SVD left singular vectors."""
+    rng = np.random.default_rng(9)
+    npix, nt, ntis = 200, 20, 8
+    ua, _ = np.linalg.qr(rng.standard_normal((100, ntis)) + 1j * rng.standard_normal((100, ntis)))
+    ub, _ = np.linalg.qr(rng.standard_normal((100, nt - ntis)) + 1j * rng.standard_normal((100, nt - ntis)))
+    u = np.zeros((npix, nt), dtype=complex)
+    u[:100, :ntis] = ua
+    u[100:, ntis:] = ub
+    sig = np.sort(rng.uniform(1.0, 2.0, nt))[::-1] * np.r_[np.full(ntis, 100.0), np.ones(nt - ntis)]
+    c = (u * sig[None, :]) @ _unitary(rng, nt).conj().T
+    lam, v = O.evd(O.covariance(c))
+    curve = O.ncc_curve(c, lam, v)
+    assert abs(curve[ntis - 1]) <= 1e-12
+    assert np.all(curve[[i for i in range(O.NCC_FN - 1, nt - O.NCC_FN) if i != ntis - 1]] > 1e-3)
+    assert O.ncc_k(curve) == (ntis, 0)
+    # the same curve from the SVD's left singular vectors (Eq. 3, C = U D V^H)
+    us, s, _ = np.linalg.svd(c, full_matrices=False)
+    a = np.abs(us)
+    ref = np.full(nt, np.nan)
+    for k in range(O.NCC_FN, nt - O.NCC_FN + 1):
+        it, ib = a[:, k - O.NCC_FN:k].sum(1), a[:, k:k + O.NCC_FN].sum(1)
+        ref[k - 1] = it @ ib / np.sqrt((it @ it) * (ib @ ib))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(np.isnan(curve), ~ok) and np.allclose(curve[ok], ref[ok], atol=1e-10)
+
+
+def test_ncc_rule_shapes_and_degenerate():
+    """Method 5 is the sigmoid of Eq. 9 centred on the Eq. 8 cut; a spectrum
+    with no valid k (an all-zero subset) keeps every component and is flagged."""
+    curve = np.full(16, np.nan)
+    curve[4:11] = [0.9, 0.5, 0.2, 0.2, 0.6, 0.7, 0.8]
+    lam = np.geomspace(1e6, 1.0, 16)
+    w, k, cv, fl = O.rule_weights(lam, O.Threshold(cut=O.CUT_NCC, shape=O.SHAPE_SIGMOID, beta_sigmoid=2.0),
+                                  ncc=curve)
+    assert k == 7 and fl == 0                       # first of the two equal minima
+    assert np.allclose(w, O.sigmoid_weights(16, 7, 2.0), atol=0)
+    w, k, _, _ = O.rule_weights(lam, O.Threshold(cut=O.CUT_NCC, shape=O.SHAPE_HARD), ncc=curve)
+    assert np.array_equal(w, (np.arange(1, 17) > 7).astype(float))
+    z = np.zeros((30, 12), dtype=complex)
+    lam0, v0 = O.evd(O.covariance(z))
+    c0 = O.ncc_curve(z, lam0, v0)
+    assert np.all(np.isnan(c0)) and O.ncc_k(c0) == (0, O.lcf_oracle.FLAG_NONPOSITIVE)
