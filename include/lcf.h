@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define LCF_ABI_VERSION 4
+#define LCF_ABI_VERSION 5
 
 typedef enum {
     LCF_OK = 0,
@@ -61,7 +61,9 @@ typedef enum {
     LCF_ERR_DEVICE = 4,          /* a HIP call failed                                   */
     LCF_ERR_NONFINITE_INPUT = 5, /* reported by lcf_sync: NaN/Inf reached a covariance  */
     LCF_ERR_NO_CONVERGENCE = 6,  /* reported by lcf_sync: Jacobi hit the sweep cap      */
-    LCF_ERR_MODEL = 7            /* MLP weights missing or checkpoint corrupt           */
+    LCF_ERR_MODEL = 7,           /* MLP weights missing or checkpoint corrupt           */
+    LCF_ERR_SCRATCH_LIMIT = 8    /* lcf_filter_noalloc: the call's workspace exceeds
+                                    LCF_NOALLOC_SCRATCH_BYTES                           */
 } lcf_status;
 
 /* Arithmetic of the covariance and reprojection GEMMs. Both keep FP64 for the
@@ -216,6 +218,28 @@ lcf_status lcf_validate(const lcf_geometry* geo, const lcf_threshold* thr, int32
 lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr,
                       int32_t precision, const void* iq, void* iq_out, float* pd,
                       const lcf_diag* diag, void* stream);
+
+/* Allocation-free variant of lcf_filter, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels, results and errors as lcf_filter, except that the
+ * plan descriptors, the workspace and the network activations of the call live
+ * in one fixed device block of LCF_NOALLOC_SCRATCH_BYTES that the library
+ * holds per device for the life of the process (set up by lcf_create), and
+ * that the call allocates no device or pinned host memory: it never grows the
+ * context's arena, never autotunes (a choice already stored in the context is
+ * used) and never captures a graph. A call whose workspace does not fit
+ * returns LCF_ERR_SCRATCH_LIMIT before any launch (a 256 x 192 x 128 packet
+ * with an 8 x 8 grid fits; a 512 x 256 x 128 packet with a 16 x 16 grid does
+ * not). Plan uploads are staged in the context's host memory (C++ heap, grown
+ * once to the largest plan). All calls on one device share the block and
+ * every call overwrites it: calls that may overlap on one device (other
+ * streams, other contexts, other threads) race and must be serialised by the
+ * caller; calls on one stream are ordered. Refused under stream capture like
+ * lcf_filter. */
+#define LCF_NOALLOC_SCRATCH_BYTES (192u * 1024u * 1024u)
+lcf_status lcf_filter_noalloc(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr,
+                              int32_t precision, const void* iq, void* iq_out, float* pd,
+                              const lcf_diag* diag, void* stream);
 
 /* Filter n packets of possibly different shapes and grids in one batched pass
  * (the parallel processing of subsets that the Discussion leaves for future work).

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblcf.so")
 
 PREC_FP32, PREC_BF16X3 = 0, 1
 CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER = 0, 1, 2, 3, 4, 5, 6
-ABI_VERSION = 4
+ABI_VERSION = 5
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 OPT_SCHEDULE, OPT_MAX_SWEEPS, OPT_USE_GRAPH, OPT_SUBSPACE_IT, OPT_STAGE_TIMING, OPT_AUTOTUNE, OPT_EVD = 1, 2, 3, 4, 5, 6, 7
@@ -27,7 +27,9 @@ STAGES = ["windows", "gram1", "gram1_reduce", "tissue", "gram2", "gram2_reduce",
 FLAG_NONPOSITIVE, FLAG_NONFINITE, FLAG_NO_CONVERGE, FLAG_MLP_FALLBACK, FLAG_EVD_JACOBI = 1, 2, 4, 8, 16
 
 STATUS = {0: "LCF_OK", 1: "LCF_ERR_INVALID_ARG", 2: "LCF_ERR_UNSUPPORTED", 3: "LCF_ERR_OUT_OF_MEMORY",
-          4: "LCF_ERR_DEVICE", 5: "LCF_ERR_NONFINITE_INPUT", 6: "LCF_ERR_NO_CONVERGENCE", 7: "LCF_ERR_MODEL"}
+          4: "LCF_ERR_DEVICE", 5: "LCF_ERR_NONFINITE_INPUT", 6: "LCF_ERR_NO_CONVERGENCE", 7: "LCF_ERR_MODEL",
+          8: "LCF_ERR_SCRATCH_LIMIT"}
+NOALLOC_SCRATCH_BYTES = 192 * 1024 * 1024
 
 
 class LcfError(RuntimeError):
@@ -94,6 +96,7 @@ def load():
     lib.lcf_validate.argtypes = [C.POINTER(Geometry), C.POINTER(ThresholdC), i32]
     lib.lcf_filter.argtypes = [vp, C.POINTER(Geometry), C.POINTER(ThresholdC), i32, vp, vp, vp,
                                C.POINTER(DiagC), vp]
+    lib.lcf_filter_noalloc.argtypes = lib.lcf_filter.argtypes
     lib.lcf_filter_batch.argtypes = [vp, i32, C.POINTER(Geometry), C.POINTER(ThresholdC), i32,
                                      C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     lib.lcf_heevd_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
@@ -111,7 +114,7 @@ def load():
     lib.lcf_tune_load.argtypes = [vp, C.c_char_p]
     lib.lcf_status_str.argtypes = [i32]
     lib.lcf_status_str.restype = C.c_char_p
-    for name in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter",
+    for name in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter", "lcf_filter_noalloc",
                  "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version",
                  "lcf_stage_time",
                  "lcf_mlp_init", "lcf_mlp_set_params", "lcf_mlp_get_params", "lcf_mlp_get_grads", "lcf_mlp_save",
@@ -200,9 +203,11 @@ class Context:
 
     def filter(self, iq, gy: int, gx: int, thr: Threshold, precision: int = PREC_FP32,
                sigma_frac: float = 1.0 / 3.0, trunc_sigmas: float = 6.0, iq_out: bool = True,
-               diag: bool = False, diag_cov: bool = False, explicit_w=None, out=None):
+               diag: bool = False, diag_cov: bool = False, explicit_w=None, out=None, noalloc: bool = False):
         """Filter one packet ``iq`` (torch complex64 on the GPU, [nt][ny][nx]).
 
+        ``noalloc`` calls ``lcf_filter_noalloc`` (the library's fixed device
+        block instead of its arena; pass ``out`` to allocate nothing here either).
         Returns (iq_out or None, pd, diag dict or None)."""
         import torch
         assert iq.is_cuda and iq.dtype == torch.complex64 and iq.is_contiguous() and iq.dim() == 3
@@ -234,9 +239,10 @@ class Context:
                 dg["eigvecs"] = torch.empty((nd, nt, nt), dtype=torch.complex128, device=dev)
             dgc = DiagC(*(_ptr(dg.get(n)) for n in ("eigvals", "weights", "k", "sweeps", "flags", "alpha",
                                                     "cov", "eigvecs", "rank")))
-        st = load().lcf_filter(self._h, C.byref(geo), C.byref(tc), precision, _ptr(iq), _ptr(io), _ptr(pd),
-                               C.byref(dgc) if dgc is not None else None, _stream())
-        _check(st, "lcf_filter")
+        fn = load().lcf_filter_noalloc if noalloc else load().lcf_filter
+        st = fn(self._h, C.byref(geo), C.byref(tc), precision, _ptr(iq), _ptr(io), _ptr(pd),
+                C.byref(dgc) if dgc is not None else None, _stream())
+        _check(st, "lcf_filter_noalloc" if noalloc else "lcf_filter")
         return io, pd, dg
 
     def filter_batch(self, iqs: Sequence, grids: Sequence, thr: Threshold, precision: int = PREC_FP32,

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,7 +18,34 @@
 
 using namespace lcf;
 
+// Fixed device block of the allocation-free entry point (lcf_filter_noalloc):
+// descriptors, workspace and network activations of one call. Each device the
+// library runs on holds its own copy until the process ends. In host code this
+// name is only a stand-in for the symbol: its device address is taken once per
+// device with hipGetSymbolAddress (lcf_create) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[LCF_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;   // device -> address of `scratch` on that device
+
+// Called with `device` current: look up (once per device) the address of the
+// fixed block there.
+lcf_status init_scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return LCF_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return LCF_ERR_DEVICE;
+    g_scratch_ptr[device] = (char*)ptr;
+    return LCF_OK;
+}
+
+char* scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
 
 // Padded frame classes. Up to 128 frames they are exactly the sizes of the
 // tridiagonal EVD's 2-, 4-, 6- and 8-wave shapes (16 columns per wave), which
@@ -289,6 +317,11 @@ struct lcf_context {
     long long mlp_step = 0;
     float* mlp_scratch = nullptr;
     size_t mlp_scratch_cap = 0;     // floats
+    // allocation-free entry point: pageable host staging of its plan uploads,
+    // free again once fixed_staged completes
+    std::vector<char> fixed_host;
+    hipEvent_t fixed_staged = nullptr;
+    bool fixed_pending = false;
 };
 
 namespace {
@@ -591,7 +624,7 @@ lcf_status run_stages(lcf_context* c, const Workspace& ws, const lcf_threshold* 
 }
 
 lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold* thr, int prec, int nt_max,
-                       int all_vectors, hipStream_t st) {
+                       int all_vectors, float* mlp_scratch, hipStream_t st) {
     const bool mlp = thr->cut == LCF_CUT_MLP;
     RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
                   thr->knee_max_frac, thr->beta_sigmoid, thr->beta_median, thr->slope_thr, thr->beta_power};
@@ -600,8 +633,8 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     if (mlp) {
         STAGE(c, LCF_STAGE_MLP, st);
         // scratch laid out as [valid ints][z | h1 a1 h2 a2 | w]; sized by the caller
-        int* valid = (int*)c->mlp_scratch;
-        float* z = c->mlp_scratch + align_up((size_t)ws.S, 64);
+        int* valid = (int*)mlp_scratch;
+        float* z = mlp_scratch + align_up((size_t)ws.S, 64);
         float* act = z + (size_t)ws.S * MLP_NT;
         float* wout = act + (size_t)ws.S * 4 * MLP_H;
         if (ws.ntp == MLP_NT) {
@@ -621,10 +654,22 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
 // views set up.
 struct Staged {
     Workspace ws;
+    char* base = nullptr;          // device block holding descriptors and workspace
     size_t seq_off = 0;
+    float* mlp_scratch = nullptr;  // network activations (learned weights only)
 };
 
-lcf_status stage_group(lcf_context* c, const Plan& pl, const lcf_threshold* thr, hipStream_t st, Staged& sg) {
+// A fixed device block that a call must fit in (the allocation-free entry
+// point): nothing is grown, plans that do not fit are refused.
+struct FixedArena {
+    char* base;
+    size_t cap;
+};
+
+
+
+lcf_status stage_group(lcf_context* c, const Plan& pl, const lcf_threshold* thr, hipStream_t st, Staged& sg,
+                       const FixedArena* fx = nullptr) {
     Layout L = make_layout(pl);
     // sequential schedule: per-subset chunk tables appended to the host block
     const size_t seq_off = L.host_bytes;
@@ -636,11 +681,29 @@ lcf_status stage_group(lcf_context* c, const Plan& pl, const lcf_threshold* thr,
     const size_t shift = host_total - L.host_bytes;
     for (size_t* p = &D.off_wtab; p <= &D.off_breal; ++p) *p += shift;
     D.total += shift;
-    lcf_status e = ensure_device(c, D.total);
-    if (e != LCF_OK) return e;
-    e = ensure_host(c, host_total);
-    if (e != LCF_OK) return e;
-    char* h = c->hbuf;
+    const size_t mlp_floats = thr->cut == LCF_CUT_MLP
+                                  ? align_up(pl.sub.size(), 64) + mlp_infer_scratch_floats((int)pl.sub.size())
+                                  : 0;
+    char* h = nullptr;
+    char* base = nullptr;
+    if (fx) {
+        // everything, network activations included, inside the caller-visible fixed block
+        if (D.total + mlp_floats * sizeof(float) > fx->cap) return LCF_ERR_SCRATCH_LIMIT;
+        if (c->fixed_pending) {
+            if (hipEventSynchronize(c->fixed_staged) != hipSuccess) return LCF_ERR_DEVICE;
+            c->fixed_pending = false;
+        }
+        if (c->fixed_host.size() < host_total) c->fixed_host.resize(host_total);
+        h = c->fixed_host.data();
+        base = fx->base;
+    } else {
+        lcf_status e = ensure_device(c, D.total);
+        if (e != LCF_OK) return e;
+        e = ensure_host(c, host_total);
+        if (e != LCF_OK) return e;
+        h = c->hbuf;
+        base = c->dbuf;
+    }
     std::memcpy(h + L.off_sub, pl.sub.data(), pl.sub.size() * sizeof(SubsetDesc));
     std::memcpy(h + L.off_chunks, pl.chunks.data(), pl.chunks.size() * sizeof(ChunkDesc));
     std::memcpy(h + L.off_cbeg, pl.chunk_begin.data(), pl.chunk_begin.size() * sizeof(int));
@@ -656,15 +719,25 @@ lcf_status stage_group(lcf_context* c, const Plan& pl, const lcf_threshold* thr,
             cb[2 * s + 1] = pl.chunk_begin[s + 1] - pl.chunk_begin[s];
         }
     }
-    HIPCHK(hipMemcpyAsync(c->dbuf, h, host_total, hipMemcpyHostToDevice, st));
-    HIPCHK(hipEventRecord(c->staged, st));
-    c->staged_pending = true;
-    sg.ws = make_ws(c->dbuf, D, pl, thr->cut == LCF_CUT_EXPLICIT ? thr->explicit_w : nullptr);
+    HIPCHK(hipMemcpyAsync(base, h, host_total, hipMemcpyHostToDevice, st));
+    if (fx) {
+        HIPCHK(hipEventRecord(c->fixed_staged, st));
+        c->fixed_pending = true;
+    } else {
+        HIPCHK(hipEventRecord(c->staged, st));
+        c->staged_pending = true;
+    }
+    sg.ws = make_ws(base, D, pl, thr->cut == LCF_CUT_EXPLICIT ? thr->explicit_w : nullptr);
+    sg.base = base;
     sg.seq_off = seq_off;
     if (thr->cut == LCF_CUT_MLP) {
-        const size_t need = align_up(pl.sub.size(), 64) + mlp_infer_scratch_floats((int)pl.sub.size());
-        e = ensure_mlp_scratch(c, need);
-        if (e != LCF_OK) return e;
+        if (fx) {
+            sg.mlp_scratch = (float*)(base + D.total);
+        } else {
+            lcf_status e = ensure_mlp_scratch(c, mlp_floats);
+            if (e != LCF_OK) return e;
+            sg.mlp_scratch = c->mlp_scratch;
+        }
     }
     return LCF_OK;
 }
@@ -676,21 +749,21 @@ lcf_status run_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf
     lcf_status e;
     if (c->schedule == 1) {
         // the paper's loop: one subset at a time through every per-subset stage
-        const ChunkDesc* dch = (const ChunkDesc*)(c->dbuf + sg.seq_off);
-        const int* dcb = (const int*)(c->dbuf + sg.seq_off + pl.chunks.size() * sizeof(ChunkDesc));
+        const ChunkDesc* dch = (const ChunkDesc*)(sg.base + sg.seq_off);
+        const int* dcb = (const int*)(sg.base + sg.seq_off + pl.chunks.size() * sizeof(ChunkDesc));
         for (int s = 0; s < (int)pl.sub.size(); ++s) {
             const int cb0 = pl.chunk_begin[s], nch = pl.chunk_begin[s + 1] - cb0;
             Workspace v = subset_view(ws, s, dch + cb0, dcb + 2 * s, nch);
             double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
             e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
             if (e != LCF_OK) return e;
-            e = run_stages2(c, v, thr, prec, pl.sub[s].nt, diag && diag->eigvecs ? 1 : 0, st);
+            e = run_stages2(c, v, thr, prec, pl.sub[s].nt, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, st);
             if (e != LCF_OK) return e;
         }
     } else {
         e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
         if (e != LCF_OK) return e;
-        e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, st);
+        e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, st);
         if (e != LCF_OK) return e;
     }
     { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
@@ -760,7 +833,7 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
 
 // Filter a list of packets. diag applies to a single packet call only.
 lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const lcf_threshold* thr, int prec,
-                          const lcf_diag* diag, hipStream_t st) {
+                          const lcf_diag* diag, hipStream_t st, const FixedArena* fx = nullptr) {
     if (!c) return LCF_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return LCF_ERR_DEVICE;
     // A call made while the caller captures the stream is refused: the plan
@@ -780,7 +853,7 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
                    (trows_max(kv.first) >= 4 && prec == LCF_PREC_FP32) ? 1 : 0);
         const std::string tkey = tune_key(pl, prec, c->schedule);
         auto tit = c->tuned.find(tkey);
-        if (tit == c->tuned.end() && c->autotune) {
+        if (tit == c->tuned.end() && c->autotune && !fx) {
             lcf_status e = tune_group(c, in, kv.second, thr, prec, st, tkey);
             if (e != LCF_OK) return e;
             tit = c->tuned.find(tkey);
@@ -795,12 +868,14 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
             }
         }
         Staged sg;
-        lcf_status e = stage_group(c, pl, thr, st, sg);
+        lcf_status e = stage_group(c, pl, thr, st, sg, fx);
         if (e != LCF_OK) return e;
         // Launch chain of the group, optionally captured once into a hipGraph and
-        // replayed for later calls with the same plan (not on the null stream, and
-        // not while stage timing is on).
-        const bool graph = c->use_graph && !c->timing && st != nullptr;
+        // replayed for later calls with the same plan (not on the null stream, not
+        // while stage timing is on, and not for the fixed block, whose chains are
+        // launched directly).
+        const bool graph = c->use_graph && !c->timing && st != nullptr && !fx;
+
         std::string key;
         if (graph) {
             key = graph_key(c, pl, in, kv.second, thr, prec, diag);
@@ -842,7 +917,12 @@ lcf_status lcf_create(int32_t device, lcf_context** out) {
     if (hipSetDevice(device) != hipSuccess) return LCF_ERR_DEVICE;
     lcf_context* c = new lcf_context();
     c->device = device;
+    if (init_scratch_ptr(device) != LCF_OK) {
+        delete c;
+        return LCF_ERR_DEVICE;
+    }
     if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fixed_staged, hipEventDisableTiming) != hipSuccess ||
         hipMalloc((void**)&c->sticky, sizeof(int)) != hipSuccess ||
         hipMemset(c->sticky, 0, sizeof(int)) != hipSuccess) {
         delete c;
@@ -865,6 +945,7 @@ lcf_status lcf_destroy(lcf_context* c) {
     if (c->hbuf) hipHostFree(c->hbuf);
     if (c->sticky) hipFree(c->sticky);
     if (c->staged) hipEventDestroy(c->staged);
+    if (c->fixed_staged) hipEventDestroy(c->fixed_staged);
     delete c;
     return LCF_OK;
 }
@@ -922,6 +1003,20 @@ lcf_status lcf_filter(lcf_context* ctx, const lcf_geometry* geo, const lcf_thres
     if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
     std::vector<PacketIn> in{PacketIn{*geo, iq, iq_out, pd, 0}};
     return filter_packets(ctx, in, thr, precision, diag, (hipStream_t)stream);
+}
+
+lcf_status lcf_filter_noalloc(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr,
+                              int32_t precision, const void* iq, void* iq_out, float* pd, const lcf_diag* diag,
+                              void* stream) {
+    if (!ctx || !iq || !pd) return LCF_ERR_INVALID_ARG;
+    lcf_status e = lcf_validate(geo, thr, precision);
+    if (e != LCF_OK) return e;
+    if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
+    char* base = scratch_ptr(ctx->device);
+    if (!base) return LCF_ERR_DEVICE;
+    const FixedArena fx{base, (size_t)LCF_NOALLOC_SCRATCH_BYTES};
+    std::vector<PacketIn> in{PacketIn{*geo, iq, iq_out, pd, 0}};
+    return filter_packets(ctx, in, thr, precision, diag, (hipStream_t)stream, &fx);
 }
 
 lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo, const lcf_threshold* thr,
@@ -1189,6 +1284,7 @@ const char* lcf_status_str(lcf_status s) {
         case LCF_ERR_NONFINITE_INPUT: return "non-finite value reached a covariance";
         case LCF_ERR_NO_CONVERGENCE: return "Jacobi eigen-solver hit the sweep cap";
         case LCF_ERR_MODEL: return "MLP weights missing or corrupt";
+        case LCF_ERR_SCRATCH_LIMIT: return "workspace of the call exceeds the fixed block of lcf_filter_noalloc";
     }
     return "unknown status";
 }
