@@ -161,14 +161,70 @@ def _leg(lcf, stream, iqs, grids, thr, prec, steps, schedule=0, graph=1, autotun
             "device_status": st}
 
 
-def extra_workloads(lcf, stream, names, stream_packets):
-    """Fast / plain / batched-FP32 legs on the clinical shape and on the uneven stream."""
+def slide_workload(lcf, stream, spec, grid, thr, mlp, hop=5, pushes=12):
+    """Sliding packets (the Experimental Studies section's hop of 5 frames): one
+    recording of nt + hop (pushes + 1) frames filtered packet after packet with
+    the covariance carried between pushes (lcf_stream_push), against the same
+    packets filtered one call each (lcf_filter with graph replay), split BF16."""
+    import dataclasses
+    import torch
+    import synth
+    nt = spec.nt
+    rec_spec = dataclasses.replace(spec, nt=nt + hop * (pushes + 1))
+    rec, _ = synth.make_packet(rec_spec)
+    gy, gx = grid
+    out = {"workload": f"sliding packets {spec.ny}x{spec.nx}x{nt}, hop {hop}, {gy}x{gx} Gaussian windows, "
+                       f"{'learned weights' if mlp else 'knee + sigmoid rule'}, split-BF16",
+           "hop": hop, "pushes": pushes}
+    with torch.cuda.stream(stream):
+        rt = torch.from_numpy(rec).cuda()
+        del rec
+        ob = (torch.empty((nt, spec.ny, spec.nx), dtype=torch.complex64, device=rt.device),
+              torch.empty((spec.ny, spec.nx), dtype=torch.float32, device=rt.device))
+        for leg in ("stream", "per_packet"):
+            ctx = lcf.Context(0, use_graph=1)
+            if mlp:
+                ctx.mlp_load(mlp)
+            sm = lcf.Stream(ctx, spec.ny, spec.nx, nt, gy, gx, thr, precision=lcf.PREC_BF16X3) \
+                if leg == "stream" else None
+            pos = [0]
+
+            def run():
+                p = pos[0]
+                pk = rt[p * hop:p * hop + nt]
+                if sm is not None:
+                    sm.push(pk, hop, out=ob)
+                else:
+                    ctx.filter(pk, gy, gx, thr, precision=lcf.PREC_BF16X3, out=ob)
+                pos[0] = p + 1
+            run()                                   # first push: every column; plans, graph
+            torch.cuda.synchronize()
+            total, per = _timed_steps(run, pushes, stream)
+            st = ctx.sync()
+            if sm is not None:
+                sm.close()
+            ctx.close()
+            ms = total / pushes
+            out[leg] = {"ms_per_packet": ms, "packets_per_s": 1e3 / ms, "frames_per_s": nt * 1e3 / ms,
+                        "step_ms": _dist(per), "device_status": st}
+        del rt
+        torch.cuda.empty_cache()
+    out["stream_over_per_packet"] = out["stream"]["packets_per_s"] / out["per_packet"]["packets_per_s"]
+    return out
+
+
+def extra_workloads(lcf, stream, names, stream_packets, slide_args=None):
+    """Fast / plain / batched-FP32 legs on the clinical shape and on the uneven
+    stream; sliding packets at the main workload's shape."""
     import multiprocessing as mp
     import torch
     import synth
     out = {}
     rule = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
     for name in names:
+        if name == "slide" and slide_args is not None:
+            out[name] = slide_workload(lcf, stream, *slide_args)
+            continue
         if name == "clinical":
             specs = [synth.spec_clinical(p) for p in range(4)]
             grids = [(8, 8)] * 4
@@ -261,8 +317,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="fast configuration with the default plan sizes")
     ap.add_argument("--ablation-steps", type=int, default=3, help="0 skips the ablation legs")
-    ap.add_argument("--extra", default="clinical,stream",
-                    help="comma list of extra workloads (clinical, stream); empty skips them")
+    ap.add_argument("--extra", default="clinical,stream,slide",
+                    help="comma list of extra workloads (clinical, stream, slide); empty skips them")
     ap.add_argument("--stream-packets", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM byte counters)")
@@ -309,12 +365,20 @@ def main():
         def step_fast():
             fast.filter_batch(iqs, grids, thr_fast, precision=lcf.PREC_BF16X3, outs=outs_f)
 
-        # per-subset ranks and flags of packet 0
-        _, _, dg = fast.filter(iqs[0], gy, gx, thr_fast, precision=lcf.PREC_BF16X3, diag=True)
+        # per-subset ranks, flags and the learned weights' gate over the step's packets
+        diags = []
+        for iq in iqs:
+            _, _, dg = fast.filter(iq, gy, gx, thr_fast, precision=lcf.PREC_BF16X3, diag=True)
+            diags.append({k: v.cpu().numpy() for k, v in dg.items()})
         torch.cuda.synchronize()
-        sweeps = dg["sweeps"].cpu().numpy()
-        ranks = dg["rank"].cpu().numpy()
-        fallback = float(((dg["flags"] & lcf.FLAG_MLP_FALLBACK) != 0).float().mean().item())
+        sweeps = np.concatenate([d["sweeps"] for d in diags])
+        ranks = np.concatenate([d["rank"] for d in diags])
+        fallback = float(np.mean(np.concatenate([(d["flags"] & lcf.FLAG_MLP_FALLBACK) != 0 for d in diags])))
+        gate_q = None
+        if use_mlp:
+            gv = np.concatenate([d["mlp_gate"] for d in diags])
+            gate_q = {"p10": float(np.quantile(gv, 0.1)), "median": float(np.median(gv)),
+                      "p90": float(np.quantile(gv, 0.9)), "threshold_db": 0.1}
 
         for _ in range(args.warmup):
             step_fast()
@@ -427,7 +491,8 @@ def main():
     extra = {}
     names = [x for x in args.extra.split(",") if x]
     if names:
-        extra = extra_workloads(lcf, stream, names, args.stream_packets)
+        extra = extra_workloads(lcf, stream, names, args.stream_packets,
+                                slide_args=(specs[0], (gy, gx), thr_fast, args.mlp if use_mlp else None))
 
     cpu = None
     parity = {}
@@ -437,16 +502,26 @@ def main():
         from oracle import mlp as M
         if use_mlp:
             params = M.unflatten(fast.mlp_get_params())
-            othr_f = O.Threshold(cut=O.CUT_MLP, mlp=lambda lam: M.forward(params, M.features(lam))[0][0])
+            othr_f = O.Threshold(cut=O.CUT_MLP, shape=O.SHAPE_SIGMOID, mlp_gate_db=0.1,
+                                 mlp=lambda lam: M.forward(params, M.features(lam), bf16=True)[0][0])
         else:
             othr_f = O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID)
         cpu = cpu_baseline(host, gy, gx, othr_f, nt, args.cpu_seconds)
         iq0, mask0 = host[0]
         ref_f = O.filter_packet(iq0, gy, gx, othr_f)
+        # a per-subset decision (curvature cut, gate) taken differently at a tie:
+        # compare with the oracle forced to the GPU's weights, and say so
+        d0 = diags[0]
+        flip = [s for s in range(gy * gx)
+                if d0["k"][s] != ref_f["k"][s] or ((d0["flags"][s] ^ ref_f["flags"][s]) & O.FLAG_MLP_FALLBACK)]
+        if flip:
+            ref_f = O.filter_packet(iq0, gy, gx, O.Threshold(cut=O.CUT_EXPLICIT,
+                                                             explicit_w=d0["weights"].astype(np.float64)))
         io_f = outs_f[0][0].cpu().numpy()
         pdx, pd99 = _pd_db(outs_f[0][1].cpu().numpy(), ref_f["pd"], mask0)
         efro = float(np.linalg.norm(io_f - ref_f["iq_out"]) / np.linalg.norm(ref_f["iq_out"]))
         parity["fast"] = {"rel_fro_iq": efro, "pd_db_max": pdx, "pd_db_p99": pd99, "packet": 0,
+                          "decisions_forced": len(flip),
                           "bounds": {"rel_fro_iq": TOL_FRO_FAST, "pd_db_max": TOL_DB}}
         parity_ok = efro <= TOL_FRO_FAST and pdx <= TOL_DB
         if plain is not None:
@@ -481,6 +556,7 @@ def main():
         "jacobi_sweeps_mean": float(np.mean(sweeps)),   # 0 where the tridiagonal solver ran
         "deflated_rank_mean": float(np.mean(ranks)),
         "mlp_fallback_rate": fallback,
+        "mlp_gate_db": gate_q,
         "autotune": {t[0]: {"gram_chunk_px": int(t[1]), "reproj_tile_rows": int(t[2]),
                             "reproj_producer_consumer": bool(int(t[3]))} for t in tuned},
         "wall_s": wall,

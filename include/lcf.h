@@ -13,7 +13,8 @@
  *   R_d    = C_w^H C_w                                              (Eqs 1, 12)
  *   R_d    = V Lambda V^H, eigenvalues descending                   (Eq. 2)
  *   w_i    eigencomponent weights: hard cut (Eq. 4), curvature rule (Eq. 6),
- *          median rule (Eq. 7), slope rule, sigmoid (Eq. 9), eigenvalue power
+ *          median rule (Eq. 7), slope rule, normalised cross-correlation of
+ *          tissue and blood images (Eq. 8), sigmoid (Eq. 9), eigenvalue power
  *          weighting (Eq. 10), caller-given, or a learned MLP
  *   Chat_d = C_w V diag(w) V^H                                      (Eqs 4, 5)
  *   PD_d   = sum_t |Chat_d|^2                                       (text after Eq. 5)
@@ -51,7 +52,7 @@
 extern "C" {
 #endif
 
-#define LCF_ABI_VERSION 5
+#define LCF_ABI_VERSION 6
 
 typedef enum {
     LCF_OK = 0,
@@ -80,7 +81,18 @@ typedef enum {
     LCF_CUT_MLP = 3,      /* weights from the context's MLP (needs Nt = 128)          */
     LCF_CUT_MEDIAN = 4,   /* k = #{i : lambda_i > beta_median * lambda_median} (Eq. 7) */
     LCF_CUT_SLOPE = 5,    /* k = first n with |slope| <= slope_thr (method 2, Fig. 2c) */
-    LCF_CUT_POWER = 6     /* soft w_i = win(i) / lambda_i^beta_power, max 1 (Eq. 10)   */
+    LCF_CUT_POWER = 6,    /* soft w_i = win(i) / lambda_i^beta_power, max 1 (Eq. 10)   */
+    LCF_CUT_NCC = 7       /* method 4 (Eq. 8): k = smallest 1-based index of the minimum
+                             over k in [5, Nt - 5] of NCC(I_T(k), I_B(k)), with
+                             I_T(k) = sum_{i=k-4..k} |u_i|, I_B(k) = sum_{i=k+1..k+5} |u_i|
+                             per pixel of the windowed subset, u_i = C_w v_i / sqrt(lambda_i)
+                             (0 where lambda_i <= 0), NCC(a, b) = sum ab / (|a| |b|) with
+                             no mean removed; no value anywhere (all images zero, or
+                             Nt < 10) gives k = 0 and LCF_FLAG_NONPOSITIVE. With
+                             LCF_SHAPE_SIGMOID this is method 5 (Eq. 9 on that k).
+                             Needs every eigenvector and the scores of every pixel: an
+                             FP64 product of the size of the projection, about as slow
+                             as the rest of the filter                              */
 } lcf_cut;
 
 typedef enum {
@@ -141,12 +153,19 @@ typedef struct {
     double* cov;       /* [nd][nt][nt] complex128 (interleaved), R_d row-major            */
     double* eigvecs;   /* [nd][nt][nt] complex128, eigenvector j in column j              */
     int32_t* rank;     /* [nd]      number of tissue components deflated                  */
+    double* curve;     /* [nd][nt]  LCF_CUT_NCC: the Eq. 8 curve, entry k-1 for 1-based k,
+                                    NaN where it has no value; untouched for other cuts    */
+    double* mlp_gate;  /* [nd]      LCF_CUT_MLP: the gate's predicted power Doppler deviation
+                                    (dB) of the network's weights from the rule's (see
+                                    LCF_OPT_MLP_GATE); +inf where the network was not
+                                    applicable; untouched for other cuts                   */
 } lcf_diag;
 
 #define LCF_FLAG_NONPOSITIVE   1  /* lambda_1 <= 0 or log10(lambda_1) == 0 under KNEE: k = 0 */
 #define LCF_FLAG_NONFINITE     2  /* NaN/Inf in the covariance                              */
 #define LCF_FLAG_NO_CONVERGE   4  /* Jacobi reached max sweeps                               */
-#define LCF_FLAG_MLP_FALLBACK  8  /* MLP input out of range: rule weights used instead      */
+#define LCF_FLAG_MLP_FALLBACK  8  /* learned weights not used, rule weights kept: input out of
+                                     range, or the gate (LCF_OPT_MLP_GATE) rejected them    */
 #define LCF_FLAG_EVD_JACOBI   16  /* near-degenerate spectrum: EVD by Jacobi instead of the
                                      tridiagonal solver (informational)                   */
 
@@ -179,6 +198,20 @@ typedef struct {
                                    1e-12 lambda_1 (flag LCF_FLAG_EVD_JACOBI; default);
                                    1 = FP64 one-sided Jacobi for every subset           */
 
+#define LCF_OPT_MLP_GATE     8  /* learned weights: the plain rule (the threshold's curvature
+                                   rule and shape) is the fallback and the judge. A subset
+                                   keeps the rule's weights (LCF_FLAG_MLP_FALLBACK) when the
+                                   predicted power Doppler deviation of the network's weights
+                                   from the rule's is at least this many milli-dB (default
+                                   100 = 0.1 dB; 0 = always the rule; -1 = no gate). The
+                                   prediction: after Eq. 13 each subset's power Doppler at a
+                                   pixel is a mixture, over components, of the same pixel
+                                   profiles weighted by each component's share of the
+                                   filtered energy, so the ratio of the two images lies
+                                   between the extreme share ratios of the components
+                                   present; the largest |10 log10| share ratio over the
+                                   components holding at least 0.1% of either energy    */
+
 /* Kernel stages reported by lcf_stage_time. */
 typedef enum {
     LCF_STAGE_WINDOWS = 0,      /* Gaussian window factors (Eq. 11)                       */
@@ -194,7 +227,9 @@ typedef enum {
     LCF_STAGE_PROJECTOR = 10,   /* P = V diag(w) V^H                                       */
     LCF_STAGE_REPROJ = 11,      /* projection, power Doppler, recombination (Eqs 4, 13)    */
     LCF_STAGE_EVD_VECTORS = 12, /* eigenvectors of the weighted components (tridiagonal solver) */
-    LCF_NUM_STAGES = 13
+    LCF_STAGE_NCC = 13,         /* method 4 scores and curve sums (Eq. 8)                  */
+    LCF_STAGE_COV_STREAM = 14,  /* sliding packets: FP64 covariance update by the hop      */
+    LCF_NUM_STAGES = 15
 } lcf_stage;
 
 typedef struct lcf_context lcf_context;
@@ -252,6 +287,37 @@ lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo
                             const lcf_threshold* thr, int32_t precision,
                             const void* const* iq, void* const* iq_out, float* const* pd,
                             void* stream);
+
+/* ---- sliding packets --------------------------------------------------------
+ * The paper processes packets that slide over a recording by a few frames
+ * (Experimental Studies section: a 5-frame hop; Discussion: display rate).
+ * Consecutive packets share every frame pair but the new ones, so the covariance
+ * of each window (Eq. 12) is carried from one packet to the next: the entries
+ * between retained frames are moved by the hop and only the hop new columns
+ * are summed over the window's box, in FP64 from the FP32 packet values (no
+ * subtraction, so nothing drifts). The FP64 covariance replaces both Gram
+ * passes of lcf_filter (it gives the tissue basis and B = Q^H R Q directly);
+ * the weights, projection, power Doppler and recombination are lcf_filter's.
+ *
+ * lcf_stream_create: one stream of packets of one geometry, rule and precision
+ *   (arguments as lcf_filter; the threshold is copied, its explicit_w pointer
+ *   kept). The stream owns two FP64 covariance buffers (nd * nt^2 complex128
+ *   each, nt padded) and the partial sums of the new columns; everything else
+ *   comes from the context's arena. *out receives the handle.
+ * lcf_stream_push: filter the current packet iq (device complex64
+ *   [nt][ny][nx]; e.g. a pointer into a longer recording [T][ny][nx] advanced
+ *   by hop frames per push) whose first nt - hop frames are the last nt - hop
+ *   frames of the previous push's packet (the caller's contract: it is not
+ *   checked). 1 <= hop <= nt; the first push after create computes every
+ *   column whatever hop says. iq_out, pd and diag as lcf_filter; calls on one
+ *   stream must be made in packet order on one HIP stream.
+ * lcf_stream_destroy: release the stream's buffers (waits for the device). */
+typedef struct lcf_stream lcf_stream;
+lcf_status lcf_stream_create(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr,
+                             int32_t precision, lcf_stream** out);
+lcf_status lcf_stream_push(lcf_stream* s, const void* iq, int32_t hop, void* iq_out, float* pd,
+                           const lcf_diag* diag, void* stream);
+lcf_status lcf_stream_destroy(lcf_stream* s);
 
 /* Batched Hermitian eigen-decomposition (Eq. 2) with the library's FP64 one-sided
  * Jacobi: a = device complex128 [n][nt][nt] (row-major, Hermitian; only read),

@@ -11,9 +11,9 @@ pinned by central finite differences and a one-layer closed form.
 """
 from .lcf_oracle import (Threshold, Window, window_boxes, window_table, casorati,
                          covariance, evd, rule_weights, knee_k,
-                         knee_curvature, median_k, slope_k, power_weights, ncc_curve, ncc_k, sigmoid_weights, projector, filter_packet,
+                         knee_curvature, median_k, slope_k, power_weights, ncc_curve, ncc_k, mlp_gate, sigmoid_weights, projector, filter_packet, filter_stream,
                          CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER, CUT_NCC, NCC_FN,
                          SHAPE_HARD, SHAPE_SIGMOID, PD_EQ13, PD_SUM,
-                         PD_EQ13_COMPENSATED)
+                         PD_EQ13_COMPENSATED, FLAG_MLP_FALLBACK, GATE_SHARE)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

@@ -52,6 +52,8 @@ SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 
 FLAG_NONPOSITIVE = 1 << 0   # lambda_1 <= 0 or log10(lambda_1) == 0 under the curvature rule
+FLAG_MLP_FALLBACK = 1 << 3  # learned weights rejected: the rule's weights are used
+GATE_SHARE = 1e-3           # components below this share of both filtered energies are ignored
 
 
 @dataclass
@@ -69,6 +71,7 @@ class Threshold:
     beta_power: float = 2.0                     # Eq. 10 order (Fig. 2g's example)
     explicit_w: Optional[np.ndarray] = None     # [nd][nt]
     mlp: Optional[object] = None                # callable(lam) -> weights, for CUT_MLP
+    mlp_gate_db: Optional[float] = None         # CUT_MLP: gate threshold (dB); None = no gate
 
 
 @dataclass
@@ -274,7 +277,16 @@ def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0, ncc=None):
     if thr.cut == CUT_EXPLICIT:
         return np.asarray(thr.explicit_w[d], dtype=np.float64).copy(), -1, curv, 0
     if thr.cut == CUT_MLP:
-        return np.asarray(thr.mlp(lam), dtype=np.float64), -1, curv, 0
+        w = np.asarray(thr.mlp(lam), dtype=np.float64)
+        if thr.mlp_gate_db is None:
+            return w, -1, curv, 0
+        # the plain rule (curvature cut with the threshold's shape) is the fallback
+        rule = Threshold(cut=CUT_KNEE, shape=thr.shape, beta_knee=thr.beta_knee,
+                         knee_max_frac=thr.knee_max_frac, beta_sigmoid=thr.beta_sigmoid)
+        w_rule, k, curv, flags = rule_weights(lam, rule)
+        if mlp_gate(lam, w, w_rule) < thr.mlp_gate_db:
+            return w, -1, curv, flags
+        return w_rule, k, curv, flags | FLAG_MLP_FALLBACK
     if thr.cut == CUT_POWER:
         w, flags = power_weights(lam, thr.beta_power)
         return w, -1, curv, flags
@@ -297,6 +309,32 @@ def rule_weights(lam: np.ndarray, thr: Threshold, d: int = 0, ncc=None):
     else:
         w = sigmoid_weights(nt, k, thr.beta_sigmoid)
     return w, k, curv, flags
+
+
+def mlp_gate(lam: np.ndarray, w_net: np.ndarray, w_rule: np.ndarray, share: float = GATE_SHARE) -> float:
+    """Predicted power Doppler deviation (dB) between two weight sets of one
+    subset. After Eq. 13 the subset's power Doppler at a pixel is proportional
+    to sum_i q_i e_i(x), with q_i = w_i^2 lambda_i / sum_j w_j^2 lambda_j and
+    e_i(x) = |(C_w v_i)(x)|^2 / lambda_i shared by both sets, so the ratio of the
+    two images at a pixel lies between the extreme ratios q_i(net) / q_i(rule)
+    of the components present there. Returned: the largest |10 log10| of that
+    ratio over the components (lambda_i > 0) holding at least ``share`` of
+    either filtered energy; +inf if only one set keeps such a component or an
+    energy is zero."""
+    lam = np.asarray(lam, dtype=np.float64)
+    en = np.asarray(w_net, dtype=np.float64) ** 2 * lam
+    er = np.asarray(w_rule, dtype=np.float64) ** 2 * lam
+    tn, tr = float(np.sum(en)), float(np.sum(er))
+    if not (tn > 0.0 and tr > 0.0):
+        return math.inf
+    g = 0.0
+    for i in range(lam.shape[0]):
+        if not lam[i] > 0.0:
+            continue
+        q, p = en[i] / tn, er[i] / tr
+        if q >= share or p >= share:
+            g = max(g, abs(10.0 * math.log10(q / p)) if (q > 0.0 and p > 0.0) else math.inf)
+    return g
 
 
 def projector(v: np.ndarray, w: np.ndarray) -> np.ndarray:
@@ -368,3 +406,17 @@ def filter_packet(iq: np.ndarray, gy: int, gx: int, thr: Threshold,
     res["nd"] = nd
     res["windows"] = wins
     return res
+
+
+def filter_stream(record: np.ndarray, nt: int, hop: int, gy: int, gx: int, thr: Threshold,
+                  count: int = None, **kw):
+    """Sliding packets of a recording (the Experimental Studies section times the
+    filter over packets that slide by a few frames): packet p holds frames
+    [p hop, p hop + nt) of ``record`` ([T][ny][nx]) and is filtered from scratch
+    by ``filter_packet``. Returns the list of per-packet results."""
+    total = record.shape[0]
+    n = (total - nt) // hop + 1
+    if count is not None:
+        n = min(n, count)
+    return [filter_packet(record[p * hop:p * hop + nt], gy, gx, thr, **kw) for p in range(n)]
+

@@ -16,14 +16,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblcf.so")
 
 PREC_FP32, PREC_BF16X3 = 0, 1
-CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER = 0, 1, 2, 3, 4, 5, 6
-ABI_VERSION = 5
+CUT_FIXED_K, CUT_KNEE, CUT_EXPLICIT, CUT_MLP, CUT_MEDIAN, CUT_SLOPE, CUT_POWER, CUT_NCC = 0, 1, 2, 3, 4, 5, 6, 7
+ABI_VERSION = 6
 SHAPE_HARD, SHAPE_SIGMOID = 0, 1
 PD_EQ13, PD_SUM, PD_EQ13_COMPENSATED = 0, 1, 2
 OPT_SCHEDULE, OPT_MAX_SWEEPS, OPT_USE_GRAPH, OPT_SUBSPACE_IT, OPT_STAGE_TIMING, OPT_AUTOTUNE, OPT_EVD = 1, 2, 3, 4, 5, 6, 7
+OPT_MLP_GATE = 8
 EVD_TRIDIAGONAL, EVD_JACOBI = 0, 1
 STAGES = ["windows", "gram1", "gram1_reduce", "tissue", "gram2", "gram2_reduce", "assemble", "evd",
-          "rules", "mlp", "projector", "reproj", "evd_vectors"]
+          "rules", "mlp", "projector", "reproj", "evd_vectors", "ncc", "cov_stream"]
 FLAG_NONPOSITIVE, FLAG_NONFINITE, FLAG_NO_CONVERGE, FLAG_MLP_FALLBACK, FLAG_EVD_JACOBI = 1, 2, 4, 8, 16
 
 STATUS = {0: "LCF_OK", 1: "LCF_ERR_INVALID_ARG", 2: "LCF_ERR_UNSUPPORTED", 3: "LCF_ERR_OUT_OF_MEMORY",
@@ -54,7 +55,7 @@ class ThresholdC(C.Structure):
 class DiagC(C.Structure):
     _fields_ = [("eigvals", C.c_void_p), ("weights", C.c_void_p), ("k", C.c_void_p), ("sweeps", C.c_void_p),
                 ("flags", C.c_void_p), ("alpha", C.c_void_p), ("cov", C.c_void_p), ("eigvecs", C.c_void_p),
-                ("rank", C.c_void_p)]
+                ("rank", C.c_void_p), ("curve", C.c_void_p), ("mlp_gate", C.c_void_p)]
 
 
 @dataclass
@@ -100,6 +101,9 @@ def load():
     lib.lcf_filter_batch.argtypes = [vp, i32, C.POINTER(Geometry), C.POINTER(ThresholdC), i32,
                                      C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     lib.lcf_heevd_batched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    lib.lcf_stream_create.argtypes = [vp, C.POINTER(Geometry), C.POINTER(ThresholdC), i32, C.POINTER(vp)]
+    lib.lcf_stream_push.argtypes = [vp, vp, i32, vp, vp, C.POINTER(DiagC), vp]
+    lib.lcf_stream_destroy.argtypes = [vp]
     lib.lcf_sync.argtypes = [vp, vp]
     lib.lcf_stage_time.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
     lib.lcf_mlp_init.argtypes = [vp, C.c_uint64]
@@ -116,6 +120,7 @@ def load():
     lib.lcf_status_str.restype = C.c_char_p
     for name in ("lcf_create", "lcf_destroy", "lcf_set_option", "lcf_validate", "lcf_filter", "lcf_filter_noalloc",
                  "lcf_filter_batch", "lcf_heevd_batched", "lcf_sync", "lcf_abi_version",
+                 "lcf_stream_create", "lcf_stream_push", "lcf_stream_destroy",
                  "lcf_stage_time",
                  "lcf_mlp_init", "lcf_mlp_set_params", "lcf_mlp_get_params", "lcf_mlp_get_grads", "lcf_mlp_save",
                  "lcf_mlp_load", "lcf_mlp_infer", "lcf_mlp_train_step", "lcf_tune_save", "lcf_tune_load"):
@@ -151,6 +156,30 @@ def _ptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
 
 
+def _diag_buffers(nd, nt, dev, cut, want, cov=False):
+    """Device buffers for lcf_diag (dict of torch tensors) and the C struct, or (None, None)."""
+    if not want:
+        return None, None
+    import torch
+    dg = dict(eigvals=torch.empty((nd, nt), dtype=torch.float64, device=dev),
+              weights=torch.empty((nd, nt), dtype=torch.float32, device=dev),
+              k=torch.empty(nd, dtype=torch.int32, device=dev),
+              sweeps=torch.empty(nd, dtype=torch.int32, device=dev),
+              flags=torch.empty(nd, dtype=torch.int32, device=dev),
+              alpha=torch.empty(nd, dtype=torch.float64, device=dev),
+              rank=torch.empty(nd, dtype=torch.int32, device=dev))
+    if cut == CUT_NCC:
+        dg["curve"] = torch.empty((nd, nt), dtype=torch.float64, device=dev)
+    if cut == CUT_MLP:
+        dg["mlp_gate"] = torch.empty(nd, dtype=torch.float64, device=dev)
+    if cov:
+        dg["cov"] = torch.empty((nd, nt, nt), dtype=torch.complex128, device=dev)
+        dg["eigvecs"] = torch.empty((nd, nt, nt), dtype=torch.complex128, device=dev)
+    dgc = DiagC(*(_ptr(dg.get(n)) for n in ("eigvals", "weights", "k", "sweeps", "flags", "alpha",
+                                            "cov", "eigvecs", "rank", "curve", "mlp_gate")))
+    return dg, dgc
+
+
 class Context:
     """An lcf_context on one device (options: schedule, max_sweeps, use_graph, autotune)."""
 
@@ -161,6 +190,7 @@ class Context:
         _check(lib.lcf_create(device, C.byref(h)), "lcf_create")
         self._h = h
         self.device = device
+        self.options = {OPT_MLP_GATE: 100}      # values set through this object (library defaults otherwise)
         self.set_option(OPT_SCHEDULE, schedule)
         self.set_option(OPT_MAX_SWEEPS, max_sweeps)
         self.set_option(OPT_USE_GRAPH, use_graph)
@@ -174,6 +204,7 @@ class Context:
 
     def set_option(self, opt: int, value: int):
         _check(load().lcf_set_option(self._h, opt, int(value)), "lcf_set_option")
+        self.options[opt] = int(value)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -223,22 +254,7 @@ class Context:
         if thr.cut == CUT_EXPLICIT:
             ew = explicit_w.to(device=dev, dtype=torch.float32).contiguous()
         tc = thr.to_c(ew.data_ptr() if ew is not None else 0)
-        dg = None
-        dgc = None
-        if diag or diag_cov:
-            nd = gy * gx
-            dg = dict(eigvals=torch.empty((nd, nt), dtype=torch.float64, device=dev),
-                      weights=torch.empty((nd, nt), dtype=torch.float32, device=dev),
-                      k=torch.empty(nd, dtype=torch.int32, device=dev),
-                      sweeps=torch.empty(nd, dtype=torch.int32, device=dev),
-                      flags=torch.empty(nd, dtype=torch.int32, device=dev),
-                      alpha=torch.empty(nd, dtype=torch.float64, device=dev),
-                      rank=torch.empty(nd, dtype=torch.int32, device=dev))
-            if diag_cov:
-                dg["cov"] = torch.empty((nd, nt, nt), dtype=torch.complex128, device=dev)
-                dg["eigvecs"] = torch.empty((nd, nt, nt), dtype=torch.complex128, device=dev)
-            dgc = DiagC(*(_ptr(dg.get(n)) for n in ("eigvals", "weights", "k", "sweeps", "flags", "alpha",
-                                                    "cov", "eigvecs", "rank")))
+        dg, dgc = _diag_buffers(nd=gy * gx, nt=nt, dev=dev, cut=thr.cut, want=diag or diag_cov, cov=diag_cov)
         fn = load().lcf_filter_noalloc if noalloc else load().lcf_filter
         st = fn(self._h, C.byref(geo), C.byref(tc), precision, _ptr(iq), _ptr(io), _ptr(pd),
                 C.byref(dgc) if dgc is not None else None, _stream())
@@ -334,3 +350,53 @@ class Context:
         st = load().lcf_heevd_batched(self._h, n, nt, _ptr(a), _ptr(w), _ptr(v), _ptr(sw), _stream())
         _check(st, "lcf_heevd_batched")
         return w, v, sw
+
+
+class Stream:
+    """An lcf_stream: sliding packets of one geometry through one context
+    (``lcf_stream_create`` / ``lcf_stream_push`` / ``lcf_stream_destroy``)."""
+
+    def __init__(self, ctx: Context, ny: int, nx: int, nt: int, gy: int, gx: int, thr: Threshold,
+                 precision: int = PREC_FP32, sigma_frac: float = 1.0 / 3.0, trunc_sigmas: float = 6.0,
+                 explicit_w=None):
+        lib = load()
+        self.ctx = ctx
+        self.geo = geometry(ny, nx, nt, gy, gx, sigma_frac, trunc_sigmas)
+        self.thr = thr
+        self._ew = explicit_w            # kept alive: the library keeps the pointer
+        tc = thr.to_c(explicit_w.data_ptr() if explicit_w is not None else 0)
+        h = C.c_void_p()
+        _check(lib.lcf_stream_create(ctx._h, C.byref(self.geo), C.byref(tc), precision, C.byref(h)),
+               "lcf_stream_create")
+        self._h = h
+
+    def push(self, iq, hop: int, iq_out: bool = True, diag: bool = False, out=None):
+        """Filter the current packet ``iq`` (torch complex64 [nt][ny][nx] on the GPU)
+        whose first nt - hop frames are the previous packet's last ones.
+        Returns (iq_out or None, pd, diag dict or None)."""
+        import torch
+        assert iq.is_cuda and iq.dtype == torch.complex64 and iq.is_contiguous() and iq.dim() == 3
+        nt, ny, nx = iq.shape
+        assert (nt, ny, nx) == (self.geo.nt, self.geo.ny, self.geo.nx)
+        if out is None:
+            pd = torch.empty((ny, nx), dtype=torch.float32, device=iq.device)
+            io = torch.empty_like(iq) if iq_out else None
+        else:
+            io, pd = out
+        dg, dgc = _diag_buffers(self.geo.gy * self.geo.gx, nt, iq.device, self.thr.cut, diag)
+        st = load().lcf_stream_push(self._h, _ptr(iq), int(hop), _ptr(io), _ptr(pd),
+                                    C.byref(dgc) if dgc is not None else None, _stream())
+        _check(st, "lcf_stream_push")
+        return io, pd, dg
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lcf_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

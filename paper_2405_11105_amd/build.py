@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "liblcf.so")
-SOURCES = ["runtime.hip", "k_gram.hip", "k_evd.hip", "k_post.hip", "k_mlp.hip"]
+SOURCES = ["runtime.hip", "k_gram.hip", "k_evd.hip", "k_post.hip", "k_mlp.hip", "k_ncc.hip", "k_stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

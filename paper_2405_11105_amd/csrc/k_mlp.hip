@@ -216,22 +216,60 @@ __global__ void __launch_bounds__(256) k_mlp_to_bf16(const float* master, uint16
 }
 
 // Replace the rule weights of valid subsets by the network output and
-// recompute alpha_d (Eq. 13) with them; invalid subsets keep the rule and are flagged.
-__global__ void __launch_bounds__(128) k_mlp_apply(Workspace ws, const float* wout, const int* valid, int pd_mode) {
-    __shared__ double red[2];
+// recompute alpha_d (Eq. 13) with them; invalid subsets keep the rule and are
+// flagged. With the gate on (gate_db >= 0), the rule is also kept (and the
+// subset flagged) when the predicted power Doppler deviation of the network's
+// weights from the rule's reaches gate_db. After Eq. 13 a subset's power
+// Doppler at pixel x is Npix Nt sum_i q_i e_i(x), with q_i = w_i^2 lambda_i /
+// sum_j w_j^2 lambda_j the component's share of the filtered energy and
+// e_i(x) = |(C_w v_i)(x)|^2 / lambda_i the same for either weight set, so the
+// ratio of the two images at any pixel lies between the extreme ratios
+// q_i(net) / q_i(rule) of the components present there. The prediction is
+// the largest |10 log10| of that ratio over components holding at least
+// GATE_SHARE of either filtered energy (infinite when only one set keeps
+// such a component, or when either energy is zero). gate_out[s * ntp] (may be
+// null) receives it.
+constexpr double GATE_SHARE = 1e-3;
+
+__global__ void __launch_bounds__(128) k_mlp_apply(Workspace ws, const float* wout, const int* valid, int pd_mode,
+                                                   double gate_db, double* gate_out) {
+    __shared__ double red[4];
     const int s = blockIdx.x, i = threadIdx.x, ntp = ws.ntp;
     if (!valid || !valid[s] || ws.sub[s].nt != MLP_NT) {
-        if (i == 0) atomicOr(&ws.flags[s], 8);
+        if (i == 0) {
+            atomicOr(&ws.flags[s], 8);
+            if (gate_out) gate_out[(long)s * ntp] = INFINITY;
+        }
         return;
     }
     const double w = (double)wout[(long)s * MLP_NT + i];
-    ws.wts[(long)s * ntp + i] = w;
-    double e = w * w * ws.lam[(long)s * ntp + i];
-    e = wave_sum(e);
-    if ((i & 63) == 0) red[i >> 6] = e;
+    const double l = ws.lam[(long)s * ntp + i];
+    const double wr = ws.wts[(long)s * ntp + i];
+    const double em = w * w * l, er = wr * wr * l;
+    const double sm = wave_sum(em), sr = wave_sum(er);
+    if ((i & 63) == 0) { red[i >> 6] = sm; red[2 + (i >> 6)] = sr; }
     __syncthreads();
+    const double en = red[0] + red[1], enr = red[2] + red[3];
+    // predicted deviation (dB) of this component's share
+    double g = 0.0;
+    if (!(en > 0.0) || !(enr > 0.0)) {
+        g = INFINITY;
+    } else if (l > 0.0) {
+        const double q = em / en, p = er / enr;
+        if (q >= GATE_SHARE || p >= GATE_SHARE) g = (q > 0.0 && p > 0.0) ? fabs(10.0 * log10(q / p)) : INFINITY;
+    }
+    for (int m = 32; m >= 1; m >>= 1) g = fmax(g, __shfl_xor(g, m, 64));
+    __syncthreads();
+    if ((i & 63) == 0) red[i >> 6] = g;
+    __syncthreads();
+    const double gmax = fmax(red[0], red[1]);
+    if (i == 0 && gate_out) gate_out[(long)s * ntp] = gmax;
+    if (gate_db >= 0.0 && !(gmax < gate_db)) {
+        if (i == 0) atomicOr(&ws.flags[s], 8);
+        return;                                  // the rule's weights and alpha stay
+    }
+    ws.wts[(long)s * ntp + i] = w;
     if (i == 0) {
-        const double en = red[0] + red[1];
         ws.alpha[s] = pd_mode == 1 ? 1.0 : (en > 0.0 ? ws.sub[s].npix_nt / en : 0.0);
         ws.kcut[s] = -1;
     }
@@ -268,8 +306,9 @@ hipError_t mlp_features(const double* lam, int ldl, int rows, float* z, int* val
     return hipGetLastError();
 }
 
-hipError_t mlp_apply(const Workspace& ws, const float* wout, const int* valid, int pd_mode, hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_apply, dim3(ws.S), dim3(MLP_NT), 0, st, ws, wout, valid, pd_mode);
+hipError_t mlp_apply(const Workspace& ws, const float* wout, const int* valid, int pd_mode, double gate_db,
+                     double* gate_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_apply, dim3(ws.S), dim3(MLP_NT), 0, st, ws, wout, valid, pd_mode, gate_db, gate_out);
     return hipGetLastError();
 }
 

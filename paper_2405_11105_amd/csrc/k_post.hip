@@ -27,8 +27,47 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     double* wts = ws.wts + (long)s * ntp;
     if (lane == 0) { sh_k = -1; sh_flag = 0; }
     __syncthreads();
-    if (rp.cut == 0 || rp.cut == 1 || rp.cut == 4 || rp.cut == 5) {
+    if (rp.cut == 0 || rp.cut == 1 || rp.cut == 4 || rp.cut == 5 || rp.cut == 7) {
         int k = rp.k_fixed;
+        if (rp.cut == 7) {
+            // method 4 (Eq. 8): add the chunk partials of the three curve sums in
+            // chunk order, NCC(k) = sum I_T I_B / (sqrt(sum I_T^2) sqrt(sum I_B^2)) over
+            // 1-based k in [fn, nt - fn] (NaN elsewhere and where an image is zero);
+            // k = smallest index of the minimum, 0 and NONPOSITIVE when none has a value
+            constexpr int FN = 5;
+            const double* part = (const double*)ws.partial;
+            const int c0 = ws.chunk_begin[s], c1 = ws.chunk_begin[s + 1];
+            double* curve = ws.curve + (long)s * ntp;
+            double best = INFINITY;
+            int bi = 1 << 30;
+            for (int i = lane; i < ntp; i += 64) {
+                const int k1 = i + 1;
+                double v = NAN;
+                if (k1 >= FN && k1 <= nt - FN) {
+                    double tb = 0.0, tt = 0.0, bb = 0.0;
+                    for (int c = c0; c < c1; ++c) {
+                        tb += part[(long)c * 3 * ntp + i];
+                        tt += part[(long)c * 3 * ntp + ntp + i];
+                        bb += part[(long)c * 3 * ntp + 2 * ntp + i];
+                    }
+                    const double den = sqrt(tt) * sqrt(bb);
+                    if (den > 0.0) v = tb / den;
+                }
+                curve[i] = v;
+                if (v < best) { best = v; bi = k1; }
+            }
+            for (int m = 32; m >= 1; m >>= 1) {
+                const double ob = __shfl_xor(best, m, 64);
+                const int oi = __shfl_xor(bi, m, 64);
+                if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (bi == (1 << 30)) {
+                k = 0;
+                if (lane == 0) sh_flag = 1;
+            } else {
+                k = bi;
+            }
+        }
         if (rp.cut == 5) {
             // slope rule: y(n) = Nt lambda_n / lambda_1, slopes by the differences
             // of the curvature rule; k = first 0-based n with |y'(n)| <= threshold
@@ -139,7 +178,7 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     for (int i = lane; i < nt; i += 64) e += wts[i] * wts[i] * lam[i];
     e = wave_sum(e);
     if (lane == 0) {
-        ws.kcut[s] = (rp.cut <= 1 || rp.cut == 4 || rp.cut == 5) ? sh_k : -1;
+        ws.kcut[s] = (rp.cut <= 1 || rp.cut == 4 || rp.cut == 5 || rp.cut == 7) ? sh_k : -1;
         ws.alpha[s] = rp.pd_mode == 1 ? 1.0 : (e > 0.0 ? sd.npix_nt / e : 0.0);
         if (sh_flag) atomicOr(&ws.flags[s], sh_flag);
     }
@@ -1536,11 +1575,12 @@ hipError_t launch_reproj(const Workspace& ws, int precision, hipStream_t st) {
 // returned in the original basis: V = Q W = H_0 .. H_{r-1} W.
 __global__ void __launch_bounds__(256) k_export(Workspace ws, int first, int nt, double* eigvals, float* weights,
                                                int* k, int* sweeps, int* flags, double* alpha, int* rank,
-                                               double2* eigvecs) {
+                                               double2* eigvecs, double* curve, double* mlp_gate) {
     const int d = blockIdx.x, s = first + d, tid = threadIdx.x, ntp = ws.ntp;
     for (int i = tid; i < nt; i += 256) {
         if (eigvals) eigvals[(long)d * nt + i] = ws.lam[(long)s * ntp + i];
         if (weights) weights[(long)d * nt + i] = (float)ws.wts[(long)s * ntp + i];
+        if (curve) curve[(long)d * nt + i] = ws.curve[(long)s * ntp + i];
     }
     if (tid == 0) {
         if (k) k[d] = ws.kcut[s];
@@ -1548,6 +1588,7 @@ __global__ void __launch_bounds__(256) k_export(Workspace ws, int first, int nt,
         if (flags) flags[d] = ws.flags[s];
         if (alpha) alpha[d] = ws.alpha[s];
         if (rank) rank[d] = ws.rank[s];
+        if (mlp_gate) mlp_gate[d] = ws.curve[(long)s * ntp];
     }
     if (!eigvecs) return;
     const int r = ws.rank[s];
@@ -1583,10 +1624,10 @@ __global__ void k_flags_or(Workspace ws, int* sticky) {
 
 hipError_t launch_export(const Workspace& ws, int first, int count, int nt, double* eigvals, float* weights,
                          int* k, int* sweeps, int* flags, double* alpha, int* rank, double2* eigvecs,
-                         hipStream_t st) {
+                         double* curve, double* mlp_gate, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_export, dim3(count), dim3(256), 0, st, ws, first, nt, eigvals, weights, k, sweeps,
-                       flags, alpha, rank, eigvecs);
+                       flags, alpha, rank, eigvecs, curve, mlp_gate);
     return hipGetLastError();
 }
 

@@ -94,6 +94,7 @@ struct Workspace {
     int* flags;         // [S]
     int* sweeps;        // [S]
     double* alpha;      // [S]
+    double* curve;      // [S][ntp] Eq. 8 curve of the NCC rule (NaN where it has no value)
     double2* pmat;      // [S][ntp][ntp] projector P in the original basis (FP64)
     float* breal;       // [S][2*nte][2*ntp] real form of [P; M] for the reprojection
     const float* explicit_w;   // [S][nt] caller weights (EXPLICIT)

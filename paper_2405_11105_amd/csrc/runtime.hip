@@ -109,7 +109,7 @@ lcf_status validate_geometry(const lcf_geometry* g) {
 
 lcf_status validate_threshold(const lcf_threshold* t, int nt) {
     if (!t) return LCF_ERR_INVALID_ARG;
-    if (t->cut < 0 || t->cut > 6 || t->shape < 0 || t->shape > 1 || t->pd_mode < 0 || t->pd_mode > 2)
+    if (t->cut < 0 || t->cut > 7 || t->shape < 0 || t->shape > 1 || t->pd_mode < 0 || t->pd_mode > 2)
         return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_FIXED_K && (t->k_fixed < 0 || t->k_fixed > nt)) return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_KNEE && (!(t->beta_knee > 0.0) || !(t->knee_max_frac > 0.0) || t->knee_max_frac > 1.0))
@@ -121,7 +121,7 @@ lcf_status validate_threshold(const lcf_threshold* t, int nt) {
     if (t->cut == LCF_CUT_POWER && !(t->beta_power > 0.0 && std::isfinite(t->beta_power)))
         return LCF_ERR_INVALID_ARG;
     if (t->shape == LCF_SHAPE_SIGMOID && (t->cut <= LCF_CUT_KNEE || t->cut == LCF_CUT_MEDIAN ||
-                                          t->cut == LCF_CUT_SLOPE) &&
+                                          t->cut == LCF_CUT_SLOPE || t->cut == LCF_CUT_NCC) &&
         !(t->beta_sigmoid > 0.0))
         return LCF_ERR_INVALID_ARG;
     if (t->cut == LCF_CUT_EXPLICIT && t->explicit_w == nullptr) return LCF_ERR_INVALID_ARG;
@@ -285,6 +285,18 @@ void build_plan(Plan& pl, const std::vector<PacketIn>& in, const std::vector<int
 
 }  // namespace
 
+struct lcf_stream {
+    lcf_context* ctx = nullptr;
+    lcf_geometry geo{};
+    lcf_threshold thr{};
+    int prec = 0;
+    Plan plan;
+    double2* rbuf[2] = {nullptr, nullptr};   // FP64 covariance of the last packet / the next one
+    double2* part = nullptr;                 // band partials of the new columns
+    int cur = 0;                             // rbuf[cur] holds the last packet's covariance
+    bool primed = false;
+};
+
 struct lcf_context {
     int device = 0;
     int schedule = 0;
@@ -308,6 +320,7 @@ struct lcf_context {
     double stage_ms[LCF_NUM_STAGES] = {0};
     long long stage_n[LCF_NUM_STAGES] = {0};
     int evd_method = 0;            // 0: tridiagonal solver (Jacobi for flagged subsets), 1: Jacobi
+    long mlp_gate_mdb = 100;       // learned weights: gate threshold in milli-dB, < 0 = no gate
     // autotuner: choices per launch-group class (tune_key)
     int autotune = 0;
     std::map<std::string, TuneChoice> tuned;
@@ -390,12 +403,14 @@ std::string graph_key(lcf_context* c, const Plan& pl, const std::vector<PacketIn
     k += buf;
     std::snprintf(buf, sizeof buf, "|m%.17g,%.17g,%.17g", thr->beta_median, thr->slope_thr, thr->beta_power);
     k += buf;
-    std::snprintf(buf, sizeof buf, "|c%d,r%d,v%d,e%d", pl.chunk, pl.trows, pl.rvar, c->evd_method);
+    std::snprintf(buf, sizeof buf, "|c%d,r%d,v%d,e%d,g%ld", pl.chunk, pl.trows, pl.rvar, c->evd_method,
+                  c->mlp_gate_mdb);
     k += buf;
     if (diag) {
-        std::snprintf(buf, sizeof buf, "|d%p,%p,%p,%p,%p,%p,%p,%p,%p", (void*)diag->eigvals, (void*)diag->weights,
-                      (void*)diag->k, (void*)diag->sweeps, (void*)diag->flags, (void*)diag->alpha, (void*)diag->cov,
-                      (void*)diag->eigvecs, (void*)diag->rank);
+        std::snprintf(buf, sizeof buf, "|d%p,%p,%p,%p,%p,%p,%p,%p,%p,%p,%p", (void*)diag->eigvals,
+                      (void*)diag->weights, (void*)diag->k, (void*)diag->sweeps, (void*)diag->flags,
+                      (void*)diag->alpha, (void*)diag->cov, (void*)diag->eigvecs, (void*)diag->rank,
+                      (void*)diag->curve, (void*)diag->mlp_gate);
         k += buf;
     }
     return k;
@@ -452,7 +467,7 @@ uint32_t crc32_update(uint32_t crc, const void* data, size_t len) {
 struct Layout {
     size_t off_sub, off_chunks, off_cbeg, off_tiles, off_cover, off_pkts, host_bytes;
     size_t off_wtab, off_partial, off_rwin, off_rext, off_hv, off_htau, off_vr64, off_vr32, off_rank, off_bmat,
-        off_wvec, off_lam, off_wts, off_kcut, off_flags, off_sweeps, off_alpha, off_pmat, off_breal, total;
+        off_wvec, off_lam, off_wts, off_kcut, off_flags, off_sweeps, off_alpha, off_curve, off_pmat, off_breal, total;
 };
 
 Layout make_layout(const Plan& pl) {
@@ -485,6 +500,7 @@ Layout make_layout(const Plan& pl) {
     L.off_flags = take(S * sizeof(int));
     L.off_sweeps = take(S * sizeof(int));
     L.off_alpha = take(S * sizeof(double));
+    L.off_curve = take(S * ntp * sizeof(double));
     L.off_pmat = take(S * ntp * ntp * sizeof(double2));
     L.off_breal = take(S * (2 * nte) * (2 * ntp) * sizeof(float));
     L.total = o;
@@ -523,6 +539,7 @@ Workspace make_ws(char* base, const Layout& L, const Plan& pl, const float* expl
     ws.flags = (int*)(base + L.off_flags);
     ws.sweeps = (int*)(base + L.off_sweeps);
     ws.alpha = (double*)(base + L.off_alpha);
+    ws.curve = (double*)(base + L.off_curve);
     ws.pmat = (double2*)(base + L.off_pmat);
     ws.breal = (float*)(base + L.off_breal);
     ws.explicit_w = explicit_w;
@@ -554,6 +571,7 @@ Workspace subset_view(const Workspace& w, int s, const ChunkDesc* chunks, const 
     v.flags = w.flags + s;
     v.sweeps = w.sweeps + s;
     v.alpha = w.alpha + s;
+    v.curve = w.curve + s * ntp;
     v.pmat = w.pmat + s * ntp * ntp;
     v.breal = w.breal + s * (2 * nte) * (2 * ntp);
     return v;
@@ -629,6 +647,12 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
                   thr->knee_max_frac, thr->beta_sigmoid, thr->beta_median, thr->slope_thr, thr->beta_power};
     { STAGE(c, LCF_STAGE_EVD, st); HIPCHK(launch_evd(ws, c->max_sweeps, nt_max, c->evd_method, st)); }
+    const bool ncc = thr->cut == LCF_CUT_NCC;
+    if (ncc) {
+        // method 4 reads every eigenvector before the cut is known
+        { STAGE(c, LCF_STAGE_EVD_VECTORS, st); HIPCHK(launch_evd_vectors(ws, c->evd_method, 1, st)); }
+        { STAGE(c, LCF_STAGE_NCC, st); HIPCHK(launch_ncc(ws, st)); }
+    }
     { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
     if (mlp) {
         STAGE(c, LCF_STAGE_MLP, st);
@@ -640,12 +664,16 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
         if (ws.ntp == MLP_NT) {
             HIPCHK(mlp_features(ws.lam, ws.ntp, ws.S, z, valid, st));
             HIPCHK(mlp_forward(c->mlp, z, ws.S, act, wout, st));
-            HIPCHK(mlp_apply(ws, wout, valid, thr->pd_mode, st));
+            HIPCHK(mlp_apply(ws, wout, valid, thr->pd_mode, c->mlp_gate_mdb < 0 ? -1.0 : 1e-3 * c->mlp_gate_mdb,
+                             ws.curve, st));
         } else {
-            HIPCHK(mlp_apply(ws, wout, nullptr, thr->pd_mode, st));   // all subsets keep the rule
+            HIPCHK(mlp_apply(ws, wout, nullptr, thr->pd_mode, -1.0, ws.curve, st));   // all subsets keep the rule
         }
     }
-    { STAGE(c, LCF_STAGE_EVD_VECTORS, st); HIPCHK(launch_evd_vectors(ws, c->evd_method, all_vectors, st)); }
+    if (!ncc) {
+        STAGE(c, LCF_STAGE_EVD_VECTORS, st);
+        HIPCHK(launch_evd_vectors(ws, c->evd_method, all_vectors, st));
+    }
     { STAGE(c, LCF_STAGE_PROJECTOR, st); HIPCHK(launch_projector(ws, prec, st)); }
     return LCF_OK;
 }
@@ -665,8 +693,6 @@ struct FixedArena {
     char* base;
     size_t cap;
 };
-
-
 
 lcf_status stage_group(lcf_context* c, const Plan& pl, const lcf_threshold* thr, hipStream_t st, Staged& sg,
                        const FixedArena* fx = nullptr) {
@@ -769,7 +795,9 @@ lcf_status run_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf
     { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
     if (diag)
         HIPCHK(launch_export(ws, 0, (int)pl.sub.size(), pl.sub[0].nt, diag->eigvals, diag->weights, diag->k,
-                             diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs, st));
+                             diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs,
+                             thr->cut == LCF_CUT_NCC ? diag->curve : nullptr,
+                             thr->cut == LCF_CUT_MLP ? diag->mlp_gate : nullptr, st));
     HIPCHK(launch_flags_or(ws, c->sticky, st));
     return LCF_OK;
 }
@@ -875,7 +903,6 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
         // while stage timing is on, and not for the fixed block, whose chains are
         // launched directly).
         const bool graph = c->use_graph && !c->timing && st != nullptr && !fx;
-
         std::string key;
         if (graph) {
             key = graph_key(c, pl, in, kv.second, thr, prec, diag);
@@ -902,6 +929,30 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
             return e;
         }
     }
+    return LCF_OK;
+}
+
+// One push of a sliding-packet stream: the covariance from the previous
+// packet's by the hop, then every stage after the Gram passes.
+lcf_status stream_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf_threshold* thr, int prec,
+                        const double2* rold, double2* rnew, double2* part, int hop, const lcf_diag* diag,
+                        hipStream_t st) {
+    const Workspace& ws = sg.ws;
+    { STAGE(c, LCF_STAGE_WINDOWS, st); HIPCHK(launch_windows(ws, st)); }
+    { STAGE(c, LCF_STAGE_COV_STREAM, st); HIPCHK(launch_cov_stream(ws, rold, rnew, part, hop, st)); }
+    { STAGE(c, LCF_STAGE_TISSUE, st); HIPCHK(launch_tissue(ws, thr->deflate_rho, c->sub_iters, st)); }
+    const bool cov = diag && diag->cov;
+    { STAGE(c, LCF_STAGE_ASSEMBLE, st); HIPCHK(launch_assemble(ws, cov, st)); }
+    if (cov) HIPCHK(launch_export_cov(ws, 0, ws.S, pl.sub[0].nt, (double2*)diag->cov, st));
+    lcf_status e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, st);
+    if (e != LCF_OK) return e;
+    { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
+    if (diag)
+        HIPCHK(launch_export(ws, 0, (int)pl.sub.size(), pl.sub[0].nt, diag->eigvals, diag->weights, diag->k,
+                             diag->sweeps, diag->flags, diag->alpha, diag->rank, (double2*)diag->eigvecs,
+                             thr->cut == LCF_CUT_NCC ? diag->curve : nullptr,
+                             thr->cut == LCF_CUT_MLP ? diag->mlp_gate : nullptr, st));
+    HIPCHK(launch_flags_or(ws, c->sticky, st));
     return LCF_OK;
 }
 
@@ -977,6 +1028,10 @@ lcf_status lcf_set_option(lcf_context* c, int32_t option, int64_t value) {
             if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
             c->autotune = (int)value;
             return LCF_OK;
+        case LCF_OPT_MLP_GATE:
+            if (value < -1 || value > 1000000) return LCF_ERR_INVALID_ARG;
+            c->mlp_gate_mdb = (long)value;
+            return LCF_OK;
         case LCF_OPT_EVD:
             if (value != 0 && value != 1) return LCF_ERR_INVALID_ARG;
             c->evd_method = (int)value;
@@ -1034,6 +1089,76 @@ lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo
         ew += (long)geo[i].gy * geo[i].gx * geo[i].nt;
     }
     return filter_packets(ctx, in, thr, precision, nullptr, (hipStream_t)stream);
+}
+
+lcf_status lcf_stream_create(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr,
+                             int32_t precision, lcf_stream** out) {
+    if (!ctx || !out) return LCF_ERR_INVALID_ARG;
+    *out = nullptr;
+    lcf_status e = lcf_validate(geo, thr, precision);
+    if (e != LCF_OK) return e;
+    if (thr->cut == LCF_CUT_MLP && !ctx->mlp_ready) return LCF_ERR_MODEL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCF_ERR_DEVICE;
+    lcf_stream* sm = new lcf_stream();
+    sm->ctx = ctx;
+    sm->geo = *geo;
+    sm->thr = *thr;
+    sm->prec = precision;
+    const int ntp = ntp_class(geo->nt);
+    std::vector<PacketIn> in{PacketIn{*geo, nullptr, nullptr, nullptr, 0}};
+    build_plan(sm->plan, in, std::vector<int>{0}, thr->pd_mode, CHUNK, trows_max(ntp),
+               (trows_max(ntp) >= 4 && precision == LCF_PREC_FP32) ? 1 : 0);
+    const size_t S = sm->plan.sub.size();
+    const size_t rbytes = S * ntp * ntp * sizeof(double2);
+    const size_t pbytes = stream_partial_elems((int)S, ntp) * sizeof(double2);
+    if (hipMalloc((void**)&sm->rbuf[0], rbytes) != hipSuccess || hipMalloc((void**)&sm->rbuf[1], rbytes) != hipSuccess ||
+        hipMalloc((void**)&sm->part, pbytes) != hipSuccess) {
+        lcf_stream_destroy(sm);
+        return LCF_ERR_OUT_OF_MEMORY;
+    }
+    if (hipMemset(sm->rbuf[0], 0, rbytes) != hipSuccess || hipMemset(sm->rbuf[1], 0, rbytes) != hipSuccess) {
+        lcf_stream_destroy(sm);
+        return LCF_ERR_DEVICE;
+    }
+    *out = sm;
+    return LCF_OK;
+}
+
+lcf_status lcf_stream_push(lcf_stream* sm, const void* iq, int32_t hop, void* iq_out, float* pd,
+                           const lcf_diag* diag, void* stream) {
+    if (!sm || !iq || !pd) return LCF_ERR_INVALID_ARG;
+    const int nt = sm->geo.nt;
+    if (hop < 1 || hop > nt) return LCF_ERR_INVALID_ARG;
+    lcf_context* c = sm->ctx;
+    if (hipSetDevice(c->device) != hipSuccess) return LCF_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    lcf_status e = refuse_capture(st);
+    if (e != LCF_OK) return e;
+    if (!sm->primed) hop = nt;
+    Plan& pl = sm->plan;
+    for (SubsetDesc& sd : pl.sub) sd.iq = (const float2*)iq;
+    pl.pkts[0].iq = (const float2*)iq;
+    pl.pkts[0].iq_out = (float*)iq_out;
+    pl.pkts[0].pd = pd;
+    Staged sg;
+    e = stage_group(c, pl, &sm->thr, st, sg);
+    if (e != LCF_OK) return e;
+    const int nxt = 1 - sm->cur;
+    e = stream_chain(c, pl, sg, &sm->thr, sm->prec, sm->rbuf[sm->cur], sm->rbuf[nxt], sm->part, hop, diag, st);
+    if (e != LCF_OK) return e;
+    sm->cur = nxt;
+    sm->primed = true;
+    return LCF_OK;
+}
+
+lcf_status lcf_stream_destroy(lcf_stream* sm) {
+    if (!sm) return LCF_OK;
+    hipSetDevice(sm->ctx->device);
+    hipDeviceSynchronize();
+    for (void* p : {(void*)sm->rbuf[0], (void*)sm->rbuf[1], (void*)sm->part})
+        if (p) hipFree(p);
+    delete sm;
+    return LCF_OK;
 }
 
 lcf_status lcf_heevd_batched(lcf_context* ctx, int32_t n, int32_t nt, const double* a, double* w, double* v,

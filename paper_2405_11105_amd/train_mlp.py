@@ -106,8 +106,25 @@ def train(ctx, lam, tgt, epochs, batch, lr, seed=0, log=None):
     return hist
 
 
+def _pd_dev(pd, ref, mask_t):
+    """|10 log10(pd / ref)| over pixels with ref >= 2 x its median outside the
+    vessels dilated by 2 rows (p99, max)."""
+    import torch
+    bg = ~mask_t
+    for d in range(1, 3):
+        bg &= ~torch.roll(mask_t, d, 0) & ~torch.roll(mask_t, -d, 0)
+    floor = torch.median(ref[bg])
+    sel = ref >= 2 * floor
+    dev = (10 * torch.log10(pd[sel] / ref[sel])).abs().double()
+    return float(torch.quantile(dev, 0.99)), float(dev.max())
+
+
 def evaluate(ctx, lcf, kind, seeds, grid, prec, workers, log=None):
-    """Held-out comparison of rule (beta = 1), searched-beta teacher and MLP."""
+    """Held-out comparison of the plain rule (beta = 1), the searched-beta
+    teacher, the network alone (no gate) and the network behind the gate (the
+    context's LCF_OPT_MLP_GATE; rejected subsets keep the plain rule): CNR of
+    each, the power Doppler deviation of the network from the rule and from
+    the teacher, and the gate's fallback rate."""
     import torch
     rows = []
     ctxmp = mp.get_context("spawn")   # workers run numpy only and never touch the GPU
@@ -121,16 +138,28 @@ def evaluate(ctx, lcf, kind, seeds, grid, prec, workers, log=None):
             best = int(np.argmax(cnrs))
             thr_t = lcf.Threshold(cut=lcf.CUT_EXPLICIT)
             _, pd_t, _ = ctx.filter(iq, grid[0], grid[1], thr_t, precision=prec, iq_out=False, explicit_w=ws[best])
+            thr_r = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+            _, pd_r, _ = ctx.filter(iq, grid[0], grid[1], thr_r, precision=prec, iq_out=False)
             thr_m = lcf.Threshold(cut=lcf.CUT_MLP, shape=lcf.SHAPE_SIGMOID)
-            _, pd_m, dg = ctx.filter(iq, grid[0], grid[1], thr_m, precision=prec, iq_out=False, diag=True)
+            _, pd_g, dg = ctx.filter(iq, grid[0], grid[1], thr_m, precision=prec, iq_out=False, diag=True)
             fallback = float(((dg["flags"] & lcf.FLAG_MLP_FALLBACK) != 0).float().mean())
-            floor = torch.median(pd_t[~mask_t])
-            sel = pd_t >= 2 * floor
-            dev = (10 * torch.log10(pd_m[sel] / pd_t[sel])).abs()
-            rows.append({"seed": int(seed), "cnr_rule": cnrs[BETAS.index(1.0)], "cnr_teacher": cnrs[best],
-                         "cnr_mlp": cnr_db(pd_m, mask_t), "best_beta": BETAS[best],
-                         "pd_db_vs_teacher_p99": float(torch.quantile(dev.double(), 0.99)),
-                         "pd_db_vs_teacher_max": float(dev.max()), "fallback_rate": fallback})
+            gate = dg["mlp_gate"].double()
+            gate_mdb = ctx.options[lcf.OPT_MLP_GATE]
+            ctx.set_option(lcf.OPT_MLP_GATE, -1)
+            try:
+                _, pd_m, _ = ctx.filter(iq, grid[0], grid[1], thr_m, precision=prec, iq_out=False)
+            finally:
+                ctx.set_option(lcf.OPT_MLP_GATE, gate_mdb)
+            torch.cuda.synchronize()
+            r = {"seed": int(seed), "best_beta": BETAS[best], "cnr_rule": cnrs[BETAS.index(1.0)],
+                 "cnr_teacher": cnrs[best], "cnr_mlp": cnr_db(pd_m, mask_t), "cnr_gated": cnr_db(pd_g, mask_t),
+                 "fallback_rate": fallback, "gate_db_median": float(torch.median(gate))}
+            for name, pd in (("mlp", pd_m), ("gated", pd_g)):
+                for refn, ref in (("rule", pd_r), ("teacher", pd_t)):
+                    p99, mx = _pd_dev(pd, ref, mask_t)
+                    r[f"pd_db_{name}_vs_{refn}_p99"] = p99
+                    r[f"pd_db_{name}_vs_{refn}_max"] = mx
+            rows.append(r)
     return rows
 
 
@@ -146,6 +175,9 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", default="mlp.ckpt")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--eval-only", default=None, metavar="CKPT",
+                    help="skip the teacher data and training; evaluate this checkpoint on the held-out packets")
+    ap.add_argument("--gate-mdb", type=int, default=100, help="LCF_OPT_MLP_GATE for the evaluation")
     args = ap.parse_args(argv)
     import torch
     import paper_2405_11105_amd as lcf
@@ -154,20 +186,24 @@ def main(argv=None):
     prec = lcf.PREC_BF16X3 if args.precision == "bf16x3" else lcf.PREC_FP32
     log = lambda m: print(m, flush=True)
     ctx = lcf.Context(0)
-    t0 = time.time()
-    lam, tgt, info = generate(ctx, lcf, args.kind, range(base_train, base_train + args.train), grid, prec,
-                              args.workers, log=log)
-    log(f"teacher data: {lam.shape[0]} spectra from {args.train} packets in {time.time() - t0:.1f} s; "
-        f"best beta histogram {np.unique([i['best_beta'] for i in info], return_counts=True)}")
-    ctx.mlp_init(1)
-    t1 = time.time()
-    hist = train(ctx, lam, tgt, args.epochs, args.batch, args.lr, log=log)
-    log(f"training: {time.time() - t1:.1f} s")
-    ctx.mlp_save(args.out)
+    ctx.set_option(lcf.OPT_MLP_GATE, args.gate_mdb)
+    hist, info = [], []
+    if args.eval_only:
+        ctx.mlp_load(args.eval_only)
+    else:
+        t0 = time.time()
+        lam, tgt, info = generate(ctx, lcf, args.kind, range(base_train, base_train + args.train), grid, prec,
+                                  args.workers, log=log)
+        log(f"teacher data: {lam.shape[0]} spectra from {args.train} packets in {time.time() - t0:.1f} s; "
+            f"best beta histogram {np.unique([i['best_beta'] for i in info], return_counts=True)}")
+        ctx.mlp_init(1)
+        t1 = time.time()
+        hist = train(ctx, lam, tgt, args.epochs, args.batch, args.lr, log=log)
+        log(f"training: {time.time() - t1:.1f} s")
+        ctx.mlp_save(args.out)
     rows = evaluate(ctx, lcf, args.kind, range(base_hold, base_hold + args.holdout), grid, prec, args.workers,
                     log=log)
-    summ = {k: float(np.mean([r[k] for r in rows])) for k in
-            ("cnr_rule", "cnr_teacher", "cnr_mlp", "pd_db_vs_teacher_p99", "pd_db_vs_teacher_max", "fallback_rate")}
+    summ = {k: float(np.mean([r[k] for r in rows])) for k in rows[0] if k not in ("seed", "best_beta")}
     log("held-out mean: " + json.dumps(summ))
     if args.report:
         with open(args.report, "w") as f:

@@ -92,7 +92,15 @@ def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, pre
         f"trunc={trunc_sigmas} prec={precision}")
     geo = dict(sigma_frac=sigma_frac, trunc_sigmas=trunc_sigmas)
     io, pd, d = run_gpu(lcf, ctx, iq, gy, gx, thr, precision=precision, **geo)
-    res = O.filter_packet(iq, gy, gx, oracle_thr(thr), **geo)
+    e_fro, emax = compare_with_oracle(lcf, iq, mask, gy, gx, thr, io, pd, d, tol_fro, tol_db, **geo)
+    return e_fro, emax, io, pd
+
+
+def compare_with_oracle(lcf, iq, mask, gy, gx, thr, io, pd, d, tol_fro, tol_db, res=None, **geo):
+    """Decision and numeric parity of one packet's GPU outputs (io, pd, diag d)
+    with the oracle (``res``: its filter_packet result, computed if None)."""
+    if res is None:
+        res = O.filter_packet(iq, gy, gx, oracle_thr(thr), **geo)
     nd = gy * gx
     # decision parity: the oracle's FP64 rule on the GPU's eigenvalues
     forced = False
@@ -126,6 +134,6 @@ def check_end_to_end(lcf, ctx, iq, mask, gy, gx, thr, tol_fro, tol_db, name, pre
          f"sweeps={d['sweeps'].min()}..{d['sweeps'].max()} rank={d['rank'].min()}..{d['rank'].max()}")
     assert e_fro <= tol_fro
     assert emax <= tol_db
-    return e_fro, emax, io, pd
+    return e_fro, emax
 
 

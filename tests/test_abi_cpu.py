@@ -52,7 +52,9 @@ def test_validate_geometry_and_threshold(lcf):
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_SLOPE, slope_thr=float("nan"))) == 1
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_POWER, beta_power=2.0)) == 0
     assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_POWER, beta_power=0.0)) == 1
-    assert lcf.validate(ok, lcf.Threshold(cut=7)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_NCC)) == 0
+    assert lcf.validate(ok, lcf.Threshold(cut=lcf.CUT_NCC, shape=lcf.SHAPE_SIGMOID, beta_sigmoid=0.0)) == 1
+    assert lcf.validate(ok, lcf.Threshold(cut=8)) == 1
 
 
 def test_abi_version_matches_binding(lcf):

@@ -1,7 +1,9 @@
 """Parity of the benchmark's own configuration against the FP64 oracle: four
 512 x 256 x 128 packets, 16 x 16 Gaussian windows (256 subsets each), learned
-weights from the committed network, all packets in one batched call replayed
-from a captured hipGraph, in split-BF16 and in FP32."""
+weights from the committed network behind the default 0.1 dB gate (the plain
+curvature rule with sigmoid weights as fallback), all packets in one batched
+call replayed from a captured hipGraph, in split-BF16 and in FP32. The packets
+are held out from the network's training seeds."""
 import os
 
 import numpy as np
@@ -10,7 +12,7 @@ import pytest
 import oracle as O
 from oracle import mlp as M
 import synth
-from parity import say, rel_fro, pd_db_error
+from parity import say, rel_fro, pd_db_error, knee_tie
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -19,6 +21,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CKPT = os.path.join(ROOT, "paper_2405_11105_amd", "weights", "mlp_512x256x128.ckpt")
 SEEDS = [20000, 20001, 20002, 20003]       # the benchmark's packets
 GRID = (16, 16)
+GATE_DB = 0.1
+RULE = O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID)
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +43,8 @@ def network(lcf):
 
 @pytest.fixture(scope="module")
 def oracle_out(packets, network):
-    thr = O.Threshold(cut=O.CUT_MLP, mlp=lambda lam: M.forward(network, M.features(lam), bf16=True)[0][0])
+    thr = O.Threshold(cut=O.CUT_MLP, shape=O.SHAPE_SIGMOID, mlp_gate_db=GATE_DB,
+                      mlp=lambda lam: M.forward(network, M.features(lam), bf16=True)[0][0])
     out = []
     for i, (iq, _) in enumerate(packets):
         say(f"   oracle packet {i}")
@@ -80,11 +85,38 @@ def test_benchmark_configuration_vs_oracle(lcf, packets, network, oracle_out, pr
                 assert ectx.sync() == 0
                 assert np.array_equal(io1.cpu().numpy(), first[i][0]) and np.array_equal(pd1.cpu().numpy(), first[i][1])
                 d = {k: v.cpu().numpy() for k, v in dg.items()}
-                assert np.all((d["flags"] & lcf.FLAG_MLP_FALLBACK) == 0)
+                res = oracle_out[i]
+                fb = (d["flags"] & lcf.FLAG_MLP_FALLBACK) != 0
+                assert np.array_equal(fb, ~(d["mlp_gate"] < GATE_DB))
                 # the network's weights on the GPU's eigenvalues, in FP64 on the same BF16 weights
                 w_ref, _ = M.forward(network, M.features(d["eigvals"]), bf16=True)
-                ew = float(np.max(np.abs(d["weights"] - w_ref)))
-                res = oracle_out[i]
+                ew, gerr, forced = 0.0, 0.0, False
+                for s in range(GRID[0] * GRID[1]):
+                    lam = d["eigvals"][s]
+                    w_rule, k_rule, curv, _ = O.rule_weights(lam, RULE)
+                    g = O.mlp_gate(lam, w_ref[s], w_rule)
+                    assert np.isinf(g) == np.isinf(d["mlp_gate"][s]), s
+                    if np.isfinite(g):
+                        gerr = max(gerr, abs(g - d["mlp_gate"][s]))
+                    if abs(g - GATE_DB) > 0.01:
+                        assert fb[s] == (g >= GATE_DB), s
+                    if fb[s]:
+                        if d["k"][s] != k_rule:
+                            assert knee_tie(curv, int(d["k"][s]), k_rule), s
+                        else:
+                            assert np.allclose(d["weights"][s], w_rule, atol=1e-6), s
+                    else:
+                        ew = max(ew, float(np.max(np.abs(d["weights"][s] - w_ref[s]))))
+                    # the oracle's own decision (on its eigenvalues) may differ only at a tie
+                    fo = (res["flags"][s] & O.FLAG_MLP_FALLBACK) != 0
+                    if fo != fb[s] or (fb[s] and d["k"][s] != res["k"][s]):
+                        forced = True
+                say(f"   packet {i}: fallback {fb.mean():.3f}, gate prediction |gpu - oracle| {gerr:.1e} dB, "
+                    f"forced={forced}")
+                assert gerr <= 0.01
+                if forced:
+                    res = O.filter_packet(iq, GRID[0], GRID[1],
+                                          O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=d["weights"].astype(np.float64)))
                 lam_err = float(np.max(np.abs(d["eigvals"] - np.array(res["lam"])) / np.array(res["lam"])[:, :1]))
                 e_fro = rel_fro(first[i][0], res["iq_out"])
                 emax, e99, e999, npx = pd_db_error(first[i][1], res["pd"], mask)

@@ -137,8 +137,12 @@ def test_filter_with_mlp_weights(lcf, ctx):
     spec = synth.spec_clinical(1)
     iq, mask = synth.make_packet(spec)
     thr = lcf.Threshold(cut=lcf.CUT_MLP, shape=lcf.SHAPE_SIGMOID)
-    io, pd, dg = ctx.filter(torch.from_numpy(iq).cuda(), 8, 8, thr, diag=True)
-    torch.cuda.synchronize()
+    ctx.set_option(lcf.OPT_MLP_GATE, -1)          # an untrained network: no gate
+    try:
+        io, pd, dg = ctx.filter(torch.from_numpy(iq).cuda(), 8, 8, thr, diag=True)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(lcf.OPT_MLP_GATE, 100)
     assert ctx.sync() == 0
     d = {k: v.cpu().numpy() for k, v in dg.items()}
     assert np.all((d["flags"] & lcf.FLAG_MLP_FALLBACK) == 0)
@@ -150,6 +154,58 @@ def test_filter_with_mlp_weights(lcf, ctx):
     emax, _, _, _ = pd_db_error(pd.cpu().numpy(), res["pd"], mask)
     _say(f"   rel_fro={e_fro:.2e} pd_db={emax:.2e}")
     assert e_fro <= 1e-5 and emax <= 0.1
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mlp_gate_forced_and_consistent(lcf, ctx, prec):
+    """Gate at 0 dB: every subset keeps the plain rule (flagged), and the
+    outputs are bitwise those of the curvature rule with sigmoid weights. Gate
+    at 0.1 dB: each subset's decision follows its exported prediction, and the
+    prediction matches the oracle's on the GPU's eigenvalues and network
+    weights (FP64 forward on the same BF16 weights)."""
+    _say(f"[mlp gate prec={prec}]")
+    ctx.mlp_init(21)
+    p = M.unflatten(ctx.mlp_get_params())
+    iq, mask = synth.make_packet(synth.spec_clinical(2))
+    dev = torch.from_numpy(iq).cuda()
+    thr = lcf.Threshold(cut=lcf.CUT_MLP, shape=lcf.SHAPE_SIGMOID)
+    ctx.set_option(lcf.OPT_MLP_GATE, 0)
+    try:
+        io, pd, dg = ctx.filter(dev, 8, 8, thr, precision=prec, diag=True)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(lcf.OPT_MLP_GATE, 100)
+    assert np.all(dg["flags"].cpu().numpy() & lcf.FLAG_MLP_FALLBACK)
+    io_r, pd_r, dg_r = ctx.filter(dev, 8, 8, lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID),
+                                  precision=prec, diag=True)
+    torch.cuda.synchronize()
+    assert torch.equal(io, io_r) and torch.equal(pd, pd_r)
+    w_rule_gpu = dg_r["weights"].cpu().numpy()
+    # default gate: decisions and predictions
+    io, pd, dg = ctx.filter(dev, 8, 8, thr, precision=prec, diag=True)
+    torch.cuda.synchronize()
+    assert ctx.sync() == 0
+    d = {k: v.cpu().numpy() for k, v in dg.items()}
+    fb = (d["flags"] & lcf.FLAG_MLP_FALLBACK) != 0
+    assert np.array_equal(fb, ~(d["mlp_gate"] < 0.1))
+    w_net, _ = M.forward(p, M.features(d["eigvals"]), bf16=True)
+    rule = O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID)
+    worst = 0.0
+    for s in range(64):
+        w_rule, _, _, _ = O.rule_weights(d["eigvals"][s], rule)
+        g = O.mlp_gate(d["eigvals"][s], w_net[s], w_rule)
+        if np.isinf(g) or np.isinf(d["mlp_gate"][s]):
+            assert np.isinf(g) and np.isinf(d["mlp_gate"][s]), s
+            continue
+        worst = max(worst, abs(g - d["mlp_gate"][s]))
+        if abs(g - 0.1) > 0.01:
+            assert fb[s] == (g >= 0.1), s
+        if fb[s]:
+            assert np.array_equal(d["weights"][s], w_rule_gpu[s]), s
+        else:
+            assert np.allclose(d["weights"][s], w_net[s], atol=2e-5), s
+    _say(f"   fallback {fb.mean():.2f}; prediction max |gpu - oracle| {worst:.2e} dB")
+    assert worst <= 0.01
 
 
 def test_mlp_fallback_for_other_nt(lcf, ctx):
@@ -185,5 +241,8 @@ def test_learned_weights_gain_over_fixed_rule(lcf, ctx):
     teach = np.array([r["cnr_teacher"] for r in rows])
     _say(f"   held-out CNR dB: rule(beta=1) {rule.mean():.2f}  mlp {mlp_.mean():.2f}  searched-beta {teach.mean():.2f}")
     _say(f"   per packet gain mlp-rule: {np.round(mlp_ - rule, 2).tolist()}")
+    _say(f"   behind the 0.1 dB gate: CNR {np.mean([r['cnr_gated'] for r in rows]):.2f} dB, fallback "
+         f"{np.mean([r['fallback_rate'] for r in rows]):.2f}, PD vs rule p99 "
+         f"{np.mean([r['pd_db_gated_vs_rule_p99'] for r in rows]):.3f} dB")
     assert hist[-1] < hist[0]
     assert mlp_.mean() > rule.mean()

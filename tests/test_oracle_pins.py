@@ -508,3 +508,57 @@ def test_ncc_rule_shapes_and_degenerate():
     lam0, v0 = O.evd(O.covariance(z))
     c0 = O.ncc_curve(z, lam0, v0)
     assert np.all(np.isnan(c0)) and O.ncc_k(c0) == (0, O.lcf_oracle.FLAG_NONPOSITIVE)
+
+
+def test_sliding_packets_share_covariance_block():
+    """Consecutive sliding packets (hop h) share every frame pair but the new
+    ones: R_{p+1}[:nt-h, :nt-h] = R_p[h:, h:] for every window (Eq. 12 sums
+    over the same pixels and frame pairs), the identity an incremental
+    covariance update relies on; the last h rows and columns are new."""
+    import synth
+    nt, hop = 20, 4
+    spec = synth.PacketSpec(24, 20, nt + 3 * hop, 50.0, 0.4, ((8, 2, 0.6),), seed=11)
+    rec, _ = synth.make_packet(spec)
+    res = O.filter_stream(rec, nt, hop, 2, 2, O.Threshold(cut=O.CUT_FIXED_K, k_fixed=2))
+    assert len(res) == 4
+    for p in range(3):
+        for d in range(4):
+            a, b = res[p]["cov"][d], res[p + 1]["cov"][d]
+            assert np.allclose(b[:nt - hop, :nt - hop], a[hop:, hop:], rtol=1e-12, atol=1e-12 * abs(a[0, 0]))
+            # the new frames do change the rest
+            assert not np.allclose(b[nt - hop:, :], a[nt - hop:, :])
+
+
+def test_mlp_gate_hand_worked_and_invariances():
+    """Gate statistic of two weight sets: hand-worked two-component case, zero
+    for equal or proportional weights (Eq. 13 normalises the filtered energy),
+    +inf when only one set keeps a component."""
+    lam = np.array([4.0, 1.0])
+    # shares p = [0.16, 1] / 1.16, q = [0.04, 1] / 1.04
+    g = O.mlp_gate(lam, np.array([0.1, 1.0]), np.array([0.2, 1.0]))
+    p0, q0 = 0.16 / 1.16, 0.04 / 1.04
+    assert abs(g - abs(10 * np.log10(q0 / p0))) < 1e-12
+    assert abs(g - 5.5464) < 1e-4
+    w = np.array([0.3, 0.9, 1.0, 0.2])
+    l4 = np.array([10.0, 3.0, 1.0, 0.5])
+    assert O.mlp_gate(l4, w, w) == 0.0
+    assert abs(O.mlp_gate(l4, 0.37 * w, w)) < 1e-12
+    assert O.mlp_gate(lam, np.array([0.5, 1.0]), np.array([0.0, 1.0])) == np.inf
+    # a component below the share in both sets is ignored
+    assert O.mlp_gate(np.array([1e-6, 1.0]), np.array([1.0, 1.0]), np.array([0.5, 1.0])) < 1e-5
+
+
+def test_mlp_gate_bounds_recombined_power_doppler():
+    """With no share cut the gate is a bound: on a small windowed packet, the
+    Eq. 13 power Doppler of the filter with one weight set differs from the
+    other's by at most the gate's largest subset value, at every pixel."""
+    rng = np.random.default_rng(5)
+    nt, ny, nx = 10, 9, 8
+    iq = (rng.standard_normal((nt, ny, nx)) + 1j * rng.standard_normal((nt, ny, nx))).astype(np.complex64)
+    w_rule = np.tile(O.sigmoid_weights(nt, 3, 2.0), (4, 1))
+    w_net = np.clip(w_rule + 0.2 * rng.standard_normal(w_rule.shape), 0.05, 1.0)
+    ra = O.filter_packet(iq, 2, 2, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=w_rule))
+    rb = O.filter_packet(iq, 2, 2, O.Threshold(cut=O.CUT_EXPLICIT, explicit_w=w_net))
+    g = max(O.mlp_gate(ra["lam"][d], w_net[d], w_rule[d], share=0.0) for d in range(4))
+    dev = np.abs(10 * np.log10(rb["pd"] / ra["pd"]))
+    assert 0.0 < dev.max() <= g + 1e-9
