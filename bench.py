@@ -13,15 +13,19 @@ Two configurations of the same library are timed on the same packets:
           and the paper's loop over subsets (one subset at a time through every
           per-subset stage), no graph.
 `value` is the fast configuration's frames/s on the 512 x 256 x 128 learned
-workload; the plain one is reported beside it, with ablations (one change at a
-time), the same comparison on the 256 x 192 x 128 clinical packets and on the
-64-packet uneven stream, per-kernel roofline figures, and the FP64 CPU oracle
-timed on the host cores. Fast and plain are checked against the oracle on
+workload (the network behind the library's default 0.1 dB gate, which keeps the
+plain rule for every subset where the network's predicted power Doppler
+deviation is larger; the fallback rate is reported); the plain one is reported
+beside it, with ablations (one change at a time), the same comparison on the
+256 x 192 x 128 clinical packets and on the 64-packet uneven stream, sliding
+packets (hop 5) at the learned workload's shape, per-kernel roofline figures,
+and the FP64 CPU oracle timed on the host cores. Fast and plain are checked against the oracle on
 packet 0; the value is withheld (null, exit status 1) when the fast path
 misses 1e-3 relative Frobenius error or 0.1 dB power Doppler error there.
 Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--batch B] [--workload learned|clinical|small]
+                  [--extra clinical,stream,slide]
 """
 import argparse
 import json
@@ -558,7 +562,9 @@ def main():
         "mlp_fallback_rate": fallback,
         "mlp_gate_db": gate_q,
         "autotune": {t[0]: {"gram_chunk_px": int(t[1]), "reproj_tile_rows": int(t[2]),
-                            "reproj_producer_consumer": bool(int(t[3]))} for t in tuned},
+                            "reproj_producer_consumer": bool(int(t[3])),
+                            "evd": {"-1": "context default", "0": "tridiagonal", "1": "jacobi"}[t[4]]}
+                     for t in tuned},
         "wall_s": wall,
     }
     print(json.dumps(out))

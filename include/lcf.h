@@ -186,10 +186,13 @@ typedef struct {
                                    chunk {512..4096 px} x reprojection kernel (tiles of
                                    2 or 4 rows; with 4 rows, all waves alike or split
                                    into producer and consumer waves)
-                                   on the call's own packets and keep the fastest
+                                   on the call's own packets and keep the fastest, then,
+                                   up to 128 frames, the other subset EVD method
+                                   (LCF_OPT_EVD values) on the winning plan
                                    (default 0: 1024 px, 4 rows up to 128 frames, else 2;
-                                   producer/consumer waves for FP32 only). Tuning
-                                   is skipped while the stream is being captured.          */
+                                   producer/consumer waves for FP32 only; the context's
+                                   EVD method). Tuning is skipped while the stream is
+                                   being captured.                                        */
 
 #define LCF_OPT_EVD          7  /* subset EVD (Eq. 2) up to 128 frames: 0 = Householder
                                    tridiagonal reduction, multisection eigenvalues and
@@ -372,7 +375,8 @@ lcf_status lcf_stage_time(lcf_context* ctx, int32_t stage, double* ms, int64_t* 
 
 /* Autotuner choices (batched form of many packets and subsets, Discussion:
  * parallel processing of subsets) as text, one line per launch-group class:
- * "<class> <chunk> <rows> <variant>". lcf_tune_save writes the context's choices to `path`;
+ * "<class> <chunk> <rows> <variant> <evd>" (evd: 0 tridiagonal, 1 Jacobi, -1 the
+ * context's LCF_OPT_EVD; lines without it are read as -1). lcf_tune_save writes the context's choices to `path`;
  * lcf_tune_load adds the choices in `path` to the context (replacing entries of
  * the same class) and drops captured graphs. Errors: LCF_ERR_INVALID_ARG for
  * NULL arguments, an unreadable/unwritable file or a malformed line (nothing is

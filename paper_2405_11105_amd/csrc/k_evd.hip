@@ -1455,6 +1455,238 @@ __global__ void __launch_bounds__(64 * (NW < 4 ? NW : 4)) k_heev_tri_vecs(Worksp
     }
 }
 
+// Subset EVD above 128 frames (padded sizes 160 and 208), steps 1-3 of the
+// tridiagonal path with the matrix in global memory: the register layout of
+// k_heev_tri_vals would not fit the register file at these sizes. The working
+// copy A (column-major, the projector slot of the subset) is reduced column by
+// column: the reflector v of column j (one block reduction), p = tau A v over
+// the trailing block (thread (g, r): row r, every fourth column from j + 1 + g,
+// so each load runs along a column), q = p - (tau / 2)(v^H p) v, and the
+// two-sided update A -= v q^H + q v^H of the trailing block. The reflectors go
+// where k_heev_tri_vecs reads them (tau in row 0 of v_j, which is zero), the
+// tridiagonal form to the same scratch, and a subset whose eigenvalues are
+// closer than 1e-12 lambda_1 keeps B (row-major, untouched here) for the
+// Jacobi kernel.
+template <int N, int RPL>
+__global__ void __launch_bounds__(1024) k_heev_big_vals(Workspace ws) {
+    constexpr int NTHR = 1024, NG = NTHR / 256;
+    static_assert(N <= 256 && 64 * RPL >= N, "rows per lane of the scan cover the size");
+    __shared__ double2 vsh[N], qsh[N];
+    __shared__ double2 psum[NG][256];
+    __shared__ double dsh[N], esh[N], e2sh[N], lamsh[N];
+    __shared__ double2 phs[N];
+    __shared__ double redd[32];
+    __shared__ double bnd[3];
+    __shared__ double tau_sh;
+    __shared__ int gcnt[NTHR];
+    __shared__ int cluster;
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = tid & 255, g = tid >> 8;
+    const int nt = ws.sub[s].nt;
+    const double2* Bm = ws.bmat + (long)s * N * N;
+    double2* A = ws.pmat + (long)s * N * N;                  // working copy, A[c * N + r] = B[r][c]
+    double2* H = ws.wvec + (long)s * N * N;
+    double* trid = reinterpret_cast<double*>(ws.pmat + (long)s * N * N) + N * N;
+    if (tid == 0) cluster = 0;
+    for (int e = tid; e < N * N; e += NTHR) {
+        const int c = e / N, rr = e % N;
+        A[e] = (rr < nt && c < nt) ? cconj(Bm[(long)c * N + rr]) : make_double2(0.0, 0.0);   // B[rr][c]
+    }
+    auto block_sum = [&](double v) {
+        v = wave_sum(v);
+        __syncthreads();
+        if (lane == 0) redd[wave] = v;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < NTHR / 64; ++w) t += redd[w];
+        return t;
+    };
+    __syncthreads();
+    for (int j = 0; j + 2 < nt; ++j) {
+        // reflector of column j (rows j + 1 ..)
+        const double2 x = (tid > j && tid < nt) ? A[(long)j * N + tid] : make_double2(0.0, 0.0);
+        const double s2 = block_sum(tid > j + 1 ? cabs2(x) : 0.0);
+        if (tid == j + 1) {
+            const double ax0 = sqrt(cabs2(x));
+            const double alpha = sqrt(s2 + ax0 * ax0);
+            const double2 ph = ax0 > 0.0 ? cscale(x, 1.0 / ax0) : make_double2(1.0, 0.0);
+            tau_sh = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+            vsh[tid] = cadd(x, cscale(ph, alpha));
+            phs[j] = cscale(ph, -alpha);                          // complex e_j for now
+            dsh[j] = A[(long)j * N + j].x;
+        } else if (tid < N) {
+            vsh[tid] = tid > j + 1 ? x : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        const double tau = tau_sh;
+        if (tid < N) H[(long)j * N + tid] = tid == 0 ? make_double2(tau, 0.0) : vsh[tid];
+        // p = A v over the trailing block
+        double2 acc = make_double2(0.0, 0.0);
+        if (r > j && r < nt) {
+            for (int c = j + 1 + g; c < nt; c += NG) {
+                const double2 a = A[(long)c * N + r], vc = vsh[c];
+                acc.x = fma(a.x, vc.x, fma(-a.y, vc.y, acc.x));
+                acc.y = fma(a.x, vc.y, fma(a.y, vc.x, acc.y));
+            }
+        }
+        psum[g][r] = acc;
+        __syncthreads();
+        double2 pr = make_double2(0.0, 0.0), vr = make_double2(0.0, 0.0);
+        if (tid < N) {
+            for (int gg = 0; gg < NG; ++gg) pr = cadd(pr, psum[gg][tid]);
+            pr = cscale(pr, tau);
+            vr = vsh[tid];
+        }
+        const double kr = block_sum(vr.x * pr.x + vr.y * pr.y);   // Re conj(v) p
+        const double ki = block_sum(vr.x * pr.y - vr.y * pr.x);   // Im conj(v) p
+        if (tid < N) {
+            const double2 K = make_double2(0.5 * tau * kr, 0.5 * tau * ki);
+            qsh[tid] = csub(pr, cmul(K, vr));
+        }
+        __syncthreads();
+        // A -= v q^H + q v^H on the trailing block
+        if (r > j && r < nt) {
+            const double2 v_r = vsh[r], q_r = qsh[r];
+            for (int c = j + 1 + g; c < nt; c += NG) {
+                const double2 vc = vsh[c], qc = qsh[c];
+                double2 a = A[(long)c * N + r];
+                a.x = fma(-v_r.x, qc.x, fma(-v_r.y, qc.y, a.x));
+                a.y = fma(-v_r.y, qc.x, fma(v_r.x, qc.y, a.y));
+                a.x = fma(-q_r.x, vc.x, fma(-q_r.y, vc.y, a.x));
+                a.y = fma(-q_r.y, vc.x, fma(q_r.x, vc.y, a.y));
+                A[(long)c * N + r] = a;
+            }
+        }
+        __syncthreads();
+    }
+    // last 2 x 2 block
+    if (tid == 0 && nt >= 2) {
+        dsh[nt - 2] = A[(long)(nt - 2) * N + nt - 2].x;
+        dsh[nt - 1] = A[(long)(nt - 1) * N + nt - 1].x;
+        phs[nt - 2] = A[(long)(nt - 2) * N + nt - 1];            // row nt - 1, column nt - 2
+    }
+    if (tid == 0 && nt == 1) dsh[0] = A[0].x;
+    __syncthreads();
+    // ---- 2. real tridiagonal: |e_j|, the phases D by a prefix product (wave 0,
+    // element j in lane j % 64, register j / 64) and the Gershgorin interval
+    if (wave == 0) {
+        double2 u[RPL];
+        double ae[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int j = lane + 64 * i;
+            const double2 e = j + 1 < nt ? phs[j] : make_double2(0.0, 0.0);
+            ae[i] = sqrt(cabs2(e));
+            u[i] = ae[i] > 0.0 ? cscale(e, 1.0 / ae[i]) : make_double2(1.0, 0.0);
+            if (j + 1 < nt) {
+                esh[j] = ae[i];
+                e2sh[j] = ae[i] * ae[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const double2 t = make_double2(__shfl_up(u[i].x, off, 64), __shfl_up(u[i].y, off, 64));
+                if (lane >= off) u[i] = cmul(t, u[i]);
+            }
+        double2 carry = make_double2(1.0, 0.0);
+        double lo = 1e300, hi = -1e300, emax = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const double2 incl = cmul(carry, u[i]);
+            const double2 prev = make_double2(__shfl_up(incl.x, 1, 64), __shfl_up(incl.y, 1, 64));
+            const int j = lane + 64 * i;
+            if (j < N) phs[j] = lane == 0 ? carry : prev;
+            carry = make_double2(rdl(incl.x, 63), rdl(incl.y, 63));
+            const double aup = __shfl_up(ae[i], 1, 64);
+            const double aprv = lane == 0 ? (i > 0 ? rdl(ae[i > 0 ? i - 1 : 0], 63) : 0.0) : aup;
+            if (j < nt) {
+                const double rad = (j > 0 ? aprv : 0.0) + (j + 1 < nt ? ae[i] : 0.0);
+                lo = fmin(lo, dsh[j] - rad);
+                hi = fmax(hi, dsh[j] + rad);
+                if (j + 1 < nt) emax = fmax(emax, ae[i] * ae[i]);
+            }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, m, 64));
+            hi = fmax(hi, __shfl_xor(hi, m, 64));
+            emax = fmax(emax, __shfl_xor(emax, m, 64));
+        }
+        if (lane == 0) {
+            const double margin = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+            bnd[0] = lo - margin;
+            bnd[1] = hi + margin;
+            bnd[2] = 1e-290 * fmax(1.0, emax);                        // pivmin
+        }
+    }
+    __syncthreads();
+    const double pivmin = bnd[2];
+    // ---- 3. eigenvalues: Sturm counts at NTHR grid points bracket every
+    // eigenvalue, then multisection with four lanes per eigenvalue
+    {
+        const double lo = bnd[0], hi = bnd[1];
+        auto sturm = [&](double xx) {
+            double q = dsh[0] - xx;
+            int c = q < 0.0;
+            for (int i = 1; i < nt; ++i) {
+                if (fabs(q) < pivmin) q = -pivmin;
+                q = (dsh[i] - xx) - e2sh[i - 1] * rcp_nr(q);
+                c += q < 0.0;
+            }
+            return c;
+        };
+        auto grid = [&](int gi) {
+            if (hi <= 0.0) return lo + (hi - lo) * (double)gi / (double)(NTHR - 1);
+            if (gi == 0) return lo;
+            return fmax(lo, hi * exp2(-64.0 * (double)(NTHR - 1 - gi) / (double)(NTHR - 2)));
+        };
+        gcnt[tid] = sturm(grid(tid));
+        __syncthreads();
+        const int k = tid >> 2, m = tid & 3;
+        const int target = nt - 1 - k;
+        int g0 = 0, g1 = NTHR - 1;
+        while (g1 - g0 > 1) {
+            const int gm = (g0 + g1) >> 1;
+            if (gcnt[gm] <= target) g0 = gm;
+            else g1 = gm;
+        }
+        double a = grid(g0), b = g1 == NTHR - 1 ? hi : grid(g1);
+        const double tol = (hi - lo) * 1.7e-17;
+        for (int it = 0; it < 24 && b - a > tol; ++it) {
+            const double h = (b - a) * 0.2;
+            const double xx = a + (double)(m + 1) * h;
+            const int cnt = k < nt ? sturm(xx) : 0;
+            int le = cnt <= target;
+            le += __shfl_xor(le, 1, 64);
+            le += __shfl_xor(le, 2, 64);
+            const double na = a + (double)le * h;
+            b = le == 4 ? b : a + (double)(le + 1) * h;
+            a = na;
+        }
+        if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
+    }
+    __syncthreads();
+    if (tid < nt) {
+        ws.lam[(long)s * N + tid] = lamsh[tid];
+        if (tid + 1 < nt && lamsh[tid] - lamsh[tid + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
+    }
+    for (int i = tid; i < N; i += NTHR) {
+        trid[i] = dsh[i];
+        trid[N + i] = esh[i];
+        trid[2 * N + i] = e2sh[i];
+        trid[3 * N + i] = phs[i].x;
+        trid[4 * N + i] = phs[i].y;
+    }
+    if (tid == 0) {
+        trid[5 * N] = pivmin;
+        ws.sweeps[s] = 0;
+    }
+    __syncthreads();
+    if (cluster && tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
+}
+
 // Normalise columns, sort by norm descending, write eigenvalues and vectors.
 // vout: column-major (vector j contiguous) when col_major, else row-major.
 __device__ void jacobi_finish(const double2* G, int nt, int ld, double* lam_out, double2* vout,
@@ -1491,9 +1723,10 @@ __device__ void jacobi_finish(const double2* G, int nt, int ld, double* lam_out,
 // Subset EVD: bmat (row-major Hermitian, stride ntp) -> wvec as column-major
 // Jacobi workspace -> sorted eigenvectors back into bmat (column-major).
 template <bool IN_LDS>
-__global__ void __launch_bounds__(JAC_THREADS) k_jacobi_subsets(Workspace ws, int max_sweeps) {
+__global__ void __launch_bounds__(JAC_THREADS) k_jacobi_subsets(Workspace ws, int max_sweeps, int only_flag) {
     extern __shared__ double2 lds_g[];
     const int s = blockIdx.x;
+    if (only_flag != 0 && (ws.flags[s] & only_flag) == 0) return;   // not selected: whole block exits
     const int nt = ws.sub[s].nt, ntp = ws.ntp;
     double2* B = ws.bmat + (long)s * ntp * ntp;
     double2* G = IN_LDS ? lds_g : ws.wvec + (long)s * ntp * ntp;
@@ -1615,20 +1848,35 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
         hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
+    // Beyond 128 frames: the tridiagonal path with the matrix in global memory
+    // (method 0) and the LDS / global Jacobi for the subsets it flags, or the
+    // Jacobi for all (method 1).
+    if (method == 0) {
+        if (ws.ntp == 160) hipLaunchKernelGGL((k_heev_big_vals<160, 3>), dim3(ws.S), dim3(1024), 0, st, ws);
+        else hipLaunchKernelGGL((k_heev_big_vals<208, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
+    }
     if (nt_max <= JAC_LDS_NT) {
         const size_t lds = (size_t)nt_max * nt_max * sizeof(double2);
-        hipLaunchKernelGGL((k_jacobi_subsets<true>), dim3(ws.S), dim3(JAC_THREADS), lds, st, ws, max_sweeps);
+        hipLaunchKernelGGL((k_jacobi_subsets<true>), dim3(ws.S), dim3(JAC_THREADS), lds, st, ws, max_sweeps, sel);
     } else {
-        hipLaunchKernelGGL((k_jacobi_subsets<false>), dim3(ws.S), dim3(JAC_THREADS), 0, st, ws, max_sweeps);
+        hipLaunchKernelGGL((k_jacobi_subsets<false>), dim3(ws.S), dim3(JAC_THREADS), 0, st, ws, max_sweeps, sel);
     }
     return hipGetLastError();
 }
 
-// Eigenvectors after the weights are known (tridiagonal solver, up to 128
-// frames); the Jacobi paths produced theirs already.
+// Eigenvectors after the weights are known (tridiagonal paths, at every size);
+// the Jacobi paths produced theirs already.
 hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStream_t st) {
     if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
-    if (method != 0 || ws.ntp > 128) return hipSuccess;
+    if (method != 0) return hipSuccess;
+    if (ws.ntp == 160) {
+        hipLaunchKernelGGL((k_heev_tri_vecs<3, 10>), dim3(ws.S), dim3(256), 0, st, ws, all);
+        return hipGetLastError();
+    }
+    if (ws.ntp == 208) {
+        hipLaunchKernelGGL((k_heev_tri_vecs<4, 13>), dim3(ws.S), dim3(256), 0, st, ws, all);
+        return hipGetLastError();
+    }
     if (ws.ntp <= 32) hipLaunchKernelGGL((k_heev_tri_vecs<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, all);
     else if (ws.ntp <= 64) hipLaunchKernelGGL((k_heev_tri_vecs<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, all);
     else if (ws.ntp == 96) hipLaunchKernelGGL((k_heev_tri_vecs<2, 6>), dim3(ws.S), dim3(256), 0, st, ws, all);

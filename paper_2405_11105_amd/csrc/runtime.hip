@@ -141,6 +141,7 @@ struct TuneChoice {
     int chunk;      // split-K chunk of the Gram passes (box pixels)
     int trows;      // image rows per reprojection tile
     int rvar;       // reprojection kernel variant
+    int evd;        // subset EVD up to 128 frames: 0 tridiagonal, 1 Jacobi; -1 the context's
 };
 
 struct PacketIn {
@@ -157,6 +158,7 @@ struct Plan {
     int chunk = CHUNK;      // split-K chunk of the Gram passes (box pixels)
     int trows = 2;          // image rows per reprojection tile (2 or 4)
     int rvar = 0;           // reprojection kernel variant (1: producer/consumer, 4-row tiles only)
+    int evd = -1;           // subset EVD method (LCF_OPT_EVD values); -1 the context's
     std::vector<SubsetDesc> sub;
     std::vector<ChunkDesc> chunks;
     std::vector<int> chunk_begin;
@@ -403,8 +405,8 @@ std::string graph_key(lcf_context* c, const Plan& pl, const std::vector<PacketIn
     k += buf;
     std::snprintf(buf, sizeof buf, "|m%.17g,%.17g,%.17g", thr->beta_median, thr->slope_thr, thr->beta_power);
     k += buf;
-    std::snprintf(buf, sizeof buf, "|c%d,r%d,v%d,e%d,g%ld", pl.chunk, pl.trows, pl.rvar, c->evd_method,
-                  c->mlp_gate_mdb);
+    std::snprintf(buf, sizeof buf, "|c%d,r%d,v%d,e%d,g%ld", pl.chunk, pl.trows, pl.rvar,
+                  pl.evd >= 0 ? pl.evd : c->evd_method, c->mlp_gate_mdb);
     k += buf;
     if (diag) {
         std::snprintf(buf, sizeof buf, "|d%p,%p,%p,%p,%p,%p,%p,%p,%p,%p,%p", (void*)diag->eigvals,
@@ -642,15 +644,15 @@ lcf_status run_stages(lcf_context* c, const Workspace& ws, const lcf_threshold* 
 }
 
 lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold* thr, int prec, int nt_max,
-                       int all_vectors, float* mlp_scratch, hipStream_t st) {
+                       int all_vectors, float* mlp_scratch, int evd, hipStream_t st) {
     const bool mlp = thr->cut == LCF_CUT_MLP;
     RuleParams rp{mlp ? (int)LCF_CUT_KNEE : thr->cut, thr->shape, thr->pd_mode, thr->k_fixed, thr->beta_knee,
                   thr->knee_max_frac, thr->beta_sigmoid, thr->beta_median, thr->slope_thr, thr->beta_power};
-    { STAGE(c, LCF_STAGE_EVD, st); HIPCHK(launch_evd(ws, c->max_sweeps, nt_max, c->evd_method, st)); }
+    { STAGE(c, LCF_STAGE_EVD, st); HIPCHK(launch_evd(ws, c->max_sweeps, nt_max, evd, st)); }
     const bool ncc = thr->cut == LCF_CUT_NCC;
     if (ncc) {
         // method 4 reads every eigenvector before the cut is known
-        { STAGE(c, LCF_STAGE_EVD_VECTORS, st); HIPCHK(launch_evd_vectors(ws, c->evd_method, 1, st)); }
+        { STAGE(c, LCF_STAGE_EVD_VECTORS, st); HIPCHK(launch_evd_vectors(ws, evd, 1, st)); }
         { STAGE(c, LCF_STAGE_NCC, st); HIPCHK(launch_ncc(ws, st)); }
     }
     { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
@@ -672,7 +674,7 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     }
     if (!ncc) {
         STAGE(c, LCF_STAGE_EVD_VECTORS, st);
-        HIPCHK(launch_evd_vectors(ws, c->evd_method, all_vectors, st));
+        HIPCHK(launch_evd_vectors(ws, evd, all_vectors, st));
     }
     { STAGE(c, LCF_STAGE_PROJECTOR, st); HIPCHK(launch_projector(ws, prec, st)); }
     return LCF_OK;
@@ -772,6 +774,7 @@ lcf_status stage_group(lcf_context* c, const Plan& pl, const lcf_threshold* thr,
 lcf_status run_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf_threshold* thr, int prec,
                      const lcf_diag* diag, hipStream_t st) {
     const Workspace& ws = sg.ws;
+    const int evd = pl.evd >= 0 ? pl.evd : c->evd_method;
     lcf_status e;
     if (c->schedule == 1) {
         // the paper's loop: one subset at a time through every per-subset stage
@@ -783,13 +786,13 @@ lcf_status run_chain(lcf_context* c, const Plan& pl, const Staged& sg, const lcf
             double2* cv = (diag && diag->cov) ? (double2*)diag->cov + (long)s * pl.sub[s].nt * pl.sub[s].nt : nullptr;
             e = run_stages(c, v, thr, prec, cv, pl.sub[s].nt, st);
             if (e != LCF_OK) return e;
-            e = run_stages2(c, v, thr, prec, pl.sub[s].nt, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, st);
+            e = run_stages2(c, v, thr, prec, pl.sub[s].nt, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, evd, st);
             if (e != LCF_OK) return e;
         }
     } else {
         e = run_stages(c, ws, thr, prec, diag ? (double2*)diag->cov : nullptr, pl.sub[0].nt, st);
         if (e != LCF_OK) return e;
-        e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, st);
+        e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, evd, st);
         if (e != LCF_OK) return e;
     }
     { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
@@ -815,9 +818,11 @@ std::string tune_key(const Plan& pl, int prec, int schedule) {
     return buf;
 }
 
-// Time every (split-K chunk, tile rows) candidate on the caller's packets with
-// HIP events (one untimed run, one timed run each) and keep the fastest. The
-// outputs end up written by the last candidate; the caller's run overwrites them.
+// Time every (split-K chunk, reprojection tile) candidate on the caller's
+// packets with HIP events (one untimed run, one timed run each) and keep the
+// fastest; then, up to 128 frames, the other subset EVD method (tridiagonal
+// solver or Jacobi) on the winning plan. The outputs end up written by the last
+// candidate; the caller's run overwrites them.
 lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std::vector<int>& idx,
                       const lcf_threshold* thr, int prec, hipStream_t st, const std::string& key) {
     static const int chunks[] = {512, 1024, 2048, 4096};
@@ -827,31 +832,35 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
     const int saved_timing = c->timing;
     c->timing = 0;
     float best = 0.f;
-    TuneChoice choice{CHUNK, 2, 0};
+    TuneChoice choice{CHUNK, 2, 0, c->evd_method};
     lcf_status res = LCF_OK;
     int ntp = 0;
     for (int i : idx) ntp = std::max(ntp, ntp_class(in[i].g.nt));
+    auto trial = [&](int ch, int rows, int var, int evd) -> bool {
+        Plan pl;
+        build_plan(pl, in, idx, thr->pd_mode, ch, rows, var);
+        pl.evd = evd;
+        Staged sg;
+        res = stage_group(c, pl, thr, st, sg);
+        if (res != LCF_OK) return false;
+        res = run_chain(c, pl, sg, thr, prec, nullptr, st);
+        if (res != LCF_OK) return false;
+        if (hipEventRecord(e0, st) != hipSuccess) { res = LCF_ERR_DEVICE; return false; }
+        res = run_chain(c, pl, sg, thr, prec, nullptr, st);
+        if (res != LCF_OK) return false;
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { res = LCF_ERR_DEVICE; return false; }
+        if (best == 0.f || ms < best) { best = ms; choice = TuneChoice{ch, rows, var, evd}; }
+        return true;
+    };
     std::vector<std::pair<int, int>> tiles = {{2, 0}};                 // (rows, variant)
     if (trows_max(ntp) >= 4) { tiles.push_back({4, 0}); tiles.push_back({4, 1}); }
-    for (const auto& tv : tiles) {
-        if (res != LCF_OK) break;
-        for (int ch : chunks) {
-            Plan pl;
-            build_plan(pl, in, idx, thr->pd_mode, ch, tv.first, tv.second);
-            Staged sg;
-            res = stage_group(c, pl, thr, st, sg);
-            if (res != LCF_OK) break;
-            res = run_chain(c, pl, sg, thr, prec, nullptr, st);
-            if (res != LCF_OK) break;
-            if (hipEventRecord(e0, st) != hipSuccess) { res = LCF_ERR_DEVICE; break; }
-            res = run_chain(c, pl, sg, thr, prec, nullptr, st);
-            if (res != LCF_OK) break;
-            float ms = 0.f;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { res = LCF_ERR_DEVICE; break; }
-            if (best == 0.f || ms < best) { best = ms; choice = TuneChoice{ch, tv.first, tv.second}; }
-        }
-    }
+    for (const auto& tv : tiles)
+        for (int ch : chunks)
+            if (!trial(ch, tv.first, tv.second, c->evd_method)) goto done;
+    if (ntp <= 128) trial(choice.chunk, choice.trows, choice.rvar, 1 - c->evd_method);
+done:
     c->timing = saved_timing;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -894,6 +903,7 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
                 build_plan(tuned, in, kv.second, thr->pd_mode, tit->second.chunk, tr, rv);
                 pl = std::move(tuned);
             }
+            pl.evd = kv.first <= 128 ? tit->second.evd : -1;
         }
         Staged sg;
         lcf_status e = stage_group(c, pl, thr, st, sg, fx);
@@ -944,7 +954,8 @@ lcf_status stream_chain(lcf_context* c, const Plan& pl, const Staged& sg, const 
     const bool cov = diag && diag->cov;
     { STAGE(c, LCF_STAGE_ASSEMBLE, st); HIPCHK(launch_assemble(ws, cov, st)); }
     if (cov) HIPCHK(launch_export_cov(ws, 0, ws.S, pl.sub[0].nt, (double2*)diag->cov, st));
-    lcf_status e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch, st);
+    lcf_status e = run_stages2(c, ws, thr, prec, pl.nt_max, diag && diag->eigvecs ? 1 : 0, sg.mlp_scratch,
+                               c->evd_method, st);
     if (e != LCF_OK) return e;
     { STAGE(c, LCF_STAGE_REPROJ, st); HIPCHK(launch_reproj(ws, prec, st)); }
     if (diag)
@@ -1371,8 +1382,8 @@ lcf_status lcf_tune_save(lcf_context* ctx, const char* path) {
     if (!f) return LCF_ERR_INVALID_ARG;
     bool ok = true;
     for (const auto& kv : ctx->tuned)
-        ok = ok && std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.chunk, kv.second.trows,
-                                kv.second.rvar) > 0;
+        ok = ok && std::fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.chunk, kv.second.trows,
+                                kv.second.rvar, kv.second.evd) > 0;
     ok = (std::fclose(f) == 0) && ok;
     return ok ? LCF_OK : LCF_ERR_INVALID_ARG;
 }
@@ -1382,15 +1393,16 @@ lcf_status lcf_tune_load(lcf_context* ctx, const char* path) {
     FILE* f = std::fopen(path, "r");
     if (!f) return LCF_ERR_INVALID_ARG;
     std::map<std::string, TuneChoice> got;
-    char key[128];
-    int chunk = 0, rows = 0, var = 0;
+    char line[512], key[128], extra[8];
     bool ok = true;
-    for (;;) {
-        const int n = std::fscanf(f, "%127s %d %d %d", key, &chunk, &rows, &var);
-        if (n == EOF) break;
-        if (n != 4 || chunk < PIX || chunk > (1 << 20) || (rows != 2 && rows != 4) || var < 0 || var > 1 ||
-            (var == 1 && rows != 4)) { ok = false; break; }
-        got[key] = TuneChoice{chunk, rows, var};
+    while (std::fgets(line, sizeof line, f)) {
+        int chunk = 0, rows = 0, var = 0, evd = -1;
+        const int n = std::sscanf(line, "%127s %d %d %d %d %7s", key, &chunk, &rows, &var, &evd, extra);
+        if (n <= 0) continue;                                       // blank line
+        // "<class> <chunk> <rows> <variant> [<evd>]"; files without the EVD column keep the context's
+        if ((n != 4 && n != 5) || chunk < PIX || chunk > (1 << 20) || (rows != 2 && rows != 4) || var < 0 ||
+            var > 1 || (var == 1 && rows != 4) || evd < -1 || evd > 1) { ok = false; break; }
+        got[key] = TuneChoice{chunk, rows, var, evd};
     }
     std::fclose(f);
     if (!ok) return LCF_ERR_INVALID_ARG;

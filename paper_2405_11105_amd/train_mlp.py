@@ -1,13 +1,18 @@
 """Train the learned eigencomponent-weight network on the GPU with the library's
 own forward/backward/Adam kernels, and evaluate it against the rule it replaces.
 
-Teacher. For every training packet the filter runs with the curvature rule
-(Eq. 6) and sigmoid weights (Eq. 9) at each scaling factor beta of a grid; the
+Teachers. ``rule`` (default): the adaptive-threshold weights of the plain rule
+itself, the curvature cut (Eq. 6, beta 1) with sigmoid weights (Eq. 9); the
+network learns the rule's map from spectrum to weights and the library's gate
+(LCF_OPT_MLP_GATE) keeps the rule wherever the network's prediction strays by
+0.1 dB or more. ``search``: for every training packet the filter runs with the
+curvature rule and sigmoid weights at each scaling factor beta of a grid; the
 beta whose power Doppler image has the highest CNR against the generator's
 vessel masks is kept, and its per-subset weights become the targets. This is
 the per-packet exhaustive beta search of the Experimental Studies section,
 which the Discussion notes is impractical in real time: the network has to
-produce the searched weights from one subset's spectrum alone.
+produce the searched weights from one subset's spectrum alone (a different
+filter from the rule, so the gate rejects it; it is evaluated without one).
 
 CNR = 10 log10((mean PD_vessel - mean PD_background) / std PD_background) with
 the background = pixels farther than 3 rows from any vessel (Data processing
@@ -64,7 +69,7 @@ def packet_runs(ctx, lcf, iq, mask_t, grid, prec, betas=BETAS):
     return lam, out_w, cnrs
 
 
-def generate(ctx, lcf, kind, seeds, grid, prec, workers, log=None):
+def generate(ctx, lcf, kind, seeds, grid, prec, workers, log=None, teacher="search"):
     """Teacher data: eigvals [N][128] (float64, GPU), targets [N][128] (float32, GPU), info."""
     import torch
     lams, tgts, info = [], [], []
@@ -77,11 +82,12 @@ def generate(ctx, lcf, kind, seeds, grid, prec, workers, log=None):
                 log(f"teacher packet {n}/{len(seeds)} ({time.time() - t0:.0f} s)")
             iq = torch.from_numpy(iq_np).cuda()
             mask_t = torch.from_numpy(mask_np).cuda()
-            lam, ws, cnrs = packet_runs(ctx, lcf, iq, mask_t, grid, prec)
+            betas = (1.0,) if teacher == "rule" else BETAS
+            lam, ws, cnrs = packet_runs(ctx, lcf, iq, mask_t, grid, prec, betas=betas)
             best = int(np.argmax(cnrs))
             lams.append(lam)
             tgts.append(ws[best])
-            info.append({"seed": int(seed), "best_beta": BETAS[best], "cnr": cnrs})
+            info.append({"seed": int(seed), "best_beta": betas[best], "cnr": cnrs})
     return torch.cat(lams), torch.cat(tgts), info
 
 
@@ -175,6 +181,7 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", default="mlp.ckpt")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--teacher", default="rule", choices=["rule", "search"])
     ap.add_argument("--eval-only", default=None, metavar="CKPT",
                     help="skip the teacher data and training; evaluate this checkpoint on the held-out packets")
     ap.add_argument("--gate-mdb", type=int, default=100, help="LCF_OPT_MLP_GATE for the evaluation")
@@ -193,7 +200,7 @@ def main(argv=None):
     else:
         t0 = time.time()
         lam, tgt, info = generate(ctx, lcf, args.kind, range(base_train, base_train + args.train), grid, prec,
-                                  args.workers, log=log)
+                                  args.workers, log=log, teacher=args.teacher)
         log(f"teacher data: {lam.shape[0]} spectra from {args.train} packets in {time.time() - t0:.1f} s; "
             f"best beta histogram {np.unique([i['best_beta'] for i in info], return_counts=True)}")
         ctx.mlp_init(1)
@@ -207,7 +214,8 @@ def main(argv=None):
     log("held-out mean: " + json.dumps(summ))
     if args.report:
         with open(args.report, "w") as f:
-            json.dump({"summary": summ, "rows": rows, "loss": hist, "train_info": info}, f)
+            json.dump({"summary": summ, "rows": rows, "loss": hist, "teacher": args.teacher,
+                       "epochs": args.epochs, "train_info": info}, f)
     ctx.close()
     return summ
 

@@ -386,10 +386,12 @@ def test_graph_cache_keys_on_median_beta(lcf, ctx):
             gctx.close()
 
 
-@pytest.mark.parametrize("nt", [128, 80])
+@pytest.mark.parametrize("nt", [128, 80, 150, 200])
 def test_evd_tridiagonal_matches_jacobi(lcf, ctx, nt):
     """The two subset eigen-solvers give the same filter (FP32 path); 80 frames
-    run the 6-wave shapes of both (96-frame class)."""
+    run the 6-wave shapes of both (96-frame class); 150 and 200 frames run the
+    global-memory Householder reduction (160 and 208 classes) against the
+    LDS / global Jacobi."""
     _say(f"[tridiagonal vs Jacobi EVD nt={nt}]")
     iq, mask = synth.make_packet(synth.spec_clinical(2, nt=nt))
     dev = torch.from_numpy(iq).cuda()
@@ -413,11 +415,13 @@ def test_evd_tridiagonal_matches_jacobi(lcf, ctx, nt):
     assert np.array_equal(d_t["k"].cpu().numpy(), d_j["k"].cpu().numpy())
 
 
-def test_evd_rank_deficient_falls_back_to_jacobi(lcf, ctx):
-    """Boxes of 30 pixels and 32 frames: every subset covariance is singular with
-    a repeated zero eigenvalue, so the tridiagonal solver hands it to Jacobi."""
-    _say("[rank-deficient subsets]")
-    spec = synth.PacketSpec(6, 5, 32, 30.0, 0.3, ((3, 1, 0.5),), seed=21)
+@pytest.mark.parametrize("nt", [32, 150])
+def test_evd_rank_deficient_falls_back_to_jacobi(lcf, ctx, nt):
+    """Boxes of at most 30 pixels and 32 (150) frames: every subset covariance is
+    singular with a repeated zero eigenvalue, so the tridiagonal solver (the
+    register one, the global-memory one) hands it to Jacobi."""
+    _say(f"[rank-deficient subsets nt={nt}]")
+    spec = synth.PacketSpec(6, 5, nt, 30.0, 0.3, ((3, 1, 0.5),), seed=21)
     iq, mask = synth.make_packet(spec)
     thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=3)
     io, pd, d = _run(lcf, ctx, iq, 2, 2, thr)

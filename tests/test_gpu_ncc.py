@@ -22,8 +22,9 @@ torch = pytest.importorskip("torch")
 # pixels of products of |u_i| sums; the GPU's eigenvectors come from the
 # deflated FP32 / split-BF16 covariance and differ from LAPACK's inside
 # clusters of nearly equal noise eigenvalues, which moves individual |u_i| but
-# little of the 5-component sums.
-TOL_CURVE = {0: 2e-4, 1: 2e-4}
+# little of the 5-component sums. Measured on the clinical packets: 1e-6
+# (FP32) and 3e-5 (split BF16).
+TOL_CURVE = {0: 2e-5, 1: 2e-4}
 
 
 @pytest.fixture(scope="module")

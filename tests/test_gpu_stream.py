@@ -101,7 +101,7 @@ def test_autotune_choice_roundtrip(lcf, ctx, tmp_path):
         tuned.tune_save(path)
         lines = open(path).read().split("\n")
         say(f"[autotune] {lines[0]}")
-        assert len([x for x in lines if x.strip()]) == 1 and len(lines[0].split()) == 4
+        assert len([x for x in lines if x.strip()]) == 1 and len(lines[0].split()) == 5
         e_io = float(torch.linalg.vector_norm(io1 - io0) / torch.linalg.vector_norm(io0))
         e_pd = float(torch.max(torch.abs(pd1 - pd0) / pd0))
         assert e_io <= 1e-5 and e_pd <= 1e-4, (e_io, e_pd)
@@ -120,3 +120,48 @@ def test_autotune_choice_roundtrip(lcf, ctx, tmp_path):
             again.close()
     finally:
         tuned.close()
+
+
+def test_stream_64_packets_one_graph_call(lcf, ctx):
+    """All 64 packets of the uneven stream in one batched call, captured into a
+    hipGraph and replayed (split BF16): replays are bitwise equal, one packet
+    per Nt class equals its single call bitwise, and the autotuned plan of the
+    same call agrees to FP32 rounding (it only moves the split-K chunks)."""
+    lst, data = _packets(64)
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    grids = [(g, g) for _, g in lst]
+    say(f"[64-packet stream] nt {sorted(set(s.nt for s, _ in lst))}, subsets {sum(g * g for _, g in lst)}")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        dev = [torch.from_numpy(iq).cuda() for iq, _ in data]
+        del data
+        outs = [(torch.empty_like(d), torch.empty(d.shape[1:], dtype=torch.float32, device="cuda")) for d in dev]
+        g = lcf.Context(0, use_graph=1)
+        t = lcf.Context(0, use_graph=1, autotune=1)
+        try:
+            g.filter_batch(dev, grids, thr, precision=lcf.PREC_BF16X3, outs=outs)        # capture
+            st.synchronize()
+            first = [(io.clone(), pd.clone()) for io, pd in outs]
+            g.filter_batch(dev, grids, thr, precision=lcf.PREC_BF16X3, outs=outs)        # replay
+            st.synchronize()
+            assert g.sync() == 0
+            for (a, b), (c, d) in zip(first, outs):
+                assert torch.equal(a, c) and torch.equal(b, d)
+            picks = {}
+            for k, (s, _) in enumerate(lst):
+                picks.setdefault(s.nt, k)
+            for nt, k in sorted(picks.items()):
+                io1, pd1, _ = ctx.filter(dev[k], grids[k][0], grids[k][1], thr, precision=lcf.PREC_BF16X3)
+                st.synchronize()
+                assert torch.equal(first[k][0], io1) and torch.equal(first[k][1], pd1), (nt, k)
+            ios_t, pds_t = t.filter_batch(dev, grids, thr, precision=lcf.PREC_BF16X3, iq_out=True)
+            st.synchronize()
+            assert t.sync() == 0
+            worst_io = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+                           for a, (b, _) in zip(ios_t, first))
+            worst_pd = max(float(torch.max(torch.abs(a - b) / b)) for a, (_, b) in zip(pds_t, first))
+            say(f"   autotuned vs default plan: iq {worst_io:.2e}, pd {worst_pd:.2e}")
+            assert worst_io <= 1e-4 and worst_pd <= 1e-3
+        finally:
+            g.close()
+            t.close()
