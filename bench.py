@@ -142,9 +142,14 @@ def _gen_packet(spec):
     return synth.make_packet(spec)
 
 
+def _progress(msg):
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def _leg(lcf, stream, iqs, grids, thr, prec, steps, schedule=0, graph=1, autotune=1, mlp=None, outs=None):
     """Time one configuration of the library on a list of packets (one call per step)."""
     import torch
+    _progress(f"leg: {len(iqs)} packets, precision {prec}, schedule {schedule}, graph {graph}")
     ctx = lcf.Context(0, schedule=schedule, use_graph=graph, autotune=autotune)
     try:
         if mlp:
@@ -156,13 +161,20 @@ def _leg(lcf, stream, iqs, grids, thr, prec, steps, schedule=0, graph=1, autotun
         run()                                    # plan, autotune, graph capture
         torch.cuda.synchronize()
         total, per = _timed_steps(run, steps, stream)
+        # host side of one call (plans, descriptor upload, launches or graph
+        # replay), measured until the call returns, with the device idle
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        host_ms = (time.perf_counter() - t0) * 1e3
+        torch.cuda.synchronize()
         st = ctx.sync()
     finally:
         ctx.close()
     frames = sum(int(iq.shape[0]) for iq in iqs)
     ms = total / steps
     return {"frames_per_s": frames / (ms / 1e3), "ms_per_step": ms, "steps": steps, "step_ms": _dist(per),
-            "device_status": st}
+            "host_ms_per_call": host_ms, "device_status": st}
 
 
 def slide_workload(lcf, stream, spec, grid, thr, mlp, hop=5, pushes=12):
@@ -186,6 +198,7 @@ def slide_workload(lcf, stream, spec, grid, thr, mlp, hop=5, pushes=12):
         ob = (torch.empty((nt, spec.ny, spec.nx), dtype=torch.complex64, device=rt.device),
               torch.empty((spec.ny, spec.nx), dtype=torch.float32, device=rt.device))
         for leg in ("stream", "per_packet"):
+            _progress(f"sliding packets: {leg}")
             ctx = lcf.Context(0, use_graph=1)
             if mlp:
                 ctx.mlp_load(mlp)
@@ -339,6 +352,7 @@ def main():
     import synth
 
     lcf.load()
+    _progress("packets")
     dev = torch.device("cuda:0")
     fac, seed0, (gy, gx) = WORKLOADS[args.workload]
     specs = [getattr(synth, fac)(seed0 + p) for p in range(args.batch)]
@@ -384,6 +398,7 @@ def main():
             gate_q = {"p10": float(np.quantile(gv, 0.1)), "median": float(np.median(gv)),
                       "p90": float(np.quantile(gv, 0.9)), "threshold_db": 0.1}
 
+        _progress("fast configuration")
         for _ in range(args.warmup):
             step_fast()
         torch.cuda.synchronize()
@@ -420,6 +435,7 @@ def main():
                     ("rule, FP32, graph", thr_plain, lcf.PREC_FP32, 1),
                     ("rule, FP32, batched, no graph", thr_plain, lcf.PREC_FP32, 0)]
             for name, thr_l, prec_l, graph_l in legs:
+                _progress(f"ablation: {name}")
                 actx = lcf.Context(0, schedule=0, use_graph=graph_l)
                 actx.tune_load(tune_file)
                 if use_mlp and thr_l.cut == lcf.CUT_MLP:
@@ -435,6 +451,7 @@ def main():
 
         plain = None
         if not args.no_plain:
+            _progress("plain configuration (per-subset loop)")
             pctx = lcf.Context(0, schedule=1, use_graph=0)
 
             def step_plain():
@@ -510,6 +527,7 @@ def main():
                                  mlp=lambda lam: M.forward(params, M.features(lam), bf16=True)[0][0])
         else:
             othr_f = O.Threshold(cut=O.CUT_KNEE, shape=O.SHAPE_SIGMOID)
+        _progress("cpu baseline (FP64 oracle)")
         cpu = cpu_baseline(host, gy, gx, othr_f, nt, args.cpu_seconds)
         iq0, mask0 = host[0]
         ref_f = O.filter_packet(iq0, gy, gx, othr_f)

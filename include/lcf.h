@@ -36,8 +36,9 @@
  *    sweep cap, degenerate spectrum) set per-subset flags that lcf_sync reports.
  *  - A context is bound to one device; it is not thread-safe. It owns the
  *    scratch arena (grown on demand, reused afterwards), plans and MLP weights.
- *  - Stream capture: lcf_filter, lcf_filter_batch, lcf_heevd_batched,
- *    lcf_mlp_infer and lcf_mlp_train_step return LCF_ERR_UNSUPPORTED, before any
+ *  - Stream capture: lcf_filter, lcf_filter_noalloc, lcf_filter_batch,
+ *    lcf_stream_push, lcf_heevd_batched, lcf_mlp_infer and lcf_mlp_train_step
+ *    return LCF_ERR_UNSUPPORTED, before any
  *    launch, when `stream` is being captured into a graph by the caller (they
  *    upload plans and may grow the arena, which a later call would overwrite or
  *    free under the caller's graph). With LCF_OPT_USE_GRAPH the library captures
