@@ -184,6 +184,20 @@ __global__ void __launch_bounds__(64) k_rules(Workspace ws, RuleParams rp) {
     }
 }
 
+// Within every block of 16 frames the split-BF16 operand rows are stored in the
+// order of the FP64 residual's accumulator layout: position 4 g + e holds frame
+// g + 4 e (a 4 x 4 transpose, its own inverse), so each lane of the residual
+// stores four consecutive positions at once.
+__host__ __device__ constexpr int sb_perm16(int x) { return (x & ~15) | ((x & 3) << 2) | ((x >> 2) & 3); }
+
+// Split-BF16 [P; M] operand planes (layout described at k_reproj_sb): the KC
+// rows of P, padded to whole K steps of 32, then a 32-row packed block for M.
+template <int NTP>
+struct SbLayout {
+    static constexpr int KC = (NTP + 31) / 32 * 32;    // rows of P per plane row, whole K steps
+    static constexpr int KB = KC + 32;                 // plane row length
+};
+
 // ------------------------------------------------------------------ projector
 // With the eigenvectors W of B = Q^H R Q (Q = H_0 .. H_{r-1}) and the weights w,
 // the projector of Eq. 4 in the original basis is
@@ -210,7 +224,7 @@ template <int NTP, int PREC>
 __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
     constexpr int NTHR = PjCfg<NTP>::NTHR, RA = PjCfg<NTP>::RA, NWV = NTHR / 64;
     constexpr int NTE = NTP + REXT;
-    constexpr int NTEP = (NTE + 31) / 32 * 32;
+    constexpr int KC = SbLayout<NTP>::KC, KB = SbLayout<NTP>::KB;
     constexpr int NB = (NTP + 127) / 128;       // 128 x 128 blocks per dimension
     constexpr int RW = NTP / 16;                // rows per lane in the reflector pass
     __shared__ double2 Wl[PCC * NTP];           // chunk of W, then W', [c][t]
@@ -293,7 +307,7 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
                 double2 wt[RA], wu[8];
 #pragma unroll
                 for (int a = 0; a < RA; ++a) {
-                    const int t = tb + RA * ti + a;
+                    const int t = tb + (PREC ? sb_perm16(RA * ti + a) : RA * ti + a);
                     wt[a] = t < NTP ? cscale(Wl[c * NTP + t], cw[c]) : make_double2(0.0, 0.0);
                 }
 #pragma unroll
@@ -327,8 +341,9 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
             }
             __syncthreads();
         }
-        // write the block: operand row k = t, output frame n = u; P = I - ... on
-        // [0, nt) x [0, nt), zero elsewhere
+        // write the block: operand row k = t (split BF16: the thread's rows are
+        // frames sb_perm16 of RA consecutive plane positions), output frame n = u;
+        // P = I - ... on [0, nt) x [0, nt), zero elsewhere
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const int n = ub + ui + 16 * b;
@@ -336,7 +351,7 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
             float re[RA], im[RA];
 #pragma unroll
             for (int a = 0; a < RA; ++a) {
-                const int k = tb + RA * ti + a;
+                const int k = tb + (PREC ? sb_perm16(RA * ti + a) : RA * ti + a);   // frame
                 const bool in = k < nt && n < nt;
                 re[a] = in ? (float)((k == n ? 1.0 : 0.0) + acc[a][b].x) : 0.f;
                 im[a] = in ? (float)acc[a][b].y : 0.f;
@@ -348,7 +363,7 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
                 uint32_t h[RA], l[RA];
 #pragma unroll
                 for (int a = 0; a < RA; ++a) split_bf16x2(re[a], im[a], h[a], l[a]);
-                // RA consecutive rows k of each plane: RA / 2 words
+                // RA consecutive positions of each plane: RA / 2 words
                 uint32_t hr[RA / 2], lr[RA / 2], hi4[RA / 2], li4[RA / 2];
 #pragma unroll
                 for (int q = 0; q < RA / 2; ++q) {
@@ -357,12 +372,12 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
                     hi4[q] = __builtin_amdgcn_perm(h[2 * q + 1], h[2 * q], 0x07060302u);
                     li4[q] = __builtin_amdgcn_perm(l[2 * q + 1], l[2 * q], 0x07060302u);
                 }
-                const long e = (long)n * NTEP + k0;
+                const long e = (long)n * KB + k0;
                 auto put = [&](long plane, const uint32_t* w) {
                     if constexpr (RA == 8)
-                        *reinterpret_cast<u32x4*>(pt + plane * NTP * NTEP + e) = u32x4{w[0], w[1], w[2], w[3]};
+                        *reinterpret_cast<u32x4*>(pt + plane * NTP * KB + e) = u32x4{w[0], w[1], w[2], w[3]};
                     else
-                        *reinterpret_cast<uint2*>(pt + plane * NTP * NTEP + e) = make_uint2(w[0], w[1]);
+                        *reinterpret_cast<uint2*>(pt + plane * NTP * KB + e) = make_uint2(w[0], w[1]);
                 };
                 put(0, hr);
                 put(1, lr);
@@ -382,19 +397,31 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
             }
         }
     }
-    // rows k in [NTP, NTEP) of the operand: M for k < NTP + r, zero beyond
+    // rows [NTP, KC) of the planes are zero; rows [KC, KB) hold M packed as the
+    // reprojection's 32-row block (Msh is zero from r and from nt up)
     if (PREC == 1) {
+        static_assert(RMAX == 8 && KB - KC == 32, "four blocks of 8 tissue columns");
         uint16_t* pt = reinterpret_cast<uint16_t*>(ws.breal + (long)s * (2 * NTE) * (2 * NTP));
-        for (int e = tid; e < NTP * (NTEP - NTP); e += NTHR) {
-            const int n = e / (NTEP - NTP), j = e % (NTEP - NTP);
-            const double2 v = j < RMAX ? Msh[j * NTP + n] : make_double2(0.0, 0.0);
-            uint32_t h, l;
-            split_bf16x2((float)v.x, (float)v.y, h, l);
-            const long o = (long)n * NTEP + NTP + j;
-            pt[0L * NTP * NTEP + o] = (uint16_t)h;
-            pt[1L * NTP * NTEP + o] = (uint16_t)l;
-            pt[2L * NTP * NTEP + o] = (uint16_t)(h >> 16);
-            pt[3L * NTP * NTEP + o] = (uint16_t)(l >> 16);
+        for (int e = tid; e < NTP * (KB - NTP); e += NTHR) {
+            const int n = e / (KB - NTP), k = NTP + e % (KB - NTP);
+            uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+            if (k >= KC) {
+                const int blk = (k - KC) >> 3, j = (k - KC) & 7;
+                const double2 v = Msh[j * NTP + n];
+                uint32_t h, l;
+                split_bf16x2((float)v.x, (float)v.y, h, l);
+                const uint32_t hre = h & 0xffffu, him = h >> 16, lre = l & 0xffffu, lim = l >> 16;
+                const bool odd = blk & 1, first = blk < 2;
+                w0 = odd ? (him ^ 0x8000u) : hre;                      // [Mh_re | -Mh_im | Mh_re | -Mh_im]
+                w1 = first ? (odd ? (lim ^ 0x8000u) : lre) : 0u;       // [Ml_re | -Ml_im | 0 | 0]
+                w2 = odd ? hre : him;                                  // [Mh_im |  Mh_re | Mh_im |  Mh_re]
+                w3 = first ? (odd ? lre : lim) : 0u;                   // [Ml_im |  Ml_re | 0 | 0]
+            }
+            const long o = (long)n * KB + k;
+            pt[0L * NTP * KB + o] = (uint16_t)w0;
+            pt[1L * NTP * KB + o] = (uint16_t)w1;
+            pt[2L * NTP * KB + o] = (uint16_t)w2;
+            pt[3L * NTP * KB + o] = (uint16_t)w3;
         }
     } else {
         float* Br = ws.breal + (long)s * (2 * NTE) * (2 * NTP);
@@ -430,8 +457,6 @@ struct RpCfg {
     static constexpr int TP = TR * TW;                                // pixels per tile
     static constexpr int NRT = TP / 16;                               // MFMA row tiles
     static constexpr int NTE = NTP + REXT;
-    static constexpr int NTEP = (NTE + 31) / 32 * 32;                 // BF16: K per part, padded
-    static constexpr int LDK = 2 * NTEP + 8;                          // BF16 row stride (uint16)
     static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;     // FP32: offset of the im part
     static constexpr int LDA = 2 * IMO + 1;                           // FP32 row stride (floats)
     static constexpr int CT = (2 * NTP) / 16;                         // output column tiles
@@ -443,7 +468,7 @@ struct RpCfg {
     static constexpr int CTW = PREC ? 2 * ((NNT + NW - 1) / NW) : (CT + NW - 1) / NW;
     static constexpr int LDC = NTP + 1;                               // staging row stride (float2)
     static constexpr int G = NTHR / TP;                               // threads per pixel for y
-    static constexpr int ABYTES = PREC ? 2 * TP * LDK * 2 : TP * LDA * 4;
+    static constexpr int ABYTES = TP * LDA * 4;                       // FP32 operand (k_reproj)
 };
 
 template <int NTP, int PREC, int TR>
@@ -709,8 +734,6 @@ struct RpPcCfg {
     static constexpr int TP = TR * TW;
     static constexpr int NRT = TP / 16;
     static constexpr int NTE = NTP + REXT;
-    static constexpr int NTEP = (NTE + 31) / 32 * 32;
-    static constexpr int LDK = 2 * NTEP + 8;
     static constexpr int IMO = (NTE % 32 == 16) ? NTE : NTE + 16;
     static constexpr int LDA = 2 * IMO + 4;                         // 16-byte aligned rows
     static constexpr int CT = (2 * NTP) / 16;
@@ -723,13 +746,14 @@ struct RpPcCfg {
     static constexpr int YPT = (REXT + G - 1) / G;                  // y columns per producer lane
     static constexpr int LDC = NTP + 1;
     static constexpr int VPT = (NTP * RMAX + PTHR - 1) / PTHR;      // V_r elements per producer lane
-    static constexpr int ABYTES = PREC ? 2 * TP * LDK * 2 : TP * LDA * 4;
+    static constexpr int ABYTES = TP * LDA * 4;
 };
 
 template <int NTP, int PREC, int TR>
 __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Workspace ws) {
     using C = RpPcCfg<NTP, PREC, TR>;
-    constexpr int NTEP = C::NTEP, LDK = C::LDK, IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
+    static_assert(PREC == 0, "the split-BF16 reprojection is k_reproj_sb");
+    constexpr int IMO = C::IMO, LDA = C::LDA, LDC = C::LDC;
     constexpr int NTHR = C::NTHR, CTW = C::CTW, G = C::G, TP = C::TP, NRT = C::NRT;
     constexpr int TPT = C::TPT, YPT = C::YPT, VPT = C::VPT, PTHR = C::PTHR;
     static_assert(PTHR % TP == 0 && G >= 1 && G <= 16 && (G & (G - 1)) == 0, "pixel lanes in one row");
@@ -742,8 +766,6 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
     __shared__ float2 ysh[TP * RMAX];          // tissue scores of the subset being formed
     __shared__ float2 vrs32[RMAX * NTP];       // V_r rounded to FP32, [j][t] (for the scores only)
     float* A = reinterpret_cast<float*>(abuf);
-    uint16_t* Ah = reinterpret_cast<uint16_t*>(abuf);
-    uint16_t* Al = Ah + TP * LDK;
     float2* craw = reinterpret_cast<float2*>(abuf);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -799,9 +821,7 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
     }
     auto sx = [&](int i) { return st[2 * i]; };
     auto sy = [&](int i) { return st[2 * i + 1]; };
-    // operand words: BF16 path, word q of (re hi, im hi, re lo, im lo) packs frames
-    // 2q, 2q + 1; FP32 path, (re, im) of frame i
-    auto opw = [&](int k) -> uint32_t { return __float_as_uint(st[O_OP + k]); };
+    // operand words: (re, im) of frame i
     auto dset = [&](int k, double v) {
         const long long b = __double_as_longlong(v);
         st[k] = __uint_as_float((uint32_t)(b & 0xffffffff));
@@ -873,20 +893,8 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
                     im -= (double)y.y * v.x - (double)y.x * v.y;
                 }
             }
-            if (PREC) {
-                const uint32_t rh = bf16_bits((float)re), ih = bf16_bits((float)im);
-                const uint32_t rl = bf16_bits((float)re - __uint_as_float(rh << 16));
-                const uint32_t il = bf16_bits((float)im - __uint_as_float(ih << 16));
-                const int h = i >> 1, sh = (i & 1) * 16;
-                const uint32_t keep = (i & 1) ? 0xffffu : 0u;     // low half from frame 2h
-                st[O_OP + h] = __uint_as_float((opw(h) & keep) | (rh << sh));
-                st[O_OP + TPT / 2 + h] = __uint_as_float((opw(TPT / 2 + h) & keep) | (ih << sh));
-                st[O_OP + TPT + h] = __uint_as_float((opw(TPT + h) & keep) | (rl << sh));
-                st[O_OP + 3 * TPT / 2 + h] = __uint_as_float((opw(3 * TPT / 2 + h) & keep) | (il << sh));
-            } else {
-                st[O_OP + 2 * i] = (float)re;
-                st[O_OP + 2 * i + 1] = (float)im;
-            }
+            st[O_OP + 2 * i] = (float)re;
+            st[O_OP + 2 * i + 1] = (float)im;
         }
 #pragma unroll
         for (int m = 0; m < YPT; ++m) {
@@ -897,47 +905,19 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
         }
     };
     auto write_operand = [&]() {
-        if (PREC) {
-            uint16_t* rowh = Ah + pp * LDK + part * TPT;
-            uint16_t* rowl = Al + pp * LDK + part * TPT;
+        float* row = A + pp * LDA + part * TPT;
 #pragma unroll
-            for (int q = 0; q < TPT / 8; ++q) {
-                const int b0 = 4 * q;
-                *reinterpret_cast<u32x4*>(rowh + 8 * q) = u32x4{opw(b0), opw(b0 + 1), opw(b0 + 2), opw(b0 + 3)};
-                *reinterpret_cast<u32x4*>(rowh + NTEP + 8 * q) =
-                    u32x4{opw(TPT / 2 + b0), opw(TPT / 2 + b0 + 1), opw(TPT / 2 + b0 + 2), opw(TPT / 2 + b0 + 3)};
-                *reinterpret_cast<u32x4*>(rowl + 8 * q) =
-                    u32x4{opw(TPT + b0), opw(TPT + b0 + 1), opw(TPT + b0 + 2), opw(TPT + b0 + 3)};
-                *reinterpret_cast<u32x4*>(rowl + NTEP + 8 * q) =
-                    u32x4{opw(3 * TPT / 2 + b0), opw(3 * TPT / 2 + b0 + 1), opw(3 * TPT / 2 + b0 + 2), opw(3 * TPT / 2 + b0 + 3)};
-            }
+        for (int q = 0; q < TPT / 4; ++q) {
+            const int f0 = O_OP + 8 * q;
+            *reinterpret_cast<float4*>(row + 4 * q) = make_float4(st[f0], st[f0 + 2], st[f0 + 4], st[f0 + 6]);
+            *reinterpret_cast<float4*>(row + IMO + 4 * q) = make_float4(st[f0 + 1], st[f0 + 3], st[f0 + 5], st[f0 + 7]);
+        }
 #pragma unroll
-            for (int m = 0; m < YPT; ++m) {
-                const int j = part * YPT + m;
-                if (j < REXT) {
-                    const float yx = st[O_Y + 2 * m], yy = st[O_Y + 2 * m + 1];
-                    const uint32_t rh = bf16_bits(yx), ih = bf16_bits(yy);
-                    Ah[pp * LDK + NTP + j] = (uint16_t)rh;
-                    Ah[pp * LDK + NTEP + NTP + j] = (uint16_t)ih;
-                    Al[pp * LDK + NTP + j] = (uint16_t)bf16_bits(yx - __uint_as_float(rh << 16));
-                    Al[pp * LDK + NTEP + NTP + j] = (uint16_t)bf16_bits(yy - __uint_as_float(ih << 16));
-                }
-            }
-        } else {
-            float* row = A + pp * LDA + part * TPT;
-#pragma unroll
-            for (int q = 0; q < TPT / 4; ++q) {
-                const int f0 = O_OP + 8 * q;
-                *reinterpret_cast<float4*>(row + 4 * q) = make_float4(st[f0], st[f0 + 2], st[f0 + 4], st[f0 + 6]);
-                *reinterpret_cast<float4*>(row + IMO + 4 * q) = make_float4(st[f0 + 1], st[f0 + 3], st[f0 + 5], st[f0 + 7]);
-            }
-#pragma unroll
-            for (int m = 0; m < YPT; ++m) {
-                const int j = part * YPT + m;
-                if (j < REXT) {
-                    A[pp * LDA + NTP + j] = st[O_Y + 2 * m];
-                    A[pp * LDA + IMO + NTP + j] = st[O_Y + 2 * m + 1];
-                }
+        for (int m = 0; m < YPT; ++m) {
+            const int j = part * YPT + m;
+            if (j < REXT) {
+                A[pp * LDA + NTP + j] = st[O_Y + 2 * m];
+                A[pp * LDA + IMO + NTP + j] = st[O_Y + 2 * m + 1];
             }
         }
     };
@@ -971,68 +951,25 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (PREC) {
-            const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * C::NTE) * (2 * NTP));
-#pragma unroll 1
-            for (int k0 = 0; k0 < 2 * NTEP; k0 += 32) {
-                const int kq = k0 + 8 * g;
-                const bool impart = k0 >= NTEP;
-                const int kk = impart ? kq - NTEP : kq;
-                u32x4 bh[CTW], bl[CTW];
-#pragma unroll
-                for (int m = 0; m < CTW; ++m) {
-                    const int ct = wave * CTW + m;
-                    bh[m] = u32x4{0u, 0u, 0u, 0u};
-                    bl[m] = u32x4{0u, 0u, 0u, 0u};
-                    if (ct < C::CT) {
-                        const int n = ct * 16 + col;
-                        const bool outim = n >= NTP;
-                        const int nn = outim ? n - NTP : n;
-                        const int plane = (outim != impart) ? 2 : 0;
-                        const uint32_t sgn = (!outim && impart) ? 0x80008000u : 0u;
-                        const uint16_t* src = planes + (long)plane * NTP * NTEP + (long)nn * NTEP + kk;
-                        bh[m] = *reinterpret_cast<const u32x4*>(src);
-                        bl[m] = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) { bh[m][q] ^= sgn; bl[m][q] ^= sgn; }
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < NRT; ++a) {
-                    const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + (16 * a + col) * LDK + kq));
-                    const bf16x8 xl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Al + (16 * a + col) * LDK + kq));
-#pragma unroll
-                    for (int m = 0; m < CTW; ++m) {
-                        if (wave * CTW + m < C::CT) {
-                            const bf16x8 xbh = __builtin_bit_cast(bf16x8, bh[m]), xbl = __builtin_bit_cast(bf16x8, bl[m]);
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, xbh, acc[a][m], 0, 0, 0);
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, xbl, acc[a][m], 0, 0, 0);
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, xbh, acc[a][m], 0, 0, 0);
-                        }
-                    }
-                }
-            }
-        } else {
-            const float* Br = ws.breal + (long)s * (2 * C::NTE) * (2 * NTP);
+        const float* Br = ws.breal + (long)s * (2 * C::NTE) * (2 * NTP);
 #pragma unroll 2
-            for (int k0 = 0; k0 < 2 * C::NTE; k0 += 4) {
-                const int kk = k0 + g;
-                const int acol = kk < C::NTE ? kk : IMO + kk - C::NTE;
-                const float* brow = Br + (long)kk * (2 * NTP);
-                float bv[CTW];
+        for (int k0 = 0; k0 < 2 * C::NTE; k0 += 4) {
+            const int kk = k0 + g;
+            const int acol = kk < C::NTE ? kk : IMO + kk - C::NTE;
+            const float* brow = Br + (long)kk * (2 * NTP);
+            float bv[CTW];
 #pragma unroll
-                for (int m = 0; m < CTW; ++m) {
-                    const int ct = wave * CTW + m;
-                    bv[m] = ct < C::CT ? brow[ct * 16 + col] : 0.f;
-                }
+            for (int m = 0; m < CTW; ++m) {
+                const int ct = wave * CTW + m;
+                bv[m] = ct < C::CT ? brow[ct * 16 + col] : 0.f;
+            }
 #pragma unroll
-                for (int a = 0; a < NRT; ++a) {
-                    const float av = A[(16 * a + col) * LDA + acol];
+            for (int a = 0; a < NRT; ++a) {
+                const float av = A[(16 * a + col) * LDA + acol];
 #pragma unroll
-                    for (int m = 0; m < CTW; ++m)
-                        if (wave * CTW + m < C::CT)
-                            acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[m], acc[a][m], 0, 0, 0);
-                }
+                for (int m = 0; m < CTW; ++m)
+                    if (wave * CTW + m < C::CT)
+                        acc[a][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[m], acc[a][m], 0, 0, 0);
             }
         }
 #pragma unroll
@@ -1111,42 +1048,69 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
 }
 
 // Split-BF16 reprojection with the tissue scores on MFMA. The packet values of
-// the tile stay in registers for all covering subsets, in the A-operand layout
-// of the score product: wave w, lane (col, g) holds s(16 a + col, 16 ks + 4 g + e)
-// for its K steps ks = w + NW i, every row tile a and e < 4. Per subset:
+// the tile stay in registers for all covering subsets: wave w, lane (col, g)
+// holds s(16 a + col, 16 ks + g + 4 e) for its K steps ks = w + NW i, every row
+// tile a and e < 4 (the accumulator layout of the FP64 residual product below;
+// the score product takes them as its A operand in the same frame order, and the
+// GEMM operand rows store frame g + 4 e at position 4 g + e). Per subset:
 //   B  partial scores y = s V_r over the wave's frames (MFMA, split BF16; any
 //      y keeps s = c' + y V_r^H exact, so its precision is free)
-//   C  the partials summed in a fixed order; the y columns of the operand
-//   D  c' = s - y V_r^H in FP64 from the same registers (each V_r value read
-//      from LDS serves the lane's NRT pixels)
-//   E  chat = [c' | y] [P; M] and the PD / IQ epilogue, as in k_reproj;
+//   C  the partials summed in a fixed order; y in its packed operand block
+//   D  c' = s - y V_r^H in FP64 on the matrix cores: per 16 frames x 16 pixels,
+//      c'^T = s^T + A B with A = -conj(V_r) and B = y^T in a real form that
+//      interleaves (re, im) along K (2 r <= 16), starting from the same
+//      registers, which already sit in the accumulator layout of that product
+//   E  chat = c' P + y M and the PD / IQ epilogue, as in k_reproj;
 //      V_r and the window of the next subset go to the other LDS buffers
+//
+// Operand layout of [P; M] (written by k_projector<NTP, 1>): four planes (Re hi,
+// Re lo, Im hi, Im lo), each [output frame n][KB] with the KC rows of P (zero
+// from nt up) followed by a 32-row block that holds M in a packed real form.
+// With the pixel's A row [yh_re | yh_im | yl_re | yl_im] (8 each; hi and lo of
+// y, zero beyond r) the block reads
+//   plane 0 [Mh_re | -Mh_im | Mh_re | -Mh_im]   plane 1 [Ml_re | -Ml_im | 0 | 0]
+//   plane 2 [Mh_im |  Mh_re | Mh_im |  Mh_re]   plane 3 [Ml_im |  Ml_re | 0 | 0]
+// so that two MFMAs give Re(yh Mh + yl Mh + yh Ml) and two the imaginary part:
+// the three products of the split for all r <= 8 tissue columns at once.
+
 template <int NTP, int TR>
 struct RpSbCfg {
     using R = RpCfg<NTP, 1, TR>;
-    static constexpr int TP = R::TP, NRT = R::NRT, NTEP = R::NTEP, LDK = R::LDK;
+    static constexpr int TP = R::TP, NRT = R::NRT;
     static constexpr int NW = R::NW, NTHR = R::NTHR, CTW = R::CTW, NNT = R::NNT;
+    static constexpr int KC = SbLayout<NTP>::KC, KB = SbLayout<NTP>::KB;
+    static constexpr int LDK = KB + KC + 8;                   // A row: re part + M block | im part
+    static constexpr int NKS = KC / 32;                       // full complex K steps
     static constexpr int QW = CTW / 2;                        // output frame tiles per wave
+    static constexpr bool QFULL = NW * QW == NNT;             // every wave's tiles exist
     static constexpr int KSTEPS = NTP / 16;                   // score K blocks of 32 (frame, re/im)
     static constexpr int MKS = (KSTEPS + NW - 1) / NW;        // K blocks per wave
     static constexpr int VPT = (NTP * RMAX + NTHR - 1) / NTHR;
+    static constexpr int LDV = NTP + 1;                       // V_r row stride (double2), odd
+    static constexpr int YLD = 2 * RMAX + 1;                  // y row stride (floats), odd
+    // the [P; M] fragments of the next K step are requested before the MFMAs of
+    // the current one where the registers allow it (else they would spill)
+    static constexpr bool PREF = NTP == 128 && TR == 4;
 };
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <int NTP, int TR>
 __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspace ws) {
     using C = RpSbCfg<NTP, TR>;
-    constexpr int NTEP = C::NTEP, LDK = C::LDK, NTHR = C::NTHR, CTW = C::CTW, QW = C::QW;
-    constexpr int TP = C::TP, NRT = C::NRT, NW = C::NW, MKS = C::MKS, VPT = C::VPT;
+    constexpr int LDK = C::LDK, NTHR = C::NTHR, CTW = C::CTW, QW = C::QW, KC = C::KC, KB = C::KB;
+    constexpr int TP = C::TP, NRT = C::NRT, NW = C::NW, MKS = C::MKS, VPT = C::VPT, LDV = C::LDV, YLD = C::YLD;
     static_assert(QW >= 1 && CTW == 2 * QW, "re and im output tiles in pairs");
+    static_assert(RMAX == 8, "the packed M block holds 8 tissue columns");
     __shared__ __attribute__((aligned(16))) uint16_t abuf[2 * TP * LDK];
-    __shared__ double2 vrs[2][RMAX * NTP];      // V_r, [j][t], double-buffered over subsets
+    __shared__ double2 vrs[2][RMAX * LDV];      // V_r, [j][t], double-buffered over subsets
     __shared__ float ypart[NW * TP * 16];       // score partials [wave][pixel][column]
-    __shared__ float2 ysh[TP * RMAX];
-    __shared__ float wd[TP];
+    __shared__ float ysh[TP * YLD];             // y, [pixel][re, im of column j]
+    __shared__ float wd[TP], aw2[TP];           // w and alpha w^2 of the current subset
     __shared__ float wsum[TP];
     __shared__ float pdsh[NW * TP];
-    uint16_t* Ah = abuf;                        // hi: [p][LDK], re at c, im at NTEP + c
-    uint16_t* Al = abuf + TP * LDK;             // lo
+    uint16_t* Ah = abuf;                        // hi: [p][LDK], re at c, M block at KC, im at KB + c
+    uint16_t* Al = abuf + TP * LDK;             // lo (no M block)
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, col = lane & 15;
     // XCD-aware order: the grid is a multiple of 8 and block b runs on XCD b % 8
@@ -1161,13 +1125,10 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
     static_assert(TW == 16, "one MFMA row tile per tile row");
     auto in_tile = [&](int p) { return (p / TW) < td.nrow && (p % TW) < npx; };
     auto pix_off = [&](int p) { return (long)(td.y + p / TW) * nx + td.x0 + p % TW; };
-    auto window = [&](const SubsetDesc& sd, int p) -> double {
-        const int y = td.y + p / TW, x = td.x0 + p % TW;
-        if (!in_tile(p) || y < sd.y0 || y > sd.y1 || x < sd.x0 || x > sd.x1) return 0.0;
-        return sd.flat ? 1.0 : ws.wtab[sd.wy_off + y - sd.y0] * ws.wtab[sd.wx_off + x - sd.x0];
-    };
+    // output frame tiles of this wave that exist (all of them when QFULL)
+    auto qok = [&](int q) { return C::QFULL || wave * QW + q < C::NNT; };
 
-    {   // K padding and the y columns beyond RMAX stay zero for every subset
+    {   // K padding, frames from nt up and the unused lo M block stay zero
         uint32_t* z = reinterpret_cast<uint32_t*>(abuf);
         for (int e = tid; e < TP * LDK; e += NTHR) z[e] = 0u;
     }
@@ -1178,7 +1139,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int ks = wave + NW * i, p = 16 * a + col, t = 16 * ks + 4 * g + e;
+                const int ks = wave + NW * i, p = 16 * a + col, t = 16 * ks + g + 4 * e;
                 sv[i][a][e] = (ks < C::KSTEPS && in_tile(p) && t < nt) ? pk.iq[(long)t * npix + pix_off(p)]
                                                                         : make_float2(0.f, 0.f);
             }
@@ -1191,11 +1152,14 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
             vnext[i] = e < NTP * RMAX ? ws.vr64[(long)s * NTP * RMAX + e] : make_double2(0.0, 0.0);
         }
     };
-    auto vstore = [&](int b) {
+    // V_r of a subset of rank r into buffer b, zero beyond the rank and from nt
+    // up (so the score and residual products need no masks)
+    auto vstore = [&](int b, int r) {
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             const int e = tid + NTHR * i;
-            if (e < NTP * RMAX) vrs[b][(e % RMAX) * NTP + e / RMAX] = vnext[i];
+            const int j = e % RMAX, t = e / RMAX;
+            if (e < NTP * RMAX) vrs[b][j * LDV + t] = (j < r && t < nt) ? vnext[i] : make_double2(0.0, 0.0);
         }
     };
     // Subset data is requested ahead of use so that no chain of dependent global
@@ -1216,7 +1180,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
         const int s0 = ws.cover[td.cov_off];
         nxt = sub_load(s0);
         vload(s0);
-        vstore(0);
+        vstore(0, nxt.r);
         if (ncov > 1) {
             s_ahead = ws.cover[td.cov_off + 1];
             vload(s_ahead);
@@ -1238,7 +1202,6 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
         const int b = ci & 1;
         const SubNext cur = nxt;
         const int s = cur.s, r = cur.r;
-        const float alpha = (float)cur.alpha;
         const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * (NTP + REXT)) * (2 * NTP));
         if (ci + 1 < ncov) nxt = sub_load(s_ahead);
         const int s_ahead2 = ci + 2 < ncov ? ws.cover[td.cov_off + ci + 2] : 0;
@@ -1268,9 +1231,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
                     u32x4 bh, bl;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const int t = 16 * ks + 4 * g + e;
-                        double2 v = make_double2(0.0, 0.0);
-                        if (j < r && t < nt) v = vrs[b][j * NTP + t];
+                        const double2 v = vrs[b][j * LDV + 16 * ks + g + 4 * e];
                         uint32_t h, l;
                         split_bf16x2(imc ? (float)v.y : (float)v.x, imc ? (float)v.x : -(float)v.y, h, l);
                         bh[e] = h;
@@ -1301,7 +1262,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
                 for (int i = 0; i < 4; ++i) ypart[(wave * TP + 16 * a + 4 * g + i) * 16 + col] = ya[a][i];
         }
         __syncthreads();
-        // ---- C: y(p, j) and the y columns of the operand
+        // ---- C: y(p, j) (zero from r up) and the packed M block of the operand
         for (int e = tid; e < TP * RMAX; e += NTHR) {
             const int p = e / RMAX, j = e % RMAX;
             float yr = 0.f, yi = 0.f;
@@ -1312,56 +1273,60 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
                     yi += ypart[(w * TP + p) * 16 + 8 + j];
                 }
             }
-            ysh[p * RMAX + j] = make_float2(yr, yi);
+            ysh[p * YLD + 2 * j] = yr;
+            ysh[p * YLD + 2 * j + 1] = yi;
             uint32_t h, l;
             split_bf16x2(yr, yi, h, l);
-            Ah[p * LDK + NTP + j] = (uint16_t)h;
-            Ah[p * LDK + NTEP + NTP + j] = (uint16_t)(h >> 16);
-            Al[p * LDK + NTP + j] = (uint16_t)l;
-            Al[p * LDK + NTEP + NTP + j] = (uint16_t)(l >> 16);
+            uint16_t* my = Ah + p * LDK + KC;
+            my[j] = (uint16_t)h;
+            my[8 + j] = (uint16_t)(h >> 16);
+            my[16 + j] = (uint16_t)l;
+            my[24 + j] = (uint16_t)(l >> 16);
         }
         __syncthreads();
-        // ---- D: c' = s - y V_r^H (FP64), written as four frames per store
+        // ---- D: c' = s - y V_r^H (FP64 MFMA), written as four frames per store.
+        // Tile (frames 16 ks .. + 15) x (pixels 16 a .. + 15); lane (col, g) holds
+        // frames g + 4 e of pixel col, which go to positions 4 g + e of the operand
+        // row. K chunk c holds tissue columns 2 c, 2 c + 1 as
+        // k = 4 c + 2 (j - 2 c) + (0: re, 1: im):
+        //   Re c' = Re s + sum_k A_re B,  A_re = (-Re v, -Im v),  B = (Re y, Im y)
+        //   Im c' = Im s + sum_k A_im B,  A_im = ( Im v, -Re v)
+        const int nch = (r + 1) >> 1;
 #pragma unroll
         for (int i = 0; i < MKS; ++i) {
             const int ks = wave + NW * i;
             if (ks < C::KSTEPS) {
                 const int t0 = 16 * ks + 4 * g;
-                double cr[NRT][4], cim[NRT][4];
+                doublex4 cre[NRT], cim[NRT];
 #pragma unroll
                 for (int a = 0; a < NRT; ++a)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        cr[a][e] = (double)sv[i][a][e].x;
-                        cim[a][e] = (double)sv[i][a][e].y;
+                        // converted per subset: kept out of the loop, the FP64 copy
+                        // would hold 64 more registers through every phase
+                        float2 sc = sv[i][a][e];
+                        asm volatile("" : "+v"(sc.x), "+v"(sc.y));
+                        cre[a][e] = (double)sc.x;
+                        cim[a][e] = (double)sc.y;
                     }
-                for (int j = 0; j < r; ++j) {
-                    double yr[NRT], yi[NRT];
+                const bool kim = g & 1;
+                for (int c = 0; c < nch; ++c) {
+                    const int j = 2 * c + (g >> 1);
+                    const double2 v = vrs[b][j * LDV + 16 * ks + col];
+                    const double are = kim ? -v.y : -v.x;
+                    const double aim = kim ? -v.x : v.y;
 #pragma unroll
                     for (int a = 0; a < NRT; ++a) {
-                        const float2 y = ysh[(16 * a + col) * RMAX + j];
-                        yr[a] = (double)y.x;
-                        yi[a] = (double)y.y;
-                    }
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const double2 v = vrs[b][j * NTP + t0 + e];
-#pragma unroll
-                        for (int a = 0; a < NRT; ++a) {
-                            // minus y * conj(v)
-                            cr[a][e] = fma(-yr[a], v.x, fma(-yi[a], v.y, cr[a][e]));
-                            cim[a][e] = fma(-yi[a], v.x, fma(yr[a], v.y, cim[a][e]));
-                        }
+                        const double yb = (double)ysh[(16 * a + col) * YLD + 2 * j + (g & 1)];
+                        cre[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, yb, cre[a], 0, 0, 0);
+                        cim[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, yb, cim[a], 0, 0, 0);
                     }
                 }
 #pragma unroll
                 for (int a = 0; a < NRT; ++a) {
                     uint32_t h[4], l[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const bool in = t0 + e < nt;
-                        split_bf16x2(in ? (float)cr[a][e] : 0.f, in ? (float)cim[a][e] : 0.f, h[e], l[e]);
-                    }
+                    for (int e = 0; e < 4; ++e) split_bf16x2((float)cre[a][e], (float)cim[a][e], h[e], l[e]);
                     const int p = 16 * a + col;
                     // (re of frames e, e + 1) and (im of frames e, e + 1) from two split words
                     const uint2 hre = make_uint2(__builtin_amdgcn_perm(h[1], h[0], 0x05040100u),
@@ -1373,15 +1338,16 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
                     const uint2 lim = make_uint2(__builtin_amdgcn_perm(l[1], l[0], 0x07060302u),
                                                  __builtin_amdgcn_perm(l[3], l[2], 0x07060302u));
                     *reinterpret_cast<uint2*>(Ah + p * LDK + t0) = hre;
-                    *reinterpret_cast<uint2*>(Ah + p * LDK + NTEP + t0) = him;
+                    *reinterpret_cast<uint2*>(Ah + p * LDK + KB + t0) = him;
                     *reinterpret_cast<uint2*>(Al + p * LDK + t0) = lre;
-                    *reinterpret_cast<uint2*>(Al + p * LDK + NTEP + t0) = lim;
+                    *reinterpret_cast<uint2*>(Al + p * LDK + KB + t0) = lim;
                 }
             }
         }
         if (tid < TP) {
             const double w = wyv * wxv;
             wd[tid] = (float)w;
+            aw2[tid] = (float)(cur.alpha * w * w);
             wsum_acc += w;
             comp_acc += cur.alpha * w * w;
         }
@@ -1389,48 +1355,53 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
         // the next subset's V_r goes to the other buffer (last read by the
         // previous subset, which every wave has finished)
         if (ci + 1 < ncov) {
-            vstore(b ^ 1);
+            vstore(b ^ 1, nxt.r);
             if (ci + 2 < ncov) vload(s_ahead2);
         }
         s_ahead = s_ahead2;
-        // ---- E: chat = [c' | y] [P; M]; K over the re part, each step forms
+        // ---- E: chat = c' P + y M; each full K step forms
         // out_re = a_re P_re - a_im P_im and out_im = a_re P_im + a_im P_re
         floatx4 acc[NRT][CTW];
 #pragma unroll
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        constexpr int KUNR = NTP > 128 ? 1 : 2;
-#pragma unroll KUNR
-        for (int k0 = 0; k0 < NTEP; k0 += 32) {
-            const int kq = k0 + 8 * g;
-            u32x4 brh[QW], brl[QW], bih[QW], bil[QW];
+        // [P; M] fragments of one K step, (Re hi, Re lo, Im hi, Im lo) per frame tile
+        auto bload = [&](u32x4 (&bf)[QW][4], int kq) {
 #pragma unroll
             for (int q = 0; q < QW; ++q) {
                 const int nq = wave * QW + q;
-                brh[q] = brl[q] = bih[q] = bil[q] = u32x4{0u, 0u, 0u, 0u};
-                if (nq < C::NNT) {
-                    const uint16_t* src = planes + (long)(nq * 16 + col) * NTEP + kq;
-                    brh[q] = *reinterpret_cast<const u32x4*>(src);
-                    brl[q] = *reinterpret_cast<const u32x4*>(src + NTP * NTEP);
-                    bih[q] = *reinterpret_cast<const u32x4*>(src + 2 * NTP * NTEP);
-                    bil[q] = *reinterpret_cast<const u32x4*>(src + 3 * NTP * NTEP);
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) bf[q][pl] = u32x4{0u, 0u, 0u, 0u};
+                if (qok(q)) {
+                    const uint16_t* src = planes + (long)(nq * 16 + col) * KB + kq;
+#pragma unroll
+                    for (int pl = 0; pl < 4; ++pl)
+                        bf[q][pl] = *reinterpret_cast<const u32x4*>(src + (long)pl * NTP * KB);
                 }
             }
+        };
+        u32x4 bc[QW][4], bn[QW][4];
+        if constexpr (C::PREF) bload(bc, 8 * g);
+#pragma unroll 1
+        for (int kstep = 0; kstep < C::NKS; ++kstep) {
+            const int kq = 32 * kstep + 8 * g;
+            if constexpr (C::PREF) bload(bn, kq + 32);      // next step; after the last P step, the M block
+            else bload(bc, kq);
 #pragma unroll
             for (int a = 0; a < NRT; ++a) {
                 const uint16_t* arow = Ah + (16 * a + col) * LDK + kq;
                 const uint16_t* lrow = Al + (16 * a + col) * LDK + kq;
                 const bf16x8 xrh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow));
                 const bf16x8 xrl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow));
-                const bf16x8 xih = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow + NTEP));
-                const bf16x8 xil = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow + NTEP));
+                const bf16x8 xih = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(arow + KB));
+                const bf16x8 xil = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(lrow + KB));
 #pragma unroll
                 for (int q = 0; q < QW; ++q) {
-                    if (wave * QW + q < C::NNT) {
-                        const bf16x8 prh = __builtin_bit_cast(bf16x8, brh[q]), prl = __builtin_bit_cast(bf16x8, brl[q]);
-                        const bf16x8 pih = __builtin_bit_cast(bf16x8, bih[q]), pil = __builtin_bit_cast(bf16x8, bil[q]);
-                        u32x4 nh = bih[q], nl = bil[q];
+                    if (qok(q)) {
+                        const bf16x8 prh = __builtin_bit_cast(bf16x8, bc[q][0]), prl = __builtin_bit_cast(bf16x8, bc[q][1]);
+                        const bf16x8 pih = __builtin_bit_cast(bf16x8, bc[q][2]), pil = __builtin_bit_cast(bf16x8, bc[q][3]);
+                        u32x4 nh = bc[q][2], nl = bc[q][3];
 #pragma unroll
                         for (int e = 0; e < 4; ++e) { nh[e] ^= 0x80008000u; nl[e] ^= 0x80008000u; }
                         const bf16x8 nih = __builtin_bit_cast(bf16x8, nh), nil = __builtin_bit_cast(bf16x8, nl);
@@ -1451,19 +1422,44 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
                     }
                 }
             }
+            if constexpr (C::PREF) {
+#pragma unroll
+                for (int q = 0; q < QW; ++q)
+#pragma unroll
+                    for (int pl = 0; pl < 4; ++pl) bc[q][pl] = bn[q][pl];
+            }
+        }
+        // the packed M block: two MFMAs per output tile
+        if constexpr (!C::PREF) bload(bc, KC + 8 * g);
+#pragma unroll
+        for (int a = 0; a < NRT; ++a) {
+            const bf16x8 xy =
+                __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + (16 * a + col) * LDK + KC + 8 * g));
+#pragma unroll
+            for (int q = 0; q < QW; ++q) {
+                if (qok(q)) {
+                    floatx4& ore = acc[a][2 * q];
+                    floatx4& oim = acc[a][2 * q + 1];
+                    ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xy, __builtin_bit_cast(bf16x8, bc[q][0]), ore, 0, 0, 0);
+                    ore = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xy, __builtin_bit_cast(bf16x8, bc[q][1]), ore, 0, 0, 0);
+                    oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xy, __builtin_bit_cast(bf16x8, bc[q][2]), oim, 0, 0, 0);
+                    oim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xy, __builtin_bit_cast(bf16x8, bc[q][3]), oim, 0, 0, 0);
+                }
+            }
         }
         // epilogue: output element (pixel 16 a + 4 g + i, column tile of accumulator m)
 #pragma unroll
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
-            for (int m = 0; m < CTW; ++m) {
-                if (wave * QW + (m >> 1) < C::NNT) {
+            for (int i = 0; i < 4; ++i) {
+                const int p = 16 * a + 4 * g + i;
+                const float w = wd[p], aw = aw2[p];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float w = wd[16 * a + 4 * g + i];
+                for (int m = 0; m < CTW; ++m) {
+                    if (qok(m >> 1)) {
                         const float v = acc[a][m][i];
-                        pd_acc[a * 4 + i] += alpha * w * w * v * v;
-                        iq_acc[a][m][i] += w * v;
+                        pd_acc[a * 4 + i] = fmaf(aw, v * v, pd_acc[a * 4 + i]);
+                        iq_acc[a][m][i] = fmaf(w, v, iq_acc[a][m][i]);
                     }
                 }
             }
@@ -1495,7 +1491,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
 #pragma unroll
             for (int m = 0; m < CTW; ++m) {
                 const int q = wave * QW + (m >> 1);
-                if (q < C::NNT) {
+                if (qok(m >> 1)) {
                     const int part_ = m & 1, t = q * 16 + col;
                     if (t < nt) {
 #pragma unroll
@@ -1522,11 +1518,8 @@ static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t 
     } else if (ws.ntiles > 0) {
         const int grid = (ws.ntiles + 7) / 8 * 8;      // multiple of 8 for the XCD mapping
         if constexpr (trows_max(NTP) >= 4) {
-            if (ws.trows == 4 && ws.rvar == 1) {
-                if (prec == 0)
-                    hipLaunchKernelGGL((k_reproj_pc<NTP, 0, 4>), dim3(grid), dim3(RpPcCfg<NTP, 0, 4>::NTHR), 0, st, ws);
-                else
-                    hipLaunchKernelGGL((k_reproj_pc<NTP, 1, 4>), dim3(grid), dim3(RpPcCfg<NTP, 1, 4>::NTHR), 0, st, ws);
+            if (ws.trows == 4 && ws.rvar == 1 && prec == 0) {
+                hipLaunchKernelGGL((k_reproj_pc<NTP, 0, 4>), dim3(grid), dim3(RpPcCfg<NTP, 0, 4>::NTHR), 0, st, ws);
                 return;
             }
             if (ws.trows == 4) {

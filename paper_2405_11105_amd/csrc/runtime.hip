@@ -157,7 +157,7 @@ struct Plan {
     int ntp = 0, nt_max = 0;
     int chunk = CHUNK;      // split-K chunk of the Gram passes (box pixels)
     int trows = 2;          // image rows per reprojection tile (2 or 4)
-    int rvar = 0;           // reprojection kernel variant (1: producer/consumer, 4-row tiles only)
+    int rvar = 0;           // reprojection kernel variant (1: producer/consumer, FP32 with 4-row tiles only)
     int evd = -1;           // subset EVD method (LCF_OPT_EVD values); -1 the context's
     std::vector<SubsetDesc> sub;
     std::vector<ChunkDesc> chunks;
@@ -855,7 +855,10 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
         return true;
     };
     std::vector<std::pair<int, int>> tiles = {{2, 0}};                 // (rows, variant)
-    if (trows_max(ntp) >= 4) { tiles.push_back({4, 0}); tiles.push_back({4, 1}); }
+    if (trows_max(ntp) >= 4) {
+        tiles.push_back({4, 0});
+        if (prec == LCF_PREC_FP32) tiles.push_back({4, 1});       // producer/consumer: FP32 only
+    }
     for (const auto& tv : tiles)
         for (int ch : chunks)
             if (!trial(ch, tv.first, tv.second, c->evd_method)) goto done;
