@@ -917,25 +917,31 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
 
 
 // ------------------------------------------------------------------ tridiagonal EVD
-// Subset EVD (Eq. 2) through a real symmetric tridiagonal matrix, for padded
-// sizes up to 128 (the matrix lives in VGPRs as in k_jacobi_reg: wave w holds
-// columns 16 w .. 16 w + 15, lane l rows l + 64 i):
+// Subset EVD (Eq. 2) through a real symmetric tridiagonal matrix:
 //  1. Householder reduction B = Q T Q^H, Q = H_0 .. H_{n-3}, H_j = I - tau v v^H,
 //     with the two-sided update A <- A - v q^H - q v^H (p = tau A v,
 //     q = p - (tau / 2)(v^H p) v); the vectors go to scratch.
 //  2. T = D T_r D^H with a diagonal unitary D makes the off-diagonal real >= 0.
+//     (Steps 1 and 2: k_heev_tri_reduce up to 128 frames, the matrix in VGPRs as
+//     in k_jacobi_reg: wave w holds columns 16 w .. 16 w + 15, lane l rows
+//     l + 64 i; k_heev_big_reduce above, the matrix in global memory.)
 //  3. Eigenvalues of T_r by multisection of Sturm counts (4 lanes per
-//     eigenvalue, 5 sub-intervals per round), sorted descending by construction.
+//     eigenvalue, 5 sub-intervals per round), sorted descending by construction
+//     (k_heev_sturm, for both).
 //  4. Each eigenvector of T_r from a twisted factorisation
 //     (T_r - lambda I) = N_r Delta_r N_r^T at the twist index r of smallest
 //     |gamma_r|, one lane per eigenvalue (one O(n) solve, no iteration).
 //  5. Eigenvectors of B: y = Q D z, the reflectors applied in reverse order.
+//     (Steps 4 and 5: k_heev_tri_vecs, after the weights.)
 // A subset whose eigenvalues are closer than 1e-12 lambda_1 (where such vectors
 // would lose orthogonality) keeps its B and is flagged for the Jacobi kernel.
+// The scratch of a subset (the second half of its projector slot) holds the
+// tridiagonal form: d, |e|, |e|^2, Re D, Im D (N each), then pivmin and the
+// Gershgorin interval.
 constexpr int FLAG_EVD_FALLBACK = 16;
 
 template <int RPL, int NW>
-__global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
+__global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
     constexpr int N = 16 * NW;             // padded size held (columns)
     constexpr int NTHR = 64 * NW;
     static_assert(64 * RPL >= N, "rows per lane cover the padded size");
@@ -945,18 +951,14 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
     __shared__ double red[2];
     __shared__ double dsh[N], esh[N], e2sh[N];
     __shared__ double2 phs[N];             // complex e_j, then D
-    __shared__ double lamsh[N], insh[N];
     __shared__ double bnd[2];
-    __shared__ int gcnt[64 * NW];          // Sturm counts at the bracketing grid
     __shared__ double tau_sh[2];
-    __shared__ int cluster;
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nt = ws.sub[s].nt;
     double2* Bm = ws.bmat + (long)s * N * N;
     double2* H = ws.wvec + (long)s * N * N;                 // Householder vectors, tau in element 0
     double* trid = reinterpret_cast<double*>(ws.pmat + (long)s * N * N) + N * N;   // tridiagonal form
-    if (tid == 0) cluster = 0;
 
     double2 A[16][RPL];
 #pragma unroll
@@ -1187,65 +1189,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
         }
     }
     __syncthreads();
-    const double pivmin = red[0];
-    // ---- 3. eigenvalues. One Sturm count per thread at NTHR grid points (the
-    // lower Gershgorin bound, then geometric steps from hi 2^-64 up to hi) brackets
-    // every eigenvalue; then multisection, lanes 4k .. 4k+3 for the k-th largest,
-    // 4 points and 5 sub-intervals per round, until the bracket is no wider than
-    // (hi - lo) 5^-24 (the width 24 rounds from the Gershgorin interval reach,
-    // below the rounding of the largest eigenvalue)
-    {
-        const double lo = bnd[0], hi = bnd[1];
-        auto sturm = [&](double x) {
-            double q = dsh[0] - x;
-            int c = q < 0.0;
-            for (int i = 1; i < nt; ++i) {
-                if (fabs(q) < pivmin) q = -pivmin;
-                q = (dsh[i] - x) - e2sh[i - 1] * rcp_nr(q);
-                c += q < 0.0;
-            }
-            return c;
-        };
-        auto grid = [&](int g) {
-            if (hi <= 0.0) return lo + (hi - lo) * (double)g / (double)(NTHR - 1);
-            if (g == 0) return lo;
-            return fmax(lo, hi * exp2(-64.0 * (double)(NTHR - 1 - g) / (double)(NTHR - 2)));
-        };
-        gcnt[tid] = sturm(grid(tid));
-        __syncthreads();
-        const int k = tid >> 2, m = tid & 3;
-        const int target = nt - 1 - k;                                 // index among ascending
-        // counts are nondecreasing along the grid: the last point with count <= target
-        int g0 = 0, g1 = NTHR - 1;                                     // gcnt[g0] <= target < gcnt[g1]
-        while (g1 - g0 > 1) {
-            const int gm = (g0 + g1) >> 1;
-            if (gcnt[gm] <= target) g0 = gm;
-            else g1 = gm;
-        }
-        double a = grid(g0), b = g1 == NTHR - 1 ? hi : grid(g1);
-        const double tol = (hi - lo) * 1.7e-17;
-        for (int it = 0; it < 24 && b - a > tol; ++it) {
-            const double h = (b - a) * 0.2;
-            const double x = a + (double)(m + 1) * h;
-            const int cnt = k < nt ? sturm(x) : 0;
-            // the points left of the eigenvalue are those with count <= target
-            int le = cnt <= target;
-            le += __shfl_xor(le, 1, 64);
-            le += __shfl_xor(le, 2, 64);
-            const double na = a + (double)le * h;
-            b = le == 4 ? b : a + (double)(le + 1) * h;
-            a = na;
-        }
-        if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
-    }
-    __syncthreads();
-    // eigenvalues; the tridiagonal form (d, |e|, |e|^2, D, pivmin) for the
-    // eigenvector pass; a subset with eigenvalues closer than 1e-12 lambda_1
-    // keeps its B for the Jacobi kernel
-    if (tid < nt) {
-        ws.lam[(long)s * N + tid] = lamsh[tid];
-        if (tid + 1 < nt && lamsh[tid] - lamsh[tid + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
-    }
+    // the tridiagonal form (d, |e|, |e|^2, D), pivmin and the Gershgorin interval
     for (int i = tid; i < N; i += 64 * NW) {
         trid[i] = dsh[i];
         trid[N + i] = esh[i];
@@ -1254,14 +1198,88 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_vals(Workspace ws) {
         trid[4 * N + i] = phs[i].y;
     }
     if (tid == 0) {
-        trid[5 * N] = pivmin;
-        ws.sweeps[s] = 0;
+        trid[5 * N] = red[0];
+        trid[5 * N + 1] = bnd[0];
+        trid[5 * N + 2] = bnd[1];
     }
+}
+
+// Step 3 for both reduction kernels. NTHR Sturm counts at grid points (the
+// lower Gershgorin bound, then geometric steps from hi 2^-64 up to hi) bracket
+// every eigenvalue; then multisection, lanes 4k .. 4k+3 for the k-th largest,
+// 4 points and 5 sub-intervals per round, until the bracket is no wider than
+// (hi - lo) 1.7e-17 (24 rounds from the Gershgorin interval reach it, below
+// the rounding of the largest eigenvalue). Each count is a dependent chain of
+// nt divisions: the kernel holds few registers, so several work-groups per CU
+// hide that latency (inside the reduction kernels two waves per SIMD did).
+template <int N, int NTHR>
+__global__ void __launch_bounds__(NTHR) k_heev_sturm(Workspace ws) {
+    static_assert(NTHR >= 4 * N, "four lanes per eigenvalue");
+    __shared__ double dsh[N], e2sh[N], lamsh[N];
+    __shared__ int gcnt[NTHR];                 // Sturm counts at the bracketing grid
+    __shared__ int cluster;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nt = ws.sub[s].nt;
+    const double* trid = reinterpret_cast<const double*>(ws.pmat + (long)s * N * N) + N * N;
+    for (int i = tid; i < N; i += NTHR) {
+        dsh[i] = trid[i];
+        e2sh[i] = trid[2 * N + i];
+    }
+    if (tid == 0) cluster = 0;
+    const double pivmin = trid[5 * N], lo = trid[5 * N + 1], hi = trid[5 * N + 2];
+    __syncthreads();
+    auto sturm = [&](double x) {
+        double q = dsh[0] - x;
+        int c = q < 0.0;
+        for (int i = 1; i < nt; ++i) {
+            if (fabs(q) < pivmin) q = -pivmin;
+            q = (dsh[i] - x) - e2sh[i - 1] * rcp_nr(q);
+            c += q < 0.0;
+        }
+        return c;
+    };
+    auto grid = [&](int g) {
+        if (hi <= 0.0) return lo + (hi - lo) * (double)g / (double)(NTHR - 1);
+        if (g == 0) return lo;
+        return fmax(lo, hi * exp2(-64.0 * (double)(NTHR - 1 - g) / (double)(NTHR - 2)));
+    };
+    gcnt[tid] = sturm(grid(tid));
+    __syncthreads();
+    const int k = tid >> 2, m = tid & 3;
+    const int target = nt - 1 - k;                                 // index among ascending
+    // counts are nondecreasing along the grid: the last point with count <= target
+    int g0 = 0, g1 = NTHR - 1;                                     // gcnt[g0] <= target < gcnt[g1]
+    while (g1 - g0 > 1) {
+        const int gm = (g0 + g1) >> 1;
+        if (gcnt[gm] <= target) g0 = gm;
+        else g1 = gm;
+    }
+    double a = grid(g0), b = g1 == NTHR - 1 ? hi : grid(g1);
+    const double tol = (hi - lo) * 1.7e-17;
+    for (int it = 0; it < 24 && b - a > tol; ++it) {
+        const double h = (b - a) * 0.2;
+        const double x = a + (double)(m + 1) * h;
+        const int cnt = k < nt ? sturm(x) : 0;
+        // the points left of the eigenvalue are those with count <= target
+        int le = cnt <= target;
+        le += __shfl_xor(le, 1, 64);
+        le += __shfl_xor(le, 2, 64);
+        const double na = a + (double)le * h;
+        b = le == 4 ? b : a + (double)(le + 1) * h;
+        a = na;
+    }
+    if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
+    __syncthreads();
+    if (tid < nt) {
+        ws.lam[(long)s * N + tid] = lamsh[tid];
+        if (tid + 1 < nt && lamsh[tid] - lamsh[tid + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
+    }
+    if (tid == 0) ws.sweeps[s] = 0;
     __syncthreads();
     if (cluster && tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
 }
 
-// Eigenvectors of the subsets solved by k_heev_tri_vals (steps 4 and 5), for
+// Eigenvectors of the subsets solved by the tridiagonal path (steps 4 and 5), for
 // the components whose weight differs from 1 (all of them when `all` is set):
 // only those enter the projector P = I - W' diag(1 - w) W'^H.
 template <int RPL, int NW>
@@ -1455,31 +1473,28 @@ __global__ void __launch_bounds__(64 * (NW < 4 ? NW : 4)) k_heev_tri_vecs(Worksp
     }
 }
 
-// Subset EVD above 128 frames (padded sizes 160 and 208), steps 1-3 of the
+// Subset EVD above 128 frames (padded sizes 160 and 208), steps 1 and 2 of the
 // tridiagonal path with the matrix in global memory: the register layout of
-// k_heev_tri_vals would not fit the register file at these sizes. The working
+// k_heev_tri_reduce would not fit the register file at these sizes. The working
 // copy A (column-major, the projector slot of the subset) is reduced column by
 // column: the reflector v of column j (one block reduction), p = tau A v over
 // the trailing block (thread (g, r): row r, every fourth column from j + 1 + g,
 // so each load runs along a column), q = p - (tau / 2)(v^H p) v, and the
 // two-sided update A -= v q^H + q v^H of the trailing block. The reflectors go
 // where k_heev_tri_vecs reads them (tau in row 0 of v_j, which is zero), the
-// tridiagonal form to the same scratch, and a subset whose eigenvalues are
-// closer than 1e-12 lambda_1 keeps B (row-major, untouched here) for the
+// tridiagonal form to the same scratch; B (row-major) is left untouched for the
 // Jacobi kernel.
 template <int N, int RPL>
-__global__ void __launch_bounds__(1024) k_heev_big_vals(Workspace ws) {
+__global__ void __launch_bounds__(1024) k_heev_big_reduce(Workspace ws) {
     constexpr int NTHR = 1024, NG = NTHR / 256;
     static_assert(N <= 256 && 64 * RPL >= N, "rows per lane of the scan cover the size");
     __shared__ double2 vsh[N], qsh[N];
     __shared__ double2 psum[NG][256];
-    __shared__ double dsh[N], esh[N], e2sh[N], lamsh[N];
+    __shared__ double dsh[N], esh[N], e2sh[N];
     __shared__ double2 phs[N];
     __shared__ double redd[32];
     __shared__ double bnd[3];
     __shared__ double tau_sh;
-    __shared__ int gcnt[NTHR];
-    __shared__ int cluster;
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = tid & 255, g = tid >> 8;
     const int nt = ws.sub[s].nt;
@@ -1487,7 +1502,6 @@ __global__ void __launch_bounds__(1024) k_heev_big_vals(Workspace ws) {
     double2* A = ws.pmat + (long)s * N * N;                  // working copy, A[c * N + r] = B[r][c]
     double2* H = ws.wvec + (long)s * N * N;
     double* trid = reinterpret_cast<double*>(ws.pmat + (long)s * N * N) + N * N;
-    if (tid == 0) cluster = 0;
     for (int e = tid; e < N * N; e += NTHR) {
         const int c = e / N, rr = e % N;
         A[e] = (rr < nt && c < nt) ? cconj(Bm[(long)c * N + rr]) : make_double2(0.0, 0.0);   // B[rr][c]
@@ -1622,56 +1636,6 @@ __global__ void __launch_bounds__(1024) k_heev_big_vals(Workspace ws) {
         }
     }
     __syncthreads();
-    const double pivmin = bnd[2];
-    // ---- 3. eigenvalues: Sturm counts at NTHR grid points bracket every
-    // eigenvalue, then multisection with four lanes per eigenvalue
-    {
-        const double lo = bnd[0], hi = bnd[1];
-        auto sturm = [&](double xx) {
-            double q = dsh[0] - xx;
-            int c = q < 0.0;
-            for (int i = 1; i < nt; ++i) {
-                if (fabs(q) < pivmin) q = -pivmin;
-                q = (dsh[i] - xx) - e2sh[i - 1] * rcp_nr(q);
-                c += q < 0.0;
-            }
-            return c;
-        };
-        auto grid = [&](int gi) {
-            if (hi <= 0.0) return lo + (hi - lo) * (double)gi / (double)(NTHR - 1);
-            if (gi == 0) return lo;
-            return fmax(lo, hi * exp2(-64.0 * (double)(NTHR - 1 - gi) / (double)(NTHR - 2)));
-        };
-        gcnt[tid] = sturm(grid(tid));
-        __syncthreads();
-        const int k = tid >> 2, m = tid & 3;
-        const int target = nt - 1 - k;
-        int g0 = 0, g1 = NTHR - 1;
-        while (g1 - g0 > 1) {
-            const int gm = (g0 + g1) >> 1;
-            if (gcnt[gm] <= target) g0 = gm;
-            else g1 = gm;
-        }
-        double a = grid(g0), b = g1 == NTHR - 1 ? hi : grid(g1);
-        const double tol = (hi - lo) * 1.7e-17;
-        for (int it = 0; it < 24 && b - a > tol; ++it) {
-            const double h = (b - a) * 0.2;
-            const double xx = a + (double)(m + 1) * h;
-            const int cnt = k < nt ? sturm(xx) : 0;
-            int le = cnt <= target;
-            le += __shfl_xor(le, 1, 64);
-            le += __shfl_xor(le, 2, 64);
-            const double na = a + (double)le * h;
-            b = le == 4 ? b : a + (double)(le + 1) * h;
-            a = na;
-        }
-        if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
-    }
-    __syncthreads();
-    if (tid < nt) {
-        ws.lam[(long)s * N + tid] = lamsh[tid];
-        if (tid + 1 < nt && lamsh[tid] - lamsh[tid + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
-    }
     for (int i = tid; i < N; i += NTHR) {
         trid[i] = dsh[i];
         trid[N + i] = esh[i];
@@ -1680,11 +1644,10 @@ __global__ void __launch_bounds__(1024) k_heev_big_vals(Workspace ws) {
         trid[4 * N + i] = phs[i].y;
     }
     if (tid == 0) {
-        trid[5 * N] = pivmin;
-        ws.sweeps[s] = 0;
+        trid[5 * N] = bnd[2];
+        trid[5 * N + 1] = bnd[0];
+        trid[5 * N + 2] = bnd[1];
     }
-    __syncthreads();
-    if (cluster && tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
 }
 
 // Normalise columns, sort by norm descending, write eigenvalues and vectors.
@@ -1829,22 +1792,34 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
     // (method 1). Beyond 128: the LDS / global Jacobi.
     const int sel = method == 0 ? FLAG_EVD_FALLBACK : 0;
     if (ws.ntp <= 32) {
-        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
+        if (method == 0) {
+            hipLaunchKernelGGL((k_heev_tri_reduce<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<32, 128>), dim3(ws.S), dim3(128), 0, st, ws);
+        }
         hipLaunchKernelGGL((k_jacobi_reg<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp <= 64) {
-        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
+        if (method == 0) {
+            hipLaunchKernelGGL((k_heev_tri_reduce<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<64, 256>), dim3(ws.S), dim3(256), 0, st, ws);
+        }
         hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp == 96) {
-        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<2, 6>), dim3(ws.S), dim3(384), 0, st, ws);
+        if (method == 0) {
+            hipLaunchKernelGGL((k_heev_tri_reduce<2, 6>), dim3(ws.S), dim3(384), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<96, 384>), dim3(ws.S), dim3(384), 0, st, ws);
+        }
         hipLaunchKernelGGL((k_jacobi_reg<2, 6>), dim3(ws.S), dim3(384), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
     if (ws.ntp <= 128) {
-        if (method == 0) hipLaunchKernelGGL((k_heev_tri_vals<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
+        if (method == 0) {
+            hipLaunchKernelGGL((k_heev_tri_reduce<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<128, 512>), dim3(ws.S), dim3(512), 0, st, ws);
+        }
         hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps, sel);
         return hipGetLastError();
     }
@@ -1852,8 +1827,13 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
     // (method 0) and the LDS / global Jacobi for the subsets it flags, or the
     // Jacobi for all (method 1).
     if (method == 0) {
-        if (ws.ntp == 160) hipLaunchKernelGGL((k_heev_big_vals<160, 3>), dim3(ws.S), dim3(1024), 0, st, ws);
-        else hipLaunchKernelGGL((k_heev_big_vals<208, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
+        if (ws.ntp == 160) {
+            hipLaunchKernelGGL((k_heev_big_reduce<160, 3>), dim3(ws.S), dim3(1024), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<160, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
+        } else {
+            hipLaunchKernelGGL((k_heev_big_reduce<208, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<208, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
+        }
     }
     if (nt_max <= JAC_LDS_NT) {
         const size_t lds = (size_t)nt_max * nt_max * sizeof(double2);
