@@ -167,8 +167,10 @@ typedef struct {
 #define LCF_FLAG_NO_CONVERGE   4  /* Jacobi reached max sweeps                               */
 #define LCF_FLAG_MLP_FALLBACK  8  /* learned weights not used, rule weights kept: input out of
                                      range, or the gate (LCF_OPT_MLP_GATE) rejected them    */
-#define LCF_FLAG_EVD_JACOBI   16  /* near-degenerate spectrum: EVD by Jacobi instead of the
-                                     tridiagonal solver (informational)                   */
+#define LCF_FLAG_EVD_JACOBI   16  /* near-degenerate pair at a component the projector needs
+                                     (weight != 1, or every component under the NCC rule or
+                                     when the diagnostics ask for all eigenvectors): EVD by
+                                     Jacobi instead of the tridiagonal solver (informational) */
 
 /* Context options (lcf_set_option). */
 #define LCF_OPT_SCHEDULE     1  /* 0 = batched (all subsets per stage in one launch, default);
@@ -198,8 +200,9 @@ typedef struct {
 #define LCF_OPT_EVD          7  /* subset EVD (Eq. 2) up to 128 frames: 0 = Householder
                                    tridiagonal reduction, multisection eigenvalues and
                                    twisted-factorisation eigenvectors, with the Jacobi
-                                   solver for subsets whose eigenvalues are closer than
-                                   1e-12 lambda_1 (flag LCF_FLAG_EVD_JACOBI; default);
+                                   solver for subsets where a component whose vector the
+                                   projector needs has a neighbour closer than 1e-12
+                                   lambda_1 (flag LCF_FLAG_EVD_JACOBI; default);
                                    1 = FP64 one-sided Jacobi for every subset           */
 
 #define LCF_OPT_MLP_GATE     8  /* learned weights: the plain rule (the threshold's curvature

@@ -933,8 +933,12 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
 //     |gamma_r|, one lane per eigenvalue (one O(n) solve, no iteration).
 //  5. Eigenvectors of B: y = Q D z, the reflectors applied in reverse order.
 //     (Steps 4 and 5: k_heev_tri_vecs, after the weights.)
-// A subset whose eigenvalues are closer than 1e-12 lambda_1 (where such vectors
-// would lose orthogonality) keeps its B and is flagged for the Jacobi kernel.
+// Only the components whose weight differs from 1 enter the projector, so only
+// their vectors are formed (step 4 and 5, after the weights). A subset where one
+// of them has a neighbour closer than 1e-12 lambda_1 (where such vectors would
+// lose orthogonality) keeps its B and is flagged for the Jacobi kernel, which
+// then runs on it alone; near-equal eigenvalues among the others (the noise
+// floor's smallest spacings) need no vectors and no fallback.
 // The scratch of a subset (the second half of its projector slot) holds the
 // tridiagonal form: d, |e|, |e|^2, Re D, Im D (N each), then pivmin and the
 // Gershgorin interval.
@@ -1215,19 +1219,33 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
 template <int N, int NTHR>
 __global__ void __launch_bounds__(NTHR) k_heev_sturm(Workspace ws) {
     static_assert(NTHR >= 4 * N, "four lanes per eigenvalue");
-    __shared__ double dsh[N], e2sh[N], lamsh[N];
+    __shared__ double dsh[N], e2sh[N];
     __shared__ int gcnt[NTHR];                 // Sturm counts at the bracketing grid
-    __shared__ int cluster;
+    __shared__ int offdiag;
     const int s = blockIdx.x, tid = threadIdx.x;
     const int nt = ws.sub[s].nt;
     const double* trid = reinterpret_cast<const double*>(ws.pmat + (long)s * N * N) + N * N;
+    if (tid == 0) offdiag = 0;
+    __syncthreads();
     for (int i = tid; i < N; i += NTHR) {
         dsh[i] = trid[i];
         e2sh[i] = trid[2 * N + i];
+        if (i + 1 < nt && e2sh[i] != 0.0) offdiag = 1;
     }
-    if (tid == 0) cluster = 0;
-    const double pivmin = trid[5 * N], lo = trid[5 * N + 1], hi = trid[5 * N + 2];
+    if (tid == 0) ws.sweeps[s] = 0;
     __syncthreads();
+    if (!offdiag) {
+        // T is diagonal (an all-zero packet, for one): its eigenvalues are the
+        // diagonal exactly, in descending order (ties by index)
+        if (tid < nt) {
+            const double v = dsh[tid];
+            int rank = 0;
+            for (int j = 0; j < nt; ++j) rank += dsh[j] > v || (dsh[j] == v && j < tid);
+            ws.lam[(long)s * N + rank] = v;
+        }
+        return;
+    }
+    const double pivmin = trid[5 * N], lo = trid[5 * N + 1], hi = trid[5 * N + 2];
     auto sturm = [&](double x) {
         double q = dsh[0] - x;
         int c = q < 0.0;
@@ -1268,15 +1286,7 @@ __global__ void __launch_bounds__(NTHR) k_heev_sturm(Workspace ws) {
         b = le == 4 ? b : a + (double)(le + 1) * h;
         a = na;
     }
-    if (m == 0 && k < nt) lamsh[k] = 0.5 * (a + b);
-    __syncthreads();
-    if (tid < nt) {
-        ws.lam[(long)s * N + tid] = lamsh[tid];
-        if (tid + 1 < nt && lamsh[tid] - lamsh[tid + 1] <= 1e-12 * fabs(lamsh[0])) cluster = 1;
-    }
-    if (tid == 0) ws.sweeps[s] = 0;
-    __syncthreads();
-    if (cluster && tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
+    if (m == 0 && k < nt) ws.lam[(long)s * N + k] = 0.5 * (a + b);
 }
 
 // Eigenvectors of the subsets solved by the tridiagonal path (steps 4 and 5), for
@@ -1295,9 +1305,10 @@ __global__ void __launch_bounds__(64 * (NW < 4 ? NW : 4)) k_heev_tri_vecs(Worksp
     __shared__ double dml[N * SG];         // [i][slot in group]: D- of the slot's eigenvalue, then its z
     __shared__ int act[N];
     __shared__ int wcnt[NWV];
+    __shared__ int cluster;
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    if (ws.flags[s] & FLAG_EVD_FALLBACK) return;          // solved by the Jacobi kernel
+    if (tid == 0) cluster = 0;
     const int nt = ws.sub[s].nt;
     double2* Bm = ws.bmat + (long)s * N * N;
     const double2* H = ws.wvec + (long)s * N * N;
@@ -1322,8 +1333,18 @@ __global__ void __launch_bounds__(64 * (NW < 4 ? NW : 4)) k_heev_tri_vecs(Worksp
         off += w < wave ? wcnt[w] : 0;
         nact += wcnt[w];
     }
-    if (flag) act[off + __popcll(mask & ((1ull << lane) - 1ull))] = tid;
+    if (flag) {
+        act[off + __popcll(mask & ((1ull << lane) - 1ull))] = tid;
+        // a selected component with a neighbour closer than 1e-12 lambda_1
+        const double tol = 1e-12 * fabs(lamsh[0]);
+        if ((tid > 0 && lamsh[tid - 1] - lamsh[tid] <= tol) || (tid + 1 < nt && lamsh[tid] - lamsh[tid + 1] <= tol))
+            cluster = 1;
+    }
     __syncthreads();
+    if (cluster) {                                  // B stays for the Jacobi kernel
+        if (tid == 0) atomicOr(&ws.flags[s], FLAG_EVD_FALLBACK);
+        return;
+    }
     for (int g0 = 0; g0 < nact; g0 += SG) {
     const int cnt = nact - g0 < SG ? nact - g0 : SG;
     // ---- 4. eigenvectors of T_r by twisted factorisation (lane k); D- and then
@@ -1785,82 +1806,73 @@ hipError_t launch_assemble(const Workspace& ws, int keep_r, hipStream_t st) {
 // class must be one of those sizes.
 static bool tri_sized(int ntp) { return ntp > 128 || ntp == 32 || ntp == 64 || ntp == 96 || ntp == 128; }
 
-hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
-    if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
-    // Up to 128 frames: the tridiagonal solver (method 0), with the
-    // register-resident Jacobi for the subsets it flags, or the Jacobi for all
-    // (method 1). Beyond 128: the LDS / global Jacobi.
-    const int sel = method == 0 ? FLAG_EVD_FALLBACK : 0;
-    if (ws.ntp <= 32) {
-        if (method == 0) {
-            hipLaunchKernelGGL((k_heev_tri_reduce<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<32, 128>), dim3(ws.S), dim3(128), 0, st, ws);
-        }
-        hipLaunchKernelGGL((k_jacobi_reg<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, max_sweeps, sel);
-        return hipGetLastError();
-    }
-    if (ws.ntp <= 64) {
-        if (method == 0) {
-            hipLaunchKernelGGL((k_heev_tri_reduce<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<64, 256>), dim3(ws.S), dim3(256), 0, st, ws);
-        }
-        hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps, sel);
-        return hipGetLastError();
-    }
-    if (ws.ntp == 96) {
-        if (method == 0) {
-            hipLaunchKernelGGL((k_heev_tri_reduce<2, 6>), dim3(ws.S), dim3(384), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<96, 384>), dim3(ws.S), dim3(384), 0, st, ws);
-        }
-        hipLaunchKernelGGL((k_jacobi_reg<2, 6>), dim3(ws.S), dim3(384), 0, st, ws, max_sweeps, sel);
-        return hipGetLastError();
-    }
-    if (ws.ntp <= 128) {
-        if (method == 0) {
-            hipLaunchKernelGGL((k_heev_tri_reduce<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<128, 512>), dim3(ws.S), dim3(512), 0, st, ws);
-        }
-        hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps, sel);
-        return hipGetLastError();
-    }
-    // Beyond 128 frames: the tridiagonal path with the matrix in global memory
-    // (method 0) and the LDS / global Jacobi for the subsets it flags, or the
-    // Jacobi for all (method 1).
-    if (method == 0) {
-        if (ws.ntp == 160) {
-            hipLaunchKernelGGL((k_heev_big_reduce<160, 3>), dim3(ws.S), dim3(1024), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<160, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
-        } else {
-            hipLaunchKernelGGL((k_heev_big_reduce<208, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<208, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
-        }
-    }
-    if (nt_max <= JAC_LDS_NT) {
+// The Jacobi solver for the subsets selected by sel (0: every subset; the
+// fallback flag: those the eigenvector kernel handed back).
+static void launch_jacobi(const Workspace& ws, int max_sweeps, int nt_max, int sel, hipStream_t st) {
+    if (ws.ntp <= 32) hipLaunchKernelGGL((k_jacobi_reg<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, max_sweeps, sel);
+    else if (ws.ntp <= 64) hipLaunchKernelGGL((k_jacobi_reg<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, max_sweeps, sel);
+    else if (ws.ntp == 96) hipLaunchKernelGGL((k_jacobi_reg<2, 6>), dim3(ws.S), dim3(384), 0, st, ws, max_sweeps, sel);
+    else if (ws.ntp <= 128) hipLaunchKernelGGL((k_jacobi_reg<2, 8>), dim3(ws.S), dim3(512), 0, st, ws, max_sweeps, sel);
+    else if (nt_max <= JAC_LDS_NT) {
         const size_t lds = (size_t)nt_max * nt_max * sizeof(double2);
         hipLaunchKernelGGL((k_jacobi_subsets<true>), dim3(ws.S), dim3(JAC_THREADS), lds, st, ws, max_sweeps, sel);
     } else {
         hipLaunchKernelGGL((k_jacobi_subsets<false>), dim3(ws.S), dim3(JAC_THREADS), 0, st, ws, max_sweeps, sel);
     }
+}
+
+// Eigenvalues: the tridiagonal path (method 0; register-resident reduction up
+// to 128 frames, global-memory reduction above, then the multisection), or the
+// Jacobi solver for every subset (method 1), which also forms the vectors.
+hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st) {
+    if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
+    if (method != 0) {
+        launch_jacobi(ws, max_sweeps, nt_max, 0, st);
+        return hipGetLastError();
+    }
+    switch (ws.ntp) {
+        case 32:
+            hipLaunchKernelGGL((k_heev_tri_reduce<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<32, 128>), dim3(ws.S), dim3(128), 0, st, ws);
+            break;
+        case 64:
+            hipLaunchKernelGGL((k_heev_tri_reduce<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<64, 256>), dim3(ws.S), dim3(256), 0, st, ws);
+            break;
+        case 96:
+            hipLaunchKernelGGL((k_heev_tri_reduce<2, 6>), dim3(ws.S), dim3(384), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<96, 384>), dim3(ws.S), dim3(384), 0, st, ws);
+            break;
+        case 128:
+            hipLaunchKernelGGL((k_heev_tri_reduce<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<128, 512>), dim3(ws.S), dim3(512), 0, st, ws);
+            break;
+        case 160:
+            hipLaunchKernelGGL((k_heev_big_reduce<160, 3>), dim3(ws.S), dim3(1024), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<160, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
+            break;
+        default:
+            hipLaunchKernelGGL((k_heev_big_reduce<208, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<208, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
+            break;
+    }
     return hipGetLastError();
 }
 
-// Eigenvectors after the weights are known (tridiagonal paths, at every size);
-// the Jacobi paths produced theirs already.
-hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStream_t st) {
+// Eigenvectors after the weights are known (tridiagonal path, at every size;
+// all = 1 forms every component's, as the NCC rule needs), then the Jacobi
+// solver for the subsets whose selected components sit in a near-degenerate
+// pair; the Jacobi path (method 1) produced its vectors already.
+hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, int max_sweeps, int nt_max, hipStream_t st) {
     if (!tri_sized(ws.ntp)) return hipErrorInvalidValue;
     if (method != 0) return hipSuccess;
-    if (ws.ntp == 160) {
-        hipLaunchKernelGGL((k_heev_tri_vecs<3, 10>), dim3(ws.S), dim3(256), 0, st, ws, all);
-        return hipGetLastError();
-    }
-    if (ws.ntp == 208) {
-        hipLaunchKernelGGL((k_heev_tri_vecs<4, 13>), dim3(ws.S), dim3(256), 0, st, ws, all);
-        return hipGetLastError();
-    }
-    if (ws.ntp <= 32) hipLaunchKernelGGL((k_heev_tri_vecs<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, all);
+    if (ws.ntp == 160) hipLaunchKernelGGL((k_heev_tri_vecs<3, 10>), dim3(ws.S), dim3(256), 0, st, ws, all);
+    else if (ws.ntp == 208) hipLaunchKernelGGL((k_heev_tri_vecs<4, 13>), dim3(ws.S), dim3(256), 0, st, ws, all);
+    else if (ws.ntp <= 32) hipLaunchKernelGGL((k_heev_tri_vecs<1, 2>), dim3(ws.S), dim3(128), 0, st, ws, all);
     else if (ws.ntp <= 64) hipLaunchKernelGGL((k_heev_tri_vecs<1, 4>), dim3(ws.S), dim3(256), 0, st, ws, all);
     else if (ws.ntp == 96) hipLaunchKernelGGL((k_heev_tri_vecs<2, 6>), dim3(ws.S), dim3(256), 0, st, ws, all);
     else hipLaunchKernelGGL((k_heev_tri_vecs<2, 8>), dim3(ws.S), dim3(256), 0, st, ws, all);
+    launch_jacobi(ws, max_sweeps, nt_max, FLAG_EVD_FALLBACK, st);
     return hipGetLastError();
 }
 

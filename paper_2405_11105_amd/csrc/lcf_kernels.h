@@ -16,7 +16,7 @@ int gram_tiles(int ntp, bool defl);
 hipError_t launch_tissue(const Workspace& ws, double rho, int iters, hipStream_t st);
 hipError_t launch_assemble(const Workspace& ws, int keep_r, hipStream_t st);
 hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int method, hipStream_t st);
-hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, hipStream_t st);
+hipError_t launch_evd_vectors(const Workspace& ws, int method, int all, int max_sweeps, int nt_max, hipStream_t st);
 hipError_t launch_heevd(int n, int nt, const double2* a, double* w, double2* v, int* sweeps,
                         double2* work, int max_sweeps, int* flags, hipStream_t st);
 hipError_t launch_rules(const Workspace& ws, const RuleParams& rp, hipStream_t st);

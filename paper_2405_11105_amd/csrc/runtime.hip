@@ -652,7 +652,7 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     const bool ncc = thr->cut == LCF_CUT_NCC;
     if (ncc) {
         // method 4 reads every eigenvector before the cut is known
-        { STAGE(c, LCF_STAGE_EVD_VECTORS, st); HIPCHK(launch_evd_vectors(ws, evd, 1, st)); }
+        { STAGE(c, LCF_STAGE_EVD_VECTORS, st); HIPCHK(launch_evd_vectors(ws, evd, 1, c->max_sweeps, nt_max, st)); }
         { STAGE(c, LCF_STAGE_NCC, st); HIPCHK(launch_ncc(ws, st)); }
     }
     { STAGE(c, LCF_STAGE_RULES, st); HIPCHK(launch_rules(ws, rp, st)); }
@@ -674,7 +674,7 @@ lcf_status run_stages2(lcf_context* c, const Workspace& ws, const lcf_threshold*
     }
     if (!ncc) {
         STAGE(c, LCF_STAGE_EVD_VECTORS, st);
-        HIPCHK(launch_evd_vectors(ws, evd, all_vectors, st));
+        HIPCHK(launch_evd_vectors(ws, evd, all_vectors, c->max_sweeps, nt_max, st));
     }
     { STAGE(c, LCF_STAGE_PROJECTOR, st); HIPCHK(launch_projector(ws, prec, st)); }
     return LCF_OK;

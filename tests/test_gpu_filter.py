@@ -418,14 +418,32 @@ def test_evd_tridiagonal_matches_jacobi(lcf, ctx, nt):
 @pytest.mark.parametrize("nt", [32, 150])
 def test_evd_rank_deficient_falls_back_to_jacobi(lcf, ctx, nt):
     """Boxes of at most 30 pixels and 32 (150) frames: every subset covariance is
-    singular with a repeated zero eigenvalue, so the tridiagonal solver (the
-    register one, the global-memory one) hands it to Jacobi."""
+    singular with a repeated zero eigenvalue, and the slow sigmoid (beta 0.5 from
+    k = 3) gives those components weights other than 1, so the projector needs
+    their vectors: the tridiagonal solver (the register one, the global-memory
+    one) hands the subset to Jacobi."""
     _say(f"[rank-deficient subsets nt={nt}]")
     spec = synth.PacketSpec(6, 5, nt, 30.0, 0.3, ((3, 1, 0.5),), seed=21)
     iq, mask = synth.make_packet(spec)
-    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=3)
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, shape=lcf.SHAPE_SIGMOID, k_fixed=3, beta_sigmoid=0.5)
     io, pd, d = _run(lcf, ctx, iq, 2, 2, thr)
     assert np.all(d["flags"] & lcf.FLAG_EVD_JACOBI)
+    res = O.filter_packet(iq, 2, 2, _oracle_thr(thr))
+    e = rel_fro(io, res["iq_out"])
+    _say(f"   rel_fro={e:.2e}")
+    assert e <= 1e-5
+
+
+def test_evd_near_degenerate_noise_needs_no_fallback(lcf, ctx):
+    """The same singular subsets with the hard cut at k = 3: the repeated zero
+    eigenvalues get weight 1, their vectors never enter the projector, so no
+    subset takes the Jacobi path and the output still matches the oracle."""
+    _say("[rank-deficient subsets, hard cut]")
+    spec = synth.PacketSpec(6, 5, 32, 30.0, 0.3, ((3, 1, 0.5),), seed=21)
+    iq, mask = synth.make_packet(spec)
+    thr = lcf.Threshold(cut=lcf.CUT_FIXED_K, k_fixed=3)
+    io, pd, d = _run(lcf, ctx, iq, 2, 2, thr)
+    assert not np.any(d["flags"] & lcf.FLAG_EVD_JACOBI)
     res = O.filter_packet(iq, 2, 2, _oracle_thr(thr))
     e = rel_fro(io, res["iq_out"])
     _say(f"   rel_fro={e:.2e}")
