@@ -1073,11 +1073,17 @@ __global__ void __launch_bounds__((RpPcCfg<NTP, PREC, TR>::NTHR)) k_reproj_pc(Wo
 // so that two MFMAs give Re(yh Mh + yl Mh + yh Ml) and two the imaginary part:
 // the three products of the split for all r <= 8 tissue columns at once.
 
-template <int NTP, int TR>
+// NWV = 4 runs four waves per tile (each with twice the output columns) in
+// under 80 KB of LDS, so that two work-groups share a CU and the matrix cores
+// of one overlap the FP64 / VALU phases of the other; NWV = 0 takes RpCfg's.
+template <int NTP, int TR, int NWV = 0>
 struct RpSbCfg {
     using R = RpCfg<NTP, 1, TR>;
-    static constexpr int TP = R::TP, NRT = R::NRT;
-    static constexpr int NW = R::NW, NTHR = R::NTHR, CTW = R::CTW, NNT = R::NNT;
+    static constexpr int TP = R::TP, NRT = R::NRT, NNT = R::NNT;
+    static constexpr int NW = NWV > 0 ? NWV : R::NW, NTHR = 64 * NW;
+    static constexpr int CTW = 2 * ((NNT + NW - 1) / NW);
+    static constexpr int VB = NWV == 4 ? 1 : 2;               // V_r buffers (one keeps LDS under 80 KB)
+    static constexpr int WPE = NWV == 4 ? 2 : 1;              // work-groups asked per CU
     static constexpr int KC = SbLayout<NTP>::KC, KB = SbLayout<NTP>::KB;
     static constexpr int LDK = KB + KC + 8;                   // A row: re part + M block | im part
     static constexpr int NKS = KC / 32;                       // full complex K steps
@@ -1090,20 +1096,22 @@ struct RpSbCfg {
     static constexpr int YLD = 2 * RMAX + 1;                  // y row stride (floats), odd
     // the [P; M] fragments of the next K step are requested before the MFMAs of
     // the current one where the registers allow it (else they would spill)
-    static constexpr bool PREF = NTP == 128 && TR == 4;
+    static constexpr bool PREF = NTP == 128 && TR == 4 && NWV == 0;
 };
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <int NTP, int TR>
-__global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspace ws) {
-    using C = RpSbCfg<NTP, TR>;
+template <int NTP, int TR, int NWV = 0>
+__global__ void __launch_bounds__((RpSbCfg<NTP, TR, NWV>::NTHR), (RpSbCfg<NTP, TR, NWV>::WPE * RpSbCfg<NTP, TR, NWV>::NTHR / 256))
+k_reproj_sb(Workspace ws) {
+    using C = RpSbCfg<NTP, TR, NWV>;
+    constexpr int VB = C::VB;
     constexpr int LDK = C::LDK, NTHR = C::NTHR, CTW = C::CTW, QW = C::QW, KC = C::KC, KB = C::KB;
     constexpr int TP = C::TP, NRT = C::NRT, NW = C::NW, MKS = C::MKS, VPT = C::VPT, LDV = C::LDV, YLD = C::YLD;
     static_assert(QW >= 1 && CTW == 2 * QW, "re and im output tiles in pairs");
     static_assert(RMAX == 8, "the packed M block holds 8 tissue columns");
     __shared__ __attribute__((aligned(16))) uint16_t abuf[2 * TP * LDK];
-    __shared__ double2 vrs[2][RMAX * LDV];      // V_r, [j][t], double-buffered over subsets
+    __shared__ double2 vrs[VB][RMAX * LDV];     // V_r, [j][t], double-buffered over subsets (VB = 2)
     __shared__ float ypart[NW * TP * 16];       // score partials [wave][pixel][column]
     __shared__ float ysh[TP * YLD];             // y, [pixel][re, im of column j]
     __shared__ float wd[TP], aw2[TP];           // w and alpha w^2 of the current subset
@@ -1159,7 +1167,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
         for (int i = 0; i < VPT; ++i) {
             const int e = tid + NTHR * i;
             const int j = e % RMAX, t = e / RMAX;
-            if (e < NTP * RMAX) vrs[b][j * LDV + t] = (j < r && t < nt) ? vnext[i] : make_double2(0.0, 0.0);
+            if (e < NTP * RMAX) vrs[VB == 2 ? b : 0][j * LDV + t] = (j < r && t < nt) ? vnext[i] : make_double2(0.0, 0.0);
         }
     };
     // Subset data is requested ahead of use so that no chain of dependent global
@@ -1199,7 +1207,7 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
     for (int i = 0; i < NRT * 4; ++i) pd_acc[i] = 0.f;
 
     for (int ci = 0; ci < ncov; ++ci) {
-        const int b = ci & 1;
+        const int b = VB == 2 ? (ci & 1) : 0;       // V_r buffer of this subset
         const SubNext cur = nxt;
         const int s = cur.s, r = cur.r;
         const uint16_t* planes = reinterpret_cast<const uint16_t*>(ws.breal + (long)s * (2 * (NTP + REXT)) * (2 * NTP));
@@ -1353,9 +1361,10 @@ __global__ void __launch_bounds__((RpSbCfg<NTP, TR>::NTHR)) k_reproj_sb(Workspac
         }
         __syncthreads();
         // the next subset's V_r goes to the other buffer (last read by the
-        // previous subset, which every wave has finished)
+        // previous subset), or with one buffer over this one (its B and D are
+        // done; the next B starts after the loop's first barrier)
         if (ci + 1 < ncov) {
-            vstore(b ^ 1, nxt.r);
+            vstore(VB == 2 ? (b ^ 1) : 0, nxt.r);
             if (ci + 2 < ncov) vload(s_ahead2);
         }
         s_ahead = s_ahead2;
@@ -1532,6 +1541,8 @@ static void post_dispatch(const Workspace& ws, int stage, int prec, hipStream_t 
         }
         if (prec == 0)
             hipLaunchKernelGGL((k_reproj<NTP, 0, 2>), dim3(grid), dim3(RpCfg<NTP, 0, 2>::NTHR), 0, st, ws);
+        else if constexpr (NTP == 128)
+            hipLaunchKernelGGL((k_reproj_sb<NTP, 2, 4>), dim3(grid), dim3(RpSbCfg<NTP, 2, 4>::NTHR), 0, st, ws);
         else
             hipLaunchKernelGGL((k_reproj_sb<NTP, 2>), dim3(grid), dim3(RpSbCfg<NTP, 2>::NTHR), 0, st, ws);
     }
