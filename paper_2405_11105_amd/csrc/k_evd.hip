@@ -1,6 +1,8 @@
 // FP64 small-matrix stages of each subset: window tables (Eq. 11), the tissue
 // basis used to deflate the covariance, the deflated-basis assembly of R, and
 // the batched Hermitian eigen-decomposition (Eq. 2) by one-sided Jacobi.
+#include <type_traits>
+
 #include "lcf_internal.h"
 #include "lcf_kernels.h"
 
@@ -648,8 +650,8 @@ __device__ __forceinline__ double swap_sum(double a, double b) {
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
 
@@ -922,9 +924,10 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
 //     with the two-sided update A <- A - v q^H - q v^H (p = tau A v,
 //     q = p - (tau / 2)(v^H p) v); the vectors go to scratch.
 //  2. T = D T_r D^H with a diagonal unitary D makes the off-diagonal real >= 0.
-//     (Steps 1 and 2: k_heev_tri_reduce up to 128 frames, the matrix in VGPRs as
-//     in k_jacobi_reg: wave w holds columns 16 w .. 16 w + 15, lane l rows
-//     l + 64 i; k_heev_big_reduce above, the matrix in global memory.)
+//     (Steps 1 and 2: k_heev_tri_reduce up to 128 frames, the matrix in VGPRs,
+//     columns dealt to the waves cyclically (slot k of wave w holds column
+//     NW k + w, lane l rows l + 64 i); k_heev_big_reduce below, the matrix in
+//     global memory.)
 //  3. Eigenvalues of T_r by multisection of Sturm counts (4 lanes per
 //     eigenvalue, 5 sub-intervals per round), sorted descending by construction
 //     (k_heev_sturm, for both).
@@ -944,19 +947,28 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
 // Gershgorin interval.
 constexpr int FLAG_EVD_FALLBACK = 16;
 
+// Sum of a double over the 64 lanes, every lane getting the same bits: lane
+// moves within rows of 16 (DPP), then the row-swap instructions.
+__device__ __forceinline__ double wave_sum_x(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    v = swap_sum<16>(v, v);
+    return swap_sum<32>(v, v);
+}
+
 template <int RPL, int NW>
 __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
     constexpr int N = 16 * NW;             // padded size held (columns)
-    constexpr int NTHR = 64 * NW;
     static_assert(64 * RPL >= N, "rows per lane cover the padded size");
-    __shared__ double2 vshb[2][N];         // Householder vector v_j, by the parity of j
-    __shared__ double2 psh[NW * N];        // per-wave partials of A v
-    __shared__ double2 qsh[N];             // q at the columns of each wave (written by that wave)
+    __shared__ double2 psh[2][NW][N];      // per-wave partials of A v, by the parity of the step
+    __shared__ double2 colb[2][N];         // the column the next reflector comes from, by parity
+    __shared__ double2 vqw[NW][2][16];     // each wave's copy of v and q at its own columns
     __shared__ double red[2];
     __shared__ double dsh[N], esh[N], e2sh[N];
     __shared__ double2 phs[N];             // complex e_j, then D
     __shared__ double bnd[2];
-    __shared__ double tau_sh[2];
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nt = ws.sub[s].nt;
@@ -964,169 +976,258 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
     double2* H = ws.wvec + (long)s * N * N;                 // Householder vectors, tau in element 0
     double* trid = reinterpret_cast<double*>(ws.pmat + (long)s * N * N) + N * N;   // tridiagonal form
 
+    // slot k: column NW k + wave, so that every wave keeps columns to update
+    // until the last steps
     double2 A[16][RPL];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int col = 16 * wave + c;
+    for (int k = 0; k < 16; ++k) {
+        const int col = NW * k + wave;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
-            A[c][i] = (row < nt && col < nt) ? cconj(Bm[(long)col * N + row]) : make_double2(0.0, 0.0);
+            A[k][i] = (row < nt && col < nt) ? cconj(Bm[(long)col * N + row]) : make_double2(0.0, 0.0);
         }
     }
 
-    // ---- 1. Householder reduction, two barriers per column. Each active wave
-    // sums the partials of A v for every row itself, and the wave holding column
-    // j + 1 applies step j to that column first and forms v_{j+1} while the other
-    // waves are still applying step j.
-    // The reflector of column jj (rows jj + 1 ..), formed by the wave holding it.
-    auto form = [&](int jj) {
-        const int jc = jj & 15;
-        double2* vsh = vshb[jj & 1];
-        double2 x[RPL];
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            x[i] = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (c == jc) x[i] = A[c][i];
-        }
+    // ---- 1. Householder reduction, one barrier per column: every wave forms
+    // the next reflector itself from the column its owner published a step
+    // earlier (updating it by the current step first), so no wave waits for
+    // another one's reflector.
+    // The reflector of column jj (rows jj + 1 ..) from x, that column of the
+    // current matrix at this lane's rows; the same bits in every wave.
+    auto form = [&](int jj, const double2 (&x)[RPL], double2 (&v)[RPL]) __attribute__((always_inline)) -> double {
         double s2 = 0.0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
             if (row > jj + 1 && row < nt) s2 += cabs2(x[i]);
         }
-        s2 = wave_sum(s2);
-        double2 t1 = x[0], t0 = x[0];
+        s2 = wave_sum_x(s2);
+        double2 t1 = x[0];
+        double t0 = x[0].x;
 #pragma unroll
         for (int i = 1; i < RPL; ++i) {
             if (i == ((jj + 1) >> 6)) t1 = x[i];
-            if (i == (jj >> 6)) t0 = x[i];
+            if (i == (jj >> 6)) t0 = x[i].x;
         }
         const double2 x0 = make_double2(rdl(t1.x, (jj + 1) & 63), rdl(t1.y, (jj + 1) & 63));
-        const double xjj = rdl(t0.x, jj & 63);
-        const double ax0 = sqrt(cabs2(x0));
-        const double alpha = sqrt(s2 + ax0 * ax0);
-        const double2 ph = ax0 > 0.0 ? cscale(x0, 1.0 / ax0) : make_double2(1.0, 0.0);
-        const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
+        const double xjj = rdl(t0, jj & 63);
+        // (a subnormal |x0|^2 or alpha (alpha + |x0|) counts as zero: the
+        // hardware reciprocal estimates take normal numbers)
+        constexpr double tiny = 2.2250738585072014e-308;
+        const double n0 = cabs2(x0);
+        const double r0 = n0 >= tiny ? rsq_nr(n0) : 0.0;
+        const double ax0 = n0 * r0;
+        const double alpha = sqrt(s2 + n0);
+        const double2 ph = n0 >= tiny ? cscale(x0, r0) : make_double2(1.0, 0.0);
+        const double den = alpha * (alpha + ax0);
+        const double tau = den >= tiny ? rcp_nr(den) : 0.0;
+        const bool rec = wave == jj % NW;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
-            if (row < N) {
-                const double2 v = row <= jj ? make_double2(0.0, 0.0)
-                                            : (row == jj + 1 ? cadd(x0, cscale(ph, alpha)) : x[i]);
-                vsh[row] = v;
-                H[(long)jj * N + row] = row == 0 ? make_double2(tau, 0.0) : v;   // row 0 of v_j is zero: holds tau
-            }
+            v[i] = row <= jj ? make_double2(0.0, 0.0) : (row == jj + 1 ? cadd(x0, cscale(ph, alpha)) : x[i]);
+            if (rec && row < N) H[(long)jj * N + row] = row == 0 ? make_double2(tau, 0.0) : v[i];   // row 0 of v_j is zero: holds tau
         }
-        if (lane == 0) {
+        if (rec && lane == 0) {
             dsh[jj] = xjj;
             phs[jj] = cscale(ph, -alpha);                           // complex e_j for now
-            tau_sh[jj & 1] = tau;
         }
+        return tau;
     };
-    if (nt > 2 && wave == 0) form(0);
-    __syncthreads();
-    for (int j = 0; j + 2 < nt; ++j) {
-        const double2* vsh = vshb[j & 1];
-        const double tau = tau_sh[j & 1];
-        const int wstart = (j + 1) >> 4;          // waves below hold only finished columns
-        // partial A v over this wave's columns (row blocks i with 64 i + 63 <= j
-        // hold only finished rows, where v and A v vanish)
-        const int ilo = (j + 1) >> 6;
-        if (wave >= wstart) {
+    // this lane's values of a vector at the wave's own columns into vqw[wave][h]
+    auto own_cols = [&](const double2 (&u)[RPL], int h) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row < N && row % NW == wave) vqw[wave][h][row / NW] = u[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // (A is only ever indexed by compile-time constants, outside any lambda, so
+    // that it stays in registers)
+
+    double2 vr[RPL];                        // v_j at this lane's rows
+    double tau = 0.0;
+    if (nt > 2) {
+        // columns 0 and 1: slot 0 of waves 0 and 1
+        if (wave < 2) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                if (row < N) colb[wave ^ 1][row] = A[0][i];
+            }
+        }
+        __syncthreads();
+        double2 x[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int row = lane + 64 * i;
+            x[i] = row < N ? colb[1][row] : make_double2(0.0, 0.0);
+        }
+        tau = form(0, x, vr);
+    }
+    // Two passes over the steps: in the second (j >= 63, two row blocks) the
+    // first row block holds only finished rows, where v and q vanish, so it is
+    // left as it is (rows i < ILO).
+    int j = 0;
+#pragma unroll
+    for (int ILO = 0; ILO < RPL; ++ILO) {
+        const int jend = ILO + 1 < RPL ? 63 : 1 << 30;
+        for (; j + 2 < nt && j < jend; ++j) {
+            const int par = j & 1;
+            // slots k >= kf hold the columns > j (v vanishes at columns <= j,
+            // which are finished: a group of 4 slots with one of them active is
+            // updated whole, which changes only finished columns that no step
+            // reads again)
+            const int kf = j < wave ? 0 : (j - wave) / NW + 1;
+            own_cols(vr, 0);
+            // partial A v over this wave's columns (slots in groups of 4 from the
+            // group of slot kf: v is zero at the finished columns among them)
             double2 acc[RPL];
 #pragma unroll
             for (int i = 0; i < RPL; ++i) acc[i] = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const double2 vc = vsh[16 * wave + c];
+            for (int g = 0; g < 4; ++g) {
+                if (4 * g + 3 >= kf) {
+                    double2 vc[4];
 #pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    if (i < ilo) continue;
-                    acc[i].x = fma(A[c][i].x, vc.x, fma(-A[c][i].y, vc.y, acc[i].x));
-                    acc[i].y = fma(A[c][i].x, vc.y, fma(A[c][i].y, vc.x, acc[i].y));
+                    for (int u = 0; u < 4; ++u) vc[u] = vqw[wave][0][4 * g + u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int i = ILO; i < RPL; ++i) {
+                            const double2 a = A[4 * g + u][i];
+                            acc[i].x = fma(a.x, vc[u].x, fma(-a.y, vc[u].y, acc[i].x));
+                            acc[i].y = fma(a.x, vc[u].y, fma(a.y, vc[u].x, acc[i].y));
+                        }
                 }
             }
+            // (rows <= j are finished: p and q there reach only other finished
+            // rows, so neither is formed)
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
+            for (int i = ILO; i < RPL; ++i) {
                 const int row = lane + 64 * i;
-                if (row < N) psh[wave * N + row] = acc[i];
+                if (row > j && row < N) psh[par][wave][row] = acc[i];
             }
-        }
-        __syncthreads();
-        // p = tau A v for this lane's rows, q = p - (tau / 2) (v^H p) v, then
-        // A -= v q^H + q v^H on this wave's columns
-        if (wave >= wstart) {
-            double2 vr[RPL], qr[RPL];
+            __syncthreads();
+            // p = tau A v for this lane's rows, q = p - (tau / 2) (v^H p) v
+            double2 qr[RPL];
             double kr = 0.0, ki = 0.0;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int row = lane + 64 * i;
                 double2 p = make_double2(0.0, 0.0);
-                if (row < N && i >= ilo)
-                    for (int w = wstart; w < NW; ++w) p = cadd(p, psh[w * N + row]);
+                if (i >= ILO && row > j && row < N) {
+                    double2 pw[NW];
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) pw[w] = psh[par][w][row];
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) p = cadd(p, pw[w]);
+                }
                 qr[i] = cscale(p, tau);
-                vr[i] = row < N ? vsh[row] : make_double2(0.0, 0.0);
                 kr = fma(vr[i].x, qr[i].x, fma(vr[i].y, qr[i].y, kr));       // conj(v) p
                 ki = fma(vr[i].x, qr[i].y, fma(-vr[i].y, qr[i].x, ki));
             }
-            kr = wave_sum(kr);
-            ki = wave_sum(ki);
+            {
+                // both sums at once: lanes below 32 end with the sum of kr, the others with ki's
+                double t = swap_sum<32>(kr, ki);
+                t += dpp_d<0xB1>(t);
+                t += dpp_d<0x4E>(t);
+                t += dpp_d<0x141>(t);
+                t += dpp_d<0x140>(t);
+                t = swap_sum<16>(t, t);
+                kr = rdl(t, 0);
+                ki = rdl(t, 32);
+            }
             const double2 K = make_double2(0.5 * tau * kr, 0.5 * tau * ki);
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                qr[i] = csub(qr[i], cmul(K, vr[i]));
-                // q at this wave's columns, for the column factors below (each wave
-                // writes and reads only its own 16 rows of qsh)
-                const int row = lane + 64 * i;
-                if (row >= 16 * wave && row < 16 * wave + 16) qsh[row] = qr[i];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            auto update = [&](int c) {
-                const int col = 16 * wave + c;
-                const double2 vc = vsh[col];
-                const double2 qc = qsh[col];
+            for (int i = 0; i < RPL; ++i) qr[i] = csub(qr[i], cmul(K, vr[i]));
+            own_cols(qr, 1);
+            // the next reflector, from column j + 1 after this step's update
+            double2 vn[RPL];
+            double taun = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) vn[i] = make_double2(0.0, 0.0);
+            if (j + 3 < nt) {
+                const int r = j + 1;
+                double2 qs = qr[0], vs = vr[0];
+#pragma unroll
+                for (int i = 1; i < RPL; ++i)
+                    if (i == (r >> 6)) { qs = qr[i]; vs = vr[i]; }
+                const double2 qc = make_double2(rdl(qs.x, r & 63), rdl(qs.y, r & 63));
+                const double2 vc = make_double2(rdl(vs.x, r & 63), rdl(vs.y, r & 63));
+                double2 x[RPL];
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
-                    if (i < ilo) continue;              // finished rows keep their values
-                    double ax = A[c][i].x, ay = A[c][i].y;
+                    const int row = lane + 64 * i;
+                    const double2 a = row < N ? colb[par][row] : make_double2(0.0, 0.0);
+                    double ax = a.x, ay = a.y;
                     ax = fma(-vr[i].x, qc.x, fma(-vr[i].y, qc.y, ax));
                     ay = fma(-vr[i].y, qc.x, fma(vr[i].x, qc.y, ay));
                     ax = fma(-qr[i].x, vc.x, fma(-qr[i].y, vc.y, ax));
                     ay = fma(-qr[i].y, vc.x, fma(qr[i].x, vc.y, ay));
-                    A[c][i] = make_double2(ax, ay);
+                    x[i] = make_double2(ax, ay);
                 }
-            };
-            const bool own = j + 3 < nt && wave == ((j + 1) >> 4);
-            const int jcn = (j + 1) & 15;
-            if (own) {
+                taun = form(r, x, vn);
+            }
+            // A -= v q^H + q v^H on this wave's columns
 #pragma unroll
-                for (int c = 0; c < 16; ++c)
-                    if (c == jcn) update(c);
-                form(j + 1);
+            for (int g = 0; g < 4; ++g) {
+                if (4 * g + 3 >= kf) {
+                    double2 vc[4], qc[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        vc[u] = vqw[wave][0][4 * g + u];
+                        qc[u] = vqw[wave][1][4 * g + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int i = ILO; i < RPL; ++i) {
+                            const int k = 4 * g + u;
+                            double ax = A[k][i].x, ay = A[k][i].y;
+                            ax = fma(-vr[i].x, qc[u].x, fma(-vr[i].y, qc[u].y, ax));
+                            ay = fma(-vr[i].y, qc[u].x, fma(vr[i].x, qc[u].y, ay));
+                            ax = fma(-qr[i].x, vc[u].x, fma(-qr[i].y, vc[u].y, ax));
+                            ay = fma(-qr[i].y, vc[u].x, fma(qr[i].x, vc[u].y, ay));
+                            A[k][i] = make_double2(ax, ay);
+                        }
+                }
+            }
+            // column j + 2 as this step leaves it, for the reflector after next
+            // (held by wave (j + 2) % NW in slot (j + 2) / NW)
+            if (j + 4 < nt && wave == (j + 2) % NW) {
+                const int ks = (j + 2) / NW;
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if (k == ks) {
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) {
+                            const int row = lane + 64 * i;
+                            if (row < N) colb[par ^ 1][row] = A[k][i];
+                        }
+                    }
             }
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (!(own && c == jcn)) update(c);
+            for (int i = 0; i < RPL; ++i) vr[i] = vn[i];
+            tau = taun;
         }
-        __syncthreads();
     }
     // last 2 x 2 block: d_{nt-2}, d_{nt-1}, e_{nt-2}
     {
         const int r0 = nt - 2, r1 = nt - 1;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const int col = 16 * wave + c;
+        for (int k = 0; k < 16; ++k) {
+            const int col = NW * k + wave;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int row = lane + 64 * i;
-                if (row == r0 && col == r0) dsh[r0] = A[c][i].x;
-                if (row == r1 && col == r1) dsh[r1] = A[c][i].x;
-                if (row == r1 && col == r0) phs[r0] = A[c][i];
+                if (row == r0 && col == r0) dsh[r0] = A[k][i].x;
+                if (row == r1 && col == r1) dsh[r1] = A[k][i].x;
+                if (row == r1 && col == r0) phs[r0] = A[k][i];
             }
         }
     }
