@@ -995,7 +995,10 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
     // another one's reflector.
     // The reflector of column jj (rows jj + 1 ..) from x, that column of the
     // current matrix at this lane's rows; the same bits in every wave.
-    auto form = [&](int jj, const double2 (&x)[RPL], double2 (&v)[RPL]) __attribute__((always_inline)) -> double {
+    // (straight-line code, so that it can interleave with the update; `record`
+    // stores what it found)
+    auto form = [&](int jj, const double2 (&x)[RPL], double2 (&v)[RPL], double& xjj, double2& ej)
+                    __attribute__((always_inline)) -> double {
         double s2 = 0.0;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
@@ -1011,7 +1014,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
             if (i == (jj >> 6)) t0 = x[i].x;
         }
         const double2 x0 = make_double2(rdl(t1.x, (jj + 1) & 63), rdl(t1.y, (jj + 1) & 63));
-        const double xjj = rdl(t0, jj & 63);
+        xjj = rdl(t0, jj & 63);
         // (a subnormal |x0|^2 or alpha (alpha + |x0|) counts as zero: the
         // hardware reciprocal estimates take normal numbers)
         constexpr double tiny = 2.2250738585072014e-308;
@@ -1022,18 +1025,28 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
         const double2 ph = n0 >= tiny ? cscale(x0, r0) : make_double2(1.0, 0.0);
         const double den = alpha * (alpha + ax0);
         const double tau = den >= tiny ? rcp_nr(den) : 0.0;
-        const bool rec = wave == jj % NW;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int row = lane + 64 * i;
             v[i] = row <= jj ? make_double2(0.0, 0.0) : (row == jj + 1 ? cadd(x0, cscale(ph, alpha)) : x[i]);
-            if (rec && row < N) H[(long)jj * N + row] = row == 0 ? make_double2(tau, 0.0) : v[i];   // row 0 of v_j is zero: holds tau
         }
-        if (rec && lane == 0) {
-            dsh[jj] = xjj;
-            phs[jj] = cscale(ph, -alpha);                           // complex e_j for now
-        }
+        ej = cscale(ph, -alpha);                                    // complex e_jj for now
         return tau;
+    };
+    // reflector jj to scratch (one wave), d_jj and e_jj to LDS
+    auto record = [&](int jj, const double2 (&v)[RPL], double tau, double xjj, double2 ej)
+                      __attribute__((always_inline)) {
+        if (wave == jj % NW) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int row = lane + 64 * i;
+                if (row < N) H[(long)jj * N + row] = row == 0 ? make_double2(tau, 0.0) : v[i];   // row 0 of v_j is zero: holds tau
+            }
+            if (lane == 0) {
+                dsh[jj] = xjj;
+                phs[jj] = ej;
+            }
+        }
     };
     // this lane's values of a vector at the wave's own columns into vqw[wave][h]
     auto own_cols = [&](const double2 (&u)[RPL], int h) __attribute__((always_inline)) {
@@ -1067,7 +1080,10 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
             const int row = lane + 64 * i;
             x[i] = row < N ? colb[1][row] : make_double2(0.0, 0.0);
         }
-        tau = form(0, x, vr);
+        double xjj;
+        double2 ej;
+        tau = form(0, x, vr, xjj, ej);
+        record(0, vr, tau, xjj, ej);
     }
     // Two passes over the steps: in the second (j >= 63, two row blocks) the
     // first row block holds only finished rows, where v and q vanish, so it is
@@ -1148,7 +1164,8 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
             own_cols(qr, 1);
             // the next reflector, from column j + 1 after this step's update
             double2 vn[RPL];
-            double taun = 0.0;
+            double taun = 0.0, xn = 0.0;
+            double2 en = make_double2(0.0, 0.0);
 #pragma unroll
             for (int i = 0; i < RPL; ++i) vn[i] = make_double2(0.0, 0.0);
             if (j + 3 < nt) {
@@ -1171,7 +1188,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
                     ay = fma(-qr[i].y, vc.x, fma(qr[i].x, vc.y, ay));
                     x[i] = make_double2(ax, ay);
                 }
-                taun = form(r, x, vn);
+                taun = form(r, x, vn, xn, en);
             }
             // A -= v q^H + q v^H on this wave's columns
 #pragma unroll
@@ -1197,6 +1214,7 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
                         }
                 }
             }
+            if (j + 3 < nt) record(j + 1, vn, taun, xn, en);
             // column j + 2 as this step leaves it, for the reflector after next
             // (held by wave (j + 2) % NW in slot (j + 2) / NW)
             if (j + 4 < nt && wave == (j + 2) % NW) {
@@ -1407,6 +1425,7 @@ __global__ void __launch_bounds__(64 * (NW < 4 ? NW : 4)) k_heev_tri_vecs(Worksp
     __shared__ int act[N];
     __shared__ int wcnt[NWV];
     __shared__ int cluster;
+    __shared__ double2 wsh[NWV][16];       // per wave: v^H y of its 16 columns
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (tid == 0) cluster = 0;
@@ -1567,9 +1586,15 @@ __global__ void __launch_bounds__(64 * (NW < 4 ? NW : 4)) k_heev_tri_vecs(Worksp
         }
         double tot = (h2 ? w2[1] : w2[0]) + dpp_d<0x4E>(h2 ? w2[0] : w2[1]);
         tot += dpp_d<0xB1>(tot);
+        // Re w_c in lane 4 c, Im w_c in lane 4 c + 2: through LDS to every lane
+        if ((lane & 1) == 0) reinterpret_cast<double*>(wsh[wave])[lane >> 1] = tot;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            const double twx = tauj * rdl(tot, 4 * c), twy = tauj * rdl(tot, 4 * c + 2);
+            const double2 wc = wsh[wave][c];
+            const double twx = tauj * wc.x, twy = tauj * wc.y;
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {                            // y -= v (tau w)
                 const double ax = fma(-vr[i].x, twx, fma(vr[i].y, twy, A[c][i].x));
