@@ -81,7 +81,7 @@ __device__ void wave_heev8(double2& h, double2& z, int lane) {
     z = make_double2(i == j ? 1.0 : 0.0, 0.0);
     for (int sweep = 0; sweep < 40; ++sweep) {
         const double a = cabs2(h);
-        const double tot = wave_sum(a), off = wave_sum(i != j ? a : 0.0);
+        const double tot = wave_sum_x(a), off = wave_sum_x(i != j ? a : 0.0);
         if (off <= 1e-30 * tot || off == 0.0) break;
         for (int k = 0; k < 7; ++k) {
             const int pj = circle_partner(j, k), pi = circle_partner(i, k);
@@ -172,14 +172,14 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
                             dr = fma(x[i][q].x, x[i][j].x, fma(x[i][q].y, x[i][j].y, dr));
                             di = fma(x[i][q].x, x[i][j].y, fma(-x[i][q].y, x[i][j].x, di));
                         }
-                        const double2 dot = make_double2(wave_sum(dr), wave_sum(di));
+                        const double2 dot = make_double2(wave_sum_x(dr), wave_sum_x(di));
 #pragma unroll
                         for (int i = 0; i < XR; ++i) x[i][j] = csub(x[i][j], cmul(dot, x[i][q]));
                     }
                     double n2 = 0.0;
 #pragma unroll
                     for (int i = 0; i < XR; ++i) n2 += cabs2(x[i][j]);
-                    const double nrm = sqrt(wave_sum(n2));
+                    const double nrm = sqrt(wave_sum_x(n2));
                     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
 #pragma unroll
                     for (int i = 0; i < XR; ++i) x[i][j] = cscale(x[i][j], inv);
@@ -212,8 +212,8 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
             }
 #pragma unroll
             for (int j = 0; j < RMAX; ++j) {
-                acc[j].x += __shfl_xor(acc[j].x, 1, 64);
-                acc[j].y += __shfl_xor(acc[j].y, 1, 64);
+                acc[j].x += dpp_d<0xB1>(acc[j].x);
+                acc[j].y += dpp_d<0xB1>(acc[j].y);
             }
             if (t < nt && half == 0) {
 #pragma unroll
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
     for (int j = 0; j < r; ++j) {
         double part = 0.0;
         for (int t = j + tid; t < nt; t += 256) part += cabs2(Y[t * RMAX + j]);
-        const double nx2 = block_sum(part, red);
+        const double nx2 = block_sum_x(part, red);
         const double nrm = sqrt(nx2);
         const double2 x0 = Y[j * RMAX + j];
         const double ax0 = sqrt(cabs2(x0));
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
         for (int c = j + 1; c < r; ++c) {
             double2 part2 = make_double2(0.0, 0.0);
             for (int t = j + tid; t < nt; t += 256) part2 = cadd(part2, cmulc(hv[(long)j * NTP + t], Y[t * RMAX + c]));
-            const double2 dot = block_sum2(part2, red);
+            const double2 dot = block_sum2_x(part2, red);
             for (int t = j + tid; t < nt; t += 256)
                 Y[t * RMAX + c] = csub(Y[t * RMAX + c], cscale(cmul(hv[(long)j * NTP + t], dot), tau));
             __syncthreads();
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
         for (int c = 0; c < r; ++c) {
             double2 part2 = make_double2(0.0, 0.0);
             for (int t = j + tid; t < nt; t += 256) part2 = cadd(part2, cmulc(hv[(long)j * NTP + t], X[t * RMAX + c]));
-            const double2 dot = block_sum2(part2, red);
+            const double2 dot = block_sum2_x(part2, red);
             for (int t = j + tid; t < nt; t += 256)
                 X[t * RMAX + c] = csub(X[t * RMAX + c], cscale(cmul(hv[(long)j * NTP + t], dot), tau));
             __syncthreads();
@@ -416,11 +416,15 @@ __global__ void __launch_bounds__(AsmCfg<NTP>::NTHR) k_assemble(Workspace ws, in
             double kpart = 0.0;
 #pragma unroll
             for (int a = 0; a < RA; ++a) {
-#pragma unroll
-                for (int m = 8; m >= 1; m >>= 1) {
-                    pa[a].x += __shfl_xor(pa[a].x, m, 16);
-                    pa[a].y += __shfl_xor(pa[a].y, m, 16);
-                }
+                // sum over the 16 lanes of the row (lane moves within it)
+                pa[a].x += dpp_d<0xB1>(pa[a].x);
+                pa[a].y += dpp_d<0xB1>(pa[a].y);
+                pa[a].x += dpp_d<0x4E>(pa[a].x);
+                pa[a].y += dpp_d<0x4E>(pa[a].y);
+                pa[a].x += dpp_d<0x141>(pa[a].x);
+                pa[a].y += dpp_d<0x141>(pa[a].y);
+                pa[a].x += dpp_d<0x140>(pa[a].x);
+                pa[a].y += dpp_d<0x140>(pa[a].y);
                 const int t = RA * ti + a;
                 if (ui == 0 && t < NTP) P[j & 1][t] = pa[a];
                 if (t < NTP) kpart += cmulc(v[t], pa[a]).x;
@@ -614,47 +618,6 @@ __device__ void jacobi_finish(const double2* G, int nt, int ld, double* lam_out,
 // half-blocks (half-block 0 stays in place). Each step handles 8 disjoint pairs:
 // lane partial sums, a transposed butterfly that leaves dot product (l >> 1) in
 // lane l, rotation parameters in lanes 0-7, broadcast by readlane.
-__device__ __forceinline__ double rdl(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
-}
-
-// Lane-swap sum of two wave-wide doubles: for M = 32 lanes below 32 return
-// a[l] + a[l + 32] and lanes above 32 return b[l - 32] + b[l]; for M = 16 the
-// same within each 32-lane half (rows of 16 lanes), a in even rows, b in odd.
-template <int M>
-__device__ __forceinline__ double swap_sum(double a, double b) {
-    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
-    const unsigned alo = (unsigned)(ab & 0xffffffff), ahi = (unsigned)(ab >> 32);
-    const unsigned blo = (unsigned)(bb & 0xffffffff), bhi = (unsigned)(bb >> 32);
-    unsigned x0, x1, y0, y1;
-    if constexpr (M == 32) {
-        const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
-        const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
-        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
-    } else {
-        const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
-        const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
-        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
-    }
-    const double p = __longlong_as_double((long long)(((unsigned long long)x1 << 32) | x0));
-    const double q = __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0));
-    return p + q;
-}
-
-// Data-parallel lane moves of a double within a row of 16 lanes (DPP):
-// 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = quad_perm [2,3,0,1] (lane ^ 2),
-// 0x141 = row_half_mirror (lane ^ 7), 0x140 = row_mirror (lane ^ 15).
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
-}
-
 // The lane-swap instructions on a double: returns the two swapped operands.
 template <int M>
 __device__ __forceinline__ void swap_d(double a, double b, double& x, double& y) {
@@ -946,17 +909,6 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
 // tridiagonal form: d, |e|, |e|^2, Re D, Im D (N each), then pivmin and the
 // Gershgorin interval.
 constexpr int FLAG_EVD_FALLBACK = 16;
-
-// Sum of a double over the 64 lanes, every lane getting the same bits: lane
-// moves within rows of 16 (DPP), then the row-swap instructions.
-__device__ __forceinline__ double wave_sum_x(double v) {
-    v += dpp_d<0xB1>(v);
-    v += dpp_d<0x4E>(v);
-    v += dpp_d<0x141>(v);
-    v += dpp_d<0x140>(v);
-    v = swap_sum<16>(v, v);
-    return swap_sum<32>(v, v);
-}
 
 template <int RPL, int NW>
 __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {

@@ -138,6 +138,84 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// A double read from one lane (two scalar reads).
+__device__ __forceinline__ double rdl(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Lane-swap sum of two wave-wide doubles: for M = 32 lanes below 32 return
+// a[l] + a[l + 32] and lanes above 32 return b[l - 32] + b[l]; for M = 16 the
+// same within each 32-lane half (rows of 16 lanes), a in even rows, b in odd.
+template <int M>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+    const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+    const unsigned alo = (unsigned)(ab & 0xffffffff), ahi = (unsigned)(ab >> 32);
+    const unsigned blo = (unsigned)(bb & 0xffffffff), bhi = (unsigned)(bb >> 32);
+    unsigned x0, x1, y0, y1;
+    if constexpr (M == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    }
+    const double p = __longlong_as_double((long long)(((unsigned long long)x1 << 32) | x0));
+    const double q = __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0));
+    return p + q;
+}
+
+// Data-parallel lane moves of a double within a row of 16 lanes (DPP):
+// 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = quad_perm [2,3,0,1] (lane ^ 2),
+// 0x141 = row_half_mirror (lane ^ 7), 0x140 = row_mirror (lane ^ 15).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Sum of a double over the 64 lanes, every lane getting the same bits: lane
+// moves within rows of 16 (DPP), then the row-swap instructions.
+__device__ __forceinline__ double wave_sum_x(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    v = swap_sum<16>(v, v);
+    return swap_sum<32>(v, v);
+}
+
+// block_sum / block_sum2 with the lane-move reduction inside each wave (every
+// thread of the block must take part).
+__device__ __forceinline__ double block_sum_x(double v, double* red) {
+    v = wave_sum_x(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+__device__ __forceinline__ double2 block_sum2_x(double2 v, double* red) {
+    v.x = wave_sum_x(v.x);
+    v.y = wave_sum_x(v.y);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { red[2 * w] = v.x; red[2 * w + 1] = v.y; }
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = 0; i < nw; ++i) { s.x += red[2 * i]; s.y += red[2 * i + 1]; }
+    return s;
+}
+
 // Block-wide sum of a double over blockDim.x threads (multiple of 64); red is
 // __shared__ scratch of at least blockDim.x/64 doubles. All threads get the sum.
 __device__ __forceinline__ double block_sum(double v, double* red) {

@@ -386,12 +386,15 @@ def test_graph_cache_keys_on_median_beta(lcf, ctx):
             gctx.close()
 
 
-@pytest.mark.parametrize("nt", [128, 80, 150, 200])
+@pytest.mark.parametrize("nt", [128, 80, 150, 200, 4, 33, 65, 66, 127])
 def test_evd_tridiagonal_matches_jacobi(lcf, ctx, nt):
     """The two subset eigen-solvers give the same filter (FP32 path); 80 frames
     run the 6-wave shapes of both (96-frame class); 150 and 200 frames run the
     global-memory Householder reduction (160 and 208 classes) against the
-    LDS / global Jacobi."""
+    LDS / global Jacobi. The register reduction's edges: 4 frames (two
+    reflectors, 2 waves), 33 (4 waves), 65 (the last step before the reduction
+    drops its first row block), 66 (one step after it), 127 (the last steps
+    leave some waves without columns to update)."""
     _say(f"[tridiagonal vs Jacobi EVD nt={nt}]")
     iq, mask = synth.make_packet(synth.spec_clinical(2, nt=nt))
     dev = torch.from_numpy(iq).cuda()
