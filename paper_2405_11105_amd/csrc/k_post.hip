@@ -288,11 +288,15 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
                         dr = fma(v.x, x[i].x, fma(v.y, x[i].y, dr));       // conj(v) x
                         di = fma(v.x, x[i].y, fma(-v.y, x[i].x, di));
                     }
-#pragma unroll
-                    for (int m = 8; m >= 1; m >>= 1) {
-                        dr += __shfl_xor(dr, m, 16);
-                        di += __shfl_xor(di, m, 16);
-                    }
+                    // sum over the 16 lanes of the row (lane moves within it)
+                    dr += dpp_d<0xB1>(dr);
+                    di += dpp_d<0xB1>(di);
+                    dr += dpp_d<0x4E>(dr);
+                    di += dpp_d<0x4E>(di);
+                    dr += dpp_d<0x141>(dr);
+                    di += dpp_d<0x141>(di);
+                    dr += dpp_d<0x140>(dr);
+                    di += dpp_d<0x140>(di);
                     const double2 d = make_double2(tau[j] * dr, tau[j] * di);
 #pragma unroll
                     for (int i = 0; i < RW; ++i) x[i] = csub(x[i], cmul(vh[j * NTP + l + 16 * i], d));
@@ -319,8 +323,8 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
                 for (int a = 0; a < RA; ++a)
 #pragma unroll
                     for (int b = 0; b < 8; ++b) {
-                        acc[a][b].x -= fma(wt[a].x, wu[b].x, wt[a].y * wu[b].y);
-                        acc[a][b].y -= fma(wt[a].y, wu[b].x, -wt[a].x * wu[b].y);
+                        acc[a][b].x = fma(-wt[a].x, wu[b].x, fma(-wt[a].y, wu[b].y, acc[a][b].x));
+                        acc[a][b].y = fma(-wt[a].y, wu[b].x, fma(wt[a].x, wu[b].y, acc[a][b].y));
                     }
             }
             // M once: M[j][n] -= sum_c W[j][c] (1 - w_c) conj(W'[n][c])
