@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
     __shared__ double2 X[NTP * RMAX];
     __shared__ double2 Y[NTP * RMAX];
     __shared__ double2 H[RMAX * RMAX], Z[RMAX * RMAX];
-    __shared__ double th[RMAX];
+    __shared__ double th[RMAX], tsh[RMAX];
     __shared__ double dg[NTP];
     __shared__ int piv[RMAX], order[RMAX];
     __shared__ double red[32];
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
                         }
                         const double2 dot = make_double2(wave_sum_x(dr), wave_sum_x(di));
 #pragma unroll
-                        for (int i = 0; i < XR; ++i) x[i][j] = csub(x[i][j], cmul(dot, x[i][q]));
+                        for (int i = 0; i < XR; ++i) x[i][j] = cfma(x[i][q], make_double2(-dot.x, -dot.y), x[i][j]);
                     }
                     double n2 = 0.0;
 #pragma unroll
@@ -204,10 +204,21 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
 #pragma unroll
             for (int j = 0; j < RMAX; ++j) acc[j] = make_double2(0.0, 0.0);
             if (t < nt) {
-                for (int u = half; u < nt; u += 2) {
-                    const double2 rtu = cconj(R((long)u * NTP + t));
+                // eight entries of R requested together (beyond nt: zero, times a
+                // finite row of X)
+                for (int u0 = half; u0 < nt; u0 += 16) {
+                    double2 rv[8];
 #pragma unroll
-                    for (int j = 0; j < RMAX; ++j) acc[j] = cadd(acc[j], cmul(rtu, X[u * RMAX + j]));
+                    for (int q = 0; q < 8; ++q) {
+                        const int u = u0 + 2 * q;
+                        rv[q] = u < nt ? cconj(R((long)u * NTP + t)) : make_double2(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int u = u0 + 2 * q < nt ? u0 + 2 * q : 0;
+#pragma unroll
+                        for (int j = 0; j < RMAX; ++j) acc[j] = cfma(rv[q], X[u * RMAX + j], acc[j]);
+                    }
                 }
             }
 #pragma unroll
@@ -235,7 +246,7 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
         const int i = tid / RMAX, j = tid % RMAX;
         double2 acc = make_double2(0.0, 0.0);
         if (i < ns && j < ns)
-            for (int t = 0; t < nt; ++t) acc = cadd(acc, cmulc(X[t * RMAX + i], Y[t * RMAX + j]));
+            for (int t = 0; t < nt; ++t) acc = cfmac(X[t * RMAX + i], Y[t * RMAX + j], acc);
         H[tid] = acc;
     }
     __syncthreads();
@@ -270,15 +281,18 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
         const int t = e / RMAX, j = e % RMAX;
         double2 acc = make_double2(0.0, 0.0);
         if (j < r)
-            for (int i = 0; i < ns; ++i) acc = cadd(acc, cmul(X[t * RMAX + i], Z[i * RMAX + order[j]]));
+            for (int i = 0; i < ns; ++i) acc = cfma(X[t * RMAX + i], Z[i * RMAX + order[j]], acc);
         Y[e] = acc;
     }
     __syncthreads();
-    // Householder QR of U[:, :r]
+    // Householder QR of U[:, :r], thread t holding row t (each thread updates
+    // only its own rows; the barriers of the block sums order the rest)
+    static_assert(NTP <= 256, "one row per thread");
+    const int t = tid;
+    const bool trow = t < nt;
     for (int j = 0; j < r; ++j) {
-        double part = 0.0;
-        for (int t = j + tid; t < nt; t += 256) part += cabs2(Y[t * RMAX + j]);
-        const double nx2 = block_sum_x(part, red);
+        const double2 yj = (trow && t >= j) ? Y[t * RMAX + j] : make_double2(0.0, 0.0);
+        const double nx2 = block_sum_x(cabs2(yj), red);
         const double nrm = sqrt(nx2);
         const double2 x0 = Y[j * RMAX + j];
         const double ax0 = sqrt(cabs2(x0));
@@ -287,41 +301,35 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
         // v = x - alpha e_j ; v^H v = 2 (|x|^2 + |x| |x0|)
         const double vv = 2.0 * (nx2 + nrm * ax0);
         const double tau = vv > 0.0 ? 2.0 / vv : 0.0;
-        for (int t = tid; t < NTP; t += 256) {
-            double2 v = make_double2(0.0, 0.0);
-            if (t > j && t < nt) v = Y[t * RMAX + j];
-            if (t == j) v = csub(x0, alpha);
-            hv[(long)j * NTP + t] = v;
+        const double2 v = t == j ? csub(x0, alpha) : (t > j && trow ? yj : make_double2(0.0, 0.0));
+        if (t < NTP) hv[(long)j * NTP + t] = v;
+        if (tid == 0) {
+            htau[j] = tau;
+            tsh[j] = tau;
         }
-        if (tid == 0) htau[j] = tau;
-        __syncthreads();
         // apply H_j to columns j+1..r-1 of U
         for (int c = j + 1; c < r; ++c) {
-            double2 part2 = make_double2(0.0, 0.0);
-            for (int t = j + tid; t < nt; t += 256) part2 = cadd(part2, cmulc(hv[(long)j * NTP + t], Y[t * RMAX + c]));
-            const double2 dot = block_sum2_x(part2, red);
-            for (int t = j + tid; t < nt; t += 256)
-                Y[t * RMAX + c] = csub(Y[t * RMAX + c], cscale(cmul(hv[(long)j * NTP + t], dot), tau));
-            __syncthreads();
+            const double2 yc = (trow && t >= j) ? Y[t * RMAX + c] : make_double2(0.0, 0.0);
+            const double2 dot = block_sum2_x(cfmac(v, yc, make_double2(0.0, 0.0)), red);
+            if (trow && t >= j) Y[t * RMAX + c] = cfma(v, make_double2(-tau * dot.x, -tau * dot.y), yc);
         }
     }
     // explicit V_r = H_0 ... H_{r-1} [e_0 .. e_{r-1}]
     for (int e = tid; e < NTP * RMAX; e += 256) {
-        const int t = e / RMAX, j = e % RMAX;
-        X[e] = make_double2((t == j && j < r) ? 1.0 : 0.0, 0.0);
+        const int te = e / RMAX, j = e % RMAX;
+        X[e] = make_double2((te == j && j < r) ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
     for (int j = r - 1; j >= 0; --j) {
-        const double tau = htau[j];
+        const double tau = tsh[j];
+        const double2 vj = trow ? hv[(long)j * NTP + t] : make_double2(0.0, 0.0);   // this thread's own write
         for (int c = 0; c < r; ++c) {
-            double2 part2 = make_double2(0.0, 0.0);
-            for (int t = j + tid; t < nt; t += 256) part2 = cadd(part2, cmulc(hv[(long)j * NTP + t], X[t * RMAX + c]));
-            const double2 dot = block_sum2_x(part2, red);
-            for (int t = j + tid; t < nt; t += 256)
-                X[t * RMAX + c] = csub(X[t * RMAX + c], cscale(cmul(hv[(long)j * NTP + t], dot), tau));
-            __syncthreads();
+            const double2 xc = (trow && t >= j) ? X[t * RMAX + c] : make_double2(0.0, 0.0);
+            const double2 dot = block_sum2_x(cfmac(vj, xc, make_double2(0.0, 0.0)), red);
+            if (trow && t >= j) X[t * RMAX + c] = cfma(vj, make_double2(-tau * dot.x, -tau * dot.y), xc);
         }
     }
+    __syncthreads();
     for (int e = tid; e < NTP * RMAX; e += 256) {
         ws.vr64[(long)s * NTP * RMAX + e] = X[e];
         ws.vr32[(long)s * NTP * RMAX + e] = make_float2((float)X[e].x, (float)X[e].y);

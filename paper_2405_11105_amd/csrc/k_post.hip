@@ -297,9 +297,9 @@ __global__ void __launch_bounds__(PjCfg<NTP>::NTHR) k_projector(Workspace ws) {
                     di += dpp_d<0x141>(di);
                     dr += dpp_d<0x140>(dr);
                     di += dpp_d<0x140>(di);
-                    const double2 d = make_double2(tau[j] * dr, tau[j] * di);
+                    const double2 nd = make_double2(-tau[j] * dr, -tau[j] * di);
 #pragma unroll
-                    for (int i = 0; i < RW; ++i) x[i] = csub(x[i], cmul(vh[j * NTP + l + 16 * i], d));
+                    for (int i = 0; i < RW; ++i) x[i] = cfma(vh[j * NTP + l + 16 * i], nd, x[i]);
                 }
 #pragma unroll
                 for (int i = 0; i < RW; ++i) Wl[c * NTP + l + 16 * i] = x[i];
