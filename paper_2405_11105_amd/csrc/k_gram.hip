@@ -425,12 +425,11 @@ struct DeflCfg {
     using GC = GramCfg<NTP, true, 1>;
     static constexpr int NTE = GC::NTE, LDB = GC::LDB, PX = GC::PX;
     static constexpr int WAVES = GC::WAVES, THREADS = GC::THREADS;
-    static constexpr int TSTEP = THREADS / PX;            // phase A: pixel tid % PX, frames tid / PX + TSTEP i
-    static constexpr int NPT = (NTP + TSTEP - 1) / TSTEP;
     static constexpr int MT = PX / 16;                    // y row tiles
     static constexpr int KSTEPS = NTP / 16;               // K blocks of 32 over (frame, re/im)
     static constexpr int KG = WAVES / MT;                 // K groups (one partial each)
     static constexpr int MAXKS = (KSTEPS + KG - 1) / KG;
+    static constexpr int NPT = 4 * MAXKS;                 // phase A values per lane (the B operand's frames)
     static constexpr int LDS_S = NTP + 1;                 // raw row stride (float2), odd
     static constexpr int FPT = (NTP + 63) / 64;           // phase D frames per lane
     static constexpr int PPW = PX / WAVES;                // phase D pixels per wave
@@ -514,8 +513,11 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
 #pragma unroll
     for (int m = 0; m < 2 * C::MAXP; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    // phase A layout and the software-pipelined loads of the next batch
-    const int my_p = tid % PX, my_t0 = tid / PX;
+    // phase A layout: lane (col, g) of wave (ymt, ykg) loads pixel 16 ymt + col at
+    // the frames of its phase-B operand, 16 ks + 4 g + e for ks = ykg + KG i, so
+    // that the scores take their operand from registers; the loads of the next
+    // batch are in flight meanwhile
+    const int my_p = 16 * ymt + col;
     // loads as in k_gram: valid addresses, mask and window product applied in phase A
     uint64_t nxt[D::NPT];
     bool fok = false;
@@ -536,13 +538,15 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
         }
         fx += PX;
         while (fx >= sd.bw) { fx -= sd.bw; ++fy; }
-        int mt = my_t0;
+        int mt = 16 * ykg + 4 * g;
         asm volatile("" : "+v"(pb), "+v"(mt));
 #pragma unroll
-        for (int i = 0; i < D::NPT; ++i) {
-            const int t = min(mt + D::TSTEP * i, nt - 1);
-            nxt[i] = giq[(long)t * npix + pb];
-        }
+        for (int i = 0; i < D::MAXKS; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int t = min(mt + 16 * D::KG * i + e, nt - 1);
+                nxt[4 * i + e] = giq[(long)t * npix + pb];
+            }
     };
     const int nb = (ch.q1 - ch.q0 + PX - 1) / PX;
     const bool cd_first = !PIPE || ((wave >> 2) & 1) == 0;
@@ -555,42 +559,41 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
         const uint32_t* El = Eh + NTE * LDB;
         const bool work = k < nb, egram = PIPE ? k > 0 : true;
         __syncthreads();                           // the previous batch's C, D and E are done
-        // ---- A
+        // ---- A: raw values to LDS for the residual (which then writes every
+        // operand row below NTP), the split window products kept for B
+        u32x4 xh[D::MAXKS], xl[D::MAXKS];
         if (work) {
             const double nw = fok ? (sd.flat ? 1.0 : fwy * fwx) : 0.0;
             const float wf = (float)nw;
-            if (my_t0 == 0) wsh[my_p] = nw;
+            if (ykg == 0 && g == 0) wsh[my_p] = nw;
 #pragma unroll
-            for (int i = 0; i < D::NPT; ++i) {
-                const int t = my_t0 + D::TSTEP * i;
-                if (t < NTP) {
-                    const float2 c = c64_bits(nxt[i], fok && t < nt);
-                    sraw[my_p * D::LDS_S + t] = c;
-                    uint32_t h, l;
-                    split_bf16x2(wf * c.x, wf * c.y, h, l);
-                    Ah[t * LDB + my_p] = h;
-                    Al[t * LDB + my_p] = l;
+            for (int i = 0; i < D::MAXKS; ++i) {
+                xh[i] = u32x4{0, 0, 0, 0};
+                xl[i] = xh[i];
+                const int ks = ykg + D::KG * i;
+                if (ks < D::KSTEPS) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int t = 16 * ks + 4 * g + e;
+                        const float2 c = c64_bits(nxt[4 * i + e], fok && t < nt);
+                        sraw[my_p * D::LDS_S + t] = c;
+                        uint32_t h, l;
+                        split_bf16x2(wf * c.x, wf * c.y, h, l);
+                        xh[i][e] = h;
+                        xl[i][e] = l;
+                    }
                 }
             }
         }
         if (work && qb + PX < ch.q1) fetch(qb + PX);   // in flight until the next batch
-        __syncthreads();
-        // ---- B: y partial of row tile ymt over this wave's K steps
+        // ---- B: y partial of row tile ymt over this wave's K steps, from registers
         if (work) {
             floatx4 ya = floatx4{0.f, 0.f, 0.f, 0.f};
-            const int prow = 16 * ymt + col;
 #pragma unroll
             for (int i = 0; i < D::MAXKS; ++i) {
                 const int ks = ykg + D::KG * i;
                 if (ks < D::KSTEPS) {
-                    u32x4 xh, xl;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int t = 16 * ks + 4 * g + e;
-                        xh[e] = Ah[t * LDB + prow];
-                        xl[e] = Al[t * LDB + prow];
-                    }
-                    const bf16x8 ah = __builtin_bit_cast(bf16x8, xh), al = __builtin_bit_cast(bf16x8, xl);
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, xh[i]), al = __builtin_bit_cast(bf16x8, xl[i]);
                     const bf16x8 bh = __builtin_bit_cast(bf16x8, vbh[i]), bl = __builtin_bit_cast(bf16x8, vbl[i]);
                     ya = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, ya, 0, 0, 0);
                     ya = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, ya, 0, 0, 0);
@@ -601,7 +604,7 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
 #pragma unroll
             for (int i = 0; i < 4; ++i) ypart[(ykg * PX + 16 * ymt + 4 * g + i) * 16 + col] = ya[i];
         }
-        __syncthreads();                           // also: phase B's reads of Ah/Al rows < NTP are done
+        __syncthreads();                           // A's raw values and B's partials are in
         if (PIPE && !cd_first && egram) gram_mfma_bf16_prio<C>(Eh, El, aoff, boff, valid, acc, lane);
         // ---- C: scores of this wave's pixels (lane: pixel 16-lane group, column)
         if (work) {
