@@ -26,7 +26,6 @@ __device__ __forceinline__ float gelu_grad_f(float h) {
     return 0.5f * (1.0f + erff(h * 0.70710678118654752f)) + h * expf(-0.5f * h * h) * 0.3989422804014327f;
 }
 
-constexpr int GT = 64;     // output tile edge
 constexpr int GK = 32;     // K step (one BF16 MFMA)
 constexpr int GLD = GK + 8;
 
@@ -50,18 +49,21 @@ struct GemmArgs {
     int asplit, bsplit;
 };
 
-template <int EPI>
+// GT x GT output tiles (64, or 32 for the small products of inference so that
+// more work-groups share the chip), four waves in a 2 x 2 layout.
+template <int EPI, int GT>
 __global__ void __launch_bounds__(256) k_mlp_gemm(GemmArgs g) {
+    constexpr int WT = GT / 32;            // 16 x 16 blocks per wave and axis
     __shared__ __attribute__((aligned(16))) uint16_t Ah[GT * GLD], Al[GT * GLD], Bh[GT * GLD], Bl[GT * GLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gq = lane >> 4, col = lane & 15;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int wy = wave >> 1, wx = wave & 1;
-    floatx4 acc[2][2];
+    floatx4 acc[WT][WT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < WT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < g.K; k0 += GK) {
         __syncthreads();
         for (int e = tid; e < GT * GK; e += 256) {
@@ -92,13 +94,13 @@ __global__ void __launch_bounds__(256) k_mlp_gemm(GemmArgs g) {
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int mr = wy * 32 + i * 16 + col;
+        for (int i = 0; i < WT; ++i) {
+            const int mr = wy * 16 * WT + i * 16 + col;
             const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Ah + mr * GLD + 8 * gq));
             const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Al + mr * GLD + 8 * gq));
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int nr = wx * 32 + j * 16 + col;
+            for (int j = 0; j < WT; ++j) {
+                const int nr = wx * 16 * WT + j * 16 + col;
                 const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(Bh + nr * GLD + 8 * gq));
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i][j], 0, 0, 0);
                 if (g.asplit) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i][j], 0, 0, 0);
@@ -110,13 +112,13 @@ __global__ void __launch_bounds__(256) k_mlp_gemm(GemmArgs g) {
         }
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WT; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wy * 32 + i * 16 + 4 * gq + r;
-                const int n = n0 + wx * 32 + j * 16 + col;
+                const int m = m0 + wy * 16 * WT + i * 16 + 4 * gq + r;
+                const int n = n0 + wx * 16 * WT + j * 16 + col;
                 if (m >= g.M || n >= g.N) continue;
                 const long o = (long)m * g.ldc + n;
                 float v = acc[i][j][r];
@@ -137,8 +139,16 @@ __global__ void __launch_bounds__(256) k_mlp_gemm(GemmArgs g) {
 
 template <int EPI>
 static hipError_t gemm(const GemmArgs& g, hipStream_t st) {
-    const dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
-    hipLaunchKernelGGL((k_mlp_gemm<EPI>), grid, dim3(256), 0, st, g);
+    // 64 x 64 tiles while they give at least one work-group per CU (training),
+    // 32 x 32 below (inference over the subsets of a call)
+    const long tiles64 = (long)((g.N + 63) / 64) * ((g.M + 63) / 64);
+    if (tiles64 >= 256) {
+        const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+        hipLaunchKernelGGL((k_mlp_gemm<EPI, 64>), grid, dim3(256), 0, st, g);
+    } else {
+        const dim3 grid((g.N + 31) / 32, (g.M + 31) / 32);
+        hipLaunchKernelGGL((k_mlp_gemm<EPI, 32>), grid, dim3(256), 0, st, g);
+    }
     return hipGetLastError();
 }
 
