@@ -58,8 +58,10 @@ __device__ __forceinline__ void tile_ij(int u, int nt16, int& i, int& j) {
     j = i + rem;
 }
 
-// Boxes with at least this many rows and columns are sampled 2 x 2 in pass 1.
+// Boxes with at least this many rows and columns are sampled in pass 1, on
+// every DEC_ROWS-th row (whole rows, so that every cache line read is used).
 constexpr int DEC_MIN = 8;
+constexpr int DEC_ROWS = 4;
 
 // Row fragment for the T tiles: each (re, im) word of the interleaved K axis
 // becomes (-im, re), so that the product with the plain column fragment sums
@@ -235,13 +237,12 @@ k_gram(Workspace ws) {
     double fwy = 1.0, fwx = 1.0;         // its window factors as loaded
     // Pass 1 only has to locate the tissue subspace (any V_r keeps the pass-2
     // decomposition exact), so in split BF16 boxes of at least DEC_MIN rows and
-    // columns are sampled on every second row and column (the FP32 path keeps
-    // every pixel: its covariance error tracks the size of C'): chunk [q0, q1)
-    // of the box maps to
-    // [q0 ne / neff, q1 ne / neff) of the ne sampled pixels.
+    // columns are sampled on every DEC_ROWS-th row (the FP32 path keeps every
+    // pixel: its covariance error tracks the size of C'): chunk [q0, q1) of the
+    // box maps to [q0 ne / neff, q1 ne / neff) of the ne sampled pixels.
     const int bh = sd.y1 - sd.y0 + 1;
-    const int dec = (!DEFL && PREC == 1 && sd.bw >= DEC_MIN && bh >= DEC_MIN) ? 2 : 1;
-    const int bwe = (sd.bw + dec - 1) / dec;
+    const int dec = (!DEFL && PREC == 1 && sd.bw >= DEC_MIN && bh >= DEC_MIN) ? DEC_ROWS : 1;
+    const int bwe = sd.bw;
     const long ne = (long)bwe * ((bh + dec - 1) / dec);
     const int q0 = dec == 1 ? ch.q0 : (int)((long)ch.q0 * ne / sd.neff);
     const int q1 = dec == 1 ? ch.q1 : (int)((long)ch.q1 * ne / sd.neff);
@@ -254,10 +255,10 @@ k_gram(Workspace ws) {
         long pb = (long)sd.y0 * nx + sd.x0;
         fok = okp;
         if (okp) {
-            pb = (long)(sd.y0 + dec * fy) * nx + sd.x0 + dec * fx;
+            pb = (long)(sd.y0 + dec * fy) * nx + sd.x0 + fx;
             if (!sd.flat) {
                 fwy = ((gptr_f64)wy)[dec * fy];
-                fwx = ((gptr_f64)wx)[dec * fx];
+                fwx = ((gptr_f64)wx)[fx];
             }
         }
         fx += PIX;
