@@ -108,7 +108,7 @@ __device__ void wave_heev8(double2& h, double2& z, int lane) {
 }
 
 template <int NTP>
-__global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int iters) {
+__global__ void __launch_bounds__(256, 4) k_tissue(Workspace ws, double rho, int iters) {
     constexpr int XR = (NTP + 63) / 64;         // rows per lane in the one-wave passes
     __shared__ double2 X[NTP * RMAX];
     __shared__ double2 Y[NTP * RMAX];
@@ -204,20 +204,29 @@ __global__ void __launch_bounds__(256) k_tissue(Workspace ws, double rho, int it
 #pragma unroll
             for (int j = 0; j < RMAX; ++j) acc[j] = make_double2(0.0, 0.0);
             if (t < nt) {
-                // eight entries of R requested together (beyond nt: zero, times a
-                // finite row of X)
-                for (int u0 = half; u0 < nt; u0 += 16) {
-                    double2 rv[8];
+                // eight entries of R requested together, the next eight (raw FP32)
+                // in flight while these are used (beyond nt: zero, times a finite
+                // row of X)
+                auto fetchR = [&](int u0, float2 (&f)[8]) {
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         const int u = u0 + 2 * q;
-                        rv[q] = u < nt ? cconj(R((long)u * NTP + t)) : make_double2(0.0, 0.0);
+                        f[q] = u < nt ? Rf[(long)u * NTP + t] : make_float2(0.f, 0.f);
                     }
+                };
+                float2 rf[8];
+                fetchR(half, rf);
+                for (int u0 = half; u0 < nt; u0 += 16) {
+                    float2 rc[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) rc[q] = rf[q];
+                    if (u0 + 16 < nt) fetchR(u0 + 16, rf);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         const int u = u0 + 2 * q < nt ? u0 + 2 * q : 0;
+                        const double2 rv = make_double2((double)rc[q].x, -(double)rc[q].y);
 #pragma unroll
-                        for (int j = 0; j < RMAX; ++j) acc[j] = cfma(rv[q], X[u * RMAX + j], acc[j]);
+                        for (int j = 0; j < RMAX; ++j) acc[j] = cfma(rv, X[u * RMAX + j], acc[j]);
                     }
                 }
             }
