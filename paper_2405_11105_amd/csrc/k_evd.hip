@@ -1298,20 +1298,20 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
 
 // Step 3 for both reduction kernels. NTHR Sturm counts at grid points (the
 // lower Gershgorin bound, then geometric steps from hi 2^-64 up to hi) bracket
-// every eigenvalue; then multisection, LPE lanes for the k-th largest, LPE
-// points and LPE + 1 sub-intervals per round, until the bracket is no wider
-// than (hi - lo) 1.7e-17 (24 rounds of 5 or 36 of 3 from the Gershgorin
-// interval reach it, below the rounding of the largest eigenvalue). Two lanes
-// per eigenvalue at 128 frames (about 66 counts per eigenvalue instead of 90
-// with four, still four waves per SIMD: 1.73 -> 1.70 ms for the EVD values of
-// the four-packet step); four elsewhere. Each count is a dependent chain of
+// every eigenvalue; then multisection, lanes 4k .. 4k+3 for the k-th largest,
+// 4 points and 5 sub-intervals per round, until the bracket is no wider than
+// (hi - lo) 1.7e-17 (24 rounds from the Gershgorin interval reach it, below
+// the rounding of the largest eigenvalue). Four lanes per eigenvalue in every
+// batch, so that a packet's eigenvalues do not depend on what it is batched
+// with: two lanes and three sub-intervals per round need about 66 counts per
+// eigenvalue instead of 90 (1.73 -> 1.70 ms for the four-packet step at 128
+// frames) but about 33 dependent rounds instead of 22, which one packet's 256
+// subsets cannot hide (0.18 -> 0.25 ms). Each count is a dependent chain of
 // nt divisions: the kernel holds few registers, so several work-groups per CU
 // hide that latency (inside the reduction kernels two waves per SIMD did).
-template <int N, int NTHR, int LPE>
+template <int N, int NTHR>
 __global__ void __launch_bounds__(NTHR) k_heev_sturm(Workspace ws) {
-    static_assert(NTHR >= LPE * N && (LPE == 2 || LPE == 4), "LPE lanes per eigenvalue");
-    // rounds of LPE + 1 sub-intervals that take any grid bracket below the tolerance
-    constexpr int ROUNDS = LPE == 4 ? 24 : 36;
+    static_assert(NTHR >= 4 * N, "four lanes per eigenvalue");
     __shared__ double dsh[N], e2sh[N];
     __shared__ int gcnt[NTHR];                 // Sturm counts at the bracketing grid
     __shared__ int offdiag;
@@ -1356,7 +1356,7 @@ __global__ void __launch_bounds__(NTHR) k_heev_sturm(Workspace ws) {
     };
     gcnt[tid] = sturm(grid(tid));
     __syncthreads();
-    const int k = tid / LPE, m = tid % LPE;
+    const int k = tid >> 2, m = tid & 3;
     const int target = nt - 1 - k;                                 // index among ascending
     // counts are nondecreasing along the grid: the last point with count <= target
     int g0 = 0, g1 = NTHR - 1;                                     // gcnt[g0] <= target < gcnt[g1]
@@ -1367,16 +1367,16 @@ __global__ void __launch_bounds__(NTHR) k_heev_sturm(Workspace ws) {
     }
     double a = grid(g0), b = g1 == NTHR - 1 ? hi : grid(g1);
     const double tol = (hi - lo) * 1.7e-17;
-    for (int it = 0; it < ROUNDS && b - a > tol; ++it) {
-        const double h = (b - a) * (1.0 / (LPE + 1));
+    for (int it = 0; it < 24 && b - a > tol; ++it) {
+        const double h = (b - a) * 0.2;
         const double x = a + (double)(m + 1) * h;
         const int cnt = k < nt ? sturm(x) : 0;
         // the points left of the eigenvalue are those with count <= target
         int le = cnt <= target;
         le += __builtin_amdgcn_mov_dpp(le, 0xB1, 0xF, 0xF, false);          // lane ^ 1
-        if constexpr (LPE == 4) le += __builtin_amdgcn_mov_dpp(le, 0x4E, 0xF, 0xF, false);   // lane ^ 2
+        le += __builtin_amdgcn_mov_dpp(le, 0x4E, 0xF, 0xF, false);          // lane ^ 2
         const double na = a + (double)le * h;
-        b = le == LPE ? b : a + (double)(le + 1) * h;
+        b = le == 4 ? b : a + (double)(le + 1) * h;
         a = na;
     }
     if (m == 0 && k < nt) ws.lam[(long)s * N + k] = 0.5 * (a + b);
@@ -1933,27 +1933,27 @@ hipError_t launch_evd(const Workspace& ws, int max_sweeps, int nt_max, int metho
     switch (ws.ntp) {
         case 32:
             hipLaunchKernelGGL((k_heev_tri_reduce<1, 2>), dim3(ws.S), dim3(128), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<32, 128, 4>), dim3(ws.S), dim3(128), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<32, 128>), dim3(ws.S), dim3(128), 0, st, ws);
             break;
         case 64:
             hipLaunchKernelGGL((k_heev_tri_reduce<1, 4>), dim3(ws.S), dim3(256), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<64, 256, 4>), dim3(ws.S), dim3(256), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<64, 256>), dim3(ws.S), dim3(256), 0, st, ws);
             break;
         case 96:
             hipLaunchKernelGGL((k_heev_tri_reduce<2, 6>), dim3(ws.S), dim3(384), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<96, 384, 4>), dim3(ws.S), dim3(384), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<96, 384>), dim3(ws.S), dim3(384), 0, st, ws);
             break;
         case 128:
             hipLaunchKernelGGL((k_heev_tri_reduce<2, 8>), dim3(ws.S), dim3(512), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<128, 256, 2>), dim3(ws.S), dim3(256), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<128, 512>), dim3(ws.S), dim3(512), 0, st, ws);
             break;
         case 160:
             hipLaunchKernelGGL((k_heev_big_reduce<160, 3>), dim3(ws.S), dim3(1024), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<160, 1024, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<160, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
             break;
         default:
             hipLaunchKernelGGL((k_heev_big_reduce<208, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
-            hipLaunchKernelGGL((k_heev_sturm<208, 1024, 4>), dim3(ws.S), dim3(1024), 0, st, ws);
+            hipLaunchKernelGGL((k_heev_sturm<208, 1024>), dim3(ws.S), dim3(1024), 0, st, ws);
             break;
     }
     return hipGetLastError();

@@ -418,6 +418,29 @@ def test_evd_tridiagonal_matches_jacobi(lcf, ctx, nt):
     assert np.array_equal(d_t["k"].cpu().numpy(), d_j["k"].cpu().numpy())
 
 
+@pytest.mark.parametrize("nt", [128, 127])
+def test_evd_tridiagonal_batch_matches_jacobi(lcf, ctx, nt):
+    """Four packets on 16 x 16 grids (1024 subsets in one batch, every
+    work-group slot of the EVD kernels filled): the filtered packets of the
+    tridiagonal solver against Jacobi's."""
+    _say(f"[tridiagonal vs Jacobi EVD, 1024-subset batch, nt={nt}]")
+    dev = [torch.from_numpy(synth.make_packet(synth.spec_clinical(p, nt=nt))[0]).cuda() for p in range(4)]
+    grids = [(16, 16)] * 4
+    thr = lcf.Threshold(cut=lcf.CUT_KNEE, shape=lcf.SHAPE_SIGMOID)
+    io_t, _ = ctx.filter_batch(dev, grids, thr, iq_out=True)
+    ctx.set_option(lcf.OPT_EVD, lcf.EVD_JACOBI)
+    try:
+        io_j, _ = ctx.filter_batch(dev, grids, thr, iq_out=True)
+    finally:
+        ctx.set_option(lcf.OPT_EVD, lcf.EVD_TRIDIAGONAL)
+    torch.cuda.synchronize()
+    assert ctx.sync() == 0
+    for p in range(4):
+        e = float(torch.linalg.vector_norm(io_t[p] - io_j[p]) / torch.linalg.vector_norm(io_j[p]))
+        _say(f"   packet {p}: iq {e:.1e}")
+        assert e <= 1e-7, p
+
+
 @pytest.mark.parametrize("nt", [32, 150])
 def test_evd_rank_deficient_falls_back_to_jacobi(lcf, ctx, nt):
     """Boxes of at most 30 pixels and 32 (150) frames: every subset covariance is
