@@ -1356,6 +1356,24 @@ k_reproj_sb(Workspace ws) {
                 }
             }
         }
+        // [P; M] fragments of one K step, (Re hi, Re lo, Im hi, Im lo) per frame tile;
+        // the first step's are requested before the barrier ahead of E
+        auto bload = [&](u32x4 (&bf)[QW][4], int kq) {
+#pragma unroll
+            for (int q = 0; q < QW; ++q) {
+                const int nq = wave * QW + q;
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) bf[q][pl] = u32x4{0u, 0u, 0u, 0u};
+                if (qok(q)) {
+                    const uint16_t* src = planes + (long)(nq * 16 + col) * KB + kq;
+#pragma unroll
+                    for (int pl = 0; pl < 4; ++pl)
+                        bf[q][pl] = *reinterpret_cast<const u32x4*>(src + (long)pl * NTP * KB);
+                }
+            }
+        };
+        u32x4 bc[QW][4];
+        if constexpr (C::PREF) bload(bc, 8 * g);
         if (tid < TP) {
             const double w = wyv * wxv;
             wd[tid] = (float)w;
@@ -1379,23 +1397,7 @@ k_reproj_sb(Workspace ws) {
         for (int a = 0; a < NRT; ++a)
 #pragma unroll
             for (int m = 0; m < CTW; ++m) acc[a][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-        // [P; M] fragments of one K step, (Re hi, Re lo, Im hi, Im lo) per frame tile
-        auto bload = [&](u32x4 (&bf)[QW][4], int kq) {
-#pragma unroll
-            for (int q = 0; q < QW; ++q) {
-                const int nq = wave * QW + q;
-#pragma unroll
-                for (int pl = 0; pl < 4; ++pl) bf[q][pl] = u32x4{0u, 0u, 0u, 0u};
-                if (qok(q)) {
-                    const uint16_t* src = planes + (long)(nq * 16 + col) * KB + kq;
-#pragma unroll
-                    for (int pl = 0; pl < 4; ++pl)
-                        bf[q][pl] = *reinterpret_cast<const u32x4*>(src + (long)pl * NTP * KB);
-                }
-            }
-        };
-        u32x4 bc[QW][4], bn[QW][4];
-        if constexpr (C::PREF) bload(bc, 8 * g);
+        u32x4 bn[QW][4];
 #pragma unroll 1
         for (int kstep = 0; kstep < C::NKS; ++kstep) {
             const int kq = 32 * kstep + 8 * g;
