@@ -243,7 +243,9 @@ typedef struct lcf_context lcf_context;
 
 /* Create a context on HIP device `device`. *out receives the handle. */
 lcf_status lcf_create(int32_t device, lcf_context** out);
-/* Release the context and its device memory. NULL is accepted. */
+/* Release the context and its device memory. NULL is accepted. Everything is
+ * released even when a HIP call fails on the way (after an earlier device
+ * fault, say); the return is then LCF_ERR_DEVICE. */
 lcf_status lcf_destroy(lcf_context* ctx);
 /* Set a context option (LCF_OPT_*). */
 lcf_status lcf_set_option(lcf_context* ctx, int32_t option, int64_t value);
@@ -318,7 +320,9 @@ lcf_status lcf_filter_batch(lcf_context* ctx, int32_t n, const lcf_geometry* geo
  *   checked). 1 <= hop <= nt; the first push after create computes every
  *   column whatever hop says. iq_out, pd and diag as lcf_filter; calls on one
  *   stream must be made in packet order on one HIP stream.
- * lcf_stream_destroy: release the stream's buffers (waits for the device). */
+ * lcf_stream_destroy: release the stream's buffers (waits for the device);
+ *   as lcf_destroy, everything is released and a failed HIP call on the way
+ *   returns LCF_ERR_DEVICE. */
 typedef struct lcf_stream lcf_stream;
 lcf_status lcf_stream_create(lcf_context* ctx, const lcf_geometry* geo, const lcf_threshold* thr,
                              int32_t precision, lcf_stream** out);

@@ -208,8 +208,8 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().lcf_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _check(load().lcf_destroy(h), "lcf_destroy")
 
     def __del__(self):
         try:
@@ -391,8 +391,8 @@ class Stream:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().lcf_stream_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _check(load().lcf_stream_destroy(h), "lcf_stream_destroy")
 
     def __del__(self):
         try:

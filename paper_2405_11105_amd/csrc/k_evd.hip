@@ -108,7 +108,7 @@ __device__ void wave_heev8(double2& h, double2& z, int lane) {
 }
 
 template <int NTP>
-__global__ void __launch_bounds__(256, 4) k_tissue(Workspace ws, double rho, int iters) {
+__global__ void __launch_bounds__(256, NTP <= 128 ? 4 : NTP <= 160 ? 3 : 2) k_tissue(Workspace ws, double rho, int iters) {
     constexpr int XR = (NTP + 63) / 64;         // rows per lane in the one-wave passes
     __shared__ double2 X[NTP * RMAX];
     __shared__ double2 Y[NTP * RMAX];
@@ -773,7 +773,6 @@ __global__ void __launch_bounds__(64 * NW) k_jacobi_reg(Workspace ws, int max_sw
     constexpr int SLOT = 8 * ROWS;                     // double2 per half-block
     __shared__ double2 xch[(NW + 1) * SLOT];
     __shared__ int idx[NW + 1];
-    __shared__ int top_id[NW], bot_id[NW];
     __shared__ int s_rot[NW];
     __shared__ double s_off[NW];
     const int s = blockIdx.x, lane = threadIdx.x & 63;

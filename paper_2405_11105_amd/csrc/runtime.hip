@@ -344,11 +344,11 @@ namespace {
 lcf_status ensure_device(lcf_context* c, size_t bytes) {
     if (bytes <= c->dcap) return LCF_OK;
     if (c->dbuf) {
-        if (hipDeviceSynchronize() != hipSuccess) return LCF_ERR_DEVICE;
-        hipFree(c->dbuf);
+        if (hipDeviceSynchronize() != hipSuccess || hipFree(c->dbuf) != hipSuccess) return LCF_ERR_DEVICE;
         c->dbuf = nullptr;
         c->dcap = 0;
-        for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+        // the graphs hold addresses in the old block; a failed destroy leaves nothing to undo
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
         c->graphs.clear();
     }
     const size_t want = align_up(bytes + bytes / 4, 1 << 20);
@@ -363,7 +363,11 @@ lcf_status ensure_host(lcf_context* c, size_t bytes) {
         c->staged_pending = false;
     }
     if (bytes <= c->hcap) return LCF_OK;
-    if (c->hbuf) hipHostFree(c->hbuf);
+    if (c->hbuf) {
+        if (hipHostFree(c->hbuf) != hipSuccess) return LCF_ERR_DEVICE;
+        c->hbuf = nullptr;
+        c->hcap = 0;
+    }
     const size_t want = align_up(bytes + bytes / 4, 1 << 16);
     if (hipHostMalloc((void**)&c->hbuf, want, hipHostMallocDefault) != hipSuccess) {
         c->hbuf = nullptr;
@@ -383,7 +387,7 @@ lcf_status refuse_capture(hipStream_t st) {
 }
 
 void drop_graphs(lcf_context* c) {
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);   // nothing to undo on failure
     c->graphs.clear();
 }
 
@@ -422,8 +426,7 @@ lcf_status ensure_mlp_scratch(lcf_context* c, size_t floats) {
     if (floats <= c->mlp_scratch_cap) return LCF_OK;
     drop_graphs(c);
     if (c->mlp_scratch) {
-        if (hipDeviceSynchronize() != hipSuccess) return LCF_ERR_DEVICE;
-        hipFree(c->mlp_scratch);
+        if (hipDeviceSynchronize() != hipSuccess || hipFree(c->mlp_scratch) != hipSuccess) return LCF_ERR_DEVICE;
         c->mlp_scratch = nullptr;
         c->mlp_scratch_cap = 0;
     }
@@ -610,7 +613,8 @@ struct StageScope {
     StageScope(lcf_context* c_, int stage_, hipStream_t st_) : c(c_), stage(stage_), st(st_) {
         if (!c->timing) return;
         if (c->evnext + 2 > c->evpool.size()) {
-            if (c->evnext + 2 > 4096) drain_timing(c);
+            // events already recorded are resolved first; if that fails, this stage is not timed
+            if (c->evnext + 2 > 4096 && drain_timing(c) != hipSuccess) return;
             while (c->evnext + 2 > c->evpool.size()) {
                 hipEvent_t e;
                 if (hipEventCreate(&e) != hipSuccess) return;
@@ -828,7 +832,7 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
     static const int chunks[] = {512, 1024, 2048, 4096};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return LCF_ERR_DEVICE; }
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return LCF_ERR_DEVICE; }
     const int saved_timing = c->timing;
     c->timing = 0;
     float best = 0.f;
@@ -865,8 +869,8 @@ lcf_status tune_group(lcf_context* c, const std::vector<PacketIn>& in, const std
     if (ntp <= 128) trial(choice.chunk, choice.trows, choice.rvar, 1 - c->evd_method);
 done:
     c->timing = saved_timing;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);     // the trial timings are already read
+    (void)hipEventDestroy(e1);
     if (res == LCF_OK) c->tuned[key] = choice;
     return res;
 }
@@ -930,11 +934,11 @@ lcf_status filter_packets(lcf_context* c, const std::vector<PacketIn>& in, const
         if (graph) {
             hipGraph_t gr = nullptr;
             const hipError_t ce = hipStreamEndCapture(st, &gr);
-            if (e != LCF_OK) { if (gr) hipGraphDestroy(gr); return e; }
+            if (e != LCF_OK) { if (gr) (void)hipGraphDestroy(gr); return e; }
             if (ce != hipSuccess) return LCF_ERR_DEVICE;
             hipGraphExec_t ex = nullptr;
             const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-            hipGraphDestroy(gr);
+            (void)hipGraphDestroy(gr);     // the executable graph does not need it
             if (ie != hipSuccess) return LCF_ERR_DEVICE;
             c->graphs[key] = ex;
             HIPCHK(hipGraphLaunch(ex, st));
@@ -999,20 +1003,23 @@ lcf_status lcf_create(int32_t device, lcf_context** out) {
 
 lcf_status lcf_destroy(lcf_context* c) {
     if (!c) return LCF_OK;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
-    for (auto e : c->evpool) hipEventDestroy(e);
+    // everything is released even after a failure; the first error is reported
+    hipError_t first = hipSuccess;
+    auto note = [&](hipError_t e) { if (first == hipSuccess && e != hipSuccess) first = e; };
+    note(hipSetDevice(c->device));
+    note(hipDeviceSynchronize());
+    for (auto& kv : c->graphs) note(hipGraphExecDestroy(kv.second));
+    for (auto e : c->evpool) note(hipEventDestroy(e));
     for (void* p : {(void*)c->mlp.master, (void*)c->mlp.wbf, (void*)c->mlp.m, (void*)c->mlp.v, (void*)c->mlp.grad,
                     (void*)c->mlp_scratch})
-        if (p) hipFree(p);
-    if (c->dbuf) hipFree(c->dbuf);
-    if (c->hbuf) hipHostFree(c->hbuf);
-    if (c->sticky) hipFree(c->sticky);
-    if (c->staged) hipEventDestroy(c->staged);
-    if (c->fixed_staged) hipEventDestroy(c->fixed_staged);
+        if (p) note(hipFree(p));
+    if (c->dbuf) note(hipFree(c->dbuf));
+    if (c->hbuf) note(hipHostFree(c->hbuf));
+    if (c->sticky) note(hipFree(c->sticky));
+    if (c->staged) note(hipEventDestroy(c->staged));
+    if (c->fixed_staged) note(hipEventDestroy(c->fixed_staged));
     delete c;
-    return LCF_OK;
+    return first == hipSuccess ? LCF_OK : LCF_ERR_DEVICE;
 }
 
 lcf_status lcf_set_option(lcf_context* c, int32_t option, int64_t value) {
@@ -1167,12 +1174,15 @@ lcf_status lcf_stream_push(lcf_stream* sm, const void* iq, int32_t hop, void* iq
 
 lcf_status lcf_stream_destroy(lcf_stream* sm) {
     if (!sm) return LCF_OK;
-    hipSetDevice(sm->ctx->device);
-    hipDeviceSynchronize();
+    // everything is released even after a failure; the first error is reported
+    hipError_t first = hipSuccess;
+    auto note = [&](hipError_t e) { if (first == hipSuccess && e != hipSuccess) first = e; };
+    note(hipSetDevice(sm->ctx->device));
+    note(hipDeviceSynchronize());
     for (void* p : {(void*)sm->rbuf[0], (void*)sm->rbuf[1], (void*)sm->part})
-        if (p) hipFree(p);
+        if (p) note(hipFree(p));
     delete sm;
-    return LCF_OK;
+    return first == hipSuccess ? LCF_OK : LCF_ERR_DEVICE;
 }
 
 lcf_status lcf_heevd_batched(lcf_context* ctx, int32_t n, int32_t nt, const double* a, double* w, double* v,
