@@ -40,7 +40,7 @@ images I_T(k) = sum of |u_i| over i = k-fn+1..k and I_B(k) = over i = k+1..k+fn
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 import math
 from typing import Optional
 

@@ -1,5 +1,4 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 oracle."""
-import math
 import sys
 
 import numpy as np
@@ -7,7 +6,7 @@ import pytest
 
 import oracle as O
 import synth
-from parity import rel_fro, pd_db_error, knee_tie, run_gpu as _run, oracle_thr as _oracle_thr, \
+from parity import rel_fro, run_gpu as _run, oracle_thr as _oracle_thr, \
     check_end_to_end as _check_end_to_end
 
 pytestmark = pytest.mark.gpu

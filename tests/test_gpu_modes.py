@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 import synth
-from parity import say, check_end_to_end, rel_fro, pd_db_error
+from parity import say, check_end_to_end
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")

@@ -2,12 +2,10 @@
 is filtered as packets that slide by `hop` frames, the covariance carried
 from push to push; every push is compared with the oracle filtering that
 packet from scratch, and with lcf_filter on the same packet."""
-import numpy as np
 import pytest
 
-import oracle as O
 import synth
-from parity import say, oracle_thr, compare_with_oracle, rel_fro, pd_db_error
+from parity import say, compare_with_oracle, rel_fro, pd_db_error
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
