@@ -668,18 +668,32 @@ __global__ void __launch_bounds__((DeflCfg<NTP>::THREADS)) k_gram_defl(Workspace
                         }
                     }
                 }
+                // the wave's PPW pixels are adjacent in an operand row: one store
+                // of up to 16 bytes per frame (single words at stride LDB would
+                // meet in a quarter of the banks)
+                constexpr int VW = D::PPW % 4 == 0 ? 4 : D::PPW % 2 == 0 ? 2 : 1;
 #pragma unroll
-                for (int kp = 0; kp < D::PPW; ++kp) {
-                    const int p = wave * D::PPW + kp;
+                for (int f = 0; f < D::FPT; ++f) {
+                    const int t = lane + 64 * f;
+                    if (t < NTP) {
+                        const bool in = t < nt;
 #pragma unroll
-                    for (int f = 0; f < D::FPT; ++f) {
-                        const int t = lane + 64 * f;
-                        if (t < NTP) {
-                            const bool in = t < nt;
-                            uint32_t h, l;
-                            split_bf16x2(in ? (float)cr[kp][f] : 0.f, in ? (float)ci[kp][f] : 0.f, h, l);
-                            Ah[t * LDB + p] = h;
-                            Al[t * LDB + p] = l;
+                        for (int k0 = 0; k0 < D::PPW; k0 += VW) {
+                            uint32_t h[VW], l[VW];
+#pragma unroll
+                            for (int v = 0; v < VW; ++v)
+                                split_bf16x2(in ? (float)cr[k0 + v][f] : 0.f, in ? (float)ci[k0 + v][f] : 0.f, h[v], l[v]);
+                            const int o = t * LDB + wave * D::PPW + k0;
+                            if constexpr (VW == 4) {
+                                *reinterpret_cast<u32x4*>(Ah + o) = u32x4{h[0], h[1], h[2], h[3]};
+                                *reinterpret_cast<u32x4*>(Al + o) = u32x4{l[0], l[1], l[2], l[3]};
+                            } else if constexpr (VW == 2) {
+                                *reinterpret_cast<uint2*>(Ah + o) = make_uint2(h[0], h[1]);
+                                *reinterpret_cast<uint2*>(Al + o) = make_uint2(l[0], l[1]);
+                            } else {
+                                Ah[o] = h[0];
+                                Al[o] = l[0];
+                            }
                         }
                     }
                 }
