@@ -24,7 +24,7 @@ constexpr int SC_NC = 16;    // new columns per work-group (the partials' row le
 // the band's sums go to part[s][g][b][i][16]. NCM = 8 serves hops up to 8
 // with half the accumulators (more waves per SIMD).
 template <int NTP, int NCM>
-__global__ void __launch_bounds__(256) k_cov_new(Workspace ws, double2* part, int hop, int ngroups, int nband) {
+__global__ void __launch_bounds__(256, (NCM <= 8 && NTP <= 128) ? 4 : 1) k_cov_new(Workspace ws, double2* part, int hop, int ngroups, int nband) {
     constexpr int LDP = NTP + 1;                        // row of one pixel (float2), odd stride
     constexpr int HALVES = 256 / NTP > 0 ? 256 / NTP : 1;
     constexpr int PPH = SC_PB / HALVES;                 // pixels per half
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256) k_cov_new(Workspace ws, double2* part, in
         __syncthreads();
         if (qb + SC_PB < q1) fetch(qb + SC_PB);     // in flight during the products
         if (crow) {
-#pragma unroll 2
+#pragma unroll 1
             for (int p = half * PPH; p < (half + 1) * PPH; ++p) {
                 const float2 a = sr[p * LDP + i];
                 const double ww = w2[p];
