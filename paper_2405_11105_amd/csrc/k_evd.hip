@@ -1249,7 +1249,9 @@ __global__ void __launch_bounds__(64 * NW) k_heev_tri_reduce(Workspace ws) {
         for (int i = 0; i < RPL; ++i) {
             const double2 incl = cmul(carry, u[i]);
             const double2 prev = make_double2(__shfl_up(incl.x, 1, 64), __shfl_up(incl.y, 1, 64));
-            dexc[i] = lane == 0 ? carry : prev;
+            // per component: a select between two double2 values becomes a select of
+            // their addresses and puts both on the stack
+            dexc[i] = make_double2(lane == 0 ? carry.x : prev.x, lane == 0 ? carry.y : prev.y);
             carry = make_double2(rdl(incl.x, 63), rdl(incl.y, 63));
         }
         double lo = 1e300, hi = -1e300, emax = 0.0;
@@ -1731,7 +1733,7 @@ __global__ void __launch_bounds__(1024) k_heev_big_reduce(Workspace ws) {
             const double2 incl = cmul(carry, u[i]);
             const double2 prev = make_double2(__shfl_up(incl.x, 1, 64), __shfl_up(incl.y, 1, 64));
             const int j = lane + 64 * i;
-            if (j < N) phs[j] = lane == 0 ? carry : prev;
+            if (j < N) phs[j] = make_double2(lane == 0 ? carry.x : prev.x, lane == 0 ? carry.y : prev.y);
             carry = make_double2(rdl(incl.x, 63), rdl(incl.y, 63));
             const double aup = __shfl_up(ae[i], 1, 64);
             const double aprv = lane == 0 ? (i > 0 ? rdl(ae[i > 0 ? i - 1 : 0], 63) : 0.0) : aup;
